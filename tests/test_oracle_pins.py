@@ -472,9 +472,9 @@ def test_error_bar_matches_spread_over_independent_records():
     """sigma^2 = Var/Np is an unbiased estimate of the variance of the chunk
     average, so its mean over independent records matches the spread of the
     averages across those records (Section 4.2)."""
-    N, Nf, m, Np = 32, 8, 10, 20
+    N, Nf, m, Np = 32, 8, 10, 4         # small Np: the Np/(Np-1) factor is 4/3
     res = {k: ([], []) for k in ("s2", "s3", "s4")}
-    for seed in range(400):
+    for seed in range(800):
         w = np.random.default_rng(1000 + seed).standard_normal(N * m * Np)
         out = O.polyspectra(w, N, Nf, m)
         for k, (means, errs) in res.items():
@@ -483,4 +483,4 @@ def test_error_bar_matches_spread_over_independent_records():
     for k, (means, errs) in res.items():
         spread2 = np.var(np.array(means), axis=0, ddof=1)
         ratio = np.mean(np.array(errs) ** 2, axis=0) / spread2
-        assert 0.85 < np.median(ratio) < 1.15, (k, np.median(ratio))
+        assert 0.9 < np.median(ratio) < 1.1, (k, np.median(ratio))
