@@ -1,0 +1,204 @@
+/*
+ * polyspec.h -- C ABI of the MI355X (gfx950) polyspectrum library.
+ *
+ * The library computes the unbiased polyspectrum estimates of
+ * Sifft, Ghorbanietemad, Wagner and Haegele, "Correct Estimation of
+ * Higher-Order Spectra" (arXiv 2505.01231):
+ *
+ *   a_k(f)      = dt sum_{i<N} g_i z_{fN+i} exp(+2 pi j i k / N)   (Section 3, eq. a_k;
+ *                                                                  +j sign of Appendix A)
+ *   S2_ab(k)    = c2(a_k, b*_k)          / (dt sum g^2)            (Section 3; Section 7)
+ *   S3_abc(k,l) = c3(a_k, b_l, c*_{k+l}) / (dt sum g^3)            (Section 4; Section 7)
+ *   S4_abcd(k,l)= c4(a_k, b*_k, c_l, d*_l)/ (dt sum g^4)           (Section 4 cut; Section 7)
+ *
+ * with c2..c4 the multivariate k-statistics of Section 4.1 evaluated over the
+ * m consecutive frames of one chunk, averaged over the Np chunks of a record,
+ * with error bars sigma = sqrt(Var/Np), Var = Np/(Np-1)(mean(x^2)-mean(x)^2)
+ * taken separately for the real and imaginary parts (Section 4.2).
+ *
+ * Frames are contiguous, non-overlapping blocks of N samples; a chunk is m
+ * consecutive frames; Np = floor(floor(L / N) / m); leftover samples are not
+ * used.  The output grid is k, l = 0..N_f-1 (frequency k / (N dt)).
+ *
+ * Conventions shared by every entry point:
+ *  - Every pointer named d_* is a device (HBM) pointer on the current HIP
+ *    device; every other pointer is host memory.  The caller owns all device
+ *    buffers (inputs, workspace, outputs); the library allocates device memory
+ *    only inside ps_plan_create (window and twiddle tables, owned by the plan,
+ *    freed by ps_plan_destroy).
+ *  - Calls that take a stream only enqueue work on it and return; results are
+ *    valid after the caller synchronises that stream.  A plan must not be used
+ *    by two streams at the same time.
+ *  - Errors are reported by return code only; nothing unwinds across the ABI.
+ *    ps_last_error() returns a thread-local description of the last failure.
+ *    Argument errors are detected before anything is enqueued.  Device faults
+ *    surface at the caller's synchronisation (and as PS_E_HIP from a later call).
+ */
+#ifndef POLYSPEC_H
+#define POLYSPEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PS_ABI_VERSION 1
+
+typedef struct ps_plan_s* ps_plan_t;
+typedef void* ps_stream_t; /* a hipStream_t; NULL is the null stream */
+
+typedef enum ps_status {
+    PS_OK = 0,
+    PS_E_INVALID_ARG = 1, /* a parameter is out of range, a pointer is NULL or misaligned */
+    PS_E_UNSUPPORTED = 2, /* valid per the paper but not implemented here (e.g. N not a power of two) */
+    PS_E_WORKSPACE = 3,   /* workspace smaller than ps_workspace_size() */
+    PS_E_HIP = 4,         /* a HIP runtime call failed */
+    PS_E_INTERNAL = 5
+} ps_status;
+
+typedef enum ps_dtype { PS_F32 = 0, PS_F64 = 1, PS_I16 = 2 } ps_dtype;
+
+/* Window g_i, i = 0..N-1.  HANN: symmetric sin^2(pi i/(N-1)); HANN_PERIODIC:
+ * sin^2(pi i/N); ACG: the approximate confined Gaussian of Appendix B with
+ * sigma_t = window_param (the paper's default 0.14, Section 3). */
+typedef enum ps_window { PS_WIN_HANN = 0, PS_WIN_HANN_PERIODIC = 1, PS_WIN_ACG = 2 } ps_window;
+
+/* Arithmetic of the S4 frame contractions (Sections 4 and 4.1):
+ *  FP32    plain FP32 vector arithmetic;
+ *  BF16X3  each FP32 operand split into three bfloat16 terms, six cross products
+ *          on the matrix cores with FP32 accumulation;
+ *  FP16X2S each operand scaled per frequency by a power of two and split into two
+ *          float16 terms, three cross products on the matrix cores.
+ * The k-statistic combination and the chunk average are FP64 in every mode. */
+typedef enum ps_precision { PS_PREC_FP32 = 0, PS_PREC_BF16X3 = 1, PS_PREC_FP16X2S = 2 } ps_precision;
+
+/* BATCHED: every chunk of a record in one pass of each kernel.
+ * PER_CHUNK: one short-time estimate (one chunk) per launch, the structure the
+ * paper describes for its own library (Section 10); kept as the reference
+ * "plain" schedule. */
+typedef enum ps_schedule { PS_SCHED_BATCHED = 0, PS_SCHED_PER_CHUNK = 1 } ps_schedule;
+
+#define PS_ORDER_S2 (1u << 2)
+#define PS_ORDER_S3 (1u << 3)
+#define PS_ORDER_S4 (1u << 4)
+
+/* Per-record flags returned by ps_record_info. */
+#define PS_FLAG_EMPTY 1u     /* no complete chunk: every output is NaN */
+#define PS_FLAG_NO_ERRBAR 2u /* Np == 1: error bars are NaN */
+
+typedef struct ps_config {
+    uint32_t struct_size; /* sizeof(ps_config) */
+    uint32_t orders;      /* PS_ORDER_* bitmask, non-zero */
+    int32_t n_channels;   /* 1..4 (Section 7) */
+    int32_t frame_len;    /* N: power of two, 256..8192 */
+    int32_t n_freq;       /* N_f; 0 => floor(f_max * N * dt) + 1 */
+    int32_t m;            /* frames per chunk: >= 2 (S2), >= 3 (S3), >= 4 (S4) */
+    double f_max;         /* used only when n_freq == 0 */
+    double dt;            /* sampling step, > 0 */
+    double window_param;  /* sigma_t for PS_WIN_ACG (> 0) */
+    int32_t window;       /* ps_window */
+    int32_t precision;    /* ps_precision */
+    int32_t schedule;     /* ps_schedule */
+    int32_t n_combos2;    /* channel combinations; 0 => every orbit (see below) */
+    int32_t n_combos3;
+    int32_t n_combos4;
+    const int8_t* combos2; /* host [n_combos2][2]: (a, b) -> C2(a_k, b*_k) */
+    const int8_t* combos3; /* host [n_combos3][3]: (a, b, c) -> C3(a_k, b_l, c*_{k+l}) */
+    const int8_t* combos4; /* host [n_combos4][4]: (a, b, c, d) -> C4(a_k, b*_k, c_l, d*_l) */
+} ps_config;
+/* "Every orbit": combinations related by the symmetries of Section 9 that keep
+ * the output grid are computed once.  S2: (a,b) with a <= b (S2_ba = conj S2_ab).
+ * S3: (a,b,c) with a <= b (S3_bac(k,l) = S3_abc(l,k)).  S4: the lexicographically
+ * smallest of {abcd, badc, cdab, dcba} (S4_badc = conj S4_abcd,
+ * S4_cdab(k,l) = S4_abcd(l,k)).  For 4 channels: 10, 40 and 76 combinations. */
+
+typedef struct ps_record {
+    const void* d_data;     /* sample 0 of channel 0; element type `dtype`, 4/8/2-byte aligned */
+    int64_t n_samples;      /* samples per channel (L) */
+    int64_t channel_stride; /* elements from one channel's sample 0 to the next's */
+    int32_t dtype;          /* ps_dtype; int16 samples are used in LSB units */
+    int32_t reserved;       /* must be 0 */
+} ps_record;
+
+/* Output of one record.  Spectra are FP64 interleaved complex (re, im); error
+ * bars are (sigma_re, sigma_im) pairs.  Layouts: S2 [n_combos2][N_f],
+ * S3 and S4 [n_combos][N_f][N_f] with index [k][l].  Any pointer may be NULL if
+ * its order was not requested.  Units: (input unit)^n * dt^(n-1). */
+typedef struct ps_output {
+    double* d_s2;
+    double* d_s2_err;
+    double* d_s3;
+    double* d_s3_err;
+    double* d_s4;
+    double* d_s4_err;
+} ps_output;
+
+typedef struct ps_plan_info {
+    int32_t frame_len;  /* N */
+    int32_t n_freq;     /* N_f */
+    int32_t n_coef;     /* coefficients kept per frame: 2 N_f - 1 with S3, else N_f */
+    int32_t m;
+    int32_t n_combos2, n_combos3, n_combos4;
+    int32_t reserved;
+    double f_max;       /* (N_f - 1) / (N dt) */
+    double sum_g[5];    /* sum_i g_i^n, n = 0..4, as used by the normalisation */
+    const int8_t* combos2; /* host, owned by the plan */
+    const int8_t* combos3;
+    const int8_t* combos4;
+} ps_plan_info;
+
+/* Validate `cfg`, build the window (FP64 on the host) and the FFT tables, and
+ * pick launch shapes.  Allocates the plan's small device tables on the current
+ * device (synchronous).  On failure *out is NULL. */
+ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out);
+
+/* Free the plan and its device tables (synchronous).  NULL is accepted. */
+ps_status ps_plan_destroy(ps_plan_t plan);
+
+ps_status ps_plan_query(ps_plan_t plan, ps_plan_info* info);
+
+/* Np and PS_FLAG_* for a record of n_samples samples per channel. */
+ps_status ps_record_info(ps_plan_t plan, int64_t n_samples, int64_t* n_chunks, uint32_t* flags);
+
+/* Device workspace (bytes) that ps_execute needs for these records. */
+ps_status ps_workspace_size(ps_plan_t plan, const ps_record* recs, int32_t n_rec, size_t* bytes);
+
+/* Enqueue the whole estimator for n_rec records on `stream`: windowed real FFT
+ * per frame, per-chunk centring and moment sums, k-statistics, FP64 chunk
+ * average and error bars.  outs[i] receives record i.  d_ws must be 256-byte
+ * aligned and at least ps_workspace_size() bytes; its contents are scratch. */
+ps_status ps_execute(ps_plan_t plan, const ps_record* recs, int32_t n_rec, void* d_ws,
+                     size_t ws_bytes, const ps_output* outs, ps_stream_t stream);
+
+/* The first stage alone (Section 3, eq. a_k without the dt factor): for every
+ * frame f < Np*m of every channel, d_coef[c][f][k] = sum_i g_i z_{fN+i}
+ * exp(+2 pi j i k/N), k < n_coef, as interleaved FP32 complex.  d_coef must hold
+ * n_channels * Np * m * n_coef float pairs. */
+ps_status ps_coefficients(ps_plan_t plan, const ps_record* rec, float* d_coef, ps_stream_t stream);
+
+/* Per-stage timing with HIP events recorded on the execution stream.  While
+ * enabled, ps_execute records an event pair around every stage launch;
+ * ps_profile_read waits for those events and returns, per stage, the summed
+ * milliseconds since the previous read: [0] windowed FFT (stage a1), [1] chunk
+ * means, [2] S2, [3] S3, [4] S4, [5] finalize; stage_ms[6..] (if n > 6) receive
+ * the number of launches of stage 0..5.  Timing adds event records between
+ * launches; leave it off outside measurements. */
+ps_status ps_profile_enable(ps_plan_t plan, int32_t on);
+ps_status ps_profile_read(ps_plan_t plan, double* stage_ms, int32_t n);
+
+/* Host only: the "every orbit" combination list of `order` (2, 3 or 4) for
+ * n_channels (1..4) channels, in the order ps_plan_create uses.  With out ==
+ * NULL only the count is returned in *n; otherwise *n is the capacity of `out`
+ * in combinations on input and the count on output. */
+ps_status ps_enumerate_combos(int32_t n_channels, int32_t order, int8_t* out, int32_t* n);
+
+const char* ps_status_string(ps_status s);
+const char* ps_last_error(void);
+int32_t ps_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POLYSPEC_H */

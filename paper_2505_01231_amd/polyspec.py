@@ -1,0 +1,219 @@
+"""Python front end of the HIP polyspectrum library.
+
+PyTorch supplies device memory and the HIP stream; every step of the
+estimator runs inside libpolyspec.so (see include/polyspec.h for the
+definitions, layouts and error behaviour).  There is no CPU fallback: a
+missing library or GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+_WINDOWS = {"hann": L.PS_WIN_HANN, "hann_periodic": L.PS_WIN_HANN_PERIODIC, "acg": L.PS_WIN_ACG}
+_PRECISION = {"fp32": L.PS_PREC_FP32, "bf16x3": L.PS_PREC_BF16X3, "fp16x2s": L.PS_PREC_FP16X2S}
+_SCHEDULE = {"batched": L.PS_SCHED_BATCHED, "per_chunk": L.PS_SCHED_PER_CHUNK}
+_DTYPES = {torch.float32: L.PS_F32, torch.float64: L.PS_F64, torch.int16: L.PS_I16}
+
+
+def enumerate_combos(n_channels: int, order: int):
+    """Every-orbit channel combinations of the given order (host only)."""
+    lib = L.load()
+    n = C.c_int32(0)
+    L.check(lib.ps_enumerate_combos(n_channels, order, None, C.byref(n)), "ps_enumerate_combos")
+    buf = (C.c_int8 * (n.value * order))()
+    L.check(lib.ps_enumerate_combos(n_channels, order, buf, C.byref(n)), "ps_enumerate_combos")
+    return [tuple(buf[i * order:(i + 1) * order]) for i in range(n.value)]
+
+
+def _flat(combos, arity):
+    if combos is None:
+        return 0, None, None
+    flat = [int(c) for cb in combos for c in cb]
+    if len(flat) != arity * len(combos):
+        raise ValueError(f"combinations of order {arity} need {arity} channels each")
+    arr = (C.c_int8 * max(1, len(flat)))(*flat)
+    return len(combos), arr, C.cast(arr, C.POINTER(C.c_int8))
+
+
+@dataclass
+class Spectra:
+    """Outputs of one record (FP64; complex values as trailing (re, im))."""
+    s2: torch.Tensor | None
+    s2_err: torch.Tensor | None
+    s3: torch.Tensor | None
+    s3_err: torch.Tensor | None
+    s4: torch.Tensor | None
+    s4_err: torch.Tensor | None
+    n_chunks: int
+    flags: int
+
+    def complex(self, name: str) -> torch.Tensor:
+        return torch.view_as_complex(getattr(self, name))
+
+
+class Plan:
+    """A configured estimator (ps_plan_t)."""
+
+    def __init__(self, frame_len: int, n_freq: int = 0, m: int = 10, dt: float = 1.0,
+                 orders=(2, 3, 4), n_channels: int = 1, window: str = "acg",
+                 window_param: float = 0.14, precision: str = "fp32", schedule: str = "batched",
+                 f_max: float = 0.0, combos2=None, combos3=None, combos4=None):
+        self._lib = L.load()
+        self._handle = None
+        cfg = L.ps_config()
+        cfg.struct_size = C.sizeof(L.ps_config)
+        cfg.orders = sum(1 << o for o in orders)
+        cfg.n_channels = n_channels
+        cfg.frame_len = frame_len
+        cfg.n_freq = n_freq
+        cfg.m = m
+        cfg.f_max = f_max
+        cfg.dt = dt
+        cfg.window_param = window_param
+        cfg.window = _WINDOWS[window]
+        cfg.precision = _PRECISION[precision]
+        cfg.schedule = _SCHEDULE[schedule]
+        self._keep = []
+        for arity, combos in ((2, combos2), (3, combos3), (4, combos4)):
+            n, arr, ptr = _flat(combos, arity)
+            setattr(cfg, f"n_combos{arity}", n)
+            setattr(cfg, f"combos{arity}", ptr)
+            self._keep.append(arr)
+        h = C.c_void_p()
+        L.check(self._lib.ps_plan_create(C.byref(cfg), C.byref(h)), "ps_plan_create")
+        self._handle = h
+        info = L.ps_plan_info()
+        L.check(self._lib.ps_plan_query(h, C.byref(info)), "ps_plan_query")
+        self.frame_len = info.frame_len
+        self.n_freq = info.n_freq
+        self.n_coef = info.n_coef
+        self.m = info.m
+        self.f_max = info.f_max
+        self.sum_g = list(info.sum_g)
+        self.n_channels = n_channels
+        self.orders = tuple(orders)
+        self.combos2 = [tuple(info.combos2[i * 2:(i + 1) * 2]) for i in range(info.n_combos2)]
+        self.combos3 = [tuple(info.combos3[i * 3:(i + 1) * 3]) for i in range(info.n_combos3)]
+        self.combos4 = [tuple(info.combos4[i * 4:(i + 1) * 4]) for i in range(info.n_combos4)]
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if self._handle is not None:
+            self._lib.ps_plan_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------
+    def record(self, x: torch.Tensor) -> L.ps_record:
+        """ps_record for a device tensor [L] (one channel) or [C, L] (channels)."""
+        if not x.is_cuda:
+            raise ValueError("input must be a device tensor")
+        if x.dtype not in _DTYPES:
+            raise ValueError(f"unsupported dtype {x.dtype}")
+        if x.dim() == 1:
+            x = x.unsqueeze(0)
+        if x.dim() != 2 or x.shape[0] != self.n_channels:
+            raise ValueError(f"expected [{self.n_channels}, L] samples")
+        if x.stride(1) != 1:
+            raise ValueError("samples must be contiguous along time")
+        r = L.ps_record()
+        r.d_data = x.data_ptr()
+        r.n_samples = x.shape[1]
+        r.channel_stride = x.stride(0) if x.shape[0] > 1 else x.shape[1]
+        r.dtype = _DTYPES[x.dtype]
+        r.reserved = 0
+        return r
+
+    def record_info(self, n_samples: int):
+        n = C.c_int64()
+        fl = C.c_uint32()
+        L.check(self._lib.ps_record_info(self._handle, n_samples, C.byref(n), C.byref(fl)), "ps_record_info")
+        return n.value, fl.value
+
+    def workspace_bytes(self, xs) -> int:
+        recs = (L.ps_record * len(xs))(*[self.record(x) for x in xs])
+        n = C.c_size_t()
+        L.check(self._lib.ps_workspace_size(self._handle, recs, len(xs), C.byref(n)), "ps_workspace_size")
+        return n.value
+
+    def allocate_outputs(self, device) -> Spectra:
+        nf = self.n_freq
+        f64 = dict(dtype=torch.float64, device=device)
+        n2, n3, n4 = len(self.combos2), len(self.combos3), len(self.combos4)
+        return Spectra(
+            s2=torch.empty((n2, nf, 2), **f64) if n2 else None,
+            s2_err=torch.empty((n2, nf, 2), **f64) if n2 else None,
+            s3=torch.empty((n3, nf, nf, 2), **f64) if n3 else None,
+            s3_err=torch.empty((n3, nf, nf, 2), **f64) if n3 else None,
+            s4=torch.empty((n4, nf, nf, 2), **f64) if n4 else None,
+            s4_err=torch.empty((n4, nf, nf, 2), **f64) if n4 else None,
+            n_chunks=0, flags=0)
+
+    @staticmethod
+    def _ptr(t):
+        return None if t is None else t.data_ptr()
+
+    def execute(self, xs, workspace: torch.Tensor | None = None, outputs=None, stream=None):
+        """Enqueue the estimator for one tensor or a list of tensors (records).
+        Returns a list of Spectra (or one Spectra for a single tensor)."""
+        single = isinstance(xs, torch.Tensor)
+        if single:
+            xs = [xs]
+        device = xs[0].device
+        recs = (L.ps_record * len(xs))(*[self.record(x) for x in xs])
+        need = C.c_size_t()
+        L.check(self._lib.ps_workspace_size(self._handle, recs, len(xs), C.byref(need)), "ps_workspace_size")
+        if workspace is None or workspace.numel() < need.value:
+            workspace = torch.empty(need.value, dtype=torch.uint8, device=device)
+        if outputs is None:
+            outputs = [self.allocate_outputs(device) for _ in xs]
+        outs = (L.ps_output * len(xs))()
+        for i, o in enumerate(outputs):
+            n, fl = self.record_info(recs[i].n_samples)
+            o.n_chunks, o.flags = n, fl
+            outs[i] = L.ps_output(self._ptr(o.s2), self._ptr(o.s2_err), self._ptr(o.s3),
+                                  self._ptr(o.s3_err), self._ptr(o.s4), self._ptr(o.s4_err))
+        st = torch.cuda.current_stream(device) if stream is None else stream
+        L.check(self._lib.ps_execute(self._handle, recs, len(xs), workspace.data_ptr(), workspace.numel(),
+                                     outs, C.c_void_p(st.cuda_stream)), "ps_execute")
+        self._last_workspace = workspace
+        return outputs[0] if single else outputs
+
+    STAGES = ("fft", "mean", "s2", "s3", "s4", "finalize")
+
+    def profile(self, on: bool = True):
+        """Turn per-stage HIP-event timing inside ps_execute on or off."""
+        L.check(self._lib.ps_profile_enable(self._handle, int(bool(on))), "ps_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{stage: (milliseconds, launches)} summed since the previous read."""
+        buf = (C.c_double * 12)()
+        L.check(self._lib.ps_profile_read(self._handle, buf, 12), "ps_profile_read")
+        return {name: (buf[i], int(buf[6 + i])) for i, name in enumerate(self.STAGES)}
+
+    def coefficients(self, x: torch.Tensor, stream=None) -> torch.Tensor:
+        """Stage a1 alone: complex64 [C, Np*m, n_coef] (without the dt factor)."""
+        rec = self.record(x)
+        n_chunks, _ = self.record_info(rec.n_samples)
+        F = n_chunks * self.m
+        out = torch.empty((self.n_channels, F, self.n_coef, 2), dtype=torch.float32, device=x.device)
+        st = torch.cuda.current_stream(x.device) if stream is None else stream
+        L.check(self._lib.ps_coefficients(self._handle, C.byref(rec), out.data_ptr(),
+                                          C.c_void_p(st.cuda_stream)), "ps_coefficients")
+        return torch.view_as_complex(out)

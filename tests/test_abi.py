@@ -1,0 +1,163 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function include/polyspec.h declares, the ctypes structures match the C
+layout, host-side validation rejects bad configurations before touching the
+device, and the channel-combination orbits are right."""
+import ctypes as C
+import itertools
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2505_01231_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "polyspec.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ps_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    declared = _declared_functions()
+    assert set(declared) == set(L.EXPORTED), declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (ps_[a-z_0-9]+)\b", out))
+    assert set(declared) <= exported
+
+
+def test_version_and_status_strings():
+    lib = L.load()
+    assert lib.ps_abi_version() == 1
+    for s in range(6):
+        assert L.status_string(s).startswith("PS_")
+
+
+_LAYOUT_PROBE = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "polyspec.h"
+#define P(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  printf("ps_config %zu\n", sizeof(ps_config));
+  printf("ps_record %zu\n", sizeof(ps_record));
+  printf("ps_output %zu\n", sizeof(ps_output));
+  printf("ps_plan_info %zu\n", sizeof(ps_plan_info));
+  P(ps_config, dt) P(ps_config, window) P(ps_config, n_combos4) P(ps_config, combos2) P(ps_config, combos4)
+  P(ps_record, n_samples) P(ps_record, dtype) P(ps_output, d_s4_err)
+  P(ps_plan_info, f_max) P(ps_plan_info, sum_g) P(ps_plan_info, combos4)
+  return 0;
+}
+"""
+
+
+def test_ctypes_layouts_match_header(tmp_path):
+    src = tmp_path / "probe.c"
+    src.write_text(_LAYOUT_PROBE)
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                             check=True).stdout.splitlines())
+    py = {
+        "ps_config": C.sizeof(L.ps_config), "ps_record": C.sizeof(L.ps_record),
+        "ps_output": C.sizeof(L.ps_output), "ps_plan_info": C.sizeof(L.ps_plan_info),
+    }
+    for k, v in py.items():
+        assert int(got[k]) == v, k
+    for key, val in got.items():
+        if "." in key:
+            struct, field = key.split(".")
+            assert getattr(getattr(L, struct), field).offset == int(val), key
+
+
+def _cfg(**kw):
+    cfg = L.ps_config()
+    cfg.struct_size = C.sizeof(L.ps_config)
+    cfg.orders = L.PS_ORDER_S2 | L.PS_ORDER_S3 | L.PS_ORDER_S4
+    cfg.n_channels = 1
+    cfg.frame_len = 256
+    cfg.n_freq = 64
+    cfg.m = 10
+    cfg.dt = 1.0
+    cfg.window = L.PS_WIN_HANN
+    cfg.window_param = 0.14
+    for k, v in kw.items():
+        setattr(cfg, k, v)
+    return cfg
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(frame_len=300), L.PS_E_UNSUPPORTED),          # not a power of two
+    (dict(frame_len=128), L.PS_E_UNSUPPORTED),          # below the supported range
+    (dict(frame_len=16384), L.PS_E_UNSUPPORTED),
+    (dict(m=3), L.PS_E_INVALID_ARG),                    # S4 needs m >= 4
+    (dict(m=2, orders=L.PS_ORDER_S3), L.PS_E_INVALID_ARG),
+    (dict(m=1, orders=L.PS_ORDER_S2), L.PS_E_INVALID_ARG),
+    (dict(n_freq=66), L.PS_E_INVALID_ARG),              # 2 (Nf - 1) > N/2 with S3
+    (dict(n_freq=130, orders=L.PS_ORDER_S2), L.PS_E_INVALID_ARG),
+    (dict(n_channels=5), L.PS_E_INVALID_ARG),
+    (dict(n_channels=0), L.PS_E_INVALID_ARG),
+    (dict(dt=0.0), L.PS_E_INVALID_ARG),
+    (dict(dt=float("nan")), L.PS_E_INVALID_ARG),
+    (dict(orders=0), L.PS_E_INVALID_ARG),
+    (dict(orders=1 << 5), L.PS_E_INVALID_ARG),
+    (dict(struct_size=8), L.PS_E_INVALID_ARG),
+    (dict(window=7), L.PS_E_INVALID_ARG),
+    (dict(window=L.PS_WIN_ACG, window_param=0.0), L.PS_E_INVALID_ARG),
+    (dict(precision=9), L.PS_E_INVALID_ARG),
+    (dict(schedule=4), L.PS_E_INVALID_ARG),
+    (dict(n_freq=0, f_max=-1.0), L.PS_E_INVALID_ARG),
+])
+def test_plan_validation_rejects_before_device_work(kw, status):
+    lib = L.load()
+    h = C.c_void_p(123)
+    cfg = _cfg(**kw)
+    assert lib.ps_plan_create(C.byref(cfg), C.byref(h)) == status
+    assert h.value is None
+    assert L.last_error()
+
+
+def test_bad_combinations_rejected():
+    lib = L.load()
+    arr = (C.c_int8 * 2)(0, 2)
+    cfg = _cfg(n_channels=2, orders=L.PS_ORDER_S2, n_combos2=1, combos2=C.cast(arr, C.POINTER(C.c_int8)))
+    h = C.c_void_p()
+    assert lib.ps_plan_create(C.byref(cfg), C.byref(h)) == L.PS_E_INVALID_ARG
+    cfg = _cfg(n_channels=2, orders=L.PS_ORDER_S2, n_combos2=1)   # NULL list with a count
+    assert lib.ps_plan_create(C.byref(cfg), C.byref(h)) == L.PS_E_INVALID_ARG
+
+
+def _orbits(n_ch, order):
+    """Independent orbit enumeration: canonical representative = lexicographic
+    minimum over the grid-preserving symmetry group of Section 9."""
+    if order == 2:
+        maps = [lambda c: c, lambda c: (c[1], c[0])]
+    elif order == 3:
+        maps = [lambda c: c, lambda c: (c[1], c[0], c[2])]
+    else:
+        maps = [lambda c: c, lambda c: (c[1], c[0], c[3], c[2]), lambda c: (c[2], c[3], c[0], c[1]),
+                lambda c: (c[3], c[2], c[1], c[0])]
+    reps = []
+    for c in itertools.product(range(n_ch), repeat=order):
+        if c == min(f(c) for f in maps):
+            reps.append(c)
+    return reps
+
+
+@pytest.mark.parametrize("n_ch", [1, 2, 3, 4])
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_combination_orbits(n_ch, order):
+    from paper_2505_01231_amd.polyspec import enumerate_combos
+    got = enumerate_combos(n_ch, order)
+    assert got == _orbits(n_ch, order)
+    if n_ch == 4:
+        assert len(got) == {2: 10, 3: 40, 4: 76}[order]
+    # every ordered combination is reachable from exactly one representative
+    assert len(set(got)) == len(got)

@@ -1,0 +1,239 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Error metric, per spectrum s (and per error-bar array):
+    err_s = max_grid |S_gpu - S_oracle| / max_grid |S_oracle|      (complex modulus)
+Tolerance 1e-5 for every spectrum and error bar (the accuracy bar the
+mixed-precision path must meet); bit-exact checks where the result is
+integer-like (NaN flags, determinism, schedule equivalence up to FP64 order).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2505_01231_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch.device("cuda:0")
+
+
+def run_gpu(z, dev, **plan_kw):
+    from paper_2505_01231_amd import Plan
+    x = torch.from_numpy(np.ascontiguousarray(z)).to(dev)
+    with Plan(**plan_kw) as p:
+        out = p.execute(x)
+        torch.cuda.synchronize()
+        res = {"n_chunks": out.n_chunks, "flags": out.flags}
+        for key in ("s2", "s3", "s4"):
+            t = getattr(out, key)
+            if t is not None:
+                res[key] = torch.view_as_complex(t).cpu().numpy()
+                res[key + "_err"] = getattr(out, key + "_err").cpu().numpy()
+        res["plan"] = dict(n_freq=p.n_freq, combos2=p.combos2, combos3=p.combos3, combos4=p.combos4)
+    return res
+
+
+def rel_err(a, b):
+    scale = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / scale) if scale > 0 else float(np.max(np.abs(a - b)))
+
+
+def compare(gpu, ref, keys=("s2", "s3", "s4"), tol=TOL, label=""):
+    report = {}
+    for k in keys:
+        if k not in gpu:
+            continue
+        e = rel_err(gpu[k], ref[k])
+        ee = rel_err(gpu[k + "_err"], ref[k + "_err"])
+        report[k] = (e, ee)
+    say(label, {k: f"{v[0]:.2e}/{v[1]:.2e}" for k, v in report.items()})
+    for k, (e, ee) in report.items():
+        assert e <= tol, (label, k, e)
+        assert ee <= tol, (label, k + "_err", ee)
+    return report
+
+
+WIN = {"hann": "hann", "acg": "acg", "hann_periodic": "hann_periodic"}
+
+
+def both(z, dev, N, Nf, m, dt=1.0, window="acg", orders=(2, 3, 4), combos2=None, combos3=None,
+         combos4=None, n_channels=1, **kw):
+    gpu = run_gpu(z, dev, frame_len=N, n_freq=Nf, m=m, dt=dt, window=window, orders=orders,
+                  n_channels=n_channels, combos2=combos2, combos3=combos3, combos4=combos4, **kw)
+    ref = O.polyspectra(z, N, Nf, m, dt=dt, window_kind=window, orders=orders,
+                        combos2=gpu["plan"]["combos2"], combos3=gpu["plan"]["combos3"],
+                        combos4=gpu["plan"]["combos4"])
+    return gpu, ref
+
+
+# ---------------------------------------------------------------- stage a1
+@pytest.mark.parametrize("N,dtype", [(256, np.float64), (1024, np.float32), (8192, np.float32),
+                                     (2048, np.int16), (512, np.float64)])
+def test_coefficients_match_oracle(dev, N, dtype):
+    from paper_2505_01231_amd import Plan
+    say("coefficients", N, dtype.__name__)
+    m = 4
+    Nf = N // 4
+    if dtype == np.int16:
+        z = np.clip(np.rint(synth.ar2_chi2(N * m * 3 + 17, seed=7) * 300), -32768, 32767).astype(np.int16)
+    else:
+        z = synth.ar2_chi2(N * m * 3 + 17, seed=7, dtype=dtype)
+    with Plan(frame_len=N, n_freq=Nf, m=m, window="acg") as p:
+        a = p.coefficients(torch.from_numpy(z).to(dev))
+        torch.cuda.synchronize()
+        a = a.cpu().numpy()[0]
+        K = p.n_coef
+    g = O.window("acg", N)
+    fr = O.chunk_frames(z, N, m).reshape(-1, N)
+    ref = O.coefficients(fr, g, 1.0, K)
+    e = rel_err(a, ref)
+    say("  coef rel err", e)
+    assert a.shape == ref.shape
+    assert e < 2e-6
+
+
+# ---------------------------------------------------------------- configurations
+def test_white_noise_config(dev):
+    """51,200 float64 white Gaussian samples, N = 256, Hann, N_f = 64, m = 10."""
+    say("white-noise config")
+    z = synth.white_gaussian(51_200, seed=1)
+    gpu, ref = both(z, dev, 256, 64, 10, window="hann")
+    assert gpu["n_chunks"] == 20
+    compare(gpu, ref, label="white")
+    # physics on the GPU result: flat S2 = sigma^2 dt = 1, S3 and S4 consistent with zero
+    s2 = gpu["s2"][0]
+    assert abs(np.mean(s2.real) - 1) < 0.05
+    for k in ("s3", "s4"):
+        z_re = gpu[k][0].real / gpu[k + "_err"][0][..., 0]
+        assert np.mean(np.abs(z_re) > 3.5) < 0.02
+
+
+def test_ar2_subset(dev):
+    """The AR(2)/chi-square signal (r = 0.95, theta = 0.3 pi) on its 2^20-sample
+    subset: N = 4096, acG window, N_f = 512, m = 10 (25 chunks, 8 tile rows)."""
+    say("ar2 subset N=4096 Nf=512")
+    z = synth.ar2_chi2(1 << 20, seed=2)
+    gpu, ref = both(z, dev, 4096, 512, 10, window="acg")
+    assert gpu["n_chunks"] == 25
+    compare(gpu, ref, label="ar2-4096")
+
+
+def test_ragged_grid_and_tail(dev):
+    """N_f not a multiple of the tile, leftover samples, odd m, dt != 1."""
+    say("ragged N=1024 Nf=200 m=7")
+    z = synth.ar2_chi2(1024 * 7 * 9 + 1000, seed=12, r=0.9, dtype=np.float32)
+    gpu, ref = both(z, dev, 1024, 200, 7, dt=0.37, window="hann_periodic")
+    assert gpu["n_chunks"] == 9
+    compare(gpu, ref, label="ragged")
+
+
+@pytest.mark.parametrize("orders,Nf", [((2,), 129), ((3,), 65), ((4,), 100), ((2, 4), 128)])
+def test_order_subsets(dev, orders, Nf):
+    say("orders", orders, Nf)
+    z = synth.ar2_chi2(256 * 6 * 5, seed=13, dtype=np.float64)
+    gpu, ref = both(z, dev, 256, Nf, 6, window="acg", orders=orders)
+    compare(gpu, ref, keys=tuple(f"s{o}" for o in orders), label=f"orders{orders}")
+
+
+def test_large_m_uses_several_frame_batches(dev):
+    say("m=37")
+    z = synth.ar2_chi2(512 * 37 * 4, seed=14, dtype=np.float32)
+    gpu, ref = both(z, dev, 512, 96, 37, window="acg")
+    compare(gpu, ref, label="m37")
+
+
+def test_cross_channel_s2_s3(dev):
+    """Two channels, explicit combinations (Section 7)."""
+    say("cross channels")
+    rng = np.random.default_rng(15)
+    s = synth.ar2_chi2(256 * 8 * 12 + 3, seed=15, r=0.9, dtype=np.float64)
+    z = np.stack([s[:-3] + 0.3 * rng.standard_normal(len(s) - 3), s[3:] ** 2 - 1.0])
+    gpu, ref = both(z, dev, 256, 40, 8, window="hann", n_channels=2, orders=(2, 3),
+                    combos2=[(0, 1), (1, 0), (1, 1)], combos3=[(0, 1, 1), (1, 0, 0), (0, 0, 1), (1, 1, 0)])
+    compare(gpu, ref, keys=("s2", "s3"), label="cross")
+
+
+# ---------------------------------------------------------------- schedule, determinism, edges
+def test_per_chunk_schedule_matches_batched(dev):
+    say("per-chunk vs batched")
+    z = synth.ar2_chi2(1024 * 10 * 13, seed=16, dtype=np.float32)
+    kw = dict(frame_len=1024, n_freq=256, m=10, window="acg")
+    a = run_gpu(z, dev, schedule="batched", **kw)
+    b = run_gpu(z, dev, schedule="per_chunk", **kw)
+    for k in ("s2", "s3", "s4"):
+        assert rel_err(a[k], b[k]) < 1e-12, k
+        assert rel_err(a[k + "_err"], b[k + "_err"]) < 1e-9, k
+
+
+def test_deterministic(dev):
+    say("determinism")
+    z = synth.ar2_chi2(2048 * 10 * 6, seed=17, dtype=np.float32)
+    kw = dict(frame_len=2048, n_freq=512, m=10, window="acg")
+    a = run_gpu(z, dev, **kw)
+    b = run_gpu(z, dev, **kw)
+    for k in ("s2", "s3", "s4", "s2_err", "s3_err", "s4_err"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+def test_edge_records(dev):
+    """Several records in one call: no complete chunk (NaN), one chunk (NaN error
+    bars), and a normal record."""
+    from paper_2505_01231_amd import Plan
+    say("edge records")
+    N, m, Nf = 256, 4, 32
+    z = synth.ar2_chi2(N * m * 5, seed=18, dtype=np.float32)
+    xs = [torch.from_numpy(z[: N * m - 1]).to(dev), torch.from_numpy(z[: N * m + 5]).to(dev),
+          torch.from_numpy(z).to(dev)]
+    with Plan(frame_len=N, n_freq=Nf, m=m, window="hann") as p:
+        outs = p.execute(xs)
+        torch.cuda.synchronize()
+        assert [o.n_chunks for o in outs] == [0, 1, 5]
+        assert outs[0].flags == 1 and outs[1].flags == 2 and outs[2].flags == 0
+        for key in ("s2", "s3", "s4"):
+            assert torch.isnan(getattr(outs[0], key)).all()
+            assert torch.isnan(getattr(outs[0], key + "_err")).all()
+            assert torch.isfinite(getattr(outs[1], key)).all()
+            assert torch.isnan(getattr(outs[1], key + "_err")).all()
+        ref = O.polyspectra(z, N, Nf, m, window_kind="hann")
+        for key in ("s2", "s3", "s4"):
+            assert rel_err(torch.view_as_complex(getattr(outs[2], key)).cpu().numpy(), ref[key]) < TOL
+        one = O.polyspectra(z[: N * m + 5], N, Nf, m, window_kind="hann")
+        assert rel_err(torch.view_as_complex(outs[1].s4).cpu().numpy(), one["s4"]) < TOL
+
+
+def test_errors_are_reported_not_faulted(dev):
+    from paper_2505_01231_amd import Plan
+    from paper_2505_01231_amd._lib import PolyspecError
+    say("error paths")
+    z = torch.zeros(256 * 40, device=dev)
+    with Plan(frame_len=256, n_freq=32, m=4) as p:
+        small = torch.empty(16, dtype=torch.uint8, device=dev)
+        import ctypes as C
+        from paper_2505_01231_amd import _lib as L
+        rec = (L.ps_record * 1)(p.record(z))
+        outs = (L.ps_output * 1)()
+        st = L.load().ps_execute(p._handle, rec, 1, small.data_ptr(), small.numel(), outs, None)
+        assert st == L.PS_E_WORKSPACE
+        with pytest.raises(ValueError):
+            p.execute(torch.zeros((2, 256 * 40), device=dev))   # two channels for a one-channel plan
+        x = torch.zeros(256 * 40, device=dev)
+        rec = (L.ps_record * 1)(p.record(x))
+        rec[0].dtype = 9
+        assert L.load().ps_execute(p._handle, rec, 1, small.data_ptr(), small.numel(), outs, None) \
+            == L.PS_E_INVALID_ARG
+        with pytest.raises(PolyspecError):
+            L.check(L.PS_E_INVALID_ARG, "x")
