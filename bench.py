@@ -79,6 +79,9 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the per-chunk FP32 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain elementwise copy of 1 GiB (3 launches) so that profiler "
+                         "byte counters can be scaled against a kernel of known traffic")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -95,6 +98,14 @@ def main(argv=None):
     from paper_2505_01231_amd import Plan, synth
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)          # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del a, b
+        log("copy calibration: 3 x (1 GiB read + 1 GiB write)")
     log("generating input")
     z = synth.ar2_chi2(N_SAMPLES, seed=SEED)
     x = torch.from_numpy(z).to(dev)
