@@ -76,7 +76,9 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--precision", default="bf16x3")
+    ap.add_argument("--fp32-steps", type=int, default=3,
+                    help="timed steps of the batched all-FP32 path (for mixed-vs-FP32)")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the per-chunk FP32 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -155,9 +157,33 @@ def main(argv=None):
             torch.cuda.synchronize()
             plain = N_SAMPLES * args.plain_steps / (time.perf_counter() - t0)
         log(f"plain per-chunk path {plain:.3e} samples/s")
-    batched_fp32 = None
-    if args.precision == "fp32":
-        batched_fp32 = value
+    batched_fp32 = value if args.precision == "fp32" else None
+    if batched_fp32 is None and args.fp32_steps > 0:
+        with Plan(frame_len=N, n_freq=NF, m=M, window="acg", precision="fp32") as pf:
+            wsf = torch.empty(pf.workspace_bytes([x]), dtype=torch.uint8, device=dev)
+            of = [pf.allocate_outputs(dev)]
+            pf.execute([x], workspace=wsf, outputs=of)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.fp32_steps):
+                pf.execute([x], workspace=wsf, outputs=of)
+            torch.cuda.synchronize()
+            batched_fp32 = N_SAMPLES * args.fp32_steps / (time.perf_counter() - t0)
+            del wsf, of
+        log(f"batched fp32 path {batched_fp32:.3e} samples/s")
+
+    # S4 on the matrix cores: executed and useful work of one launch.
+    s4_ms, s4_n = stages["s4"]
+    s4_avg_ms = s4_ms / max(1, s4_n)
+    n_tiles = (NF // 64) * (NF // 64 + 1) // 2
+    s4_info = {"avg_launch_ms": s4_avg_ms,
+               "useful_tflops": 10.0 * (NF * (NF + 1) / 2) * n_frames / (s4_avg_ms * 1e-3) / 1e12}
+    if args.precision != "fp32":
+        # 64 x 64 tile, 4 waves x 4 blocks x 5 sums x 2 (K = 64) MFMA 16x16x32 per chunk
+        mfma_flops = n_tiles * n_chunks * 4 * 4 * 5 * 2 * (16 * 16 * 32 * 2)
+        s4_info.update({"mfma_executed_tflops": mfma_flops / (s4_avg_ms * 1e-3) / 1e12,
+                        "mfma_peak_tflops": 2500.0,
+                        "mfma_frac_of_peak": mfma_flops / (s4_avg_ms * 1e-3) / 2.5e15})
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(z)
     if cpu:
@@ -190,8 +216,11 @@ def main(argv=None):
             "flops_per_launch": s3_flops_per_launch(n_frames, NF),
         },
         "cpu_baseline": cpu,
-        "paths": {"batched_fp32": batched_fp32, "per_chunk_fp32": plain,
+        "paths": {"main": args.precision, "main_value": value, "batched_fp32": batched_fp32,
+                  "per_chunk_fp32": plain,
+                  "speedup_vs_batched_fp32": (value / batched_fp32) if batched_fp32 else None,
                   "speedup_vs_per_chunk_fp32": (value / plain) if plain else None},
+        "s4_matrix_cores": s4_info,
         "stage_ms_per_step": stage_ms,
     }
     print(json.dumps(line), flush=True)

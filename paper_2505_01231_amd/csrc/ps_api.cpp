@@ -148,9 +148,8 @@ int choose_split_vec(int Nf, int64_t n_chunks, int n_cu) {
 struct Layout {
     int64_t Np = 0, F = 0;
     int chunk_frames = 0;   // frames resident in the coefficient buffer
-    int chunk_rows = 0;     // chunks resident in the mean buffer
     int split2 = 1, split3_sym = 1, split3_full = 1, split4 = 1;
-    size_t off_coef = 0, off_mean = 0, off_p2 = 0, off_p3 = 0, off_p4 = 0, total = 0;
+    size_t off_coef = 0, off_p2 = 0, off_p3 = 0, off_p4 = 0, total = 0;
     std::vector<size_t> p3_off, p4_off;
     size_t p2_stride = 0;
 };
@@ -161,7 +160,6 @@ Layout layout_for(const ps_plan_s* p, int64_t n_samples) {
     L.F = L.Np * p->m;
     const bool per_chunk = p->schedule == PS_SCHED_PER_CHUNK;
     L.chunk_frames = per_chunk ? p->m : (int)L.F;
-    L.chunk_rows = per_chunk ? 1 : (int)L.Np;
     if (!per_chunk) {
         L.split2 = choose_split_vec(p->Nf, L.Np, p->n_cu);
         L.split3_sym = choose_split(p->n_tiles_sym, L.Np, p->n_cu * p->bpc_s3);
@@ -171,8 +169,6 @@ Layout layout_for(const ps_plan_s* p, int64_t n_samples) {
     size_t off = 0;
     L.off_coef = off;
     off = align256(off + (size_t)p->C * L.chunk_frames * p->K * sizeof(float2));
-    L.off_mean = off;
-    off = align256(off + (size_t)p->C * L.chunk_rows * p->K * sizeof(float2));
     L.off_p2 = off;
     L.p2_stride = align256((size_t)L.split2 * 4 * p->Nf * sizeof(double));
     off += (size_t)p->n2() * L.p2_stride;
@@ -309,7 +305,7 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
         return fail(PS_E_INVALID_ARG, "acG window needs sigma_t > 0");
     if (cfg->precision < PS_PREC_FP32 || cfg->precision > PS_PREC_FP16X2S)
         return fail(PS_E_INVALID_ARG, "unknown precision %d", cfg->precision);
-    if (cfg->precision != PS_PREC_FP32)
+    if (cfg->precision == PS_PREC_FP16X2S)
         return fail(PS_E_UNSUPPORTED, "precision %d not available in this build", cfg->precision);
     if (cfg->schedule != PS_SCHED_BATCHED && cfg->schedule != PS_SCHED_PER_CHUNK)
         return fail(PS_E_INVALID_ARG, "unknown schedule %d", cfg->schedule);
@@ -428,7 +424,7 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
         p->n_cu = std::max(1, prop.multiProcessorCount);
     p->bpc_s3 = ps::s3_blocks_per_cu();
-    p->bpc_s4 = ps::s4_blocks_per_cu();
+    p->bpc_s4 = p->precision == PS_PREC_FP32 ? ps::s4_blocks_per_cu() : ps::s4_mfma_blocks_per_cu();
     *out = p;
     return PS_OK;
 }
@@ -566,9 +562,7 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
         }
         char* ws = static_cast<char*>(d_ws);
         float2* coef = reinterpret_cast<float2*>(ws + L.off_coef);
-        float2* mean = reinterpret_cast<float2*>(ws + L.off_mean);
         const int64_t coef_cs = (int64_t)L.chunk_frames * p->K;
-        const int64_t mean_cs = (int64_t)L.chunk_rows * p->K;
         const bool per_chunk = p->schedule == PS_SCHED_PER_CHUNK;
         const int64_t n_steps = per_chunk ? L.Np : 1;
 
@@ -594,24 +588,19 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
                 PS_HIP(ps::launch_window_rfft(fa, st));
             }
 
-            ps::MeanArgs ma{};
-            ma.coef = coef;
-            ma.coef_chan_stride = coef_cs;
-            ma.mean = mean;
-            ma.mean_chan_stride = mean_cs;
-            ma.K = p->K;
-            ma.m = m;
-            ma.chunk0 = c_lo;
-            ma.n_chunks = c_hi - c_lo;
-            ma.coef_chunk0 = c_lo;
-            ma.mean_chunk0 = c_lo;
-            ma.n_channels = p->C;
+            ps::CentreArgs ca{};
+            ca.coef = coef;
+            ca.coef_chan_stride = coef_cs;
+            ca.K = p->K;
+            ca.m = m;
+            ca.n_chunks = c_hi - c_lo;
+            ca.n_channels = p->C;
             {
                 StageTimer t(p, st, 1);
-                PS_HIP(ps::launch_chunk_mean(ma, st));
+                PS_HIP(ps::launch_centre(ca, st));
             }
 
-            ps::CoefView cv{coef, mean, coef_cs, mean_cs, p->K, m, c_lo, c_lo};
+            ps::CoefView cv{coef, coef_cs, p->K, m, c_lo};
             const int acc = step > 0 ? 1 : 0;
             for (int i = 0; i < p->n2(); ++i) {
                 ps::S2Args a{};
@@ -657,7 +646,11 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
                 a.accumulate = acc;
                 a.gamma = gamma;
                 StageTimer t(p, st, 4);
-                PS_HIP(ps::launch_s4_single(a, st));
+                if (p->precision == PS_PREC_FP32) {
+                    PS_HIP(ps::launch_s4_single(a, st));
+                } else {
+                    PS_HIP(ps::launch_s4_mfma(a, st));
+                }
             }
         }
 

@@ -1,6 +1,6 @@
-// Stage a1: windowed real FFT of every frame (Section 3, eq. a_k) and the
-// per-chunk mean of the coefficients used for centring (the k-statistics of
-// Section 4.1 in their centred form, Appendix H).
+// Stage a1: windowed real FFT of every frame (Section 3, eq. a_k), and the
+// per-chunk centring a' = a - mean_f a that the k-statistics of Section 4.1
+// need in their centred form (Appendix H).
 //
 //   a_k = sum_{i<N} g_i z_i exp(+2 pi j i k / N),  k < K        (dt folded into the output scale)
 //
@@ -159,15 +159,11 @@ hipError_t launch_n(const FftArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_chunk_mean(const float2* __restrict__ coef, int64_t coef_cs,
-                                                    float2* __restrict__ mean, int64_t mean_cs, int K,
-                                                    int m, int chunk0, int coef_chunk0,
-                                                    int mean_chunk0) {
+// a_k(f) -= (1/m) sum_{f' in chunk} a_k(f'), in place, one thread per (chunk, k).
+__global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64_t coef_cs, int K, int m) {
     const int k = blockIdx.x * 256 + threadIdx.x;
-    const int c = chunk0 + blockIdx.y;
-    const int ch = blockIdx.z;
     if (k >= K) return;
-    const float2* p = coef + ch * coef_cs + (int64_t)(c - coef_chunk0) * m * K + k;
+    float2* p = coef + blockIdx.z * coef_cs + (int64_t)blockIdx.y * m * K + k;
     float sr = 0.f, si = 0.f;
     for (int f = 0; f < m; ++f) {
         const float2 v = p[(int64_t)f * K];
@@ -175,7 +171,11 @@ __global__ __launch_bounds__(256) void k_chunk_mean(const float2* __restrict__ c
         si += v.y;
     }
     const float inv = 1.0f / (float)m;
-    mean[ch * mean_cs + (int64_t)(c - mean_chunk0) * K + k] = make_float2(sr * inv, si * inv);
+    const float mr = sr * inv, mi = si * inv;
+    for (int f = 0; f < m; ++f) {
+        const float2 v = p[(int64_t)f * K];
+        p[(int64_t)f * K] = make_float2(v.x - mr, v.y - mi);
+    }
 }
 
 }  // namespace
@@ -193,11 +193,10 @@ hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s) {
     }
 }
 
-hipError_t launch_chunk_mean(const MeanArgs& a, hipStream_t s) {
+hipError_t launch_centre(const CentreArgs& a, hipStream_t s) {
     if (a.n_chunks <= 0) return hipSuccess;
     dim3 grid((a.K + 255) / 256, a.n_chunks, a.n_channels);
-    k_chunk_mean<<<grid, 256, 0, s>>>(a.coef, a.coef_chan_stride, a.mean, a.mean_chan_stride, a.K,
-                                      a.m, a.chunk0, a.coef_chunk0, a.mean_chunk0);
+    k_centre<<<grid, 256, 0, s>>>(a.coef, a.coef_chan_stride, a.K, a.m);
     return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@ namespace ps {
 constexpr int kTile = 64;
 // Frames staged in LDS at once by the moment kernels.
 constexpr int kFrameBatch = 16;
+constexpr int kFrameBatchSmall = 10;
 
 // ---------------------------------------------------------------- stage a1
 struct FftArgs {
@@ -32,27 +33,23 @@ struct FftArgs {
 };
 hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s);
 
-struct MeanArgs {
-    const float2* coef;     // [C][frames][K]
+// In-place centring: a_k(f) -= mean over the m frames of its chunk.
+struct CentreArgs {
+    float2* coef;           // [C][n_chunks * m][K]
     int64_t coef_chan_stride;
-    float2* mean;           // [C][chunks][K]
-    int64_t mean_chan_stride;
     int K, m;
-    int chunk0, n_chunks;   // chunks [chunk0, chunk0 + n_chunks); coef frame of chunk c is (c - coef_chunk0) * m
-    int coef_chunk0;        // chunk whose first frame is frame 0 of `coef`
-    int mean_chunk0;        // chunk stored at row 0 of `mean`
+    int n_chunks;
     int n_channels;
 };
-hipError_t launch_chunk_mean(const MeanArgs& a, hipStream_t s);
+hipError_t launch_centre(const CentreArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- moments
-// Common description of the chunk-centred coefficient source.
+// Chunk-centred coefficients a' = a - mean_f a (after launch_centre).
 struct CoefView {
-    const float2* coef;     // [C][frames][K] (frame index relative to coef_chunk0 * m)
-    const float2* mean;     // [C][chunks][K] (chunk index relative to mean_chunk0)
-    int64_t coef_chan_stride, mean_chan_stride;
+    const float2* coef;     // [C][frames][K]; chunk c starts at frame (c - coef_chunk0) * m
+    int64_t coef_chan_stride;
     int K, m;
-    int coef_chunk0, mean_chunk0;
+    int coef_chunk0;
 };
 
 struct S2Args {
@@ -80,9 +77,11 @@ struct GridArgs {
 };
 hipError_t launch_s3(const GridArgs& a, hipStream_t s);
 hipError_t launch_s4_single(const GridArgs& a, hipStream_t s);
+hipError_t launch_s4_mfma(const GridArgs& a, hipStream_t s);
 
 int s3_blocks_per_cu();
 int s4_blocks_per_cu();
+int s4_mfma_blocks_per_cu();
 
 // ---------------------------------------------------------------- finalize
 struct FinalizeVecArgs {

@@ -1,9 +1,8 @@
 // Per-chunk moment sums, k-statistic combination and FP64 chunk accumulation
 // (Sections 3, 4, 4.1, 4.2 and 7; the centred form of Appendix H).
 //
-// Inputs are the coefficients a_k(f) of stage a1 and their per-chunk means;
-// every kernel works with the chunk-centred values a' = a - mean_f a.  For a
-// chunk of m frames (sums over f):
+// Inputs are the chunk-centred coefficients a' = a - mean_f a of stage a1
+// (centred in place by launch_centre).  For a chunk of m frames (sums over f):
 //
 //   S2:  s2_k   = sum a'_k b'*_k                           c2 = s2 / (m-1)
 //   S3:  T3_kl  = sum a'_k b'_l c'*_{k+l}                  c3 = m T3 / ((m-1)(m-2))
@@ -29,11 +28,6 @@
 
 namespace ps {
 namespace {
-
-__device__ __forceinline__ float2 ld_centred(const float2* __restrict__ p, float2 mu) {
-    const float2 v = *p;
-    return make_float2(v.x - mu.x, v.y - mu.y);
-}
 
 // Remap blockIdx.x onto (split, tile) so that each XCD sees a contiguous,
 // split-major range of work items.
@@ -65,17 +59,13 @@ __global__ __launch_bounds__(256) void k_s2(S2Args p) {
     const CoefView& v = p.v;
     const float2* A = v.coef + p.a * v.coef_chan_stride;
     const float2* B = v.coef + p.b * v.coef_chan_stride;
-    const float2* MA = v.mean + p.a * v.mean_chan_stride;
-    const float2* MB = v.mean + p.b * v.mean_chan_stride;
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
     for (int c = c0; c < c1; ++c) {
-        const float2 ma = MA[(int64_t)(c - v.mean_chunk0) * v.K + k];
-        const float2 mb = MB[(int64_t)(c - v.mean_chunk0) * v.K + k];
         const int64_t base = (int64_t)(c - v.coef_chunk0) * v.m * v.K + k;
         float re = 0.f, im = 0.f;
         for (int f = 0; f < v.m; ++f) {
-            const float2 x = ld_centred(A + base + (int64_t)f * v.K, ma);
-            const float2 y = ld_centred(B + base + (int64_t)f * v.K, mb);
+            const float2 x = A[base + (int64_t)f * v.K];
+            const float2 y = B[base + (int64_t)f * v.K];
             re += x.x * y.x + x.y * y.y;   // x * conj(y)
             im += x.y * y.x - x.x * y.y;
         }
@@ -101,13 +91,16 @@ __global__ __launch_bounds__(256) void k_s2(S2Args p) {
 // Thread (ti, tj) = (tid / 16, tid % 16) owns the grid points
 // (k0 + ti + 16u, l0 + tj + 16v), u, v < 4, whose third factor sits at
 // k + l = k0 + l0 + ti + tj + 16(u + v).  Per frame it reads 4 + 4 + 7 values
-// from LDS and does 16 complex triple products (8 FMA-class ops each).
+// from LDS and does 16 complex triple products as 2 multiplies + 6 FMAs each.
+// Frames are staged through LDS in batches of FB; the next batch is fetched
+// into registers while the current one is being multiplied.
 constexpr int kS3Threads = 256;
 
+template <int FB>
 __global__ __launch_bounds__(kS3Threads, 2) void k_s3(GridArgs p) {
-    __shared__ float2 sA[kFrameBatch][kTile];
-    __shared__ float2 sB[kFrameBatch][kTile];
-    __shared__ float2 sC[kFrameBatch][2 * kTile];
+    __shared__ float2 sA[FB][kTile];
+    __shared__ float2 sB[FB][kTile];
+    __shared__ float2 sC[FB][2 * kTile];
 
     int split, tile;
     if (!xcd_work_item(p.n_tiles, p.n_split, split, tile)) return;
@@ -116,12 +109,6 @@ __global__ __launch_bounds__(kS3Threads, 2) void k_s3(GridArgs p) {
     const int2 t = p.tiles[tile];
     const int k0 = t.x * kTile, l0 = t.y * kTile;
     const CoefView& v = p.v;
-    const float2* A = v.coef + p.ch[0] * v.coef_chan_stride;
-    const float2* B = v.coef + p.ch[1] * v.coef_chan_stride;
-    const float2* C = v.coef + p.ch[2] * v.coef_chan_stride;
-    const float2* MA = v.mean + p.ch[0] * v.mean_chan_stride;
-    const float2* MB = v.mean + p.ch[1] * v.mean_chan_stride;
-    const float2* MC = v.mean + p.ch[2] * v.mean_chan_stride;
 
     const int tid = threadIdx.x;
     const int ti = tid >> 4, tj = tid & 15;
@@ -129,79 +116,86 @@ __global__ __launch_bounds__(kS3Threads, 2) void k_s3(GridArgs p) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.0;
 
-    // Column handled by this thread in the cooperative loads: 0..63 -> a_k,
-    // 64..127 -> b_l, 128..254 -> c_{k+l}; 255 idle.
+    // Loader role: column 0..63 -> a_k, 64..127 -> b_l, 128..254 -> c_{k+l}; 255 idle.
     const int col = tid;
     const float2* src = nullptr;
-    const float2* msrc = nullptr;
     bool live = false;
     if (col < kTile) {
         live = k0 + col < p.Nf;
-        src = A + k0 + col;
-        msrc = MA + k0 + col;
+        src = v.coef + p.ch[0] * v.coef_chan_stride + k0 + col;
     } else if (col < 2 * kTile) {
         live = l0 + col - kTile < p.Nf;
-        src = B + l0 + col - kTile;
-        msrc = MB + l0 + col - kTile;
+        src = v.coef + p.ch[1] * v.coef_chan_stride + l0 + col - kTile;
     } else if (col < 4 * kTile - 1) {
         live = k0 + l0 + col - 2 * kTile < v.K;
-        src = C + k0 + l0 + col - 2 * kTile;
-        msrc = MC + k0 + l0 + col - 2 * kTile;
+        src = v.coef + p.ch[2] * v.coef_chan_stride + k0 + l0 + col - 2 * kTile;
     }
 
-#pragma unroll 1
-    for (int c = c0; c < c1; ++c) {
-        const float2 m_here = live ? msrc[(int64_t)(c - v.mean_chunk0) * v.K] : make_float2(0.f, 0.f);
-        const int64_t fbase = (int64_t)(c - v.coef_chunk0) * v.m * v.K;
-        float tr[16], tim[16];
+    const int per_chunk = (v.m + FB - 1) / FB;
+    const int n_batches = (c1 - c0) * per_chunk;
+    float2 pre[FB];
+    auto fetch = [&](int b) {
+        const int c = c0 + b / per_chunk;
+        const int fb = (b % per_chunk) * FB;
+        const int nf = min(FB, v.m - fb);
+        const float2* q = src + ((int64_t)(c - v.coef_chunk0) * v.m + fb) * v.K;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) tr[q] = tim[q] = 0.f;
+        for (int f = 0; f < FB; ++f)
+            pre[f] = (live && f < nf) ? q[(int64_t)f * v.K] : make_float2(0.f, 0.f);
+    };
+    if (n_batches > 0) fetch(0);
 
+    float tr[16], tm[16];
 #pragma unroll 1
-        for (int fb = 0; fb < v.m; fb += kFrameBatch) {
-            const int nf = min(kFrameBatch, v.m - fb);
-            __syncthreads();
-            for (int f = 0; f < nf; ++f) {
-                float2 x = live ? ld_centred(src + fbase + (int64_t)(fb + f) * v.K, m_here)
-                                : make_float2(0.f, 0.f);
-                if (col < kTile) {
-                    sA[f][col] = x;
-                } else if (col < 2 * kTile) {
-                    sB[f][col - kTile] = x;
-                } else if (col < 4 * kTile - 1) {
-                    sC[f][col - 2 * kTile] = make_float2(x.x, -x.y);   // conjugate
-                }
-            }
-            __syncthreads();
-#pragma unroll 1
-            for (int f = 0; f < nf; ++f) {
-                float2 a[4], b[4], cc[7];
+    for (int b = 0; b < n_batches; ++b) {
+        const int fbi = b % per_chunk;
+        const int nf = min(FB, v.m - fbi * FB);
+        if (fbi == 0) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) a[u] = sA[f][ti + 16 * u];
+            for (int q = 0; q < 16; ++q) tr[q] = tm[q] = 0.f;
+        }
+        __syncthreads();
 #pragma unroll
-                for (int u = 0; u < 4; ++u) b[u] = sB[f][tj + 16 * u];
+        for (int f = 0; f < FB; ++f) {
+            if (col < kTile) sA[f][col] = pre[f];
+            else if (col < 2 * kTile) sB[f][col - kTile] = pre[f];
+            else if (col < 4 * kTile - 1) sC[f][col - 2 * kTile] = pre[f];
+        }
+        __syncthreads();
+        if (b + 1 < n_batches) fetch(b + 1);
+#pragma unroll 2
+        for (int f = 0; f < nf; ++f) {
+            float2 a[4], bb[4], cc[7];
 #pragma unroll
-                for (int w = 0; w < 7; ++w) cc[w] = sC[f][ti + tj + 16 * w];
+            for (int u = 0; u < 4; ++u) a[u] = sA[f][ti + 16 * u];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 4; ++u) bb[u] = sB[f][tj + 16 * u];
 #pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        const float pr = a[u].x * b[w].x - a[u].y * b[w].y;
-                        const float pi = a[u].x * b[w].y + a[u].y * b[w].x;
-                        const float2 z = cc[u + w];
-                        tr[u * 4 + w] += pr * z.x - pi * z.y;
-                        tim[u * 4 + w] += pr * z.y + pi * z.x;
-                    }
+            for (int w = 0; w < 7; ++w) cc[w] = sC[f][ti + tj + 16 * w];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    // p = a b;  T3 += p * conj(c)
+                    const float pr = fmaf(a[u].x, bb[w].x, -(a[u].y * bb[w].y));
+                    const float pi = fmaf(a[u].x, bb[w].y, a[u].y * bb[w].x);
+                    const float2 z = cc[u + w];
+                    float r = fmaf(pr, z.x, tr[u * 4 + w]);
+                    tr[u * 4 + w] = fmaf(pi, z.y, r);
+                    float m = fmaf(pi, z.x, tm[u * 4 + w]);
+                    tm[u * 4 + w] = fmaf(-pr, z.y, m);
                 }
             }
         }
+        if (fbi == per_chunk - 1) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const double re = tr[q], im = tim[q];
-            acc[q][0] += re;
-            acc[q][1] += im;
-            acc[q][2] += re * re;
-            acc[q][3] += im * im;
+            for (int q = 0; q < 16; ++q) {
+                const double re = tr[q], im = tm[q];
+                acc[q][0] += re;
+                acc[q][1] += im;
+                acc[q][2] = fma(re, re, acc[q][2]);
+                acc[q][3] = fma(im, im, acc[q][3]);
+            }
         }
     }
 
@@ -239,7 +233,6 @@ __global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(GridArgs p) {
     const int k0 = t.x * kTile, l0 = t.y * kTile;
     const CoefView& v = p.v;
     const float2* A = v.coef + p.ch[0] * v.coef_chan_stride;
-    const float2* MA = v.mean + p.ch[0] * v.mean_chan_stride;
 
     const int tid = threadIdx.x;
     const int ti = tid >> 4, tj = tid & 15;
@@ -250,21 +243,17 @@ __global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(GridArgs p) {
     const int col = tid;
     bool live = false;
     const float2* src = nullptr;
-    const float2* msrc = nullptr;
     if (col < kTile) {
         live = k0 + col < p.Nf;
         src = A + k0 + col;
-        msrc = MA + k0 + col;
     } else if (col < 2 * kTile) {
         live = l0 + col - kTile < p.Nf;
         src = A + l0 + col - kTile;
-        msrc = MA + l0 + col - kTile;
     }
     const double gamma = p.gamma;
 
 #pragma unroll 1
     for (int c = c0; c < c1; ++c) {
-        const float2 m_here = live ? msrc[(int64_t)(c - v.mean_chunk0) * v.K] : make_float2(0.f, 0.f);
         const int64_t fbase = (int64_t)(c - v.coef_chunk0) * v.m * v.K;
         float X[16], Y[16], U[16], V[16], M4[16], pk[4], pl[4];
 #pragma unroll
@@ -278,8 +267,7 @@ __global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(GridArgs p) {
             __syncthreads();
             if (col < 2 * kTile) {
                 for (int f = 0; f < nf; ++f) {
-                    float2 x = live ? ld_centred(src + fbase + (int64_t)(fb + f) * v.K, m_here)
-                                    : make_float2(0.f, 0.f);
+                    const float2 x = live ? src[fbase + (int64_t)(fb + f) * v.K] : make_float2(0.f, 0.f);
                     if (col < kTile) sA[f][col] = x;
                     else sB[f][col - kTile] = x;
                 }
@@ -342,6 +330,192 @@ __global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(GridArgs p) {
     }
 }
 
+// ------------------------------------------------------------------ S4, one channel, matrix cores
+// The same sums as k_s4_single, with the frame contractions on the matrix
+// cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  Each FP32 operand x is
+// split into three bfloat16 terms x = h + m + l (h, m by truncation to 8
+// significant bits, l rounded): the representation error is ~2^-24 |x|.  The
+// six products h.h + h.m + m.h + h.l + l.h + m.m are laid side by side along
+// the contraction dimension: per frame f the k-side operand row holds
+// [h h m h l m] and the l-side row [h m h l h m] at positions 6f..6f+5, so one
+// MFMA contraction over 6 x 10 frames (padded to 64) yields the FP32-accurate
+// frame sum.  Dropped terms (m.l, l.m, l.l) are below 2^-25 relative.
+//
+// LDS holds, per chunk (in batches of 10 frames), the operand rows of both
+// sides: rows 0..63 Re, 64..127 Im, 128..191 P = |a'|^2 of the tile's 64
+// columns.  Wave w computes the 16 x 64 strip of grid points with k in
+// k0 + 16w + [0, 16): for each 16 x 16 block five accumulators X, U, V, Y, M4,
+// so all five sums of a grid point sit in the same lane and element and the
+// k-statistic combination runs in registers.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaFrames = 10;      // frames per operand batch: 6 x 10 = 60 <= 64
+constexpr int kOpStride = 72;        // bf16 per LDS operand row (144 B: 16-B aligned, conflict-free b128 reads)
+constexpr int kS4MThreads = 256;
+
+__device__ __forceinline__ void split3(float x, uint32_t& h, uint32_t& m, uint32_t& l) {
+    const uint32_t ux = __float_as_uint(x);
+    const uint32_t uh = ux & 0xFFFF0000u;
+    const float r1 = x - __uint_as_float(uh);            // exact
+    const uint32_t um = __float_as_uint(r1) & 0xFFFF0000u;
+    const float r2 = r1 - __uint_as_float(um);           // exact
+    h = uh >> 16;
+    m = um >> 16;
+    l = (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)r2);
+}
+
+// Write the six split terms of x for frame slot f into an operand row.
+template <int SIDE>
+__device__ __forceinline__ void put_terms(unsigned short* row, int f, float x) {
+    uint32_t h, m, l;
+    split3(x, h, m, l);
+    uint32_t* w = reinterpret_cast<uint32_t*>(row + 6 * f);
+    if (SIDE == 0) {            // [h h m h l m]
+        w[0] = h | (h << 16);
+        w[1] = m | (h << 16);
+        w[2] = l | (m << 16);
+    } else {                    // [h m h l h m]
+        w[0] = h | (m << 16);
+        w[1] = h | (l << 16);
+        w[2] = h | (m << 16);
+    }
+}
+
+__global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(GridArgs p) {
+    __shared__ __attribute__((aligned(16))) unsigned short opK[3 * kTile][kOpStride];
+    __shared__ __attribute__((aligned(16))) unsigned short opL[3 * kTile][kOpStride];
+    __shared__ float psum[2][2][kTile];
+
+    int split, tile;
+    if (!xcd_work_item(p.n_tiles, p.n_split, split, tile)) return;
+    int c0, c1;
+    split_range(p.chunk0, p.chunk1, p.n_split, split, c0, c1);
+    const int2 t = p.tiles[tile];
+    const int k0 = t.x * kTile, l0 = t.y * kTile;
+    const CoefView& v = p.v;
+    const float2* A = v.coef + p.ch[0] * v.coef_chan_stride;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+
+    // Loader role: thread -> (side, column, half of the frame slots).
+    const int side = tid >> 7;
+    const int col = (tid >> 1) & (kTile - 1);
+    const int half = tid & 1;
+    const int gcol = (side ? l0 : k0) + col;
+    const bool live = gcol < p.Nf;
+    const float2* src = A + gcol;
+    unsigned short(*op)[kOpStride] = side ? opL : opK;
+
+    // Zero the padding slots 60..63 of every row once; they are never written again.
+    for (int r = tid; r < 2 * 3 * kTile; r += kS4MThreads) {
+        unsigned short* row = (r < 3 * kTile) ? opK[r] : opL[r - 3 * kTile];
+        *reinterpret_cast<uint2*>(row + 6 * kMfmaFrames) = make_uint2(0u, 0u);
+    }
+
+    double acc[4][4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[a][e][0] = acc[a][e][1] = 0.0;
+    const double gamma = p.gamma;
+
+#pragma unroll 1
+    for (int c = c0; c < c1; ++c) {
+        const int64_t fbase = (int64_t)(c - v.coef_chunk0) * v.m * v.K;
+        float pacc = 0.f;
+        floatx4_t d[4][5];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 5; ++b) d[a][b] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll 1
+        for (int fb = 0; fb < v.m; fb += kMfmaFrames) {
+            const int nf = min(kMfmaFrames, v.m - fb);
+            __syncthreads();
+#pragma unroll
+            for (int f = half; f < kMfmaFrames; f += 2) {
+                float re = 0.f, im = 0.f;
+                if (live && f < nf) {
+                    const float2 x = src[fbase + (int64_t)(fb + f) * v.K];
+                    re = x.x;
+                    im = x.y;
+                }
+                const float P = re * re + im * im;
+                pacc += P;
+                if (side == 0) {
+                    put_terms<0>(op[col], f, re);
+                    put_terms<0>(op[kTile + col], f, im);
+                    put_terms<0>(op[2 * kTile + col], f, P);
+                } else {
+                    put_terms<1>(op[col], f, re);
+                    put_terms<1>(op[kTile + col], f, im);
+                    put_terms<1>(op[2 * kTile + col], f, P);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const int koff = ks * 32 + lg * 8;
+                const int rk = w * 16 + li;
+                const bf16x8_t aR = *reinterpret_cast<const bf16x8_t*>(&opK[rk][koff]);
+                const bf16x8_t aI = *reinterpret_cast<const bf16x8_t*>(&opK[kTile + rk][koff]);
+                const bf16x8_t aP = *reinterpret_cast<const bf16x8_t*>(&opK[2 * kTile + rk][koff]);
+#pragma unroll
+                for (int lb = 0; lb < 4; ++lb) {
+                    const int rl = lb * 16 + li;
+                    const bf16x8_t bR = *reinterpret_cast<const bf16x8_t*>(&opL[rl][koff]);
+                    const bf16x8_t bI = *reinterpret_cast<const bf16x8_t*>(&opL[kTile + rl][koff]);
+                    const bf16x8_t bP = *reinterpret_cast<const bf16x8_t*>(&opL[2 * kTile + rl][koff]);
+                    d[lb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR, bR, d[lb][0], 0, 0, 0);  // X
+                    d[lb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR, bI, d[lb][1], 0, 0, 0);  // U
+                    d[lb][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI, bR, d[lb][2], 0, 0, 0);  // V
+                    d[lb][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI, bI, d[lb][3], 0, 0, 0);  // Y
+                    d[lb][4] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aP, bP, d[lb][4], 0, 0, 0);  // M4
+                }
+            }
+        }
+        psum[side][half][col] = pacc;
+        __syncthreads();
+        // Accumulator element e of lane (lg, li) is grid point
+        // k = k0 + 16w + 4 lg + e, l = l0 + 16 lb + li.
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int kl = w * 16 + 4 * lg + e;
+            const float pk = psum[0][0][kl] + psum[0][1][kl];
+#pragma unroll
+            for (int lb = 0; lb < 4; ++lb) {
+                const int ll = lb * 16 + li;
+                const float pl = psum[1][0][ll] + psum[1][1][ll];
+                const float X = d[lb][0][e], U = d[lb][1][e], V = d[lb][2][e], Y = d[lb][3][e];
+                const float sq = X * X + Y * Y + U * U + V * V;
+                const float q = fmaf(2.0f, sq, pk * pl);
+                const double val = (double)d[lb][4][e] - gamma * (double)q;
+                acc[lb][e][0] += val;
+                acc[lb][e][1] += val * val;
+            }
+        }
+    }
+
+    double* o = p.part + ((int64_t)split * p.n_tiles + tile) * 2 * (kTile * kTile);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+#pragma unroll
+        for (int lb = 0; lb < 4; ++lb) {
+            const int idx = (w * 16 + 4 * lg + e) * kTile + lb * 16 + li;
+#pragma unroll
+            for (int comp = 0; comp < 2; ++comp) {
+                double val = acc[lb][e][comp];
+                if (p.accumulate) val += o[comp * kTile * kTile + idx];
+                o[comp * kTile * kTile + idx] = val;
+            }
+        }
+    }
+}
+
 int blocks_per_cu(const void* fn, int threads) {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, 0) != hipSuccess || n < 1) n = 1;
@@ -357,11 +531,18 @@ hipError_t launch_s2(const S2Args& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Frame batch of the S3 kernel: 10 when m is a multiple of 10 or below it
+// (the default m = 10 fits one batch), 16 otherwise.
+bool s3_small_batch(int m) { return m <= kFrameBatchSmall || m % kFrameBatchSmall == 0; }
+
 hipError_t launch_s3(const GridArgs& a, hipStream_t s) {
     if (a.chunk1 <= a.chunk0) return hipSuccess;
     const int total = a.n_tiles * a.n_split;
     dim3 grid(((total + 7) / 8) * 8);
-    k_s3<<<grid, kS3Threads, 0, s>>>(a);
+    if (s3_small_batch(a.v.m))
+        k_s3<kFrameBatchSmall><<<grid, kS3Threads, 0, s>>>(a);
+    else
+        k_s3<kFrameBatch><<<grid, kS3Threads, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -373,7 +554,20 @@ hipError_t launch_s4_single(const GridArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-int s3_blocks_per_cu() { return blocks_per_cu(reinterpret_cast<const void*>(&k_s3), kS3Threads); }
+hipError_t launch_s4_mfma(const GridArgs& a, hipStream_t s) {
+    if (a.chunk1 <= a.chunk0) return hipSuccess;
+    const int total = a.n_tiles * a.n_split;
+    dim3 grid(((total + 7) / 8) * 8);
+    k_s4_mfma_bf16<<<grid, kS4MThreads, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+int s3_blocks_per_cu() {
+    return blocks_per_cu(reinterpret_cast<const void*>(&k_s3<kFrameBatch>), kS3Threads);
+}
 int s4_blocks_per_cu() { return blocks_per_cu(reinterpret_cast<const void*>(&k_s4_single), kS4Threads); }
+int s4_mfma_blocks_per_cu() {
+    return blocks_per_cu(reinterpret_cast<const void*>(&k_s4_mfma_bf16), kS4MThreads);
+}
 
 }  // namespace ps

@@ -107,11 +107,15 @@ def test_coefficients_match_oracle(dev, N, dtype):
 
 
 # ---------------------------------------------------------------- configurations
-def test_white_noise_config(dev):
+PRECISIONS = ["fp32", "bf16x3"]
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_white_noise_config(dev, precision):
     """51,200 float64 white Gaussian samples, N = 256, Hann, N_f = 64, m = 10."""
-    say("white-noise config")
+    say("white-noise config", precision)
     z = synth.white_gaussian(51_200, seed=1)
-    gpu, ref = both(z, dev, 256, 64, 10, window="hann")
+    gpu, ref = both(z, dev, 256, 64, 10, window="hann", precision=precision)
     assert gpu["n_chunks"] == 20
     compare(gpu, ref, label="white")
     # physics on the GPU result: flat S2 = sigma^2 dt = 1, S3 and S4 consistent with zero
@@ -122,21 +126,33 @@ def test_white_noise_config(dev):
         assert np.mean(np.abs(z_re) > 3.5) < 0.02
 
 
-def test_ar2_subset(dev):
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_ar2_subset(dev, precision):
     """The AR(2)/chi-square signal (r = 0.95, theta = 0.3 pi) on its 2^20-sample
     subset: N = 4096, acG window, N_f = 512, m = 10 (25 chunks, 8 tile rows)."""
-    say("ar2 subset N=4096 Nf=512")
+    say("ar2 subset N=4096 Nf=512", precision)
     z = synth.ar2_chi2(1 << 20, seed=2)
-    gpu, ref = both(z, dev, 4096, 512, 10, window="acg")
+    gpu, ref = both(z, dev, 4096, 512, 10, window="acg", precision=precision)
     assert gpu["n_chunks"] == 25
-    compare(gpu, ref, label="ar2-4096")
+    compare(gpu, ref, label=f"ar2-4096-{precision}")
 
 
-def test_ragged_grid_and_tail(dev):
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_ar2_n8192_subset(dev, precision):
+    """The same signal at N = 8192, N_f = 2048 (32 tile rows) on 2^21 samples
+    (25 chunks)."""
+    say("ar2 subset N=8192 Nf=2048", precision)
+    z = synth.ar2_chi2(1 << 21, seed=3)
+    gpu, ref = both(z, dev, 8192, 2048, 10, window="acg", precision=precision, orders=(2, 4))
+    compare(gpu, ref, keys=("s2", "s4"), label=f"ar2-8192-{precision}")
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_ragged_grid_and_tail(dev, precision):
     """N_f not a multiple of the tile, leftover samples, odd m, dt != 1."""
-    say("ragged N=1024 Nf=200 m=7")
+    say("ragged N=1024 Nf=200 m=7", precision)
     z = synth.ar2_chi2(1024 * 7 * 9 + 1000, seed=12, r=0.9, dtype=np.float32)
-    gpu, ref = both(z, dev, 1024, 200, 7, dt=0.37, window="hann_periodic")
+    gpu, ref = both(z, dev, 1024, 200, 7, dt=0.37, window="hann_periodic", precision=precision)
     assert gpu["n_chunks"] == 9
     compare(gpu, ref, label="ragged")
 
@@ -149,10 +165,11 @@ def test_order_subsets(dev, orders, Nf):
     compare(gpu, ref, keys=tuple(f"s{o}" for o in orders), label=f"orders{orders}")
 
 
-def test_large_m_uses_several_frame_batches(dev):
-    say("m=37")
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_large_m_uses_several_frame_batches(dev, precision):
+    say("m=37", precision)
     z = synth.ar2_chi2(512 * 37 * 4, seed=14, dtype=np.float32)
-    gpu, ref = both(z, dev, 512, 96, 37, window="acg")
+    gpu, ref = both(z, dev, 512, 96, 37, window="acg", precision=precision)
     compare(gpu, ref, label="m37")
 
 
@@ -168,10 +185,11 @@ def test_cross_channel_s2_s3(dev):
 
 
 # ---------------------------------------------------------------- schedule, determinism, edges
-def test_per_chunk_schedule_matches_batched(dev):
-    say("per-chunk vs batched")
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_per_chunk_schedule_matches_batched(dev, precision):
+    say("per-chunk vs batched", precision)
     z = synth.ar2_chi2(1024 * 10 * 13, seed=16, dtype=np.float32)
-    kw = dict(frame_len=1024, n_freq=256, m=10, window="acg")
+    kw = dict(frame_len=1024, n_freq=256, m=10, window="acg", precision=precision)
     a = run_gpu(z, dev, schedule="batched", **kw)
     b = run_gpu(z, dev, schedule="per_chunk", **kw)
     for k in ("s2", "s3", "s4"):
@@ -179,10 +197,11 @@ def test_per_chunk_schedule_matches_batched(dev):
         assert rel_err(a[k + "_err"], b[k + "_err"]) < 1e-9, k
 
 
-def test_deterministic(dev):
-    say("determinism")
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_deterministic(dev, precision):
+    say("determinism", precision)
     z = synth.ar2_chi2(2048 * 10 * 6, seed=17, dtype=np.float32)
-    kw = dict(frame_len=2048, n_freq=512, m=10, window="acg")
+    kw = dict(frame_len=2048, n_freq=512, m=10, window="acg", precision=precision)
     a = run_gpu(z, dev, **kw)
     b = run_gpu(z, dev, **kw)
     for k in ("s2", "s3", "s4", "s2_err", "s3_err", "s4_err"):
