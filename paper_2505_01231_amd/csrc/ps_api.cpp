@@ -673,8 +673,6 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
             f.n_split = sym ? L.split3_sym : L.split3_full;
             f.n_tiles = sym ? p->n_tiles_sym : p->n_tiles_full;
             f.ncomp = 4;
-            f.tile_of = sym ? p->d_tile_of_sym : p->d_tile_of_full;
-            f.T = p->T;
             f.sym = sym;
             f.Nf = Nf;
             f.n_chunks = L.Np;
@@ -682,7 +680,7 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
             f.out = o.d_s3 ? o.d_s3 + 2 * i * nf2 : nullptr;
             f.err = o.d_s3_err ? o.d_s3_err + 2 * i * nf2 : nullptr;
             StageTimer t(p, st, 5);
-            PS_HIP(ps::launch_finalize_grid(f, st));
+            PS_HIP(ps::launch_finalize_grid(f, sym ? p->d_tiles_sym : p->d_tiles_full, st));
         }
         for (int i = 0; i < p->n4(); ++i) {
             ps::FinalizeGridArgs f{};
@@ -690,8 +688,6 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
             f.n_split = L.split4;
             f.n_tiles = p->n_tiles_sym;
             f.ncomp = 2;
-            f.tile_of = p->d_tile_of_sym;
-            f.T = p->T;
             f.sym = 1;
             f.Nf = Nf;
             f.n_chunks = L.Np;
@@ -699,7 +695,7 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
             f.out = o.d_s4 ? o.d_s4 + 2 * i * nf2 : nullptr;
             f.err = o.d_s4_err ? o.d_s4_err + 2 * i * nf2 : nullptr;
             StageTimer t(p, st, 5);
-            PS_HIP(ps::launch_finalize_grid(f, st));
+            PS_HIP(ps::launch_finalize_grid(f, p->d_tiles_sym, st));
         }
     }
     return PS_OK;

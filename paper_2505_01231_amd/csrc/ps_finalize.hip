@@ -50,41 +50,61 @@ __global__ __launch_bounds__(256) void k_finalize_vec(FinalizeVecArgs p) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_finalize_grid(FinalizeGridArgs p) {
-    const int l = blockIdx.x * 256 + threadIdx.x;
-    const int k = blockIdx.y;
-    if (l >= p.Nf) return;
-    int kk = k, ll = l;
-    if (p.sym && k > l) {
-        kk = l;
-        ll = k;
-    }
-    const int tile = p.tile_of[(kk / kTile) * p.T + ll / kTile];
-    const int idx = (kk % kTile) * kTile + (ll % kTile);
+// One block per partial tile: sums over the chunk parts in a fixed order and
+// writes the tile's grid points (all of them, or only k <= l for symmetric
+// spectra) with coalesced reads of the partials and coalesced row writes.
+__global__ __launch_bounds__(256) void k_finalize_tiles(FinalizeGridArgs p, const int2* tiles) {
+    const int tile = blockIdx.x;
+    const int2 t = tiles[tile];
+    const int k0 = t.x * kTile, l0 = t.y * kTile;
     constexpr int TT = kTile * kTile;
-    double s[4] = {0, 0, 0, 0};
-    for (int sp = 0; sp < p.n_split; ++sp) {
-        const double* q = p.part + ((int64_t)sp * p.n_tiles + tile) * p.ncomp * TT + idx;
-        for (int c = 0; c < p.ncomp; ++c) s[c] += q[c * TT];
-    }
     const double np = (double)p.n_chunks;
-    double mr, sr, mi = 0.0, si = 0.0;
-    if (p.ncomp == 4) {
-        mean_sigma(s[0], s[2], np, p.scale, mr, sr);
-        mean_sigma(s[1], s[3], np, p.scale, mi, si);
-    } else {
-        mean_sigma(s[0], s[1], np, p.scale, mr, sr);
-        if (np < 1.0) mi = mr;      // NaN
-        if (np < 2.0) si = sr;      // NaN
+    for (int idx = threadIdx.x; idx < TT; idx += 256) {
+        const int k = k0 + idx / kTile, l = l0 + idx % kTile;
+        if (k >= p.Nf || l >= p.Nf || (p.sym && k > l)) continue;
+        double s[4] = {0, 0, 0, 0};
+        for (int sp = 0; sp < p.n_split; ++sp) {
+            const double* q = p.part + ((int64_t)sp * p.n_tiles + tile) * p.ncomp * TT + idx;
+            for (int c = 0; c < p.ncomp; ++c) s[c] += q[c * TT];
+        }
+        double mr, sr, mi = 0.0, si = 0.0;
+        if (p.ncomp == 4) {
+            mean_sigma(s[0], s[2], np, p.scale, mr, sr);
+            mean_sigma(s[1], s[3], np, p.scale, mi, si);
+        } else {
+            mean_sigma(s[0], s[1], np, p.scale, mr, sr);
+            if (np < 1.0) mi = mr;      // NaN
+            if (np < 2.0) si = sr;      // NaN
+        }
+        const int64_t o = ((int64_t)k * p.Nf + l) * 2;
+        if (p.out) {
+            p.out[o] = mr;
+            p.out[o + 1] = mi;
+        }
+        if (p.err) {
+            p.err[o] = sr;
+            p.err[o + 1] = si;
+        }
     }
-    const int64_t o = ((int64_t)k * p.Nf + l) * 2;
-    if (p.out) {
-        p.out[o] = mr;
-        p.out[o + 1] = mi;
+}
+
+// Symmetric spectra: copy (k, l) -> (l, k) for k < l through an LDS transpose
+// of 32 x 32 blocks of complex (16-byte) values.
+__global__ __launch_bounds__(256) void k_mirror(double* __restrict__ a, int Nf) {
+    __shared__ double2 sh[32][33];
+    const int bx = blockIdx.x, by = blockIdx.y;     // destination block (row by, column bx), by >= bx
+    if (by < bx) return;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    double2* v = reinterpret_cast<double2*>(a);
+    // source block: rows bx*32.., columns by*32.. (upper triangle)
+    for (int r = ty; r < 32; r += 8) {
+        const int k = bx * 32 + r, l = by * 32 + tx;
+        if (k < Nf && l < Nf) sh[r][tx] = v[(int64_t)k * Nf + l];
     }
-    if (p.err) {
-        p.err[o] = sr;
-        p.err[o + 1] = si;
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int k = by * 32 + r, l = bx * 32 + tx;    // destination (k, l) with k > l
+        if (k < Nf && l < Nf && k > l) v[(int64_t)k * Nf + l] = sh[tx][r];
     }
 }
 
@@ -100,9 +120,14 @@ hipError_t launch_finalize_vec(const FinalizeVecArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_finalize_grid(const FinalizeGridArgs& a, hipStream_t s) {
-    dim3 grid((a.Nf + 255) / 256, a.Nf);
-    k_finalize_grid<<<grid, 256, 0, s>>>(a);
+hipError_t launch_finalize_grid(const FinalizeGridArgs& a, const int2* tiles, hipStream_t s) {
+    k_finalize_tiles<<<a.n_tiles, 256, 0, s>>>(a, tiles);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !a.sym) return e;
+    const int nb = (a.Nf + 31) / 32;
+    dim3 grid(nb, nb);
+    if (a.out) k_mirror<<<grid, 256, 0, s>>>(a.out, a.Nf);
+    if (a.err) k_mirror<<<grid, 256, 0, s>>>(a.err, a.Nf);
     return hipGetLastError();
 }
 

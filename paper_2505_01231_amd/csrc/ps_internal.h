@@ -97,16 +97,14 @@ hipError_t launch_finalize_vec(const FinalizeVecArgs& a, hipStream_t s);
 struct FinalizeGridArgs {
     const double* part;     // [n_split][n_tiles][ncomp][kTile*kTile]
     int n_split, n_tiles, ncomp;
-    const int* tile_of;     // [T*T] tile id of tile (kt, lt), -1 if absent
-    int T;
-    int sym;                // only tiles kt <= lt exist; (k, l) with k > l read (l, k)
+    int sym;                // only tiles kt <= lt exist; (k, l) with k > l is the mirror of (l, k)
     int Nf;
     int64_t n_chunks;
     double scale;
     double* out;            // [Nf][Nf][2]
     double* err;            // [Nf][Nf][2]
 };
-hipError_t launch_finalize_grid(const FinalizeGridArgs& a, hipStream_t s);
+hipError_t launch_finalize_grid(const FinalizeGridArgs& a, const int2* tiles, hipStream_t s);
 
 hipError_t launch_fill_nan(double* p, int64_t n, hipStream_t s);
 

@@ -382,6 +382,47 @@ __device__ __forceinline__ void put_terms(unsigned short* row, int f, float x) {
     }
 }
 
+// One batch of MFMA contractions for wave w: 2 K-steps of 32 over the 64
+// operand columns.  FIRST starts the chunk's sums from zero (literal C = 0).
+template <bool FIRST>
+__device__ __forceinline__ void s4_mfma_batch(const unsigned short (*opK)[kOpStride],
+                                              const unsigned short (*opL)[kOpStride], int w, int li,
+                                              int lg, floatx4_t (&d)[4][5]) {
+    const floatx4_t zero = {0.f, 0.f, 0.f, 0.f};
+    const int rk = w * 16 + li;
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        const int koff = ks * 32 + lg * 8;
+        const bf16x8_t aR = *reinterpret_cast<const bf16x8_t*>(&opK[rk][koff]);
+        const bf16x8_t aI = *reinterpret_cast<const bf16x8_t*>(&opK[kTile + rk][koff]);
+        const bf16x8_t aP = *reinterpret_cast<const bf16x8_t*>(&opK[2 * kTile + rk][koff]);
+        bf16x8_t bR = *reinterpret_cast<const bf16x8_t*>(&opL[li][koff]);
+        bf16x8_t bI = *reinterpret_cast<const bf16x8_t*>(&opL[kTile + li][koff]);
+        bf16x8_t bP = *reinterpret_cast<const bf16x8_t*>(&opL[2 * kTile + li][koff]);
+#pragma unroll
+        for (int lb = 0; lb < 4; ++lb) {
+            // Fetch the next l-block's operands while this one's contractions run.
+            bf16x8_t nR = bR, nI = bI, nP = bP;
+            if (lb < 3) {
+                const int rl = (lb + 1) * 16 + li;
+                nR = *reinterpret_cast<const bf16x8_t*>(&opL[rl][koff]);
+                nI = *reinterpret_cast<const bf16x8_t*>(&opL[kTile + rl][koff]);
+                nP = *reinterpret_cast<const bf16x8_t*>(&opL[2 * kTile + rl][koff]);
+            }
+            const bool z = FIRST && ks == 0;
+            d[lb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR, bR, z ? zero : d[lb][0], 0, 0, 0);  // X
+            d[lb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR, bI, z ? zero : d[lb][1], 0, 0, 0);  // U
+            d[lb][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI, bR, z ? zero : d[lb][2], 0, 0, 0);  // V
+            d[lb][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI, bI, z ? zero : d[lb][3], 0, 0, 0);  // Y
+            d[lb][4] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aP, bP, z ? zero : d[lb][4], 0, 0, 0);  // M4
+            __builtin_amdgcn_sched_barrier(0);
+            bR = nR;
+            bI = nI;
+            bP = nP;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(GridArgs p) {
     __shared__ __attribute__((aligned(16))) unsigned short opK[3 * kTile][kOpStride];
     __shared__ __attribute__((aligned(16))) unsigned short opL[3 * kTile][kOpStride];
@@ -394,7 +435,6 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(GridArgs p) {
     const int2 t = p.tiles[tile];
     const int k0 = t.x * kTile, l0 = t.y * kTile;
     const CoefView& v = p.v;
-    const float2* A = v.coef + p.ch[0] * v.coef_chan_stride;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
@@ -406,7 +446,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(GridArgs p) {
     const int half = tid & 1;
     const int gcol = (side ? l0 : k0) + col;
     const bool live = gcol < p.Nf;
-    const float2* src = A + gcol;
+    const float2* src = v.coef + p.ch[0] * v.coef_chan_stride + gcol;
     unsigned short(*op)[kOpStride] = side ? opL : opK;
 
     // Zero the padding slots 60..63 of every row once; they are never written again.
@@ -420,64 +460,58 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(GridArgs p) {
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[a][e][0] = acc[a][e][1] = 0.0;
-    const double gamma = p.gamma;
+    const float gamma = (float)p.gamma;
+    const double gamma_d = p.gamma;
 
-#pragma unroll 1
-    for (int c = c0; c < c1; ++c) {
-        const int64_t fbase = (int64_t)(c - v.coef_chunk0) * v.m * v.K;
-        float pacc = 0.f;
-        floatx4_t d[4][5];
+    constexpr int kSlots = kMfmaFrames / 2;       // frame slots of this thread: half + 2j
+    const int per_chunk = (v.m + kMfmaFrames - 1) / kMfmaFrames;
+    const int n_batches = (c1 - c0) * per_chunk;
+    float2 pre[kSlots];
+    auto fetch = [&](int b) {
+        const int c = c0 + b / per_chunk;
+        const int fb = (b % per_chunk) * kMfmaFrames;
+        const int nf = min(kMfmaFrames, v.m - fb);
+        const float2* q = src + ((int64_t)(c - v.coef_chunk0) * v.m + fb) * v.K;
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 5; ++b) d[a][b] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < kSlots; ++j) {
+            const int f = half + 2 * j;
+            pre[j] = (live && f < nf) ? q[(int64_t)f * v.K] : make_float2(0.f, 0.f);
+        }
+    };
+    if (n_batches > 0) fetch(0);
 
+    floatx4_t d[4][5];
+    float pacc = 0.f;
+    (void)gamma;
 #pragma unroll 1
-        for (int fb = 0; fb < v.m; fb += kMfmaFrames) {
-            const int nf = min(kMfmaFrames, v.m - fb);
-            __syncthreads();
+    for (int b = 0; b < n_batches; ++b) {
+        const int fbi = b % per_chunk;
+        if (fbi == 0) pacc = 0.f;
+        __syncthreads();
 #pragma unroll
-            for (int f = half; f < kMfmaFrames; f += 2) {
-                float re = 0.f, im = 0.f;
-                if (live && f < nf) {
-                    const float2 x = src[fbase + (int64_t)(fb + f) * v.K];
-                    re = x.x;
-                    im = x.y;
-                }
-                const float P = re * re + im * im;
-                pacc += P;
-                if (side == 0) {
-                    put_terms<0>(op[col], f, re);
-                    put_terms<0>(op[kTile + col], f, im);
-                    put_terms<0>(op[2 * kTile + col], f, P);
-                } else {
-                    put_terms<1>(op[col], f, re);
-                    put_terms<1>(op[kTile + col], f, im);
-                    put_terms<1>(op[2 * kTile + col], f, P);
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                const int koff = ks * 32 + lg * 8;
-                const int rk = w * 16 + li;
-                const bf16x8_t aR = *reinterpret_cast<const bf16x8_t*>(&opK[rk][koff]);
-                const bf16x8_t aI = *reinterpret_cast<const bf16x8_t*>(&opK[kTile + rk][koff]);
-                const bf16x8_t aP = *reinterpret_cast<const bf16x8_t*>(&opK[2 * kTile + rk][koff]);
-#pragma unroll
-                for (int lb = 0; lb < 4; ++lb) {
-                    const int rl = lb * 16 + li;
-                    const bf16x8_t bR = *reinterpret_cast<const bf16x8_t*>(&opL[rl][koff]);
-                    const bf16x8_t bI = *reinterpret_cast<const bf16x8_t*>(&opL[kTile + rl][koff]);
-                    const bf16x8_t bP = *reinterpret_cast<const bf16x8_t*>(&opL[2 * kTile + rl][koff]);
-                    d[lb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR, bR, d[lb][0], 0, 0, 0);  // X
-                    d[lb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR, bI, d[lb][1], 0, 0, 0);  // U
-                    d[lb][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI, bR, d[lb][2], 0, 0, 0);  // V
-                    d[lb][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI, bI, d[lb][3], 0, 0, 0);  // Y
-                    d[lb][4] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aP, bP, d[lb][4], 0, 0, 0);  // M4
-                }
+        for (int j = 0; j < kSlots; ++j) {
+            const int f = half + 2 * j;
+            const float re = pre[j].x, im = pre[j].y;
+            const float P = re * re + im * im;
+            pacc += P;
+            if (side == 0) {
+                put_terms<0>(op[col], f, re);
+                put_terms<0>(op[kTile + col], f, im);
+                put_terms<0>(op[2 * kTile + col], f, P);
+            } else {
+                put_terms<1>(op[col], f, re);
+                put_terms<1>(op[kTile + col], f, im);
+                put_terms<1>(op[2 * kTile + col], f, P);
             }
         }
+        __syncthreads();
+        if (fbi == 0) s4_mfma_batch<true>(opK, opL, w, li, lg, d);
+        else s4_mfma_batch<false>(opK, opL, w, li, lg, d);
+        // Next batch's loads overlap the epilogue (issuing them before the
+        // contractions would keep them live across the accumulator peak).
+        if (b + 1 < n_batches) fetch(b + 1);
+        if (fbi != per_chunk - 1) continue;
+
         psum[side][half][col] = pacc;
         __syncthreads();
         // Accumulator element e of lane (lg, li) is grid point
@@ -491,11 +525,11 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(GridArgs p) {
                 const int ll = lb * 16 + li;
                 const float pl = psum[1][0][ll] + psum[1][1][ll];
                 const float X = d[lb][0][e], U = d[lb][1][e], V = d[lb][2][e], Y = d[lb][3][e];
-                const float sq = X * X + Y * Y + U * U + V * V;
+                const float sq = fmaf(X, X, fmaf(Y, Y, fmaf(U, U, V * V)));
                 const float q = fmaf(2.0f, sq, pk * pl);
-                const double val = (double)d[lb][4][e] - gamma * (double)q;
+                const double val = fma(-gamma_d, (double)q, (double)d[lb][4][e]);
                 acc[lb][e][0] += val;
-                acc[lb][e][1] += val * val;
+                acc[lb][e][1] = fma(val, val, acc[lb][e][1]);
             }
         }
     }
