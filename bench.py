@@ -30,7 +30,7 @@ WORKLOAD = "ar2-chi2 1ch 2^28 f32, N=8192, N_f=2048, m=10, acG 0.14, S2+S3+S4"
 PEAK_HBM_GBS = 8000.0
 # FP32 FMA on the vector ALUs without packed-FP32 instructions:
 # 256 CUs x 64 lanes x 2 flop x 2.4 GHz.  (The vendor's 157.3 TFLOP/s assumes
-# packed FP32, which this build does not emit.)
+# packed FP32 instructions, which the library's device code is compiled without.)
 PEAK_FP32_VALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
 

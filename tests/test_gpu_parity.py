@@ -256,3 +256,43 @@ def test_errors_are_reported_not_faulted(dev):
             == L.PS_E_INVALID_ARG
         with pytest.raises(PolyspecError):
             L.check(L.PS_E_INVALID_ARG, "x")
+
+
+# ---------------------------------------------------------------- full size, sampled
+@pytest.mark.parametrize("precision", ["bf16x3"])
+def test_full_size_sampled_points(dev, precision):
+    """The benchmark workload itself (2^28 float32 AR(2)/chi-square samples,
+    N = 8192, N_f = 2048, m = 10, 3276 chunks) in the benchmark's launch
+    configuration; the oracle evaluates S2, S3 and S4 point by point on a sample
+    of grid points that includes the GPU's largest |S3| and |S4|."""
+    from paper_2505_01231_amd import Plan
+    say("full size 2^28, N=8192, Nf=2048", precision)
+    N, Nf, m = 8192, 2048, 10
+    z = synth.ar2_chi2(1 << 28, seed=3)
+    x = torch.from_numpy(z).to(dev)
+    with Plan(frame_len=N, n_freq=Nf, m=m, window="acg", precision=precision) as p:
+        out = p.execute(x)
+        torch.cuda.synchronize()
+        s2 = torch.view_as_complex(out.s2[0]).cpu().numpy()
+        s3 = torch.view_as_complex(out.s3[0]).cpu().numpy()
+        s4 = torch.view_as_complex(out.s4[0]).cpu().numpy()
+        e4 = out.s4_err[0].cpu().numpy()
+    del x
+    assert out.n_chunks == 3276
+    rng = np.random.default_rng(7)
+    pts = [tuple(int(v) for v in np.unravel_index(np.argmax(np.abs(s3)), s3.shape)),
+           tuple(int(v) for v in np.unravel_index(np.argmax(np.abs(s4)), s4.shape)),
+           (0, 0), (0, Nf - 1), (Nf - 1, Nf - 1), (Nf - 1, 0), (63, 64), (64, 63)]
+    pts += [tuple(int(v) for v in rng.integers(0, Nf, 2)) for _ in range(16)]
+    bins2 = [pts[0][0], pts[1][0], 0, 1, Nf - 1] + [int(v) for v in rng.integers(0, Nf, 8)]
+    say("  oracle on", len(pts), "points")
+    ref = O.polyspectra_at(z, N, m, window_kind="acg", points2=bins2, points3=pts, points4=pts)
+    got2 = s2[bins2]
+    got3 = np.array([s3[k, l] for k, l in pts])
+    got4 = np.array([s4[k, l] for k, l in pts])
+    got4e = np.array([e4[k, l, 0] for k, l in pts])
+    errs = {"s2": rel_err(got2, ref["s2"]), "s3": rel_err(got3, ref["s3"]),
+            "s4": rel_err(got4, ref["s4"]), "s4_err": rel_err(got4e, ref["s4_err"][:, 0])}
+    say("  sampled rel err", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= TOL, (k, v)
