@@ -92,15 +92,15 @@ struct ps_plan_s {
     int window = 0, precision = 0, schedule = 0;
     std::vector<int8_t> c2, c3, c4;
     double sum_g[5] = {0, 0, 0, 0, 0};
-    int T = 0;
-    int n_tiles_sym = 0, n_tiles_full = 0;
+    int T = 0, TX = 0;
+    int n_tiles_sym = 0, n_tiles_full = 0, n_tilesx_sym = 0, n_tilesx_full = 0;
     float* d_g = nullptr;
     float2* d_tw = nullptr;
-    int2* d_tiles_sym = nullptr;
-    int2* d_tiles_full = nullptr;
-    int* d_tile_of_sym = nullptr;
-    int* d_tile_of_full = nullptr;
-    int n_cu = 256, bpc_s3 = 2, bpc_s4 = 2;
+    int2* d_tiles_sym = nullptr;     // 64 x 64 tiles, kt <= lt
+    int2* d_tiles_full = nullptr;    // 64 x 64 tiles, all
+    int2* d_tilesx_sym = nullptr;    // 32 x 32 tiles (cross-channel S4), kt <= lt
+    int2* d_tilesx_full = nullptr;
+    int n_cu = 256, bpc_s3 = 2, bpc_s4 = 2, bpc_s4x = 2;
     // Stage timing (ps_profile_enable): event pairs recorded on the stream.
     bool prof = false;
     struct Timed {
@@ -117,6 +117,11 @@ struct ps_plan_s {
     bool s4_single(int i) const {
         const int8_t* q = &c4[4 * i];
         return q[0] == q[1] && q[1] == q[2] && q[2] == q[3];
+    }
+    // S4_abcd(k,l) = S4_cdab(l,k): symmetric grid when (a,b) = (c,d).
+    bool s4_sym(int i) const {
+        const int8_t* q = &c4[4 * i];
+        return q[0] == q[2] && q[1] == q[3];
     }
 };
 
@@ -145,12 +150,25 @@ int choose_split_vec(int Nf, int64_t n_chunks, int n_cu) {
     return (int)std::min<int64_t>(s, std::max<int64_t>(1, n_chunks));
 }
 
+// Launch shape and partial-sum slot of one S4 channel combination.
+struct S4Shape {
+    bool single = true;   // a = b = c = d: real form, 64-tiles (FP32 vector or matrix cores)
+    bool sym = true;      // only tiles kt <= lt
+    int edge = 64;
+    int n_tiles = 0;
+    const int2* d_tiles = nullptr;
+    int split = 1;
+    int ncomp = 2;
+    size_t off = 0;
+};
+
 struct Layout {
     int64_t Np = 0, F = 0;
     int chunk_frames = 0;   // frames resident in the coefficient buffer
-    int split2 = 1, split3_sym = 1, split3_full = 1, split4 = 1;
+    int split2 = 1, split3_sym = 1, split3_full = 1;
     size_t off_coef = 0, off_p2 = 0, off_p3 = 0, off_p4 = 0, total = 0;
-    std::vector<size_t> p3_off, p4_off;
+    std::vector<size_t> p3_off;
+    std::vector<S4Shape> s4;
     size_t p2_stride = 0;
 };
 
@@ -164,7 +182,6 @@ Layout layout_for(const ps_plan_s* p, int64_t n_samples) {
         L.split2 = choose_split_vec(p->Nf, L.Np, p->n_cu);
         L.split3_sym = choose_split(p->n_tiles_sym, L.Np, p->n_cu * p->bpc_s3);
         L.split3_full = choose_split(p->n_tiles_full, L.Np, p->n_cu * p->bpc_s3);
-        L.split4 = choose_split(p->n_tiles_sym, L.Np, p->n_cu * p->bpc_s4);
     }
     size_t off = 0;
     L.off_coef = off;
@@ -183,9 +200,26 @@ Layout layout_for(const ps_plan_s* p, int64_t n_samples) {
     }
     L.off_p4 = off;
     for (int i = 0; i < p->n4(); ++i) {
-        L.p4_off.push_back(off);
-        const size_t n = (size_t)L.split4 * p->n_tiles_sym * 2 * TT;
+        S4Shape sh;
+        sh.single = p->s4_single(i);
+        sh.sym = p->s4_sym(i);
+        if (sh.single) {
+            sh.edge = ps::kTile;
+            sh.n_tiles = p->n_tiles_sym;
+            sh.d_tiles = p->d_tiles_sym;
+            sh.ncomp = 2;
+            if (!per_chunk) sh.split = choose_split(sh.n_tiles, L.Np, p->n_cu * p->bpc_s4);
+        } else {
+            sh.edge = ps::kTileX;
+            sh.n_tiles = sh.sym ? p->n_tilesx_sym : p->n_tilesx_full;
+            sh.d_tiles = sh.sym ? p->d_tilesx_sym : p->d_tilesx_full;
+            sh.ncomp = 4;
+            if (!per_chunk) sh.split = choose_split(sh.n_tiles, L.Np, p->n_cu * p->bpc_s4x);
+        }
+        sh.off = off;
+        const size_t n = (size_t)sh.split * sh.n_tiles * sh.ncomp * sh.edge * sh.edge;
         off = align256(off + n * sizeof(double));
+        L.s4.push_back(sh);
     }
     L.total = std::max<size_t>(off, 256);
     return L;
@@ -275,8 +309,8 @@ ps_status ps_plan_destroy(ps_plan_t p) {
     hipFree(p->d_tw);
     hipFree(p->d_tiles_sym);
     hipFree(p->d_tiles_full);
-    hipFree(p->d_tile_of_sym);
-    hipFree(p->d_tile_of_full);
+    hipFree(p->d_tilesx_sym);
+    hipFree(p->d_tilesx_full);
     delete p;
     return PS_OK;
 }
@@ -364,11 +398,6 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
                 return fail(PS_E_INVALID_ARG, "combination refers to channel %d of %d", ch, p->C);
             }
     }
-    for (int i = 0; i < p->n4(); ++i)
-        if (!p->s4_single(i)) {
-            delete p;
-            return fail(PS_E_UNSUPPORTED, "S4 cross-channel combinations are not available in this build");
-        }
 
     // Window and sums (FP64); FFT twiddles exp(+2 pi j t/N) rounded once to FP32.
     std::vector<double> g;
@@ -388,20 +417,22 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     }
 
     // Output tiles: upper triangle (kt <= lt) for symmetric spectra, all otherwise.
-    p->T = (Nf + ps::kTile - 1) / ps::kTile;
-    std::vector<int2> ts, tf;
-    std::vector<int> of_s(p->T * p->T, -1), of_f(p->T * p->T, -1);
-    for (int kt = 0; kt < p->T; ++kt)
-        for (int lt = 0; lt < p->T; ++lt) {
-            of_f[kt * p->T + lt] = (int)tf.size();
-            tf.push_back(make_int2(kt, lt));
-            if (kt <= lt) {
-                of_s[kt * p->T + lt] = (int)ts.size();
-                ts.push_back(make_int2(kt, lt));
+    auto make_tiles = [](int T, std::vector<int2>& sym, std::vector<int2>& full) {
+        for (int kt = 0; kt < T; ++kt)
+            for (int lt = 0; lt < T; ++lt) {
+                full.push_back(make_int2(kt, lt));
+                if (kt <= lt) sym.push_back(make_int2(kt, lt));
             }
-        }
+    };
+    p->T = (Nf + ps::kTile - 1) / ps::kTile;
+    p->TX = (Nf + ps::kTileX - 1) / ps::kTileX;
+    std::vector<int2> ts, tf, txs, txf;
+    make_tiles(p->T, ts, tf);
+    make_tiles(p->TX, txs, txf);
     p->n_tiles_sym = (int)ts.size();
     p->n_tiles_full = (int)tf.size();
+    p->n_tilesx_sym = (int)txs.size();
+    p->n_tilesx_full = (int)txf.size();
 
     auto upload = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
         hipError_t e = hipMalloc(dst, bytes);
@@ -413,8 +444,8 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     if (e == hipSuccess) e = upload((void**)&p->d_tw, tw.data(), tw.size() * sizeof(float2));
     if (e == hipSuccess) e = upload((void**)&p->d_tiles_sym, ts.data(), ts.size() * sizeof(int2));
     if (e == hipSuccess) e = upload((void**)&p->d_tiles_full, tf.data(), tf.size() * sizeof(int2));
-    if (e == hipSuccess) e = upload((void**)&p->d_tile_of_sym, of_s.data(), of_s.size() * sizeof(int));
-    if (e == hipSuccess) e = upload((void**)&p->d_tile_of_full, of_f.data(), of_f.size() * sizeof(int));
+    if (e == hipSuccess) e = upload((void**)&p->d_tilesx_sym, txs.data(), txs.size() * sizeof(int2));
+    if (e == hipSuccess) e = upload((void**)&p->d_tilesx_full, txf.data(), txf.size() * sizeof(int2));
     if (e != hipSuccess) {
         ps_plan_destroy(p);
         return fail(PS_E_HIP, "device table setup failed: %s", hipGetErrorString(e));
@@ -425,6 +456,7 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
         p->n_cu = std::max(1, prop.multiProcessorCount);
     p->bpc_s3 = ps::s3_blocks_per_cu();
     p->bpc_s4 = p->precision == PS_PREC_FP32 ? ps::s4_blocks_per_cu() : ps::s4_mfma_blocks_per_cu();
+    p->bpc_s4x = ps::s4_cross_blocks_per_cu();
     *out = p;
     return PS_OK;
 }
@@ -633,20 +665,23 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
                 PS_HIP(ps::launch_s3(a, st));
             }
             for (int i = 0; i < p->n4(); ++i) {
+                const S4Shape& sh = L.s4[i];
                 ps::GridArgs a{};
                 a.v = cv;
                 a.Nf = Nf;
                 for (int j = 0; j < 4; ++j) a.ch[j] = p->c4[4 * i + j];
-                a.tiles = p->d_tiles_sym;
-                a.n_tiles = p->n_tiles_sym;
+                a.tiles = sh.d_tiles;
+                a.n_tiles = sh.n_tiles;
                 a.chunk0 = c_lo;
                 a.chunk1 = c_hi;
-                a.n_split = L.split4;
-                a.part = reinterpret_cast<double*>(ws + L.p4_off[i]);
+                a.n_split = sh.split;
+                a.part = reinterpret_cast<double*>(ws + sh.off);
                 a.accumulate = acc;
                 a.gamma = gamma;
                 StageTimer t(p, st, 4);
-                if (p->precision == PS_PREC_FP32) {
+                if (!sh.single) {
+                    PS_HIP(ps::launch_s4_cross(a, st));
+                } else if (p->precision == PS_PREC_FP32) {
                     PS_HIP(ps::launch_s4_single(a, st));
                 } else {
                     PS_HIP(ps::launch_s4_mfma(a, st));
@@ -673,6 +708,7 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
             f.n_split = sym ? L.split3_sym : L.split3_full;
             f.n_tiles = sym ? p->n_tiles_sym : p->n_tiles_full;
             f.ncomp = 4;
+            f.edge = ps::kTile;
             f.sym = sym;
             f.Nf = Nf;
             f.n_chunks = L.Np;
@@ -683,19 +719,21 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
             PS_HIP(ps::launch_finalize_grid(f, sym ? p->d_tiles_sym : p->d_tiles_full, st));
         }
         for (int i = 0; i < p->n4(); ++i) {
+            const S4Shape& sh = L.s4[i];
             ps::FinalizeGridArgs f{};
-            f.part = reinterpret_cast<const double*>(ws + L.p4_off[i]);
-            f.n_split = L.split4;
-            f.n_tiles = p->n_tiles_sym;
-            f.ncomp = 2;
-            f.sym = 1;
+            f.part = reinterpret_cast<const double*>(ws + sh.off);
+            f.n_split = sh.split;
+            f.n_tiles = sh.n_tiles;
+            f.ncomp = sh.ncomp;
+            f.edge = sh.edge;
+            f.sym = sh.sym;
             f.Nf = Nf;
             f.n_chunks = L.Np;
             f.scale = scale4;
             f.out = o.d_s4 ? o.d_s4 + 2 * i * nf2 : nullptr;
             f.err = o.d_s4_err ? o.d_s4_err + 2 * i * nf2 : nullptr;
             StageTimer t(p, st, 5);
-            PS_HIP(ps::launch_finalize_grid(f, p->d_tiles_sym, st));
+            PS_HIP(ps::launch_finalize_grid(f, sh.d_tiles, st));
         }
     }
     return PS_OK;

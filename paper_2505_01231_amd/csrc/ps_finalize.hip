@@ -56,11 +56,12 @@ __global__ __launch_bounds__(256) void k_finalize_vec(FinalizeVecArgs p) {
 __global__ __launch_bounds__(256) void k_finalize_tiles(FinalizeGridArgs p, const int2* tiles) {
     const int tile = blockIdx.x;
     const int2 t = tiles[tile];
-    const int k0 = t.x * kTile, l0 = t.y * kTile;
-    constexpr int TT = kTile * kTile;
+    const int E = p.edge;
+    const int k0 = t.x * E, l0 = t.y * E;
+    const int TT = E * E;
     const double np = (double)p.n_chunks;
     for (int idx = threadIdx.x; idx < TT; idx += 256) {
-        const int k = k0 + idx / kTile, l = l0 + idx % kTile;
+        const int k = k0 + idx / E, l = l0 + idx % E;
         if (k >= p.Nf || l >= p.Nf || (p.sym && k > l)) continue;
         double s[4] = {0, 0, 0, 0};
         for (int sp = 0; sp < p.n_split; ++sp) {

@@ -11,6 +11,9 @@ namespace ps {
 // Output-tile edge of the S3/S4 moment kernels: a tile covers 64 x 64 (k, l)
 // grid points; the 256 threads of a block each own a 4 x 4 sub-grid.
 constexpr int kTile = 64;
+// Tile edge of the cross-channel S4 kernel (20 frame sums per grid point leave
+// room for 2 x 2 grid points per thread only).
+constexpr int kTileX = 32;
 // Frames staged in LDS at once by the moment kernels.
 constexpr int kFrameBatch = 16;
 constexpr int kFrameBatchSmall = 10;
@@ -78,10 +81,12 @@ struct GridArgs {
 hipError_t launch_s3(const GridArgs& a, hipStream_t s);
 hipError_t launch_s4_single(const GridArgs& a, hipStream_t s);
 hipError_t launch_s4_mfma(const GridArgs& a, hipStream_t s);
+hipError_t launch_s4_cross(const GridArgs& a, hipStream_t s);
 
 int s3_blocks_per_cu();
 int s4_blocks_per_cu();
 int s4_mfma_blocks_per_cu();
+int s4_cross_blocks_per_cu();
 
 // ---------------------------------------------------------------- finalize
 struct FinalizeVecArgs {
@@ -95,8 +100,9 @@ struct FinalizeVecArgs {
 hipError_t launch_finalize_vec(const FinalizeVecArgs& a, hipStream_t s);
 
 struct FinalizeGridArgs {
-    const double* part;     // [n_split][n_tiles][ncomp][kTile*kTile]
+    const double* part;     // [n_split][n_tiles][ncomp][edge*edge]
     int n_split, n_tiles, ncomp;
+    int edge;               // tile edge (kTile or kTileX)
     int sym;                // only tiles kt <= lt exist; (k, l) with k > l is the mirror of (l, k)
     int Nf;
     int64_t n_chunks;

@@ -550,6 +550,135 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(GridArgs p) {
     }
 }
 
+// ------------------------------------------------------------------ S4, channel combinations
+// C4(a_k, b*_k, c_l, d*_l) for general channels (Section 7), in the centred
+// form of Appendix H with x = a'_k, y = b'*_k, z = c'_l, w = d'*_l:
+//   c4 = [m(m+1) sum xyzw - (m-1)(sum xy sum zw + sum xz sum yw + sum xw sum yz)]
+//        / ((m-1)(m-2)(m-3)),
+// where, with E_k = a'_k b'*_k and F_l = c'_l d'*_l,
+//   sum xyzw = sum E_k F_l,  sum xy = e_k = sum E_k,  sum zw = f_l = sum F_l,
+//   sum xz = G_ac = sum a'_k c'_l,   sum yw = conj(G_bd),
+//   sum xw = H_ad = sum a'_k d'*_l,  sum yz = conj(H_bc).
+// Five complex frame sums per grid point (FP32 vector arithmetic), the
+// combination and the chunk sums in FP64.  Tiles are 32 x 32; each thread owns
+// the grid points (k0 + ti + 16u, l0 + tj + 16v), u, v < 2.
+constexpr int kS4XThreads = 256;
+
+__device__ __forceinline__ void cmac(float2& acc, float2 x, float2 y) {        // acc += x y
+    acc.x = fmaf(x.x, y.x, fmaf(-x.y, y.y, acc.x));
+    acc.y = fmaf(x.x, y.y, fmaf(x.y, y.x, acc.y));
+}
+__device__ __forceinline__ void cmacc(float2& acc, float2 x, float2 y) {       // acc += x conj(y)
+    acc.x = fmaf(x.x, y.x, fmaf(x.y, y.y, acc.x));
+    acc.y = fmaf(x.y, y.x, fmaf(-x.x, y.y, acc.y));
+}
+
+__global__ __launch_bounds__(kS4XThreads, 2) void k_s4_cross(GridArgs p) {
+    __shared__ float2 sv[4][kFrameBatch][kTileX];   // a'_k, b'_k, c'_l, d'_l
+
+    int split, tile;
+    if (!xcd_work_item(p.n_tiles, p.n_split, split, tile)) return;
+    int c0, c1;
+    split_range(p.chunk0, p.chunk1, p.n_split, split, c0, c1);
+    const int2 t = p.tiles[tile];
+    const int k0 = t.x * kTileX, l0 = t.y * kTileX;
+    const CoefView& v = p.v;
+
+    const int tid = threadIdx.x;
+    const int ti = tid >> 4, tj = tid & 15;
+    // Loader role: (array, column, half of the frames).
+    const int arr = (tid & 127) >> 5, col = tid & 31, half = tid >> 7;
+    const int gcol = (arr < 2 ? k0 : l0) + col;
+    const bool live = gcol < p.Nf;
+    const float2* src = v.coef + p.ch[arr] * v.coef_chan_stride + gcol;
+
+    double acc[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q][0] = acc[q][1] = acc[q][2] = acc[q][3] = 0.0;
+    const double gamma = p.gamma;
+
+#pragma unroll 1
+    for (int c = c0; c < c1; ++c) {
+        const int64_t fbase = (int64_t)(c - v.coef_chunk0) * v.m * v.K;
+        float2 sef[4], gac[4], gbd[4], had[4], hbc[4], e[2], f[2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sef[q] = gac[q] = gbd[q] = had[q] = hbc[q] = make_float2(0.f, 0.f);
+        e[0] = e[1] = f[0] = f[1] = make_float2(0.f, 0.f);
+#pragma unroll 1
+        for (int fb = 0; fb < v.m; fb += kFrameBatch) {
+            const int nf = min(kFrameBatch, v.m - fb);
+            __syncthreads();
+            for (int fr = half; fr < nf; fr += 2)
+                sv[arr][fr][col] = live ? src[fbase + (int64_t)(fb + fr) * v.K] : make_float2(0.f, 0.f);
+            __syncthreads();
+#pragma unroll 1
+            for (int fr = 0; fr < nf; ++fr) {
+                float2 a[2], b[2], cc[2], d[2], E[2], F[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    a[u] = sv[0][fr][ti + 16 * u];
+                    b[u] = sv[1][fr][ti + 16 * u];
+                    cc[u] = sv[2][fr][tj + 16 * u];
+                    d[u] = sv[3][fr][tj + 16 * u];
+                    E[u] = make_float2(fmaf(a[u].x, b[u].x, a[u].y * b[u].y), fmaf(a[u].y, b[u].x, -(a[u].x * b[u].y)));
+                    F[u] = make_float2(fmaf(cc[u].x, d[u].x, cc[u].y * d[u].y), fmaf(cc[u].y, d[u].x, -(cc[u].x * d[u].y)));
+                    e[u].x += E[u].x;
+                    e[u].y += E[u].y;
+                    f[u].x += F[u].x;
+                    f[u].y += F[u].y;
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int w = 0; w < 2; ++w) {
+                        const int q = u * 2 + w;
+                        cmac(sef[q], E[u], F[w]);
+                        cmac(gac[q], a[u], cc[w]);
+                        cmac(gbd[q], b[u], d[w]);
+                        cmacc(had[q], a[u], d[w]);
+                        cmacc(hbc[q], b[u], cc[w]);
+                    }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+                const int q = u * 2 + w;
+                // T = e f + G_ac conj(G_bd) + H_ad conj(H_bc), in FP64
+                const double er = e[u].x, ei = e[u].y, fr_ = f[w].x, fi = f[w].y;
+                double tr = er * fr_ - ei * fi, tim = er * fi + ei * fr_;
+                const double g1r = gac[q].x, g1i = gac[q].y, g2r = gbd[q].x, g2i = gbd[q].y;
+                tr += g1r * g2r + g1i * g2i;
+                tim += g1i * g2r - g1r * g2i;
+                const double h1r = had[q].x, h1i = had[q].y, h2r = hbc[q].x, h2i = hbc[q].y;
+                tr += h1r * h2r + h1i * h2i;
+                tim += h1i * h2r - h1r * h2i;
+                const double vr = fma(-gamma, tr, (double)sef[q].x);
+                const double vi = fma(-gamma, tim, (double)sef[q].y);
+                acc[q][0] += vr;
+                acc[q][1] += vi;
+                acc[q][2] = fma(vr, vr, acc[q][2]);
+                acc[q][3] = fma(vi, vi, acc[q][3]);
+            }
+    }
+
+    constexpr int TT = kTileX * kTileX;
+    double* o = p.part + ((int64_t)split * p.n_tiles + tile) * 4 * TT;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const int idx = (ti + 16 * u) * kTileX + tj + 16 * w;
+#pragma unroll
+            for (int comp = 0; comp < 4; ++comp) {
+                double val = acc[u * 2 + w][comp];
+                if (p.accumulate) val += o[comp * TT + idx];
+                o[comp * TT + idx] = val;
+            }
+        }
+}
+
 int blocks_per_cu(const void* fn, int threads) {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, 0) != hipSuccess || n < 1) n = 1;
@@ -594,6 +723,18 @@ hipError_t launch_s4_mfma(const GridArgs& a, hipStream_t s) {
     dim3 grid(((total + 7) / 8) * 8);
     k_s4_mfma_bf16<<<grid, kS4MThreads, 0, s>>>(a);
     return hipGetLastError();
+}
+
+hipError_t launch_s4_cross(const GridArgs& a, hipStream_t s) {
+    if (a.chunk1 <= a.chunk0) return hipSuccess;
+    const int total = a.n_tiles * a.n_split;
+    dim3 grid(((total + 7) / 8) * 8);
+    k_s4_cross<<<grid, kS4XThreads, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+int s4_cross_blocks_per_cu() {
+    return blocks_per_cu(reinterpret_cast<const void*>(&k_s4_cross), kS4XThreads);
 }
 
 int s3_blocks_per_cu() {

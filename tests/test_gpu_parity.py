@@ -296,3 +296,28 @@ def test_full_size_sampled_points(dev, precision):
     say("  sampled rel err", {k: f"{v:.2e}" for k, v in errs.items()})
     for k, v in errs.items():
         assert v <= TOL, (k, v)
+
+
+# ---------------------------------------------------------------- channel combinations
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_all_orbits_two_channels(dev, precision):
+    """Every S2/S3/S4 combination orbit of two channels (Section 7), including the
+    cross-channel S4 forms C4(a_k, b*_k, c_l, d*_l)."""
+    say("all orbits, 2 channels", precision)
+    rng = np.random.default_rng(21)
+    s = synth.ar2_chi2(256 * 8 * 9 + 5, seed=21, r=0.9, dtype=np.float64)
+    z = np.stack([s[:-5] + 0.5 * rng.standard_normal(len(s) - 5), s[5:] ** 2 - 1.0 + s[:-5]])
+    gpu, ref = both(z, dev, 256, 40, 8, window="acg", n_channels=2, precision=precision)
+    assert len(gpu["plan"]["combos4"]) == 7     # (16 + 4 + 4 + 4) / 4 orbits
+    compare(gpu, ref, label=f"orbits2-{precision}")
+
+
+def test_all_orbits_four_channels_int16(dev):
+    """Four int16 channels mixed from two AR(2)/chi-square sources plus noise:
+    all 10 / 40 / 76 combination orbits."""
+    say("all orbits, 4 int16 channels")
+    z, clipped = synth.mixed_channels(512 * 10 * 5 + 77, seed=4)
+    assert clipped == 0
+    gpu, ref = both(z, dev, 512, 64, 10, window="acg", n_channels=4)
+    assert [len(gpu["plan"][f"combos{o}"]) for o in (2, 3, 4)] == [10, 40, 76]
+    compare(gpu, ref, label="orbits4-int16")
