@@ -93,14 +93,17 @@ struct ps_plan_s {
     std::vector<int8_t> c2, c3, c4;
     double sum_g[5] = {0, 0, 0, 0, 0};
     int T = 0, TX = 0;
-    int n_tiles_sym = 0, n_tiles_full = 0, n_tilesx_sym = 0, n_tilesx_full = 0;
+    int n_tiles[4] = {0, 0, 0, 0};   // per ps::TileKind
     float* d_g = nullptr;
     float2* d_tw = nullptr;
-    int2* d_tiles_sym = nullptr;     // 64 x 64 tiles, kt <= lt
-    int2* d_tiles_full = nullptr;    // 64 x 64 tiles, all
-    int2* d_tilesx_sym = nullptr;    // 32 x 32 tiles (cross-channel S4), kt <= lt
-    int2* d_tilesx_full = nullptr;
+    int2* d_tiles[4] = {nullptr, nullptr, nullptr, nullptr};
     int n_cu = 256, bpc_s3 = 2, bpc_s4 = 2, bpc_s4x = 2;
+    // Pinned host staging of the per-execute work tables (two, used in turn;
+    // an event guards reuse until the copy that read it has finished).
+    char* h_stage[2] = {nullptr, nullptr};
+    size_t h_cap[2] = {0, 0};
+    hipEvent_t h_ev[2] = {nullptr, nullptr};
+    int h_next = 0;
     // Stage timing (ps_profile_enable): event pairs recorded on the stream.
     bool prof = false;
     struct Timed {
@@ -123,12 +126,18 @@ struct ps_plan_s {
         const int8_t* q = &c4[4 * i];
         return q[0] == q[2] && q[1] == q[3];
     }
+    ps::TileTables tables() const {
+        ps::TileTables t;
+        for (int i = 0; i < 4; ++i) t.t[i] = d_tiles[i];
+        return t;
+    }
 };
 
 namespace {
 
-// Split of the chunk range over blocks: the smallest split count whose
-// wave-quantised time is within 3% of the best for up to 64 parts.
+// Split of one kernel's chunk range over blocks when the launch holds a single
+// record and combination: the smallest split count whose wave-quantised time
+// is within 3% of the best for up to 64 parts.
 int choose_split(int n_tiles, int64_t n_chunks, int slots) {
     if (n_chunks <= 1) return 1;
     const int smax = (int)std::min<int64_t>(64, n_chunks);
@@ -143,86 +152,193 @@ int choose_split(int n_tiles, int64_t n_chunks, int slots) {
     return smax;
 }
 
-int choose_split_vec(int Nf, int64_t n_chunks, int n_cu) {
-    const int blocks = (Nf + 255) / 256;
-    int s = (4 * n_cu + blocks - 1) / blocks;
-    s = std::max(1, std::min<int>(s, 256));
-    return (int)std::min<int64_t>(s, std::max<int64_t>(1, n_chunks));
+// ------------------------------------------------------------ batch description
+struct RecInfo {
+    int64_t Np = 0, F = 0, frame0 = 0, chunk0 = 0;
+};
+
+struct SegTable {
+    std::vector<ps::Seg> v;
+    int64_t n_items = 0;
+    size_t dev_off = 0;     // byte offset of the table inside the table region
+    void add(ps::Seg s, int64_t items) {
+        s.item0 = n_items;
+        n_items += items;
+        v.push_back(s);
+    }
+};
+
+// One set of launches: every record (batched schedule) or one record
+// (per-chunk schedule).
+struct Group {
+    int rec = -1;           // record of a per-chunk group
+    SegTable s2, s3, s4s, s4x, f2, f3, f4, m3, m4;
+    SegTable* all[9] = {&s2, &s3, &s4s, &s4x, &f2, &f3, &f4, &m3, &m4};
+};
+
+struct Batch {
+    std::vector<RecInfo> ri;
+    std::vector<ps::RecDesc> rd;
+    int64_t F_tot = 0, chunks_tot = 0;
+    int64_t coef_rows = 0;          // frames resident per channel in the coefficient region
+    std::vector<Group> groups;
+    size_t off_coef = 0, off_tab = 0, off_part = 0, total = 0;
+    size_t tab_bytes = 0;
+    int64_t part_doubles = 0;
+};
+
+size_t align64(size_t x) { return (x + 63) & ~size_t(63); }
+
+// Chunk split of one stage in one group: for a single record and combination
+// the wave-quantisation choice above; for many segments the work is already
+// spread, so only small batches get split further.
+int stage_split(int64_t base_items, int n_segs, int n_tiles_one, int64_t Np_one, int slots) {
+    if (n_segs == 1) return choose_split(n_tiles_one, Np_one, slots);
+    const int64_t want = (4LL * slots + base_items - 1) / std::max<int64_t>(base_items, 1);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(64, want));
 }
 
-// Launch shape and partial-sum slot of one S4 channel combination.
-struct S4Shape {
-    bool single = true;   // a = b = c = d: real form, 64-tiles (FP32 vector or matrix cores)
-    bool sym = true;      // only tiles kt <= lt
-    int edge = 64;
-    int n_tiles = 0;
-    const int2* d_tiles = nullptr;
-    int split = 1;
-    int ncomp = 2;
-    size_t off = 0;
-};
-
-struct Layout {
-    int64_t Np = 0, F = 0;
-    int chunk_frames = 0;   // frames resident in the coefficient buffer
-    int split2 = 1, split3_sym = 1, split3_full = 1;
-    size_t off_coef = 0, off_p2 = 0, off_p3 = 0, off_p4 = 0, total = 0;
-    std::vector<size_t> p3_off;
-    std::vector<S4Shape> s4;
-    size_t p2_stride = 0;
-};
-
-Layout layout_for(const ps_plan_s* p, int64_t n_samples) {
-    Layout L;
-    L.Np = (n_samples / p->N) / p->m;
-    L.F = L.Np * p->m;
+void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_output* outs, Batch& B) {
     const bool per_chunk = p->schedule == PS_SCHED_PER_CHUNK;
-    L.chunk_frames = per_chunk ? p->m : (int)L.F;
-    if (!per_chunk) {
-        L.split2 = choose_split_vec(p->Nf, L.Np, p->n_cu);
-        L.split3_sym = choose_split(p->n_tiles_sym, L.Np, p->n_cu * p->bpc_s3);
-        L.split3_full = choose_split(p->n_tiles_full, L.Np, p->n_cu * p->bpc_s3);
+    const int m = p->m, K = p->K, Nf = p->Nf;
+    const int64_t nf2 = (int64_t)Nf * Nf;
+    const double dt = p->dt;
+    const double scale2 = dt / ((m - 1) * p->sum_g[2]);
+    const double scale3 = dt * dt * m / ((double)(m - 1) * (m - 2) * p->sum_g[3]);
+    const double scale4 = dt * dt * dt * m * (m + 1.0) / ((double)(m - 1) * (m - 2) * (m - 3) * p->sum_g[4]);
+    B.ri.assign(n, RecInfo{});
+    B.rd.assign(n, ps::RecDesc{});
+    for (int r = 0; r < n; ++r) {
+        RecInfo& q = B.ri[r];
+        q.Np = (recs[r].n_samples / p->N) / m;
+        q.F = q.Np * m;
+        q.frame0 = B.F_tot;
+        q.chunk0 = B.chunks_tot;
+        B.F_tot += q.F;
+        B.chunks_tot += q.Np;
+        ps::RecDesc& d = B.rd[r];
+        d.data = recs[r].d_data;
+        d.chan_stride = recs[r].channel_stride;
+        d.frame0 = q.frame0;
+        d.dtype = recs[r].dtype;
+        d.pad = 0;
     }
-    size_t off = 0;
-    L.off_coef = off;
-    off = align256(off + (size_t)p->C * L.chunk_frames * p->K * sizeof(float2));
-    L.off_p2 = off;
-    L.p2_stride = align256((size_t)L.split2 * 4 * p->Nf * sizeof(double));
-    off += (size_t)p->n2() * L.p2_stride;
-    L.off_p3 = off;
-    const size_t TT = (size_t)ps::kTile * ps::kTile;
-    for (int i = 0; i < p->n3(); ++i) {
-        L.p3_off.push_back(off);
-        const bool sym = p->s3_sym(i);
-        const size_t n = (size_t)(sym ? L.split3_sym : L.split3_full) *
-                         (sym ? p->n_tiles_sym : p->n_tiles_full) * 4 * TT;
-        off = align256(off + n * sizeof(double));
+    B.coef_rows = per_chunk ? m : B.F_tot;
+
+    // groups
+    if (per_chunk) {
+        for (int r = 0; r < n; ++r)
+            if (B.ri[r].Np > 0) {
+                B.groups.emplace_back();
+                B.groups.back().rec = r;
+            }
+    } else {
+        B.groups.emplace_back();
     }
-    L.off_p4 = off;
-    for (int i = 0; i < p->n4(); ++i) {
-        S4Shape sh;
-        sh.single = p->s4_single(i);
-        sh.sym = p->s4_sym(i);
-        if (sh.single) {
-            sh.edge = ps::kTile;
-            sh.n_tiles = p->n_tiles_sym;
-            sh.d_tiles = p->d_tiles_sym;
-            sh.ncomp = 2;
-            if (!per_chunk) sh.split = choose_split(sh.n_tiles, L.Np, p->n_cu * p->bpc_s4);
-        } else {
-            sh.edge = ps::kTileX;
-            sh.n_tiles = sh.sym ? p->n_tilesx_sym : p->n_tilesx_full;
-            sh.d_tiles = sh.sym ? p->d_tilesx_sym : p->d_tilesx_full;
-            sh.ncomp = 4;
-            if (!per_chunk) sh.split = choose_split(sh.n_tiles, L.Np, p->n_cu * p->bpc_s4x);
+    const int kblocks = (Nf + 255) / 256;
+    const int64_t TT = (int64_t)ps::kTile * ps::kTile, TX = (int64_t)ps::kTileX * ps::kTileX;
+    int64_t part = 0;
+    for (Group& G : B.groups) {
+        const int r_lo = per_chunk ? G.rec : 0, r_hi = per_chunk ? G.rec + 1 : n;
+        // per-stage base items (split 1) and segment counts, for the split choice
+        int64_t base2 = 0, base3 = 0, base4s = 0, base4x = 0;
+        int ns2 = 0, ns3 = 0, ns4s = 0, ns4x = 0;
+        int64_t Np_one = 0;
+        for (int r = r_lo; r < r_hi; ++r) {
+            if (B.ri[r].Np == 0) continue;
+            Np_one = B.ri[r].Np;
+            for (int i = 0; i < p->n2(); ++i) { base2 += kblocks; ++ns2; }
+            for (int i = 0; i < p->n3(); ++i) { base3 += p->n_tiles[p->s3_sym(i) ? ps::kSym64 : ps::kFull64]; ++ns3; }
+            for (int i = 0; i < p->n4(); ++i) {
+                if (p->s4_single(i)) { base4s += p->n_tiles[ps::kSym64]; ++ns4s; }
+                else { base4x += p->n_tiles[p->s4_sym(i) ? ps::kSym32 : ps::kFull32]; ++ns4x; }
+            }
         }
-        sh.off = off;
-        const size_t n = (size_t)sh.split * sh.n_tiles * sh.ncomp * sh.edge * sh.edge;
-        off = align256(off + n * sizeof(double));
-        L.s4.push_back(sh);
+        int sp2 = 1, sp3 = 1, sp4s = 1, sp4x = 1;
+        if (!per_chunk) {
+            sp2 = ns2 == 1 ? (int)std::max<int64_t>(1, std::min<int64_t>(256, (4LL * p->n_cu + kblocks - 1) / kblocks))
+                           : stage_split(base2, ns2, kblocks, Np_one, 4 * p->n_cu);
+            sp3 = stage_split(base3, ns3, ns3 ? (int)(base3 / ns3) : 1, Np_one, p->n_cu * p->bpc_s3);
+            sp4s = stage_split(base4s, ns4s, ns4s ? (int)(base4s / ns4s) : 1, Np_one, p->n_cu * p->bpc_s4);
+            sp4x = stage_split(base4x, ns4x, ns4x ? (int)(base4x / ns4x) : 1, Np_one, p->n_cu * p->bpc_s4x);
+        }
+        for (int r = r_lo; r < r_hi; ++r) {
+            const RecInfo& q = B.ri[r];
+            if (q.Np == 0) continue;
+            const ps_output* o = outs ? &outs[r] : nullptr;
+            ps::Seg base{};
+            base.coef = q.chunk0 * m * K;
+            base.n_chunks = (int32_t)q.Np;
+            for (int i = 0; i < p->n2(); ++i) {
+                ps::Seg sg = base;
+                sg.n_tiles = kblocks;
+                sg.split = (int)std::min<int64_t>(sp2, q.Np);
+                sg.tiles = 0;
+                for (int j = 0; j < 2; ++j) sg.ch[j] = p->c2[2 * i + j];
+                sg.part = part;
+                part += (int64_t)sg.split * 4 * Nf;
+                sg.out = o && o->d_s2 ? o->d_s2 + 2 * (int64_t)i * Nf : nullptr;
+                sg.err = o && o->d_s2_err ? o->d_s2_err + 2 * (int64_t)i * Nf : nullptr;
+                sg.scale = scale2;
+                sg.ncomp = 4;
+                G.s2.add(sg, (int64_t)sg.split * kblocks);
+                G.f2.add(sg, kblocks);
+            }
+            for (int i = 0; i < p->n3(); ++i) {
+                ps::Seg sg = base;
+                const bool sym = p->s3_sym(i);
+                sg.tiles = sym ? ps::kSym64 : ps::kFull64;
+                sg.n_tiles = p->n_tiles[sg.tiles];
+                sg.split = (int)std::min<int64_t>(sp3, q.Np);
+                for (int j = 0; j < 3; ++j) sg.ch[j] = p->c3[3 * i + j];
+                sg.part = part;
+                part += (int64_t)sg.split * sg.n_tiles * 4 * TT;
+                sg.out = o && o->d_s3 ? o->d_s3 + 2 * i * nf2 : nullptr;
+                sg.err = o && o->d_s3_err ? o->d_s3_err + 2 * i * nf2 : nullptr;
+                sg.scale = scale3;
+                sg.sym = sym;
+                sg.ncomp = 4;
+                G.s3.add(sg, (int64_t)sg.split * sg.n_tiles);
+                G.f3.add(sg, sg.n_tiles);
+                if (sym) G.m3.add(sg, (int64_t)((Nf + 31) / 32) * ((Nf + 31) / 32));
+            }
+            for (int i = 0; i < p->n4(); ++i) {
+                ps::Seg sg = base;
+                const bool single = p->s4_single(i), sym = p->s4_sym(i);
+                sg.tiles = single ? ps::kSym64 : (sym ? ps::kSym32 : ps::kFull32);
+                sg.n_tiles = p->n_tiles[sg.tiles];
+                sg.split = (int)std::min<int64_t>(single ? sp4s : sp4x, q.Np);
+                for (int j = 0; j < 4; ++j) sg.ch[j] = p->c4[4 * i + j];
+                sg.ncomp = single ? 2 : 4;
+                sg.part = part;
+                part += (int64_t)sg.split * sg.n_tiles * sg.ncomp * (single ? TT : TX);
+                sg.out = o && o->d_s4 ? o->d_s4 + 2 * i * nf2 : nullptr;
+                sg.err = o && o->d_s4_err ? o->d_s4_err + 2 * i * nf2 : nullptr;
+                sg.scale = scale4;
+                sg.sym = sym;
+                (single ? G.s4s : G.s4x).add(sg, (int64_t)sg.split * sg.n_tiles);
+                G.f4.add(sg, sg.n_tiles);
+                if (sym) G.m4.add(sg, (int64_t)((Nf + 31) / 32) * ((Nf + 31) / 32));
+            }
+        }
     }
-    L.total = std::max<size_t>(off, 256);
-    return L;
+    B.part_doubles = part;
+    // table region: record descriptors, then every segment table
+    size_t tab = align64(sizeof(ps::RecDesc) * std::max(1, n));
+    for (Group& G : B.groups)
+        for (SegTable* t : G.all) {
+            t->dev_off = tab;
+            tab = align64(tab + sizeof(ps::Seg) * t->v.size());
+        }
+    B.tab_bytes = tab;
+    size_t off = 0;
+    B.off_coef = off;
+    off = align256(off + (size_t)p->C * B.coef_rows * K * sizeof(float2));
+    B.off_tab = off;
+    off = align256(off + B.tab_bytes);
+    B.off_part = off;
+    off = align256(off + (size_t)B.part_doubles * sizeof(double));
+    B.total = std::max<size_t>(off, 256);
 }
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -305,12 +421,16 @@ ps_status ps_plan_destroy(ps_plan_t p) {
         hipEventDestroy(t.a);
         hipEventDestroy(t.b);
     }
+    for (int i = 0; i < 2; ++i) {
+        if (p->h_ev[i]) {
+            hipEventSynchronize(p->h_ev[i]);
+            hipEventDestroy(p->h_ev[i]);
+        }
+        if (p->h_stage[i]) hipHostFree(p->h_stage[i]);
+    }
     hipFree(p->d_g);
     hipFree(p->d_tw);
-    hipFree(p->d_tiles_sym);
-    hipFree(p->d_tiles_full);
-    hipFree(p->d_tilesx_sym);
-    hipFree(p->d_tilesx_full);
+    for (int i = 0; i < 4; ++i) hipFree(p->d_tiles[i]);
     delete p;
     return PS_OK;
 }
@@ -426,13 +546,10 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     };
     p->T = (Nf + ps::kTile - 1) / ps::kTile;
     p->TX = (Nf + ps::kTileX - 1) / ps::kTileX;
-    std::vector<int2> ts, tf, txs, txf;
-    make_tiles(p->T, ts, tf);
-    make_tiles(p->TX, txs, txf);
-    p->n_tiles_sym = (int)ts.size();
-    p->n_tiles_full = (int)tf.size();
-    p->n_tilesx_sym = (int)txs.size();
-    p->n_tilesx_full = (int)txf.size();
+    std::vector<int2> tiles[4];
+    make_tiles(p->T, tiles[ps::kSym64], tiles[ps::kFull64]);
+    make_tiles(p->TX, tiles[ps::kSym32], tiles[ps::kFull32]);
+    for (int i = 0; i < 4; ++i) p->n_tiles[i] = (int)tiles[i].size();
 
     auto upload = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
         hipError_t e = hipMalloc(dst, bytes);
@@ -442,10 +559,8 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = upload((void**)&p->d_g, gf.data(), gf.size() * sizeof(float));
     if (e == hipSuccess) e = upload((void**)&p->d_tw, tw.data(), tw.size() * sizeof(float2));
-    if (e == hipSuccess) e = upload((void**)&p->d_tiles_sym, ts.data(), ts.size() * sizeof(int2));
-    if (e == hipSuccess) e = upload((void**)&p->d_tiles_full, tf.data(), tf.size() * sizeof(int2));
-    if (e == hipSuccess) e = upload((void**)&p->d_tilesx_sym, txs.data(), txs.size() * sizeof(int2));
-    if (e == hipSuccess) e = upload((void**)&p->d_tilesx_full, txf.data(), txf.size() * sizeof(int2));
+    for (int i = 0; i < 4 && e == hipSuccess; ++i)
+        e = upload((void**)&p->d_tiles[i], tiles[i].data(), tiles[i].size() * sizeof(int2));
     if (e != hipSuccess) {
         ps_plan_destroy(p);
         return fail(PS_E_HIP, "device table setup failed: %s", hipGetErrorString(e));
@@ -517,13 +632,13 @@ ps_status ps_record_info(ps_plan_t p, int64_t n_samples, int64_t* n_chunks, uint
 
 ps_status ps_workspace_size(ps_plan_t p, const ps_record* recs, int32_t n_rec, size_t* bytes) {
     if (!p || !bytes || n_rec < 0 || (n_rec > 0 && !recs)) return fail(PS_E_INVALID_ARG, "bad argument");
-    size_t need = 256;
     for (int i = 0; i < n_rec; ++i) {
         ps_status s = check_record(p, &recs[i]);
         if (s != PS_OK) return s;
-        need = std::max(need, layout_for(p, recs[i].n_samples).total);
     }
-    *bytes = need;
+    Batch B;
+    build_batch(p, recs, n_rec, nullptr, B);
+    *bytes = B.total;
     return PS_OK;
 }
 
@@ -535,11 +650,12 @@ ps_status ps_coefficients(ps_plan_t p, const ps_record* rec, float* d_coef, ps_s
     if (F == 0) return PS_OK;
     if (!d_coef || !aligned(d_coef, 8)) return fail(PS_E_INVALID_ARG, "coefficient buffer NULL or misaligned");
     ps::FftArgs a{};
-    a.x = rec->d_data;
-    a.dtype = rec->dtype;
-    a.chan_stride = rec->channel_stride;
-    a.frame0 = 0;
-    a.n_frames = (int)F;
+    a.recs = nullptr;
+    a.single = ps::RecDesc{rec->d_data, rec->channel_stride, 0, rec->dtype, 0};
+    a.n_recs = 1;
+    a.g_lo = 0;
+    a.g_hi = F;
+    a.out_g0 = 0;
     a.n_channels = p->C;
     a.log2n = p->log2n;
     a.K = p->K;
@@ -547,10 +663,107 @@ ps_status ps_coefficients(ps_plan_t p, const ps_record* rec, float* d_coef, ps_s
     a.tw = p->d_tw;
     a.out = reinterpret_cast<float2*>(d_coef);
     a.out_chan_stride = F * p->K;
-    a.out_frame0 = 0;
     PS_HIP(ps::launch_window_rfft(a, (hipStream_t)stream));
     return PS_OK;
 }
+
+namespace {
+
+// Copy the batch's record descriptors and segment tables into the workspace
+// (one H2D copy from the plan's pinned staging buffer).
+ps_status upload_tables(ps_plan_t p, const Batch& B, char* d_tab, hipStream_t st) {
+    const int i = p->h_next;
+    p->h_next ^= 1;
+    if (p->h_ev[i]) PS_HIP(hipEventSynchronize(p->h_ev[i]));
+    if (p->h_cap[i] < B.tab_bytes) {
+        if (p->h_stage[i]) hipHostFree(p->h_stage[i]);
+        p->h_stage[i] = nullptr;
+        p->h_cap[i] = 0;
+        const size_t cap = std::max<size_t>(B.tab_bytes, 1 << 20);
+        PS_HIP(hipHostMalloc((void**)&p->h_stage[i], cap, hipHostMallocDefault));
+        p->h_cap[i] = cap;
+    }
+    if (!p->h_ev[i]) PS_HIP(hipEventCreateWithFlags(&p->h_ev[i], hipEventDisableTiming));
+    char* h = p->h_stage[i];
+    std::memcpy(h, B.rd.data(), sizeof(ps::RecDesc) * B.rd.size());
+    for (const Group& G : B.groups)
+        for (const SegTable* t : G.all)
+            if (!t->v.empty()) std::memcpy(h + t->dev_off, t->v.data(), sizeof(ps::Seg) * t->v.size());
+    PS_HIP(hipMemcpyAsync(d_tab, h, B.tab_bytes, hipMemcpyHostToDevice, st));
+    PS_HIP(hipEventRecord(p->h_ev[i], st));
+    return PS_OK;
+}
+
+ps::BatchArgs batch_args(const ps_plan_s* p, const Batch& B, const SegTable& t, char* ws, int per_chunk,
+                         int win_lo, int win_hi, int accumulate) {
+    ps::BatchArgs a{};
+    a.segs = reinterpret_cast<const ps::Seg*>(ws + B.off_tab + t.dev_off);
+    a.n_segs = (int)t.v.size();
+    a.n_items = t.n_items;
+    a.tt = p->tables();
+    a.coef = reinterpret_cast<const float2*>(ws + B.off_coef);
+    a.coef_chan_stride = B.coef_rows * p->K;
+    a.part = reinterpret_cast<double*>(ws + B.off_part);
+    a.K = p->K;
+    a.m = p->m;
+    a.Nf = p->Nf;
+    a.per_chunk = per_chunk;
+    a.win_lo = win_lo;
+    a.win_hi = win_hi;
+    a.accumulate = accumulate;
+    a.gamma = (p->m - 1.0) / (p->m * (p->m + 1.0));
+    return a;
+}
+
+ps::FinalizeArgs fin_args(const ps_plan_s* p, const Batch& B, const SegTable& t, char* ws) {
+    ps::FinalizeArgs f{};
+    f.segs = reinterpret_cast<const ps::Seg*>(ws + B.off_tab + t.dev_off);
+    f.n_segs = (int)t.v.size();
+    f.n_items = t.n_items;
+    f.tt = p->tables();
+    f.part = reinterpret_cast<const double*>(ws + B.off_part);
+    f.Nf = p->Nf;
+    return f;
+}
+
+// The moment stages of one group (one launch each).
+ps_status launch_moments(ps_plan_t p, const Batch& B, const Group& G, char* ws, int per_chunk, int win_lo,
+                         int win_hi, int accumulate, hipStream_t st) {
+    if (G.s2.n_items) {
+        StageTimer t(p, st, 2);
+        PS_HIP(ps::launch_s2(batch_args(p, B, G.s2, ws, per_chunk, win_lo, win_hi, accumulate), st));
+    }
+    if (G.s3.n_items) {
+        StageTimer t(p, st, 3);
+        PS_HIP(ps::launch_s3(batch_args(p, B, G.s3, ws, per_chunk, win_lo, win_hi, accumulate), st));
+    }
+    if (G.s4s.n_items) {
+        StageTimer t(p, st, 4);
+        const ps::BatchArgs a = batch_args(p, B, G.s4s, ws, per_chunk, win_lo, win_hi, accumulate);
+        if (p->precision == PS_PREC_FP32) {
+            PS_HIP(ps::launch_s4_single(a, st));
+        } else {
+            PS_HIP(ps::launch_s4_mfma(a, st));
+        }
+    }
+    if (G.s4x.n_items) {
+        StageTimer t(p, st, 4);
+        PS_HIP(ps::launch_s4_cross(batch_args(p, B, G.s4x, ws, per_chunk, win_lo, win_hi, accumulate), st));
+    }
+    return PS_OK;
+}
+
+ps_status launch_finalize(ps_plan_t p, const Batch& B, const Group& G, char* ws, hipStream_t st) {
+    StageTimer t(p, st, 5);
+    if (G.f2.n_items) PS_HIP(ps::launch_finalize_vec(fin_args(p, B, G.f2, ws), st));
+    if (G.f3.n_items) PS_HIP(ps::launch_finalize_grid(fin_args(p, B, G.f3, ws), st));
+    if (G.m3.n_items) PS_HIP(ps::launch_mirror(fin_args(p, B, G.m3, ws), st));
+    if (G.f4.n_items) PS_HIP(ps::launch_finalize_grid(fin_args(p, B, G.f4, ws), st));
+    if (G.m4.n_items) PS_HIP(ps::launch_mirror(fin_args(p, B, G.m4, ws), st));
+    return PS_OK;
+}
+
+}  // namespace
 
 ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_ws, size_t ws_bytes,
                      const ps_output* outs, ps_stream_t stream) {
@@ -561,180 +774,95 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
     for (int r = 0; r < n_rec; ++r) {
         ps_status s = check_record(p, &recs[r]);
         if (s != PS_OK) return s;
-        const Layout L = layout_for(p, recs[r].n_samples);
-        if (!d_ws || ws_bytes < L.total)
-            return fail(PS_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, L.total);
         const ps_output& o = outs[r];
-        const double* need[6] = {p->n2() ? o.d_s2 : nullptr, p->n2() ? o.d_s2_err : nullptr,
-                                 p->n3() ? o.d_s3 : nullptr, p->n3() ? o.d_s3_err : nullptr,
-                                 p->n4() ? o.d_s4 : nullptr, p->n4() ? o.d_s4_err : nullptr};
-        for (const double* q : need)
+        const double* ptrs[6] = {o.d_s2, o.d_s2_err, o.d_s3, o.d_s3_err, o.d_s4, o.d_s4_err};
+        for (const double* q : ptrs)
             if (q && !aligned(q, 8)) return fail(PS_E_INVALID_ARG, "output pointer misaligned");
     }
+    if (n_rec == 0) return PS_OK;
+    Batch B;
+    build_batch(p, recs, n_rec, outs, B);
+    if (!d_ws || ws_bytes < B.total) return fail(PS_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
+
     const int Nf = p->Nf, m = p->m;
-    const double dt = p->dt;
-    const double scale2 = dt / ((m - 1) * p->sum_g[2]);
-    const double scale3 = dt * dt * m / ((double)(m - 1) * (m - 2) * p->sum_g[3]);
-    const double scale4 = dt * dt * dt * m * (m + 1.0) / ((double)(m - 1) * (m - 2) * (m - 3) * p->sum_g[4]);
-    const double gamma = (m - 1.0) / (m * (m + 1.0));
     const int64_t nf2 = (int64_t)Nf * Nf;
-
     for (int r = 0; r < n_rec; ++r) {
-        const ps_record& rec = recs[r];
+        if (B.ri[r].Np > 0) continue;
         const ps_output& o = outs[r];
-        const Layout L = layout_for(p, rec.n_samples);
-        if (L.Np == 0) {
-            PS_HIP(ps::launch_fill_nan(o.d_s2, 2 * (int64_t)p->n2() * Nf, st));
-            PS_HIP(ps::launch_fill_nan(o.d_s2_err, 2 * (int64_t)p->n2() * Nf, st));
-            PS_HIP(ps::launch_fill_nan(o.d_s3, 2 * (int64_t)p->n3() * nf2, st));
-            PS_HIP(ps::launch_fill_nan(o.d_s3_err, 2 * (int64_t)p->n3() * nf2, st));
-            PS_HIP(ps::launch_fill_nan(o.d_s4, 2 * (int64_t)p->n4() * nf2, st));
-            PS_HIP(ps::launch_fill_nan(o.d_s4_err, 2 * (int64_t)p->n4() * nf2, st));
-            continue;
-        }
-        char* ws = static_cast<char*>(d_ws);
-        float2* coef = reinterpret_cast<float2*>(ws + L.off_coef);
-        const int64_t coef_cs = (int64_t)L.chunk_frames * p->K;
-        const bool per_chunk = p->schedule == PS_SCHED_PER_CHUNK;
-        const int64_t n_steps = per_chunk ? L.Np : 1;
+        PS_HIP(ps::launch_fill_nan(o.d_s2, 2 * (int64_t)p->n2() * Nf, st));
+        PS_HIP(ps::launch_fill_nan(o.d_s2_err, 2 * (int64_t)p->n2() * Nf, st));
+        PS_HIP(ps::launch_fill_nan(o.d_s3, 2 * (int64_t)p->n3() * nf2, st));
+        PS_HIP(ps::launch_fill_nan(o.d_s3_err, 2 * (int64_t)p->n3() * nf2, st));
+        PS_HIP(ps::launch_fill_nan(o.d_s4, 2 * (int64_t)p->n4() * nf2, st));
+        PS_HIP(ps::launch_fill_nan(o.d_s4_err, 2 * (int64_t)p->n4() * nf2, st));
+    }
+    if (B.chunks_tot == 0) return PS_OK;
 
-        for (int64_t step = 0; step < n_steps; ++step) {
-            const int c_lo = per_chunk ? (int)step : 0;
-            const int c_hi = per_chunk ? (int)step + 1 : (int)L.Np;
-            ps::FftArgs fa{};
-            fa.x = rec.d_data;
-            fa.dtype = rec.dtype;
-            fa.chan_stride = rec.channel_stride;
-            fa.frame0 = (int64_t)c_lo * m;
-            fa.n_frames = (c_hi - c_lo) * m;
-            fa.n_channels = p->C;
-            fa.log2n = p->log2n;
-            fa.K = p->K;
-            fa.g = p->d_g;
-            fa.tw = p->d_tw;
-            fa.out = coef;
-            fa.out_chan_stride = coef_cs;
-            fa.out_frame0 = (int64_t)c_lo * m;
+    char* ws = static_cast<char*>(d_ws);
+    ps_status s = upload_tables(p, B, ws + B.off_tab, st);
+    if (s != PS_OK) return s;
+    float2* coef = reinterpret_cast<float2*>(ws + B.off_coef);
+    const int64_t coef_cs = B.coef_rows * p->K;
+
+    ps::FftArgs fa{};
+    fa.n_channels = p->C;
+    fa.log2n = p->log2n;
+    fa.K = p->K;
+    fa.g = p->d_g;
+    fa.tw = p->d_tw;
+    fa.out = coef;
+    fa.out_chan_stride = coef_cs;
+    ps::CentreArgs ca{};
+    ca.coef = coef;
+    ca.coef_chan_stride = coef_cs;
+    ca.K = p->K;
+    ca.m = m;
+    ca.n_channels = p->C;
+
+    if (p->schedule != PS_SCHED_PER_CHUNK) {
+        fa.recs = reinterpret_cast<const ps::RecDesc*>(ws + B.off_tab);
+        fa.n_recs = n_rec;
+        fa.g_lo = 0;
+        fa.g_hi = B.F_tot;
+        fa.out_g0 = 0;
+        {
+            StageTimer t(p, st, 0);
+            PS_HIP(ps::launch_window_rfft(fa, st));
+        }
+        ca.n_chunks = B.chunks_tot;
+        {
+            StageTimer t(p, st, 1);
+            PS_HIP(ps::launch_centre(ca, st));
+        }
+        s = launch_moments(p, B, B.groups[0], ws, 0, 0, 0, 0, st);
+        if (s != PS_OK) return s;
+        return launch_finalize(p, B, B.groups[0], ws, st);
+    }
+
+    // Per-chunk schedule: one short-time estimate per launch set, record by record.
+    for (const Group& G : B.groups) {
+        const int r = G.rec;
+        fa.recs = nullptr;
+        fa.single = ps::RecDesc{recs[r].d_data, recs[r].channel_stride, 0, recs[r].dtype, 0};
+        fa.n_recs = 1;
+        for (int64_t c = 0; c < B.ri[r].Np; ++c) {
+            fa.g_lo = c * m;
+            fa.g_hi = (c + 1) * m;
+            fa.out_g0 = c * m;
             {
                 StageTimer t(p, st, 0);
                 PS_HIP(ps::launch_window_rfft(fa, st));
             }
-
-            ps::CentreArgs ca{};
-            ca.coef = coef;
-            ca.coef_chan_stride = coef_cs;
-            ca.K = p->K;
-            ca.m = m;
-            ca.n_chunks = c_hi - c_lo;
-            ca.n_channels = p->C;
+            ca.n_chunks = 1;
             {
                 StageTimer t(p, st, 1);
                 PS_HIP(ps::launch_centre(ca, st));
             }
-
-            ps::CoefView cv{coef, coef_cs, p->K, m, c_lo};
-            const int acc = step > 0 ? 1 : 0;
-            for (int i = 0; i < p->n2(); ++i) {
-                ps::S2Args a{};
-                a.v = cv;
-                a.Nf = Nf;
-                a.a = p->c2[2 * i];
-                a.b = p->c2[2 * i + 1];
-                a.chunk0 = c_lo;
-                a.chunk1 = c_hi;
-                a.n_split = L.split2;
-                a.part = reinterpret_cast<double*>(ws + L.off_p2 + i * L.p2_stride);
-                a.accumulate = acc;
-                StageTimer t(p, st, 2);
-                PS_HIP(ps::launch_s2(a, st));
-            }
-            for (int i = 0; i < p->n3(); ++i) {
-                const bool sym = p->s3_sym(i);
-                ps::GridArgs a{};
-                a.v = cv;
-                a.Nf = Nf;
-                for (int j = 0; j < 3; ++j) a.ch[j] = p->c3[3 * i + j];
-                a.tiles = sym ? p->d_tiles_sym : p->d_tiles_full;
-                a.n_tiles = sym ? p->n_tiles_sym : p->n_tiles_full;
-                a.chunk0 = c_lo;
-                a.chunk1 = c_hi;
-                a.n_split = sym ? L.split3_sym : L.split3_full;
-                a.part = reinterpret_cast<double*>(ws + L.p3_off[i]);
-                a.accumulate = acc;
-                StageTimer t(p, st, 3);
-                PS_HIP(ps::launch_s3(a, st));
-            }
-            for (int i = 0; i < p->n4(); ++i) {
-                const S4Shape& sh = L.s4[i];
-                ps::GridArgs a{};
-                a.v = cv;
-                a.Nf = Nf;
-                for (int j = 0; j < 4; ++j) a.ch[j] = p->c4[4 * i + j];
-                a.tiles = sh.d_tiles;
-                a.n_tiles = sh.n_tiles;
-                a.chunk0 = c_lo;
-                a.chunk1 = c_hi;
-                a.n_split = sh.split;
-                a.part = reinterpret_cast<double*>(ws + sh.off);
-                a.accumulate = acc;
-                a.gamma = gamma;
-                StageTimer t(p, st, 4);
-                if (!sh.single) {
-                    PS_HIP(ps::launch_s4_cross(a, st));
-                } else if (p->precision == PS_PREC_FP32) {
-                    PS_HIP(ps::launch_s4_single(a, st));
-                } else {
-                    PS_HIP(ps::launch_s4_mfma(a, st));
-                }
-            }
+            s = launch_moments(p, B, G, ws, 1, (int)c, (int)c + 1, c > 0 ? 1 : 0, st);
+            if (s != PS_OK) return s;
         }
-
-        for (int i = 0; i < p->n2(); ++i) {
-            ps::FinalizeVecArgs f{};
-            f.part = reinterpret_cast<const double*>(ws + L.off_p2 + i * L.p2_stride);
-            f.n_split = L.split2;
-            f.Nf = Nf;
-            f.n_chunks = L.Np;
-            f.scale = scale2;
-            f.out = o.d_s2 ? o.d_s2 + 2 * (int64_t)i * Nf : nullptr;
-            f.err = o.d_s2_err ? o.d_s2_err + 2 * (int64_t)i * Nf : nullptr;
-            StageTimer t(p, st, 5);
-            PS_HIP(ps::launch_finalize_vec(f, st));
-        }
-        for (int i = 0; i < p->n3(); ++i) {
-            const bool sym = p->s3_sym(i);
-            ps::FinalizeGridArgs f{};
-            f.part = reinterpret_cast<const double*>(ws + L.p3_off[i]);
-            f.n_split = sym ? L.split3_sym : L.split3_full;
-            f.n_tiles = sym ? p->n_tiles_sym : p->n_tiles_full;
-            f.ncomp = 4;
-            f.edge = ps::kTile;
-            f.sym = sym;
-            f.Nf = Nf;
-            f.n_chunks = L.Np;
-            f.scale = scale3;
-            f.out = o.d_s3 ? o.d_s3 + 2 * i * nf2 : nullptr;
-            f.err = o.d_s3_err ? o.d_s3_err + 2 * i * nf2 : nullptr;
-            StageTimer t(p, st, 5);
-            PS_HIP(ps::launch_finalize_grid(f, sym ? p->d_tiles_sym : p->d_tiles_full, st));
-        }
-        for (int i = 0; i < p->n4(); ++i) {
-            const S4Shape& sh = L.s4[i];
-            ps::FinalizeGridArgs f{};
-            f.part = reinterpret_cast<const double*>(ws + sh.off);
-            f.n_split = sh.split;
-            f.n_tiles = sh.n_tiles;
-            f.ncomp = sh.ncomp;
-            f.edge = sh.edge;
-            f.sym = sh.sym;
-            f.Nf = Nf;
-            f.n_chunks = L.Np;
-            f.scale = scale4;
-            f.out = o.d_s4 ? o.d_s4 + 2 * i * nf2 : nullptr;
-            f.err = o.d_s4_err ? o.d_s4_err + 2 * i * nf2 : nullptr;
-            StageTimer t(p, st, 5);
-            PS_HIP(ps::launch_finalize_grid(f, sh.d_tiles, st));
-        }
+        s = launch_finalize(p, B, G, ws, st);
+        if (s != PS_OK) return s;
     }
     return PS_OK;
 }

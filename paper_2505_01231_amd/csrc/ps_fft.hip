@@ -4,7 +4,9 @@
 //
 //   a_k = sum_{i<N} g_i z_i exp(+2 pi j i k / N),  k < K        (dt folded into the output scale)
 //
-// One 256-thread block transforms one frame.  The N real samples are packed as
+// One 256-thread block transforms one frame; the frames of every record of a
+// batch form one launch (the block finds its record by binary search over the
+// records' first global frame).  The N real samples are packed as
 // M = N/2 complex points x_n = w_{2n} + j w_{2n+1} (w = g z), transformed by a
 // radix-4 (plus one radix-2) Stockham FFT in LDS with the +j sign, and
 // unpacked: with X the M-point transform,
@@ -25,28 +27,41 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 
 template <typename T>
-__device__ __forceinline__ float to_f(T v) { return static_cast<float>(v); }
+__device__ __forceinline__ void load_windowed(float2* s, const T* __restrict__ xf, const float* __restrict__ g,
+                                              int M, int tid) {
+    for (int n = tid; n < M; n += kFftThreads) {
+        const float w0 = g[2 * n] * static_cast<float>(xf[2 * n]);
+        const float w1 = g[2 * n + 1] * static_cast<float>(xf[2 * n + 1]);
+        s[n] = make_float2(w0, w1);
+    }
+}
 
-template <int LOG2N, typename T>
-__global__ __launch_bounds__(kFftThreads) void k_window_rfft(
-    const T* __restrict__ x, int64_t chan_stride, int64_t frame0, const float* __restrict__ g,
-    const float2* __restrict__ tw, float2* __restrict__ out, int64_t out_chan_stride,
-    int64_t out_frame0, int K) {
+template <int LOG2N>
+__global__ __launch_bounds__(kFftThreads) void k_window_rfft(FftArgs a) {
     constexpr int N = 1 << LOG2N;
     constexpr int M = N / 2;
     constexpr int LOG2M = LOG2N - 1;
     __shared__ float2 s[M];
 
-    const int64_t f = frame0 + blockIdx.x;
+    const int64_t gf = a.g_lo + blockIdx.x;     // global frame
     const int c = blockIdx.y;
-    const T* xf = x + c * chan_stride + f * N;
-    const int tid = threadIdx.x;
-
-    for (int n = tid; n < M; n += kFftThreads) {
-        const float w0 = g[2 * n] * to_f(xf[2 * n]);
-        const float w1 = g[2 * n + 1] * to_f(xf[2 * n + 1]);
-        s[n] = make_float2(w0, w1);
+    RecDesc r = a.single;
+    if (a.recs) {
+        int lo = 0, hi = a.n_recs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.recs[mid].frame0 <= gf) lo = mid;
+            else hi = mid - 1;
+        }
+        r = a.recs[lo];
     }
+    const int64_t off = c * r.chan_stride + (gf - r.frame0) * N;
+    const int tid = threadIdx.x;
+    const float* __restrict__ g = a.g;
+    const float2* __restrict__ tw = a.tw;
+    if (r.dtype == 0) load_windowed(s, static_cast<const float*>(r.data) + off, g, M, tid);
+    else if (r.dtype == 1) load_windowed(s, static_cast<const double*>(r.data) + off, g, M, tid);
+    else load_windowed(s, static_cast<const int16_t*>(r.data) + off, g, M, tid);
     __syncthreads();
 
     // Radix-4 Stockham passes: span Ns = 1, 4, 16, ...; butterfly j reads
@@ -121,7 +136,8 @@ __global__ __launch_bounds__(kFftThreads) void k_window_rfft(
         __syncthreads();
     }
 
-    float2* o = out + c * out_chan_stride + (f - out_frame0) * K;
+    const int K = a.K;
+    float2* o = a.out + c * a.out_chan_stride + (gf - a.out_g0) * K;
     for (int k = tid; k < K; k += kFftThreads) {
         const float2 xk = s[k & (M - 1)];
         const float2 xm = s[(M - k) & (M - 1)];
@@ -136,26 +152,9 @@ __global__ __launch_bounds__(kFftThreads) void k_window_rfft(
 
 template <int LOG2N>
 hipError_t launch_n(const FftArgs& a, hipStream_t st) {
-    dim3 grid(a.n_frames, a.n_channels);
-    switch (a.dtype) {
-        case 0:
-            k_window_rfft<LOG2N, float><<<grid, kFftThreads, 0, st>>>(
-                static_cast<const float*>(a.x), a.chan_stride, a.frame0, a.g, a.tw, a.out,
-                a.out_chan_stride, a.out_frame0, a.K);
-            break;
-        case 1:
-            k_window_rfft<LOG2N, double><<<grid, kFftThreads, 0, st>>>(
-                static_cast<const double*>(a.x), a.chan_stride, a.frame0, a.g, a.tw, a.out,
-                a.out_chan_stride, a.out_frame0, a.K);
-            break;
-        case 2:
-            k_window_rfft<LOG2N, int16_t><<<grid, kFftThreads, 0, st>>>(
-                static_cast<const int16_t*>(a.x), a.chan_stride, a.frame0, a.g, a.tw, a.out,
-                a.out_chan_stride, a.out_frame0, a.K);
-            break;
-        default:
-            return hipErrorInvalidValue;
-    }
+    const int64_t n = a.g_hi - a.g_lo;
+    dim3 grid((unsigned)n, a.n_channels);
+    k_window_rfft<LOG2N><<<grid, kFftThreads, 0, st>>>(a);
     return hipGetLastError();
 }
 
@@ -181,7 +180,7 @@ __global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64
 }  // namespace
 
 hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s) {
-    if (a.n_frames <= 0 || a.n_channels <= 0) return hipSuccess;
+    if (a.g_hi <= a.g_lo || a.n_channels <= 0 || a.n_recs <= 0) return hipSuccess;
     switch (a.log2n) {
         case 8: return launch_n<8>(a, s);
         case 9: return launch_n<9>(a, s);
@@ -195,7 +194,7 @@ hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s) {
 
 hipError_t launch_centre(const CentreArgs& a, hipStream_t s) {
     if (a.n_chunks <= 0) return hipSuccess;
-    dim3 grid((a.K + 255) / 256, a.n_chunks, a.n_channels);
+    dim3 grid((a.K + 255) / 256, (unsigned)a.n_chunks, a.n_channels);
     k_centre<<<grid, 256, 0, s>>>(a.coef, a.coef_chan_stride, a.K, a.m);
     return hipGetLastError();
 }

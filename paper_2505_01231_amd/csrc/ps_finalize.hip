@@ -30,71 +30,78 @@ __device__ __forceinline__ void mean_sigma(double s, double s2, double np, doubl
     sigma = fabs(scale) * sqrt(fmax(var, 0.0) / np);
 }
 
-__global__ __launch_bounds__(256) void k_finalize_vec(FinalizeVecArgs p) {
-    const int k = blockIdx.x * 256 + threadIdx.x;
+// S2: one block per (record, combination, 256-wide k block).
+__global__ __launch_bounds__(256) void k_finalize_vec(FinalizeArgs p) {
+    const int64_t x = blockIdx.x;
+    if (x >= p.n_items) return;
+    const Seg& sg = p.segs[find_seg(p.segs, p.n_segs, x)];
+    const int k = (int)(x - sg.item0) * 256 + threadIdx.x;
     if (k >= p.Nf) return;
+    const double* part = p.part + sg.part;
     double s[4] = {0, 0, 0, 0};
-    for (int sp = 0; sp < p.n_split; ++sp)
-        for (int c = 0; c < 4; ++c) s[c] += p.part[((int64_t)sp * 4 + c) * p.Nf + k];
-    const double np = (double)p.n_chunks;
+    for (int sp = 0; sp < sg.split; ++sp)
+        for (int c = 0; c < 4; ++c) s[c] += part[((int64_t)sp * 4 + c) * p.Nf + k];
+    const double np = (double)sg.n_chunks;
     double mr, sr, mi, si;
-    mean_sigma(s[0], s[2], np, p.scale, mr, sr);
-    mean_sigma(s[1], s[3], np, p.scale, mi, si);
-    if (p.out) {
-        p.out[2 * k] = mr;
-        p.out[2 * k + 1] = mi;
+    mean_sigma(s[0], s[2], np, sg.scale, mr, sr);
+    mean_sigma(s[1], s[3], np, sg.scale, mi, si);
+    if (sg.out) {
+        sg.out[2 * k] = mr;
+        sg.out[2 * k + 1] = mi;
     }
-    if (p.err) {
-        p.err[2 * k] = sr;
-        p.err[2 * k + 1] = si;
+    if (sg.err) {
+        sg.err[2 * k] = sr;
+        sg.err[2 * k + 1] = si;
     }
 }
 
-// One block per partial tile: sums over the chunk parts in a fixed order and
-// writes the tile's grid points (all of them, or only k <= l for symmetric
-// spectra) with coalesced reads of the partials and coalesced row writes.
-__global__ __launch_bounds__(256) void k_finalize_tiles(FinalizeGridArgs p, const int2* tiles) {
-    const int tile = blockIdx.x;
-    const int2 t = tiles[tile];
-    const int E = p.edge;
+// S3 / S4: one block per (record, combination, partial tile): sums over the
+// chunk parts in a fixed order and writes the tile's grid points (all of them,
+// or only k <= l for symmetric spectra) with coalesced accesses.
+__global__ __launch_bounds__(256) void k_finalize_tiles(FinalizeArgs p) {
+    const int64_t x = blockIdx.x;
+    if (x >= p.n_items) return;
+    const Seg& sg = p.segs[find_seg(p.segs, p.n_segs, x)];
+    const int tile = (int)(x - sg.item0);
+    const int E = sg.tiles >= kSym32 ? kTileX : kTile;
+    const int2 t = p.tt.t[sg.tiles][tile];
     const int k0 = t.x * E, l0 = t.y * E;
     const int TT = E * E;
-    const double np = (double)p.n_chunks;
+    const double np = (double)sg.n_chunks;
+    const int ncomp = sg.ncomp;
     for (int idx = threadIdx.x; idx < TT; idx += 256) {
         const int k = k0 + idx / E, l = l0 + idx % E;
-        if (k >= p.Nf || l >= p.Nf || (p.sym && k > l)) continue;
+        if (k >= p.Nf || l >= p.Nf || (sg.sym && k > l)) continue;
         double s[4] = {0, 0, 0, 0};
-        for (int sp = 0; sp < p.n_split; ++sp) {
-            const double* q = p.part + ((int64_t)sp * p.n_tiles + tile) * p.ncomp * TT + idx;
-            for (int c = 0; c < p.ncomp; ++c) s[c] += q[c * TT];
+        for (int sp = 0; sp < sg.split; ++sp) {
+            const double* q = p.part + sg.part + ((int64_t)sp * sg.n_tiles + tile) * ncomp * TT + idx;
+            for (int c = 0; c < ncomp; ++c) s[c] += q[c * TT];
         }
         double mr, sr, mi = 0.0, si = 0.0;
-        if (p.ncomp == 4) {
-            mean_sigma(s[0], s[2], np, p.scale, mr, sr);
-            mean_sigma(s[1], s[3], np, p.scale, mi, si);
+        if (ncomp == 4) {
+            mean_sigma(s[0], s[2], np, sg.scale, mr, sr);
+            mean_sigma(s[1], s[3], np, sg.scale, mi, si);
         } else {
-            mean_sigma(s[0], s[1], np, p.scale, mr, sr);
+            mean_sigma(s[0], s[1], np, sg.scale, mr, sr);
             if (np < 1.0) mi = mr;      // NaN
             if (np < 2.0) si = sr;      // NaN
         }
         const int64_t o = ((int64_t)k * p.Nf + l) * 2;
-        if (p.out) {
-            p.out[o] = mr;
-            p.out[o + 1] = mi;
+        if (sg.out) {
+            sg.out[o] = mr;
+            sg.out[o + 1] = mi;
         }
-        if (p.err) {
-            p.err[o] = sr;
-            p.err[o + 1] = si;
+        if (sg.err) {
+            sg.err[o] = sr;
+            sg.err[o + 1] = si;
         }
     }
 }
 
 // Symmetric spectra: copy (k, l) -> (l, k) for k < l through an LDS transpose
-// of 32 x 32 blocks of complex (16-byte) values.
-__global__ __launch_bounds__(256) void k_mirror(double* __restrict__ a, int Nf) {
-    __shared__ double2 sh[32][33];
-    const int bx = blockIdx.x, by = blockIdx.y;     // destination block (row by, column bx), by >= bx
-    if (by < bx) return;
+// of 32 x 32 blocks of complex (16-byte) values; one block per (segment,
+// destination block), for the spectrum and its error bars.
+__device__ __forceinline__ void mirror_block(double* a, int Nf, int bx, int by, double2 (*sh)[33]) {
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     double2* v = reinterpret_cast<double2*>(a);
     // source block: rows bx*32.., columns by*32.. (upper triangle)
@@ -107,6 +114,20 @@ __global__ __launch_bounds__(256) void k_mirror(double* __restrict__ a, int Nf) 
         const int k = by * 32 + r, l = bx * 32 + tx;    // destination (k, l) with k > l
         if (k < Nf && l < Nf && k > l) v[(int64_t)k * Nf + l] = sh[tx][r];
     }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_mirror(FinalizeArgs p) {
+    __shared__ double2 sh[32][33];
+    const int64_t x = blockIdx.x;
+    if (x >= p.n_items) return;
+    const Seg& sg = p.segs[find_seg(p.segs, p.n_segs, x)];
+    const int nb = (p.Nf + 31) / 32;
+    const int local = (int)(x - sg.item0);
+    const int by = local / nb, bx = local % nb;   // destination block row by, column bx
+    if (by < bx) return;
+    if (sg.out) mirror_block(sg.out, p.Nf, bx, by, sh);
+    if (sg.err) mirror_block(sg.err, p.Nf, bx, by, sh);
 }
 
 __global__ void k_fill_nan(double* p, int64_t n) {
@@ -116,19 +137,21 @@ __global__ void k_fill_nan(double* p, int64_t n) {
 
 }  // namespace
 
-hipError_t launch_finalize_vec(const FinalizeVecArgs& a, hipStream_t s) {
-    k_finalize_vec<<<(a.Nf + 255) / 256, 256, 0, s>>>(a);
+hipError_t launch_finalize_vec(const FinalizeArgs& a, hipStream_t s) {
+    if (a.n_items <= 0) return hipSuccess;
+    k_finalize_vec<<<(unsigned)a.n_items, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize_grid(const FinalizeGridArgs& a, const int2* tiles, hipStream_t s) {
-    k_finalize_tiles<<<a.n_tiles, 256, 0, s>>>(a, tiles);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !a.sym) return e;
-    const int nb = (a.Nf + 31) / 32;
-    dim3 grid(nb, nb);
-    if (a.out) k_mirror<<<grid, 256, 0, s>>>(a.out, a.Nf);
-    if (a.err) k_mirror<<<grid, 256, 0, s>>>(a.err, a.Nf);
+hipError_t launch_finalize_grid(const FinalizeArgs& a, hipStream_t s) {
+    if (a.n_items <= 0) return hipSuccess;
+    k_finalize_tiles<<<(unsigned)a.n_items, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mirror(const FinalizeArgs& a, hipStream_t s) {
+    if (a.n_items <= 0) return hipSuccess;
+    k_mirror<<<(unsigned)a.n_items, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

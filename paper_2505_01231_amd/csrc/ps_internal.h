@@ -1,5 +1,12 @@
 // Internal interface between the host runtime (ps_api.cpp) and the kernel
 // launchers (ps_fft.hip, ps_moments.hip, ps_finalize.hip).  Not part of the ABI.
+//
+// Batching: one ps_execute runs each stage as ONE launch over every record and
+// every channel combination.  The host describes the work as a table of
+// segments (one per record and combination) that it copies into the
+// workspace; each block finds its segment by binary search over the
+// segments' first work-item index and derives its tile, chunk part and
+// partial-sum slot from it.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,8 +15,8 @@
 
 namespace ps {
 
-// Output-tile edge of the S3/S4 moment kernels: a tile covers 64 x 64 (k, l)
-// grid points; the 256 threads of a block each own a 4 x 4 sub-grid.
+// Output-tile edge of the S3 / single-channel S4 kernels: a tile covers 64 x 64
+// (k, l) grid points; the 256 threads of a block each own a 4 x 4 sub-grid.
 constexpr int kTile = 64;
 // Tile edge of the cross-channel S4 kernel (20 frame sums per grid point leave
 // room for 2 x 2 grid points per thread only).
@@ -18,21 +25,38 @@ constexpr int kTileX = 32;
 constexpr int kFrameBatch = 16;
 constexpr int kFrameBatchSmall = 10;
 
-// ---------------------------------------------------------------- stage a1
-struct FftArgs {
-    const void* x;          // sample 0 of channel 0 of the record
-    int dtype;              // ps_dtype
+// Tile tables owned by the plan.
+enum TileKind { kSym64 = 0, kFull64 = 1, kSym32 = 2, kFull32 = 3 };
+struct TileTables {
+    const int2* t[4];
+};
+
+// ---------------------------------------------------------------- records (stage a1)
+// Coefficient region of the workspace: [C][F_total][K] float2, records'
+// frames concatenated in record order (chunk g of the batch = frames
+// [g m, (g+1) m) of every channel).
+struct RecDesc {
+    const void* data;       // sample 0 of channel 0
     int64_t chan_stride;    // elements between channels
-    int64_t frame0;         // first frame to transform
-    int n_frames;           // frames per channel
+    int64_t frame0;         // first global frame of this record
+    int32_t dtype;          // ps_dtype
+    int32_t pad;
+};
+
+struct FftArgs {
+    const RecDesc* recs;    // device table sorted by frame0, or NULL: use `single`
+    RecDesc single;
+    int n_recs;
+    int64_t g_lo, g_hi;     // global frames to transform
+    int64_t out_g0;         // global frame stored at row 0 of `out`
     int n_channels;
     int log2n;              // log2(N), 8..13
     int K;                  // coefficients kept per frame
     const float* g;         // window [N]
     const float2* tw;       // exp(+2 pi j t / N), t < N
-    float2* out;            // [C][out_frames][K], frame index (f - frame0_out)
-    int64_t out_chan_stride;  // float2 elements between channels of `out`
-    int64_t out_frame0;     // frame index subtracted before writing
+    float2* out;            // [C][rows][K]
+    int64_t out_chan_stride;
+    int dtype;              // common dtype of the records (launch template)
 };
 hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s);
 
@@ -41,47 +65,49 @@ struct CentreArgs {
     float2* coef;           // [C][n_chunks * m][K]
     int64_t coef_chan_stride;
     int K, m;
-    int n_chunks;
+    int64_t n_chunks;
     int n_channels;
 };
 hipError_t launch_centre(const CentreArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- moments
-// Chunk-centred coefficients a' = a - mean_f a (after launch_centre).
-struct CoefView {
-    const float2* coef;     // [C][frames][K]; chunk c starts at frame (c - coef_chunk0) * m
+// One segment = one (record, channel combination) of one stage.
+struct Seg {
+    int64_t item0;          // first work item (block) of the segment
+    int64_t coef;           // float2 offset of the record's chunk 0 in the coefficient region
+    int64_t part;           // double offset of the segment's partial sums
+    int32_t n_tiles;        // tiles (S3/S4) or 256-wide k blocks (S2)
+    int32_t split;          // chunk parts
+    int32_t n_chunks;       // Np of the record
+    int32_t tiles;          // TileKind
+    int32_t ch[4];          // channels of the combination
+    double* out;            // finalize: spectrum slot, [Nf][2] or [Nf][Nf][2]
+    double* err;
+    double scale;           // finalize: prefactor * dt^(n-1) / sum g^n
+    int32_t sym;            // finalize: mirror (k, l) -> (l, k)
+    int32_t ncomp;          // finalize: 4 (complex) or 2 (real)
+};
+
+struct BatchArgs {
+    const Seg* segs;        // device table, sorted by item0
+    int n_segs;
+    int64_t n_items;
+    TileTables tt;
+    const float2* coef;     // coefficient region
     int64_t coef_chan_stride;
-    int K, m;
-    int coef_chunk0;
-};
-
-struct S2Args {
-    CoefView v;
-    int Nf;
-    int a, b;               // channels: C2(a_k, b*_k)
-    int chunk0, chunk1;     // chunk range of this launch
-    int n_split;
-    double* part;           // [n_split][4][Nf]: sum re, sum im, sum re^2, sum im^2 of sum_f a' b'*
-    int accumulate;
-};
-hipError_t launch_s2(const S2Args& a, hipStream_t s);
-
-struct GridArgs {
-    CoefView v;
-    int Nf;
-    int ch[4];              // channels of the combination
-    const int2* tiles;      // [n_tiles] (kt, lt)
-    int n_tiles;
-    int chunk0, chunk1;
-    int n_split;
-    double* part;           // [n_split][n_tiles][ncomp][kTile*kTile]
-    int accumulate;
+    double* part;           // partial-sum region
+    int K, m, Nf;
+    // Per-chunk schedule: only chunks [win_lo, win_hi) of each segment are
+    // processed and chunk c sits at frame (c - win_lo) m of the region.
+    int per_chunk, win_lo, win_hi;
+    int accumulate;         // add to the partial sums instead of overwriting
     double gamma;           // S4: (m-1)/(m(m+1))
 };
-hipError_t launch_s3(const GridArgs& a, hipStream_t s);
-hipError_t launch_s4_single(const GridArgs& a, hipStream_t s);
-hipError_t launch_s4_mfma(const GridArgs& a, hipStream_t s);
-hipError_t launch_s4_cross(const GridArgs& a, hipStream_t s);
+hipError_t launch_s2(const BatchArgs& a, hipStream_t s);
+hipError_t launch_s3(const BatchArgs& a, hipStream_t s);
+hipError_t launch_s4_single(const BatchArgs& a, hipStream_t s);
+hipError_t launch_s4_mfma(const BatchArgs& a, hipStream_t s);
+hipError_t launch_s4_cross(const BatchArgs& a, hipStream_t s);
 
 int s3_blocks_per_cu();
 int s4_blocks_per_cu();
@@ -89,29 +115,30 @@ int s4_mfma_blocks_per_cu();
 int s4_cross_blocks_per_cu();
 
 // ---------------------------------------------------------------- finalize
-struct FinalizeVecArgs {
-    const double* part;     // [n_split][4][Nf]
-    int n_split, Nf;
-    int64_t n_chunks;
-    double scale;
-    double* out;            // [Nf][2]
-    double* err;            // [Nf][2]
-};
-hipError_t launch_finalize_vec(const FinalizeVecArgs& a, hipStream_t s);
-
-struct FinalizeGridArgs {
-    const double* part;     // [n_split][n_tiles][ncomp][edge*edge]
-    int n_split, n_tiles, ncomp;
-    int edge;               // tile edge (kTile or kTileX)
-    int sym;                // only tiles kt <= lt exist; (k, l) with k > l is the mirror of (l, k)
+struct FinalizeArgs {
+    const Seg* segs;        // items: S2 k blocks, or tiles
+    int n_segs;
+    int64_t n_items;
+    TileTables tt;
+    const double* part;
     int Nf;
-    int64_t n_chunks;
-    double scale;
-    double* out;            // [Nf][Nf][2]
-    double* err;            // [Nf][Nf][2]
 };
-hipError_t launch_finalize_grid(const FinalizeGridArgs& a, const int2* tiles, hipStream_t s);
+hipError_t launch_finalize_vec(const FinalizeArgs& a, hipStream_t s);
+hipError_t launch_finalize_grid(const FinalizeArgs& a, hipStream_t s);
+// Mirror (k, l) -> (l, k) for k < l; items are 32 x 32 output blocks.
+hipError_t launch_mirror(const FinalizeArgs& a, hipStream_t s);
 
 hipError_t launch_fill_nan(double* p, int64_t n, hipStream_t s);
+
+// Segment lookup shared by the kernels: the last segment with item0 <= v.
+__device__ __forceinline__ int find_seg(const Seg* segs, int n, int64_t v) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].item0 <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 }  // namespace ps

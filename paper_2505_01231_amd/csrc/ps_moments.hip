@@ -29,39 +29,74 @@
 namespace ps {
 namespace {
 
-// Remap blockIdx.x onto (split, tile) so that each XCD sees a contiguous,
-// split-major range of work items.
-__device__ __forceinline__ bool xcd_work_item(int n_tiles, int n_split, int& split, int& tile) {
-    const int total = n_tiles * n_split;
-    const int per_xcd = (total + 7) >> 3;
-    const int b = blockIdx.x;
-    const int v = (b & 7) * per_xcd + (b >> 3);
-    if (v >= total) return false;
-    split = v / n_tiles;
-    tile = v - split * n_tiles;
+// A block's work item: blockIdx.x is remapped so that each XCD (blocks are
+// dealt round-robin over the 8 XCDs) sees a contiguous range of items; the
+// item is located in the segment table (record x combination) and split into
+// (chunk part, tile).
+struct Item {
+    int split, tile, c0, c1;
+    int k0, l0;
+    int ch[4];
+    double* part;               // partial-sum slot of this (part, tile)
+};
+
+// Coefficients of the item's record: chunk c, frame f, column k of channel ch
+// is at coef[ch * cs + off + (c m + f) K + k].
+struct View {
+    const float2* coef;
+    int64_t cs, off;
+    int K, m;
+};
+
+template <int EDGE, int NCOMP>
+__device__ __forceinline__ bool resolve_item(const BatchArgs& b, Item& it, View& v) {
+    const int64_t per_xcd = (b.n_items + 7) >> 3;
+    const int64_t x = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (x >= b.n_items) return false;
+    const Seg& s = b.segs[find_seg(b.segs, b.n_segs, x)];
+    const int64_t local = x - s.item0;
+    it.split = (int)(local / s.n_tiles);
+    it.tile = (int)(local - (int64_t)it.split * s.n_tiles);
+    const int64_t n = s.n_chunks;
+    it.c0 = (int)(n * it.split / s.split);
+    it.c1 = (int)(n * (it.split + 1) / s.split);
+    if (b.per_chunk) {
+        it.c0 = max(it.c0, b.win_lo);
+        it.c1 = min(it.c1, b.win_hi);
+    }
+    if (EDGE > 0) {
+        const int2 t = b.tt.t[s.tiles][it.tile];
+        it.k0 = t.x * EDGE;
+        it.l0 = t.y * EDGE;
+        it.part = b.part + s.part + ((int64_t)it.split * s.n_tiles + it.tile) * NCOMP * EDGE * EDGE;
+    } else {
+        it.k0 = it.tile * 256;
+        it.l0 = 0;
+        it.part = b.part + s.part + (int64_t)it.split * NCOMP * b.Nf;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) it.ch[j] = s.ch[j];
+    v.coef = b.coef;
+    v.cs = b.coef_chan_stride;
+    v.off = b.per_chunk ? -(int64_t)b.win_lo * b.m * b.K : s.coef;
+    v.K = b.K;
+    v.m = b.m;
     return true;
 }
 
-__device__ __forceinline__ void split_range(int chunk0, int chunk1, int n_split, int split, int& c0,
-                                            int& c1) {
-    const int64_t n = chunk1 - chunk0;
-    c0 = chunk0 + (int)((n * split) / n_split);
-    c1 = chunk0 + (int)((n * (split + 1)) / n_split);
-}
-
 // ------------------------------------------------------------------ S2
-__global__ __launch_bounds__(256) void k_s2(S2Args p) {
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    const int split = blockIdx.y;
+__global__ __launch_bounds__(256) void k_s2(BatchArgs p) {
+    Item it;
+    View v;
+    if (!resolve_item<0, 4>(p, it, v)) return;
+    const int k = it.k0 + threadIdx.x;
     if (k >= p.Nf) return;
-    int c0, c1;
-    split_range(p.chunk0, p.chunk1, p.n_split, split, c0, c1);
-    const CoefView& v = p.v;
-    const float2* A = v.coef + p.a * v.coef_chan_stride;
-    const float2* B = v.coef + p.b * v.coef_chan_stride;
+    const int c0 = it.c0, c1 = it.c1;
+    const float2* A = v.coef + it.ch[0] * v.cs;
+    const float2* B = v.coef + it.ch[1] * v.cs;
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
     for (int c = c0; c < c1; ++c) {
-        const int64_t base = (int64_t)(c - v.coef_chunk0) * v.m * v.K + k;
+        const int64_t base = v.off + (int64_t)c * v.m * v.K + k;
         float re = 0.f, im = 0.f;
         for (int f = 0; f < v.m; ++f) {
             const float2 x = A[base + (int64_t)f * v.K];
@@ -74,7 +109,7 @@ __global__ __launch_bounds__(256) void k_s2(S2Args p) {
         s2 += (double)re * re;
         s3 += (double)im * im;
     }
-    double* o = p.part + (int64_t)split * 4 * p.Nf + k;
+    double* o = it.part + k;
     if (p.accumulate) {
         s0 += o[0];
         s1 += o[p.Nf];
@@ -97,18 +132,16 @@ __global__ __launch_bounds__(256) void k_s2(S2Args p) {
 constexpr int kS3Threads = 256;
 
 template <int FB>
-__global__ __launch_bounds__(kS3Threads, 2) void k_s3(GridArgs p) {
+__global__ __launch_bounds__(kS3Threads, 2) void k_s3(BatchArgs p) {
     __shared__ float2 sA[FB][kTile];
     __shared__ float2 sB[FB][kTile];
     __shared__ float2 sC[FB][2 * kTile];
 
-    int split, tile;
-    if (!xcd_work_item(p.n_tiles, p.n_split, split, tile)) return;
-    int c0, c1;
-    split_range(p.chunk0, p.chunk1, p.n_split, split, c0, c1);
-    const int2 t = p.tiles[tile];
-    const int k0 = t.x * kTile, l0 = t.y * kTile;
-    const CoefView& v = p.v;
+    Item it;
+    View v;
+    if (!resolve_item<kTile, 4>(p, it, v)) return;
+    const int c0 = it.c0, c1 = it.c1;
+    const int k0 = it.k0, l0 = it.l0;
 
     const int tid = threadIdx.x;
     const int ti = tid >> 4, tj = tid & 15;
@@ -122,13 +155,13 @@ __global__ __launch_bounds__(kS3Threads, 2) void k_s3(GridArgs p) {
     bool live = false;
     if (col < kTile) {
         live = k0 + col < p.Nf;
-        src = v.coef + p.ch[0] * v.coef_chan_stride + k0 + col;
+        src = v.coef + it.ch[0] * v.cs + k0 + col;
     } else if (col < 2 * kTile) {
         live = l0 + col - kTile < p.Nf;
-        src = v.coef + p.ch[1] * v.coef_chan_stride + l0 + col - kTile;
+        src = v.coef + it.ch[1] * v.cs + l0 + col - kTile;
     } else if (col < 4 * kTile - 1) {
         live = k0 + l0 + col - 2 * kTile < v.K;
-        src = v.coef + p.ch[2] * v.coef_chan_stride + k0 + l0 + col - 2 * kTile;
+        src = v.coef + it.ch[2] * v.cs + k0 + l0 + col - 2 * kTile;
     }
 
     const int per_chunk = (v.m + FB - 1) / FB;
@@ -138,7 +171,7 @@ __global__ __launch_bounds__(kS3Threads, 2) void k_s3(GridArgs p) {
         const int c = c0 + b / per_chunk;
         const int fb = (b % per_chunk) * FB;
         const int nf = min(FB, v.m - fb);
-        const float2* q = src + ((int64_t)(c - v.coef_chunk0) * v.m + fb) * v.K;
+        const float2* q = src + v.off + ((int64_t)c * v.m + fb) * v.K;
 #pragma unroll
         for (int f = 0; f < FB; ++f)
             pre[f] = (live && f < nf) ? q[(int64_t)f * v.K] : make_float2(0.f, 0.f);
@@ -199,7 +232,7 @@ __global__ __launch_bounds__(kS3Threads, 2) void k_s3(GridArgs p) {
         }
     }
 
-    double* o = p.part + ((int64_t)split * p.n_tiles + tile) * 4 * (kTile * kTile);
+    double* o = it.part;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
 #pragma unroll
@@ -221,18 +254,16 @@ __global__ __launch_bounds__(kS3Threads, 2) void k_s3(GridArgs p) {
 // v = M4 - gamma (p_k p_l + 2(X^2+Y^2+U^2+V^2)), gamma = (m-1)/(m(m+1)).
 constexpr int kS4Threads = 256;
 
-__global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(GridArgs p) {
+__global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(BatchArgs p) {
     __shared__ float2 sA[kFrameBatch][kTile];
     __shared__ float2 sB[kFrameBatch][kTile];
 
-    int split, tile;
-    if (!xcd_work_item(p.n_tiles, p.n_split, split, tile)) return;
-    int c0, c1;
-    split_range(p.chunk0, p.chunk1, p.n_split, split, c0, c1);
-    const int2 t = p.tiles[tile];
-    const int k0 = t.x * kTile, l0 = t.y * kTile;
-    const CoefView& v = p.v;
-    const float2* A = v.coef + p.ch[0] * v.coef_chan_stride;
+    Item it;
+    View v;
+    if (!resolve_item<kTile, 2>(p, it, v)) return;
+    const int c0 = it.c0, c1 = it.c1;
+    const int k0 = it.k0, l0 = it.l0;
+    const float2* A = v.coef + it.ch[0] * v.cs;
 
     const int tid = threadIdx.x;
     const int ti = tid >> 4, tj = tid & 15;
@@ -254,7 +285,7 @@ __global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(GridArgs p) {
 
 #pragma unroll 1
     for (int c = c0; c < c1; ++c) {
-        const int64_t fbase = (int64_t)(c - v.coef_chunk0) * v.m * v.K;
+        const int64_t fbase = v.off + (int64_t)c * v.m * v.K;
         float X[16], Y[16], U[16], V[16], M4[16], pk[4], pl[4];
 #pragma unroll
         for (int q = 0; q < 16; ++q) X[q] = Y[q] = U[q] = V[q] = M4[q] = 0.f;
@@ -314,7 +345,7 @@ __global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(GridArgs p) {
         }
     }
 
-    double* o = p.part + ((int64_t)split * p.n_tiles + tile) * 2 * (kTile * kTile);
+    double* o = it.part;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
 #pragma unroll
@@ -423,18 +454,16 @@ __device__ __forceinline__ void s4_mfma_batch(const unsigned short (*opK)[kOpStr
     }
 }
 
-__global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(GridArgs p) {
+__global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
     __shared__ __attribute__((aligned(16))) unsigned short opK[3 * kTile][kOpStride];
     __shared__ __attribute__((aligned(16))) unsigned short opL[3 * kTile][kOpStride];
     __shared__ float psum[2][2][kTile];
 
-    int split, tile;
-    if (!xcd_work_item(p.n_tiles, p.n_split, split, tile)) return;
-    int c0, c1;
-    split_range(p.chunk0, p.chunk1, p.n_split, split, c0, c1);
-    const int2 t = p.tiles[tile];
-    const int k0 = t.x * kTile, l0 = t.y * kTile;
-    const CoefView& v = p.v;
+    Item it;
+    View v;
+    if (!resolve_item<kTile, 2>(p, it, v)) return;
+    const int c0 = it.c0, c1 = it.c1;
+    const int k0 = it.k0, l0 = it.l0;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
@@ -446,7 +475,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(GridArgs p) {
     const int half = tid & 1;
     const int gcol = (side ? l0 : k0) + col;
     const bool live = gcol < p.Nf;
-    const float2* src = v.coef + p.ch[0] * v.coef_chan_stride + gcol;
+    const float2* src = v.coef + it.ch[0] * v.cs + gcol;
     unsigned short(*op)[kOpStride] = side ? opL : opK;
 
     // Zero the padding slots 60..63 of every row once; they are never written again.
@@ -471,7 +500,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(GridArgs p) {
         const int c = c0 + b / per_chunk;
         const int fb = (b % per_chunk) * kMfmaFrames;
         const int nf = min(kMfmaFrames, v.m - fb);
-        const float2* q = src + ((int64_t)(c - v.coef_chunk0) * v.m + fb) * v.K;
+        const float2* q = src + v.off + ((int64_t)c * v.m + fb) * v.K;
 #pragma unroll
         for (int j = 0; j < kSlots; ++j) {
             const int f = half + 2 * j;
@@ -534,7 +563,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(GridArgs p) {
         }
     }
 
-    double* o = p.part + ((int64_t)split * p.n_tiles + tile) * 2 * (kTile * kTile);
+    double* o = it.part;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
 #pragma unroll
@@ -573,16 +602,14 @@ __device__ __forceinline__ void cmacc(float2& acc, float2 x, float2 y) {       /
     acc.y = fmaf(x.y, y.x, fmaf(-x.x, y.y, acc.y));
 }
 
-__global__ __launch_bounds__(kS4XThreads, 2) void k_s4_cross(GridArgs p) {
+__global__ __launch_bounds__(kS4XThreads, 2) void k_s4_cross(BatchArgs p) {
     __shared__ float2 sv[4][kFrameBatch][kTileX];   // a'_k, b'_k, c'_l, d'_l
 
-    int split, tile;
-    if (!xcd_work_item(p.n_tiles, p.n_split, split, tile)) return;
-    int c0, c1;
-    split_range(p.chunk0, p.chunk1, p.n_split, split, c0, c1);
-    const int2 t = p.tiles[tile];
-    const int k0 = t.x * kTileX, l0 = t.y * kTileX;
-    const CoefView& v = p.v;
+    Item it;
+    View v;
+    if (!resolve_item<kTileX, 4>(p, it, v)) return;
+    const int c0 = it.c0, c1 = it.c1;
+    const int k0 = it.k0, l0 = it.l0;
 
     const int tid = threadIdx.x;
     const int ti = tid >> 4, tj = tid & 15;
@@ -590,7 +617,7 @@ __global__ __launch_bounds__(kS4XThreads, 2) void k_s4_cross(GridArgs p) {
     const int arr = (tid & 127) >> 5, col = tid & 31, half = tid >> 7;
     const int gcol = (arr < 2 ? k0 : l0) + col;
     const bool live = gcol < p.Nf;
-    const float2* src = v.coef + p.ch[arr] * v.coef_chan_stride + gcol;
+    const float2* src = v.coef + it.ch[arr] * v.cs + gcol;
 
     double acc[4][4];
 #pragma unroll
@@ -599,7 +626,7 @@ __global__ __launch_bounds__(kS4XThreads, 2) void k_s4_cross(GridArgs p) {
 
 #pragma unroll 1
     for (int c = c0; c < c1; ++c) {
-        const int64_t fbase = (int64_t)(c - v.coef_chunk0) * v.m * v.K;
+        const int64_t fbase = v.off + (int64_t)c * v.m * v.K;
         float2 sef[4], gac[4], gbd[4], had[4], hbc[4], e[2], f[2];
 #pragma unroll
         for (int q = 0; q < 4; ++q) sef[q] = gac[q] = gbd[q] = had[q] = hbc[q] = make_float2(0.f, 0.f);
@@ -664,7 +691,7 @@ __global__ __launch_bounds__(kS4XThreads, 2) void k_s4_cross(GridArgs p) {
     }
 
     constexpr int TT = kTileX * kTileX;
-    double* o = p.part + ((int64_t)split * p.n_tiles + tile) * 4 * TT;
+    double* o = it.part;
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -687,10 +714,11 @@ int blocks_per_cu(const void* fn, int threads) {
 
 }  // namespace
 
-hipError_t launch_s2(const S2Args& a, hipStream_t s) {
-    if (a.chunk1 <= a.chunk0) return hipSuccess;
-    dim3 grid((a.Nf + 255) / 256, a.n_split);
-    k_s2<<<grid, 256, 0, s>>>(a);
+static dim3 item_grid(const BatchArgs& a) { return dim3((unsigned)(((a.n_items + 7) / 8) * 8)); }
+
+hipError_t launch_s2(const BatchArgs& a, hipStream_t s) {
+    if (a.n_items <= 0) return hipSuccess;
+    k_s2<<<item_grid(a), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -698,38 +726,30 @@ hipError_t launch_s2(const S2Args& a, hipStream_t s) {
 // (the default m = 10 fits one batch), 16 otherwise.
 bool s3_small_batch(int m) { return m <= kFrameBatchSmall || m % kFrameBatchSmall == 0; }
 
-hipError_t launch_s3(const GridArgs& a, hipStream_t s) {
-    if (a.chunk1 <= a.chunk0) return hipSuccess;
-    const int total = a.n_tiles * a.n_split;
-    dim3 grid(((total + 7) / 8) * 8);
-    if (s3_small_batch(a.v.m))
-        k_s3<kFrameBatchSmall><<<grid, kS3Threads, 0, s>>>(a);
+hipError_t launch_s3(const BatchArgs& a, hipStream_t s) {
+    if (a.n_items <= 0) return hipSuccess;
+    if (s3_small_batch(a.m))
+        k_s3<kFrameBatchSmall><<<item_grid(a), kS3Threads, 0, s>>>(a);
     else
-        k_s3<kFrameBatch><<<grid, kS3Threads, 0, s>>>(a);
+        k_s3<kFrameBatch><<<item_grid(a), kS3Threads, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_s4_single(const GridArgs& a, hipStream_t s) {
-    if (a.chunk1 <= a.chunk0) return hipSuccess;
-    const int total = a.n_tiles * a.n_split;
-    dim3 grid(((total + 7) / 8) * 8);
-    k_s4_single<<<grid, kS4Threads, 0, s>>>(a);
+hipError_t launch_s4_single(const BatchArgs& a, hipStream_t s) {
+    if (a.n_items <= 0) return hipSuccess;
+    k_s4_single<<<item_grid(a), kS4Threads, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_s4_mfma(const GridArgs& a, hipStream_t s) {
-    if (a.chunk1 <= a.chunk0) return hipSuccess;
-    const int total = a.n_tiles * a.n_split;
-    dim3 grid(((total + 7) / 8) * 8);
-    k_s4_mfma_bf16<<<grid, kS4MThreads, 0, s>>>(a);
+hipError_t launch_s4_mfma(const BatchArgs& a, hipStream_t s) {
+    if (a.n_items <= 0) return hipSuccess;
+    k_s4_mfma_bf16<<<item_grid(a), kS4MThreads, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t launch_s4_cross(const GridArgs& a, hipStream_t s) {
-    if (a.chunk1 <= a.chunk0) return hipSuccess;
-    const int total = a.n_tiles * a.n_split;
-    dim3 grid(((total + 7) / 8) * 8);
-    k_s4_cross<<<grid, kS4XThreads, 0, s>>>(a);
+hipError_t launch_s4_cross(const BatchArgs& a, hipStream_t s) {
+    if (a.n_items <= 0) return hipSuccess;
+    k_s4_cross<<<item_grid(a), kS4XThreads, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -321,3 +321,43 @@ def test_all_orbits_four_channels_int16(dev):
     gpu, ref = both(z, dev, 512, 64, 10, window="acg", n_channels=4)
     assert [len(gpu["plan"][f"combos{o}"]) for o in (2, 3, 4)] == [10, 40, 76]
     compare(gpu, ref, label="orbits4-int16")
+
+
+# ---------------------------------------------------------------- batching form
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_batched_uneven_records(dev, precision):
+    """Many records of uneven length (including one without a complete chunk and
+    one with a single chunk) and every combination orbit of 2 channels in ONE
+    ps_execute: each stage is one launch over all records and combinations.
+    Each record must equal the oracle and its own single-record execution."""
+    from paper_2505_01231_amd import Plan
+    say("batched uneven records", precision)
+    N, Nf, m = 512, 100, 6
+    rng = np.random.default_rng(31)
+    lengths = [N * m * 3 + 17, N * m - 1, N * m + 100, N * m * 7, int(N * m * 4.5), N * m * 2]
+    recs = []
+    for i, L in enumerate(lengths):
+        s = synth.ar2_chi2(L + 3, seed=40 + i, r=0.9, dtype=np.float32)
+        recs.append(np.stack([s[:-3], (s[3:] ** 2 - 1).astype(np.float32)]))
+    xs = [torch.from_numpy(np.ascontiguousarray(z)).to(dev) for z in recs]
+    with Plan(frame_len=N, n_freq=Nf, m=m, window="hann", n_channels=2, precision=precision) as p:
+        outs = p.execute(xs)
+        torch.cuda.synchronize()
+        singles = [p.execute(x) for x in xs]
+        torch.cuda.synchronize()
+        combos = dict(combos2=p.combos2, combos3=p.combos3, combos4=p.combos4)
+        for i, z in enumerate(recs):
+            o, s1 = outs[i], singles[i]
+            assert o.n_chunks == (lengths[i] // N) // m
+            if o.n_chunks == 0:
+                assert torch.isnan(o.s3).all()
+                continue
+            ref = O.polyspectra(z, N, Nf, m, window_kind="hann", **combos)
+            for key in ("s2", "s3", "s4"):
+                g = torch.view_as_complex(getattr(o, key)).cpu().numpy()
+                g1 = torch.view_as_complex(getattr(s1, key)).cpu().numpy()
+                assert rel_err(g, ref[key]) <= TOL, (i, key, rel_err(g, ref[key]))
+                assert rel_err(g, g1) <= 1e-12, (i, key)
+                if o.n_chunks > 1:
+                    e = getattr(o, key + "_err").cpu().numpy()
+                    assert rel_err(e, ref[key + "_err"]) <= TOL, (i, key + "_err")
