@@ -172,6 +172,45 @@ ps_status ps_workspace_size(ps_plan_t plan, const ps_record* recs, int32_t n_rec
 ps_status ps_execute(ps_plan_t plan, const ps_record* recs, int32_t n_rec, void* d_ws,
                      size_t ws_bytes, const ps_output* outs, ps_stream_t stream);
 
+/* Graph form of ps_execute for repeated runs over the same buffers: the whole
+ * launch sequence (one launch per stage over every record and combination) is
+ * captured once into a HIP graph, with its work tables built and copied
+ * synchronously into device memory owned by the graph; ps_graph_launch then
+ * replays it with a single hipGraphLaunch on any stream.  The records' device
+ * data (whose contents may change between launches), the workspace and the
+ * outputs given here must stay allocated while the graph exists, and the
+ * workspace must not be used by other calls while a launch is in flight.
+ * Contains no memset nodes (clears are kernels).  ps_graph_create synchronises
+ * with the device; errors as for ps_execute. */
+typedef struct ps_graph_s* ps_graph_t;
+ps_status ps_graph_create(ps_plan_t plan, const ps_record* recs, int32_t n_rec, void* d_ws, size_t ws_bytes,
+                          const ps_output* outs, ps_graph_t* out);
+ps_status ps_graph_launch(ps_graph_t graph, ps_stream_t stream);
+ps_status ps_graph_destroy(ps_graph_t graph);
+
+/* Streaming form (quasi-polyspectra of non-stationary signals, Section 8):
+ * time-resolved spectra of consecutive windows of a host-resident stream.
+ * ps_streamer_create allocates, once, `depth` device staging slots of
+ * window_samples samples per channel, one workspace and a copy stream
+ * (default priority).  ps_streamer_push takes one window from pinned host
+ * memory (channels contiguous, channel c at c * window_samples): it enqueues
+ * the host-to-device copy into the next slot on the copy stream once that
+ * slot's previous computation is done, makes `compute` wait for the copy,
+ * enqueues the estimator for the window on `compute` writing to `outs` (as in
+ * ps_execute), and returns the slot index.  The copy of the next window thus
+ * overlaps the computation of the current one.  The host buffer must stay
+ * untouched until the window's copy has completed, and `outs` must not be read
+ * before its computation has (ps_streamer_wait on the slot, or synchronising
+ * `compute`).  Windows must be pushed from one host thread, all on the same
+ * `compute` stream. */
+typedef struct ps_streamer_s* ps_streamer_t;
+ps_status ps_streamer_create(ps_plan_t plan, int64_t window_samples, int32_t dtype, int32_t depth,
+                             ps_streamer_t* out);
+ps_status ps_streamer_push(ps_streamer_t s, const void* h_pinned, const ps_output* outs, ps_stream_t compute,
+                           int32_t* slot);
+ps_status ps_streamer_wait(ps_streamer_t s, int32_t slot);
+ps_status ps_streamer_destroy(ps_streamer_t s);
+
 /* The first stage alone (Section 3, eq. a_k without the dt factor): for every
  * frame f < Np*m of every channel, d_coef[c][f][k] = sum_i g_i z_{fN+i}
  * exp(+2 pi j i k/N), k < n_coef, as interleaved FP32 complex.  d_coef must hold

@@ -22,7 +22,9 @@ PS_FLAG_EMPTY, PS_FLAG_NO_ERRBAR = 1, 2
 EXPORTED = (
     "ps_plan_create", "ps_plan_destroy", "ps_plan_query", "ps_record_info", "ps_workspace_size",
     "ps_execute", "ps_coefficients", "ps_status_string", "ps_last_error", "ps_abi_version",
-    "ps_enumerate_combos", "ps_profile_enable", "ps_profile_read",
+    "ps_enumerate_combos", "ps_profile_enable", "ps_profile_read", "ps_graph_create",
+    "ps_graph_launch", "ps_graph_destroy", "ps_streamer_create", "ps_streamer_push",
+    "ps_streamer_wait", "ps_streamer_destroy",
 )
 
 
@@ -86,9 +88,18 @@ def load() -> C.CDLL:
     lib.ps_enumerate_combos.argtypes = [i32, i32, C.POINTER(C.c_int8), C.POINTER(i32)]
     lib.ps_profile_enable.argtypes = [vp, i32]
     lib.ps_profile_read.argtypes = [vp, C.POINTER(C.c_double), i32]
+    lib.ps_graph_create.argtypes = [vp, C.POINTER(ps_record), i32, vp, sz, C.POINTER(ps_output), C.POINTER(vp)]
+    lib.ps_graph_launch.argtypes = [vp, vp]
+    lib.ps_graph_destroy.argtypes = [vp]
+    lib.ps_streamer_create.argtypes = [vp, i64, i32, i32, C.POINTER(vp)]
+    lib.ps_streamer_push.argtypes = [vp, vp, C.POINTER(ps_output), vp, C.POINTER(i32)]
+    lib.ps_streamer_wait.argtypes = [vp, i32]
+    lib.ps_streamer_destroy.argtypes = [vp]
     for name in ("ps_plan_create", "ps_plan_destroy", "ps_plan_query", "ps_record_info",
                  "ps_workspace_size", "ps_execute", "ps_coefficients", "ps_enumerate_combos",
-                 "ps_profile_enable", "ps_profile_read"):
+                 "ps_profile_enable", "ps_profile_read", "ps_graph_create", "ps_graph_launch",
+                 "ps_graph_destroy", "ps_streamer_create", "ps_streamer_push", "ps_streamer_wait",
+                 "ps_streamer_destroy"):
         getattr(lib, name).restype = C.c_int
     lib.ps_status_string.argtypes = [C.c_int]
     lib.ps_status_string.restype = C.c_char_p

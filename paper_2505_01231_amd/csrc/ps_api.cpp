@@ -694,10 +694,10 @@ ps_status upload_tables(ps_plan_t p, const Batch& B, char* d_tab, hipStream_t st
     return PS_OK;
 }
 
-ps::BatchArgs batch_args(const ps_plan_s* p, const Batch& B, const SegTable& t, char* ws, int per_chunk,
-                         int win_lo, int win_hi, int accumulate) {
+ps::BatchArgs batch_args(const ps_plan_s* p, const Batch& B, const SegTable& t, char* ws, const char* tab,
+                         int per_chunk, int win_lo, int win_hi, int accumulate) {
     ps::BatchArgs a{};
-    a.segs = reinterpret_cast<const ps::Seg*>(ws + B.off_tab + t.dev_off);
+    a.segs = reinterpret_cast<const ps::Seg*>(tab + t.dev_off);
     a.n_segs = (int)t.v.size();
     a.n_items = t.n_items;
     a.tt = p->tables();
@@ -715,9 +715,9 @@ ps::BatchArgs batch_args(const ps_plan_s* p, const Batch& B, const SegTable& t, 
     return a;
 }
 
-ps::FinalizeArgs fin_args(const ps_plan_s* p, const Batch& B, const SegTable& t, char* ws) {
+ps::FinalizeArgs fin_args(const ps_plan_s* p, const Batch& B, const SegTable& t, char* ws, const char* tab) {
     ps::FinalizeArgs f{};
-    f.segs = reinterpret_cast<const ps::Seg*>(ws + B.off_tab + t.dev_off);
+    f.segs = reinterpret_cast<const ps::Seg*>(tab + t.dev_off);
     f.n_segs = (int)t.v.size();
     f.n_items = t.n_items;
     f.tt = p->tables();
@@ -727,19 +727,19 @@ ps::FinalizeArgs fin_args(const ps_plan_s* p, const Batch& B, const SegTable& t,
 }
 
 // The moment stages of one group (one launch each).
-ps_status launch_moments(ps_plan_t p, const Batch& B, const Group& G, char* ws, int per_chunk, int win_lo,
-                         int win_hi, int accumulate, hipStream_t st) {
+ps_status launch_moments(ps_plan_t p, const Batch& B, const Group& G, char* ws, const char* tab, int per_chunk,
+                         int win_lo, int win_hi, int accumulate, hipStream_t st) {
     if (G.s2.n_items) {
         StageTimer t(p, st, 2);
-        PS_HIP(ps::launch_s2(batch_args(p, B, G.s2, ws, per_chunk, win_lo, win_hi, accumulate), st));
+        PS_HIP(ps::launch_s2(batch_args(p, B, G.s2, ws, tab, per_chunk, win_lo, win_hi, accumulate), st));
     }
     if (G.s3.n_items) {
         StageTimer t(p, st, 3);
-        PS_HIP(ps::launch_s3(batch_args(p, B, G.s3, ws, per_chunk, win_lo, win_hi, accumulate), st));
+        PS_HIP(ps::launch_s3(batch_args(p, B, G.s3, ws, tab, per_chunk, win_lo, win_hi, accumulate), st));
     }
     if (G.s4s.n_items) {
         StageTimer t(p, st, 4);
-        const ps::BatchArgs a = batch_args(p, B, G.s4s, ws, per_chunk, win_lo, win_hi, accumulate);
+        const ps::BatchArgs a = batch_args(p, B, G.s4s, ws, tab, per_chunk, win_lo, win_hi, accumulate);
         if (p->precision == PS_PREC_FP32) {
             PS_HIP(ps::launch_s4_single(a, st));
         } else {
@@ -748,29 +748,29 @@ ps_status launch_moments(ps_plan_t p, const Batch& B, const Group& G, char* ws, 
     }
     if (G.s4x.n_items) {
         StageTimer t(p, st, 4);
-        PS_HIP(ps::launch_s4_cross(batch_args(p, B, G.s4x, ws, per_chunk, win_lo, win_hi, accumulate), st));
+        PS_HIP(ps::launch_s4_cross(batch_args(p, B, G.s4x, ws, tab, per_chunk, win_lo, win_hi, accumulate), st));
     }
     return PS_OK;
 }
 
-ps_status launch_finalize(ps_plan_t p, const Batch& B, const Group& G, char* ws, hipStream_t st) {
+ps_status launch_finalize(ps_plan_t p, const Batch& B, const Group& G, char* ws, const char* tab, hipStream_t st) {
     StageTimer t(p, st, 5);
-    if (G.f2.n_items) PS_HIP(ps::launch_finalize_vec(fin_args(p, B, G.f2, ws), st));
-    if (G.f3.n_items) PS_HIP(ps::launch_finalize_grid(fin_args(p, B, G.f3, ws), st));
-    if (G.m3.n_items) PS_HIP(ps::launch_mirror(fin_args(p, B, G.m3, ws), st));
-    if (G.f4.n_items) PS_HIP(ps::launch_finalize_grid(fin_args(p, B, G.f4, ws), st));
-    if (G.m4.n_items) PS_HIP(ps::launch_mirror(fin_args(p, B, G.m4, ws), st));
+    if (G.f2.n_items) PS_HIP(ps::launch_finalize_vec(fin_args(p, B, G.f2, ws, tab), st));
+    if (G.f3.n_items) PS_HIP(ps::launch_finalize_grid(fin_args(p, B, G.f3, ws, tab), st));
+    if (G.m3.n_items) PS_HIP(ps::launch_mirror(fin_args(p, B, G.m3, ws, tab), st));
+    if (G.f4.n_items) PS_HIP(ps::launch_finalize_grid(fin_args(p, B, G.f4, ws, tab), st));
+    if (G.m4.n_items) PS_HIP(ps::launch_mirror(fin_args(p, B, G.m4, ws, tab), st));
     return PS_OK;
 }
 
 }  // namespace
 
-ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_ws, size_t ws_bytes,
-                     const ps_output* outs, ps_stream_t stream) {
+namespace {
+
+ps_status validate_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_ws,
+                           const ps_output* outs) {
     if (!p || n_rec < 0 || (n_rec > 0 && (!recs || !outs))) return fail(PS_E_INVALID_ARG, "bad argument");
     if (!aligned(d_ws, 256)) return fail(PS_E_INVALID_ARG, "workspace must be 256-byte aligned");
-    hipStream_t st = (hipStream_t)stream;
-    // Validate everything before enqueueing anything.
     for (int r = 0; r < n_rec; ++r) {
         ps_status s = check_record(p, &recs[r]);
         if (s != PS_OK) return s;
@@ -779,11 +779,12 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
         for (const double* q : ptrs)
             if (q && !aligned(q, 8)) return fail(PS_E_INVALID_ARG, "output pointer misaligned");
     }
-    if (n_rec == 0) return PS_OK;
-    Batch B;
-    build_batch(p, recs, n_rec, outs, B);
-    if (!d_ws || ws_bytes < B.total) return fail(PS_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
+    return PS_OK;
+}
 
+// Every launch of one execution, given device tables at `tab`.
+ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_t n_rec, const ps_output* outs,
+                      char* ws, const char* tab, hipStream_t st) {
     const int Nf = p->Nf, m = p->m;
     const int64_t nf2 = (int64_t)Nf * Nf;
     for (int r = 0; r < n_rec; ++r) {
@@ -797,10 +798,6 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
         PS_HIP(ps::launch_fill_nan(o.d_s4_err, 2 * (int64_t)p->n4() * nf2, st));
     }
     if (B.chunks_tot == 0) return PS_OK;
-
-    char* ws = static_cast<char*>(d_ws);
-    ps_status s = upload_tables(p, B, ws + B.off_tab, st);
-    if (s != PS_OK) return s;
     float2* coef = reinterpret_cast<float2*>(ws + B.off_coef);
     const int64_t coef_cs = B.coef_rows * p->K;
 
@@ -818,9 +815,10 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
     ca.K = p->K;
     ca.m = m;
     ca.n_channels = p->C;
+    ps_status s = PS_OK;
 
     if (p->schedule != PS_SCHED_PER_CHUNK) {
-        fa.recs = reinterpret_cast<const ps::RecDesc*>(ws + B.off_tab);
+        fa.recs = reinterpret_cast<const ps::RecDesc*>(tab);
         fa.n_recs = n_rec;
         fa.g_lo = 0;
         fa.g_hi = B.F_tot;
@@ -834,9 +832,9 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
             StageTimer t(p, st, 1);
             PS_HIP(ps::launch_centre(ca, st));
         }
-        s = launch_moments(p, B, B.groups[0], ws, 0, 0, 0, 0, st);
+        s = launch_moments(p, B, B.groups[0], ws, tab, 0, 0, 0, 0, st);
         if (s != PS_OK) return s;
-        return launch_finalize(p, B, B.groups[0], ws, st);
+        return launch_finalize(p, B, B.groups[0], ws, tab, st);
     }
 
     // Per-chunk schedule: one short-time estimate per launch set, record by record.
@@ -858,12 +856,213 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
                 StageTimer t(p, st, 1);
                 PS_HIP(ps::launch_centre(ca, st));
             }
-            s = launch_moments(p, B, G, ws, 1, (int)c, (int)c + 1, c > 0 ? 1 : 0, st);
+            s = launch_moments(p, B, G, ws, tab, 1, (int)c, (int)c + 1, c > 0 ? 1 : 0, st);
             if (s != PS_OK) return s;
         }
-        s = launch_finalize(p, B, G, ws, st);
+        s = launch_finalize(p, B, G, ws, tab, st);
         if (s != PS_OK) return s;
     }
+    return PS_OK;
+}
+
+}  // namespace
+
+ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_ws, size_t ws_bytes,
+                     const ps_output* outs, ps_stream_t stream) {
+    ps_status s = validate_execute(p, recs, n_rec, d_ws, outs);
+    if (s != PS_OK || n_rec == 0) return s;
+    hipStream_t st = (hipStream_t)stream;
+    Batch B;
+    build_batch(p, recs, n_rec, outs, B);
+    if (!d_ws || ws_bytes < B.total) return fail(PS_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
+    char* ws = static_cast<char*>(d_ws);
+    if (B.chunks_tot > 0) {
+        s = upload_tables(p, B, ws + B.off_tab, st);
+        if (s != PS_OK) return s;
+    }
+    return enqueue_all(p, B, recs, n_rec, outs, ws, ws + B.off_tab, st);
+}
+
+// ------------------------------------------------------------------ graphs
+struct ps_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* d_tab = nullptr;      // work tables owned by the graph
+};
+
+ps_status ps_graph_destroy(ps_graph_t g) {
+    if (!g) return PS_OK;
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    if (g->d_tab) hipFree(g->d_tab);
+    delete g;
+    return PS_OK;
+}
+
+ps_status ps_graph_create(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_ws, size_t ws_bytes,
+                          const ps_output* outs, ps_graph_t* out) {
+    if (!out) return fail(PS_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    ps_status s = validate_execute(p, recs, n_rec, d_ws, outs);
+    if (s != PS_OK) return s;
+    Batch B;
+    build_batch(p, recs, n_rec, outs, B);
+    if (!d_ws || ws_bytes < B.total) return fail(PS_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, B.total);
+    auto* g = new ps_graph_s();
+    // Work tables: built once on the host, copied synchronously into device
+    // memory that the graph owns (nothing is staged at replay time).
+    std::vector<char> h(B.tab_bytes);
+    std::memcpy(h.data(), B.rd.data(), sizeof(ps::RecDesc) * B.rd.size());
+    for (const Group& G : B.groups)
+        for (const SegTable* t : G.all)
+            if (!t->v.empty()) std::memcpy(h.data() + t->dev_off, t->v.data(), sizeof(ps::Seg) * t->v.size());
+    hipError_t e = hipMalloc(&g->d_tab, std::max<size_t>(B.tab_bytes, 256));
+    if (e == hipSuccess) e = hipMemcpy(g->d_tab, h.data(), B.tab_bytes, hipMemcpyHostToDevice);
+    hipStream_t cs = nullptr;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        if (cs) hipStreamDestroy(cs);
+        ps_graph_destroy(g);
+        return fail(PS_E_HIP, "graph setup failed: %s", hipGetErrorString(e));
+    }
+    const bool prof = p->prof;
+    p->prof = false;       // no timing events inside a graph
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        s = enqueue_all(p, B, recs, n_rec, outs, static_cast<char*>(d_ws), static_cast<const char*>(g->d_tab), cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        g->graph = graph;
+        if (s == PS_OK && e2 != hipSuccess) s = fail(PS_E_HIP, "stream capture failed: %s", hipGetErrorString(e2));
+    } else {
+        s = fail(PS_E_HIP, "stream capture failed: %s", hipGetErrorString(e));
+    }
+    p->prof = prof;
+    hipStreamDestroy(cs);
+    if (s == PS_OK) {
+        e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) s = fail(PS_E_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    if (s != PS_OK) {
+        ps_graph_destroy(g);
+        return s;
+    }
+    *out = g;
+    return PS_OK;
+}
+
+ps_status ps_graph_launch(ps_graph_t g, ps_stream_t stream) {
+    if (!g || !g->exec) return fail(PS_E_INVALID_ARG, "graph is NULL");
+    PS_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return PS_OK;
+}
+
+// ------------------------------------------------------------------ streaming
+struct ps_streamer_s {
+    ps_plan_t plan = nullptr;
+    int64_t window = 0;
+    int dtype = 0, depth = 0;
+    size_t esz = 0;
+    hipStream_t copy = nullptr;
+    std::vector<void*> stage;           // device staging slots
+    std::vector<hipEvent_t> copied, done;
+    std::vector<int> used;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    int next = 0;
+    std::vector<void*> allocs;
+};
+
+ps_status ps_streamer_destroy(ps_streamer_t s) {
+    if (!s) return PS_OK;
+    for (hipEvent_t e : s->done)
+        if (e) hipEventSynchronize(e);
+    if (s->copy) hipStreamSynchronize(s->copy);
+    for (hipEvent_t e : s->copied)
+        if (e) hipEventDestroy(e);
+    for (hipEvent_t e : s->done)
+        if (e) hipEventDestroy(e);
+    for (void* a : s->allocs) hipFree(a);
+    if (s->copy) hipStreamDestroy(s->copy);
+    delete s;
+    return PS_OK;
+}
+
+ps_status ps_streamer_create(ps_plan_t p, int64_t window_samples, int32_t dtype, int32_t depth,
+                             ps_streamer_t* out) {
+    if (!out) return fail(PS_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!p || window_samples <= 0 || depth < 1 || depth > 16 || dtype < PS_F32 || dtype > PS_I16)
+        return fail(PS_E_INVALID_ARG, "bad argument");
+    auto* s = new ps_streamer_s();
+    s->plan = p;
+    s->window = window_samples;
+    s->dtype = dtype;
+    s->depth = depth;
+    s->esz = dtype == PS_F32 ? 4 : (dtype == PS_F64 ? 8 : 2);
+    hipError_t e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
+    auto alloc = [&](size_t bytes) -> void* {
+        void* q = nullptr;
+        if (e == hipSuccess && bytes > 0) {
+            e = hipMalloc(&q, bytes);
+            if (e == hipSuccess) s->allocs.push_back(q);
+        }
+        return q;
+    };
+    ps_record r{};
+    r.d_data = nullptr;
+    r.n_samples = window_samples;
+    r.channel_stride = window_samples;
+    r.dtype = dtype;
+    Batch B;
+    build_batch(p, &r, 1, nullptr, B);
+    s->ws_bytes = B.total;
+    s->ws = alloc(B.total);
+    for (int i = 0; i < depth && e == hipSuccess; ++i) {
+        s->stage.push_back(alloc(s->esz * window_samples * p->C));
+        hipEvent_t a = nullptr, b = nullptr;
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
+        s->copied.push_back(a);
+        s->done.push_back(b);
+        s->used.push_back(0);
+    }
+    if (e != hipSuccess) {
+        ps_streamer_destroy(s);
+        return fail(PS_E_HIP, "streamer setup failed: %s", hipGetErrorString(e));
+    }
+    *out = s;
+    return PS_OK;
+}
+
+ps_status ps_streamer_push(ps_streamer_t s, const void* h_pinned, const ps_output* outs, ps_stream_t compute,
+                           int32_t* slot) {
+    if (!s || !h_pinned || !outs) return fail(PS_E_INVALID_ARG, "bad argument");
+    const int i = s->next;
+    s->next = (s->next + 1) % s->depth;
+    hipStream_t cs = (hipStream_t)compute;
+    // The slot's staging buffer may still be read by its previous computation.
+    if (s->used[i]) PS_HIP(hipStreamWaitEvent(s->copy, s->done[i], 0));
+    PS_HIP(hipMemcpyAsync(s->stage[i], h_pinned, s->esz * s->window * s->plan->C, hipMemcpyHostToDevice,
+                          s->copy));
+    PS_HIP(hipEventRecord(s->copied[i], s->copy));
+    PS_HIP(hipStreamWaitEvent(cs, s->copied[i], 0));
+    ps_record r{};
+    r.d_data = s->stage[i];
+    r.n_samples = s->window;
+    r.channel_stride = s->window;
+    r.dtype = s->dtype;
+    ps_status st = ps_execute(s->plan, &r, 1, s->ws, s->ws_bytes, outs, compute);
+    if (st != PS_OK) return st;
+    PS_HIP(hipEventRecord(s->done[i], cs));
+    s->used[i] = 1;
+    if (slot) *slot = i;
+    return PS_OK;
+}
+
+ps_status ps_streamer_wait(ps_streamer_t s, int32_t slot) {
+    if (!s || slot < 0 || slot >= s->depth) return fail(PS_E_INVALID_ARG, "bad argument");
+    if (s->used[slot]) PS_HIP(hipEventSynchronize(s->done[slot]));
     return PS_OK;
 }
 

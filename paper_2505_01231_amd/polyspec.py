@@ -195,6 +195,30 @@ class Plan:
         self._last_workspace = workspace
         return outputs[0] if single else outputs
 
+    def graph(self, xs, workspace: torch.Tensor | None = None, outputs=None) -> "Graph":
+        """Capture the execution over these tensors/buffers as a HIP graph
+        (ps_graph_create); replay with Graph.launch()."""
+        single = isinstance(xs, torch.Tensor)
+        if single:
+            xs = [xs]
+        device = xs[0].device
+        recs = (L.ps_record * len(xs))(*[self.record(x) for x in xs])
+        need = C.c_size_t()
+        L.check(self._lib.ps_workspace_size(self._handle, recs, len(xs), C.byref(need)), "ps_workspace_size")
+        if workspace is None or workspace.numel() < need.value:
+            workspace = torch.empty(need.value, dtype=torch.uint8, device=device)
+        if outputs is None:
+            outputs = [self.allocate_outputs(device) for _ in xs]
+        outs = (L.ps_output * len(xs))()
+        for i, o in enumerate(outputs):
+            o.n_chunks, o.flags = self.record_info(recs[i].n_samples)
+            outs[i] = L.ps_output(self._ptr(o.s2), self._ptr(o.s2_err), self._ptr(o.s3),
+                                  self._ptr(o.s3_err), self._ptr(o.s4), self._ptr(o.s4_err))
+        h = C.c_void_p()
+        L.check(self._lib.ps_graph_create(self._handle, recs, len(xs), workspace.data_ptr(), workspace.numel(),
+                                          outs, C.byref(h)), "ps_graph_create")
+        return Graph(self, h, list(xs), workspace, outputs[0] if single else outputs)
+
     STAGES = ("fft", "mean", "s2", "s3", "s4", "finalize")
 
     def profile(self, on: bool = True):
@@ -217,3 +241,82 @@ class Plan:
         L.check(self._lib.ps_coefficients(self._handle, C.byref(rec), out.data_ptr(),
                                           C.c_void_p(st.cuda_stream)), "ps_coefficients")
         return torch.view_as_complex(out)
+
+
+class Graph:
+    """A captured execution (ps_graph_t).  Keeps its inputs, workspace and
+    outputs alive; ``outputs`` are refreshed by every launch."""
+
+    def __init__(self, plan: Plan, handle, inputs, workspace, outputs):
+        self._plan = plan
+        self._handle = handle
+        self.inputs = inputs
+        self.workspace = workspace
+        self.outputs = outputs
+
+    def launch(self, stream=None):
+        dev = self.workspace.device
+        st = torch.cuda.current_stream(dev) if stream is None else stream
+        L.check(self._plan._lib.ps_graph_launch(self._handle, C.c_void_p(st.cuda_stream)), "ps_graph_launch")
+        return self.outputs
+
+    def close(self):
+        if self._handle is not None:
+            self._plan._lib.ps_graph_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Streamer:
+    """Time-resolved spectra of consecutive windows of a host stream
+    (ps_streamer_*): one push per window; the host-to-device copy of the next
+    window overlaps the estimator on the current one."""
+
+    def __init__(self, plan: Plan, window_samples: int, dtype=torch.float32, depth: int = 3):
+        self._plan = plan
+        self.window = window_samples
+        self.dtype = dtype
+        self.depth = depth
+        h = C.c_void_p()
+        L.check(plan._lib.ps_streamer_create(plan._handle, window_samples, _DTYPES[dtype], depth, C.byref(h)),
+                "ps_streamer_create")
+        self._handle = h
+        self.n_chunks, self.flags = plan.record_info(window_samples)
+
+    def push(self, host_window: torch.Tensor, outputs: Spectra, stream=None) -> int:
+        """Enqueue one window (pinned host tensor [C, window] or [window])
+        writing into ``outputs``; returns the slot to wait on."""
+        if host_window.is_cuda or not host_window.is_pinned():
+            raise ValueError("windows must be pinned host tensors")
+        if host_window.dtype != self.dtype or host_window.numel() != self.window * self._plan.n_channels:
+            raise ValueError("window shape or dtype does not match the streamer")
+        if not host_window.is_contiguous():
+            raise ValueError("window must be contiguous")
+        outputs.n_chunks, outputs.flags = self.n_chunks, self.flags
+        p = Plan._ptr
+        out = L.ps_output(p(outputs.s2), p(outputs.s2_err), p(outputs.s3), p(outputs.s3_err), p(outputs.s4),
+                          p(outputs.s4_err))
+        st = torch.cuda.current_stream() if stream is None else stream
+        slot = C.c_int32()
+        L.check(self._plan._lib.ps_streamer_push(self._handle, host_window.data_ptr(), C.byref(out),
+                                                 C.c_void_p(st.cuda_stream), C.byref(slot)), "ps_streamer_push")
+        return slot.value
+
+    def wait(self, slot: int):
+        L.check(self._plan._lib.ps_streamer_wait(self._handle, slot), "ps_streamer_wait")
+
+    def close(self):
+        if self._handle is not None:
+            self._plan._lib.ps_streamer_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

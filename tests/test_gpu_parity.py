@@ -361,3 +361,82 @@ def test_batched_uneven_records(dev, precision):
                 if o.n_chunks > 1:
                     e = getattr(o, key + "_err").cpu().numpy()
                     assert rel_err(e, ref[key + "_err"]) <= TOL, (i, key + "_err")
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_graph_replays_match_eager(dev, precision):
+    """ps_graph_create / ps_graph_launch: the captured launch sequence replayed
+    several times, with eager work and synchronisations in between and with the
+    input contents changed between replays; every replay equals the eager run."""
+    from paper_2505_01231_amd import Plan
+    say("graph replays", precision)
+    N, Nf, m = 1024, 160, 10
+    zs = [synth.ar2_chi2(N * m * n + 33, seed=60 + n, dtype=np.float32) for n in (3, 1, 5)]
+    xs = [torch.from_numpy(z).to(dev) for z in zs]
+    with Plan(frame_len=N, n_freq=Nf, m=m, window="acg", precision=precision) as p:
+        g = p.graph(xs)
+        for rep in range(4):
+            if rep == 2:      # new data in the same buffers
+                for x, z in zip(xs, zs):
+                    x.copy_(torch.from_numpy((1.5 * z[::-1]).copy()))
+            outs = g.launch()
+            torch.cuda.synchronize()
+            eager = p.execute(xs)          # eager work between replays
+            junk = torch.randn(1 << 20, device=dev).sum()
+            torch.cuda.synchronize()
+            for o, e in zip(outs, eager):
+                for key in ("s2", "s3", "s4", "s2_err", "s3_err", "s4_err"):
+                    a, b = getattr(o, key).cpu().numpy(), getattr(e, key).cpu().numpy()
+                    assert np.array_equal(a, b, equal_nan=True), (rep, key)
+            del junk
+        g.close()
+
+
+# ---------------------------------------------------------------- streaming (quasi-polyspectra)
+def test_streamer_time_resolved_windows(dev):
+    """Consecutive windows of a host stream whose chi-square drive amplitude
+    ramps from 0.5 to 2.0 (a non-stationary signal, Section 8), pushed from
+    pinned memory through ps_streamer (copies overlap computation).  Every
+    window equals ps_execute on the same samples bit for bit, two windows
+    match the oracle, and the time-resolved spectra follow S_n ~ s^n."""
+    from paper_2505_01231_amd import Plan, Streamer
+    say("streamer windows")
+    N, Nf, m, W, nwin = 2048, 128, 10, 1 << 19, 8
+    total = W * nwin
+    z = synth.modulated_ar2(total, seed=5, total=total, r=0.9)
+    s_of_t = 0.5 + 1.5 * np.arange(total) / (total - 1)
+    with Plan(frame_len=N, n_freq=Nf, m=m, window="acg", precision="bf16x3") as p:
+        st = Streamer(p, W, dtype=torch.float32, depth=3)
+        sets = [p.allocate_outputs(dev) for _ in range(3)]
+        host = [torch.empty(W, dtype=torch.float32, pin_memory=True) for _ in range(3)]
+        results = []
+        slots = []
+        for w in range(nwin):
+            k = w % 3
+            if w >= 3:
+                st.wait(slots[w - 3])            # slot, host buffer and output set free again
+                results[w - 3] = {key: getattr(sets[k], key).cpu().numpy() for key in ("s2", "s3", "s4")}
+            host[k].copy_(torch.from_numpy(z[w * W:(w + 1) * W]))
+            slots.append(st.push(host[k], sets[k]))
+            results.append(None)
+        for w in range(max(0, nwin - 3), nwin):
+            st.wait(slots[w])
+            results[w] = {key: getattr(sets[w % 3], key).cpu().numpy() for key in ("s2", "s3", "s4")}
+        st.close()
+        for w in range(nwin):
+            ref = p.execute(torch.from_numpy(z[w * W:(w + 1) * W].copy()).to(dev))
+            torch.cuda.synchronize()
+            for key in ("s2", "s3", "s4"):
+                assert np.array_equal(results[w][key], getattr(ref, key).cpu().numpy()), (w, key)
+    for w in (0, nwin - 1):
+        ref = O.polyspectra(z[w * W:(w + 1) * W], N, Nf, m, window_kind="acg")
+        for key in ("s2", "s3", "s4"):
+            got = results[w][key][..., 0] + 1j * results[w][key][..., 1]
+            assert rel_err(got, ref[key]) <= TOL, (w, key)
+    # time-resolved scaling with the window's drive amplitude
+    s_w = np.array([s_of_t[w * W:(w + 1) * W].mean() for w in range(nwin)])
+    for n, key, tol in ((2, "s2", 0.15), (3, "s3", 0.4), (4, "s4", 0.6)):
+        amp = np.array([np.max(np.abs(results[w][key][0, ..., 0])) for w in range(nwin)])
+        slope = np.polyfit(np.log(s_w), np.log(amp), 1)[0]
+        say(f"  log-slope {key}: {slope:.2f} (expected {n})")
+        assert abs(slope - n) < tol, (key, slope)
