@@ -71,6 +71,100 @@ def cpu_baseline(z, seconds_target=15.0):
     }
 
 
+def run_batching(torch, dev, precision):
+    """Batching form: every record of a frame length in one ps_execute (each
+    stage one launch over records x combinations), grouped so that the FP64
+    outputs of a group stay under ~16 GB."""
+    import numpy as np
+
+    from paper_2505_01231_amd import Plan, synth
+    lengths = synth.uneven_record_lengths(24, seed=4)
+    frame_lens = (1024, 2048, 4096)
+    total_samples, total_time, groups, launches = 0, 0.0, 0, 0
+    per_n = {}
+    for j, n in enumerate(frame_lens):
+        recs = []
+        for i in range(j, 24, 3):
+            z, clipped = synth.mixed_channels(int(lengths[i]), seed=100 + i)
+            recs.append(torch.from_numpy(z).to(dev))
+        with Plan(frame_len=n, n_freq=n // 4, m=10, window="acg", n_channels=4, precision=precision) as p:
+            nf = p.n_freq
+            out_bytes = (len(p.combos2) * nf + (len(p.combos3) + len(p.combos4)) * nf * nf) * 2 * 16
+            per_group = max(1, int(16e9 // out_bytes))
+            grp = [recs[i:i + per_group] for i in range(0, len(recs), per_group)]
+            ws = torch.empty(max(p.workspace_bytes(g) for g in grp), dtype=torch.uint8, device=dev)
+            outs = [p.allocate_outputs(dev) for _ in range(per_group)]
+            p.execute(grp[0], workspace=ws, outputs=outs[:len(grp[0])])      # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for g in grp:
+                p.execute(g, workspace=ws, outputs=outs[:len(g)])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ns = sum(int(x.shape[1]) * 4 for x in recs)
+            per_n[str(n)] = {"records": len(recs), "groups": len(grp), "channel_samples": ns,
+                             "seconds": dt, "channel_samples_per_s": ns / dt}
+            total_samples += ns
+            total_time += dt
+            groups += len(grp)
+            del ws, outs
+        log(f"batching N={n}: {per_n[str(n)]['channel_samples_per_s']:.3e} channel-samples/s")
+    return {"records": 24, "channels": 4, "combinations": [10, 40, 76], "executes": groups,
+            "channel_samples_per_s": total_samples / total_time, "per_frame_length": per_n,
+            "note": "each ps_execute runs every stage as one launch over its records x combinations"}
+
+
+def run_streaming(torch, dev, precision, n_windows=64, pool=8):
+    """Streaming form: consecutive 2^20-sample windows of an amplitude-ramped
+    AR(2)/chi-square stream, pushed from pinned host buffers through
+    ps_streamer (H2D copies overlap computation).  A pool of `pool` generated
+    windows is reused cyclically."""
+    from paper_2505_01231_amd import Plan, Streamer, synth
+    W = 1 << 20
+    total = W * n_windows
+    host = []
+    for i in range(pool):
+        t = torch.empty(W, dtype=torch.float32, pin_memory=True)
+        t.copy_(torch.from_numpy(synth.modulated_ar2(W, seed=5, start=i * W, total=W * pool)))
+        host.append(t)
+    with Plan(frame_len=4096, n_freq=1024, m=10, window="acg", precision=precision) as p:
+        st = Streamer(p, W, dtype=torch.float32, depth=3)
+        outs = [p.allocate_outputs(dev) for _ in range(3)]
+        slots = []
+        for w in range(3):                                   # warm-up
+            slots.append(st.push(host[w % pool], outs[w % 3]))
+        for sl in slots:
+            st.wait(sl)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        slots = []
+        for w in range(n_windows):
+            if w >= 3:
+                st.wait(slots[w - 3])
+            slots.append(st.push(host[w % pool], outs[w % 3]))
+        for sl in slots[-3:]:
+            st.wait(sl)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st.close()
+    rate = total / dt
+    # reference: a plain pinned host-to-device copy of the same volume
+    big = torch.empty(W * 16, dtype=torch.float32, pin_memory=True)
+    dst = torch.empty(W * 16, dtype=torch.float32, device=dev)
+    dst.copy_(big, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(4):
+        dst.copy_(big, non_blocking=True)
+    torch.cuda.synchronize()
+    link = 4 * big.numel() * 4 / (time.perf_counter() - t0) / 1e9
+    log(f"streaming {rate:.3e} samples/s, H2D {total * 4 / dt / 1e9:.1f} GB/s (plain pinned copy {link:.1f} GB/s)")
+    return {"windows": n_windows, "window_samples": W, "samples_per_s": rate,
+            "h2d_GBps": total * 4 / dt / 1e9, "plain_pinned_h2d_GBps": link, "seconds": dt,
+            "extrapolated_1e10_stream_s": 1e10 / rate,
+            "note": "N=4096, N_f=1024, m=10, depth-3 pinned ring; the H2D rate includes the copy/compute overlap"}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +175,12 @@ def main(argv=None):
                     help="timed steps of the batched all-FP32 path (for mixed-vs-FP32)")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the per-chunk FP32 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batching", action="store_true",
+                    help="also time the batching form: 24 four-channel int16 records of uneven length "
+                         "(2^16..2^22), N in {1024, 2048, 4096}, N_f = N/4, every combination orbit")
+    ap.add_argument("--streaming", action="store_true",
+                    help="also time the streaming form: 64 windows of 2^20 samples from pinned host "
+                         "memory, N = 4096, N_f = 1024, copy/compute overlap")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain elementwise copy of 1 GiB (3 launches) so that profiler "
                          "byte counters can be scaled against a kernel of known traffic")
@@ -185,6 +285,9 @@ def main(argv=None):
                         "mfma_peak_tflops": 2500.0,
                         "mfma_frac_of_peak": mfma_flops / (s4_avg_ms * 1e-3) / 2.5e15})
 
+    batching = run_batching(torch, dev, args.precision) if args.batching else None
+    streaming = run_streaming(torch, dev, args.precision) if args.streaming else None
+
     cpu = None if args.no_cpu_baseline else cpu_baseline(z)
     if cpu:
         log(f"cpu baseline {cpu['value']:.3e} samples/s")
@@ -221,6 +324,8 @@ def main(argv=None):
                   "speedup_vs_batched_fp32": (value / batched_fp32) if batched_fp32 else None,
                   "speedup_vs_per_chunk_fp32": (value / plain) if plain else None},
         "s4_matrix_cores": s4_info,
+        "batching": batching,
+        "streaming": streaming,
         "stage_ms_per_step": stage_ms,
     }
     print(json.dumps(line), flush=True)
