@@ -69,8 +69,9 @@ typedef enum ps_window { PS_WIN_HANN = 0, PS_WIN_HANN_PERIODIC = 1, PS_WIN_ACG =
  *  FP32    plain FP32 vector arithmetic;
  *  BF16X3  each FP32 operand split into three bfloat16 terms, six cross products
  *          on the matrix cores with FP32 accumulation;
- *  FP16X2S each operand scaled per frequency by a power of two and split into two
- *          float16 terms, three cross products on the matrix cores.
+ *  FP16X2S each operand scaled per chunk and frequency by a power of two and split
+ *          into two float16 terms, three cross products on the matrix cores
+ *          (requires m <= 10, else PS_E_UNSUPPORTED).
  * The k-statistic combination and the chunk average are FP64 in every mode. */
 typedef enum ps_precision { PS_PREC_FP32 = 0, PS_PREC_BF16X3 = 1, PS_PREC_FP16X2S = 2 } ps_precision;
 

@@ -459,8 +459,8 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
         return fail(PS_E_INVALID_ARG, "acG window needs sigma_t > 0");
     if (cfg->precision < PS_PREC_FP32 || cfg->precision > PS_PREC_FP16X2S)
         return fail(PS_E_INVALID_ARG, "unknown precision %d", cfg->precision);
-    if (cfg->precision == PS_PREC_FP16X2S)
-        return fail(PS_E_UNSUPPORTED, "precision %d not available in this build", cfg->precision);
+    if (cfg->precision == PS_PREC_FP16X2S && (cfg->orders & PS_ORDER_S4) && cfg->m > 10)
+        return fail(PS_E_UNSUPPORTED, "FP16X2S needs m <= 10 (one scale per chunk and column)");
     if (cfg->schedule != PS_SCHED_BATCHED && cfg->schedule != PS_SCHED_PER_CHUNK)
         return fail(PS_E_INVALID_ARG, "unknown schedule %d", cfg->schedule);
     int Nf = cfg->n_freq;
@@ -570,7 +570,9 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
         p->n_cu = std::max(1, prop.multiProcessorCount);
     p->bpc_s3 = ps::s3_blocks_per_cu();
-    p->bpc_s4 = p->precision == PS_PREC_FP32 ? ps::s4_blocks_per_cu() : ps::s4_mfma_blocks_per_cu();
+    p->bpc_s4 = p->precision == PS_PREC_FP32     ? ps::s4_blocks_per_cu()
+                : p->precision == PS_PREC_BF16X3 ? ps::s4_mfma_blocks_per_cu()
+                                                 : ps::s4_mfma_f16_blocks_per_cu();
     p->bpc_s4x = ps::s4_cross_blocks_per_cu();
     *out = p;
     return PS_OK;
@@ -742,8 +744,10 @@ ps_status launch_moments(ps_plan_t p, const Batch& B, const Group& G, char* ws, 
         const ps::BatchArgs a = batch_args(p, B, G.s4s, ws, tab, per_chunk, win_lo, win_hi, accumulate);
         if (p->precision == PS_PREC_FP32) {
             PS_HIP(ps::launch_s4_single(a, st));
-        } else {
+        } else if (p->precision == PS_PREC_BF16X3) {
             PS_HIP(ps::launch_s4_mfma(a, st));
+        } else {
+            PS_HIP(ps::launch_s4_mfma_f16(a, st));
         }
     }
     if (G.s4x.n_items) {

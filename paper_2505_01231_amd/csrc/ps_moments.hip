@@ -579,6 +579,208 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
     }
 }
 
+// ------------------------------------------------------------------ S4, one channel, FP16 x 2 scaled
+// The same sums on the matrix cores with v_mfma_f32_16x16x32_f16.  Per chunk
+// and column, the values are scaled by a power of two s = 2^e with
+// max_f(|Re|, |Im|) < s (exact), P by s^2, and split in two float16 terms
+// x = h + l (h = fp16(x), l = fp16(x - h)): with |x/s| < 1 the representation
+// error is below 2^-22 s, i.e. relative to the column's largest value.  The
+// three products h.h + h.l + l.h sit along the contraction dimension, per frame
+// [h h l] on the k side and [h l h] on the l side (slots 3f..3f+2, 30 of 32
+// used), so one MFMA contraction per chunk yields the FP32-accurate sums;
+// l.l (below 2^-22) is dropped.  The epilogue undoes the scales exactly:
+// X, Y, U, V and M4 carry (s_k s_l)^2 after squaring / by construction.
+typedef _Float16 halfx8_t __attribute__((ext_vector_type(8)));
+
+constexpr int kF16Stride = 40;       // halves per LDS operand row (80 B: 16-B aligned, conflict-free)
+constexpr int kF16Frames = 10;       // frames per operand batch: 3 x 10 = 30 <= 32
+
+__device__ __forceinline__ uint32_t pack_h(_Float16 lo, _Float16 hi) {
+    return (uint32_t)__builtin_bit_cast(unsigned short, lo) | ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16);
+}
+
+// Write the split terms of two consecutive frames (x0 at frame f, x1 at f+1)
+// into an operand row: slots 3f .. 3f+5 = 12 bytes.
+template <int SIDE>
+__device__ __forceinline__ void put_pair_f16(unsigned short* row, int f, float x0, float x1) {
+    const _Float16 h0 = (_Float16)x0, h1 = (_Float16)x1;
+    const _Float16 l0 = (_Float16)(x0 - (float)h0), l1 = (_Float16)(x1 - (float)h1);
+    uint32_t* w = reinterpret_cast<uint32_t*>(row + 3 * f);
+    if (SIDE == 0) {            // [h0 h0 l0 | h1 h1 l1]
+        w[0] = pack_h(h0, h0);
+        w[1] = pack_h(l0, h1);
+        w[2] = pack_h(h1, l1);
+    } else {                    // [h0 l0 h0 | h1 l1 h1]
+        w[0] = pack_h(h0, l0);
+        w[1] = pack_h(h0, h1);
+        w[2] = pack_h(l1, h1);
+    }
+}
+
+__device__ __forceinline__ float pow2_above(float a) {
+    // smallest power of two strictly above a (a >= 0); 1 for a == 0
+    if (!(a > 0.f)) return 1.0f;
+    int e;
+    (void)frexpf(a, &e);            // a = f 2^e, f in [0.5, 1)
+    return ldexpf(1.0f, e);
+}
+
+__global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16(BatchArgs p) {
+    __shared__ __attribute__((aligned(16))) unsigned short opK[3 * kTile][kF16Stride];
+    __shared__ __attribute__((aligned(16))) unsigned short opL[3 * kTile][kF16Stride];
+    __shared__ float psum[2][2][kTile];
+    __shared__ float sc2[2][kTile];              // s^2 per column of each side
+
+    Item it;
+    View v;
+    if (!resolve_item<kTile, 2>(p, it, v)) return;
+    const int c0 = it.c0, c1 = it.c1;
+    const int k0 = it.k0, l0 = it.l0;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+
+    // Loader role: thread -> (side, column, half); half 0 owns the frame pairs
+    // (0,1), (4,5), (8,9), half 1 owns (2,3), (6,7).
+    const int side = tid >> 7;
+    const int col = (tid >> 1) & (kTile - 1);
+    const int half = tid & 1;
+    const int gcol = (side ? l0 : k0) + col;
+    const bool live = gcol < p.Nf;
+    const float2* src = v.coef + it.ch[0] * v.cs + gcol;
+    unsigned short(*op)[kF16Stride] = side ? opL : opK;
+
+    // Zero the padding slots 30..31 of every row once.
+    for (int r = tid; r < 2 * 3 * kTile; r += kS4MThreads) {
+        unsigned short* row = (r < 3 * kTile) ? opK[r] : opL[r - 3 * kTile];
+        *reinterpret_cast<uint32_t*>(row + 3 * kF16Frames) = 0u;
+    }
+
+    double acc[4][4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[a][e][0] = acc[a][e][1] = 0.0;
+    const double gamma_d = p.gamma;
+
+    constexpr int kPairs = 3;                 // pair slots per thread (half 1 uses 2)
+    const int per_chunk = (v.m + kF16Frames - 1) / kF16Frames;
+    const int n_batches = (c1 - c0) * per_chunk;
+    float2 pre[2 * kPairs];
+    auto fetch = [&](int b) {
+        const int c = c0 + b / per_chunk;
+        const int fb = (b % per_chunk) * kF16Frames;
+        const int nf = min(kF16Frames, v.m - fb);
+        const float2* q = src + v.off + ((int64_t)c * v.m + fb) * v.K;
+#pragma unroll
+        for (int j = 0; j < kPairs; ++j) {
+            const int f = 2 * (half + 2 * j);
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                pre[2 * j + u] = (live && f + u < nf && f < kF16Frames) ? q[(int64_t)(f + u) * v.K]
+                                                                        : make_float2(0.f, 0.f);
+        }
+    };
+    if (n_batches > 0) fetch(0);
+
+    floatx4_t d[4][5];
+    float pacc = 0.f;
+    const floatx4_t zero = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int b = 0; b < n_batches; ++b) {
+        const int fbi = b % per_chunk;
+        // Column scale (shared by the chunk's frame batches: the first batch sets it).
+        float amax = 0.f;
+#pragma unroll
+        for (int j = 0; j < 2 * kPairs; ++j) amax = fmaxf(amax, fmaxf(fabsf(pre[j].x), fabsf(pre[j].y)));
+        amax = fmaxf(amax, __shfl_xor(amax, 1));
+        if (fbi == 0) pacc = 0.f;
+        __syncthreads();
+        if (fbi == 0 && half == 0) sc2[side][col] = pow2_above(amax) * pow2_above(amax);
+        __syncthreads();
+        const float s2 = sc2[side][col];
+        const float inv_s = 1.0f / sqrtf(s2);       // exact: s is a power of two
+        const float inv_s2 = 1.0f / s2;
+#pragma unroll
+        for (int j = 0; j < kPairs; ++j) {
+            const int f = 2 * (half + 2 * j);
+            if (f >= kF16Frames) break;
+            const float2 a0 = pre[2 * j], a1 = pre[2 * j + 1];
+            const float P0 = a0.x * a0.x + a0.y * a0.y, P1 = a1.x * a1.x + a1.y * a1.y;
+            pacc += P0 + P1;
+            if (side == 0) {
+                put_pair_f16<0>(op[col], f, a0.x * inv_s, a1.x * inv_s);
+                put_pair_f16<0>(op[kTile + col], f, a0.y * inv_s, a1.y * inv_s);
+                put_pair_f16<0>(op[2 * kTile + col], f, P0 * inv_s2, P1 * inv_s2);
+            } else {
+                put_pair_f16<1>(op[col], f, a0.x * inv_s, a1.x * inv_s);
+                put_pair_f16<1>(op[kTile + col], f, a0.y * inv_s, a1.y * inv_s);
+                put_pair_f16<1>(op[2 * kTile + col], f, P0 * inv_s2, P1 * inv_s2);
+            }
+        }
+        __syncthreads();
+        {
+            const int koff = lg * 8;
+            const int rk = w * 16 + li;
+            const halfx8_t aR = *reinterpret_cast<const halfx8_t*>(&opK[rk][koff]);
+            const halfx8_t aI = *reinterpret_cast<const halfx8_t*>(&opK[kTile + rk][koff]);
+            const halfx8_t aP = *reinterpret_cast<const halfx8_t*>(&opK[2 * kTile + rk][koff]);
+            const bool z = fbi == 0;
+#pragma unroll
+            for (int lb = 0; lb < 4; ++lb) {
+                const int rl = lb * 16 + li;
+                const halfx8_t bR = *reinterpret_cast<const halfx8_t*>(&opL[rl][koff]);
+                const halfx8_t bI = *reinterpret_cast<const halfx8_t*>(&opL[kTile + rl][koff]);
+                const halfx8_t bP = *reinterpret_cast<const halfx8_t*>(&opL[2 * kTile + rl][koff]);
+                d[lb][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aR, bR, z ? zero : d[lb][0], 0, 0, 0);  // X
+                d[lb][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aR, bI, z ? zero : d[lb][1], 0, 0, 0);  // U
+                d[lb][2] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aI, bR, z ? zero : d[lb][2], 0, 0, 0);  // V
+                d[lb][3] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aI, bI, z ? zero : d[lb][3], 0, 0, 0);  // Y
+                d[lb][4] = __builtin_amdgcn_mfma_f32_16x16x32_f16(aP, bP, z ? zero : d[lb][4], 0, 0, 0);  // M4
+            }
+        }
+        if (b + 1 < n_batches) fetch(b + 1);
+        if (fbi != per_chunk - 1) continue;
+
+        psum[side][half][col] = pacc;
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int kl = w * 16 + 4 * lg + e;
+            const float pk = psum[0][0][kl] + psum[0][1][kl];
+            const float s2k = sc2[0][kl];
+#pragma unroll
+            for (int lb = 0; lb < 4; ++lb) {
+                const int ll = lb * 16 + li;
+                const float pl = psum[1][0][ll] + psum[1][1][ll];
+                const float sig = s2k * sc2[1][ll];           // (s_k s_l)^2, a power of two
+                const float X = d[lb][0][e], U = d[lb][1][e], V = d[lb][2][e], Y = d[lb][3][e];
+                const float sq = fmaf(X, X, fmaf(Y, Y, fmaf(U, U, V * V)));
+                const float q = fmaf(2.0f * sig, sq, pk * pl);
+                const double val = fma(-gamma_d, (double)q, (double)(d[lb][4][e] * sig));
+                acc[lb][e][0] += val;
+                acc[lb][e][1] = fma(val, val, acc[lb][e][1]);
+            }
+        }
+    }
+
+    double* o = it.part;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+#pragma unroll
+        for (int lb = 0; lb < 4; ++lb) {
+            const int idx = (w * 16 + 4 * lg + e) * kTile + lb * 16 + li;
+#pragma unroll
+            for (int comp = 0; comp < 2; ++comp) {
+                double val = acc[lb][e][comp];
+                if (p.accumulate) val += o[comp * kTile * kTile + idx];
+                o[comp * kTile * kTile + idx] = val;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ S4, channel combinations
 // C4(a_k, b*_k, c_l, d*_l) for general channels (Section 7), in the centred
 // form of Appendix H with x = a'_k, y = b'*_k, z = c'_l, w = d'*_l:
@@ -761,6 +963,16 @@ int s3_blocks_per_cu() {
     return blocks_per_cu(reinterpret_cast<const void*>(&k_s3<kFrameBatch>), kS3Threads);
 }
 int s4_blocks_per_cu() { return blocks_per_cu(reinterpret_cast<const void*>(&k_s4_single), kS4Threads); }
+hipError_t launch_s4_mfma_f16(const BatchArgs& a, hipStream_t s) {
+    if (a.n_items <= 0) return hipSuccess;
+    k_s4_mfma_f16<<<item_grid(a), kS4MThreads, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+int s4_mfma_f16_blocks_per_cu() {
+    return blocks_per_cu(reinterpret_cast<const void*>(&k_s4_mfma_f16), kS4MThreads);
+}
+
 int s4_mfma_blocks_per_cu() {
     return blocks_per_cu(reinterpret_cast<const void*>(&k_s4_mfma_bf16), kS4MThreads);
 }

@@ -107,7 +107,7 @@ def test_coefficients_match_oracle(dev, N, dtype):
 
 
 # ---------------------------------------------------------------- configurations
-PRECISIONS = ["fp32", "bf16x3"]
+PRECISIONS = ["fp32", "bf16x3", "fp16x2s"]
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
@@ -165,12 +165,21 @@ def test_order_subsets(dev, orders, Nf):
     compare(gpu, ref, keys=tuple(f"s{o}" for o in orders), label=f"orders{orders}")
 
 
-@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_large_m_uses_several_frame_batches(dev, precision):
     say("m=37", precision)
     z = synth.ar2_chi2(512 * 37 * 4, seed=14, dtype=np.float32)
     gpu, ref = both(z, dev, 512, 96, 37, window="acg", precision=precision)
     compare(gpu, ref, label="m37")
+
+
+def test_fp16_split_needs_one_batch_per_chunk(dev):
+    from paper_2505_01231_amd import Plan
+    from paper_2505_01231_amd._lib import PS_E_UNSUPPORTED, PolyspecError
+    with pytest.raises(PolyspecError) as e:
+        Plan(frame_len=512, n_freq=96, m=11, precision="fp16x2s")
+    assert e.value.status == PS_E_UNSUPPORTED
+    Plan(frame_len=512, n_freq=96, m=11, precision="fp16x2s", orders=(2, 3)).close()
 
 
 def test_cross_channel_s2_s3(dev):
@@ -259,7 +268,7 @@ def test_errors_are_reported_not_faulted(dev):
 
 
 # ---------------------------------------------------------------- full size, sampled
-@pytest.mark.parametrize("precision", ["bf16x3"])
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x2s"])
 def test_full_size_sampled_points(dev, precision):
     """The benchmark workload itself (2^28 float32 AR(2)/chi-square samples,
     N = 8192, N_f = 2048, m = 10, 3276 chunks) in the benchmark's launch
