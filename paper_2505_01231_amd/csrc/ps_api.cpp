@@ -135,21 +135,16 @@ struct ps_plan_s {
 
 namespace {
 
-// Split of one kernel's chunk range over blocks when the launch holds a single
-// record and combination: the smallest split count whose wave-quantised time
-// is within 3% of the best for up to 64 parts.
-int choose_split(int n_tiles, int64_t n_chunks, int slots) {
-    if (n_chunks <= 1) return 1;
-    const int smax = (int)std::min<int64_t>(64, n_chunks);
-    auto cost = [&](int s) {
-        const double waves = std::ceil((double)n_tiles * s / slots);
-        return waves * std::ceil((double)n_chunks / s);
-    };
-    double best = 1e300;
-    for (int s = 1; s <= smax; ++s) best = std::min(best, cost(s));
-    for (int s = 1; s <= smax; ++s)
-        if (cost(s) <= 1.03 * best) return s;
-    return smax;
+// Blocks of one segment in the batched schedule: the stage's (tile, chunk)
+// units are spread over its resident blocks, L = ceil(U_stage / slots) units
+// per block at most, so that every segment gets ceil(U_seg / L) blocks.
+int64_t units_per_block(int64_t U_stage, int64_t slots) {
+    return std::max<int64_t>(1, (U_stage + slots - 1) / std::max<int64_t>(slots, 1));
+}
+int32_t seg_blocks(int64_t T, int64_t Np, int64_t L, bool per_chunk) {
+    if (per_chunk) return (int32_t)T;
+    const int64_t U = T * Np;
+    return (int32_t)std::max<int64_t>(1, std::min<int64_t>(U, (U + L - 1) / L));
 }
 
 // ------------------------------------------------------------ batch description
@@ -188,15 +183,6 @@ struct Batch {
 };
 
 size_t align64(size_t x) { return (x + 63) & ~size_t(63); }
-
-// Chunk split of one stage in one group: for a single record and combination
-// the wave-quantisation choice above; for many segments the work is already
-// spread, so only small batches get split further.
-int stage_split(int64_t base_items, int n_segs, int n_tiles_one, int64_t Np_one, int slots) {
-    if (n_segs == 1) return choose_split(n_tiles_one, Np_one, slots);
-    const int64_t want = (4LL * slots + base_items - 1) / std::max<int64_t>(base_items, 1);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(64, want));
-}
 
 void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_output* outs, Batch& B) {
     const bool per_chunk = p->schedule == PS_SCHED_PER_CHUNK;
@@ -240,28 +226,22 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
     int64_t part = 0;
     for (Group& G : B.groups) {
         const int r_lo = per_chunk ? G.rec : 0, r_hi = per_chunk ? G.rec + 1 : n;
-        // per-stage base items (split 1) and segment counts, for the split choice
-        int64_t base2 = 0, base3 = 0, base4s = 0, base4x = 0;
-        int ns2 = 0, ns3 = 0, ns4s = 0, ns4x = 0;
-        int64_t Np_one = 0;
+        // units per stage, for the block counts
+        int64_t U2 = 0, U3 = 0, U4s = 0, U4x = 0;
         for (int r = r_lo; r < r_hi; ++r) {
-            if (B.ri[r].Np == 0) continue;
-            Np_one = B.ri[r].Np;
-            for (int i = 0; i < p->n2(); ++i) { base2 += kblocks; ++ns2; }
-            for (int i = 0; i < p->n3(); ++i) { base3 += p->n_tiles[p->s3_sym(i) ? ps::kSym64 : ps::kFull64]; ++ns3; }
+            const int64_t Np = B.ri[r].Np;
+            if (Np == 0) continue;
+            U2 += (int64_t)p->n2() * kblocks * Np;
+            for (int i = 0; i < p->n3(); ++i) U3 += p->n_tiles[p->s3_sym(i) ? ps::kSym64 : ps::kFull64] * Np;
             for (int i = 0; i < p->n4(); ++i) {
-                if (p->s4_single(i)) { base4s += p->n_tiles[ps::kSym64]; ++ns4s; }
-                else { base4x += p->n_tiles[p->s4_sym(i) ? ps::kSym32 : ps::kFull32]; ++ns4x; }
+                if (p->s4_single(i)) U4s += p->n_tiles[ps::kSym64] * Np;
+                else U4x += p->n_tiles[p->s4_sym(i) ? ps::kSym32 : ps::kFull32] * Np;
             }
         }
-        int sp2 = 1, sp3 = 1, sp4s = 1, sp4x = 1;
-        if (!per_chunk) {
-            sp2 = ns2 == 1 ? (int)std::max<int64_t>(1, std::min<int64_t>(256, (4LL * p->n_cu + kblocks - 1) / kblocks))
-                           : stage_split(base2, ns2, kblocks, Np_one, 4 * p->n_cu);
-            sp3 = stage_split(base3, ns3, ns3 ? (int)(base3 / ns3) : 1, Np_one, p->n_cu * p->bpc_s3);
-            sp4s = stage_split(base4s, ns4s, ns4s ? (int)(base4s / ns4s) : 1, Np_one, p->n_cu * p->bpc_s4);
-            sp4x = stage_split(base4x, ns4x, ns4x ? (int)(base4x / ns4x) : 1, Np_one, p->n_cu * p->bpc_s4x);
-        }
+        const int64_t L2 = units_per_block(U2, 4LL * p->n_cu);
+        const int64_t L3 = units_per_block(U3, (int64_t)p->n_cu * p->bpc_s3);
+        const int64_t L4s = units_per_block(U4s, (int64_t)p->n_cu * p->bpc_s4);
+        const int64_t L4x = units_per_block(U4x, (int64_t)p->n_cu * p->bpc_s4x);
         for (int r = r_lo; r < r_hi; ++r) {
             const RecInfo& q = B.ri[r];
             if (q.Np == 0) continue;
@@ -272,16 +252,16 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
             for (int i = 0; i < p->n2(); ++i) {
                 ps::Seg sg = base;
                 sg.n_tiles = kblocks;
-                sg.split = (int)std::min<int64_t>(sp2, q.Np);
+                sg.blocks = seg_blocks(kblocks, q.Np, L2, per_chunk);
                 sg.tiles = 0;
                 for (int j = 0; j < 2; ++j) sg.ch[j] = p->c2[2 * i + j];
                 sg.part = part;
-                part += (int64_t)sg.split * 4 * Nf;
+                part += ps::Sched{sg.n_tiles, q.Np, sg.blocks}.n_slots() * 4 * 256;
                 sg.out = o && o->d_s2 ? o->d_s2 + 2 * (int64_t)i * Nf : nullptr;
                 sg.err = o && o->d_s2_err ? o->d_s2_err + 2 * (int64_t)i * Nf : nullptr;
                 sg.scale = scale2;
                 sg.ncomp = 4;
-                G.s2.add(sg, (int64_t)sg.split * kblocks);
+                G.s2.add(sg, sg.blocks);
                 G.f2.add(sg, kblocks);
             }
             for (int i = 0; i < p->n3(); ++i) {
@@ -289,17 +269,17 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 const bool sym = p->s3_sym(i);
                 sg.tiles = sym ? ps::kSym64 : ps::kFull64;
                 sg.n_tiles = p->n_tiles[sg.tiles];
-                sg.split = (int)std::min<int64_t>(sp3, q.Np);
+                sg.blocks = seg_blocks(sg.n_tiles, q.Np, L3, per_chunk);
                 for (int j = 0; j < 3; ++j) sg.ch[j] = p->c3[3 * i + j];
                 sg.part = part;
-                part += (int64_t)sg.split * sg.n_tiles * 4 * TT;
+                part += ps::Sched{sg.n_tiles, q.Np, sg.blocks}.n_slots() * 4 * TT;
                 sg.out = o && o->d_s3 ? o->d_s3 + 2 * i * nf2 : nullptr;
                 sg.err = o && o->d_s3_err ? o->d_s3_err + 2 * i * nf2 : nullptr;
                 sg.scale = scale3;
                 sg.sym = sym;
                 sg.ncomp = 4;
-                G.s3.add(sg, (int64_t)sg.split * sg.n_tiles);
-                G.f3.add(sg, sg.n_tiles);
+                G.s3.add(sg, sg.blocks);
+                G.f3.add(sg, (int64_t)sg.n_tiles * (TT / 256));
                 if (sym) G.m3.add(sg, (int64_t)((Nf + 31) / 32) * ((Nf + 31) / 32));
             }
             for (int i = 0; i < p->n4(); ++i) {
@@ -307,17 +287,17 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 const bool single = p->s4_single(i), sym = p->s4_sym(i);
                 sg.tiles = single ? ps::kSym64 : (sym ? ps::kSym32 : ps::kFull32);
                 sg.n_tiles = p->n_tiles[sg.tiles];
-                sg.split = (int)std::min<int64_t>(single ? sp4s : sp4x, q.Np);
+                sg.blocks = seg_blocks(sg.n_tiles, q.Np, single ? L4s : L4x, per_chunk);
                 for (int j = 0; j < 4; ++j) sg.ch[j] = p->c4[4 * i + j];
                 sg.ncomp = single ? 2 : 4;
                 sg.part = part;
-                part += (int64_t)sg.split * sg.n_tiles * sg.ncomp * (single ? TT : TX);
+                part += ps::Sched{sg.n_tiles, q.Np, sg.blocks}.n_slots() * sg.ncomp * (single ? TT : TX);
                 sg.out = o && o->d_s4 ? o->d_s4 + 2 * i * nf2 : nullptr;
                 sg.err = o && o->d_s4_err ? o->d_s4_err + 2 * i * nf2 : nullptr;
                 sg.scale = scale4;
                 sg.sym = sym;
-                (single ? G.s4s : G.s4x).add(sg, (int64_t)sg.split * sg.n_tiles);
-                G.f4.add(sg, sg.n_tiles);
+                (single ? G.s4s : G.s4x).add(sg, sg.blocks);
+                G.f4.add(sg, (int64_t)sg.n_tiles * ((single ? TT : TX) / 256));
                 if (sym) G.m4.add(sg, (int64_t)((Nf + 31) / 32) * ((Nf + 31) / 32));
             }
         }

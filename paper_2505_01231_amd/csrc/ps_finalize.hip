@@ -1,8 +1,9 @@
 // Chunk average and error bars (Section 4.2), in FP64.
 //
-// The moment kernels leave, per grid point and chunk part, the sums over
-// chunks of the un-scaled estimate x (its real and imaginary parts) and of
-// their squares.  Here the parts are added in a fixed order and
+// The moment kernels leave, per grid point and piece of work (a tile and a
+// range of its chunks), the sums over chunks of the un-scaled estimate x (its
+// real and imaginary parts) and of their squares.  Here a tile's pieces are
+// added in slot order (fixed, see Sched) and
 //   mean  = scale * sum x / Np
 //   Var   = Np/(Np-1) (sum x^2 / Np - (sum x / Np)^2)          (per Re and Im)
 //   sigma = |scale| * sqrt(Var / Np)
@@ -35,12 +36,17 @@ __global__ __launch_bounds__(256) void k_finalize_vec(FinalizeArgs p) {
     const int64_t x = blockIdx.x;
     if (x >= p.n_items) return;
     const Seg& sg = p.segs[find_seg(p.segs, p.n_segs, x)];
-    const int k = (int)(x - sg.item0) * 256 + threadIdx.x;
+    const int64_t t = x - sg.item0;
+    const int k = (int)t * 256 + threadIdx.x;
     if (k >= p.Nf) return;
-    const double* part = p.part + sg.part;
+    const double* part = p.part + sg.part + threadIdx.x;
     double s[4] = {0, 0, 0, 0};
-    for (int sp = 0; sp < sg.split; ++sp)
-        for (int c = 0; c < 4; ++c) s[c] += part[((int64_t)sp * 4 + c) * p.Nf + k];
+    int64_t s0 = 0, ns = 0;
+    if (sg.n_chunks > 0) slot_range(Sched{sg.n_tiles, sg.n_chunks, sg.blocks}, t, s0, ns);
+    for (int64_t slot = s0; slot < s0 + ns; ++slot) {
+        const double* q = part + slot * 4 * 256;
+        for (int c = 0; c < 4; ++c) s[c] += q[c * 256];
+    }
     const double np = (double)sg.n_chunks;
     double mr, sr, mi, si;
     mean_sigma(s[0], s[2], np, sg.scale, mr, sr);
@@ -55,26 +61,31 @@ __global__ __launch_bounds__(256) void k_finalize_vec(FinalizeArgs p) {
     }
 }
 
-// S3 / S4: one block per (record, combination, partial tile): sums over the
-// chunk parts in a fixed order and writes the tile's grid points (all of them,
-// or only k <= l for symmetric spectra) with coalesced accesses.
+// S3 / S4: one block per (record, combination, tile, 256 grid points of the
+// tile): adds the tile's slots in slot order and writes its grid points (all of
+// them, or only k <= l for symmetric spectra) with coalesced accesses.
 __global__ __launch_bounds__(256) void k_finalize_tiles(FinalizeArgs p) {
     const int64_t x = blockIdx.x;
     if (x >= p.n_items) return;
     const Seg& sg = p.segs[find_seg(p.segs, p.n_segs, x)];
-    const int tile = (int)(x - sg.item0);
     const int E = sg.tiles >= kSym32 ? kTileX : kTile;
+    const int TT = E * E;
+    const int per_tile = TT / 256;
+    const int64_t local = x - sg.item0;
+    const int tile = (int)(local / per_tile);
     const int2 t = p.tt.t[sg.tiles][tile];
     const int k0 = t.x * E, l0 = t.y * E;
-    const int TT = E * E;
     const double np = (double)sg.n_chunks;
     const int ncomp = sg.ncomp;
-    for (int idx = threadIdx.x; idx < TT; idx += 256) {
+    int64_t s0 = 0, ns = 0;
+    if (sg.n_chunks > 0) slot_range(Sched{sg.n_tiles, sg.n_chunks, sg.blocks}, tile, s0, ns);
+    {
+        const int idx = (int)(local - (int64_t)tile * per_tile) * 256 + threadIdx.x;
         const int k = k0 + idx / E, l = l0 + idx % E;
-        if (k >= p.Nf || l >= p.Nf || (sg.sym && k > l)) continue;
+        if (k >= p.Nf || l >= p.Nf || (sg.sym && k > l)) return;
         double s[4] = {0, 0, 0, 0};
-        for (int sp = 0; sp < sg.split; ++sp) {
-            const double* q = p.part + sg.part + ((int64_t)sp * sg.n_tiles + tile) * ncomp * TT + idx;
+        for (int64_t slot = s0; slot < s0 + ns; ++slot) {
+            const double* q = p.part + sg.part + slot * ncomp * TT + idx;
             for (int c = 0; c < ncomp; ++c) s[c] += q[c * TT];
         }
         double mr, sr, mi = 0.0, si = 0.0;

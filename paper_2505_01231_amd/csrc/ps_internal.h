@@ -5,8 +5,8 @@
 // every channel combination.  The host describes the work as a table of
 // segments (one per record and combination) that it copies into the
 // workspace; each block finds its segment by binary search over the
-// segments' first work-item index and derives its tile, chunk part and
-// partial-sum slot from it.
+// segments' first work-item index and derives its share of the segment's
+// (tile, chunk) units and partial-sum slots from it (see Sched).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -70,6 +70,40 @@ struct CentreArgs {
 };
 hipError_t launch_centre(const CentreArgs& a, hipStream_t s);
 
+// ---------------------------------------------------------------- work decomposition
+// A segment's work is T tiles x W chunks of (tile, chunk) units spread over B
+// blocks.  Tiles [0, T1), T1 = (T / B) B, are processed whole: block j takes
+// tiles j, j + B, j + 2B, ... (rounds), and the blocks of one round walk the
+// chunks in the same order, so that their coefficient reads meet in L2.  The
+// R = T - T1 remaining tiles hold U = R W units, taken in tile-major order and
+// cut into Q = min(B, U) non-empty runs of equal length (stream-K); run j goes
+// to block j, before its rounds, and touches at most two tiles since R < B.
+// Every piece (one tile, one chunk range) writes its own partial-sum slot:
+//   whole tile t              -> slot t
+//   run j's piece of tile t   -> slot T1 + j + (t - T1)
+// Runs are ordered and non-empty, so these are distinct and the slots of one
+// tile are consecutive; the finalize kernels add them in slot order, so the
+// result does not depend on timing.  The per-chunk schedule uses B = T (one
+// tile per block, every launch the same slots).
+struct Sched {
+    int64_t T, W, B;
+    __host__ __device__ int64_t T1() const { return (T / B) * B; }
+    __host__ __device__ int64_t R() const { return T - T1(); }
+    __host__ __device__ int64_t rounds() const { return T / B; }
+    __host__ __device__ int64_t runs() const { return R() * W < B ? R() * W : B; }
+    __host__ __device__ int64_t n_slots() const { return T1() + (R() > 0 ? runs() + R() : 0); }
+    // first unit of run j (j <= runs(); later blocks have no run)
+    __host__ __device__ int64_t run_begin(int64_t j) const {
+        const int64_t Q = runs();
+        return j >= Q ? R() * W : j * R() * W / Q;
+    }
+    // the run holding unit v (R > 0, W > 0)
+    __host__ __device__ int64_t run_of(int64_t v) const {
+        const int64_t U = R() * W;
+        return ((v + 1) * runs() + U - 1) / U - 1;
+    }
+};
+
 // ---------------------------------------------------------------- moments
 // One segment = one (record, channel combination) of one stage.
 struct Seg {
@@ -77,7 +111,7 @@ struct Seg {
     int64_t coef;           // float2 offset of the record's chunk 0 in the coefficient region
     int64_t part;           // double offset of the segment's partial sums
     int32_t n_tiles;        // tiles (S3/S4) or 256-wide k blocks (S2)
-    int32_t split;          // chunk parts
+    int32_t blocks;         // B of the segment's Sched (blocks of the moment stage)
     int32_t n_chunks;       // Np of the record
     int32_t tiles;          // TileKind
     int32_t ch[4];          // channels of the combination
@@ -131,6 +165,20 @@ hipError_t launch_finalize_grid(const FinalizeArgs& a, hipStream_t s);
 hipError_t launch_mirror(const FinalizeArgs& a, hipStream_t s);
 
 hipError_t launch_fill_nan(double* p, int64_t n, hipStream_t s);
+
+// The partial-sum slots of tile t: n consecutive slots from s0 (see Sched).
+__device__ __forceinline__ void slot_range(const Sched& sc, int64_t t, int64_t& s0, int64_t& n) {
+    const int64_t T1 = sc.T1();
+    if (t < T1) {
+        s0 = t;
+        n = 1;
+        return;
+    }
+    const int64_t v0 = (t - T1) * sc.W;
+    const int64_t j0 = sc.run_of(v0), j1 = sc.run_of(v0 + sc.W - 1);
+    s0 = T1 + j0 + (t - T1);
+    n = j1 - j0 + 1;
+}
 
 // Segment lookup shared by the kernels: the last segment with item0 <= v.
 __device__ __forceinline__ int find_seg(const Seg* segs, int n, int64_t v) {

@@ -18,26 +18,35 @@
 // Section 4.2 error bar.  The prefactors, the window sums and dt are applied
 // there.
 //
-// Work split: a launch covers the chunk range [chunk0, chunk1) split into
-// n_split contiguous parts; each block owns one 64x64 output tile and one part
-// and writes its own partial sums (no atomics: the reduction order is fixed).
-// Consecutive block ids are spread over the 8 XCDs by the hardware; the ids are
-// remapped so that the blocks resident on one XCD work on the same chunk part
-// at the same time and share its coefficients in that XCD's L2.
+// Work: each stage is one launch over every segment (record x combination);
+// a block takes its share of the segment's (tile, chunk) units as described at
+// Sched (whole tiles in rounds, plus one stream-K run over the remaining
+// tiles) and writes one partial-sum slot per piece (no atomics: the reduction
+// order is fixed).  Consecutive block ids are dealt round-robin over the 8 XCDs
+// by the hardware; the ids are remapped so that each XCD sees a contiguous
+// range of blocks: the tiles of one round on one XCD then walk the same chunks
+// at the same time and share their coefficients in that XCD's L2.
 #include "ps_internal.h"
 
 namespace ps {
 namespace {
 
-// A block's work item: blockIdx.x is remapped so that each XCD (blocks are
-// dealt round-robin over the 8 XCDs) sees a contiguous range of items; the
-// item is located in the segment table (record x combination) and split into
-// (chunk part, tile).
+// A block's share of its segment.
+struct Block {
+    const Seg* s;
+    Sched sc;
+    int64_t j;              // block index within the segment
+    int64_t v, v1;          // remaining units of the block's stream-K run
+    int64_t round;          // next whole-tile round
+    int cbase;              // record chunk of the segment's chunk 0 in this launch
+};
+
+// One piece of work: a tile and a range of its chunks.
 struct Item {
-    int split, tile, c0, c1;
+    int tile, c0, c1;       // c0, c1: record chunk indices
     int k0, l0;
     int ch[4];
-    double* part;               // partial-sum slot of this (part, tile)
+    double* part;           // partial-sum slot of the piece
 };
 
 // Coefficients of the item's record: chunk c, frame f, column k of channel ch
@@ -48,34 +57,24 @@ struct View {
     int K, m;
 };
 
-template <int EDGE, int NCOMP>
-__device__ __forceinline__ bool resolve_item(const BatchArgs& b, Item& it, View& v) {
+__device__ __forceinline__ bool resolve_block(const BatchArgs& b, Block& bk, View& v) {
     const int64_t per_xcd = (b.n_items + 7) >> 3;
     const int64_t x = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
     if (x >= b.n_items) return false;
     const Seg& s = b.segs[find_seg(b.segs, b.n_segs, x)];
-    const int64_t local = x - s.item0;
-    it.split = (int)(local / s.n_tiles);
-    it.tile = (int)(local - (int64_t)it.split * s.n_tiles);
-    const int64_t n = s.n_chunks;
-    it.c0 = (int)(n * it.split / s.split);
-    it.c1 = (int)(n * (it.split + 1) / s.split);
+    bk.s = &s;
+    bk.j = x - s.item0;
+    int64_t cb = 0, ce = s.n_chunks;
     if (b.per_chunk) {
-        it.c0 = max(it.c0, b.win_lo);
-        it.c1 = min(it.c1, b.win_hi);
+        cb = max(cb, (int64_t)b.win_lo);
+        ce = min(ce, (int64_t)b.win_hi);
     }
-    if (EDGE > 0) {
-        const int2 t = b.tt.t[s.tiles][it.tile];
-        it.k0 = t.x * EDGE;
-        it.l0 = t.y * EDGE;
-        it.part = b.part + s.part + ((int64_t)it.split * s.n_tiles + it.tile) * NCOMP * EDGE * EDGE;
-    } else {
-        it.k0 = it.tile * 256;
-        it.l0 = 0;
-        it.part = b.part + s.part + (int64_t)it.split * NCOMP * b.Nf;
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) it.ch[j] = s.ch[j];
+    if (ce <= cb) return false;
+    bk.cbase = (int)cb;
+    bk.sc = Sched{s.n_tiles, ce - cb, s.blocks};
+    bk.v = bk.sc.run_begin(bk.j);
+    bk.v1 = bk.sc.run_begin(bk.j + 1);
+    bk.round = 0;
     v.coef = b.coef;
     v.cs = b.coef_chan_stride;
     v.off = b.per_chunk ? -(int64_t)b.win_lo * b.m * b.K : s.coef;
@@ -84,42 +83,85 @@ __device__ __forceinline__ bool resolve_item(const BatchArgs& b, Item& it, View&
     return true;
 }
 
+// Next piece of the block: first its run, then its whole tiles.  Uniform over
+// the block.  EDGE = tile edge (0: 256-wide k blocks of S2), NCOMP = partial
+// components per grid point.
+template <int EDGE, int NCOMP>
+__device__ __forceinline__ bool next_item(const BatchArgs& b, Block& bk, Item& it) {
+    const Seg& s = *bk.s;
+    int64_t t, c0, c1, slot;
+    if (bk.v < bk.v1) {
+        const int64_t T1 = bk.sc.T1(), W = bk.sc.W;
+        t = T1 + bk.v / W;
+        c0 = bk.v % W;
+        c1 = min(W, c0 + (bk.v1 - bk.v));
+        slot = T1 + bk.j + (t - T1);
+        bk.v += c1 - c0;
+    } else if (bk.round < bk.sc.rounds()) {
+        t = bk.round * bk.sc.B + bk.j;
+        c0 = 0;
+        c1 = bk.sc.W;
+        slot = t;
+        ++bk.round;
+    } else {
+        return false;
+    }
+    it.tile = (int)t;
+    it.c0 = bk.cbase + (int)c0;
+    it.c1 = bk.cbase + (int)c1;
+    if (EDGE > 0) {
+        const int2 tt = b.tt.t[s.tiles][t];
+        it.k0 = tt.x * EDGE;
+        it.l0 = tt.y * EDGE;
+        it.part = b.part + s.part + slot * NCOMP * EDGE * EDGE;
+    } else {
+        it.k0 = (int)t * 256;
+        it.l0 = 0;
+        it.part = b.part + s.part + slot * NCOMP * 256;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) it.ch[q] = s.ch[q];
+    return true;
+}
+
 // ------------------------------------------------------------------ S2
 __global__ __launch_bounds__(256) void k_s2(BatchArgs p) {
-    Item it;
+    Block bk;
     View v;
-    if (!resolve_item<0, 4>(p, it, v)) return;
-    const int k = it.k0 + threadIdx.x;
-    if (k >= p.Nf) return;
-    const int c0 = it.c0, c1 = it.c1;
-    const float2* A = v.coef + it.ch[0] * v.cs;
-    const float2* B = v.coef + it.ch[1] * v.cs;
-    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    for (int c = c0; c < c1; ++c) {
-        const int64_t base = v.off + (int64_t)c * v.m * v.K + k;
-        float re = 0.f, im = 0.f;
-        for (int f = 0; f < v.m; ++f) {
-            const float2 x = A[base + (int64_t)f * v.K];
-            const float2 y = B[base + (int64_t)f * v.K];
-            re += x.x * y.x + x.y * y.y;   // x * conj(y)
-            im += x.y * y.x - x.x * y.y;
+    if (!resolve_block(p, bk, v)) return;
+    Item it;
+    while (next_item<0, 4>(p, bk, it)) {
+        const int k = it.k0 + threadIdx.x;
+        if (k >= p.Nf) continue;
+        const float2* A = v.coef + it.ch[0] * v.cs;
+        const float2* B = v.coef + it.ch[1] * v.cs;
+        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        for (int c = it.c0; c < it.c1; ++c) {
+            const int64_t base = v.off + (int64_t)c * v.m * v.K + k;
+            float re = 0.f, im = 0.f;
+            for (int f = 0; f < v.m; ++f) {
+                const float2 x = A[base + (int64_t)f * v.K];
+                const float2 y = B[base + (int64_t)f * v.K];
+                re += x.x * y.x + x.y * y.y;   // x * conj(y)
+                im += x.y * y.x - x.x * y.y;
+            }
+            s0 += re;
+            s1 += im;
+            s2 += (double)re * re;
+            s3 += (double)im * im;
         }
-        s0 += re;
-        s1 += im;
-        s2 += (double)re * re;
-        s3 += (double)im * im;
+        double* o = it.part + threadIdx.x;
+        if (p.accumulate) {
+            s0 += o[0];
+            s1 += o[256];
+            s2 += o[512];
+            s3 += o[768];
+        }
+        o[0] = s0;
+        o[256] = s1;
+        o[512] = s2;
+        o[768] = s3;
     }
-    double* o = it.part + k;
-    if (p.accumulate) {
-        s0 += o[0];
-        s1 += o[p.Nf];
-        s2 += o[2 * p.Nf];
-        s3 += o[3 * p.Nf];
-    }
-    o[0] = s0;
-    o[p.Nf] = s1;
-    o[2 * p.Nf] = s2;
-    o[3 * p.Nf] = s3;
 }
 
 // ------------------------------------------------------------------ S3
@@ -137,9 +179,11 @@ __global__ __launch_bounds__(kS3Threads, 2) void k_s3(BatchArgs p) {
     __shared__ float2 sB[FB][kTile];
     __shared__ float2 sC[FB][2 * kTile];
 
-    Item it;
+    Block bk;
     View v;
-    if (!resolve_item<kTile, 4>(p, it, v)) return;
+    if (!resolve_block(p, bk, v)) return;
+    Item it;
+    while (next_item<kTile, 4>(p, bk, it)) {
     const int c0 = it.c0, c1 = it.c1;
     const int k0 = it.k0, l0 = it.l0;
 
@@ -246,6 +290,7 @@ __global__ __launch_bounds__(kS3Threads, 2) void k_s3(BatchArgs p) {
             }
         }
     }
+    }
 }
 
 // ------------------------------------------------------------------ S4, one channel
@@ -258,9 +303,11 @@ __global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(BatchArgs p) {
     __shared__ float2 sA[kFrameBatch][kTile];
     __shared__ float2 sB[kFrameBatch][kTile];
 
-    Item it;
+    Block bk;
     View v;
-    if (!resolve_item<kTile, 2>(p, it, v)) return;
+    if (!resolve_block(p, bk, v)) return;
+    Item it;
+    while (next_item<kTile, 2>(p, bk, it)) {
     const int c0 = it.c0, c1 = it.c1;
     const int k0 = it.k0, l0 = it.l0;
     const float2* A = v.coef + it.ch[0] * v.cs;
@@ -358,6 +405,7 @@ __global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(BatchArgs p) {
                 o[comp * kTile * kTile + idx] = val;
             }
         }
+    }
     }
 }
 
@@ -459,11 +507,9 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
     __shared__ __attribute__((aligned(16))) unsigned short opL[3 * kTile][kOpStride];
     __shared__ float psum[2][2][kTile];
 
-    Item it;
+    Block bk;
     View v;
-    if (!resolve_item<kTile, 2>(p, it, v)) return;
-    const int c0 = it.c0, c1 = it.c1;
-    const int k0 = it.k0, l0 = it.l0;
+    if (!resolve_block(p, bk, v)) return;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
@@ -473,9 +519,6 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
     const int side = tid >> 7;
     const int col = (tid >> 1) & (kTile - 1);
     const int half = tid & 1;
-    const int gcol = (side ? l0 : k0) + col;
-    const bool live = gcol < p.Nf;
-    const float2* src = v.coef + it.ch[0] * v.cs + gcol;
     unsigned short(*op)[kOpStride] = side ? opL : opK;
 
     // Zero the padding slots 60..63 of every row once; they are never written again.
@@ -483,6 +526,14 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
         unsigned short* row = (r < 3 * kTile) ? opK[r] : opL[r - 3 * kTile];
         *reinterpret_cast<uint2*>(row + 6 * kMfmaFrames) = make_uint2(0u, 0u);
     }
+
+    Item it;
+    while (next_item<kTile, 2>(p, bk, it)) {
+    const int c0 = it.c0, c1 = it.c1;
+    const int k0 = it.k0, l0 = it.l0;
+    const int gcol = (side ? l0 : k0) + col;
+    const bool live = gcol < p.Nf;
+    const float2* src = v.coef + it.ch[0] * v.cs + gcol;
 
     double acc[4][4][2];
 #pragma unroll
@@ -577,6 +628,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
             }
         }
     }
+    }
 }
 
 // ------------------------------------------------------------------ S4, one channel, FP16 x 2 scaled
@@ -631,11 +683,9 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16(BatchArgs p) {
     __shared__ float psum[2][2][kTile];
     __shared__ float sc2[2][kTile];              // s^2 per column of each side
 
-    Item it;
+    Block bk;
     View v;
-    if (!resolve_item<kTile, 2>(p, it, v)) return;
-    const int c0 = it.c0, c1 = it.c1;
-    const int k0 = it.k0, l0 = it.l0;
+    if (!resolve_block(p, bk, v)) return;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
@@ -646,9 +696,6 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16(BatchArgs p) {
     const int side = tid >> 7;
     const int col = (tid >> 1) & (kTile - 1);
     const int half = tid & 1;
-    const int gcol = (side ? l0 : k0) + col;
-    const bool live = gcol < p.Nf;
-    const float2* src = v.coef + it.ch[0] * v.cs + gcol;
     unsigned short(*op)[kF16Stride] = side ? opL : opK;
 
     // Zero the padding slots 30..31 of every row once.
@@ -656,6 +703,14 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16(BatchArgs p) {
         unsigned short* row = (r < 3 * kTile) ? opK[r] : opL[r - 3 * kTile];
         *reinterpret_cast<uint32_t*>(row + 3 * kF16Frames) = 0u;
     }
+
+    Item it;
+    while (next_item<kTile, 2>(p, bk, it)) {
+    const int c0 = it.c0, c1 = it.c1;
+    const int k0 = it.k0, l0 = it.l0;
+    const int gcol = (side ? l0 : k0) + col;
+    const bool live = gcol < p.Nf;
+    const float2* src = v.coef + it.ch[0] * v.cs + gcol;
 
     double acc[4][4][2];
 #pragma unroll
@@ -779,6 +834,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16(BatchArgs p) {
             }
         }
     }
+    }
 }
 
 // ------------------------------------------------------------------ S4, channel combinations
@@ -807,9 +863,11 @@ __device__ __forceinline__ void cmacc(float2& acc, float2 x, float2 y) {       /
 __global__ __launch_bounds__(kS4XThreads, 2) void k_s4_cross(BatchArgs p) {
     __shared__ float2 sv[4][kFrameBatch][kTileX];   // a'_k, b'_k, c'_l, d'_l
 
-    Item it;
+    Block bk;
     View v;
-    if (!resolve_item<kTileX, 4>(p, it, v)) return;
+    if (!resolve_block(p, bk, v)) return;
+    Item it;
+    while (next_item<kTileX, 4>(p, bk, it)) {
     const int c0 = it.c0, c1 = it.c1;
     const int k0 = it.k0, l0 = it.l0;
 
@@ -906,6 +964,7 @@ __global__ __launch_bounds__(kS4XThreads, 2) void k_s4_cross(BatchArgs p) {
                 o[comp * TT + idx] = val;
             }
         }
+    }
 }
 
 int blocks_per_cu(const void* fn, int threads) {
