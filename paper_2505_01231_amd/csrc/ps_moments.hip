@@ -411,101 +411,110 @@ __global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(BatchArgs p) {
 
 // ------------------------------------------------------------------ S4, one channel, matrix cores
 // The same sums as k_s4_single, with the frame contractions on the matrix
-// cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  Each FP32 operand x is
-// split into three bfloat16 terms x = h + m + l (h, m by truncation to 8
-// significant bits, l rounded): the representation error is ~2^-24 |x|.  The
-// six products h.h + h.m + m.h + h.l + l.h + m.m are laid side by side along
-// the contraction dimension: per frame f the k-side operand row holds
-// [h h m h l m] and the l-side row [h m h l h m] at positions 6f..6f+5, so one
-// MFMA contraction over 6 x 10 frames (padded to 64) yields the FP32-accurate
-// frame sum.  Dropped terms (m.l, l.m, l.l) are below 2^-25 relative.
+// cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation).  Each FP32 operand x is
+// split into three bfloat16 terms x = h + m + l, each rounded to nearest
+// (h = bf16(x), m = bf16(x - h), l = bf16(x - h - m); both differences are
+// exact), so |x - h - m - l| <= 2^-25 |x|.  The six products
+// h.h + h.m + m.h + h.l + l.h + m.m lie side by side along the contraction
+// dimension: per frame f the k-side operand row holds [h h m h l m] and the
+// l-side row [h m h l h m] at positions 6f..6f+5, so one contraction over
+// 6 x 10 frames (padded to 64) yields the frame sum to ~2^-23 relative (the
+// dropped m.l + l.m + l.l are below 2^-23 |x y|).  One packed conversion per
+// 32-bit word gives the words directly: k side bf16x2(x, x) = [h h],
+// bf16x2(x - h, x) = [m h], bf16x2(x - h - m, x - h) = [l m]; l side
+// [h m], [h l], [h m] likewise.
 //
-// LDS holds, per chunk (in batches of 10 frames), the operand rows of both
-// sides: rows 0..63 Re, 64..127 Im, 128..191 P = |a'|^2 of the tile's 64
-// columns.  Wave w computes the 16 x 64 strip of grid points with k in
-// k0 + 16w + [0, 16): for each 16 x 16 block five accumulators X, U, V, Y, M4,
-// so all five sums of a grid point sit in the same lane and element and the
-// k-statistic combination runs in registers.
+// LDS holds, per batch of 10 frames, the operand rows of both sides: rows
+// 0..63 Re, 64..127 Im, 128..191 P = |a'|^2 of the tile's 64 columns, 144 B
+// apart (the 32-row, 16-byte-per-lane reads of the 32x32x16 operands are free
+// of bank conflicts at that stride).  Wave w owns the 32 x 32 quadrant
+// (k0 + 32 (w / 2), l0 + 32 (w % 2)) of the tile with five accumulators X, U,
+// V, Y, M4, so all five sums of a grid point sit in the same lane and register
+// and the k-statistic combination runs there.  The term -gamma p_k p_l of the
+// combination enters the M4 contraction as one more K step (the split terms of
+// -gamma p_k and p_l in slots 0..5), so per grid point and chunk the epilogue
+// is v = M4' - 2 gamma (X^2 + Y^2 + U^2 + V^2) plus the FP64 chunk sums.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float floatx2_t __attribute__((ext_vector_type(2)));
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
+typedef float floatx16_t __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kMfmaFrames = 10;      // frames per operand batch: 6 x 10 = 60 <= 64
-constexpr int kOpStride = 72;        // bf16 per LDS operand row (144 B: 16-B aligned, conflict-free b128 reads)
+constexpr int kMfmaFrames = 10;      // frames per operand batch: 6 x 10 = 60 <= 64 slots
+constexpr int kOpDw = 36;            // 32-bit words per LDS operand row (144 B; 32 used)
 constexpr int kS4MThreads = 256;
 
-__device__ __forceinline__ void split3(float x, uint32_t& h, uint32_t& m, uint32_t& l) {
-    const uint32_t ux = __float_as_uint(x);
-    const uint32_t uh = ux & 0xFFFF0000u;
-    const float r1 = x - __uint_as_float(uh);            // exact
-    const uint32_t um = __float_as_uint(r1) & 0xFFFF0000u;
-    const float r2 = r1 - __uint_as_float(um);           // exact
-    h = uh >> 16;
-    m = um >> 16;
-    l = (uint32_t)__builtin_bit_cast(unsigned short, (__bf16)r2);
+// bf16x2 word (lo, hi), each rounded to nearest even.
+__device__ __forceinline__ uint32_t pk_bf16(float lo, float hi) {
+    const floatx2_t v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
 }
+__device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
 
-// Write the six split terms of x for frame slot f into an operand row.
+// The three words of x for one frame slot: k side [h h][m h][l m] (SIDE 0),
+// l side [h m][h l][h m] (SIDE 1; the third word equals the first).
 template <int SIDE>
-__device__ __forceinline__ void put_terms(unsigned short* row, int f, float x) {
-    uint32_t h, m, l;
-    split3(x, h, m, l);
-    uint32_t* w = reinterpret_cast<uint32_t*>(row + 6 * f);
-    if (SIDE == 0) {            // [h h m h l m]
-        w[0] = h | (h << 16);
-        w[1] = m | (h << 16);
-        w[2] = l | (m << 16);
-    } else {                    // [h m h l h m]
-        w[0] = h | (m << 16);
-        w[1] = h | (l << 16);
-        w[2] = h | (m << 16);
+__device__ __forceinline__ void split_words(float x, uint32_t& w0, uint32_t& w1, uint32_t& w2) {
+    const uint32_t hh = pk_bf16(x, x);
+    const float r = x - bf_lo(hh);                        // x - h, exact
+    if (SIDE == 0) {
+        w0 = hh;
+        w1 = pk_bf16(r, x);                               // [m h]
+        const float s = r - bf_lo(w1);                    // x - h - m, exact
+        w2 = pk_bf16(s, r);                               // [l m]
+    } else {
+        w0 = pk_bf16(x, r);                               // [h m]
+        const float s = r - bf_hi(w0);
+        w1 = pk_bf16(x, s);                               // [h l]
+        w2 = w0;
     }
 }
 
-// One batch of MFMA contractions for wave w: 2 K-steps of 32 over the 64
-// operand columns.  FIRST starts the chunk's sums from zero (literal C = 0).
-template <bool FIRST>
-__device__ __forceinline__ void s4_mfma_batch(const unsigned short (*opK)[kOpStride],
-                                              const unsigned short (*opL)[kOpStride], int w, int li,
-                                              int lg, floatx4_t (&d)[4][5]) {
-    const floatx4_t zero = {0.f, 0.f, 0.f, 0.f};
-    const int rk = w * 16 + li;
+// Operand words for one extra K step holding a single product a.b (split as
+// above): lanes 0..31 carry slots 0..7 = [6 terms, 0, 0], lanes 32..63 zeros.
+template <int SIDE>
+__device__ __forceinline__ bf16x8_t single_term(float x, bool live) {
+    uint32_t w0, w1, w2;
+    split_words<SIDE>(x, w0, w1, w2);
+    const u32x4_t u = {live ? w0 : 0u, live ? w1 : 0u, live ? w2 : 0u, 0u};
+    return __builtin_bit_cast(bf16x8_t, u);
+}
+
+__device__ __forceinline__ float xor1(float v) {        // value of the neighbouring lane (lane ^ 1)
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
+// Stage one batch of this thread's frame slots (frames half + 2j) of column
+// `col` into the operand rows of its side; returns the sum of P over them.
+template <int SIDE>
+__device__ __forceinline__ float stage_rows(uint32_t (*op)[kOpDw], int col, int half, const float2 (&pre)[kMfmaFrames / 2]) {
+    float pa = 0.f;
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-        const int koff = ks * 32 + lg * 8;
-        const bf16x8_t aR = *reinterpret_cast<const bf16x8_t*>(&opK[rk][koff]);
-        const bf16x8_t aI = *reinterpret_cast<const bf16x8_t*>(&opK[kTile + rk][koff]);
-        const bf16x8_t aP = *reinterpret_cast<const bf16x8_t*>(&opK[2 * kTile + rk][koff]);
-        bf16x8_t bR = *reinterpret_cast<const bf16x8_t*>(&opL[li][koff]);
-        bf16x8_t bI = *reinterpret_cast<const bf16x8_t*>(&opL[kTile + li][koff]);
-        bf16x8_t bP = *reinterpret_cast<const bf16x8_t*>(&opL[2 * kTile + li][koff]);
-#pragma unroll
-        for (int lb = 0; lb < 4; ++lb) {
-            // Fetch the next l-block's operands while this one's contractions run.
-            bf16x8_t nR = bR, nI = bI, nP = bP;
-            if (lb < 3) {
-                const int rl = (lb + 1) * 16 + li;
-                nR = *reinterpret_cast<const bf16x8_t*>(&opL[rl][koff]);
-                nI = *reinterpret_cast<const bf16x8_t*>(&opL[kTile + rl][koff]);
-                nP = *reinterpret_cast<const bf16x8_t*>(&opL[2 * kTile + rl][koff]);
-            }
-            const bool z = FIRST && ks == 0;
-            d[lb][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR, bR, z ? zero : d[lb][0], 0, 0, 0);  // X
-            d[lb][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aR, bI, z ? zero : d[lb][1], 0, 0, 0);  // U
-            d[lb][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI, bR, z ? zero : d[lb][2], 0, 0, 0);  // V
-            d[lb][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aI, bI, z ? zero : d[lb][3], 0, 0, 0);  // Y
-            d[lb][4] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aP, bP, z ? zero : d[lb][4], 0, 0, 0);  // M4
-            __builtin_amdgcn_sched_barrier(0);
-            bR = nR;
-            bI = nI;
-            bP = nP;
-        }
+    for (int j = 0; j < kMfmaFrames / 2; ++j) {
+        const int f = half + 2 * j;
+        const float re = pre[j].x, im = pre[j].y;
+        const float P = fmaf(re, re, im * im);
+        pa += P;
+        uint32_t a0, a1, a2, b0, b1, b2, e0, e1, e2;
+        split_words<SIDE>(re, a0, a1, a2);
+        split_words<SIDE>(im, b0, b1, b2);
+        split_words<SIDE>(P, e0, e1, e2);
+        uint32_t* wr = &op[col][3 * f];
+        uint32_t* wi = &op[kTile + col][3 * f];
+        uint32_t* wp = &op[2 * kTile + col][3 * f];
+        wr[0] = a0; wr[1] = a1; wr[2] = a2;
+        wi[0] = b0; wi[1] = b1; wi[2] = b2;
+        wp[0] = e0; wp[1] = e1; wp[2] = e2;
     }
+    return pa;
 }
 
 __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
-    __shared__ __attribute__((aligned(16))) unsigned short opK[3 * kTile][kOpStride];
-    __shared__ __attribute__((aligned(16))) unsigned short opL[3 * kTile][kOpStride];
-    __shared__ float psum[2][2][kTile];
+    __shared__ __attribute__((aligned(16))) uint32_t opK[3 * kTile][kOpDw];
+    __shared__ __attribute__((aligned(16))) uint32_t opL[3 * kTile][kOpDw];
+    __shared__ float psum[2][kTile];
 
     Block bk;
     View v;
@@ -513,19 +522,23 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
-    const int li = lane & 15, lg = lane >> 4;
+    const int r32 = lane & 31, kh = lane >> 5;
+    const int rowK = 32 * (w >> 1) + r32, rowL = 32 * (w & 1) + r32;
 
     // Loader role: thread -> (side, column, half of the frame slots).
     const int side = tid >> 7;
     const int col = (tid >> 1) & (kTile - 1);
     const int half = tid & 1;
-    unsigned short(*op)[kOpStride] = side ? opL : opK;
+    uint32_t(*op)[kOpDw] = side ? opL : opK;
 
-    // Zero the padding slots 60..63 of every row once; they are never written again.
+    // Zero the padding words 30..31 of every row once; they are never written again.
     for (int r = tid; r < 2 * 3 * kTile; r += kS4MThreads) {
-        unsigned short* row = (r < 3 * kTile) ? opK[r] : opL[r - 3 * kTile];
-        *reinterpret_cast<uint2*>(row + 6 * kMfmaFrames) = make_uint2(0u, 0u);
+        uint32_t* row = (r < 3 * kTile) ? opK[r] : opL[r - 3 * kTile];
+        row[3 * kMfmaFrames] = 0u;
+        row[3 * kMfmaFrames + 1] = 0u;
     }
+    const float gamma = (float)p.gamma;
+    const float m2g = -2.0f * gamma;
 
     Item it;
     while (next_item<kTile, 2>(p, bk, it)) {
@@ -535,13 +548,9 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
     const bool live = gcol < p.Nf;
     const float2* src = v.coef + it.ch[0] * v.cs + gcol;
 
-    double acc[4][4][2];
+    double acc[16][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc[a][e][0] = acc[a][e][1] = 0.0;
-    const float gamma = (float)p.gamma;
-    const double gamma_d = p.gamma;
+    for (int r = 0; r < 16; ++r) acc[r][0] = acc[r][1] = 0.0;
 
     constexpr int kSlots = kMfmaFrames / 2;       // frame slots of this thread: half + 2j
     const int per_chunk = (v.m + kMfmaFrames - 1) / kMfmaFrames;
@@ -560,72 +569,78 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
     };
     if (n_batches > 0) fetch(0);
 
-    floatx4_t d[4][5];
+    floatx16_t d[5];
     float pacc = 0.f;
-    (void)gamma;
 #pragma unroll 1
     for (int b = 0; b < n_batches; ++b) {
         const int fbi = b % per_chunk;
-        if (fbi == 0) pacc = 0.f;
+        const bool first = fbi == 0, last = fbi == per_chunk - 1;
+        if (first) pacc = 0.f;
         __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kSlots; ++j) {
-            const int f = half + 2 * j;
-            const float re = pre[j].x, im = pre[j].y;
-            const float P = re * re + im * im;
-            pacc += P;
-            if (side == 0) {
-                put_terms<0>(op[col], f, re);
-                put_terms<0>(op[kTile + col], f, im);
-                put_terms<0>(op[2 * kTile + col], f, P);
-            } else {
-                put_terms<1>(op[col], f, re);
-                put_terms<1>(op[kTile + col], f, im);
-                put_terms<1>(op[2 * kTile + col], f, P);
-            }
+        pacc += side == 0 ? stage_rows<0>(op, col, half, pre) : stage_rows<1>(op, col, half, pre);
+        if (last) {
+            const float tot = pacc + xor1(pacc);          // p over the chunk's frames
+            if (half == 0) psum[side][col] = tot;
         }
         __syncthreads();
-        if (fbi == 0) s4_mfma_batch<true>(opK, opL, w, li, lg, d);
-        else s4_mfma_batch<false>(opK, opL, w, li, lg, d);
-        // Next batch's loads overlap the epilogue (issuing them before the
-        // contractions would keep them live across the accumulator peak).
-        if (b + 1 < n_batches) fetch(b + 1);
-        if (fbi != per_chunk - 1) continue;
-
-        psum[side][half][col] = pacc;
-        __syncthreads();
-        // Accumulator element e of lane (lg, li) is grid point
-        // k = k0 + 16w + 4 lg + e, l = l0 + 16 lb + li.
+        // Four K steps of 16 slots (the scheduling barrier keeps each step's
+        // operand reads next to its contractions: fewer live registers).
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int kl = w * 16 + 4 * lg + e;
-            const float pk = psum[0][0][kl] + psum[0][1][kl];
-#pragma unroll
-            for (int lb = 0; lb < 4; ++lb) {
-                const int ll = lb * 16 + li;
-                const float pl = psum[1][0][ll] + psum[1][1][ll];
-                const float X = d[lb][0][e], U = d[lb][1][e], V = d[lb][2][e], Y = d[lb][3][e];
-                const float sq = fmaf(X, X, fmaf(Y, Y, fmaf(U, U, V * V)));
-                const float q = fmaf(2.0f, sq, pk * pl);
-                const double val = fma(-gamma_d, (double)q, (double)d[lb][4][e]);
-                acc[lb][e][0] += val;
-                acc[lb][e][1] = fma(val, val, acc[lb][e][1]);
+        for (int ks = 0; ks < 4; ++ks) {
+            const int wo = 8 * ks + 4 * kh;                // first word of this lane's 8 slots
+            const bf16x8_t aR = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(&opK[rowK][wo]));
+            const bf16x8_t aI = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(&opK[kTile + rowK][wo]));
+            const bf16x8_t aP = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(&opK[2 * kTile + rowK][wo]));
+            const bf16x8_t bR = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(&opL[rowL][wo]));
+            const bf16x8_t bI = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(&opL[kTile + rowL][wo]));
+            const bf16x8_t bP = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(&opL[2 * kTile + rowL][wo]));
+            if (first && ks == 0) {
+                const floatx16_t z = {};
+                d[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aR, bR, z, 0, 0, 0);   // X
+                d[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aR, bI, z, 0, 0, 0);   // U
+                d[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aI, bR, z, 0, 0, 0);   // V
+                d[3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aI, bI, z, 0, 0, 0);   // Y
+                d[4] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aP, bP, z, 0, 0, 0);   // M4
+            } else {
+                d[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aR, bR, d[0], 0, 0, 0);
+                d[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aR, bI, d[1], 0, 0, 0);
+                d[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aI, bR, d[2], 0, 0, 0);
+                d[3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aI, bI, d[3], 0, 0, 0);
+                d[4] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aP, bP, d[4], 0, 0, 0);
             }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (last) {
+            // M4 <- M4 - gamma p_k p_l, as one more contraction step
+            const bf16x8_t xa = single_term<0>(-gamma * psum[0][rowK], kh == 0);
+            const bf16x8_t xb = single_term<1>(psum[1][rowL], kh == 0);
+            d[4] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa, xb, d[4], 0, 0, 0);
+        }
+        // Next batch's loads overlap the epilogue.
+        if (b + 1 < n_batches) fetch(b + 1);
+        if (!last) continue;
+
+        // Register r of lane (kh, r32) is grid point
+        // k = k0 + 32 (w / 2) + 8 (r / 4) + 4 kh + r % 4, l = l0 + 32 (w % 2) + r32.
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float X = d[0][r], U = d[1][r], V = d[2][r], Y = d[3][r];
+            const float sq = fmaf(X, X, fmaf(Y, Y, fmaf(U, U, V * V)));
+            const double val = (double)fmaf(m2g, sq, d[4][r]);
+            acc[r][0] += val;
+            acc[r][1] = fma(val, val, acc[r][1]);
         }
     }
 
     double* o = it.part;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int r = 0; r < 16; ++r) {
+        const int idx = (32 * (w >> 1) + 8 * (r >> 2) + 4 * kh + (r & 3)) * kTile + 32 * (w & 1) + r32;
 #pragma unroll
-        for (int lb = 0; lb < 4; ++lb) {
-            const int idx = (w * 16 + 4 * lg + e) * kTile + lb * 16 + li;
-#pragma unroll
-            for (int comp = 0; comp < 2; ++comp) {
-                double val = acc[lb][e][comp];
-                if (p.accumulate) val += o[comp * kTile * kTile + idx];
-                o[comp * kTile * kTile + idx] = val;
-            }
+        for (int comp = 0; comp < 2; ++comp) {
+            double val = acc[r][comp];
+            if (p.accumulate) val += o[comp * kTile * kTile + idx];
+            o[comp * kTile * kTile + idx] = val;
         }
     }
     }
