@@ -31,6 +31,15 @@
 namespace ps {
 namespace {
 
+// Workgroup barrier that orders LDS accesses only.  The threads of a block
+// share data through LDS alone, so outstanding global loads (the next batch's
+// prefetch) may stay in flight across it; __syncthreads() would wait for them.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // A block's share of its segment.
 struct Block {
     const Seg* s;
@@ -231,14 +240,14 @@ __global__ __launch_bounds__(kS3Threads, 2) void k_s3(BatchArgs p) {
 #pragma unroll
             for (int q = 0; q < 16; ++q) tr[q] = tm[q] = 0.f;
         }
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int f = 0; f < FB; ++f) {
             if (col < kTile) sA[f][col] = pre[f];
             else if (col < 2 * kTile) sB[f][col - kTile] = pre[f];
             else if (col < 4 * kTile - 1) sC[f][col - 2 * kTile] = pre[f];
         }
-        __syncthreads();
+        lds_barrier();
         if (b + 1 < n_batches) fetch(b + 1);
 #pragma unroll 2
         for (int f = 0; f < nf; ++f) {
@@ -342,7 +351,7 @@ __global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(BatchArgs p) {
 #pragma unroll 1
         for (int fb = 0; fb < v.m; fb += kFrameBatch) {
             const int nf = min(kFrameBatch, v.m - fb);
-            __syncthreads();
+            lds_barrier();
             if (col < 2 * kTile) {
                 for (int f = 0; f < nf; ++f) {
                     const float2 x = live ? src[fbase + (int64_t)(fb + f) * v.K] : make_float2(0.f, 0.f);
@@ -350,7 +359,7 @@ __global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(BatchArgs p) {
                     else sB[f][col - kTile] = x;
                 }
             }
-            __syncthreads();
+            lds_barrier();
 #pragma unroll 1
             for (int f = 0; f < nf; ++f) {
                 float2 a[4], b[4];
@@ -576,15 +585,18 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
         const int fbi = b % per_chunk;
         const bool first = fbi == 0, last = fbi == per_chunk - 1;
         if (first) pacc = 0.f;
-        __syncthreads();
+        lds_barrier();
         pacc += side == 0 ? stage_rows<0>(op, col, half, pre) : stage_rows<1>(op, col, half, pre);
         if (last) {
             const float tot = pacc + xor1(pacc);          // p over the chunk's frames
             if (half == 0) psum[side][col] = tot;
         }
-        __syncthreads();
+        lds_barrier();
         // Four K steps of 16 slots (the scheduling barrier keeps each step's
-        // operand reads next to its contractions: fewer live registers).
+        // operand reads next to its contractions: fewer live registers).  The
+        // wave runs them at raised priority, so that the matrix pipe is fed
+        // while the other wave of the SIMD uses the vector ALU.
+        __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int wo = 8 * ks + 4 * kh;                // first word of this lane's 8 slots
@@ -616,6 +628,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
             const bf16x8_t xb = single_term<1>(psum[1][rowL], kh == 0);
             d[4] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa, xb, d[4], 0, 0, 0);
         }
+        __builtin_amdgcn_s_setprio(0);
         // Next batch's loads overlap the epilogue.
         if (b + 1 < n_batches) fetch(b + 1);
         if (!last) continue;
@@ -766,9 +779,9 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16(BatchArgs p) {
         for (int j = 0; j < 2 * kPairs; ++j) amax = fmaxf(amax, fmaxf(fabsf(pre[j].x), fabsf(pre[j].y)));
         amax = fmaxf(amax, __shfl_xor(amax, 1));
         if (fbi == 0) pacc = 0.f;
-        __syncthreads();
+        lds_barrier();
         if (fbi == 0 && half == 0) sc2[side][col] = pow2_above(amax) * pow2_above(amax);
-        __syncthreads();
+        lds_barrier();
         const float s2 = sc2[side][col];
         const float inv_s = 1.0f / sqrtf(s2);       // exact: s is a power of two
         const float inv_s2 = 1.0f / s2;
@@ -789,7 +802,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16(BatchArgs p) {
                 put_pair_f16<1>(op[2 * kTile + col], f, P0 * inv_s2, P1 * inv_s2);
             }
         }
-        __syncthreads();
+        lds_barrier();
         {
             const int koff = lg * 8;
             const int rk = w * 16 + li;
@@ -814,7 +827,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16(BatchArgs p) {
         if (fbi != per_chunk - 1) continue;
 
         psum[side][half][col] = pacc;
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int kl = w * 16 + 4 * lg + e;
@@ -909,10 +922,10 @@ __global__ __launch_bounds__(kS4XThreads, 2) void k_s4_cross(BatchArgs p) {
 #pragma unroll 1
         for (int fb = 0; fb < v.m; fb += kFrameBatch) {
             const int nf = min(kFrameBatch, v.m - fb);
-            __syncthreads();
+            lds_barrier();
             for (int fr = half; fr < nf; fr += 2)
                 sv[arr][fr][col] = live ? src[fbase + (int64_t)(fb + fr) * v.K] : make_float2(0.f, 0.f);
-            __syncthreads();
+            lds_barrier();
 #pragma unroll 1
             for (int fr = 0; fr < nf; ++fr) {
                 float2 a[2], b[2], cc[2], d[2], E[2], F[2];
