@@ -439,10 +439,14 @@ __global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(BatchArgs p) {
 // of bank conflicts at that stride).  Wave w owns the 32 x 32 quadrant
 // (k0 + 32 (w / 2), l0 + 32 (w % 2)) of the tile with five accumulators X, U,
 // V, Y, M4, so all five sums of a grid point sit in the same lane and register
-// and the k-statistic combination runs there.  The term -gamma p_k p_l of the
-// combination enters the M4 contraction as one more K step (the split terms of
-// -gamma p_k and p_l in slots 0..5), so per grid point and chunk the epilogue
-// is v = M4' - 2 gamma (X^2 + Y^2 + U^2 + V^2) plus the FP64 chunk sums.
+// and the k-statistic combination runs there.  The kernel accumulates the
+// k-statistic numerator with integer coefficients, exact in FP32,
+//   v = m(m+1) M4 - (m-1) (p_k p_l + 2 (X^2 + Y^2 + U^2 + V^2)),
+// (the finalize scale carries 1 / (m(m+1))): a rounded gamma = (m-1)/(m(m+1))
+// would bias every chunk alike.  The k-side P row holds m(m+1) P, and the term
+// -(m-1) p_k p_l enters the M4 contraction as one more K step (the split terms
+// of -(m-1) p_k and p_l in slots 0..5), so per grid point and chunk the
+// epilogue is v = M4' - 2 (m-1) (X^2 + Y^2 + U^2 + V^2) plus the FP64 chunk sums.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float floatx2_t __attribute__((ext_vector_type(2)));
@@ -496,9 +500,11 @@ __device__ __forceinline__ float xor1(float v) {        // value of the neighbou
 }
 
 // Stage one batch of this thread's frame slots (frames half + 2j) of column
-// `col` into the operand rows of its side; returns the sum of P over them.
+// `col` into the operand rows of its side (the P row scaled by pscale);
+// returns the sum of P over them.
 template <int SIDE>
-__device__ __forceinline__ float stage_rows(uint32_t (*op)[kOpDw], int col, int half, const float2 (&pre)[kMfmaFrames / 2]) {
+__device__ __forceinline__ float stage_rows(uint32_t (*op)[kOpDw], int col, int half, const float2 (&pre)[kMfmaFrames / 2],
+                                            float pscale) {
     float pa = 0.f;
 #pragma unroll
     for (int j = 0; j < kMfmaFrames / 2; ++j) {
@@ -509,7 +515,7 @@ __device__ __forceinline__ float stage_rows(uint32_t (*op)[kOpDw], int col, int 
         uint32_t a0, a1, a2, b0, b1, b2, e0, e1, e2;
         split_words<SIDE>(re, a0, a1, a2);
         split_words<SIDE>(im, b0, b1, b2);
-        split_words<SIDE>(P, e0, e1, e2);
+        split_words<SIDE>(P * pscale, e0, e1, e2);
         uint32_t* wr = &op[col][3 * f];
         uint32_t* wi = &op[kTile + col][3 * f];
         uint32_t* wp = &op[2 * kTile + col][3 * f];
@@ -546,8 +552,9 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
         row[3 * kMfmaFrames] = 0u;
         row[3 * kMfmaFrames + 1] = 0u;
     }
-    const float gamma = (float)p.gamma;
-    const float m2g = -2.0f * gamma;
+    const float cm1 = (float)(v.m * (v.m + 1));         // m(m+1), exact
+    const float cm2 = (float)(v.m - 1);                 // m-1
+    const float m2c = -2.0f * cm2;
 
     Item it;
     while (next_item<kTile, 2>(p, bk, it)) {
@@ -586,7 +593,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
         const bool first = fbi == 0, last = fbi == per_chunk - 1;
         if (first) pacc = 0.f;
         lds_barrier();
-        pacc += side == 0 ? stage_rows<0>(op, col, half, pre) : stage_rows<1>(op, col, half, pre);
+        pacc += side == 0 ? stage_rows<0>(op, col, half, pre, cm1) : stage_rows<1>(op, col, half, pre, 1.0f);
         if (last) {
             const float tot = pacc + xor1(pacc);          // p over the chunk's frames
             if (half == 0) psum[side][col] = tot;
@@ -623,8 +630,8 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
             __builtin_amdgcn_sched_barrier(0);
         }
         if (last) {
-            // M4 <- M4 - gamma p_k p_l, as one more contraction step
-            const bf16x8_t xa = single_term<0>(-gamma * psum[0][rowK], kh == 0);
+            // M4' = m(m+1) M4 - (m-1) p_k p_l: one more contraction step
+            const bf16x8_t xa = single_term<0>(-cm2 * psum[0][rowK], kh == 0);
             const bf16x8_t xb = single_term<1>(psum[1][rowL], kh == 0);
             d[4] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa, xb, d[4], 0, 0, 0);
         }
@@ -639,7 +646,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
         for (int r = 0; r < 16; ++r) {
             const float X = d[0][r], U = d[1][r], V = d[2][r], Y = d[3][r];
             const float sq = fmaf(X, X, fmaf(Y, Y, fmaf(U, U, V * V)));
-            const double val = (double)fmaf(m2g, sq, d[4][r]);
+            const double val = (double)fmaf(m2c, sq, d[4][r]);
             acc[r][0] += val;
             acc[r][1] = fma(val, val, acc[r][1]);
         }
