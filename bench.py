@@ -27,6 +27,11 @@ N, NF, M = 8192, 2048, 10
 SEED = 3
 WORKLOAD = "ar2-chi2 1ch 2^28 f32, N=8192, N_f=2048, m=10, acG 0.14, S2+S3+S4"
 
+# Calibrated HBM bytes of the S3 kernel at this workload (rocprofv3 FETCH_SIZE /
+# WRITE_SIZE); reported as roofline.traffic only while the kernel's source is
+# the one the counters were taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_s3_ar2_2p28_n8192_nf2048_traffic.json")
+
 PEAK_HBM_GBS = 8000.0
 # FP32 FMA on the vector ALUs without packed-FP32 instructions:
 # 256 CUs x 64 lanes x 2 flop x 2.4 GHz.  (The vendor's 157.3 TFLOP/s assumes
@@ -43,6 +48,20 @@ def s3_flops_per_launch(n_frames: int, nf: int) -> float:
     a_k a_l conj(a_{k+l}) accumulated per frame and grid point k <= l
     (14 flops: 2 mul + 6 FMA)."""
     return 14.0 * (nf * (nf + 1) / 2) * n_frames
+
+
+def s3_traffic():
+    """Stored S3 HBM bytes per launch, or None when absent or stale."""
+    try:
+        from paper_2505_01231_amd.profile_summary import s3_source_digest
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+        if t.get("source_sha256") != s3_source_digest():
+            log("stored S3 traffic counters are stale (kernel source changed): traffic = null")
+            return None
+        return t["hbm_read_bytes_per_launch"] + t["hbm_write_bytes_per_launch"]
+    except (OSError, ValueError, KeyError, RuntimeError):
+        return None
 
 
 def cpu_baseline(z, seconds_target=15.0):
@@ -279,8 +298,12 @@ def main(argv=None):
     s4_info = {"avg_launch_ms": s4_avg_ms,
                "useful_tflops": 10.0 * (NF * (NF + 1) / 2) * n_frames / (s4_avg_ms * 1e-3) / 1e12}
     if args.precision != "fp32":
-        # 64 x 64 tile, 4 waves x 4 blocks x 5 sums x 2 (K = 64) MFMA 16x16x32 per chunk
-        mfma_flops = n_tiles * n_chunks * 4 * 4 * 5 * 2 * (16 * 16 * 32 * 2)
+        if args.precision == "bf16x3":
+            # per 64 x 64 tile and chunk: 4 waves x (4 K steps x 5 sums + 1) MFMA 32x32x16
+            mfma_flops = n_tiles * n_chunks * 4 * 21 * (32 * 32 * 16 * 2)
+        else:
+            # per 64 x 64 tile and chunk: 4 waves x 4 blocks x 5 sums MFMA 16x16x32 (one K step)
+            mfma_flops = n_tiles * n_chunks * 4 * 4 * 5 * (16 * 16 * 32 * 2)
         s4_info.update({"mfma_executed_tflops": mfma_flops / (s4_avg_ms * 1e-3) / 1e12,
                         "mfma_peak_tflops": 2500.0,
                         "mfma_frac_of_peak": mfma_flops / (s4_avg_ms * 1e-3) / 2.5e15})
@@ -314,7 +337,7 @@ def main(argv=None):
             "peak": PEAK_FP32_VALU_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VALU_TFLOPS,
-            "traffic": None,
+            "traffic": s3_traffic(),
             "avg_launch_ms": s3_avg_ms,
             "flops_per_launch": s3_flops_per_launch(n_frames, NF),
         },

@@ -518,12 +518,18 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     }
 
     // Output tiles: upper triangle (kt <= lt) for symmetric spectra, all otherwise.
+    // Tiles in 8 x 8 blocks: the consecutive tiles that one XCD processes at a
+    // time then share their k and l columns (and half of the k + l range) in
+    // that XCD's L2, instead of spanning whole tile rows.
     auto make_tiles = [](int T, std::vector<int2>& sym, std::vector<int2>& full) {
-        for (int kt = 0; kt < T; ++kt)
-            for (int lt = 0; lt < T; ++lt) {
-                full.push_back(make_int2(kt, lt));
-                if (kt <= lt) sym.push_back(make_int2(kt, lt));
-            }
+        constexpr int G = 8;
+        for (int bk = 0; bk < T; bk += G)
+            for (int bl = 0; bl < T; bl += G)
+                for (int kt = bk; kt < std::min(T, bk + G); ++kt)
+                    for (int lt = bl; lt < std::min(T, bl + G); ++lt) {
+                        full.push_back(make_int2(kt, lt));
+                        if (kt <= lt) sym.push_back(make_int2(kt, lt));
+                    }
     };
     p->T = (Nf + ps::kTile - 1) / ps::kTile;
     p->TX = (Nf + ps::kTileX - 1) / ps::kTileX;

@@ -159,17 +159,38 @@ hipError_t launch_n(const FftArgs& a, hipStream_t st) {
 }
 
 // a_k(f) -= (1/m) sum_{f' in chunk} a_k(f'), in place, one thread per (chunk, k).
+// Chunks of up to kCentreRegs frames stay in registers between the mean and
+// the subtraction, so each coefficient is read from HBM once.
+constexpr int kCentreRegs = 16;
+
 __global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64_t coef_cs, int K, int m) {
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= K) return;
     float2* p = coef + blockIdx.z * coef_cs + (int64_t)blockIdx.y * m * K + k;
+    const float inv = 1.0f / (float)m;
+    if (m <= kCentreRegs) {
+        float2 v[kCentreRegs];
+        float sr = 0.f, si = 0.f;
+#pragma unroll
+        for (int f = 0; f < kCentreRegs; ++f) {
+            if (f < m) {
+                v[f] = p[(int64_t)f * K];
+                sr += v[f].x;
+                si += v[f].y;
+            }
+        }
+        const float mr = sr * inv, mi = si * inv;
+#pragma unroll
+        for (int f = 0; f < kCentreRegs; ++f)
+            if (f < m) p[(int64_t)f * K] = make_float2(v[f].x - mr, v[f].y - mi);
+        return;
+    }
     float sr = 0.f, si = 0.f;
     for (int f = 0; f < m; ++f) {
         const float2 v = p[(int64_t)f * K];
         sr += v.x;
         si += v.y;
     }
-    const float inv = 1.0f / (float)m;
     const float mr = sr * inv, mi = si * inv;
     for (int f = 0; f < m; ++f) {
         const float2 v = p[(int64_t)f * K];
