@@ -4,143 +4,244 @@
 //
 //   a_k = sum_{i<N} g_i z_i exp(+2 pi j i k / N),  k < K        (dt folded into the output scale)
 //
-// One 256-thread block transforms one frame; the frames of every record of a
-// batch form one launch (the block finds its record by binary search over the
-// records' first global frame).  The N real samples are packed as
-// M = N/2 complex points x_n = w_{2n} + j w_{2n+1} (w = g z), transformed by a
-// radix-4 (plus one radix-2) Stockham FFT in LDS with the +j sign, and
-// unpacked: with X the M-point transform,
+// The N real samples of a frame are packed as M = N/2 complex points
+// x_n = w_{2n} + j w_{2n+1} (w = g z), transformed by a Stockham FFT with the
+// +j sign, and unpacked: with X the M-point transform,
 //   E_k = (X_k + conj X_{M-k}) / 2,  O_k = (X_k - conj X_{M-k}) / (2j),
 //   a_k = E_k + exp(+2 pi j k / N) O_k   (indices of X taken mod M).
-// Twiddles come from a table exp(+2 pi j t / N) computed in FP64 on the host.
-// The stage streams N samples in and K complex values out per frame: it is
-// bound by HBM bandwidth, not arithmetic.
+// T = M/16 threads per frame each hold 16 points in registers; the passes are
+// radix 16 (one radix-2/4/8 pass when log2 M is not a multiple of 4), so a
+// 4096-point transform takes three passes through LDS.  The first pass reads
+// the windowed samples from global memory straight into registers.  LDS holds
+// X with one padding entry per 16 (index i at i + i/16), which keeps the
+// first pass's 16-strided writes free of bank conflicts.  A 256-thread block
+// transforms 256/T frames.  Twiddles come from a table exp(+2 pi j t / N)
+// computed in FP64 on the host.  The stage streams N samples in and K complex
+// values out per frame: it is bound by HBM bandwidth, not arithmetic.
 #include "ps_internal.h"
 
 namespace ps {
 namespace {
 
 constexpr int kFftThreads = 256;
+constexpr int kFftLds = kFftThreads * 17;      // float2 entries: 4096 points + padding per block
 
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+__device__ __forceinline__ float2 mulj(float2 a) { return make_float2(-a.y, a.x); }   // j a
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+
+// 4-point DFT with the +j sign on v[o], v[o+S], v[o+2S], v[o+3S], in place, natural order.
+template <int S>
+__device__ __forceinline__ void dft4(float2* v, int o) {
+    const float2 a = v[o], b = v[o + S], c = v[o + 2 * S], d = v[o + 3 * S];
+    const float2 s02 = cadd(a, c), d02 = csub(a, c), s13 = cadd(b, d), d13 = csub(b, d);
+    v[o] = cadd(s02, s13);
+    v[o + S] = cadd(d02, mulj(d13));
+    v[o + 2 * S] = csub(s02, s13);
+    v[o + 3 * S] = csub(d02, mulj(d13));
+}
+template <int S>
+__device__ __forceinline__ void dft2(float2* v, int o) {
+    const float2 a = v[o], b = v[o + S];
+    v[o] = cadd(a, b);
+    v[o + S] = csub(a, b);
+}
+
+// exp(+2 pi j q s / 16) for q, s < 4
+__device__ __forceinline__ float2 w16(int qs) {
+    constexpr float c1 = 0.92387953251128674f, s1 = 0.38268343236508978f, h = 0.70710678118654752f;
+    switch (qs) {
+        case 1: return make_float2(c1, s1);
+        case 2: return make_float2(h, h);
+        case 3: return make_float2(s1, c1);
+        case 4: return make_float2(0.f, 1.f);
+        case 6: return make_float2(-h, h);
+        case 9: return make_float2(-c1, -s1);
+        default: return make_float2(1.f, 0.f);
+    }
+}
+
+// R-point DFT (+j sign) of v[o .. o+R); output k is left at v[o + opos<R>(k)].
+template <int R>
+__device__ __forceinline__ void dft(float2* v, int o) {
+    if constexpr (R == 16) {
+        // n = q + 4 r, k = s + 4 t: DFT4 over r, twiddle exp(2 pi j q s / 16), DFT4 over q
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dft4<4>(v, o + q);
+#pragma unroll
+        for (int q = 1; q < 4; ++q)
+#pragma unroll
+            for (int s2 = 1; s2 < 4; ++s2) v[o + q + 4 * s2] = cmul(v[o + q + 4 * s2], w16(q * s2));
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) dft4<1>(v, o + 4 * s2);
+    } else if constexpr (R == 8) {
+        // n = q + 2 r, k = s + 4 t: DFT4 over r, twiddle exp(2 pi j q s / 8), DFT2 over q
+        dft4<2>(v, o);
+        dft4<2>(v, o + 1);
+        constexpr float h = 0.70710678118654752f;
+        v[o + 3] = cmul(v[o + 3], make_float2(h, h));
+        v[o + 5] = mulj(v[o + 5]);
+        v[o + 7] = cmul(v[o + 7], make_float2(-h, h));
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) dft2<1>(v, o + 2 * s2);
+    } else if constexpr (R == 4) {
+        dft4<1>(v, o);
+    } else {
+        dft2<1>(v, o);
+    }
+}
+template <int R>
+__device__ __forceinline__ constexpr int opos(int k) {
+    return R == 16 ? 4 * (k & 3) + (k >> 2) : R == 8 ? 2 * (k & 3) + (k >> 2) : k;
+}
+
+// Pair of consecutive samples (2n, 2n+1) as float2: one vector load when the
+// frame is aligned for it, two scalar loads otherwise.
+template <typename T>
+__device__ __forceinline__ float2 sample_pair(const T* __restrict__ xf, int n, bool vec);
+template <>
+__device__ __forceinline__ float2 sample_pair<float>(const float* __restrict__ xf, int n, bool vec) {
+    if (vec) return reinterpret_cast<const float2*>(xf)[n];
+    return make_float2(xf[2 * n], xf[2 * n + 1]);
+}
+template <>
+__device__ __forceinline__ float2 sample_pair<double>(const double* __restrict__ xf, int n, bool vec) {
+    if (vec) {
+        const double2 d = reinterpret_cast<const double2*>(xf)[n];
+        return make_float2((float)d.x, (float)d.y);
+    }
+    return make_float2((float)xf[2 * n], (float)xf[2 * n + 1]);
+}
+template <>
+__device__ __forceinline__ float2 sample_pair<int16_t>(const int16_t* __restrict__ xf, int n, bool vec) {
+    if (vec) {
+        const short2 d = reinterpret_cast<const short2*>(xf)[n];
+        return make_float2((float)d.x, (float)d.y);
+    }
+    return make_float2((float)xf[2 * n], (float)xf[2 * n + 1]);
+}
 
 template <typename T>
-__device__ __forceinline__ void load_windowed(float2* s, const T* __restrict__ xf, const float* __restrict__ g,
-                                              int M, int tid) {
-    for (int n = tid; n < M; n += kFftThreads) {
-        const float w0 = g[2 * n] * static_cast<float>(xf[2 * n]);
-        const float w1 = g[2 * n + 1] * static_cast<float>(xf[2 * n + 1]);
-        s[n] = make_float2(w0, w1);
+__device__ __forceinline__ void load_first(float2 (&v)[16], const T* __restrict__ xf, const float* __restrict__ g,
+                                           int t, int Tn, bool live) {
+    const bool vec = (reinterpret_cast<uintptr_t>(xf) % (2 * sizeof(T))) == 0;
+    const float2* __restrict__ g2 = reinterpret_cast<const float2*>(g);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int n = t + r * Tn;
+        if (live) {
+            const float2 x = sample_pair(xf, n, vec), w = g2[n];
+            v[r] = make_float2(w.x * x.x, w.y * x.y);
+        } else {
+            v[r] = make_float2(0.f, 0.f);
+        }
     }
+}
+
+// Twiddles of a Stockham pass of radix R and span Ns (see fft_pass) for the
+// butterflies of thread t: w[b R + r] = exp(+2 pi j r k / (R Ns)), k = j mod Ns.
+template <int LOG2M, int R>
+__device__ __forceinline__ void pass_twiddles(float2 (&w)[16], int t, int Ns, const float2* __restrict__ tw) {
+    constexpr int M = 1 << LOG2M, Tn = M / 16, B = 16 / R, N = 2 * M;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int k = (t + b * Tn) & (Ns - 1);
+        const int step = k * (N / (R * Ns));
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[b * R + r] = tw[r * step];
+    }
+}
+
+// Stockham pass of radix R and span Ns over the M points of one frame held in
+// LDS at s: butterfly j reads x[j + r M/R], twiddles by exp(+2 pi j r k / (R Ns))
+// with k = j mod Ns (w, from pass_twiddles), and writes y[(j - k) R + k + r Ns].
+// Thread t owns the 16/R butterflies j = t + b T.  FROM_REGS: the inputs are
+// already in v (first pass, Ns = 1, natural order).
+template <int LOG2M, int R, bool FROM_REGS>
+__device__ __forceinline__ void fft_pass(float2 (&v)[16], const float2 (&w)[16], float2* s, int t, int Ns) {
+    constexpr int M = 1 << LOG2M, Tn = M / 16, B = 16 / R;
+    if (!FROM_REGS) {
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b * R + r] = s[pad(t + b * Tn + r * (M / R))];
+        lds_barrier();
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], w[b * R + r]);
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) dft<R>(v, b * R);
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int j = t + b * Tn, k = j & (Ns - 1);
+        const int base = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[pad(base + r * Ns)] = v[b * R + opos<R>(r)];
+    }
+    lds_barrier();
 }
 
 template <int LOG2N>
 __global__ __launch_bounds__(kFftThreads) void k_window_rfft(FftArgs a) {
     constexpr int N = 1 << LOG2N;
-    constexpr int M = N / 2;
     constexpr int LOG2M = LOG2N - 1;
-    __shared__ float2 s[M];
+    constexpr int M = N / 2, Tn = M / 16, F = kFftThreads / Tn;
+    constexpr int P16 = LOG2M / 4, REM = LOG2M % 4;
+    // radices of the passes after the first (0: none)
+    constexpr int R2 = P16 >= 2 ? 16 : (REM ? (1 << REM) : 0);
+    constexpr int R3 = P16 >= 3 ? 16 : (P16 == 2 && REM ? (1 << REM) : 0);
+    static_assert(P16 <= 3 && !(P16 == 3 && REM), "frame length up to 8192");
+    __shared__ float2 lds[kFftLds];
 
-    const int64_t gf = a.g_lo + blockIdx.x;     // global frame
+    const int fl = threadIdx.x / Tn, t = threadIdx.x % Tn;
+    float2* s = lds + fl * (M + M / 16);
+    const int64_t gf = a.g_lo + (int64_t)blockIdx.x * F + fl;     // global frame
+    const bool live = gf < a.g_hi;
     const int c = blockIdx.y;
-    RecDesc r = a.single;
-    if (a.recs) {
+    RecDesc rec = a.single;
+    if (a.recs && live) {
         int lo = 0, hi = a.n_recs - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (a.recs[mid].frame0 <= gf) lo = mid;
             else hi = mid - 1;
         }
-        r = a.recs[lo];
+        rec = a.recs[lo];
     }
-    const int64_t off = c * r.chan_stride + (gf - r.frame0) * N;
-    const int tid = threadIdx.x;
+    const int64_t off = c * rec.chan_stride + (gf - rec.frame0) * N;
     const float* __restrict__ g = a.g;
     const float2* __restrict__ tw = a.tw;
-    if (r.dtype == 0) load_windowed(s, static_cast<const float*>(r.data) + off, g, M, tid);
-    else if (r.dtype == 1) load_windowed(s, static_cast<const double*>(r.data) + off, g, M, tid);
-    else load_windowed(s, static_cast<const int16_t*>(r.data) + off, g, M, tid);
-    __syncthreads();
 
-    // Radix-4 Stockham passes: span Ns = 1, 4, 16, ...; butterfly j reads
-    // x[j + r M/4], twiddles by exp(+2 pi j r k / (4 Ns)) with k = j mod Ns,
-    // applies the 4-point DFT (+j) and writes to (j - k) * 4 + k + r Ns.
-    constexpr int B4 = M / 4;
-    constexpr int P4 = (B4 + kFftThreads - 1) / kFftThreads;
-    int Ns = 1;
-#pragma unroll 1
-    for (int pass = 0; pass < LOG2M / 2; ++pass) {
-        float2 v[P4][4];
-#pragma unroll
-        for (int q = 0; q < P4; ++q) {
-            const int j = tid + q * kFftThreads;
-            if (j < B4) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[q][r] = s[j + r * B4];
-            }
-        }
-        __syncthreads();
-        const int step = N / (Ns * 4);
-#pragma unroll
-        for (int q = 0; q < P4; ++q) {
-            const int j = tid + q * kFftThreads;
-            if (j < B4) {
-                const int k = j & (Ns - 1);
-                const float2 v0 = v[q][0];
-                const float2 v1 = cmul(v[q][1], tw[k * step]);
-                const float2 v2 = cmul(v[q][2], tw[2 * k * step]);
-                const float2 v3 = cmul(v[q][3], tw[3 * k * step]);
-                const float2 s02 = make_float2(v0.x + v2.x, v0.y + v2.y);
-                const float2 d02 = make_float2(v0.x - v2.x, v0.y - v2.y);
-                const float2 s13 = make_float2(v1.x + v3.x, v1.y + v3.y);
-                const float2 d13 = make_float2(v1.x - v3.x, v1.y - v3.y);
-                // y1 = d02 + j d13, y3 = d02 - j d13 (the +j 4-point kernel)
-                const int base = (j - k) * 4 + k;
-                s[base] = make_float2(s02.x + s13.x, s02.y + s13.y);
-                s[base + Ns] = make_float2(d02.x - d13.y, d02.y + d13.x);
-                s[base + 2 * Ns] = make_float2(s02.x - s13.x, s02.y - s13.y);
-                s[base + 3 * Ns] = make_float2(d02.x + d13.y, d02.y - d13.x);
-            }
-        }
-        __syncthreads();
-        Ns *= 4;
-    }
-    if constexpr (LOG2M & 1) {
-        constexpr int B2 = M / 2;
-        constexpr int P2 = (B2 + kFftThreads - 1) / kFftThreads;
-        float2 v[P2][2];
-#pragma unroll
-        for (int q = 0; q < P2; ++q) {
-            const int j = tid + q * kFftThreads;
-            if (j < B2) {
-                v[q][0] = s[j];
-                v[q][1] = s[j + B2];
-            }
-        }
-        __syncthreads();
-        const int step = N / (Ns * 2);
-#pragma unroll
-        for (int q = 0; q < P2; ++q) {
-            const int j = tid + q * kFftThreads;
-            if (j < B2) {
-                const int k = j & (Ns - 1);
-                const float2 v0 = v[q][0];
-                const float2 v1 = cmul(v[q][1], tw[k * step]);
-                const int base = (j - k) * 2 + k;
-                s[base] = make_float2(v0.x + v1.x, v0.y + v1.y);
-                s[base + Ns] = make_float2(v0.x - v1.x, v0.y - v1.y);
-            }
-        }
-        __syncthreads();
-    }
+    // Each pass's twiddles are requested one pass ahead of their use.
+    float2 v[16], w2[16], w3[16];
+    if constexpr (R2 > 0) pass_twiddles<LOG2M, R2>(w2, t, 16, tw);
+    if (rec.dtype == 0) load_first(v, static_cast<const float*>(rec.data) + off, g, t, Tn, live);
+    else if (rec.dtype == 1) load_first(v, static_cast<const double*>(rec.data) + off, g, t, Tn, live);
+    else load_first(v, static_cast<const int16_t*>(rec.data) + off, g, t, Tn, live);
 
+    fft_pass<LOG2M, 16, true>(v, w2, s, t, 1);
+    if constexpr (R3 > 0) pass_twiddles<LOG2M, R3>(w3, t, 16 * R2, tw);
+    if constexpr (R2 > 0) fft_pass<LOG2M, R2, false>(v, w2, s, t, 16);
+    if constexpr (R3 > 0) fft_pass<LOG2M, R3, false>(v, w3, s, t, 16 * R2);
+
+    if (!live) return;
+    // K <= M + 1: at most KMAX outputs per thread, unrolled so that their
+    // twiddle loads are issued together.
+    constexpr int KMAX = (M + 1 + Tn - 1) / Tn;
     const int K = a.K;
     float2* o = a.out + c * a.out_chan_stride + (gf - a.out_g0) * K;
-    for (int k = tid; k < K; k += kFftThreads) {
-        const float2 xk = s[k & (M - 1)];
-        const float2 xm = s[(M - k) & (M - 1)];
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        const int k = t + i * Tn;
+        if (k >= K) break;
+        const float2 xk = s[pad(k & (M - 1))];
+        const float2 xm = s[pad((M - k) & (M - 1))];
         const float er = 0.5f * (xk.x + xm.x);
         const float ei = 0.5f * (xk.y - xm.y);
         const float orr = 0.5f * (xk.y + xm.y);   // (X_k - conj X_{M-k}) * (-j/2)
@@ -152,8 +253,9 @@ __global__ __launch_bounds__(kFftThreads) void k_window_rfft(FftArgs a) {
 
 template <int LOG2N>
 hipError_t launch_n(const FftArgs& a, hipStream_t st) {
+    constexpr int M = (1 << LOG2N) / 2, F = kFftThreads / (M / 16);
     const int64_t n = a.g_hi - a.g_lo;
-    dim3 grid((unsigned)n, a.n_channels);
+    dim3 grid((unsigned)((n + F - 1) / F), a.n_channels);
     k_window_rfft<LOG2N><<<grid, kFftThreads, 0, st>>>(a);
     return hipGetLastError();
 }

@@ -180,6 +180,15 @@ __device__ __forceinline__ void slot_range(const Sched& sc, int64_t t, int64_t& 
     n = j1 - j0 + 1;
 }
 
+// Workgroup barrier that orders LDS accesses only.  The threads of a block
+// share data through LDS alone, so outstanding global loads (prefetches) may
+// stay in flight across it; __syncthreads() would wait for them.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Segment lookup shared by the kernels: the last segment with item0 <= v.
 __device__ __forceinline__ int find_seg(const Seg* segs, int n, int64_t v) {
     int lo = 0, hi = n - 1;

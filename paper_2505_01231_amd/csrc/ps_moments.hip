@@ -31,15 +31,6 @@
 namespace ps {
 namespace {
 
-// Workgroup barrier that orders LDS accesses only.  The threads of a block
-// share data through LDS alone, so outstanding global loads (the next batch's
-// prefetch) may stay in flight across it; __syncthreads() would wait for them.
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 // A block's share of its segment.
 struct Block {
     const Seg* s;

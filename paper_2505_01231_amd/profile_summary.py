@@ -43,7 +43,7 @@ def s3_source_digest() -> str:
         (api, r"auto make_tiles = \[\]\(.*?\n    \};\n"),
         (api, r"int64_t units_per_block\(.*?\n\}\n"),
         (api, r"int32_t seg_blocks\(.*?\n\}\n"),
-        (src, r"__device__ __forceinline__ void lds_barrier\(\) \{.*?\n\}\n"),
+        (inc, r"__device__ __forceinline__ void lds_barrier\(\) \{.*?\n\}\n"),
         (src, r"__device__ __forceinline__ bool resolve_block\(.*?\n\}\n"),
         (src, r"__device__ __forceinline__ bool next_item\(.*?\n\}\n"),
         (src, r"template <int FB>\n__global__ __launch_bounds__\(kS3Threads, 2\) void k_s3\(BatchArgs p\) \{.*?\n\}\n"),
