@@ -167,8 +167,8 @@ struct SegTable {
 // (per-chunk schedule).
 struct Group {
     int rec = -1;           // record of a per-chunk group
-    SegTable s2, s3, s4s, s4x, f2, f3, f4, m3, m4;
-    SegTable* all[9] = {&s2, &s3, &s4s, &s4x, &f2, &f3, &f4, &m3, &m4};
+    SegTable s2, s3, s4s, s4x, f2, f3, f4;
+    SegTable* all[7] = {&s2, &s3, &s4s, &s4x, &f2, &f3, &f4};
 };
 
 struct Batch {
@@ -280,7 +280,6 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 sg.ncomp = 4;
                 G.s3.add(sg, sg.blocks);
                 G.f3.add(sg, (int64_t)sg.n_tiles * (TT / 256));
-                if (sym) G.m3.add(sg, (int64_t)((Nf + 31) / 32) * ((Nf + 31) / 32));
             }
             for (int i = 0; i < p->n4(); ++i) {
                 ps::Seg sg = base;
@@ -299,7 +298,6 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 sg.sym = sym;
                 (single ? G.s4s : G.s4x).add(sg, sg.blocks);
                 G.f4.add(sg, (int64_t)sg.n_tiles * ((single ? TT : TX) / 256));
-                if (sym) G.m4.add(sg, (int64_t)((Nf + 31) / 32) * ((Nf + 31) / 32));
             }
         }
     }
@@ -748,9 +746,7 @@ ps_status launch_finalize(ps_plan_t p, const Batch& B, const Group& G, char* ws,
     StageTimer t(p, st, 5);
     if (G.f2.n_items) PS_HIP(ps::launch_finalize_vec(fin_args(p, B, G.f2, ws, tab), st));
     if (G.f3.n_items) PS_HIP(ps::launch_finalize_grid(fin_args(p, B, G.f3, ws, tab), st));
-    if (G.m3.n_items) PS_HIP(ps::launch_mirror(fin_args(p, B, G.m3, ws, tab), st));
     if (G.f4.n_items) PS_HIP(ps::launch_finalize_grid(fin_args(p, B, G.f4, ws, tab), st));
-    if (G.m4.n_items) PS_HIP(ps::launch_mirror(fin_args(p, B, G.m4, ws, tab), st));
     return PS_OK;
 }
 

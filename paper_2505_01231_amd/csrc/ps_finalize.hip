@@ -61,34 +61,40 @@ __global__ __launch_bounds__(256) void k_finalize_vec(FinalizeArgs p) {
     }
 }
 
-// S3 / S4: one block per (record, combination, tile, 256 grid points of the
-// tile): adds the tile's slots in slot order and writes its grid points (all of
-// them, or only k <= l for symmetric spectra) with coalesced accesses.
+// S3 / S4: one block per (record, combination, tile, 16 x 16 sub-block of the
+// tile): adds the tile's slots in slot order and writes the sub-block's grid
+// points (all of them, or only k <= l for symmetric spectra); a symmetric
+// spectrum also gets its mirror (l, k) <- (k, l), k < l, written through an
+// LDS transpose so that both writes are row-contiguous.
 __global__ __launch_bounds__(256) void k_finalize_tiles(FinalizeArgs p) {
+    __shared__ double2 sm[16][17], se[16][17];
     const int64_t x = blockIdx.x;
     if (x >= p.n_items) return;
     const Seg& sg = p.segs[find_seg(p.segs, p.n_segs, x)];
     const int E = sg.tiles >= kSym32 ? kTileX : kTile;
     const int TT = E * E;
-    const int per_tile = TT / 256;
+    const int sub = E / 16, per_tile = sub * sub;
     const int64_t local = x - sg.item0;
     const int tile = (int)(local / per_tile);
+    const int sb = (int)(local - (int64_t)tile * per_tile);
     const int2 t = p.tt.t[sg.tiles][tile];
-    const int k0 = t.x * E, l0 = t.y * E;
+    const int kb = t.x * E + 16 * (sb / sub), lb = t.y * E + 16 * (sb % sub);   // sub-block origin
+    const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
     const double np = (double)sg.n_chunks;
     const int ncomp = sg.ncomp;
     int64_t s0 = 0, ns = 0;
     if (sg.n_chunks > 0) slot_range(Sched{sg.n_tiles, sg.n_chunks, sg.blocks}, tile, s0, ns);
-    {
-        const int idx = (int)(local - (int64_t)tile * per_tile) * 256 + threadIdx.x;
-        const int k = k0 + idx / E, l = l0 + idx % E;
-        if (k >= p.Nf || l >= p.Nf || (sg.sym && k > l)) return;
+
+    const int k = kb + i, l = lb + j;
+    const bool valid = k < p.Nf && l < p.Nf && !(sg.sym && k > l);
+    double mr = 0.0, sr = 0.0, mi = 0.0, si = 0.0;
+    if (valid) {
+        const int idx = (k - t.x * E) * E + (l - t.y * E);
         double s[4] = {0, 0, 0, 0};
         for (int64_t slot = s0; slot < s0 + ns; ++slot) {
             const double* q = p.part + sg.part + slot * ncomp * TT + idx;
             for (int c = 0; c < ncomp; ++c) s[c] += q[c * TT];
         }
-        double mr, sr, mi = 0.0, si = 0.0;
         if (ncomp == 4) {
             mean_sigma(s[0], s[2], np, sg.scale, mr, sr);
             mean_sigma(s[1], s[3], np, sg.scale, mi, si);
@@ -107,38 +113,25 @@ __global__ __launch_bounds__(256) void k_finalize_tiles(FinalizeArgs p) {
             sg.err[o + 1] = si;
         }
     }
-}
-
-// Symmetric spectra: copy (k, l) -> (l, k) for k < l through an LDS transpose
-// of 32 x 32 blocks of complex (16-byte) values; one block per (segment,
-// destination block), for the spectrum and its error bars.
-__device__ __forceinline__ void mirror_block(double* a, int Nf, int bx, int by, double2 (*sh)[33]) {
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    double2* v = reinterpret_cast<double2*>(a);
-    // source block: rows bx*32.., columns by*32.. (upper triangle)
-    for (int r = ty; r < 32; r += 8) {
-        const int k = bx * 32 + r, l = by * 32 + tx;
-        if (k < Nf && l < Nf) sh[r][tx] = v[(int64_t)k * Nf + l];
-    }
+    if (!sg.sym) return;            // uniform over the block
+    sm[i][j] = make_double2(mr, mi);
+    se[i][j] = make_double2(sr, si);
     __syncthreads();
-    for (int r = ty; r < 32; r += 8) {
-        const int k = by * 32 + r, l = bx * 32 + tx;    // destination (k, l) with k > l
-        if (k < Nf && l < Nf && k > l) v[(int64_t)k * Nf + l] = sh[tx][r];
+    // thread (i, j) now writes point (kb + j, lb + i) to (lb + i, kb + j)
+    const int km = kb + j, lm = lb + i;
+    if (km < lm && lm < p.Nf) {
+        const int64_t o = ((int64_t)lm * p.Nf + km) * 2;
+        if (sg.out) {
+            const double2 v = sm[j][i];
+            sg.out[o] = v.x;
+            sg.out[o + 1] = v.y;
+        }
+        if (sg.err) {
+            const double2 v = se[j][i];
+            sg.err[o] = v.x;
+            sg.err[o + 1] = v.y;
+        }
     }
-    __syncthreads();
-}
-
-__global__ __launch_bounds__(256) void k_mirror(FinalizeArgs p) {
-    __shared__ double2 sh[32][33];
-    const int64_t x = blockIdx.x;
-    if (x >= p.n_items) return;
-    const Seg& sg = p.segs[find_seg(p.segs, p.n_segs, x)];
-    const int nb = (p.Nf + 31) / 32;
-    const int local = (int)(x - sg.item0);
-    const int by = local / nb, bx = local % nb;   // destination block row by, column bx
-    if (by < bx) return;
-    if (sg.out) mirror_block(sg.out, p.Nf, bx, by, sh);
-    if (sg.err) mirror_block(sg.err, p.Nf, bx, by, sh);
 }
 
 __global__ void k_fill_nan(double* p, int64_t n) {
@@ -160,11 +153,6 @@ hipError_t launch_finalize_grid(const FinalizeArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_mirror(const FinalizeArgs& a, hipStream_t s) {
-    if (a.n_items <= 0) return hipSuccess;
-    k_mirror<<<(unsigned)a.n_items, 256, 0, s>>>(a);
-    return hipGetLastError();
-}
 
 hipError_t launch_fill_nan(double* p, int64_t n, hipStream_t s) {
     if (!p || n <= 0) return hipSuccess;

@@ -160,9 +160,8 @@ struct FinalizeArgs {
     int Nf;
 };
 hipError_t launch_finalize_vec(const FinalizeArgs& a, hipStream_t s);
+// Items are 16 x 16 sub-blocks of tiles; symmetric spectra are mirrored here.
 hipError_t launch_finalize_grid(const FinalizeArgs& a, hipStream_t s);
-// Mirror (k, l) -> (l, k) for k < l; items are 32 x 32 output blocks.
-hipError_t launch_mirror(const FinalizeArgs& a, hipStream_t s);
 
 hipError_t launch_fill_nan(double* p, int64_t n, hipStream_t s);
 
