@@ -212,6 +212,22 @@ ps_status ps_streamer_push(ps_streamer_t s, const void* h_pinned, const ps_outpu
 ps_status ps_streamer_wait(ps_streamer_t s, int32_t slot);
 ps_status ps_streamer_destroy(ps_streamer_t s);
 
+/* Several windows per push.  ps_streamer_create_multi is ps_streamer_create
+ * with staging slots of up to max_windows (1..64) consecutive windows.
+ * ps_streamer_push_multi takes n_windows (1..max_windows) consecutive windows
+ * from one pinned host buffer (window w, channel c starting at sample
+ * (w * n_channels + c) * window_samples) and runs them as ONE ps_execute with
+ * one record per window, outs[w] receiving window w; copy/compute overlap,
+ * ownership and the rules above are as for ps_streamer_push, per slot.  The
+ * group shares every launch and its tail, which keeps the GPU busy when one
+ * window is a small problem.  ps_streamer_push is ps_streamer_push_multi with
+ * one window.  Errors: PS_E_INVALID_ARG for n_windows outside 1..max_windows or
+ * NULL arguments; otherwise as for ps_execute. */
+ps_status ps_streamer_create_multi(ps_plan_t plan, int64_t window_samples, int32_t max_windows, int32_t dtype,
+                                   int32_t depth, ps_streamer_t* out);
+ps_status ps_streamer_push_multi(ps_streamer_t s, const void* h_pinned, int32_t n_windows, const ps_output* outs,
+                                 ps_stream_t compute, int32_t* slot);
+
 /* The first stage alone (Section 3, eq. a_k without the dt factor): for every
  * frame f < Np*m of every channel, d_coef[c][f][k] = sum_i g_i z_{fN+i}
  * exp(+2 pi j i k/N), k < n_coef, as interleaved FP32 complex.  d_coef must hold

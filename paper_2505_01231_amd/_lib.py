@@ -24,7 +24,7 @@ EXPORTED = (
     "ps_execute", "ps_coefficients", "ps_status_string", "ps_last_error", "ps_abi_version",
     "ps_enumerate_combos", "ps_profile_enable", "ps_profile_read", "ps_graph_create",
     "ps_graph_launch", "ps_graph_destroy", "ps_streamer_create", "ps_streamer_push",
-    "ps_streamer_wait", "ps_streamer_destroy",
+    "ps_streamer_wait", "ps_streamer_destroy", "ps_streamer_create_multi", "ps_streamer_push_multi",
 )
 
 
@@ -95,11 +95,13 @@ def load() -> C.CDLL:
     lib.ps_streamer_push.argtypes = [vp, vp, C.POINTER(ps_output), vp, C.POINTER(i32)]
     lib.ps_streamer_wait.argtypes = [vp, i32]
     lib.ps_streamer_destroy.argtypes = [vp]
+    lib.ps_streamer_create_multi.argtypes = [vp, i64, i32, i32, i32, C.POINTER(vp)]
+    lib.ps_streamer_push_multi.argtypes = [vp, vp, i32, C.POINTER(ps_output), vp, C.POINTER(i32)]
     for name in ("ps_plan_create", "ps_plan_destroy", "ps_plan_query", "ps_record_info",
                  "ps_workspace_size", "ps_execute", "ps_coefficients", "ps_enumerate_combos",
                  "ps_profile_enable", "ps_profile_read", "ps_graph_create", "ps_graph_launch",
                  "ps_graph_destroy", "ps_streamer_create", "ps_streamer_push", "ps_streamer_wait",
-                 "ps_streamer_destroy"):
+                 "ps_streamer_destroy", "ps_streamer_create_multi", "ps_streamer_push_multi"):
         getattr(lib, name).restype = C.c_int
     lib.ps_status_string.argtypes = [C.c_int]
     lib.ps_status_string.restype = C.c_char_p

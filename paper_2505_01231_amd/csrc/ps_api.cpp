@@ -948,7 +948,7 @@ ps_status ps_graph_launch(ps_graph_t g, ps_stream_t stream) {
 struct ps_streamer_s {
     ps_plan_t plan = nullptr;
     int64_t window = 0;
-    int dtype = 0, depth = 0;
+    int dtype = 0, depth = 0, max_windows = 1;
     size_t esz = 0;
     hipStream_t copy = nullptr;
     std::vector<void*> stage;           // device staging slots
@@ -975,17 +975,19 @@ ps_status ps_streamer_destroy(ps_streamer_t s) {
     return PS_OK;
 }
 
-ps_status ps_streamer_create(ps_plan_t p, int64_t window_samples, int32_t dtype, int32_t depth,
-                             ps_streamer_t* out) {
+ps_status ps_streamer_create_multi(ps_plan_t p, int64_t window_samples, int32_t max_windows, int32_t dtype,
+                                   int32_t depth, ps_streamer_t* out) {
     if (!out) return fail(PS_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    if (!p || window_samples <= 0 || depth < 1 || depth > 16 || dtype < PS_F32 || dtype > PS_I16)
+    if (!p || window_samples <= 0 || depth < 1 || depth > 16 || dtype < PS_F32 || dtype > PS_I16 ||
+        max_windows < 1 || max_windows > 64)
         return fail(PS_E_INVALID_ARG, "bad argument");
     auto* s = new ps_streamer_s();
     s->plan = p;
     s->window = window_samples;
     s->dtype = dtype;
     s->depth = depth;
+    s->max_windows = max_windows;
     s->esz = dtype == PS_F32 ? 4 : (dtype == PS_F64 ? 8 : 2);
     hipError_t e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
     auto alloc = [&](size_t bytes) -> void* {
@@ -996,17 +998,22 @@ ps_status ps_streamer_create(ps_plan_t p, int64_t window_samples, int32_t dtype,
         }
         return q;
     };
-    ps_record r{};
-    r.d_data = nullptr;
-    r.n_samples = window_samples;
-    r.channel_stride = window_samples;
-    r.dtype = dtype;
-    Batch B;
-    build_batch(p, &r, 1, nullptr, B);
-    s->ws_bytes = B.total;
-    s->ws = alloc(B.total);
+    // workspace for the largest of the group sizes 1..max_windows
+    std::vector<ps_record> rs(max_windows);
+    for (ps_record& r : rs) {
+        r = ps_record{};
+        r.n_samples = window_samples;
+        r.channel_stride = window_samples;
+        r.dtype = dtype;
+    }
+    for (int n = 1; n <= max_windows; ++n) {
+        Batch B;
+        build_batch(p, rs.data(), n, nullptr, B);
+        s->ws_bytes = std::max(s->ws_bytes, B.total);
+    }
+    s->ws = alloc(s->ws_bytes);
     for (int i = 0; i < depth && e == hipSuccess; ++i) {
-        s->stage.push_back(alloc(s->esz * window_samples * p->C));
+        s->stage.push_back(alloc(s->esz * window_samples * p->C * max_windows));
         hipEvent_t a = nullptr, b = nullptr;
         if (e == hipSuccess) e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
@@ -1022,29 +1029,44 @@ ps_status ps_streamer_create(ps_plan_t p, int64_t window_samples, int32_t dtype,
     return PS_OK;
 }
 
-ps_status ps_streamer_push(ps_streamer_t s, const void* h_pinned, const ps_output* outs, ps_stream_t compute,
-                           int32_t* slot) {
+ps_status ps_streamer_create(ps_plan_t p, int64_t window_samples, int32_t dtype, int32_t depth,
+                             ps_streamer_t* out) {
+    return ps_streamer_create_multi(p, window_samples, 1, dtype, depth, out);
+}
+
+ps_status ps_streamer_push_multi(ps_streamer_t s, const void* h_pinned, int32_t n_windows, const ps_output* outs,
+                                 ps_stream_t compute, int32_t* slot) {
     if (!s || !h_pinned || !outs) return fail(PS_E_INVALID_ARG, "bad argument");
+    if (n_windows < 1 || n_windows > s->max_windows)
+        return fail(PS_E_INVALID_ARG, "n_windows %d outside 1..%d", n_windows, s->max_windows);
     const int i = s->next;
     s->next = (s->next + 1) % s->depth;
     hipStream_t cs = (hipStream_t)compute;
+    const size_t win_bytes = s->esz * s->window * s->plan->C;
     // The slot's staging buffer may still be read by its previous computation.
     if (s->used[i]) PS_HIP(hipStreamWaitEvent(s->copy, s->done[i], 0));
-    PS_HIP(hipMemcpyAsync(s->stage[i], h_pinned, s->esz * s->window * s->plan->C, hipMemcpyHostToDevice,
-                          s->copy));
+    PS_HIP(hipMemcpyAsync(s->stage[i], h_pinned, win_bytes * n_windows, hipMemcpyHostToDevice, s->copy));
     PS_HIP(hipEventRecord(s->copied[i], s->copy));
     PS_HIP(hipStreamWaitEvent(cs, s->copied[i], 0));
-    ps_record r{};
-    r.d_data = s->stage[i];
-    r.n_samples = s->window;
-    r.channel_stride = s->window;
-    r.dtype = s->dtype;
-    ps_status st = ps_execute(s->plan, &r, 1, s->ws, s->ws_bytes, outs, compute);
+    ps_record rs[64];
+    for (int w = 0; w < n_windows; ++w) {
+        rs[w] = ps_record{};
+        rs[w].d_data = static_cast<char*>(s->stage[i]) + win_bytes * w;
+        rs[w].n_samples = s->window;
+        rs[w].channel_stride = s->window;
+        rs[w].dtype = s->dtype;
+    }
+    ps_status st = ps_execute(s->plan, rs, n_windows, s->ws, s->ws_bytes, outs, compute);
     if (st != PS_OK) return st;
     PS_HIP(hipEventRecord(s->done[i], cs));
     s->used[i] = 1;
     if (slot) *slot = i;
     return PS_OK;
+}
+
+ps_status ps_streamer_push(ps_streamer_t s, const void* h_pinned, const ps_output* outs, ps_stream_t compute,
+                           int32_t* slot) {
+    return ps_streamer_push_multi(s, h_pinned, 1, outs, compute, slot);
 }
 
 ps_status ps_streamer_wait(ps_streamer_t s, int32_t slot) {

@@ -274,37 +274,49 @@ class Graph:
 
 class Streamer:
     """Time-resolved spectra of consecutive windows of a host stream
-    (ps_streamer_*): one push per window; the host-to-device copy of the next
-    window overlaps the estimator on the current one."""
+    (ps_streamer_*): each push copies one window, or up to ``windows_per_push``
+    consecutive windows, from pinned host memory into a staging slot and runs
+    them as one execute; the copy of the next push overlaps the estimator on
+    the current one."""
 
-    def __init__(self, plan: Plan, window_samples: int, dtype=torch.float32, depth: int = 3):
+    def __init__(self, plan: Plan, window_samples: int, dtype=torch.float32, depth: int = 3,
+                 windows_per_push: int = 1):
         self._plan = plan
         self.window = window_samples
         self.dtype = dtype
         self.depth = depth
+        self.windows_per_push = windows_per_push
         h = C.c_void_p()
-        L.check(plan._lib.ps_streamer_create(plan._handle, window_samples, _DTYPES[dtype], depth, C.byref(h)),
-                "ps_streamer_create")
+        L.check(plan._lib.ps_streamer_create_multi(plan._handle, window_samples, windows_per_push, _DTYPES[dtype],
+                                                   depth, C.byref(h)), "ps_streamer_create_multi")
         self._handle = h
         self.n_chunks, self.flags = plan.record_info(window_samples)
 
-    def push(self, host_window: torch.Tensor, outputs: Spectra, stream=None) -> int:
-        """Enqueue one window (pinned host tensor [C, window] or [window])
-        writing into ``outputs``; returns the slot to wait on."""
-        if host_window.is_cuda or not host_window.is_pinned():
+    def push(self, host_windows: torch.Tensor, outputs, stream=None) -> int:
+        """Enqueue n consecutive windows (pinned host tensor holding n * C * window
+        samples, window-major) writing window w into ``outputs[w]`` (a Spectra, or
+        a list of n); returns the slot to wait on."""
+        if host_windows.is_cuda or not host_windows.is_pinned():
             raise ValueError("windows must be pinned host tensors")
-        if host_window.dtype != self.dtype or host_window.numel() != self.window * self._plan.n_channels:
+        per = self.window * self._plan.n_channels
+        if host_windows.dtype != self.dtype or host_windows.numel() % per != 0:
             raise ValueError("window shape or dtype does not match the streamer")
-        if not host_window.is_contiguous():
-            raise ValueError("window must be contiguous")
-        outputs.n_chunks, outputs.flags = self.n_chunks, self.flags
+        if not host_windows.is_contiguous():
+            raise ValueError("windows must be contiguous")
+        n = host_windows.numel() // per
+        outs = [outputs] if isinstance(outputs, Spectra) else list(outputs)
+        if len(outs) != n or not 1 <= n <= self.windows_per_push:
+            raise ValueError(f"{n} windows with {len(outs)} outputs (at most {self.windows_per_push} per push)")
         p = Plan._ptr
-        out = L.ps_output(p(outputs.s2), p(outputs.s2_err), p(outputs.s3), p(outputs.s3_err), p(outputs.s4),
-                          p(outputs.s4_err))
+        arr = (L.ps_output * n)()
+        for w, o in enumerate(outs):
+            o.n_chunks, o.flags = self.n_chunks, self.flags
+            arr[w] = L.ps_output(p(o.s2), p(o.s2_err), p(o.s3), p(o.s3_err), p(o.s4), p(o.s4_err))
         st = torch.cuda.current_stream() if stream is None else stream
         slot = C.c_int32()
-        L.check(self._plan._lib.ps_streamer_push(self._handle, host_window.data_ptr(), C.byref(out),
-                                                 C.c_void_p(st.cuda_stream), C.byref(slot)), "ps_streamer_push")
+        L.check(self._plan._lib.ps_streamer_push_multi(self._handle, host_windows.data_ptr(), n, arr,
+                                                       C.c_void_p(st.cuda_stream), C.byref(slot)),
+                "ps_streamer_push_multi")
         return slot.value
 
     def wait(self, slot: int):

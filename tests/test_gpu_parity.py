@@ -449,3 +449,41 @@ def test_streamer_time_resolved_windows(dev):
         slope = np.polyfit(np.log(s_w), np.log(amp), 1)[0]
         say(f"  log-slope {key}: {slope:.2f} (expected {n})")
         assert abs(slope - n) < tol, (key, slope)
+
+
+@pytest.mark.gpu
+def test_streamer_multi_window_pushes(dev):
+    """Several consecutive windows per push (ps_streamer_push_multi): groups of
+    3, 2 and 3 windows through two staging slots.  Every window equals
+    ps_execute over the same group of records bit for bit, and one window
+    matches the oracle."""
+    from paper_2505_01231_amd import Plan, Streamer
+    say("streamer multi-window pushes")
+    N, Nf, m, W = 2048, 128, 10, 1 << 18
+    groups = [3, 2, 3]
+    total = W * sum(groups)
+    z = synth.modulated_ar2(total, seed=7, total=total, r=0.9)
+    with Plan(frame_len=N, n_freq=Nf, m=m, window="acg", precision="bf16x3") as p:
+        st = Streamer(p, W, dtype=torch.float32, depth=2, windows_per_push=3)
+        with pytest.raises(ValueError):
+            st.push(torch.empty(4 * W, dtype=torch.float32, pin_memory=True),
+                    [p.allocate_outputs(dev) for _ in range(4)])
+        results, w0 = [], 0
+        for n in groups:
+            host = torch.from_numpy(z[w0 * W:(w0 + n) * W].copy()).pin_memory()
+            outs = [p.allocate_outputs(dev) for _ in range(n)]
+            st.wait(st.push(host, outs))
+            results.append([{k: getattr(o, k).cpu().numpy() for k in ("s2", "s3", "s4", "s4_err")} for o in outs])
+            ref = p.execute([torch.from_numpy(z[(w0 + i) * W:(w0 + i + 1) * W].copy()).to(dev) for i in range(n)])
+            torch.cuda.synchronize()
+            for i in range(n):
+                for k in ("s2", "s3", "s4", "s4_err"):
+                    assert np.array_equal(results[-1][i][k], getattr(ref[i], k).cpu().numpy()), (w0 + i, k)
+            w0 += n
+        st.close()
+    w = 6                                      # second window of the third group
+    ref = O.polyspectra(z[w * W:(w + 1) * W], N, Nf, m, window_kind="acg")
+    got = results[2][1]
+    for key in ("s2", "s3", "s4"):
+        g = got[key][..., 0] + 1j * got[key][..., 1]
+        assert rel_err(g, ref[key]) <= TOL, key
