@@ -135,11 +135,42 @@ struct ps_plan_s {
 
 namespace {
 
-// Blocks of one segment in the batched schedule: the stage's (tile, chunk)
-// units are spread over its resident blocks, L = ceil(U_stage / slots) units
-// per block at most, so that every segment gets ceil(U_seg / L) blocks.
-int64_t units_per_block(int64_t U_stage, int64_t slots) {
-    return std::max<int64_t>(1, (U_stage + slots - 1) / std::max<int64_t>(slots, 1));
+// Units (tile, chunk) per block of one stage in the batched schedule.  A block
+// belongs to one segment, so a segment of U units gets ceil(U / L) blocks of at
+// most L units.  L is chosen among candidates (whole waves of resident blocks
+// over the stage's total, and even cuts of the largest segment) to minimise
+// the makespan estimate waves x (L + 1), waves = ceil(blocks / slots): with
+// many segments the plain ceil(U_stage / slots) leaves a nearly empty second
+// wave of blocks.  The + 1 charges each block one unit for its partial-sum
+// write, which favours fewer, longer blocks among equals.
+int64_t units_per_block(const std::vector<int64_t>& U_seg, int64_t slots) {
+    int64_t U = 0, U_max = 0;
+    for (int64_t u : U_seg) {
+        U += u;
+        U_max = std::max(U_max, u);
+    }
+    if (U == 0) return 1;
+    slots = std::max<int64_t>(slots, 1);
+    auto cost = [&](int64_t L, int64_t& blocks) {
+        blocks = 0;
+        for (int64_t u : U_seg) blocks += (u + L - 1) / L;
+        return (double)((blocks + slots - 1) / slots) * (double)(L + 1);
+    };
+    int64_t best_L = std::max<int64_t>(1, (U + slots - 1) / slots), best_blocks = 0;
+    double best = cost(best_L, best_blocks);
+    auto consider = [&](int64_t L) {
+        if (L < 1) return;
+        int64_t blocks = 0;
+        const double c = cost(L, blocks);
+        if (c < best || (c == best && blocks < best_blocks)) {
+            best = c;
+            best_L = L;
+            best_blocks = blocks;
+        }
+    };
+    for (int64_t w = 1; w <= 32; ++w) consider((U + slots * w - 1) / (slots * w));
+    for (int64_t k = 1; k <= 64; ++k) consider((U_max + k - 1) / k);
+    return best_L;
 }
 int32_t seg_blocks(int64_t T, int64_t Np, int64_t L, bool per_chunk) {
     if (per_chunk) return (int32_t)T;
@@ -226,16 +257,16 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
     int64_t part = 0;
     for (Group& G : B.groups) {
         const int r_lo = per_chunk ? G.rec : 0, r_hi = per_chunk ? G.rec + 1 : n;
-        // units per stage, for the block counts
-        int64_t U2 = 0, U3 = 0, U4s = 0, U4x = 0;
+        // units of every segment per stage, for the block counts
+        std::vector<int64_t> U2, U3, U4s, U4x;
         for (int r = r_lo; r < r_hi; ++r) {
             const int64_t Np = B.ri[r].Np;
             if (Np == 0) continue;
-            U2 += (int64_t)p->n2() * kblocks * Np;
-            for (int i = 0; i < p->n3(); ++i) U3 += p->n_tiles[p->s3_sym(i) ? ps::kSym64 : ps::kFull64] * Np;
+            for (int i = 0; i < p->n2(); ++i) U2.push_back((int64_t)kblocks * Np);
+            for (int i = 0; i < p->n3(); ++i) U3.push_back(p->n_tiles[p->s3_sym(i) ? ps::kSym64 : ps::kFull64] * Np);
             for (int i = 0; i < p->n4(); ++i) {
-                if (p->s4_single(i)) U4s += p->n_tiles[ps::kSym64] * Np;
-                else U4x += p->n_tiles[p->s4_sym(i) ? ps::kSym32 : ps::kFull32] * Np;
+                if (p->s4_single(i)) U4s.push_back(p->n_tiles[ps::kSym64] * Np);
+                else U4x.push_back(p->n_tiles[p->s4_sym(i) ? ps::kSym32 : ps::kFull32] * Np);
             }
         }
         const int64_t L2 = units_per_block(U2, 4LL * p->n_cu);
@@ -558,7 +589,7 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     p->bpc_s4 = p->precision == PS_PREC_FP32     ? ps::s4_blocks_per_cu()
                 : p->precision == PS_PREC_BF16X3 ? ps::s4_mfma_blocks_per_cu()
                                                  : ps::s4_mfma_f16_blocks_per_cu();
-    p->bpc_s4x = ps::s4_cross_blocks_per_cu();
+    p->bpc_s4x = p->precision == PS_PREC_BF16X3 ? ps::s4_cross_mfma_blocks_per_cu() : ps::s4_cross_blocks_per_cu();
     *out = p;
     return PS_OK;
 }
@@ -737,7 +768,8 @@ ps_status launch_moments(ps_plan_t p, const Batch& B, const Group& G, char* ws, 
     }
     if (G.s4x.n_items) {
         StageTimer t(p, st, 4);
-        PS_HIP(ps::launch_s4_cross(batch_args(p, B, G.s4x, ws, tab, per_chunk, win_lo, win_hi, accumulate), st));
+        PS_HIP((p->precision == PS_PREC_BF16X3 ? ps::launch_s4_cross_mfma : ps::launch_s4_cross)(
+            batch_args(p, B, G.s4x, ws, tab, per_chunk, win_lo, win_hi, accumulate), st));
     }
     return PS_OK;
 }

@@ -143,12 +143,14 @@ hipError_t launch_s4_single(const BatchArgs& a, hipStream_t s);
 hipError_t launch_s4_mfma(const BatchArgs& a, hipStream_t s);
 hipError_t launch_s4_mfma_f16(const BatchArgs& a, hipStream_t s);
 hipError_t launch_s4_cross(const BatchArgs& a, hipStream_t s);
+hipError_t launch_s4_cross_mfma(const BatchArgs& a, hipStream_t s);
 
 int s3_blocks_per_cu();
 int s4_blocks_per_cu();
 int s4_mfma_blocks_per_cu();
 int s4_mfma_f16_blocks_per_cu();
 int s4_cross_blocks_per_cu();
+int s4_cross_mfma_blocks_per_cu();
 
 // ---------------------------------------------------------------- finalize
 struct FinalizeArgs {

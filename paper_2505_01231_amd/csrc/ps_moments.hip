@@ -993,6 +993,198 @@ __global__ __launch_bounds__(kS4XThreads, 2) void k_s4_cross(BatchArgs p) {
     }
 }
 
+// ------------------------------------------------------------------ S4, channel combinations, matrix cores
+// The sums of k_s4_cross on the matrix cores (v_mfma_f32_16x16x32_bf16, FP32
+// accumulation, the BF16 x 3 split and 6-slot frame layout of k_s4_mfma_bf16).
+// Each complex frame sum is four real Gram contractions, e.g.
+//   sum E_k F_l = (sum E_r F_r - sum E_i F_i) + j (sum E_r F_i + sum E_i F_r),
+// so the five sums E F, a c, b c*, b d, a d* take 20 Grams between six k-side
+// row types (Re, Im of E = a' b'*, a', b') and six l-side types (F = c' d'*,
+// c', d').  Tiles are 32 x 32; wave w owns the 16 x 16 block
+// (16 (w / 2), 16 (w % 2)) with 20 accumulators of 4 registers, lane (lg, li)
+// holding grid points (4 lg + e, li).  LDS rows are 160 bytes apart, a stride
+// at which the 16-row, 16-byte-per-lane operand reads of 16x16x32 are free of
+// bank conflicts.  The combination T = e f + G_ac conj(G_bd) + H_ad conj(H_bc)
+// and v = sum E F - gamma T are formed in FP64, as are the chunk sums.
+constexpr int kOpDwX = 40;           // 32-bit words per LDS operand row (160 B; 32 used)
+constexpr int kS4XMThreads = 256;
+constexpr int kCrossSlots = 3;       // frame slots q, q + 4, q + 8 of a loader thread
+
+// Stage this thread's frame slots of column `col`: P = x conj(y) and the split
+// words of (Re P, Im P, Re x, Im x, Re y, Im y) into row types 0..5; returns
+// the sum of P over the slots.
+template <int SIDE>
+__device__ __forceinline__ float2 stage_cross(uint32_t (*op)[kOpDwX], int col, int q, const float2 (&px)[kCrossSlots],
+                                              const float2 (&py)[kCrossSlots]) {
+    float2 pa = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int j = 0; j < kCrossSlots; ++j) {
+        const int f = q + 4 * j;
+        if (f >= kMfmaFrames) break;
+        const float2 x = px[j], y = py[j];
+        const float2 P = make_float2(fmaf(x.x, y.x, x.y * y.y), fmaf(x.y, y.x, -(x.x * y.y)));
+        pa.x += P.x;
+        pa.y += P.y;
+        const float val[6] = {P.x, P.y, x.x, x.y, y.x, y.y};
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+            uint32_t w0, w1, w2;
+            split_words<SIDE>(val[t], w0, w1, w2);
+            uint32_t* wr = &op[t * kTileX + col][3 * f];
+            wr[0] = w0;
+            wr[1] = w1;
+            wr[2] = w2;
+        }
+    }
+    return pa;
+}
+
+// ONE_BATCH: every chunk fits one frame batch (m <= 10), so each batch starts
+// and ends a chunk (compile-time).
+template <bool ONE_BATCH>
+__global__ __launch_bounds__(kS4XMThreads, 2) void k_s4_cross_mfma(BatchArgs p) {
+    __shared__ __attribute__((aligned(16))) uint32_t opA[6 * kTileX][kOpDwX];
+    __shared__ __attribute__((aligned(16))) uint32_t opB[6 * kTileX][kOpDwX];
+    __shared__ float2 psum[2][kTileX];
+
+    Block bk;
+    View v;
+    if (!resolve_block(p, bk, v)) return;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int rowA = 16 * (w >> 1) + li, rowB = 16 * (w & 1) + li;
+
+    // Loader role: (side, column, frame residue q): frames q, q + 4, q + 8.
+    const int side = __builtin_amdgcn_readfirstlane(tid >> 7);    // uniform per wave
+    const int col = (tid & 127) >> 2;
+    const int q = tid & 3;
+    uint32_t(*op)[kOpDwX] = side ? opB : opA;
+
+    for (int r = tid; r < 2 * 6 * kTileX; r += kS4XMThreads) {
+        uint32_t* row = (r < 6 * kTileX) ? opA[r] : opB[r - 6 * kTileX];
+        row[3 * kMfmaFrames] = 0u;
+        row[3 * kMfmaFrames + 1] = 0u;
+    }
+    const double gamma = p.gamma;
+
+    Item it;
+    while (next_item<kTileX, 4>(p, bk, it)) {
+    const int c0 = it.c0, c1 = it.c1;
+    const int gcol = (side ? it.l0 : it.k0) + col;
+    const bool live = gcol < p.Nf;
+    const float2* srcx = v.coef + it.ch[2 * side] * v.cs + gcol;        // a (k side) or c (l side)
+    const float2* srcy = v.coef + it.ch[2 * side + 1] * v.cs + gcol;    // b or d
+
+    double acc[4][4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[e][0] = acc[e][1] = acc[e][2] = acc[e][3] = 0.0;
+
+    constexpr int kJ = kCrossSlots;
+    const int per_chunk = (v.m + kMfmaFrames - 1) / kMfmaFrames;
+    const int n_batches = (c1 - c0) * per_chunk;
+    float2 px[kJ], py[kJ];
+    auto fetch = [&](int b) {
+        const int c = c0 + b / per_chunk;
+        const int fb = (b % per_chunk) * kMfmaFrames;
+        const int nf = min(kMfmaFrames, v.m - fb);
+        const int64_t o = v.off + ((int64_t)c * v.m + fb) * v.K;
+#pragma unroll
+        for (int j = 0; j < kJ; ++j) {
+            const int f = q + 4 * j;
+            const bool ok = live && f < nf;
+            px[j] = ok ? srcx[o + (int64_t)f * v.K] : make_float2(0.f, 0.f);
+            py[j] = ok ? srcy[o + (int64_t)f * v.K] : make_float2(0.f, 0.f);
+        }
+    };
+    if (n_batches > 0) fetch(0);
+
+    floatx4_t d[20];
+    float2 pacc = make_float2(0.f, 0.f);
+#pragma unroll 1
+    for (int b = 0; b < n_batches; ++b) {
+        const int fbi = ONE_BATCH ? 0 : b % per_chunk;
+        const bool first = ONE_BATCH || fbi == 0, last = ONE_BATCH || fbi == per_chunk - 1;
+        if (first) pacc = make_float2(0.f, 0.f);
+        lds_barrier();
+        {   // E = x conj(y) (k side: a b*, l side: c d*)
+            const float2 pa = side == 0 ? stage_cross<0>(op, col, q, px, py) : stage_cross<1>(op, col, q, px, py);
+            pacc.x += pa.x;
+            pacc.y += pa.y;
+        }
+        if (last) {
+            float2 tot = pacc;
+            tot.x += xor1(tot.x);
+            tot.y += xor1(tot.y);
+            tot.x += __shfl_xor(tot.x, 2);
+            tot.y += __shfl_xor(tot.y, 2);
+            if (q == 0) psum[side][col] = tot;
+        }
+        lds_barrier();
+        __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const int wo = 16 * ks + 4 * lg;
+            bf16x8_t A[6], B[6];
+#pragma unroll
+            for (int t = 0; t < 6; ++t) {
+                A[t] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(&opA[t * kTileX + rowA][wo]));
+                B[t] = __builtin_bit_cast(bf16x8_t, *reinterpret_cast<const u32x4_t*>(&opB[t * kTileX + rowB][wo]));
+            }
+            // (A type, B type) of the 20 Grams: E.F, a.c, b.c, b.d, a.d, each rr, ii, ri, ir
+            constexpr int ga[20] = {0, 1, 0, 1, 2, 3, 2, 3, 4, 5, 4, 5, 4, 5, 4, 5, 2, 3, 2, 3};
+            constexpr int gb[20] = {0, 1, 1, 0, 2, 3, 3, 2, 2, 3, 3, 2, 4, 5, 5, 4, 4, 5, 5, 4};
+            const floatx4_t z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int g = 0; g < 20; ++g)
+                d[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ga[g]], B[gb[g]], (first && ks == 0) ? z : d[g], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __builtin_amdgcn_s_setprio(0);
+        if (b + 1 < n_batches) fetch(b + 1);
+        if (!last) continue;
+
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float2 ek = psum[0][16 * (w >> 1) + 4 * lg + e], fl = psum[1][rowB];
+            // complex sums from the real Grams (FP32, like the Grams), then FP64
+            const double sef_r = d[0][e] - d[1][e], sef_i = d[2][e] + d[3][e];
+            const double gac_r = d[4][e] - d[5][e], gac_i = d[6][e] + d[7][e];
+            const double hbc_r = d[8][e] + d[9][e], hbc_i = d[11][e] - d[10][e];
+            const double gbd_r = d[12][e] - d[13][e], gbd_i = d[14][e] + d[15][e];
+            const double had_r = d[16][e] + d[17][e], had_i = d[19][e] - d[18][e];
+            // T = e f + G_ac conj(G_bd) + H_ad conj(H_bc)
+            double tr = (double)ek.x * fl.x - (double)ek.y * fl.y;
+            double ti = (double)ek.x * fl.y + (double)ek.y * fl.x;
+            tr += gac_r * gbd_r + gac_i * gbd_i;
+            ti += gac_i * gbd_r - gac_r * gbd_i;
+            tr += had_r * hbc_r + had_i * hbc_i;
+            ti += had_i * hbc_r - had_r * hbc_i;
+            const double vr = fma(-gamma, tr, sef_r);
+            const double vi = fma(-gamma, ti, sef_i);
+            acc[e][0] += vr;
+            acc[e][1] += vi;
+            acc[e][2] = fma(vr, vr, acc[e][2]);
+            acc[e][3] = fma(vi, vi, acc[e][3]);
+        }
+    }
+
+    constexpr int TT = kTileX * kTileX;
+    double* o = it.part;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int idx = (16 * (w >> 1) + 4 * lg + e) * kTileX + rowB;
+#pragma unroll
+        for (int comp = 0; comp < 4; ++comp) {
+            double val = acc[e][comp];
+            if (p.accumulate) val += o[comp * TT + idx];
+            o[comp * TT + idx] = val;
+        }
+    }
+    }
+}
+
 int blocks_per_cu(const void* fn, int threads) {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, 0) != hipSuccess || n < 1) n = 1;
@@ -1032,6 +1224,19 @@ hipError_t launch_s4_mfma(const BatchArgs& a, hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;
     k_s4_mfma_bf16<<<item_grid(a), kS4MThreads, 0, s>>>(a);
     return hipGetLastError();
+}
+
+hipError_t launch_s4_cross_mfma(const BatchArgs& a, hipStream_t s) {
+    if (a.n_items <= 0) return hipSuccess;
+    if (a.m <= kMfmaFrames)
+        k_s4_cross_mfma<true><<<item_grid(a), kS4XMThreads, 0, s>>>(a);
+    else
+        k_s4_cross_mfma<false><<<item_grid(a), kS4XMThreads, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+int s4_cross_mfma_blocks_per_cu() {
+    return blocks_per_cu(reinterpret_cast<const void*>(&k_s4_cross_mfma<false>), kS4XMThreads);
 }
 
 hipError_t launch_s4_cross(const BatchArgs& a, hipStream_t s) {

@@ -321,15 +321,17 @@ def test_all_orbits_two_channels(dev, precision):
     compare(gpu, ref, label=f"orbits2-{precision}")
 
 
-def test_all_orbits_four_channels_int16(dev):
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_all_orbits_four_channels_int16(dev, precision):
     """Four int16 channels mixed from two AR(2)/chi-square sources plus noise:
-    all 10 / 40 / 76 combination orbits."""
-    say("all orbits, 4 int16 channels")
+    all 10 / 40 / 76 combination orbits (the cross-channel S4 on the vector
+    ALUs and on the matrix cores)."""
+    say("all orbits, 4 int16 channels", precision)
     z, clipped = synth.mixed_channels(512 * 10 * 5 + 77, seed=4)
     assert clipped == 0
-    gpu, ref = both(z, dev, 512, 64, 10, window="acg", n_channels=4)
+    gpu, ref = both(z, dev, 512, 64, 10, window="acg", n_channels=4, precision=precision)
     assert [len(gpu["plan"][f"combos{o}"]) for o in (2, 3, 4)] == [10, 40, 76]
-    compare(gpu, ref, label="orbits4-int16")
+    compare(gpu, ref, label=f"orbits4-int16-{precision}")
 
 
 # ---------------------------------------------------------------- batching form
