@@ -517,6 +517,8 @@ __device__ __forceinline__ float stage_rows(uint32_t (*op)[kOpDw], int col, int 
     return pa;
 }
 
+// ONE_BATCH: every chunk fits one frame batch (m <= 10, compile-time).
+template <bool ONE_BATCH>
 __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
     __shared__ __attribute__((aligned(16))) uint32_t opK[3 * kTile][kOpDw];
     __shared__ __attribute__((aligned(16))) uint32_t opL[3 * kTile][kOpDw];
@@ -532,7 +534,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
     const int rowK = 32 * (w >> 1) + r32, rowL = 32 * (w & 1) + r32;
 
     // Loader role: thread -> (side, column, half of the frame slots).
-    const int side = tid >> 7;
+    const int side = __builtin_amdgcn_readfirstlane(tid >> 7);    // uniform per wave
     const int col = (tid >> 1) & (kTile - 1);
     const int half = tid & 1;
     uint32_t(*op)[kOpDw] = side ? opL : opK;
@@ -580,8 +582,8 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
     float pacc = 0.f;
 #pragma unroll 1
     for (int b = 0; b < n_batches; ++b) {
-        const int fbi = b % per_chunk;
-        const bool first = fbi == 0, last = fbi == per_chunk - 1;
+        const int fbi = ONE_BATCH ? 0 : b % per_chunk;
+        const bool first = ONE_BATCH || fbi == 0, last = ONE_BATCH || fbi == per_chunk - 1;
         if (first) pacc = 0.f;
         lds_barrier();
         pacc += side == 0 ? stage_rows<0>(op, col, half, pre, cm1) : stage_rows<1>(op, col, half, pre, 1.0f);
@@ -1222,7 +1224,10 @@ hipError_t launch_s4_single(const BatchArgs& a, hipStream_t s) {
 
 hipError_t launch_s4_mfma(const BatchArgs& a, hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;
-    k_s4_mfma_bf16<<<item_grid(a), kS4MThreads, 0, s>>>(a);
+    if (a.m <= kMfmaFrames)
+        k_s4_mfma_bf16<true><<<item_grid(a), kS4MThreads, 0, s>>>(a);
+    else
+        k_s4_mfma_bf16<false><<<item_grid(a), kS4MThreads, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -1264,7 +1269,7 @@ int s4_mfma_f16_blocks_per_cu() {
 }
 
 int s4_mfma_blocks_per_cu() {
-    return blocks_per_cu(reinterpret_cast<const void*>(&k_s4_mfma_bf16), kS4MThreads);
+    return blocks_per_cu(reinterpret_cast<const void*>(&k_s4_mfma_bf16<false>), kS4MThreads);
 }
 
 }  // namespace ps
