@@ -170,20 +170,15 @@ __global__ __launch_bounds__(256) void k_s2(BatchArgs p) {
 // k + l = k0 + l0 + ti + tj + 16(u + v).  Per frame it reads 4 + 4 + 7 values
 // from LDS and does 16 complex triple products as 2 multiplies + 6 FMAs each.
 // Frames are staged through LDS in batches of FB; the next batch is fetched
-// into registers while the current one is being multiplied.
+// into registers while the current one is being multiplied.  On a diagonal
+// tile of a symmetric spectrum (k0 == l0) the points with u > v lie below the
+// diagonal (k > l), which the finalize never reads: that form skips them.
 constexpr int kS3Threads = 256;
 
-template <int FB>
-__global__ __launch_bounds__(kS3Threads, 2) void k_s3(BatchArgs p) {
-    __shared__ float2 sA[FB][kTile];
-    __shared__ float2 sB[FB][kTile];
-    __shared__ float2 sC[FB][2 * kTile];
-
-    Block bk;
-    View v;
-    if (!resolve_block(p, bk, v)) return;
-    Item it;
-    while (next_item<kTile, 4>(p, bk, it)) {
+// One piece of work (a tile and a range of its chunks) of k_s3.
+template <int FB, bool DIAG>
+__device__ __forceinline__ void s3_item(const BatchArgs& p, const View& v, const Item& it, float2 (*sA)[kTile],
+                                        float2 (*sB)[kTile], float2 (*sC)[2 * kTile]) {
     const int c0 = it.c0, c1 = it.c1;
     const int k0 = it.k0, l0 = it.l0;
 
@@ -253,6 +248,7 @@ __global__ __launch_bounds__(kS3Threads, 2) void k_s3(BatchArgs p) {
             for (int u = 0; u < 4; ++u) {
 #pragma unroll
                 for (int w = 0; w < 4; ++w) {
+                    if (DIAG && u > w) continue;
                     // p = a b;  T3 += p * conj(c)
                     const float pr = fmaf(a[u].x, bb[w].x, -(a[u].y * bb[w].y));
                     const float pi = fmaf(a[u].x, bb[w].y, a[u].y * bb[w].x);
@@ -267,6 +263,7 @@ __global__ __launch_bounds__(kS3Threads, 2) void k_s3(BatchArgs p) {
         if (fbi == per_chunk - 1) {
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
+                if (DIAG && (q >> 2) > (q & 3)) continue;
                 const double re = tr[q], im = tm[q];
                 acc[q][0] += re;
                 acc[q][1] += im;
@@ -290,6 +287,21 @@ __global__ __launch_bounds__(kS3Threads, 2) void k_s3(BatchArgs p) {
             }
         }
     }
+}
+
+template <int FB>
+__global__ __launch_bounds__(kS3Threads, 2) void k_s3(BatchArgs p) {
+    __shared__ float2 sA[FB][kTile];
+    __shared__ float2 sB[FB][kTile];
+    __shared__ float2 sC[FB][2 * kTile];
+
+    Block bk;
+    View v;
+    if (!resolve_block(p, bk, v)) return;
+    Item it;
+    while (next_item<kTile, 4>(p, bk, it)) {
+        if (bk.s->tiles == kSym64 && it.k0 == it.l0) s3_item<FB, true>(p, v, it, sA, sB, sC);
+        else s3_item<FB, false>(p, v, it, sA, sB, sC);
     }
 }
 

@@ -46,6 +46,7 @@ def s3_source_digest() -> str:
         (inc, r"__device__ __forceinline__ void lds_barrier\(\) \{.*?\n\}\n"),
         (src, r"__device__ __forceinline__ bool resolve_block\(.*?\n\}\n"),
         (src, r"__device__ __forceinline__ bool next_item\(.*?\n\}\n"),
+        (src, r"template <int FB, bool DIAG>\n__device__ __forceinline__ void s3_item\(.*?\n\}\n"),
         (src, r"template <int FB>\n__global__ __launch_bounds__\(kS3Threads, 2\) void k_s3\(BatchArgs p\) \{.*?\n\}\n"),
         (inc, r"struct Sched \{.*?\n\};\n"),
     ]
@@ -107,7 +108,7 @@ def main(argv=None):
             raise SystemExit("only the S3 kernel's source digest is defined")
         out = {"kernel": a.kernel, "source_sha256": s3_source_digest(),
                "hbm_read_bytes_per_launch": r["read_bytes"], "hbm_write_bytes_per_launch": r["write_bytes"],
-               "avg_launch_us_under_counters": r["avg_us"], "fetch_scale": fcal, "write_scale": wcal,
+               "avg_launch_us_kernel_trace": r["avg_us"], "fetch_scale": fcal, "write_scale": wcal,
                "command": a.command}
         with open(a.traffic_json, "w") as f:
             json.dump(out, f, indent=1)

@@ -106,6 +106,37 @@ def test_coefficients_match_oracle(dev, N, dtype):
     assert e < 2e-6
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64, np.int16])
+def test_coefficients_unaligned_frames(dev, dtype):
+    """Frames that start at an odd sample address (a view from sample 1 and an
+    odd channel stride) take the scalar sample loads of the transform."""
+    from paper_2505_01231_amd import Plan
+    say("coefficients unaligned", dtype.__name__)
+    N, m, C = 1024, 4, 2
+    L_ = N * m * 2 + 4                  # channel stride L_ + 3 is odd
+    raw = synth.ar2_chi2(C * (L_ + 3) + 1, seed=11)
+    if dtype == np.int16:
+        raw = np.clip(np.rint(raw * 300), -32768, 32767)
+    base = torch.from_numpy(raw.astype(dtype)).to(dev)
+    # channel c = base[1 + c (L_ + 3) : ... + L_]: channel 0 starts at an odd
+    # address, channel 1 (odd stride) at an even one
+    x = base[1:1 + C * (L_ + 3)].view(C, L_ + 3)[:, :L_]
+    assert x.stride(0) % 2 == 1 and x.data_ptr() % (2 * x.element_size()) != 0
+    with Plan(frame_len=N, n_freq=N // 4, m=m, n_channels=C, window="acg") as p:
+        a = p.coefficients(x)
+        torch.cuda.synchronize()
+        a = a.cpu().numpy()
+        K = p.n_coef
+    g = O.window("acg", N)
+    xc = x.cpu().numpy()
+    for c in range(C):
+        fr = O.chunk_frames(xc[c], N, m).reshape(-1, N)
+        ref = O.coefficients(fr, g, 1.0, K)
+        e = rel_err(a[c], ref)
+        say("  channel", c, "coef rel err", e)
+        assert e < 2e-6
+
+
 # ---------------------------------------------------------------- configurations
 PRECISIONS = ["fp32", "bf16x3", "fp16x2s"]
 
