@@ -539,12 +539,22 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     }
     std::vector<float> gf(N);
     for (int i = 0; i < N; ++i) gf[i] = (float)g[i];
-    std::vector<float2> tw(N);
     const double two_pi = 6.28318530717958647692;
+    std::vector<float2> tw;
+    tw.reserve(ps::fft_twiddle_count(p->log2n));
     for (int t = 0; t < N; ++t) {
         const double ang = two_pi * t / N;
-        tw[t] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+        tw.push_back(make_float2((float)std::cos(ang), (float)std::sin(ang)));
     }
+    // per-pass tables of the transform's later passes, [r][k]
+    const int R2 = ps::fft_radix2(p->log2n), R3 = ps::fft_radix3(p->log2n);
+    const int pass_r[2] = {R2, R3}, pass_ns[2] = {16, 16 * R2};
+    for (int q = 0; q < 2; ++q)
+        for (int r = 0; r < pass_r[q]; ++r)
+            for (int k = 0; k < pass_ns[q]; ++k) {
+                const double ang = two_pi * r * k / ((double)pass_r[q] * pass_ns[q]);
+                tw.push_back(make_float2((float)std::cos(ang), (float)std::sin(ang)));
+            }
 
     // Output tiles: upper triangle (kt <= lt) for symmetric spectra, all otherwise.
     // Tiles in 8 x 8 blocks: the consecutive tiles that one XCD processes at a

@@ -15,9 +15,11 @@
 // the windowed samples from global memory straight into registers.  LDS holds
 // X with one padding entry per 16 (index i at i + i/16), which keeps the
 // first pass's 16-strided writes free of bank conflicts.  A 256-thread block
-// transforms 256/T frames.  Twiddles come from a table exp(+2 pi j t / N)
-// computed in FP64 on the host.  The stage streams N samples in and K complex
-// values out per frame: it is bound by HBM bandwidth, not arithmetic.
+// transforms 256/T frames.  Twiddles come from tables computed in FP64 on the
+// host: exp(+2 pi j t / N) for the unpack, and one table per later pass laid
+// out [r][k], so that the twiddles of consecutive threads are consecutive
+// entries (a gather from the plain table touches up to one cache line per
+// lane).  The stage streams N samples in and K complex values out per frame.
 #include "ps_internal.h"
 
 namespace ps {
@@ -128,31 +130,39 @@ __device__ __forceinline__ float2 sample_pair<int16_t>(const int16_t* __restrict
 template <typename T>
 __device__ __forceinline__ void load_first(float2 (&v)[16], const T* __restrict__ xf, const float* __restrict__ g,
                                            int t, int Tn, bool live) {
-    const bool vec = (reinterpret_cast<uintptr_t>(xf) % (2 * sizeof(T))) == 0;
+    if (!live) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
+        return;
+    }
+    // One branch per frame (the alignment is the frame's), not one per load.
+    float2 x[16];
+    if ((reinterpret_cast<uintptr_t>(xf) % (2 * sizeof(T))) == 0) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = sample_pair(xf, t + r * Tn, true);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[r] = sample_pair(xf, t + r * Tn, false);
+    }
     const float2* __restrict__ g2 = reinterpret_cast<const float2*>(g);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-        const int n = t + r * Tn;
-        if (live) {
-            const float2 x = sample_pair(xf, n, vec), w = g2[n];
-            v[r] = make_float2(w.x * x.x, w.y * x.y);
-        } else {
-            v[r] = make_float2(0.f, 0.f);
-        }
+        const float2 w = g2[t + r * Tn];
+        v[r] = make_float2(w.x * x[r].x, w.y * x[r].y);
     }
 }
 
 // Twiddles of a Stockham pass of radix R and span Ns (see fft_pass) for the
-// butterflies of thread t: w[b R + r] = exp(+2 pi j r k / (R Ns)), k = j mod Ns.
+// butterflies of thread t: w[b R + r] = exp(+2 pi j r k / (R Ns)), k = j mod Ns,
+// from the pass's table tbl[r Ns + k] (consecutive threads read consecutive k).
 template <int LOG2M, int R>
-__device__ __forceinline__ void pass_twiddles(float2 (&w)[16], int t, int Ns, const float2* __restrict__ tw) {
-    constexpr int M = 1 << LOG2M, Tn = M / 16, B = 16 / R, N = 2 * M;
+__device__ __forceinline__ void pass_twiddles(float2 (&w)[16], int t, int Ns, const float2* __restrict__ tbl) {
+    constexpr int M = 1 << LOG2M, Tn = M / 16, B = 16 / R;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const int k = (t + b * Tn) & (Ns - 1);
-        const int step = k * (N / (R * Ns));
 #pragma unroll
-        for (int r = 1; r < R; ++r) w[b * R + r] = tw[r * step];
+        for (int r = 1; r < R; ++r) w[b * R + r] = tbl[r * Ns + k];
     }
 }
 
@@ -188,14 +198,13 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[16], const float2 (&w)[16],
 }
 
 template <int LOG2N>
-__global__ __launch_bounds__(kFftThreads) void k_window_rfft(FftArgs a) {
+__global__ __launch_bounds__(kFftThreads, 4) void k_window_rfft(FftArgs a) {
     constexpr int N = 1 << LOG2N;
     constexpr int LOG2M = LOG2N - 1;
     constexpr int M = N / 2, Tn = M / 16, F = kFftThreads / Tn;
     constexpr int P16 = LOG2M / 4, REM = LOG2M % 4;
     // radices of the passes after the first (0: none)
-    constexpr int R2 = P16 >= 2 ? 16 : (REM ? (1 << REM) : 0);
-    constexpr int R3 = P16 >= 3 ? 16 : (P16 == 2 && REM ? (1 << REM) : 0);
+    constexpr int R2 = fft_radix2(LOG2N), R3 = fft_radix3(LOG2N);
     static_assert(P16 <= 3 && !(P16 == 3 && REM), "frame length up to 8192");
     __shared__ float2 lds[kFftLds];
 
@@ -220,13 +229,13 @@ __global__ __launch_bounds__(kFftThreads) void k_window_rfft(FftArgs a) {
 
     // Each pass's twiddles are requested one pass ahead of their use.
     float2 v[16], w2[16], w3[16];
-    if constexpr (R2 > 0) pass_twiddles<LOG2M, R2>(w2, t, 16, tw);
+    if constexpr (R2 > 0) pass_twiddles<LOG2M, R2>(w2, t, 16, tw + N);
     if (rec.dtype == 0) load_first(v, static_cast<const float*>(rec.data) + off, g, t, Tn, live);
     else if (rec.dtype == 1) load_first(v, static_cast<const double*>(rec.data) + off, g, t, Tn, live);
     else load_first(v, static_cast<const int16_t*>(rec.data) + off, g, t, Tn, live);
 
     fft_pass<LOG2M, 16, true>(v, w2, s, t, 1);
-    if constexpr (R3 > 0) pass_twiddles<LOG2M, R3>(w3, t, 16 * R2, tw);
+    if constexpr (R3 > 0) pass_twiddles<LOG2M, R3>(w3, t, 16 * R2, tw + N + 16 * R2);
     if constexpr (R2 > 0) fft_pass<LOG2M, R2, false>(v, w2, s, t, 16);
     if constexpr (R3 > 0) fft_pass<LOG2M, R3, false>(v, w3, s, t, 16 * R2);
 

@@ -53,12 +53,27 @@ struct FftArgs {
     int log2n;              // log2(N), 8..13
     int K;                  // coefficients kept per frame
     const float* g;         // window [N]
-    const float2* tw;       // exp(+2 pi j t / N), t < N
+    const float2* tw;       // twiddles, see fft_twiddle_count
     float2* out;            // [C][rows][K]
     int64_t out_chan_stride;
     int dtype;              // common dtype of the records (launch template)
 };
 hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s);
+
+// Radices of the second and third pass of the frame transform (M = N/2 points:
+// radix 16 first, then radix 16 while whole powers of 16 remain, then one
+// radix 2/4/8 pass for the rest; 0 = no such pass).  The twiddle table `tw`
+// holds exp(+2 pi j t / N), t < N, followed by one table per later pass of
+// radix R and span Ns, laid out [r][k] (r < R, k < Ns): exp(+2 pi j r k / (R Ns)).
+__host__ __device__ constexpr int fft_radix2(int log2n) {
+    return (log2n - 1) / 4 >= 2 ? 16 : ((log2n - 1) % 4 ? 1 << ((log2n - 1) % 4) : 0);
+}
+__host__ __device__ constexpr int fft_radix3(int log2n) {
+    return (log2n - 1) / 4 >= 3 ? 16 : ((log2n - 1) / 4 == 2 && (log2n - 1) % 4 ? 1 << ((log2n - 1) % 4) : 0);
+}
+__host__ __device__ constexpr int fft_twiddle_count(int log2n) {
+    return (1 << log2n) + fft_radix2(log2n) * 16 + fft_radix3(log2n) * 16 * fft_radix2(log2n);
+}
 
 // In-place centring: a_k(f) -= mean over the m frames of its chunk.
 struct CentreArgs {
