@@ -244,6 +244,48 @@ ps_status ps_coefficients(ps_plan_t plan, const ps_record* rec, float* d_coef, p
 ps_status ps_profile_enable(ps_plan_t plan, int32_t on);
 ps_status ps_profile_read(ps_plan_t plan, double* stage_ms, int32_t n);
 
+/* Launch configuration of the moment stages.  These change how fast
+ * ps_execute runs, not
+ * what it computes: the spectra agree to the order of FP64 additions (the
+ * tiles split across blocks, whose partial sums are added separately, depend
+ * on the tile order).
+ *   tile_group      the output tiles of a spectrum are walked in
+ *                   tile_group x tile_group blocks of tiles (1 = row by row);
+ *                   1, 2, 4, 8 (default) or 16.  Larger blocks keep the
+ *                   coefficient columns that concurrent blocks read in L2.
+ *   s3_frame_batch  frames staged per LDS batch by the S3 kernel: 10 or 16, or
+ *                   0 (default) to choose by m (10 when m <= 10 or m is a
+ *                   multiple of 10, else 16).
+ * ps_plan_set_tuning rewrites the plan's tile tables in device memory
+ * (synchronously): no execute or graph launch of the plan may be in flight.
+ * Graphs captured earlier use the new order from their next launch.  Errors:
+ * PS_E_INVALID_ARG for NULL or values outside the lists above. */
+typedef struct ps_tuning {
+    int32_t tile_group;
+    int32_t s3_frame_batch;
+} ps_tuning;
+ps_status ps_plan_get_tuning(ps_plan_t plan, ps_tuning* t);
+ps_status ps_plan_set_tuning(ps_plan_t plan, const ps_tuning* t);
+
+/* Autotuner: times every candidate configuration (tile_group 1, 4, 8, 16;
+ * with S3 requested and m > 10 also both S3 frame batches) with one warm-up
+ * and `reps` (1..100) timed ps_execute calls on the caller's records,
+ * workspace and outputs (arguments as for ps_execute; the outputs end up
+ * holding the last run's spectra), measured with HIP events on `stream`, and
+ * keeps the fastest in the plan.  Synchronises the stream; the same rule as
+ * for ps_plan_set_tuning applies.  `report` (may be NULL) receives the
+ * candidates, the mean milliseconds per execute of each and the index of the
+ * one kept. */
+#define PS_TUNE_MAX 16
+typedef struct ps_tune_report {
+    int32_t n;
+    int32_t best;
+    ps_tuning cand[PS_TUNE_MAX];
+    double ms[PS_TUNE_MAX];
+} ps_tune_report;
+ps_status ps_plan_autotune(ps_plan_t plan, const ps_record* recs, int32_t n_rec, void* d_ws, size_t ws_bytes,
+                           const ps_output* outs, int32_t reps, ps_stream_t stream, ps_tune_report* report);
+
 /* Host only: the "every orbit" combination list of `order` (2, 3 or 4) for
  * n_channels (1..4) channels, in the order ps_plan_create uses.  With out ==
  * NULL only the count is returned in *n; otherwise *n is the capacity of `out`

@@ -25,7 +25,9 @@ EXPORTED = (
     "ps_enumerate_combos", "ps_profile_enable", "ps_profile_read", "ps_graph_create",
     "ps_graph_launch", "ps_graph_destroy", "ps_streamer_create", "ps_streamer_push",
     "ps_streamer_wait", "ps_streamer_destroy", "ps_streamer_create_multi", "ps_streamer_push_multi",
+    "ps_plan_get_tuning", "ps_plan_set_tuning", "ps_plan_autotune",
 )
+PS_TUNE_MAX = 16
 
 
 class ps_config(C.Structure):
@@ -58,6 +60,15 @@ class ps_plan_info(C.Structure):
         ("combos2", C.POINTER(C.c_int8)), ("combos3", C.POINTER(C.c_int8)),
         ("combos4", C.POINTER(C.c_int8)),
     ]
+
+
+class ps_tuning(C.Structure):
+    _fields_ = [("tile_group", C.c_int32), ("s3_frame_batch", C.c_int32)]
+
+
+class ps_tune_report(C.Structure):
+    _fields_ = [("n", C.c_int32), ("best", C.c_int32), ("cand", ps_tuning * PS_TUNE_MAX),
+                ("ms", C.c_double * PS_TUNE_MAX)]
 
 
 _lib = None
@@ -97,6 +108,10 @@ def load() -> C.CDLL:
     lib.ps_streamer_destroy.argtypes = [vp]
     lib.ps_streamer_create_multi.argtypes = [vp, i64, i32, i32, i32, C.POINTER(vp)]
     lib.ps_streamer_push_multi.argtypes = [vp, vp, i32, C.POINTER(ps_output), vp, C.POINTER(i32)]
+    lib.ps_plan_get_tuning.argtypes = [vp, C.POINTER(ps_tuning)]
+    lib.ps_plan_set_tuning.argtypes = [vp, C.POINTER(ps_tuning)]
+    lib.ps_plan_autotune.argtypes = [vp, C.POINTER(ps_record), i32, vp, sz, C.POINTER(ps_output), i32, vp,
+                                     C.POINTER(ps_tune_report)]
     for name in ("ps_plan_create", "ps_plan_destroy", "ps_plan_query", "ps_record_info",
                  "ps_workspace_size", "ps_execute", "ps_coefficients", "ps_enumerate_combos",
                  "ps_profile_enable", "ps_profile_read", "ps_graph_create", "ps_graph_launch",

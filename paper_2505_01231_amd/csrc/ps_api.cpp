@@ -83,6 +83,22 @@ void all_combos(int C, std::vector<int8_t>& c2, std::vector<int8_t>& c3, std::ve
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Output tiles: upper triangle (kt <= lt) for symmetric spectra, all
+// otherwise, walked in G x G blocks of tiles: the consecutive tiles that one
+// XCD processes at a time then share their k and l columns (and part of the
+// k + l range) in that XCD's L2, instead of spanning whole tile rows.
+void tile_order(int T, int G, std::vector<int2>& sym, std::vector<int2>& full) {
+    sym.clear();
+    full.clear();
+    for (int bk = 0; bk < T; bk += G)
+        for (int bl = 0; bl < T; bl += G)
+            for (int kt = bk; kt < std::min(T, bk + G); ++kt)
+                for (int lt = bl; lt < std::min(T, bl + G); ++lt) {
+                    full.push_back(make_int2(kt, lt));
+                    if (kt <= lt) sym.push_back(make_int2(kt, lt));
+                }
+}
+
 }  // namespace
 
 struct ps_plan_s {
@@ -98,6 +114,9 @@ struct ps_plan_s {
     float2* d_tw = nullptr;
     int2* d_tiles[4] = {nullptr, nullptr, nullptr, nullptr};
     int n_cu = 256, bpc_s3 = 2, bpc_s4 = 2, bpc_s4x = 2;
+    // Launch configuration (ps_plan_set_tuning / ps_plan_autotune).
+    int tile_group = 8;     // tile order: tile_group x tile_group blocks
+    int s3_fb = 0;          // S3 frame batch; 0: chosen by m
     // Pinned host staging of the per-execute work tables (two, used in turn;
     // an event guards reuse until the copy that read it has finished).
     char* h_stage[2] = {nullptr, nullptr};
@@ -556,25 +575,11 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
                 tw.push_back(make_float2((float)std::cos(ang), (float)std::sin(ang)));
             }
 
-    // Output tiles: upper triangle (kt <= lt) for symmetric spectra, all otherwise.
-    // Tiles in 8 x 8 blocks: the consecutive tiles that one XCD processes at a
-    // time then share their k and l columns (and half of the k + l range) in
-    // that XCD's L2, instead of spanning whole tile rows.
-    auto make_tiles = [](int T, std::vector<int2>& sym, std::vector<int2>& full) {
-        constexpr int G = 8;
-        for (int bk = 0; bk < T; bk += G)
-            for (int bl = 0; bl < T; bl += G)
-                for (int kt = bk; kt < std::min(T, bk + G); ++kt)
-                    for (int lt = bl; lt < std::min(T, bl + G); ++lt) {
-                        full.push_back(make_int2(kt, lt));
-                        if (kt <= lt) sym.push_back(make_int2(kt, lt));
-                    }
-    };
     p->T = (Nf + ps::kTile - 1) / ps::kTile;
     p->TX = (Nf + ps::kTileX - 1) / ps::kTileX;
     std::vector<int2> tiles[4];
-    make_tiles(p->T, tiles[ps::kSym64], tiles[ps::kFull64]);
-    make_tiles(p->TX, tiles[ps::kSym32], tiles[ps::kFull32]);
+    tile_order(p->T, p->tile_group, tiles[ps::kSym64], tiles[ps::kFull64]);
+    tile_order(p->TX, p->tile_group, tiles[ps::kSym32], tiles[ps::kFull32]);
     for (int i = 0; i < 4; ++i) p->n_tiles[i] = (int)tiles[i].size();
 
     auto upload = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
@@ -601,6 +606,103 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
                                                  : ps::s4_mfma_f16_blocks_per_cu();
     p->bpc_s4x = p->precision == PS_PREC_BF16X3 ? ps::s4_cross_mfma_blocks_per_cu() : ps::s4_cross_blocks_per_cu();
     *out = p;
+    return PS_OK;
+}
+
+// ------------------------------------------------------------ launch configuration
+namespace {
+hipError_t write_tiles(ps_plan_t p) {
+    std::vector<int2> tiles[4];
+    tile_order(p->T, p->tile_group, tiles[ps::kSym64], tiles[ps::kFull64]);
+    tile_order(p->TX, p->tile_group, tiles[ps::kSym32], tiles[ps::kFull32]);
+    for (int i = 0; i < 4; ++i) {
+        if (tiles[i].empty()) continue;
+        const hipError_t e = hipMemcpy(p->d_tiles[i], tiles[i].data(), tiles[i].size() * sizeof(int2),
+                                       hipMemcpyHostToDevice);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+bool valid_tuning(const ps_tuning& t) {
+    const bool g = t.tile_group == 1 || t.tile_group == 2 || t.tile_group == 4 || t.tile_group == 8 ||
+                   t.tile_group == 16;
+    const bool f = t.s3_frame_batch == 0 || t.s3_frame_batch == ps::kFrameBatchSmall ||
+                   t.s3_frame_batch == ps::kFrameBatch;
+    return g && f;
+}
+}  // namespace
+
+ps_status ps_plan_get_tuning(ps_plan_t p, ps_tuning* t) {
+    if (!p || !t) return fail(PS_E_INVALID_ARG, "NULL argument");
+    t->tile_group = p->tile_group;
+    t->s3_frame_batch = p->s3_fb;
+    return PS_OK;
+}
+
+ps_status ps_plan_set_tuning(ps_plan_t p, const ps_tuning* t) {
+    if (!p || !t) return fail(PS_E_INVALID_ARG, "NULL argument");
+    if (!valid_tuning(*t))
+        return fail(PS_E_INVALID_ARG, "tuning: tile_group %d (1, 2, 4, 8 or 16), s3_frame_batch %d (0, %d or %d)",
+                    t->tile_group, t->s3_frame_batch, ps::kFrameBatchSmall, ps::kFrameBatch);
+    p->s3_fb = t->s3_frame_batch;
+    if (t->tile_group != p->tile_group) {
+        p->tile_group = t->tile_group;
+        PS_HIP(write_tiles(p));
+    }
+    return PS_OK;
+}
+
+ps_status ps_plan_autotune(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_ws, size_t ws_bytes,
+                           const ps_output* outs, int32_t reps, ps_stream_t stream, ps_tune_report* report) {
+    if (!p || !recs || n_rec <= 0 || !outs) return fail(PS_E_INVALID_ARG, "autotune: NULL or empty argument");
+    if (reps < 1 || reps > 100) return fail(PS_E_INVALID_ARG, "autotune: reps = %d (1..100)", reps);
+    hipStream_t st = (hipStream_t)stream;
+    ps_tuning cand[PS_TUNE_MAX];
+    int n = 0;
+    const int groups[4] = {1, 4, 8, 16};
+    // The S3 frame batch matters when a chunk does not fit one small batch.
+    const bool fb_choice = p->has(3) && p->m > ps::kFrameBatchSmall;
+    for (int g : groups) {
+        if (fb_choice) {
+            cand[n++] = ps_tuning{g, ps::kFrameBatchSmall};
+            cand[n++] = ps_tuning{g, ps::kFrameBatch};
+        } else {
+            cand[n++] = ps_tuning{g, 0};
+        }
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PS_HIP(hipEventCreate(&e0));
+    PS_HIP(hipEventCreate(&e1));
+    double ms[PS_TUNE_MAX];
+    int best = 0;
+    ps_status rc = PS_OK;
+    for (int i = 0; i < n && rc == PS_OK; ++i) {
+        if ((rc = ps_plan_set_tuning(p, &cand[i])) != PS_OK) break;
+        if ((rc = ps_execute(p, recs, n_rec, d_ws, ws_bytes, outs, stream)) != PS_OK) break;     // warm-up
+        if (hipEventRecord(e0, st) != hipSuccess) rc = fail(PS_E_HIP, "autotune: hipEventRecord failed");
+        for (int r = 0; r < reps && rc == PS_OK; ++r) rc = ps_execute(p, recs, n_rec, d_ws, ws_bytes, outs, stream);
+        if (rc != PS_OK) break;
+        float el = 0.f;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&el, e0, e1) != hipSuccess) {
+            rc = fail(PS_E_HIP, "autotune: event timing failed");
+            break;
+        }
+        ms[i] = el / reps;
+        if (ms[i] < ms[best]) best = i;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc != PS_OK) return rc;
+    if ((rc = ps_plan_set_tuning(p, &cand[best])) != PS_OK) return rc;
+    if (report) {
+        report->n = n;
+        report->best = best;
+        for (int i = 0; i < n; ++i) {
+            report->cand[i] = cand[i];
+            report->ms[i] = ms[i];
+        }
+    }
     return PS_OK;
 }
 
@@ -740,6 +842,7 @@ ps::BatchArgs batch_args(const ps_plan_s* p, const Batch& B, const SegTable& t, 
     a.win_hi = win_hi;
     a.accumulate = accumulate;
     a.gamma = (p->m - 1.0) / (p->m * (p->m + 1.0));
+    a.s3_fb = p->s3_fb;
     return a;
 }
 

@@ -151,6 +151,7 @@ struct BatchArgs {
     int per_chunk, win_lo, win_hi;
     int accumulate;         // add to the partial sums instead of overwriting
     double gamma;           // S4: (m-1)/(m(m+1))
+    int s3_fb;              // S3 frames per LDS batch (kFrameBatchSmall or kFrameBatch); 0: chosen by m
 };
 hipError_t launch_s2(const BatchArgs& a, hipStream_t s);
 hipError_t launch_s3(const BatchArgs& a, hipStream_t s);

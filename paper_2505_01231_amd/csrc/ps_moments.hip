@@ -1221,7 +1221,8 @@ bool s3_small_batch(int m) { return m <= kFrameBatchSmall || m % kFrameBatchSmal
 
 hipError_t launch_s3(const BatchArgs& a, hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;
-    if (s3_small_batch(a.m))
+    const int fb = a.s3_fb ? a.s3_fb : (s3_small_batch(a.m) ? kFrameBatchSmall : kFrameBatch);
+    if (fb == kFrameBatchSmall)
         k_s3<kFrameBatchSmall><<<item_grid(a), kS3Threads, 0, s>>>(a);
     else
         k_s3<kFrameBatch><<<item_grid(a), kS3Threads, 0, s>>>(a);

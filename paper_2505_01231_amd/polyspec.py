@@ -219,6 +219,48 @@ class Plan:
                                           outs, C.byref(h)), "ps_graph_create")
         return Graph(self, h, list(xs), workspace, outputs[0] if single else outputs)
 
+    @property
+    def tuning(self) -> dict:
+        """The launch configuration (ps_plan_get_tuning)."""
+        t = L.ps_tuning()
+        L.check(self._lib.ps_plan_get_tuning(self._handle, C.byref(t)), "ps_plan_get_tuning")
+        return {"tile_group": t.tile_group, "s3_frame_batch": t.s3_frame_batch}
+
+    def set_tuning(self, tile_group: int = 8, s3_frame_batch: int = 0):
+        """Set the launch configuration (ps_plan_set_tuning); no execute of this
+        plan may be in flight."""
+        t = L.ps_tuning(tile_group, s3_frame_batch)
+        L.check(self._lib.ps_plan_set_tuning(self._handle, C.byref(t)), "ps_plan_set_tuning")
+
+    def autotune(self, xs, reps: int = 3, workspace: torch.Tensor | None = None, outputs=None, stream=None) -> dict:
+        """Time the candidate launch configurations on these records and keep the
+        fastest (ps_plan_autotune).  Returns {"best": tuning, "candidates":
+        [(tuning, ms per execute), ...]}; the outputs hold the last run."""
+        single = isinstance(xs, torch.Tensor)
+        if single:
+            xs = [xs]
+        device = xs[0].device
+        recs = (L.ps_record * len(xs))(*[self.record(x) for x in xs])
+        need = C.c_size_t()
+        L.check(self._lib.ps_workspace_size(self._handle, recs, len(xs), C.byref(need)), "ps_workspace_size")
+        if workspace is None or workspace.numel() < need.value:
+            workspace = torch.empty(need.value, dtype=torch.uint8, device=device)
+        if outputs is None:
+            outputs = [self.allocate_outputs(device) for _ in xs]
+        outs = (L.ps_output * len(xs))()
+        for i, o in enumerate(outputs):
+            o.n_chunks, o.flags = self.record_info(recs[i].n_samples)
+            outs[i] = L.ps_output(self._ptr(o.s2), self._ptr(o.s2_err), self._ptr(o.s3),
+                                  self._ptr(o.s3_err), self._ptr(o.s4), self._ptr(o.s4_err))
+        st = torch.cuda.current_stream(device) if stream is None else stream
+        rep = L.ps_tune_report()
+        L.check(self._lib.ps_plan_autotune(self._handle, recs, len(xs), workspace.data_ptr(), workspace.numel(),
+                                           outs, int(reps), C.c_void_p(st.cuda_stream), C.byref(rep)),
+                "ps_plan_autotune")
+        cands = [({"tile_group": rep.cand[i].tile_group, "s3_frame_batch": rep.cand[i].s3_frame_batch}, rep.ms[i])
+                 for i in range(rep.n)]
+        return {"best": cands[rep.best][0], "candidates": cands}
+
     STAGES = ("fft", "mean", "s2", "s3", "s4", "finalize")
 
     def profile(self, on: bool = True):

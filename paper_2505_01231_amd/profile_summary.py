@@ -40,7 +40,8 @@ def s3_source_digest() -> str:
     with open(os.path.join(csrc, "ps_api.cpp")) as f:
         api = f.read()
     pats = [
-        (api, r"auto make_tiles = \[\]\(.*?\n    \};\n"),
+        (api, r"void tile_order\(.*?\n\}\n"),
+        (api, r"int tile_group = \d+;"),
         (api, r"int64_t units_per_block\(.*?\n\}\n"),
         (api, r"int32_t seg_blocks\(.*?\n\}\n"),
         (inc, r"__device__ __forceinline__ void lds_barrier\(\) \{.*?\n\}\n"),

@@ -50,6 +50,9 @@ int main(void) {
   printf("ps_record %zu\n", sizeof(ps_record));
   printf("ps_output %zu\n", sizeof(ps_output));
   printf("ps_plan_info %zu\n", sizeof(ps_plan_info));
+  printf("ps_tuning %zu\n", sizeof(ps_tuning));
+  printf("ps_tune_report %zu\n", sizeof(ps_tune_report));
+  P(ps_tuning, s3_frame_batch) P(ps_tune_report, cand) P(ps_tune_report, ms)
   P(ps_config, dt) P(ps_config, window) P(ps_config, n_combos4) P(ps_config, combos2) P(ps_config, combos4)
   P(ps_record, n_samples) P(ps_record, dtype) P(ps_output, d_s4_err)
   P(ps_plan_info, f_max) P(ps_plan_info, sum_g) P(ps_plan_info, combos4)
@@ -68,6 +71,7 @@ def test_ctypes_layouts_match_header(tmp_path):
     py = {
         "ps_config": C.sizeof(L.ps_config), "ps_record": C.sizeof(L.ps_record),
         "ps_output": C.sizeof(L.ps_output), "ps_plan_info": C.sizeof(L.ps_plan_info),
+        "ps_tuning": C.sizeof(L.ps_tuning), "ps_tune_report": C.sizeof(L.ps_tune_report),
     }
     for k, v in py.items():
         assert int(got[k]) == v, k
@@ -161,3 +165,14 @@ def test_combination_orbits(n_ch, order):
         assert len(got) == {2: 10, 3: 40, 4: 76}[order]
     # every ordered combination is reachable from exactly one representative
     assert len(set(got)) == len(got)
+
+
+def test_tuning_calls_reject_null_arguments():
+    """The launch-configuration calls validate their arguments on the host."""
+    lib = L.load()
+    t = L.ps_tuning(8, 0)
+    assert lib.ps_plan_get_tuning(None, C.byref(t)) == L.PS_E_INVALID_ARG
+    assert lib.ps_plan_set_tuning(None, C.byref(t)) == L.PS_E_INVALID_ARG
+    rep = L.ps_tune_report()
+    assert lib.ps_plan_autotune(None, None, 0, None, 0, None, 3, None, C.byref(rep)) == L.PS_E_INVALID_ARG
+    assert "NULL" in L.last_error()

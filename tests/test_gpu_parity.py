@@ -434,6 +434,78 @@ def test_graph_replays_match_eager(dev, precision):
         g.close()
 
 
+# ---------------------------------------------------------------- launch configuration (autotuner)
+def _tuning_case(dev):
+    """Two channels (every S3/S4 orbit, so all four tile tables are used), a
+    ragged grid (N_f = 200: 4 tiles of 64, 7 of 32) and m = 12, where the S3
+    frame batch is a real choice."""
+    s = synth.ar2_chi2(1024 * 12 * 4 + 9, seed=77, r=0.9, dtype=np.float32)
+    z = np.stack([s[:-9], (s[9:] ** 2 - 1.0 + 0.3 * s[:-9]).astype(np.float32)])
+    return z, torch.from_numpy(np.ascontiguousarray(z)).to(dev)
+
+
+def _spectra(out):
+    return {k: getattr(out, k).cpu().numpy() for k in ("s2", "s3", "s4", "s2_err", "s3_err", "s4_err")}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_tuning_configurations_agree(dev, precision):
+    """Every tile order and S3 frame batch computes the same spectra up to the
+    order of FP64 additions; the default configuration equals the oracle."""
+    from paper_2505_01231_amd import Plan
+    say("tuning configurations", precision)
+    z, x = _tuning_case(dev)
+    with Plan(frame_len=1024, n_freq=200, m=12, window="acg", n_channels=2, precision=precision) as p:
+        assert p.tuning == {"tile_group": 8, "s3_frame_batch": 0}
+        base = _spectra(p.execute(x))
+        torch.cuda.synchronize()
+        ref = O.polyspectra(z, 1024, 200, 12, window_kind="acg", combos2=p.combos2, combos3=p.combos3,
+                            combos4=p.combos4)
+        for key in ("s2", "s3", "s4"):
+            got = base[key][..., 0] + 1j * base[key][..., 1]
+            assert rel_err(got, ref[key]) <= TOL, key
+        for g in (1, 2, 4, 16):
+            for fb in (10, 16):
+                p.set_tuning(g, fb)
+                assert p.tuning == {"tile_group": g, "s3_frame_batch": fb}
+                out = _spectra(p.execute(x))
+                torch.cuda.synchronize()
+                for key, b in base.items():
+                    assert rel_err(out[key], b) <= 1e-12, (g, fb, key, rel_err(out[key], b))
+        p.set_tuning(8, 0)
+
+
+def test_autotune_keeps_the_fastest(dev):
+    """ps_plan_autotune times all candidates, keeps the fastest in the plan and
+    leaves the results unchanged up to FP64 addition order; bad values are
+    rejected without changing the configuration."""
+    from paper_2505_01231_amd import Plan
+    from paper_2505_01231_amd._lib import PolyspecError
+    say("autotune")
+    z, x = _tuning_case(dev)
+    with Plan(frame_len=1024, n_freq=200, m=12, window="acg", n_channels=2, precision="bf16x3") as p:
+        base = _spectra(p.execute(x))
+        rep = p.autotune(x, reps=2)
+        torch.cuda.synchronize()
+        cands = rep["candidates"]
+        say("  candidates", [(c["tile_group"], c["s3_frame_batch"], round(ms, 3)) for c, ms in cands])
+        assert len(cands) == 8                      # 4 tile orders x 2 S3 frame batches (m > 10)
+        assert {(c["tile_group"], c["s3_frame_batch"]) for c, _ in cands} == \
+            {(g, fb) for g in (1, 4, 8, 16) for fb in (10, 16)}
+        assert all(ms > 0 for _, ms in cands)
+        fastest = min(cands, key=lambda c: c[1])[0]
+        assert rep["best"] == fastest == p.tuning
+        out = _spectra(p.execute(x))
+        torch.cuda.synchronize()
+        for key, b in base.items():
+            assert rel_err(out[key], b) <= 1e-12, key
+        kept = p.tuning
+        for bad in ((3, 0), (8, 12), (0, 10)):
+            with pytest.raises(PolyspecError):
+                p.set_tuning(*bad)
+            assert p.tuning == kept
+
+
 # ---------------------------------------------------------------- streaming (quasi-polyspectra)
 def test_streamer_time_resolved_windows(dev):
     """Consecutive windows of a host stream whose chi-square drive amplitude
