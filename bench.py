@@ -113,7 +113,8 @@ def run_batching(torch, dev, precision):
             grp = [recs[i:i + per_group] for i in range(0, len(recs), per_group)]
             ws = torch.empty(max(p.workspace_bytes(g) for g in grp), dtype=torch.uint8, device=dev)
             outs = [p.allocate_outputs(dev) for _ in range(per_group)]
-            p.execute(grp[0], workspace=ws, outputs=outs[:len(grp[0])])      # warm-up
+            # autotuner (also the warm-up): tile order timed on the first group
+            tune = p.autotune(grp[0], reps=1, workspace=ws, outputs=outs[:len(grp[0])])
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for g in grp:
@@ -122,7 +123,9 @@ def run_batching(torch, dev, precision):
             dt = time.perf_counter() - t0
             ns = sum(int(x.shape[1]) * 4 for x in recs)
             per_n[str(n)] = {"records": len(recs), "groups": len(grp), "channel_samples": ns,
-                             "seconds": dt, "channel_samples_per_s": ns / dt}
+                             "seconds": dt, "channel_samples_per_s": ns / dt,
+                             "tuning": tune["best"],
+                             "tuning_ms": {str(c["tile_group"]): round(ms, 3) for c, ms in tune["candidates"]}}
             total_samples += ns
             total_time += dt
             groups += len(grp)
@@ -130,7 +133,9 @@ def run_batching(torch, dev, precision):
         log(f"batching N={n}: {per_n[str(n)]['channel_samples_per_s']:.3e} channel-samples/s")
     return {"records": 24, "channels": 4, "combinations": [10, 40, 76], "executes": groups,
             "channel_samples_per_s": total_samples / total_time, "per_frame_length": per_n,
-            "note": "each ps_execute runs every stage as one launch over its records x combinations"}
+            "note": "each ps_execute runs every stage as one launch over its records x combinations; "
+                    "tile order per frame length chosen by ps_plan_autotune (ms per execute of the "
+                    "first group by tile_group)"}
 
 
 def run_streaming(torch, dev, precision, n_windows=64, pool=16, per_push=8, depth=3):
