@@ -227,7 +227,8 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_window_rfft(FftArgs a) {
     const float* __restrict__ g = a.g;
     const float2* __restrict__ tw = a.tw;
 
-    // Each pass's twiddles are requested one pass ahead of their use.
+    // The second pass's twiddles are requested before the samples, the third
+    // pass's just before its LDS reads (one pass ahead they spill registers).
     float2 v[16], w2[16], w3[16];
     if constexpr (R2 > 0) pass_twiddles<LOG2M, R2>(w2, t, 16, tw + N);
     if (rec.dtype == 0) load_first(v, static_cast<const float*>(rec.data) + off, g, t, Tn, live);
@@ -235,8 +236,8 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_window_rfft(FftArgs a) {
     else load_first(v, static_cast<const int16_t*>(rec.data) + off, g, t, Tn, live);
 
     fft_pass<LOG2M, 16, true>(v, w2, s, t, 1);
-    if constexpr (R3 > 0) pass_twiddles<LOG2M, R3>(w3, t, 16 * R2, tw + N + 16 * R2);
     if constexpr (R2 > 0) fft_pass<LOG2M, R2, false>(v, w2, s, t, 16);
+    if constexpr (R3 > 0) pass_twiddles<LOG2M, R3>(w3, t, 16 * R2, tw + N + 16 * R2);
     if constexpr (R3 > 0) fft_pass<LOG2M, R3, false>(v, w3, s, t, 16 * R2);
 
     if (!live) return;
