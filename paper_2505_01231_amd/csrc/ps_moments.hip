@@ -545,9 +545,13 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
     const int r32 = lane & 31, kh = lane >> 5;
     const int rowK = 32 * (w >> 1) + r32, rowL = 32 * (w & 1) + r32;
 
-    // Loader role: thread -> (side, column, half of the frame slots).
+    // Loader role: thread -> (side, column, half of the frame slots).  The LDS
+    // serves a wave's 32-bit writes in two lane groups, {0-15, 32-47} and
+    // {16-31, 48-63}; at the 144-byte row stride columns c and c + 16 share a
+    // bank, so lanes 32-47 take columns 8-15 and lanes 16-31 columns 16-23:
+    // each group then writes 16 consecutive columns, in distinct banks.
     const int side = __builtin_amdgcn_readfirstlane(tid >> 7);    // uniform per wave
-    const int col = (tid >> 1) & (kTile - 1);
+    const int col = 32 * (w & 1) + (((lane >> 1) & 7) | (((lane >> 5) & 1) << 3) | (((lane >> 4) & 1) << 4));
     const int half = tid & 1;
     uint32_t(*op)[kOpDw] = side ? opL : opK;
 
@@ -1071,8 +1075,11 @@ __global__ __launch_bounds__(kS4XMThreads, 2) void k_s4_cross_mfma(BatchArgs p) 
     const int rowA = 16 * (w >> 1) + li, rowB = 16 * (w & 1) + li;
 
     // Loader role: (side, column, frame residue q): frames q, q + 4, q + 8.
+    // Columns c and c + 8 share an LDS bank at the 160-byte row stride, so the
+    // lanes of each 32-bit write group ({0-15, 32-47}, {16-31, 48-63}) take
+    // eight consecutive columns (as in k_s4_mfma_bf16).
     const int side = __builtin_amdgcn_readfirstlane(tid >> 7);    // uniform per wave
-    const int col = (tid & 127) >> 2;
+    const int col = 16 * (w & 1) + (((lane >> 2) & 3) | (((lane >> 5) & 1) << 2) | (((lane >> 4) & 1) << 3));
     const int q = tid & 3;
     uint32_t(*op)[kOpDwX] = side ? opB : opA;
 
