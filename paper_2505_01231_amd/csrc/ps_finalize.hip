@@ -31,21 +31,36 @@ __device__ __forceinline__ void mean_sigma(double s, double s2, double np, doubl
     sigma = fabs(scale) * sqrt(fmax(var, 0.0) / np);
 }
 
-// S2: one block per (record, combination, 256-wide k block).
+// S2: one block per (record, combination, 16-wide k group of a 256-wide k
+// block).  Thread (g, kk) adds the slots s0 + g, s0 + g + 16, ... of point
+// kk; the 16 group sums are then added in LDS in group order (a fixed order,
+// so the result does not depend on timing).
+constexpr int kVecGroups = 16;
+
 __global__ __launch_bounds__(256) void k_finalize_vec(FinalizeArgs p) {
-    const int64_t x = blockIdx.x;
+    __shared__ double red[kVecGroups][4][16];
+    const int64_t x = blockIdx.x / kVecGroups;         // item: a 256-wide k block
     if (x >= p.n_items) return;
+    const int sub = blockIdx.x % kVecGroups;
     const Seg& sg = p.segs[find_seg(p.segs, p.n_segs, x)];
     const int64_t t = x - sg.item0;
-    const int k = (int)t * 256 + threadIdx.x;
-    if (k >= p.Nf) return;
-    const double* part = p.part + sg.part + threadIdx.x;
-    double s[4] = {0, 0, 0, 0};
+    const int kk = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int kl = 16 * sub + kk;                       // k within the item
+    const int k = (int)t * 256 + kl;
     int64_t s0 = 0, ns = 0;
     if (sg.n_chunks > 0) slot_range(Sched{sg.n_tiles, sg.n_chunks, sg.blocks}, t, s0, ns);
-    for (int64_t slot = s0; slot < s0 + ns; ++slot) {
+    double s[4] = {0, 0, 0, 0};
+    const double* part = p.part + sg.part + kl;
+    for (int64_t slot = s0 + g; slot < s0 + ns; slot += kVecGroups) {
         const double* q = part + slot * 4 * 256;
         for (int c = 0; c < 4; ++c) s[c] += q[c * 256];
+    }
+    for (int c = 0; c < 4; ++c) red[g][c][kk] = s[c];
+    __syncthreads();
+    if (g != 0 || k >= p.Nf) return;
+    for (int c = 0; c < 4; ++c) {
+        s[c] = 0;
+        for (int gg = 0; gg < kVecGroups; ++gg) s[c] += red[gg][c][kk];
     }
     const double np = (double)sg.n_chunks;
     double mr, sr, mi, si;
@@ -143,7 +158,7 @@ __global__ void k_fill_nan(double* p, int64_t n) {
 
 hipError_t launch_finalize_vec(const FinalizeArgs& a, hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;
-    k_finalize_vec<<<(unsigned)a.n_items, 256, 0, s>>>(a);
+    k_finalize_vec<<<(unsigned)(a.n_items * kVecGroups), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -125,6 +125,12 @@ __device__ __forceinline__ bool next_item(const BatchArgs& b, Block& bk, Item& i
 }
 
 // ------------------------------------------------------------------ S2
+// For one channel, chunks of up to kS2Regs frames are loaded whole before
+// their products (one round trip to memory per chunk, not one per frame); a
+// pair of channels keeps the per-frame loop (its two register arrays would
+// cost occupancy for a kernel of a few microseconds).
+constexpr int kS2Regs = 16;
+
 __global__ __launch_bounds__(256) void k_s2(BatchArgs p) {
     Block bk;
     View v;
@@ -135,15 +141,27 @@ __global__ __launch_bounds__(256) void k_s2(BatchArgs p) {
         if (k >= p.Nf) continue;
         const float2* A = v.coef + it.ch[0] * v.cs;
         const float2* B = v.coef + it.ch[1] * v.cs;
+        const bool same = it.ch[0] == it.ch[1];      // S2 of one channel: one load per frame
         double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
         for (int c = it.c0; c < it.c1; ++c) {
             const int64_t base = v.off + (int64_t)c * v.m * v.K + k;
             float re = 0.f, im = 0.f;
-            for (int f = 0; f < v.m; ++f) {
-                const float2 x = A[base + (int64_t)f * v.K];
-                const float2 y = B[base + (int64_t)f * v.K];
-                re += x.x * y.x + x.y * y.y;   // x * conj(y)
-                im += x.y * y.x - x.x * y.y;
+            if (v.m <= kS2Regs && same) {
+                // all loads of the chunk in flight at once; x conj(x) = |x|^2
+                float2 x[kS2Regs];
+#pragma unroll
+                for (int f = 0; f < kS2Regs; ++f)
+                    if (f < v.m) x[f] = A[base + (int64_t)f * v.K];
+#pragma unroll
+                for (int f = 0; f < kS2Regs; ++f)
+                    if (f < v.m) re += x[f].x * x[f].x + x[f].y * x[f].y;
+            } else {
+                for (int f = 0; f < v.m; ++f) {
+                    const float2 x = A[base + (int64_t)f * v.K];
+                    const float2 y = B[base + (int64_t)f * v.K];
+                    re += x.x * y.x + x.y * y.y;   // x * conj(y)
+                    im += x.y * y.x - x.x * y.y;
+                }
             }
             s0 += re;
             s1 += im;
