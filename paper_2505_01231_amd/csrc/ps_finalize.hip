@@ -103,13 +103,20 @@ __global__ __launch_bounds__(256) void k_finalize_tiles(FinalizeArgs p) {
     const int k = kb + i, l = lb + j;
     const bool valid = k < p.Nf && l < p.Nf && !(sg.sym && k > l);
     double mr = 0.0, sr = 0.0, mi = 0.0, si = 0.0;
+    // The point's offset inside the tile does not depend on the tile table,
+    // and every component of every slot is loaded before any is added (one
+    // round trip to memory, not one per component).
+    const int idx = (16 * (sb / sub) + i) * E + 16 * (sb % sub) + j;
+    double s[4] = {0, 0, 0, 0};
+    for (int64_t slot = s0; slot < s0 + ns; ++slot) {
+        const double* q = p.part + sg.part + slot * ncomp * TT + idx;
+        double v[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = c < ncomp ? q[c * TT] : 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s[c] += v[c];
+    }
     if (valid) {
-        const int idx = (k - t.x * E) * E + (l - t.y * E);
-        double s[4] = {0, 0, 0, 0};
-        for (int64_t slot = s0; slot < s0 + ns; ++slot) {
-            const double* q = p.part + sg.part + slot * ncomp * TT + idx;
-            for (int c = 0; c < ncomp; ++c) s[c] += q[c * TT];
-        }
         if (ncomp == 4) {
             mean_sigma(s[0], s[2], np, sg.scale, mr, sr);
             mean_sigma(s[1], s[3], np, sg.scale, mi, si);
