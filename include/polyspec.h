@@ -275,7 +275,9 @@ ps_status ps_plan_set_tuning(ps_plan_t plan, const ps_tuning* t);
  * keeps the fastest in the plan.  Synchronises the stream; the same rule as
  * for ps_plan_set_tuning applies.  `report` (may be NULL) receives the
  * candidates, the mean milliseconds per execute of each and the index of the
- * one kept. */
+ * one kept.  Errors: PS_E_INVALID_ARG for NULL or empty arguments or reps out
+ * of range; otherwise as for ps_execute, with the plan's configuration left as
+ * it was before the call. */
 #define PS_TUNE_MAX 16
 typedef struct ps_tune_report {
     int32_t n;

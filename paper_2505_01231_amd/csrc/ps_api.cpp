@@ -670,9 +670,13 @@ ps_status ps_plan_autotune(ps_plan_t p, const ps_record* recs, int32_t n_rec, vo
             cand[n++] = ps_tuning{g, 0};
         }
     }
+    const ps_tuning orig{p->tile_group, p->s3_fb};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     PS_HIP(hipEventCreate(&e0));
-    PS_HIP(hipEventCreate(&e1));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(PS_E_HIP, "autotune: hipEventCreate failed");
+    }
     double ms[PS_TUNE_MAX];
     int best = 0;
     ps_status rc = PS_OK;
@@ -693,7 +697,15 @@ ps_status ps_plan_autotune(ps_plan_t p, const ps_record* recs, int32_t n_rec, vo
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    if (rc != PS_OK) return rc;
+    if (rc != PS_OK) {
+        // keep the configuration the plan had (the error detail stays the first failure's)
+        if (orig.tile_group != p->tile_group) {
+            p->tile_group = orig.tile_group;
+            (void)write_tiles(p);
+        }
+        p->s3_fb = orig.s3_frame_batch;
+        return rc;
+    }
     if ((rc = ps_plan_set_tuning(p, &cand[best])) != PS_OK) return rc;
     if (report) {
         report->n = n;

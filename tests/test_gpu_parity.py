@@ -504,6 +504,20 @@ def test_autotune_keeps_the_fastest(dev):
             with pytest.raises(PolyspecError):
                 p.set_tuning(*bad)
             assert p.tuning == kept
+        # a failing autotune (workspace too small: rejected on the host before
+        # any launch) leaves the configuration as it was
+        import ctypes as C
+        from paper_2505_01231_amd import _lib as L
+        p.set_tuning(1, 16)
+        recs = (L.ps_record * 1)(p.record(x))
+        small = torch.empty(256, dtype=torch.uint8, device=dev)
+        o = p.allocate_outputs(dev)
+        outs = (L.ps_output * 1)(L.ps_output(*[t.data_ptr() for t in (o.s2, o.s2_err, o.s3, o.s3_err, o.s4, o.s4_err)]))
+        st = torch.cuda.current_stream(dev)
+        rc = p._lib.ps_plan_autotune(p._handle, recs, 1, small.data_ptr(), small.numel(), outs, 1,
+                                     C.c_void_p(st.cuda_stream), None)
+        assert rc != 0
+        assert p.tuning == {"tile_group": 1, "s3_frame_batch": 16}
 
 
 # ---------------------------------------------------------------- streaming (quasi-polyspectra)
