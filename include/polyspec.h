@@ -258,8 +258,10 @@ ps_status ps_profile_read(ps_plan_t plan, double* stage_ms, int32_t n);
  *                   multiple of 10, else 16).
  * ps_plan_set_tuning rewrites the plan's tile tables in device memory
  * (synchronously): no execute or graph launch of the plan may be in flight.
- * Graphs captured earlier use the new order from their next launch.  Errors:
- * PS_E_INVALID_ARG for NULL or values outside the lists above. */
+ * Graphs captured earlier use the new tile order from their next launch and
+ * keep the S3 frame batch they were captured with (the frame batch does not
+ * change the S3 sums: frames are added in the same order either way).
+ * Errors: PS_E_INVALID_ARG for NULL or values outside the lists above. */
 typedef struct ps_tuning {
     int32_t tile_group;
     int32_t s3_frame_batch;

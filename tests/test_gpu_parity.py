@@ -520,6 +520,27 @@ def test_autotune_keeps_the_fastest(dev):
         assert p.tuning == {"tile_group": 1, "s3_frame_batch": 16}
 
 
+def test_graph_follows_tuning_changes(dev):
+    """A graph captured before ps_plan_set_tuning replays with the new tile order
+    (the tables are rewritten in place; the captured S3 frame batch, which does
+    not change the sums, stays) and matches an eager execute at that
+    configuration bitwise."""
+    from paper_2505_01231_amd import Plan
+    say("graph after set_tuning")
+    z, x = _tuning_case(dev)
+    with Plan(frame_len=1024, n_freq=200, m=12, window="acg", n_channels=2, precision="bf16x3") as p:
+        g = p.graph(x)
+        for tg, fb in ((1, 10), (16, 16), (8, 0)):
+            p.set_tuning(tg, fb)
+            got = _spectra(g.launch())
+            torch.cuda.synchronize()
+            want = _spectra(p.execute(x))
+            torch.cuda.synchronize()
+            for key in got:
+                assert np.array_equal(got[key], want[key], equal_nan=True), (tg, fb, key)
+        g.close()
+
+
 # ---------------------------------------------------------------- streaming (quasi-polyspectra)
 def test_streamer_time_resolved_windows(dev):
     """Consecutive windows of a host stream whose chi-square drive amplitude
