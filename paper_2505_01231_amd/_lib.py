@@ -87,6 +87,14 @@ def load() -> C.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2505_01231_amd.build`")
+    # PyTorch ships its own HIP runtime under the same soname as the system
+    # one (libamdhip64.so.7).  Whichever is loaded first serves the whole
+    # process; torch must get its own, so it is loaded before this library
+    # (which then binds to torch's copy: one runtime, shared device memory).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
     lib.ps_plan_create.argtypes = [C.POINTER(ps_config), C.POINTER(vp)]

@@ -7,6 +7,7 @@ import itertools
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -176,3 +177,20 @@ def test_tuning_calls_reject_null_arguments():
     rep = L.ps_tune_report()
     assert lib.ps_plan_autotune(None, None, 0, None, 0, None, 3, None, C.byref(rep)) == L.PS_E_INVALID_ARG
     assert "NULL" in L.last_error()
+
+
+def test_library_binds_to_torchs_hip_runtime():
+    """Loading the library first must not hand torch the system HIP runtime:
+    load() imports torch before the library, whose HIP dependency (same
+    soname as torch's copy) then resolves to torch's."""
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2505_01231_amd import _lib\n"
+            "assert 'torch' not in sys.modules\n"
+            "_lib.load()\n"
+            "assert 'torch' in sys.modules\n"
+            "maps = open('/proc/self/maps').read()\n"
+            "hip = {l.split()[-1] for l in maps.splitlines() if 'libamdhip64' in l}\n"
+            "assert len(hip) == 1, hip\n"
+            "import torch, os\n"
+            "assert next(iter(hip)).startswith(os.path.dirname(torch.__file__)), hip\n") % ROOT
+    subprocess.run([sys.executable, "-c", code], check=True, timeout=300)
