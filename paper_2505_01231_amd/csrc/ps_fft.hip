@@ -275,10 +275,14 @@ hipError_t launch_n(const FftArgs& a, hipStream_t st) {
 // the subtraction, so each coefficient is read from HBM once.
 constexpr int kCentreRegs = 16;
 
-__global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64_t coef_cs, int K, int m) {
-    const int k = blockIdx.x * 256 + threadIdx.x;
+// Grid: x = chunk * kblocks + (256-wide k block), y = channel (the chunk count
+// can exceed the 65536 limit of the y and z grid dimensions).
+__global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64_t coef_cs, int K, int m,
+                                                int kblocks) {
+    const int64_t chunk = blockIdx.x / kblocks;
+    const int k = (int)(blockIdx.x - chunk * kblocks) * 256 + threadIdx.x;
     if (k >= K) return;
-    float2* p = coef + blockIdx.z * coef_cs + (int64_t)blockIdx.y * m * K + k;
+    float2* p = coef + blockIdx.y * coef_cs + chunk * m * K + k;
     const float inv = 1.0f / (float)m;
     if (m <= kCentreRegs) {
         float2 v[kCentreRegs];
@@ -327,8 +331,11 @@ hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s) {
 
 hipError_t launch_centre(const CentreArgs& a, hipStream_t s) {
     if (a.n_chunks <= 0) return hipSuccess;
-    dim3 grid((a.K + 255) / 256, (unsigned)a.n_chunks, a.n_channels);
-    k_centre<<<grid, 256, 0, s>>>(a.coef, a.coef_chan_stride, a.K, a.m);
+    const int kblocks = (a.K + 255) / 256;
+    const int64_t nx = (int64_t)kblocks * a.n_chunks;
+    if (nx > 0x7fffffff) return hipErrorInvalidConfiguration;
+    dim3 grid((unsigned)nx, a.n_channels);
+    k_centre<<<grid, 256, 0, s>>>(a.coef, a.coef_chan_stride, a.K, a.m, kblocks);
     return hipGetLastError();
 }
 

@@ -338,6 +338,47 @@ def test_full_size_sampled_points(dev, precision):
         assert v <= TOL, (k, v)
 
 
+def test_more_chunks_than_a_grid_dimension(dev):
+    """A record with more chunks than the 65536 limit of the y/z grid
+    dimensions (2^28 samples at N = 256, m = 10: 104857 chunks): its means
+    equal the chunk-weighted means of a batched run over chunk-aligned slices
+    of it (the same chunk sums, added in another order), and a sample of grid
+    points matches the oracle."""
+    from paper_2505_01231_amd import Plan
+    say("104857 chunks, N=256")
+    N, Nf, m = 256, 64, 10
+    L = 1 << 28
+    g = torch.Generator(device=dev)
+    g.manual_seed(11)
+    x = torch.randn(L, device=dev, generator=g)
+    x = x * x - 1.0                               # chi-square(1), centred: non-zero S3 and S4
+    chunk = N * m
+    with Plan(frame_len=N, n_freq=Nf, m=m, window="acg", precision="bf16x3") as p:
+        full = p.execute(x)
+        torch.cuda.synchronize()
+        assert full.n_chunks == (L // N) // m == 104857
+        per = 30000
+        parts = [x[i * per * chunk:min(L, (i + 1) * per * chunk)] for i in range(4)]
+        outs = p.execute(parts)
+        torch.cuda.synchronize()
+        n = np.array([o.n_chunks for o in outs], dtype=np.float64)
+        assert n.sum() == full.n_chunks
+        for key in ("s2", "s3", "s4"):
+            f = getattr(full, key).cpu().numpy()
+            comb = sum(ni * getattr(o, key).cpu().numpy() for ni, o in zip(n, outs)) / n.sum()
+            assert rel_err(comb, f) <= 1e-12, (key, rel_err(comb, f))
+        s3 = torch.view_as_complex(full.s3[0]).cpu().numpy()
+        s4 = torch.view_as_complex(full.s4[0]).cpu().numpy()
+    z = x.cpu().numpy().astype(np.float64)
+    del x, parts
+    pts = [(0, 0), (5, 17), (63, 63), (31, 2), (10, 40)]
+    ref = O.polyspectra_at(z, N, m, window_kind="acg", points3=pts, points4=pts)
+    e3 = rel_err(np.array([s3[k, l] for k, l in pts]), ref["s3"])
+    e4 = rel_err(np.array([s4[k, l] for k, l in pts]), ref["s4"])
+    say("  sampled rel err s3", f"{e3:.2e}", "s4", f"{e4:.2e}")
+    assert e3 <= TOL and e4 <= TOL
+
+
 # ---------------------------------------------------------------- channel combinations
 @pytest.mark.parametrize("precision", PRECISIONS)
 def test_all_orbits_two_channels(dev, precision):
