@@ -196,6 +196,29 @@ def test_order_subsets(dev, orders, Nf):
     compare(gpu, ref, keys=tuple(f"s{o}" for o in orders), label=f"orders{orders}")
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("Nf", [1, 2, 3])
+def test_tiny_grids(dev, precision, Nf):
+    """N_f of 1-3: one tile, almost all of it outside the grid."""
+    say("tiny grid", Nf, precision)
+    z = synth.ar2_chi2(256 * 5 * 6 + 11, seed=21 + Nf, dtype=np.float32)
+    gpu, ref = both(z, dev, 256, Nf, 5, window="hann", precision=precision)
+    compare(gpu, ref, label=f"tiny-{Nf}-{precision}")
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_largest_grid_for_s3(dev, precision):
+    """N_f = N/4 + 1, the largest grid with S3: the third factor a_(k+l) reaches
+    the Nyquist coefficient k + l = N/2, and the grid is one point past four
+    whole tiles."""
+    say("N_f = N/4 + 1", precision)
+    N = 1024
+    Nf = N // 4 + 1
+    z = synth.ar2_chi2(N * 10 * 4 + 3, seed=33, dtype=np.float32)
+    gpu, ref = both(z, dev, N, Nf, 10, window="acg", precision=precision)
+    compare(gpu, ref, label=f"largest-{precision}")
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_large_m_uses_several_frame_batches(dev, precision):
     say("m=37", precision)
