@@ -57,7 +57,28 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")
+    build_c_client(verbose)
     return LIB
+
+
+CLIENT_SRC = os.path.join(CSRC, "examples", "ps_c_client.c")
+CLIENT = os.path.join(PKG, "ps_c_client")
+ROCM = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+
+
+def build_c_client(verbose: bool = False) -> str:
+    """The plain-C client of the ABI (gcc, HIP runtime headers, no hipcc):
+    linked against the library beside it."""
+    cmd = ["gcc", "-std=c99", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", INCLUDE,
+           "-I", os.path.join(ROCM, "include"), CLIENT_SRC, "-o", CLIENT, "-L", PKG, "-lpolyspec",
+           "-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-Wl,-rpath,$ORIGIN",
+           "-Wl,-rpath," + os.path.join(ROCM, "lib")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"C client build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print(f"built {CLIENT}")
+    return CLIENT
 
 
 def main(argv=None):

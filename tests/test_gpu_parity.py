@@ -605,6 +605,38 @@ def test_graph_follows_tuning_changes(dev):
         g.close()
 
 
+def test_plain_c_client(dev, tmp_path):
+    """The ABI from C alone: paper_2505_01231_amd/ps_c_client (C99, gcc, device
+    memory and stream from the HIP runtime, no PyTorch in its process) writes
+    S2, S3, S4 and their error bars, which equal the oracle's."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = os.path.join(root, "paper_2505_01231_amd", "ps_c_client")
+    assert os.path.exists(exe), "ps_c_client is missing: python -m paper_2505_01231_amd.build"
+    N, Nf, m = 512, 100, 10
+    z = synth.ar2_chi2(N * m * 5 + 17, seed=41, dtype=np.float32)
+    inp, out = tmp_path / "z.f32", tmp_path / "s.f64"
+    z.tofile(inp)
+    ref = O.polyspectra(z, N, Nf, m, window_kind="acg")
+    for precision in (0, 1):
+        say("C client, precision", precision)
+        r = subprocess.run([exe, str(inp), str(out), str(N), str(Nf), str(m), str(precision)],
+                           capture_output=True, text=True, timeout=120)
+        assert r.returncode == 0, r.stderr
+        d = np.fromfile(out, dtype=np.float64)
+        assert int(d[0]) == ref["n_chunks"] == 5
+        sizes = [2 * Nf, 2 * Nf, 2 * Nf * Nf, 2 * Nf * Nf, 2 * Nf * Nf, 2 * Nf * Nf]
+        parts = np.split(d[1:], np.cumsum(sizes)[:-1])
+        assert len(d) == 1 + sum(sizes)
+        got = {"s2": parts[0].reshape(1, Nf, 2), "s2_err": parts[1].reshape(1, Nf, 2),
+               "s3": parts[2].reshape(1, Nf, Nf, 2), "s3_err": parts[3].reshape(1, Nf, Nf, 2),
+               "s4": parts[4].reshape(1, Nf, Nf, 2), "s4_err": parts[5].reshape(1, Nf, Nf, 2)}
+        for key in ("s2", "s3", "s4"):
+            got[key] = got[key][..., 0] + 1j * got[key][..., 1]
+        compare(got, ref, label=f"c-client-{precision}")
+
+
 # ---------------------------------------------------------------- streaming (quasi-polyspectra)
 def test_streamer_time_resolved_windows(dev):
     """Consecutive windows of a host stream whose chi-square drive amplitude
