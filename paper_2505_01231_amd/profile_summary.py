@@ -4,6 +4,7 @@
         --trace DIR/trace_kernel_stats.csv [--kernel-trace DIR/trace_kernel_trace.csv] \
         --fetch DIR/fetch_counter_collection.csv --write DIR/write_counter_collection.csv \
         [--traffic-json OUT.json --kernel k_s3]
+    python -m paper_2505_01231_amd.profile_summary --counters A_counter_collection.csv [B_...csv ...]
 
 The counter runs must include the plain 1 GiB copy that ``bench.py
 --copy-calibration`` launches first (three dispatches of torch's elementwise
@@ -12,7 +13,9 @@ scaled by what they read for that copy of known size.  Prints a markdown table
 of average duration and calibrated HBM bytes per dispatch; with
 ``--traffic-json`` also stores the calibrated bytes of one kernel together with
 a digest of that kernel's source, which ``bench.py`` checks before it reports
-the figure as ``roofline.traffic``.
+the figure as ``roofline.traffic``.  With ``--counters`` it prints instead, per
+kernel, the mean over dispatches of every counter or derived metric that the
+given ``--pmc`` runs collected (unit utilisation, instruction counts).
 """
 from __future__ import annotations
 
@@ -79,6 +82,20 @@ def _timed_avg_us(kernel_trace: str) -> dict:
     return {k: sum(v[1:]) / len(v[1:]) for k, v in d.items() if len(v) > 1}
 
 
+def counter_table(paths: list[str]) -> tuple[list[str], dict]:
+    """Mean value per (kernel, counter) over the dispatches of the given runs."""
+    names: list[str] = []
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in paths:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                c = r["Counter_Name"]
+                if c not in names:
+                    names.append(c)
+                vals[r["Kernel_Name"].split("(")[0]][c].append(float(r["Counter_Value"]))
+    return names, {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in vals.items()}
+
+
 def summarize(trace: str, fetch: str, write: str, kernel_trace: str | None = None):
     with open(trace) as f:
         stats = list(csv.DictReader(f))
@@ -102,14 +119,24 @@ def summarize(trace: str, fetch: str, write: str, kernel_trace: str | None = Non
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--counters", nargs="+", help="*_counter_collection.csv files: print a per-kernel counter table")
+    ap.add_argument("--trace")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
     ap.add_argument("--kernel-trace", help="the per-dispatch *_kernel_trace.csv of the trace run")
     ap.add_argument("--traffic-json")
     ap.add_argument("--kernel", default="k_s3")
     ap.add_argument("--command", default="", help="the rocprofv3 command lines, recorded in the JSON")
     a = ap.parse_args(argv)
+    if a.counters:
+        names, table = counter_table(a.counters)
+        print("| kernel | " + " | ".join(names) + " |")
+        print("|---|" + "---|" * len(names))
+        for k, d in table.items():
+            print(f"| {k} | " + " | ".join(f"{d[c]:.4g}" if c in d else "" for c in names) + " |")
+        return
+    if not (a.trace and a.fetch and a.write):
+        ap.error("--trace, --fetch and --write are required without --counters")
     fcal, wcal, rows = summarize(a.trace, a.fetch, a.write, a.kernel_trace)
     print(f"calibration: FETCH_SIZE x{fcal:.3f}, WRITE_SIZE x{wcal:.3f} (1 GiB copy)\n")
     print("| kernel | calls | avg us (all) | avg us (after the first) | FETCH KiB raw | WRITE KiB raw | "
