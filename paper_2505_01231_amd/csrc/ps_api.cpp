@@ -343,8 +343,8 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 part += ps::Sched{sg.n_tiles, q.Np, sg.blocks}.n_slots() * sg.ncomp * (single ? TT : TX);
                 sg.out = o && o->d_s4 ? o->d_s4 + 2 * i * nf2 : nullptr;
                 sg.err = o && o->d_s4_err ? o->d_s4_err + 2 * i * nf2 : nullptr;
-                // the matrix-core S4 kernel sums the numerator scaled by m(m+1)
-                sg.scale = single && p->precision == PS_PREC_BF16X3 ? scale4 / (m * (m + 1.0)) : scale4;
+                // the BF16 x 3 matrix-core S4 kernels sum the numerator scaled by m(m+1)
+                sg.scale = p->precision == PS_PREC_BF16X3 ? scale4 / (m * (m + 1.0)) : scale4;
                 sg.sym = sym;
                 (single ? G.s4s : G.s4x).add(sg, sg.blocks);
                 G.f4.add(sg, (int64_t)sg.n_tiles * ((single ? TT : TX) / 256));

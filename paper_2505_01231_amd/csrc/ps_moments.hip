@@ -1040,18 +1040,22 @@ __global__ __launch_bounds__(kS4XThreads, 2) void k_s4_cross(BatchArgs p) {
 // (16 (w / 2), 16 (w % 2)) with 20 accumulators of 4 registers, lane (lg, li)
 // holding grid points (4 lg + e, li).  LDS rows are 160 bytes apart, a stride
 // at which the 16-row, 16-byte-per-lane operand reads of 16x16x32 are free of
-// bank conflicts.  The combination T = e f + G_ac conj(G_bd) + H_ad conj(H_bc)
-// and v = sum E F - gamma T are formed in FP64, as are the chunk sums.
+// bank conflicts.  As in k_s4_mfma_bf16 the kernel forms the k-statistic
+// numerator with integer coefficients,
+//   v = m(m+1) sum E F - (m-1) T,  T = e f + G_ac conj(G_bd) + H_ad conj(H_bc),
+// in FP32 (the k-side E rows hold m(m+1) E, so the E.F Grams give the first
+// term; the finalize scale carries 1 / (m(m+1))), and only the chunk sums in
+// FP64.
 constexpr int kOpDwX = 40;           // 32-bit words per LDS operand row (160 B; 32 used)
 constexpr int kS4XMThreads = 256;
 constexpr int kCrossSlots = 3;       // frame slots q, q + 4, q + 8 of a loader thread
 
 // Stage this thread's frame slots of column `col`: P = x conj(y) and the split
-// words of (Re P, Im P, Re x, Im x, Re y, Im y) into row types 0..5; returns
-// the sum of P over the slots.
+// words of (pscale Re P, pscale Im P, Re x, Im x, Re y, Im y) into row types
+// 0..5; returns the sum of P (unscaled) over the slots.
 template <int SIDE>
 __device__ __forceinline__ float2 stage_cross(uint32_t (*op)[kOpDwX], int col, int q, const float2 (&px)[kCrossSlots],
-                                              const float2 (&py)[kCrossSlots]) {
+                                              const float2 (&py)[kCrossSlots], float pscale) {
     float2 pa = make_float2(0.f, 0.f);
 #pragma unroll
     for (int j = 0; j < kCrossSlots; ++j) {
@@ -1061,7 +1065,7 @@ __device__ __forceinline__ float2 stage_cross(uint32_t (*op)[kOpDwX], int col, i
         const float2 P = make_float2(fmaf(x.x, y.x, x.y * y.y), fmaf(x.y, y.x, -(x.x * y.y)));
         pa.x += P.x;
         pa.y += P.y;
-        const float val[6] = {P.x, P.y, x.x, x.y, y.x, y.y};
+        const float val[6] = {P.x * pscale, P.y * pscale, x.x, x.y, y.x, y.y};
 #pragma unroll
         for (int t = 0; t < 6; ++t) {
             uint32_t w0, w1, w2;
@@ -1106,7 +1110,8 @@ __global__ __launch_bounds__(kS4XMThreads, 2) void k_s4_cross_mfma(BatchArgs p) 
         row[3 * kMfmaFrames] = 0u;
         row[3 * kMfmaFrames + 1] = 0u;
     }
-    const double gamma = p.gamma;
+    const float cm1 = (float)(v.m * (v.m + 1));         // m(m+1), exact
+    const float cm2 = (float)(v.m - 1);                 // m-1
 
     Item it;
     while (next_item<kTileX, 4>(p, bk, it)) {
@@ -1148,7 +1153,7 @@ __global__ __launch_bounds__(kS4XMThreads, 2) void k_s4_cross_mfma(BatchArgs p) 
         if (first) pacc = make_float2(0.f, 0.f);
         lds_barrier();
         {   // E = x conj(y) (k side: a b*, l side: c d*)
-            const float2 pa = side == 0 ? stage_cross<0>(op, col, q, px, py) : stage_cross<1>(op, col, q, px, py);
+            const float2 pa = side == 0 ? stage_cross<0>(op, col, q, px, py, cm1) : stage_cross<1>(op, col, q, px, py, 1.0f);
             pacc.x += pa.x;
             pacc.y += pa.y;
         }
@@ -1187,21 +1192,21 @@ __global__ __launch_bounds__(kS4XMThreads, 2) void k_s4_cross_mfma(BatchArgs p) 
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const float2 ek = psum[0][16 * (w >> 1) + 4 * lg + e], fl = psum[1][rowB];
-            // complex sums from the real Grams (FP32, like the Grams), then FP64
-            const double sef_r = d[0][e] - d[1][e], sef_i = d[2][e] + d[3][e];
-            const double gac_r = d[4][e] - d[5][e], gac_i = d[6][e] + d[7][e];
-            const double hbc_r = d[8][e] + d[9][e], hbc_i = d[11][e] - d[10][e];
-            const double gbd_r = d[12][e] - d[13][e], gbd_i = d[14][e] + d[15][e];
-            const double had_r = d[16][e] + d[17][e], had_i = d[19][e] - d[18][e];
+            // complex sums from the real Grams (sum E F scaled by m(m+1))
+            const float sef_r = d[0][e] - d[1][e], sef_i = d[2][e] + d[3][e];
+            const float gac_r = d[4][e] - d[5][e], gac_i = d[6][e] + d[7][e];
+            const float hbc_r = d[8][e] + d[9][e], hbc_i = d[11][e] - d[10][e];
+            const float gbd_r = d[12][e] - d[13][e], gbd_i = d[14][e] + d[15][e];
+            const float had_r = d[16][e] + d[17][e], had_i = d[19][e] - d[18][e];
             // T = e f + G_ac conj(G_bd) + H_ad conj(H_bc)
-            double tr = (double)ek.x * fl.x - (double)ek.y * fl.y;
-            double ti = (double)ek.x * fl.y + (double)ek.y * fl.x;
-            tr += gac_r * gbd_r + gac_i * gbd_i;
-            ti += gac_i * gbd_r - gac_r * gbd_i;
-            tr += had_r * hbc_r + had_i * hbc_i;
-            ti += had_i * hbc_r - had_r * hbc_i;
-            const double vr = fma(-gamma, tr, sef_r);
-            const double vi = fma(-gamma, ti, sef_i);
+            float tr = fmaf(ek.x, fl.x, -(ek.y * fl.y));
+            float ti = fmaf(ek.x, fl.y, ek.y * fl.x);
+            tr = fmaf(gac_r, gbd_r, fmaf(gac_i, gbd_i, tr));
+            ti = fmaf(gac_i, gbd_r, fmaf(-gac_r, gbd_i, ti));
+            tr = fmaf(had_r, hbc_r, fmaf(had_i, hbc_i, tr));
+            ti = fmaf(had_i, hbc_r, fmaf(-had_r, hbc_i, ti));
+            const double vr = (double)fmaf(-cm2, tr, sef_r);
+            const double vi = (double)fmaf(-cm2, ti, sef_i);
             acc[e][0] += vr;
             acc[e][1] += vi;
             acc[e][2] = fma(vr, vr, acc[e][2]);
