@@ -351,6 +351,36 @@ def polyspectra(z, N: int, Nf: int, m: int, dt: float = 1.0, window_kind: str = 
     return out
 
 
+def polyspectra_interlaced(z, N: int, Nf: int, m: int, **kw):
+    """Interlaced windows (Section 3): the window weighs the middle of each
+    frame more than its edges, and frames shifted by half a window (T/2, i.e.
+    N/2 samples) weigh the other parts; the interlaced result is the average of
+    the spectra of both frame sets.
+
+    Each set is estimated on its own: the frames of record z, and the frames of
+    z without its first N/2 samples, each cut into its own chunks.  The paper
+    gives no error estimate for the average; the reading adopted is the average
+    of the two sets' error bars (the sets overlap, their estimates are
+    positively correlated, and sd(X + Y) <= sd(X) + sd(Y) makes this never an
+    underestimate).  If the shifted set has no complete chunk the first set's
+    result is returned alone.  Keyword arguments are those of polyspectra.
+    Adds 'n_chunks_shifted' to the result.
+    """
+    z = np.asarray(z)
+    first = polyspectra(z, N, Nf, m, **kw)
+    shifted_z = z[..., N // 2:]
+    if chunk_count(shifted_z.shape[-1], N, m) == 0:
+        out = dict(first)
+        out["n_chunks_shifted"] = 0
+        return out
+    second = polyspectra(shifted_z, N, Nf, m, **kw)
+    out = dict(first)
+    for key in ("s2", "s3", "s4", "s2_err", "s3_err", "s4_err"):
+        out[key] = 0.5 * (first[key] + second[key])
+    out["n_chunks_shifted"] = second["n_chunks"]
+    return out
+
+
 def polyspectra_at(z, N: int, m: int, dt: float = 1.0, window_kind: str = "acg",
                    window_param: float = 0.14, points2=(), points3=(), points4=(),
                    combo2=(0, 0), combo3=(0, 0, 0), combo4=(0, 0, 0, 0),

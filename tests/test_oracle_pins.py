@@ -484,3 +484,70 @@ def test_error_bar_matches_spread_over_independent_records():
         spread2 = np.var(np.array(means), axis=0, ddof=1)
         ratio = np.mean(np.array(errs) ** 2, axis=0) / spread2
         assert 0.9 < np.median(ratio) < 1.1, (k, np.median(ratio))
+
+
+# --------------------------------------------------------------------------
+# Interlaced windows (Section 3)
+# --------------------------------------------------------------------------
+
+
+def test_interlaced_weights_the_shifted_half_window():
+    """White noise present only in the first quarter of every N-sample period.
+    The frames from sample 0 see it under the first quarter of the window, the
+    frames shifted by N/2 under its third quarter.  Frames are independent, so
+    E S2_k = kappa2 dt (sum of g^2 over the occupied samples) / sum g^2 at every
+    k, and the interlaced average is kappa2 dt (A + B) / (2 sum g^2), A and B
+    the sums of g^2 over the first and third quarters of a symmetric Hann
+    window (taken from scipy).  A is small: a missing shift gives A, a shift by
+    N/4 sees the fourth quarter (= A by symmetry), a sum instead of an average
+    doubles the result."""
+    N, Nf, m, Np, dt = 64, 17, 10, 150, 0.5
+    L = N * m * Np + N                  # both frame sets hold Np chunks
+    w = np.random.default_rng(97).standard_normal(L)
+    z = np.where((np.arange(L) % N) < N // 4, w, 0.0)
+    out = O.polyspectra_interlaced(z, N, Nf, m, dt=dt, window_kind="hann", orders=(2,))
+    assert out["n_chunks"] == Np and out["n_chunks_shifted"] == Np
+    g2 = scipy.signal.windows.hann(N, sym=True) ** 2
+    A, B = g2[:N // 4].sum(), g2[N // 2:3 * N // 4].sum()
+    expect = dt * (A + B) / (2 * g2.sum())
+    got = out["s2"][0].real
+    assert abs(got.mean() / expect - 1) < 0.05, (got.mean(), expect)
+    # every bin within 5 of its own error bars
+    assert np.all(np.abs(got - expect) < 5 * out["s2_err"][0][:, 0])
+    assert A / (A + B) < 0.1            # the alternatives above are far away
+
+
+def test_interlaced_without_shifted_chunk_is_the_first_set():
+    """A record whose shifted frame set has no complete chunk: the first set's
+    spectra alone (the shifted set starts N/2 samples later and so holds one
+    frame fewer here)."""
+    N, Nf, m = 32, 8, 5
+    z = np.random.default_rng(98).standard_normal(N * m + N // 4)
+    out = O.polyspectra_interlaced(z, N, Nf, m)
+    ref = O.polyspectra(z, N, Nf, m)
+    assert out["n_chunks"] == 1 and out["n_chunks_shifted"] == 0
+    for key in ("s2", "s3", "s4"):
+        assert np.array_equal(out[key], ref[key])
+
+
+@pytest.mark.slow
+def test_interlaced_error_bar_is_conservative():
+    """The interlaced error bar (the mean of the two sets' sigmas) against the
+    spread of the interlaced spectrum over independent white-noise records:
+    the two sets overlap by half a window, so their estimates are positively
+    correlated and the variance of their average lies between sigma^2 / 2
+    (independent) and sigma^2 (identical).  The reported sigma^2 must not fall
+    below the spread (ratio >= 0.9) and exceeds it by at most the factor 2 of
+    independent sets (ratio <= 2.5 with sampling noise)."""
+    N, Nf, m, Np = 32, 8, 6, 5
+    res = {k: ([], []) for k in ("s2", "s3", "s4")}
+    for seed in range(300):
+        w = np.random.default_rng(3000 + seed).standard_normal(N * m * Np + N)
+        out = O.polyspectra_interlaced(w, N, Nf, m, window_kind="hann")
+        for k, (means, errs) in res.items():
+            means.append(out[k][0].real)
+            errs.append(out[k + "_err"][0][..., 0])
+    for k, (means, errs) in res.items():
+        spread2 = np.var(np.array(means), axis=0, ddof=1)
+        ratio = np.median(np.mean(np.array(errs) ** 2, axis=0) / spread2)
+        assert 0.9 < ratio < 2.5, (k, ratio)
