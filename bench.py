@@ -200,6 +200,9 @@ def main(argv=None):
     ap.add_argument("--fp32-steps", type=int, default=3,
                     help="timed steps of the batched all-FP32 path (for mixed-vs-FP32)")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the per-chunk FP32 path")
+    ap.add_argument("--interlaced-steps", type=int, default=2,
+                    help="timed steps of the interlaced form (second frame set shifted by N/2, "
+                         "spectra averaged) on the same record")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batching", action="store_true",
                     help="also time the batching form: 24 four-channel int16 records of uneven length "
@@ -315,6 +318,26 @@ def main(argv=None):
                         "mfma_peak_tflops": 2500.0,
                         "mfma_frac_of_peak": mfma_flops / (s4_avg_ms * 1e-3) / 2.5e15})
 
+    # Interlaced windows: the same record with a second frame set shifted by N/2
+    # (twice the frames), spectra of both sets averaged.
+    interlaced = None
+    if args.interlaced_steps > 0:
+        with Plan(frame_len=N, n_freq=NF, m=M, window="acg", precision=args.precision, interlaced=True) as pi:
+            wsi = torch.empty(pi.workspace_bytes([x]), dtype=torch.uint8, device=dev)
+            oi = [pi.allocate_outputs(dev)]
+            pi.execute([x], workspace=wsi, outputs=oi)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.interlaced_steps):
+                pi.execute([x], workspace=wsi, outputs=oi)
+            torch.cuda.synchronize()
+            dt_i = time.perf_counter() - t0
+            interlaced = {"samples_per_s": N_SAMPLES * args.interlaced_steps / dt_i,
+                          "ms_per_step": dt_i / args.interlaced_steps * 1e3,
+                          "frames_per_step": 2 * n_frames, "steps": args.interlaced_steps}
+            del wsi, oi
+        log(f"interlaced {interlaced['samples_per_s']:.3e} samples/s")
+
     batching = run_batching(torch, dev, args.precision) if args.batching else None
     streaming = run_streaming(torch, dev, args.precision) if args.streaming else None
 
@@ -354,6 +377,7 @@ def main(argv=None):
                   "speedup_vs_batched_fp32": (value / batched_fp32) if batched_fp32 else None,
                   "speedup_vs_per_chunk_fp32": (value / plain) if plain else None},
         "s4_matrix_cores": s4_info,
+        "interlaced": interlaced,
         "batching": batching,
         "streaming": streaming,
         "stage_ms_per_step": stage_ms,

@@ -108,7 +108,19 @@ typedef struct ps_config {
     const int8_t* combos2; /* host [n_combos2][2]: (a, b) -> C2(a_k, b*_k) */
     const int8_t* combos3; /* host [n_combos3][3]: (a, b, c) -> C3(a_k, b_l, c*_{k+l}) */
     const int8_t* combos4; /* host [n_combos4][4]: (a, b, c, d) -> C4(a_k, b*_k, c_l, d*_l) */
+    int32_t interlaced;    /* 0 or 1: interlaced windows (see below); PS_SCHED_BATCHED only */
+    int32_t reserved;      /* must be 0 */
 } ps_config;
+/* Interlaced windows (Section 3): the centre of a window weighs the signal more
+ * than its edges; the same spectra computed on windows shifted by T/2 weigh it
+ * the other way.  With interlaced = 1 every record (or streamer window) is
+ * processed twice, as the frame set starting at sample 0 and as the set
+ * starting at sample N/2, each cut into its own chunks, and the output is the
+ * average of the two spectra.  Its error bar is the average of the two error
+ * bars: the sets overlap, so their estimates are positively correlated, and
+ * this average is never below the error of the averaged spectrum.  When the
+ * shifted set has no complete chunk the output is the first set's alone.
+ * ps_record_info reports the first set (Np, flags). */
 /* "Every orbit": combinations related by the symmetries of Section 9 that keep
  * the output grid are computed once.  S2: (a,b) with a <= b (S2_ba = conj S2_ab).
  * S3: (a,b,c) with a <= b (S3_bac(k,l) = S3_abc(l,k)).  S4: the lexicographically
@@ -160,7 +172,8 @@ ps_status ps_plan_destroy(ps_plan_t plan);
 
 ps_status ps_plan_query(ps_plan_t plan, ps_plan_info* info);
 
-/* Np and PS_FLAG_* for a record of n_samples samples per channel. */
+/* Np and PS_FLAG_* for a record of n_samples samples per channel (with
+ * interlaced windows: of the frame set that starts at sample 0). */
 ps_status ps_record_info(ps_plan_t plan, int64_t n_samples, int64_t* n_chunks, uint32_t* flags);
 
 /* Device workspace (bytes) that ps_execute needs for these records. */

@@ -38,7 +38,7 @@ class ps_config(C.Structure):
         ("window", C.c_int32), ("precision", C.c_int32), ("schedule", C.c_int32),
         ("n_combos2", C.c_int32), ("n_combos3", C.c_int32), ("n_combos4", C.c_int32),
         ("combos2", C.POINTER(C.c_int8)), ("combos3", C.POINTER(C.c_int8)),
-        ("combos4", C.POINTER(C.c_int8)),
+        ("combos4", C.POINTER(C.c_int8)), ("interlaced", C.c_int32), ("reserved", C.c_int32),
     ]
 
 

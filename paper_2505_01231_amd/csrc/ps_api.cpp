@@ -106,6 +106,7 @@ struct ps_plan_s {
     double dt = 1, f_max = 0, window_param = 0.14;
     uint32_t orders = 0;
     int window = 0, precision = 0, schedule = 0;
+    bool interlaced = false;    // second frame set shifted by N/2, spectra averaged
     std::vector<int8_t> c2, c3, c4;
     double sum_g[5] = {0, 0, 0, 0, 0};
     int T = 0, TX = 0;
@@ -221,8 +222,12 @@ struct Group {
     SegTable* all[7] = {&s2, &s3, &s4s, &s4x, &f2, &f3, &f4};
 };
 
+// With interlaced windows every caller record r becomes two internal records:
+// 2r, its frames from sample 0, and 2r + 1, its frames from sample N/2 (stride
+// 2); the finalize of 2r combines both.
 struct Batch {
-    std::vector<RecInfo> ri;
+    int stride = 1;                 // internal records per caller record
+    std::vector<RecInfo> ri;        // per internal record
     std::vector<ps::RecDesc> rd;
     int64_t F_tot = 0, chunks_tot = 0;
     int64_t coef_rows = 0;          // frames resident per channel in the coefficient region
@@ -242,26 +247,32 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
     const double scale2 = dt / ((m - 1) * p->sum_g[2]);
     const double scale3 = dt * dt * m / ((double)(m - 1) * (m - 2) * p->sum_g[3]);
     const double scale4 = dt * dt * dt * m * (m + 1.0) / ((double)(m - 1) * (m - 2) * (m - 3) * p->sum_g[4]);
-    B.ri.assign(n, RecInfo{});
-    B.rd.assign(n, ps::RecDesc{});
-    for (int r = 0; r < n; ++r) {
-        RecInfo& q = B.ri[r];
-        q.Np = (recs[r].n_samples / p->N) / m;
+    B.stride = p->interlaced ? 2 : 1;
+    const int n_int = n * B.stride;
+    B.ri.assign(n_int, RecInfo{});
+    B.rd.assign(n_int, ps::RecDesc{});
+    for (int ir = 0; ir < n_int; ++ir) {
+        const ps_record& rec = recs[ir / B.stride];
+        // the shifted frame set of interlaced windows starts T/2 = N/2 samples later
+        const int64_t skip = (ir % B.stride) ? p->N / 2 : 0;
+        const size_t esz = rec.dtype == PS_F32 ? 4 : (rec.dtype == PS_F64 ? 8 : 2);
+        RecInfo& q = B.ri[ir];
+        q.Np = (std::max<int64_t>(0, rec.n_samples - skip) / p->N) / m;
         q.F = q.Np * m;
         q.frame0 = B.F_tot;
         q.chunk0 = B.chunks_tot;
         B.F_tot += q.F;
         B.chunks_tot += q.Np;
-        ps::RecDesc& d = B.rd[r];
-        d.data = recs[r].d_data;
-        d.chan_stride = recs[r].channel_stride;
+        ps::RecDesc& d = B.rd[ir];
+        d.data = q.Np > 0 ? static_cast<const char*>(rec.d_data) + skip * esz : rec.d_data;
+        d.chan_stride = rec.channel_stride;
         d.frame0 = q.frame0;
-        d.dtype = recs[r].dtype;
+        d.dtype = rec.dtype;
         d.pad = 0;
     }
     B.coef_rows = per_chunk ? m : B.F_tot;
 
-    // groups
+    // groups (interlaced windows: batched schedule only)
     if (per_chunk) {
         for (int r = 0; r < n; ++r)
             if (B.ri[r].Np > 0) {
@@ -275,7 +286,7 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
     const int64_t TT = (int64_t)ps::kTile * ps::kTile, TX = (int64_t)ps::kTileX * ps::kTileX;
     int64_t part = 0;
     for (Group& G : B.groups) {
-        const int r_lo = per_chunk ? G.rec : 0, r_hi = per_chunk ? G.rec + 1 : n;
+        const int r_lo = per_chunk ? G.rec : 0, r_hi = per_chunk ? G.rec + 1 : n_int;
         // units of every segment per stage, for the block counts
         std::vector<int64_t> U2, U3, U4s, U4x;
         for (int r = r_lo; r < r_hi; ++r) {
@@ -292,10 +303,26 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
         const int64_t L3 = units_per_block(U3, (int64_t)p->n_cu * p->bpc_s3);
         const int64_t L4s = units_per_block(U4s, (int64_t)p->n_cu * p->bpc_s4);
         const int64_t L4x = units_per_block(U4x, (int64_t)p->n_cu * p->bpc_s4x);
+        // finalize segments of the last first-set record, per combination, for
+        // its shifted twin (which follows it) to attach its partial sums to
+        std::vector<size_t> fin2(p->n2()), fin3(p->n3()), fin4(p->n4());
         for (int r = r_lo; r < r_hi; ++r) {
             const RecInfo& q = B.ri[r];
             if (q.Np == 0) continue;
-            const ps_output* o = outs ? &outs[r] : nullptr;
+            const bool twin = r % B.stride != 0;   // shifted set: no output of its own
+            const ps_output* o = outs ? &outs[r / B.stride] : nullptr;
+            // a finalize segment for the first set, or the twin's sums attached to it
+            auto finalize = [&](SegTable& f, std::vector<size_t>& fin, int i, const ps::Seg& sg, int64_t items) {
+                if (!twin) {
+                    fin[i] = f.v.size();
+                    f.add(sg, items);
+                } else {
+                    ps::Seg& a = f.v[fin[i]];
+                    a.part2 = sg.part;
+                    a.n_chunks2 = sg.n_chunks;
+                    a.blocks2 = sg.blocks;
+                }
+            };
             ps::Seg base{};
             base.coef = q.chunk0 * m * K;
             base.n_chunks = (int32_t)q.Np;
@@ -312,7 +339,7 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 sg.scale = scale2;
                 sg.ncomp = 4;
                 G.s2.add(sg, sg.blocks);
-                G.f2.add(sg, kblocks);
+                finalize(G.f2, fin2, i, sg, kblocks);
             }
             for (int i = 0; i < p->n3(); ++i) {
                 ps::Seg sg = base;
@@ -329,7 +356,7 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 sg.sym = sym;
                 sg.ncomp = 4;
                 G.s3.add(sg, sg.blocks);
-                G.f3.add(sg, (int64_t)sg.n_tiles * (TT / 256));
+                finalize(G.f3, fin3, i, sg, (int64_t)sg.n_tiles * (TT / 256));
             }
             for (int i = 0; i < p->n4(); ++i) {
                 ps::Seg sg = base;
@@ -347,13 +374,13 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 sg.scale = p->precision == PS_PREC_BF16X3 ? scale4 / (m * (m + 1.0)) : scale4;
                 sg.sym = sym;
                 (single ? G.s4s : G.s4x).add(sg, sg.blocks);
-                G.f4.add(sg, (int64_t)sg.n_tiles * ((single ? TT : TX) / 256));
+                finalize(G.f4, fin4, i, sg, (int64_t)sg.n_tiles * ((single ? TT : TX) / 256));
             }
         }
     }
     B.part_doubles = part;
     // table region: record descriptors, then every segment table
-    size_t tab = align64(sizeof(ps::RecDesc) * std::max(1, n));
+    size_t tab = align64(sizeof(ps::RecDesc) * std::max<size_t>(1, B.rd.size()));
     for (Group& G : B.groups)
         for (SegTable* t : G.all) {
             t->dev_off = tab;
@@ -492,6 +519,10 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
         return fail(PS_E_UNSUPPORTED, "FP16X2S needs m <= 10 (one scale per chunk and column)");
     if (cfg->schedule != PS_SCHED_BATCHED && cfg->schedule != PS_SCHED_PER_CHUNK)
         return fail(PS_E_INVALID_ARG, "unknown schedule %d", cfg->schedule);
+    if (cfg->interlaced != 0 && cfg->interlaced != 1) return fail(PS_E_INVALID_ARG, "interlaced must be 0 or 1");
+    if (cfg->reserved != 0) return fail(PS_E_INVALID_ARG, "reserved must be 0");
+    if (cfg->interlaced && cfg->schedule != PS_SCHED_BATCHED)
+        return fail(PS_E_UNSUPPORTED, "interlaced windows need the batched schedule");
     int Nf = cfg->n_freq;
     if (Nf == 0) {
         if (!(cfg->f_max >= 0) || !std::isfinite(cfg->f_max))
@@ -519,6 +550,7 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     p->window_param = cfg->window_param;
     p->precision = cfg->precision;
     p->schedule = cfg->schedule;
+    p->interlaced = cfg->interlaced != 0;
 
     // Channel combinations: explicit lists or every orbit.
     std::vector<int8_t> a2, a3, a4;
@@ -932,7 +964,7 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
     const int Nf = p->Nf, m = p->m;
     const int64_t nf2 = (int64_t)Nf * Nf;
     for (int r = 0; r < n_rec; ++r) {
-        if (B.ri[r].Np > 0) continue;
+        if (B.ri[r * B.stride].Np > 0) continue;
         const ps_output& o = outs[r];
         PS_HIP(ps::launch_fill_nan(o.d_s2, 2 * (int64_t)p->n2() * Nf, st));
         PS_HIP(ps::launch_fill_nan(o.d_s2_err, 2 * (int64_t)p->n2() * Nf, st));
@@ -963,7 +995,7 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
 
     if (p->schedule != PS_SCHED_PER_CHUNK) {
         fa.recs = reinterpret_cast<const ps::RecDesc*>(tab);
-        fa.n_recs = n_rec;
+        fa.n_recs = (int)B.rd.size();
         fa.g_lo = 0;
         fa.g_hi = B.F_tot;
         fa.out_g0 = 0;

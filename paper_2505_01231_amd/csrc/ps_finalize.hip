@@ -9,6 +9,11 @@
 //   sigma = |scale| * sqrt(Var / Np)
 // where `scale` carries the k-statistic prefactor, dt^(n-1) and 1/sum g^n.
 // Np == 0 gives NaN everywhere; Np == 1 gives NaN error bars.
+// With interlaced windows a segment also carries the sums of the frame set
+// shifted by N/2 (its own chunks, n_chunks2 > 0): the output is the average of
+// the two sets' means and of their sigmas (Section 3 averages the interlaced
+// spectra; the mean of the sigmas bounds the error of the average whatever
+// the correlation between the overlapping sets).
 #include "ps_internal.h"
 
 namespace ps {
@@ -31,14 +36,20 @@ __device__ __forceinline__ void mean_sigma(double s, double s2, double np, doubl
     sigma = fabs(scale) * sqrt(fmax(var, 0.0) / np);
 }
 
+// The interlaced average of the two frame sets' results at one grid point.
+__device__ __forceinline__ void combine_sets(double& mean, double& sigma, double mean2, double sigma2) {
+    mean = 0.5 * (mean + mean2);
+    sigma = 0.5 * (sigma + sigma2);
+}
+
 // S2: one block per (record, combination, 16-wide k group of a 256-wide k
-// block).  Thread (g, kk) adds the slots s0 + g, s0 + g + 16, ... of point
-// kk; the 16 group sums are then added in LDS in group order (a fixed order,
-// so the result does not depend on timing).
+// block).  Thread (g, kk) adds the slots s0 + g, s0 + g + 16, ... of point kk
+// (of each frame set); the 16 group sums are then added in LDS in group order
+// (a fixed order, so the result does not depend on timing).
 constexpr int kVecGroups = 16;
 
 __global__ __launch_bounds__(256) void k_finalize_vec(FinalizeArgs p) {
-    __shared__ double red[kVecGroups][4][16];
+    __shared__ double red[kVecGroups][8][16];
     const int64_t x = blockIdx.x / kVecGroups;         // item: a 256-wide k block
     if (x >= p.n_items) return;
     const int sub = blockIdx.x % kVecGroups;
@@ -47,25 +58,35 @@ __global__ __launch_bounds__(256) void k_finalize_vec(FinalizeArgs p) {
     const int kk = threadIdx.x & 15, g = threadIdx.x >> 4;
     const int kl = 16 * sub + kk;                       // k within the item
     const int k = (int)t * 256 + kl;
-    int64_t s0 = 0, ns = 0;
-    if (sg.n_chunks > 0) slot_range(Sched{sg.n_tiles, sg.n_chunks, sg.blocks}, t, s0, ns);
-    double s[4] = {0, 0, 0, 0};
-    const double* part = p.part + sg.part + kl;
-    for (int64_t slot = s0 + g; slot < s0 + ns; slot += kVecGroups) {
-        const double* q = part + slot * 4 * 256;
-        for (int c = 0; c < 4; ++c) s[c] += q[c * 256];
+    const bool two = sg.n_chunks2 > 0;
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int set = 0; set < (two ? 2 : 1); ++set) {
+        const int64_t W = set ? sg.n_chunks2 : sg.n_chunks;
+        int64_t s0 = 0, ns = 0;
+        if (W > 0) slot_range(Sched{sg.n_tiles, W, set ? sg.blocks2 : sg.blocks}, t, s0, ns);
+        const double* part = p.part + (set ? sg.part2 : sg.part) + kl;
+        for (int64_t slot = s0 + g; slot < s0 + ns; slot += kVecGroups) {
+            const double* q = part + slot * 4 * 256;
+            for (int c = 0; c < 4; ++c) s[4 * set + c] += q[c * 256];
+        }
     }
-    for (int c = 0; c < 4; ++c) red[g][c][kk] = s[c];
+    for (int c = 0; c < 8; ++c) red[g][c][kk] = s[c];
     __syncthreads();
     if (g != 0 || k >= p.Nf) return;
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < 8; ++c) {
         s[c] = 0;
         for (int gg = 0; gg < kVecGroups; ++gg) s[c] += red[gg][c][kk];
     }
-    const double np = (double)sg.n_chunks;
     double mr, sr, mi, si;
-    mean_sigma(s[0], s[2], np, sg.scale, mr, sr);
-    mean_sigma(s[1], s[3], np, sg.scale, mi, si);
+    mean_sigma(s[0], s[2], (double)sg.n_chunks, sg.scale, mr, sr);
+    mean_sigma(s[1], s[3], (double)sg.n_chunks, sg.scale, mi, si);
+    if (two) {
+        double mr2, sr2, mi2, si2;
+        mean_sigma(s[4], s[6], (double)sg.n_chunks2, sg.scale, mr2, sr2);
+        mean_sigma(s[5], s[7], (double)sg.n_chunks2, sg.scale, mi2, si2);
+        combine_sets(mr, sr, mr2, sr2);
+        combine_sets(mi, si, mi2, si2);
+    }
     if (sg.out) {
         sg.out[2 * k] = mr;
         sg.out[2 * k + 1] = mi;
@@ -95,10 +116,8 @@ __global__ __launch_bounds__(256) void k_finalize_tiles(FinalizeArgs p) {
     const int2 t = p.tt.t[sg.tiles][tile];
     const int kb = t.x * E + 16 * (sb / sub), lb = t.y * E + 16 * (sb % sub);   // sub-block origin
     const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
-    const double np = (double)sg.n_chunks;
     const int ncomp = sg.ncomp;
-    int64_t s0 = 0, ns = 0;
-    if (sg.n_chunks > 0) slot_range(Sched{sg.n_tiles, sg.n_chunks, sg.blocks}, tile, s0, ns);
+    const bool two = sg.n_chunks2 > 0;
 
     const int k = kb + i, l = lb + j;
     const bool valid = k < p.Nf && l < p.Nf && !(sg.sym && k > l);
@@ -107,24 +126,38 @@ __global__ __launch_bounds__(256) void k_finalize_tiles(FinalizeArgs p) {
     // and every component of every slot is loaded before any is added (one
     // round trip to memory, not one per component).
     const int idx = (16 * (sb / sub) + i) * E + 16 * (sb % sub) + j;
-    double s[4] = {0, 0, 0, 0};
-    for (int64_t slot = s0; slot < s0 + ns; ++slot) {
-        const double* q = p.part + sg.part + slot * ncomp * TT + idx;
-        double v[4];
+    for (int set = 0; set < (two ? 2 : 1); ++set) {
+        const int64_t W = set ? sg.n_chunks2 : sg.n_chunks;
+        const double np = (double)W;
+        int64_t s0 = 0, ns = 0;
+        if (W > 0) slot_range(Sched{sg.n_tiles, W, set ? sg.blocks2 : sg.blocks}, tile, s0, ns);
+        const double* base = p.part + (set ? sg.part2 : sg.part) + idx;
+        double s[4] = {0, 0, 0, 0};
+        for (int64_t slot = s0; slot < s0 + ns; ++slot) {
+            const double* q = base + slot * ncomp * TT;
+            double v[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) v[c] = c < ncomp ? q[c * TT] : 0.0;
+            for (int c = 0; c < 4; ++c) v[c] = c < ncomp ? q[c * TT] : 0.0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) s[c] += v[c];
+            for (int c = 0; c < 4; ++c) s[c] += v[c];
+        }
+        double r_m, r_s, i_m = 0.0, i_s = 0.0;
+        if (ncomp == 4) {
+            mean_sigma(s[0], s[2], np, sg.scale, r_m, r_s);
+            mean_sigma(s[1], s[3], np, sg.scale, i_m, i_s);
+        } else {
+            mean_sigma(s[0], s[1], np, sg.scale, r_m, r_s);
+            if (np < 1.0) i_m = r_m;    // NaN
+            if (np < 2.0) i_s = r_s;    // NaN
+        }
+        if (set == 0) {
+            mr = r_m, sr = r_s, mi = i_m, si = i_s;
+        } else {
+            combine_sets(mr, sr, r_m, r_s);
+            combine_sets(mi, si, i_m, i_s);
+        }
     }
     if (valid) {
-        if (ncomp == 4) {
-            mean_sigma(s[0], s[2], np, sg.scale, mr, sr);
-            mean_sigma(s[1], s[3], np, sg.scale, mi, si);
-        } else {
-            mean_sigma(s[0], s[1], np, sg.scale, mr, sr);
-            if (np < 1.0) mi = mr;      // NaN
-            if (np < 2.0) si = sr;      // NaN
-        }
         const int64_t o = ((int64_t)k * p.Nf + l) * 2;
         if (sg.out) {
             sg.out[o] = mr;

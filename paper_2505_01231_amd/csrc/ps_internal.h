@@ -135,6 +135,11 @@ struct Seg {
     double scale;           // finalize: prefactor * dt^(n-1) / sum g^n
     int32_t sym;            // finalize: mirror (k, l) -> (l, k)
     int32_t ncomp;          // finalize: 4 (complex) or 2 (real)
+    // finalize with interlaced windows: the partial sums of the shifted frame
+    // set (its own Sched{n_tiles, n_chunks2, blocks2}); n_chunks2 == 0: none
+    int64_t part2;
+    int32_t n_chunks2;
+    int32_t blocks2;
 };
 
 struct BatchArgs {

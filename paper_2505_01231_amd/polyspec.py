@@ -57,12 +57,14 @@ class Spectra:
 
 
 class Plan:
-    """A configured estimator (ps_plan_t)."""
+    """A configured estimator (ps_plan_t).  ``interlaced=True`` averages the
+    spectra of the frames starting at sample 0 and of the frames starting half a
+    frame later (Section 3's interlaced windows; batched schedule only)."""
 
     def __init__(self, frame_len: int, n_freq: int = 0, m: int = 10, dt: float = 1.0,
                  orders=(2, 3, 4), n_channels: int = 1, window: str = "acg",
                  window_param: float = 0.14, precision: str = "fp32", schedule: str = "batched",
-                 f_max: float = 0.0, combos2=None, combos3=None, combos4=None):
+                 f_max: float = 0.0, combos2=None, combos3=None, combos4=None, interlaced: bool = False):
         self._lib = L.load()
         self._handle = None
         cfg = L.ps_config()
@@ -78,6 +80,7 @@ class Plan:
         cfg.window = _WINDOWS[window]
         cfg.precision = _PRECISION[precision]
         cfg.schedule = _SCHEDULE[schedule]
+        cfg.interlaced = 1 if interlaced else 0
         self._keep = []
         for arity, combos in ((2, combos2), (3, combos3), (4, combos4)):
             n, arr, ptr = _flat(combos, arity)
@@ -96,6 +99,7 @@ class Plan:
         self.f_max = info.f_max
         self.sum_g = list(info.sum_g)
         self.n_channels = n_channels
+        self.interlaced = bool(interlaced)
         self.orders = tuple(orders)
         self.combos2 = [tuple(info.combos2[i * 2:(i + 1) * 2]) for i in range(info.n_combos2)]
         self.combos3 = [tuple(info.combos3[i * 3:(i + 1) * 3]) for i in range(info.n_combos3)]

@@ -498,6 +498,106 @@ def test_graph_replays_match_eager(dev, precision):
         g.close()
 
 
+# ---------------------------------------------------------------- interlaced windows (Section 3)
+def both_interlaced(z, dev, N, Nf, m, window="acg", n_channels=1, **kw):
+    gpu = run_gpu(z, dev, frame_len=N, n_freq=Nf, m=m, window=window, n_channels=n_channels,
+                  interlaced=True, **kw)
+    ref = O.polyspectra_interlaced(z, N, Nf, m, window_kind=window, combos2=gpu["plan"]["combos2"],
+                                   combos3=gpu["plan"]["combos3"], combos4=gpu["plan"]["combos4"])
+    return gpu, ref
+
+
+def _close_or_both_nan(a, b, tol):
+    nan_a, nan_b = np.isnan(a), np.isnan(b)
+    assert np.array_equal(nan_a, nan_b)
+    if nan_a.all():
+        return 0.0
+    e = rel_err(np.where(nan_a, 0, a), np.where(nan_b, 0, b))
+    assert e <= tol, e
+    return e
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_interlaced_matches_oracle(dev, precision):
+    """Interlaced windows: the spectra of the frames from sample 0 and of the
+    frames from sample N/2, averaged (error bars averaged likewise)."""
+    say("interlaced", precision)
+    N, Nf, m = 256, 60, 8
+    z = synth.ar2_chi2(N * m * 6 + 300, seed=71, dtype=np.float32)
+    gpu, ref = both_interlaced(z, dev, N, Nf, m, precision=precision)
+    assert gpu["n_chunks"] == ref["n_chunks"] == 6 and ref["n_chunks_shifted"] == 6
+    compare(gpu, ref, label=f"interlaced-{precision}")
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.int16])
+def test_interlaced_channels_and_dtypes(dev, dtype):
+    """Every combination orbit of two channels with interlaced windows; the
+    shifted frame set starts N/2 elements of the record's own type later."""
+    say("interlaced, 2 channels", np.dtype(dtype).name)
+    N, Nf, m = 512, 64, 10
+    if dtype == np.int16:
+        z, clipped = synth.mixed_channels(N * m * 4 + 700, seed=72, n_channels=2)
+        assert clipped == 0 and z.dtype == np.int16
+    else:
+        s = synth.ar2_chi2(N * m * 4 + 703, seed=72, r=0.9, dtype=np.float64)
+        z = np.stack([s[:-3], s[3:] ** 2 - 1.0])
+    gpu, ref = both_interlaced(z, dev, N, Nf, m, n_channels=2, precision="bf16x3")
+    compare(gpu, ref, label=f"interlaced-2ch-{np.dtype(dtype).name}")
+
+
+def test_interlaced_uneven_records(dev):
+    """Several records in one execute with interlaced windows: a record without
+    a complete chunk (NaN), one whose shifted set has no complete chunk (the
+    first set alone, NaN error bars as Np = 1), one with a single chunk in each
+    set, and longer ones; each equals the oracle and its own single execution."""
+    from paper_2505_01231_amd import Plan
+    say("interlaced uneven records")
+    N, Nf, m = 256, 50, 6
+    lengths = [N * m * 3 + 17, N * m - 1, N * m + N // 4, N * m + N // 2, N * m * 5 + 200]
+    zs = [synth.ar2_chi2(L, seed=80 + i, r=0.9, dtype=np.float32) for i, L in enumerate(lengths)]
+    xs = [torch.from_numpy(z).to(dev) for z in zs]
+    with Plan(frame_len=N, n_freq=Nf, m=m, window="hann", precision="bf16x3", interlaced=True) as p:
+        outs = p.execute(xs)
+        torch.cuda.synchronize()
+        singles = [p.execute(x) for x in xs]
+        torch.cuda.synchronize()
+        combos = dict(combos2=p.combos2, combos3=p.combos3, combos4=p.combos4)
+        for i, z in enumerate(zs):
+            o, s1 = outs[i], singles[i]
+            ref = O.polyspectra_interlaced(z, N, Nf, m, window_kind="hann", **combos)
+            assert o.n_chunks == ref["n_chunks"], i
+            if o.n_chunks == 0:
+                assert torch.isnan(o.s3).all() and torch.isnan(o.s4_err).all()
+                continue
+            for key in ("s2", "s3", "s4"):
+                g = torch.view_as_complex(getattr(o, key)).cpu().numpy()
+                g1 = torch.view_as_complex(getattr(s1, key)).cpu().numpy()
+                assert rel_err(g, ref[key]) <= TOL, (i, key, rel_err(g, ref[key]))
+                assert rel_err(g, g1) <= 1e-12, (i, key)
+                _close_or_both_nan(getattr(o, key + "_err").cpu().numpy(), ref[key + "_err"], TOL)
+
+
+def test_interlaced_graph_replays_match_eager(dev):
+    """A captured interlaced execute replays bit-identically to the eager one."""
+    from paper_2505_01231_amd import Plan
+    say("interlaced graph")
+    N, Nf, m = 1024, 160, 10
+    zs = [synth.ar2_chi2(N * m * n + N // 2 + 9, seed=90 + n, dtype=np.float32) for n in (2, 4)]
+    xs = [torch.from_numpy(z).to(dev) for z in zs]
+    with Plan(frame_len=N, n_freq=Nf, m=m, window="acg", precision="bf16x3", interlaced=True) as p:
+        g = p.graph(xs)
+        for rep in range(3):
+            outs = g.launch()
+            torch.cuda.synchronize()
+            eager = p.execute(xs)
+            torch.cuda.synchronize()
+            for o, e in zip(outs, eager):
+                for key in ("s2", "s3", "s4", "s2_err", "s3_err", "s4_err"):
+                    a, b = getattr(o, key).cpu().numpy(), getattr(e, key).cpu().numpy()
+                    assert np.array_equal(a, b, equal_nan=True), (rep, key)
+        g.close()
+
+
 # ---------------------------------------------------------------- launch configuration (autotuner)
 def _tuning_case(dev):
     """Two channels (every S3/S4 orbit, so all four tile tables are used), a
