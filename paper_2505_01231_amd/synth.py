@@ -18,6 +18,9 @@ Signals (all real valued, numpy PCG64 via ``default_rng(seed)``):
 * ``modulated_ar2``   -- an AR(2)/chi-square process whose drive amplitude
   ramps linearly in time: a non-stationary signal for quasi-polyspectra
   (Section 8).
+* ``drifting_ar2``    -- a Gaussian-driven AR(2) whose resonance angle moves
+  linearly from theta0 to theta1 over the record (Section 8's oscillator with a
+  drifting frequency); theta0 == theta1 gives the stationary process.
 """
 from __future__ import annotations
 
@@ -102,4 +105,19 @@ def modulated_ar2(n: int, seed: int, start: int = 0, total: int | None = None,
     t = (np.arange(start - burn, start + n, dtype=np.float64)).clip(0, None)
     e *= s0 + (s1 - s0) * t / max(total - 1, 1)
     x = lfilter([1.0], ar2_coeffs(r, theta), e)
+    return x[burn:].astype(dtype)
+
+
+def drifting_ar2(n: int, seed: int, theta0: float, theta1: float, r: float = 0.98,
+                 burn: int = 2000, dtype=np.float64) -> np.ndarray:
+    """x_n = 2 r cos(theta_n) x_{n-1} - r^2 x_{n-2} + w_n, w ~ N(0, 1), with
+    theta_n moving linearly from theta0 (at the first kept sample) to theta1
+    (at the last); ``burn`` start-up samples at theta0 are discarded."""
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal(n + burn)
+    theta = np.concatenate([np.full(burn, theta0), np.linspace(theta0, theta1, n)])
+    c1, c2 = 2.0 * r * np.cos(theta), r * r
+    x = np.zeros(n + burn)
+    for i in range(2, n + burn):
+        x[i] = c1[i] * x[i - 1] - c2 * x[i - 2] + w[i]
     return x[burn:].astype(dtype)

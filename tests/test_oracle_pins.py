@@ -551,3 +551,34 @@ def test_interlaced_error_bar_is_conservative():
         spread2 = np.var(np.array(means), axis=0, ddof=1)
         ratio = np.median(np.mean(np.array(errs) ** 2, axis=0) / spread2)
         assert 0.9 < ratio < 2.5, (k, ratio)
+
+
+# --------------------------------------------------------------------------
+# Quasi-polyspectra (Section 8): dependence on m flags non-stationarity
+# --------------------------------------------------------------------------
+
+
+def _diag_kurtosis(out):
+    """Mean over the band (S2 above a fifth of its peak) of S4(k, k) / S2(k)^2."""
+    s2, s4 = out["s2"][0].real, out["s4"][0].real
+    band = s2 > 0.2 * s2.max()
+    return float((np.diag(s4)[band] / s2[band] ** 2).mean())
+
+
+@pytest.mark.slow
+def test_quasi_spectra_depend_on_m_only_when_nonstationary():
+    """A Gaussian oscillator has zero trispectrum, for any m, when stationary.
+    When its frequency drifts, a chunk of many frames sees the power of each
+    bin rise and fall as the resonance passes, so the short-time estimates
+    acquire positive fourth cumulants on the diagonal (the quasi-correlations
+    of Section 8) that grow with m.  Measured by S4(k, k) / S2(k)^2 over the
+    band: near 0 for the stationary record at m = 40 and 400, large for the
+    drifting record at m = 400 and much smaller at m = 40."""
+    N, Nf, L = 64, 25, 64 * 4000
+    still = synth.drifting_ar2(L, seed=5, theta0=0.3 * np.pi, theta1=0.3 * np.pi)
+    drift = synth.drifting_ar2(L, seed=5, theta0=0.1 * np.pi, theta1=0.7 * np.pi)
+    q = {(name, m): _diag_kurtosis(O.polyspectra(z, N, Nf, m, orders=(2, 4)))
+         for name, z in (("still", still), ("drift", drift)) for m in (40, 400)}
+    assert abs(q["still", 40]) < 3 and abs(q["still", 400]) < 3, q
+    assert q["drift", 400] > 30, q
+    assert q["drift", 400] - q["drift", 40] > 25, q
