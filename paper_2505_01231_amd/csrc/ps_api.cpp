@@ -1059,6 +1059,46 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
     return enqueue_all(p, B, recs, n_rec, outs, ws, ws + B.off_tab, st);
 }
 
+namespace {
+
+// One record of m N samples per chunk [chunk_lo, chunk_lo + n) of `rec`.
+ps_status chunk_records(ps_plan_t p, const ps_record* rec, int64_t chunk_lo, int64_t n, std::vector<ps_record>& out) {
+    if (!p || !rec) return fail(PS_E_INVALID_ARG, "NULL argument");
+    const ps_status s = check_record(p, rec);
+    if (s != PS_OK) return s;
+    const int64_t np = (rec->n_samples / p->N) / p->m;
+    if (chunk_lo < 0 || n < 0 || n > 0x7fffffff || chunk_lo > np - n)
+        return fail(PS_E_INVALID_ARG, "chunks [%lld, %lld) outside the record's %lld", (long long)chunk_lo,
+                    (long long)(chunk_lo + n), (long long)np);
+    const int64_t esz = rec->dtype == PS_F32 ? 4 : (rec->dtype == PS_F64 ? 8 : 2);
+    const int64_t span = (int64_t)p->m * p->N;
+    out.assign((size_t)n, *rec);
+    for (int64_t i = 0; i < n; ++i) {
+        out[i].d_data = static_cast<const char*>(rec->d_data) + (chunk_lo + i) * span * esz;
+        out[i].n_samples = span;
+    }
+    return PS_OK;
+}
+
+}  // namespace
+
+ps_status ps_sequential_workspace_size(ps_plan_t p, const ps_record* rec, int64_t chunk_lo, int64_t n_chunks,
+                                       size_t* bytes) {
+    if (!bytes) return fail(PS_E_INVALID_ARG, "bytes is NULL");
+    std::vector<ps_record> rs;
+    const ps_status s = chunk_records(p, rec, chunk_lo, n_chunks, rs);
+    if (s != PS_OK) return s;
+    return ps_workspace_size(p, rs.data(), (int32_t)rs.size(), bytes);
+}
+
+ps_status ps_execute_sequential(ps_plan_t p, const ps_record* rec, int64_t chunk_lo, int64_t n_chunks, void* d_ws,
+                                size_t ws_bytes, const ps_output* outs, ps_stream_t stream) {
+    std::vector<ps_record> rs;
+    const ps_status s = chunk_records(p, rec, chunk_lo, n_chunks, rs);
+    if (s != PS_OK) return s;
+    return ps_execute(p, rs.data(), (int32_t)rs.size(), d_ws, ws_bytes, outs, stream);
+}
+
 // ------------------------------------------------------------------ graphs
 struct ps_graph_s {
     hipGraph_t graph = nullptr;

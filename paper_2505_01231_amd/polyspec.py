@@ -199,6 +199,40 @@ class Plan:
         self._last_workspace = workspace
         return outputs[0] if single else outputs
 
+    def sequential(self, x, chunk_lo: int = 0, n_chunks: int | None = None,
+                   workspace: torch.Tensor | None = None, stream=None) -> Spectra:
+        """Sequential spectra (ps_execute_sequential): the short-time estimate of
+        each chunk [chunk_lo, chunk_lo + n_chunks) of one record, not averaged.
+        The returned tensors carry a leading chunk dimension; error bars are NaN
+        (one chunk has no spread)."""
+        rec = self.record(x)
+        if n_chunks is None:
+            n_chunks = max(0, self.record_info(rec.n_samples)[0] - chunk_lo)
+        need = C.c_size_t()
+        L.check(self._lib.ps_sequential_workspace_size(self._handle, C.byref(rec), chunk_lo, n_chunks,
+                                                       C.byref(need)), "ps_sequential_workspace_size")
+        device = x.device
+        if workspace is None or workspace.numel() < need.value:
+            workspace = torch.empty(max(need.value, 256), dtype=torch.uint8, device=device)
+        nf = self.n_freq
+        f64 = dict(dtype=torch.float64, device=device)
+        n2, n3, n4 = len(self.combos2), len(self.combos3), len(self.combos4)
+        shape = {"s2": (n2, nf, 2), "s3": (n3, nf, nf, 2), "s4": (n4, nf, nf, 2)}
+        t = {}
+        for key, n in (("s2", n2), ("s3", n3), ("s4", n4)):
+            for suffix in ("", "_err"):
+                t[key + suffix] = torch.empty((n_chunks,) + shape[key], **f64) if n else None
+        outs = (L.ps_output * max(1, n_chunks))()
+        for i in range(n_chunks):
+            outs[i] = L.ps_output(*[None if t[k] is None else t[k][i].data_ptr()
+                                    for k in ("s2", "s2_err", "s3", "s3_err", "s4", "s4_err")])
+        st = torch.cuda.current_stream(device) if stream is None else stream
+        L.check(self._lib.ps_execute_sequential(self._handle, C.byref(rec), chunk_lo, n_chunks, workspace.data_ptr(),
+                                                workspace.numel(), outs, C.c_void_p(st.cuda_stream)),
+                "ps_execute_sequential")
+        self._last_workspace = workspace
+        return Spectra(n_chunks=n_chunks, flags=0, **t)
+
     def graph(self, xs, workspace: torch.Tensor | None = None, outputs=None) -> "Graph":
         """Capture the execution over these tensors/buffers as a HIP graph
         (ps_graph_create); replay with Graph.launch()."""
@@ -378,3 +412,25 @@ class Streamer:
             self.close()
         except Exception:
             pass
+
+
+def quasi_spectra(x, ms, **plan_kw) -> dict:
+    """Quasi-polyspectra for several chunk lengths m (Section 8): one plan per m
+    over the same record.  For a stationary signal the spectra do not depend on
+    m (within their error bars); a change with m points to non-stationarity.
+    Returns {m: Spectra}."""
+    out = {}
+    for m in ms:
+        with Plan(m=m, **plan_kw) as p:
+            out[m] = p.execute(x)
+    torch.cuda.synchronize(x.device)
+    return out
+
+
+def m_dependence(a: Spectra, b: Spectra, key: str = "s4") -> torch.Tensor:
+    """Per grid point |S_a - S_b| / sqrt(sigma_a^2 + sigma_b^2) (real and
+    imaginary parts separately) between two quasi-spectra of one record
+    computed with different m."""
+    d = (getattr(a, key) - getattr(b, key)).abs()
+    e = (getattr(a, key + "_err") ** 2 + getattr(b, key + "_err") ** 2).sqrt()
+    return d / e

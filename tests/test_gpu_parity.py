@@ -598,6 +598,81 @@ def test_interlaced_graph_replays_match_eager(dev):
         g.close()
 
 
+# ---------------------------------------------------------------- sequential spectra, quasi-spectra (Section 8)
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_sequential_spectra_match_oracle_chunks(dev, precision):
+    """ps_execute_sequential: the short-time estimate of each chunk of a range,
+    not averaged, equals the oracle's per-chunk spectra; error bars are NaN."""
+    from paper_2505_01231_amd import Plan
+    say("sequential", precision)
+    N, Nf, m = 256, 40, 6
+    z = synth.ar2_chi2(N * m * 7 + 50, seed=101, dtype=np.float32)
+    ref = O.polyspectra(z, N, Nf, m, return_chunks=True)
+    with Plan(frame_len=N, n_freq=Nf, m=m, precision=precision) as p:
+        seq = p.sequential(torch.from_numpy(z).to(dev), chunk_lo=2, n_chunks=4)
+        torch.cuda.synchronize()
+        assert seq.n_chunks == 4
+        for i in range(4):
+            for o in (2, 3, 4):
+                g = torch.view_as_complex(getattr(seq, f"s{o}")[i]).cpu().numpy()
+                e = rel_err(g, ref[f"chunks{o}"][2 + i])
+                assert e <= TOL, (precision, i, o, e)
+                assert torch.isnan(getattr(seq, f"s{o}_err")[i]).all()
+
+
+def test_sequential_spectra_channels_and_errors(dev):
+    """Sequential spectra of every combination orbit of two channels (whole
+    record), and the range checks of ps_execute_sequential."""
+    import ctypes
+    from paper_2505_01231_amd import Plan
+    from paper_2505_01231_amd import _lib as L
+    say("sequential, 2 channels")
+    N, Nf, m = 256, 32, 5
+    s = synth.ar2_chi2(N * m * 3 + 9, seed=102, r=0.9, dtype=np.float64)
+    z = np.stack([s[:-3], s[3:] ** 2 - 1.0])
+    x = torch.from_numpy(z).to(dev)
+    with Plan(frame_len=N, n_freq=Nf, m=m, n_channels=2, precision="bf16x3") as p:
+        seq = p.sequential(x)
+        torch.cuda.synchronize()
+        ref = O.polyspectra(z, N, Nf, m, return_chunks=True, combos2=p.combos2, combos3=p.combos3,
+                            combos4=p.combos4)
+        assert seq.n_chunks == ref["n_chunks"] == 3
+        for c in range(3):
+            for o in (2, 3, 4):
+                g = torch.view_as_complex(getattr(seq, f"s{o}")[c]).cpu().numpy()
+                assert rel_err(g, ref[f"chunks{o}"][c]) <= TOL, (c, o)
+        rec = p.record(x)
+        n = ctypes.c_size_t()
+        for lo, cnt in ((2, 2), (-1, 1), (0, 4)):
+            st = p._lib.ps_sequential_workspace_size(p._handle, ctypes.byref(rec), lo, cnt, ctypes.byref(n))
+            assert st == L.PS_E_INVALID_ARG, (lo, cnt)
+        empty = p.sequential(x, chunk_lo=3, n_chunks=0)
+        assert empty.n_chunks == 0 and empty.s4.shape[0] == 0
+
+
+def test_quasi_spectra_sweep(dev):
+    """The m sweep of quasi-spectra on an oscillator whose frequency drifts:
+    every m matches the oracle, and the diagonal of S4 / S2^2 grows with m
+    (Section 8's quasi-correlations)."""
+    from paper_2505_01231_amd import quasi_spectra
+    say("quasi-spectra sweep")
+    N, Nf = 256, 64
+    z = synth.drifting_ar2(N * 1200, seed=103, theta0=0.1 * np.pi, theta1=0.7 * np.pi, dtype=np.float32)
+    res = quasi_spectra(torch.from_numpy(z).to(dev), [10, 300], frame_len=N, n_freq=Nf, orders=(2, 4),
+                        precision="bf16x3")
+    q = {}
+    for m, out in res.items():
+        ref = O.polyspectra(z, N, Nf, m, orders=(2, 4))
+        for key in ("s2", "s4"):
+            g = torch.view_as_complex(getattr(out, key)).cpu().numpy()
+            assert rel_err(g, ref[key]) <= TOL, (m, key)
+        s2, s4 = out.s2[0, :, 0].cpu().numpy(), out.s4[0, :, :, 0].cpu().numpy()
+        band = s2 > 0.2 * s2.max()
+        q[m] = float((np.diag(s4)[band] / s2[band] ** 2).mean())
+    say("  diagonal S4/S2^2 by m", q)
+    assert q[300] > 3 * max(q[10], 1.0), q
+
+
 # ---------------------------------------------------------------- launch configuration (autotuner)
 def _tuning_case(dev):
     """Two channels (every S3/S4 orbit, so all four tile tables are used), a
