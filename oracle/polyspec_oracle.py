@@ -18,8 +18,9 @@ Paper anchors (section / equation of the paper):
   The +j sign follows the Fourier convention of Appendix A.
 * Window: symmetric Hann, periodic Hann, or the approximate confined Gaussian
   window of Appendix B (sigma_t = 0.14 by default, Section 3).
-* Spectra: S2 (end of Section 3), S3 and the two-dimensional S4 cut
+* Spectra: S1 and S2 (end of Section 3), S3 and the two-dimensional S4 cut
   (Section 4), multichannel forms (Section 7):
+    S1_a        = C1(a_0)                    / (dt sum g)     (C1 = mean)
     S2_ab(k)    = C2(a_k, b*_k)              / (dt sum g^2)
     S3_abc(k,l) = C3(a_k, b_l, c*_{k+l})     / (dt sum g^3)
     S4_abcd(k,l)= C4(a_k, b*_k, c_l, d*_l)   / (dt sum g^4)
@@ -301,10 +302,12 @@ def polyspectra(z, N: int, Nf: int, m: int, dt: float = 1.0, window_kind: str = 
                 window_param: float = 0.14, orders=(2, 3, 4), combos2=None, combos3=None,
                 combos4=None, estimator: str = "kstat", method: str = "fft",
                 return_chunks: bool = False, g=None):
-    """S2, S3, S4 of a real record (single channel [L] or channels [C, L]).
+    """S1, S2, S3, S4 of a real record (single channel [L] or channels [C, L]).
 
-    Default combos for one channel: (0,0), (0,0,0), (0,0,0,0).
-    Returns a dict with 's2' [n2, Nf] complex, 's2_err' [n2, Nf, 2],
+    Default combos for one channel: (0,0), (0,0,0), (0,0,0,0).  S1 (order 1,
+    one value per channel) is included when 1 is in `orders`.
+    Returns a dict with 's1' [C] complex and 's1_err' [C, 2] (order 1 only),
+    's2' [n2, Nf] complex, 's2_err' [n2, Nf, 2],
     's3'/'s4' [n, Nf, Nf] complex and their errors, 'n_chunks', and (if asked)
     the per-chunk normalised spectra under 'chunks2/3/4'.
     """
@@ -332,8 +335,12 @@ def polyspectra(z, N: int, Nf: int, m: int, dt: float = 1.0, window_kind: str = 
     per2 = np.empty((Np, len(combos2), Nf), dtype=np.complex128)
     per3 = np.empty((Np, len(combos3), Nf, Nf), dtype=np.complex128)
     per4 = np.empty((Np, len(combos4), Nf, Nf), dtype=np.complex128)
+    per1 = np.empty((Np, C), dtype=np.complex128)
+    n1 = _norm(g, dt, 1)
     for p in range(Np):
         A = coefficients(frames[:, p], g, dt, K, method)      # [C, m, K]
+        # first-order k-statistic: the mean of a_0 over the chunk's frames
+        per1[p] = A[:, :, 0].mean(axis=1) / n1
         A = np.swapaxes(A, -1, -2)                            # [C, K, m]
         c2, c3, c4 = chunk_spectra(A, Nf, combos2, combos3, combos4, estimator)
         for i, v in enumerate(c2):
@@ -343,11 +350,15 @@ def polyspectra(z, N: int, Nf: int, m: int, dt: float = 1.0, window_kind: str = 
         for i, v in enumerate(c4):
             per4[p, i] = v / n4
     out = {"n_chunks": Np, "combos2": combos2, "combos3": combos3, "combos4": combos4}
+    if 1 in orders:
+        out["s1"], out["s1_err"] = average_with_error(per1)
     out["s2"], out["s2_err"] = average_with_error(per2)
     out["s3"], out["s3_err"] = average_with_error(per3)
     out["s4"], out["s4_err"] = average_with_error(per4)
     if return_chunks:
         out["chunks2"], out["chunks3"], out["chunks4"] = per2, per3, per4
+        if 1 in orders:
+            out["chunks1"] = per1
     return out
 
 
@@ -375,8 +386,9 @@ def polyspectra_interlaced(z, N: int, Nf: int, m: int, **kw):
         return out
     second = polyspectra(shifted_z, N, Nf, m, **kw)
     out = dict(first)
-    for key in ("s2", "s3", "s4", "s2_err", "s3_err", "s4_err"):
-        out[key] = 0.5 * (first[key] + second[key])
+    for key in ("s1", "s2", "s3", "s4", "s1_err", "s2_err", "s3_err", "s4_err"):
+        if key in first:
+            out[key] = 0.5 * (first[key] + second[key])
     out["n_chunks_shifted"] = second["n_chunks"]
     return out
 

@@ -582,3 +582,42 @@ def test_quasi_spectra_depend_on_m_only_when_nonstationary():
     assert abs(q["still", 40]) < 3 and abs(q["still", 400]) < 3, q
     assert q["drift", 400] > 30, q
     assert q["drift", 400] - q["drift", 40] > 25, q
+
+
+# --------------------------------------------------------------------------
+# First-order spectrum S1 (Section 3): the windowed mean
+# --------------------------------------------------------------------------
+
+
+@pytest.mark.parametrize("window_kind", ["hann", "acg"])
+def test_s1_of_a_constant_is_the_constant(window_kind):
+    """z = c gives a_0 = dt c sum g in every frame, so S1 = c exactly and its
+    error bar is 0 (a wrong bin, normalisation or dt factor breaks this)."""
+    N, Nf, m, c, dt = 32, 4, 5, -2.75, 0.5
+    z = np.full(N * m * 4, c)
+    out = O.polyspectra(z, N, Nf, m, dt=dt, window_kind=window_kind, orders=(1,))
+    assert np.allclose(out["s1"], c, rtol=1e-13, atol=0)
+    assert np.all(np.abs(out["s1_err"]) < 1e-12)
+
+
+def test_s1_shift_and_scale():
+    """S1 is linear: S1(alpha z + c) = alpha S1(z) + c per channel, while S2
+    does not see the offset (per-chunk centring)."""
+    N, Nf, m = 32, 6, 4
+    rng = np.random.default_rng(99)
+    z = rng.standard_normal((2, N * m * 6))
+    a = O.polyspectra(z, N, Nf, m, orders=(1, 2))
+    b = O.polyspectra(3.0 * z + np.array([[1.5], [-4.0]]), N, Nf, m, orders=(1, 2))
+    assert np.allclose(b["s1"], 3.0 * a["s1"] + np.array([1.5, -4.0]), rtol=0, atol=1e-12)
+    assert np.allclose(b["s1_err"], 3.0 * a["s1_err"], rtol=1e-10)
+    assert np.allclose(b["s2"], 9.0 * a["s2"], rtol=1e-10)
+
+
+def test_s1_of_white_noise_is_its_mean():
+    """E S1 = mu for i.i.d. samples of mean mu (any window), within the
+    estimator's own error bar."""
+    N, Nf, m = 64, 4, 10
+    z = 0.7 + np.random.default_rng(100).standard_normal(N * m * 200)
+    out = O.polyspectra(z, N, Nf, m, orders=(1,))
+    s1, e = out["s1"][0].real, out["s1_err"][0][0]
+    assert abs(s1 - 0.7) < 4 * e and 0 < e < 0.01
