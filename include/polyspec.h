@@ -81,6 +81,7 @@ typedef enum ps_precision { PS_PREC_FP32 = 0, PS_PREC_BF16X3 = 1, PS_PREC_FP16X2
  * "plain" schedule. */
 typedef enum ps_schedule { PS_SCHED_BATCHED = 0, PS_SCHED_PER_CHUNK = 1 } ps_schedule;
 
+#define PS_ORDER_S1 (1u << 1) /* first-order spectrum: the windowed mean (Section 3) */
 #define PS_ORDER_S2 (1u << 2)
 #define PS_ORDER_S3 (1u << 3)
 #define PS_ORDER_S4 (1u << 4)
@@ -95,7 +96,7 @@ typedef struct ps_config {
     int32_t n_channels;   /* 1..4 (Section 7) */
     int32_t frame_len;    /* N: power of two, 256..8192 */
     int32_t n_freq;       /* N_f; 0 => floor(f_max * N * dt) + 1 */
-    int32_t m;            /* frames per chunk: >= 2 (S2), >= 3 (S3), >= 4 (S4) */
+    int32_t m;            /* frames per chunk: >= 1 (S1), >= 2 (S2), >= 3 (S3), >= 4 (S4) */
     double f_max;         /* used only when n_freq == 0 */
     double dt;            /* sampling step, > 0 */
     double window_param;  /* sigma_t for PS_WIN_ACG (> 0) */
@@ -137,8 +138,10 @@ typedef struct ps_record {
 
 /* Output of one record.  Spectra are FP64 interleaved complex (re, im); error
  * bars are (sigma_re, sigma_im) pairs.  Layouts: S2 [n_combos2][N_f],
- * S3 and S4 [n_combos][N_f][N_f] with index [k][l].  Any pointer may be NULL if
- * its order was not requested.  Units: (input unit)^n * dt^(n-1). */
+ * S3 and S4 [n_combos][N_f][N_f] with index [k][l], S1 [n_channels] (one value
+ * per channel: S1_a = C1(a_0) / (dt sum g), the windowed mean; real, so its
+ * imaginary part and sigma_im are 0).  Any pointer may be NULL if its order
+ * was not requested.  Units: (input unit)^n * dt^(n-1). */
 typedef struct ps_output {
     double* d_s2;
     double* d_s2_err;
@@ -146,6 +149,8 @@ typedef struct ps_output {
     double* d_s3_err;
     double* d_s4;
     double* d_s4_err;
+    double* d_s1;     /* PS_ORDER_S1 */
+    double* d_s1_err;
 } ps_output;
 
 typedef struct ps_plan_info {

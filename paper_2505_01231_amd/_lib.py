@@ -16,7 +16,7 @@ PS_F32, PS_F64, PS_I16 = 0, 1, 2
 PS_WIN_HANN, PS_WIN_HANN_PERIODIC, PS_WIN_ACG = 0, 1, 2
 PS_PREC_FP32, PS_PREC_BF16X3, PS_PREC_FP16X2S = 0, 1, 2
 PS_SCHED_BATCHED, PS_SCHED_PER_CHUNK = 0, 1
-PS_ORDER_S2, PS_ORDER_S3, PS_ORDER_S4 = 1 << 2, 1 << 3, 1 << 4
+PS_ORDER_S1, PS_ORDER_S2, PS_ORDER_S3, PS_ORDER_S4 = 1 << 1, 1 << 2, 1 << 3, 1 << 4
 PS_FLAG_EMPTY, PS_FLAG_NO_ERRBAR = 1, 2
 
 EXPORTED = (
@@ -50,7 +50,8 @@ class ps_record(C.Structure):
 
 class ps_output(C.Structure):
     _fields_ = [("d_s2", C.c_void_p), ("d_s2_err", C.c_void_p), ("d_s3", C.c_void_p),
-                ("d_s3_err", C.c_void_p), ("d_s4", C.c_void_p), ("d_s4_err", C.c_void_p)]
+                ("d_s3_err", C.c_void_p), ("d_s4", C.c_void_p), ("d_s4_err", C.c_void_p),
+                ("d_s1", C.c_void_p), ("d_s1_err", C.c_void_p)]
 
 
 class ps_plan_info(C.Structure):

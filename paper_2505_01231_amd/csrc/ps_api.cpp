@@ -218,8 +218,8 @@ struct SegTable {
 // (per-chunk schedule).
 struct Group {
     int rec = -1;           // record of a per-chunk group
-    SegTable s2, s3, s4s, s4x, f2, f3, f4;
-    SegTable* all[7] = {&s2, &s3, &s4s, &s4x, &f2, &f3, &f4};
+    SegTable s2, s3, s4s, s4x, f2, f3, f4, f1;
+    SegTable* all[8] = {&s2, &s3, &s4s, &s4x, &f2, &f3, &f4, &f1};
 };
 
 // With interlaced windows every caller record r becomes two internal records:
@@ -232,7 +232,7 @@ struct Batch {
     int64_t F_tot = 0, chunks_tot = 0;
     int64_t coef_rows = 0;          // frames resident per channel in the coefficient region
     std::vector<Group> groups;
-    size_t off_coef = 0, off_tab = 0, off_part = 0, total = 0;
+    size_t off_coef = 0, off_tab = 0, off_part = 0, off_s1 = 0, total = 0;
     size_t tab_bytes = 0;
     int64_t part_doubles = 0;
 };
@@ -305,7 +305,7 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
         const int64_t L4x = units_per_block(U4x, (int64_t)p->n_cu * p->bpc_s4x);
         // finalize segments of the last first-set record, per combination, for
         // its shifted twin (which follows it) to attach its partial sums to
-        std::vector<size_t> fin2(p->n2()), fin3(p->n3()), fin4(p->n4());
+        std::vector<size_t> fin2(p->n2()), fin3(p->n3()), fin4(p->n4()), fin1(p->C);
         for (int r = r_lo; r < r_hi; ++r) {
             const RecInfo& q = B.ri[r];
             if (q.Np == 0) continue;
@@ -326,6 +326,18 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
             ps::Seg base{};
             base.coef = q.chunk0 * m * K;
             base.n_chunks = (int32_t)q.Np;
+            if (p->has(1)) {
+                // S1 per channel: the record's per-chunk means of a_0 from index chunk0
+                for (int c = 0; c < p->C; ++c) {
+                    ps::Seg sg = base;
+                    sg.part = q.chunk0;
+                    sg.ch[0] = c;
+                    sg.out = o && o->d_s1 ? o->d_s1 + 2 * c : nullptr;
+                    sg.err = o && o->d_s1_err ? o->d_s1_err + 2 * c : nullptr;
+                    sg.scale = 1.0 / p->sum_g[1];
+                    finalize(G.f1, fin1, c, sg, 1);
+                }
+            }
             for (int i = 0; i < p->n2(); ++i) {
                 ps::Seg sg = base;
                 sg.n_tiles = kblocks;
@@ -394,6 +406,8 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
     off = align256(off + B.tab_bytes);
     B.off_part = off;
     off = align256(off + (size_t)B.part_doubles * sizeof(double));
+    B.off_s1 = off;
+    if (p->has(1)) off = align256(off + (size_t)p->C * B.chunks_tot * sizeof(float));
     B.total = std::max<size_t>(off, 256);
 }
 
@@ -497,9 +511,9 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     if (!cfg) return fail(PS_E_INVALID_ARG, "cfg is NULL");
     if (cfg->struct_size < sizeof(ps_config))
         return fail(PS_E_INVALID_ARG, "struct_size %u < %zu", cfg->struct_size, sizeof(ps_config));
-    const uint32_t known = PS_ORDER_S2 | PS_ORDER_S3 | PS_ORDER_S4;
+    const uint32_t known = PS_ORDER_S1 | PS_ORDER_S2 | PS_ORDER_S3 | PS_ORDER_S4;
     if (cfg->orders == 0 || (cfg->orders & ~known))
-        return fail(PS_E_INVALID_ARG, "orders must be a non-empty subset of {2,3,4}");
+        return fail(PS_E_INVALID_ARG, "orders must be a non-empty subset of {1,2,3,4}");
     if (cfg->n_channels < 1 || cfg->n_channels > 4)
         return fail(PS_E_INVALID_ARG, "n_channels must be 1..4");
     const int N = cfg->frame_len;
@@ -507,7 +521,10 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
         return fail(PS_E_UNSUPPORTED, "frame_len %d is not a power of two", N);
     if (N < 256 || N > 8192) return fail(PS_E_UNSUPPORTED, "frame_len %d outside 256..8192", N);
     if (!(cfg->dt > 0) || !std::isfinite(cfg->dt)) return fail(PS_E_INVALID_ARG, "dt must be > 0");
-    const int min_m = (cfg->orders & PS_ORDER_S4) ? 4 : (cfg->orders & PS_ORDER_S3) ? 3 : 2;
+    const int min_m = (cfg->orders & PS_ORDER_S4)   ? 4
+                      : (cfg->orders & PS_ORDER_S3) ? 3
+                      : (cfg->orders & PS_ORDER_S2) ? 2
+                                                    : 1;
     if (cfg->m < min_m) return fail(PS_E_INVALID_ARG, "m = %d < %d (k-statistic denominator)", cfg->m, min_m);
     if (cfg->window < PS_WIN_HANN || cfg->window > PS_WIN_ACG)
         return fail(PS_E_INVALID_ARG, "unknown window %d", cfg->window);
@@ -898,6 +915,8 @@ ps::FinalizeArgs fin_args(const ps_plan_s* p, const Batch& B, const SegTable& t,
     f.tt = p->tables();
     f.part = reinterpret_cast<const double*>(ws + B.off_part);
     f.Nf = p->Nf;
+    f.s1 = p->has(1) ? reinterpret_cast<const float*>(ws + B.off_s1) : nullptr;
+    f.s1_cs = B.chunks_tot;
     return f;
 }
 
@@ -936,6 +955,7 @@ ps_status launch_finalize(ps_plan_t p, const Batch& B, const Group& G, char* ws,
     if (G.f2.n_items) PS_HIP(ps::launch_finalize_vec(fin_args(p, B, G.f2, ws, tab), st));
     if (G.f3.n_items) PS_HIP(ps::launch_finalize_grid(fin_args(p, B, G.f3, ws, tab), st));
     if (G.f4.n_items) PS_HIP(ps::launch_finalize_grid(fin_args(p, B, G.f4, ws, tab), st));
+    if (G.f1.n_items) PS_HIP(ps::launch_finalize_s1(fin_args(p, B, G.f1, ws, tab), st));
     return PS_OK;
 }
 
@@ -951,7 +971,7 @@ ps_status validate_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, vo
         ps_status s = check_record(p, &recs[r]);
         if (s != PS_OK) return s;
         const ps_output& o = outs[r];
-        const double* ptrs[6] = {o.d_s2, o.d_s2_err, o.d_s3, o.d_s3_err, o.d_s4, o.d_s4_err};
+        const double* ptrs[8] = {o.d_s2, o.d_s2_err, o.d_s3, o.d_s3_err, o.d_s4, o.d_s4_err, o.d_s1, o.d_s1_err};
         for (const double* q : ptrs)
             if (q && !aligned(q, 8)) return fail(PS_E_INVALID_ARG, "output pointer misaligned");
     }
@@ -972,6 +992,10 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
         PS_HIP(ps::launch_fill_nan(o.d_s3_err, 2 * (int64_t)p->n3() * nf2, st));
         PS_HIP(ps::launch_fill_nan(o.d_s4, 2 * (int64_t)p->n4() * nf2, st));
         PS_HIP(ps::launch_fill_nan(o.d_s4_err, 2 * (int64_t)p->n4() * nf2, st));
+        if (p->has(1)) {
+            PS_HIP(ps::launch_fill_nan(o.d_s1, 2 * (int64_t)p->C, st));
+            PS_HIP(ps::launch_fill_nan(o.d_s1_err, 2 * (int64_t)p->C, st));
+        }
     }
     if (B.chunks_tot == 0) return PS_OK;
     float2* coef = reinterpret_cast<float2*>(ws + B.off_coef);
@@ -991,6 +1015,9 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
     ca.K = p->K;
     ca.m = m;
     ca.n_channels = p->C;
+    ca.s1 = p->has(1) ? reinterpret_cast<float*>(ws + B.off_s1) : nullptr;
+    ca.s1_cs = B.chunks_tot;
+    ca.s1_chunk0 = 0;
     ps_status s = PS_OK;
 
     if (p->schedule != PS_SCHED_PER_CHUNK) {
@@ -1028,6 +1055,7 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
                 PS_HIP(ps::launch_window_rfft(fa, st));
             }
             ca.n_chunks = 1;
+            ca.s1_chunk0 = B.ri[r].chunk0 + c;
             {
                 StageTimer t(p, st, 1);
                 PS_HIP(ps::launch_centre(ca, st));

@@ -278,12 +278,17 @@ constexpr int kCentreRegs = 16;
 // Grid: x = chunk * kblocks + (256-wide k block), y = channel (the chunk count
 // can exceed the 65536 limit of the y and z grid dimensions).
 __global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64_t coef_cs, int K, int m,
-                                                int kblocks) {
+                                                int kblocks, float* __restrict__ s1, int64_t s1_cs,
+                                                int64_t s1_chunk0) {
     const int64_t chunk = blockIdx.x / kblocks;
     const int k = (int)(blockIdx.x - chunk * kblocks) * 256 + threadIdx.x;
     if (k >= K) return;
     float2* p = coef + blockIdx.y * coef_cs + chunk * m * K + k;
     const float inv = 1.0f / (float)m;
+    // S1: the chunk's mean of a_0 (real for a real signal)
+    auto keep_mean = [&](float mr) {
+        if (s1 && k == 0) s1[blockIdx.y * s1_cs + s1_chunk0 + chunk] = mr;
+    };
     if (m <= kCentreRegs) {
         float2 v[kCentreRegs];
         float sr = 0.f, si = 0.f;
@@ -296,6 +301,7 @@ __global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64
             }
         }
         const float mr = sr * inv, mi = si * inv;
+        keep_mean(mr);
 #pragma unroll
         for (int f = 0; f < kCentreRegs; ++f)
             if (f < m) p[(int64_t)f * K] = make_float2(v[f].x - mr, v[f].y - mi);
@@ -308,6 +314,7 @@ __global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64
         si += v.y;
     }
     const float mr = sr * inv, mi = si * inv;
+    keep_mean(mr);
     for (int f = 0; f < m; ++f) {
         const float2 v = p[(int64_t)f * K];
         p[(int64_t)f * K] = make_float2(v.x - mr, v.y - mi);
@@ -335,7 +342,7 @@ hipError_t launch_centre(const CentreArgs& a, hipStream_t s) {
     const int64_t nx = (int64_t)kblocks * a.n_chunks;
     if (nx > 0x7fffffff) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)nx, a.n_channels);
-    k_centre<<<grid, 256, 0, s>>>(a.coef, a.coef_chan_stride, a.K, a.m, kblocks);
+    k_centre<<<grid, 256, 0, s>>>(a.coef, a.coef_chan_stride, a.K, a.m, kblocks, a.s1, a.s1_cs, a.s1_chunk0);
     return hipGetLastError();
 }
 

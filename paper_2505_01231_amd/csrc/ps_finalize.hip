@@ -194,6 +194,54 @@ __global__ void k_fill_nan(double* p, int64_t n) {
     if (i < n) p[i] = __longlong_as_double(0x7ff8000000000000LL);
 }
 
+// S1: one block per (record, channel).  Thread t adds the per-chunk means of
+// a_0 of chunks t, t + 256, ... in FP64 (of each frame set); the partial sums
+// are then added in a fixed tree order.  S1 is real: Im = 0, sigma_Im = 0
+// (NaN where the mean or the error bar is undefined).
+__global__ __launch_bounds__(256) void k_finalize_s1(FinalizeArgs p) {
+    __shared__ double red[4][256];
+    const int64_t x = blockIdx.x;
+    if (x >= p.n_items) return;
+    const Seg& sg = p.segs[find_seg(p.segs, p.n_segs, x)];
+    const bool two = sg.n_chunks2 > 0;
+    const float* v = p.s1 + (int64_t)sg.ch[0] * p.s1_cs;
+    const int tid = threadIdx.x;
+    for (int set = 0; set < 2; ++set) {
+        const int64_t c0 = set ? sg.part2 : sg.part, W = set ? (two ? sg.n_chunks2 : 0) : sg.n_chunks;
+        double s = 0.0, s2 = 0.0;
+        for (int64_t c = tid; c < W; c += 256) {
+            const double d = v[c0 + c];
+            s += d;
+            s2 = fma(d, d, s2);
+        }
+        red[2 * set][tid] = s;
+        red[2 * set + 1][tid] = s2;
+    }
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h)
+            for (int q = 0; q < 4; ++q) red[q][tid] += red[q][tid + h];
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    double mean, sigma;
+    mean_sigma(red[0][0], red[1][0], (double)sg.n_chunks, sg.scale, mean, sigma);
+    if (two) {
+        double mean2, sigma2;
+        mean_sigma(red[2][0], red[3][0], (double)sg.n_chunks2, sg.scale, mean2, sigma2);
+        combine_sets(mean, sigma, mean2, sigma2);
+    }
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    if (sg.out) {
+        sg.out[0] = mean;
+        sg.out[1] = mean == mean ? 0.0 : nan;
+    }
+    if (sg.err) {
+        sg.err[0] = sigma;
+        sg.err[1] = sigma == sigma ? 0.0 : nan;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_finalize_vec(const FinalizeArgs& a, hipStream_t s) {
@@ -208,6 +256,11 @@ hipError_t launch_finalize_grid(const FinalizeArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_finalize_s1(const FinalizeArgs& a, hipStream_t s) {
+    if (a.n_items <= 0 || !a.s1) return hipSuccess;
+    k_finalize_s1<<<(unsigned)a.n_items, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill_nan(double* p, int64_t n, hipStream_t s) {
     if (!p || n <= 0) return hipSuccess;

@@ -75,13 +75,17 @@ __host__ __device__ constexpr int fft_twiddle_count(int log2n) {
     return (1 << log2n) + fft_radix2(log2n) * 16 + fft_radix3(log2n) * 16 * fft_radix2(log2n);
 }
 
-// In-place centring: a_k(f) -= mean over the m frames of its chunk.
+// In-place centring: a_k(f) -= mean over the m frames of its chunk.  With
+// `s1` set, the chunk's mean of Re a_0 (the first-order k-statistic) is also
+// stored at s1[channel * s1_cs + s1_chunk0 + chunk].
 struct CentreArgs {
     float2* coef;           // [C][n_chunks * m][K]
     int64_t coef_chan_stride;
     int K, m;
     int64_t n_chunks;
     int n_channels;
+    float* s1;
+    int64_t s1_cs, s1_chunk0;
 };
 hipError_t launch_centre(const CentreArgs& a, hipStream_t s);
 
@@ -181,10 +185,16 @@ struct FinalizeArgs {
     TileTables tt;
     const double* part;
     int Nf;
+    const float* s1;        // per-chunk means of a_0, [C][s1_cs] (S1 only)
+    int64_t s1_cs;
 };
 hipError_t launch_finalize_vec(const FinalizeArgs& a, hipStream_t s);
 // Items are 16 x 16 sub-blocks of tiles; symmetric spectra are mirrored here.
 hipError_t launch_finalize_grid(const FinalizeArgs& a, hipStream_t s);
+// S1: one item per (record, channel); Seg.part (and part2) hold the index of
+// the record's (and its interlaced twin's) first chunk in `s1`, Seg.ch[0] the
+// channel.
+hipError_t launch_finalize_s1(const FinalizeArgs& a, hipStream_t s);
 
 hipError_t launch_fill_nan(double* p, int64_t n, hipStream_t s);
 

@@ -42,7 +42,8 @@ def _flat(combos, arity):
 
 @dataclass
 class Spectra:
-    """Outputs of one record (FP64; complex values as trailing (re, im))."""
+    """Outputs of one record (FP64; complex values as trailing (re, im)).
+    s1 [n_channels, 2] holds S1 (the windowed mean) when order 1 was requested."""
     s2: torch.Tensor | None
     s2_err: torch.Tensor | None
     s3: torch.Tensor | None
@@ -51,6 +52,14 @@ class Spectra:
     s4_err: torch.Tensor | None
     n_chunks: int
     flags: int
+    s1: torch.Tensor | None = None
+    s1_err: torch.Tensor | None = None
+
+    def c_struct(self) -> L.ps_output:
+        """The ps_output of these tensors (NULL for the orders not held)."""
+        p = Plan._ptr
+        return L.ps_output(p(self.s2), p(self.s2_err), p(self.s3), p(self.s3_err), p(self.s4), p(self.s4_err),
+                           p(self.s1), p(self.s1_err))
 
     def complex(self, name: str) -> torch.Tensor:
         return torch.view_as_complex(getattr(self, name))
@@ -167,7 +176,9 @@ class Plan:
             s3_err=torch.empty((n3, nf, nf, 2), **f64) if n3 else None,
             s4=torch.empty((n4, nf, nf, 2), **f64) if n4 else None,
             s4_err=torch.empty((n4, nf, nf, 2), **f64) if n4 else None,
-            n_chunks=0, flags=0)
+            n_chunks=0, flags=0,
+            s1=torch.empty((self.n_channels, 2), **f64) if 1 in self.orders else None,
+            s1_err=torch.empty((self.n_channels, 2), **f64) if 1 in self.orders else None)
 
     @staticmethod
     def _ptr(t):
@@ -191,8 +202,7 @@ class Plan:
         for i, o in enumerate(outputs):
             n, fl = self.record_info(recs[i].n_samples)
             o.n_chunks, o.flags = n, fl
-            outs[i] = L.ps_output(self._ptr(o.s2), self._ptr(o.s2_err), self._ptr(o.s3),
-                                  self._ptr(o.s3_err), self._ptr(o.s4), self._ptr(o.s4_err))
+            outs[i] = o.c_struct()
         st = torch.cuda.current_stream(device) if stream is None else stream
         L.check(self._lib.ps_execute(self._handle, recs, len(xs), workspace.data_ptr(), workspace.numel(),
                                      outs, C.c_void_p(st.cuda_stream)), "ps_execute")
@@ -217,15 +227,16 @@ class Plan:
         nf = self.n_freq
         f64 = dict(dtype=torch.float64, device=device)
         n2, n3, n4 = len(self.combos2), len(self.combos3), len(self.combos4)
-        shape = {"s2": (n2, nf, 2), "s3": (n3, nf, nf, 2), "s4": (n4, nf, nf, 2)}
+        n1 = self.n_channels if 1 in self.orders else 0
+        shape = {"s1": (n1, 2), "s2": (n2, nf, 2), "s3": (n3, nf, nf, 2), "s4": (n4, nf, nf, 2)}
         t = {}
-        for key, n in (("s2", n2), ("s3", n3), ("s4", n4)):
+        for key, n in (("s1", n1), ("s2", n2), ("s3", n3), ("s4", n4)):
             for suffix in ("", "_err"):
                 t[key + suffix] = torch.empty((n_chunks,) + shape[key], **f64) if n else None
         outs = (L.ps_output * max(1, n_chunks))()
         for i in range(n_chunks):
             outs[i] = L.ps_output(*[None if t[k] is None else t[k][i].data_ptr()
-                                    for k in ("s2", "s2_err", "s3", "s3_err", "s4", "s4_err")])
+                                    for k in ("s2", "s2_err", "s3", "s3_err", "s4", "s4_err", "s1", "s1_err")])
         st = torch.cuda.current_stream(device) if stream is None else stream
         L.check(self._lib.ps_execute_sequential(self._handle, C.byref(rec), chunk_lo, n_chunks, workspace.data_ptr(),
                                                 workspace.numel(), outs, C.c_void_p(st.cuda_stream)),
@@ -250,8 +261,7 @@ class Plan:
         outs = (L.ps_output * len(xs))()
         for i, o in enumerate(outputs):
             o.n_chunks, o.flags = self.record_info(recs[i].n_samples)
-            outs[i] = L.ps_output(self._ptr(o.s2), self._ptr(o.s2_err), self._ptr(o.s3),
-                                  self._ptr(o.s3_err), self._ptr(o.s4), self._ptr(o.s4_err))
+            outs[i] = o.c_struct()
         h = C.c_void_p()
         L.check(self._lib.ps_graph_create(self._handle, recs, len(xs), workspace.data_ptr(), workspace.numel(),
                                           outs, C.byref(h)), "ps_graph_create")
@@ -288,8 +298,7 @@ class Plan:
         outs = (L.ps_output * len(xs))()
         for i, o in enumerate(outputs):
             o.n_chunks, o.flags = self.record_info(recs[i].n_samples)
-            outs[i] = L.ps_output(self._ptr(o.s2), self._ptr(o.s2_err), self._ptr(o.s3),
-                                  self._ptr(o.s3_err), self._ptr(o.s4), self._ptr(o.s4_err))
+            outs[i] = o.c_struct()
         st = torch.cuda.current_stream(device) if stream is None else stream
         rep = L.ps_tune_report()
         L.check(self._lib.ps_plan_autotune(self._handle, recs, len(xs), workspace.data_ptr(), workspace.numel(),
@@ -387,11 +396,10 @@ class Streamer:
         outs = [outputs] if isinstance(outputs, Spectra) else list(outputs)
         if len(outs) != n or not 1 <= n <= self.windows_per_push:
             raise ValueError(f"{n} windows with {len(outs)} outputs (at most {self.windows_per_push} per push)")
-        p = Plan._ptr
         arr = (L.ps_output * n)()
         for w, o in enumerate(outs):
             o.n_chunks, o.flags = self.n_chunks, self.flags
-            arr[w] = L.ps_output(p(o.s2), p(o.s2_err), p(o.s3), p(o.s3_err), p(o.s4), p(o.s4_err))
+            arr[w] = o.c_struct()
         st = torch.cuda.current_stream() if stream is None else stream
         slot = C.c_int32()
         L.check(self._plan._lib.ps_streamer_push_multi(self._handle, host_windows.data_ptr(), n, arr,

@@ -56,7 +56,7 @@ int main(void) {
   P(ps_tuning, s3_frame_batch) P(ps_tune_report, cand) P(ps_tune_report, ms)
   P(ps_config, dt) P(ps_config, window) P(ps_config, n_combos4) P(ps_config, combos2) P(ps_config, combos4)
   P(ps_config, interlaced) P(ps_config, reserved)
-  P(ps_record, n_samples) P(ps_record, dtype) P(ps_output, d_s4_err)
+  P(ps_record, n_samples) P(ps_record, dtype) P(ps_output, d_s4_err) P(ps_output, d_s1) P(ps_output, d_s1_err)
   P(ps_plan_info, f_max) P(ps_plan_info, sum_g) P(ps_plan_info, combos4)
   return 0;
 }
@@ -114,6 +114,8 @@ def _cfg(**kw):
     (dict(dt=float("nan")), L.PS_E_INVALID_ARG),
     (dict(orders=0), L.PS_E_INVALID_ARG),
     (dict(orders=1 << 5), L.PS_E_INVALID_ARG),
+    (dict(orders=1), L.PS_E_INVALID_ARG),               # bit 0 is no order
+    (dict(orders=L.PS_ORDER_S1 | L.PS_ORDER_S2, m=1), L.PS_E_INVALID_ARG),
     (dict(struct_size=8), L.PS_E_INVALID_ARG),
     (dict(window=7), L.PS_E_INVALID_ARG),
     (dict(window=L.PS_WIN_ACG, window_param=0.0), L.PS_E_INVALID_ARG),

@@ -673,6 +673,67 @@ def test_quasi_spectra_sweep(dev):
     assert q[300] > 3 * max(q[10], 1.0), q
 
 
+# ---------------------------------------------------------------- first-order spectrum S1 (Section 3)
+def _s1(out):
+    return out.s1[:, 0].cpu().numpy(), out.s1_err.cpu().numpy()
+
+
+@pytest.mark.parametrize("schedule", ["batched", "per_chunk"])
+def test_s1_matches_oracle(dev, schedule):
+    """S1 per channel (the windowed mean, with its error bar) next to S2..S4, on
+    two channels with different offsets, in both schedules; a record without a
+    chunk gives NaN."""
+    from paper_2505_01231_amd import Plan
+    say("S1", schedule)
+    N, Nf, m = 512, 60, 6
+    s = synth.ar2_chi2(N * m * 9 + 40, seed=111, r=0.9, dtype=np.float64)
+    z = np.stack([s[:-3] + 1.5, 0.5 * (s[3:] ** 2 - 1.0) - 0.25]).astype(np.float32)
+    with Plan(frame_len=N, n_freq=Nf, m=m, n_channels=2, orders=(1, 2, 3, 4), precision="bf16x3",
+              schedule=schedule) as p:
+        outs = p.execute([torch.from_numpy(z).to(dev), torch.from_numpy(z[:, :N * m - 1].copy()).to(dev)])
+        torch.cuda.synchronize()
+        ref = O.polyspectra(z, N, Nf, m, orders=(1, 2, 3, 4), combos2=p.combos2, combos3=p.combos3,
+                            combos4=p.combos4)
+        s1, e1 = _s1(outs[0])
+        assert rel_err(s1, ref["s1"].real) <= TOL, (s1, ref["s1"])
+        assert rel_err(e1, ref["s1_err"]) <= TOL
+        assert np.all(outs[0].s1[:, 1].cpu().numpy() == 0)
+        for key in ("s2", "s3", "s4"):
+            g = torch.view_as_complex(getattr(outs[0], key)).cpu().numpy()
+            assert rel_err(g, ref[key]) <= TOL, key
+        assert torch.isnan(outs[1].s1).all() and torch.isnan(outs[1].s1_err).all()
+
+
+def test_s1_alone_constant_interlaced_and_sequential(dev):
+    """An S1-only plan at m = 1 on a constant record gives the constant with a
+    zero error bar; S1 of interlaced windows and of sequential spectra follow
+    the oracle."""
+    from paper_2505_01231_amd import Plan
+    say("S1 alone / interlaced / sequential")
+    N = 256
+    c = torch.full((N * 7 + 5,), -3.25, device=dev)
+    with Plan(frame_len=N, n_freq=8, m=1, orders=(1,)) as p:
+        o = p.execute(c)
+        torch.cuda.synchronize()
+        assert o.n_chunks == 7 and o.s2 is None
+        assert abs(o.s1[0, 0].item() + 3.25) <= 1e-6 * 3.25 and abs(o.s1_err[0, 0].item()) <= 1e-6
+    Nf, m = 40, 5
+    z = synth.ar2_chi2(N * m * 6 + 200, seed=112, dtype=np.float32) + np.float32(0.75)
+    x = torch.from_numpy(z).to(dev)
+    with Plan(frame_len=N, n_freq=Nf, m=m, orders=(1, 2), interlaced=True) as p:
+        o = p.execute(x)
+        torch.cuda.synchronize()
+        ref = O.polyspectra_interlaced(z, N, Nf, m, orders=(1, 2))
+        s1, e1 = _s1(o)
+        assert rel_err(s1, ref["s1"].real) <= TOL and rel_err(e1, ref["s1_err"]) <= TOL
+    with Plan(frame_len=N, n_freq=Nf, m=m, orders=(1, 2)) as p:
+        seq = p.sequential(x)
+        torch.cuda.synchronize()
+        ref = O.polyspectra(z, N, Nf, m, orders=(1, 2), return_chunks=True)
+        g = seq.s1[:, :, 0].cpu().numpy()            # [chunks, channels]
+        assert rel_err(g, ref["chunks1"].real) <= TOL
+
+
 # ---------------------------------------------------------------- launch configuration (autotuner)
 def _tuning_case(dev):
     """Two channels (every S3/S4 orbit, so all four tile tables are used), a
