@@ -59,6 +59,7 @@ typedef enum ps_status {
 } ps_status;
 
 typedef enum ps_dtype { PS_F32 = 0, PS_F64 = 1, PS_I16 = 2 } ps_dtype;
+typedef enum ps_estimator { PS_EST_KSTAT = 0, PS_EST_NATURAL = 1 } ps_estimator;
 
 /* Window g_i, i = 0..N-1.  HANN: symmetric sin^2(pi i/(N-1)); HANN_PERIODIC:
  * sin^2(pi i/N); ACG: the approximate confined Gaussian of Appendix B with
@@ -110,8 +111,12 @@ typedef struct ps_config {
     const int8_t* combos3; /* host [n_combos3][3]: (a, b, c) -> C3(a_k, b_l, c*_{k+l}) */
     const int8_t* combos4; /* host [n_combos4][4]: (a, b, c, d) -> C4(a_k, b*_k, c_l, d*_l) */
     int32_t interlaced;    /* 0 or 1: interlaced windows (see below); PS_SCHED_BATCHED only */
-    int32_t reserved;      /* must be 0 */
+    int32_t estimator;     /* ps_estimator */
 } ps_config;
+/* Cumulant estimator per chunk.  PS_EST_KSTAT: the unbiased k-statistics of
+ * Section 4.1.  PS_EST_NATURAL: the natural (plug-in) estimator of Section 6,
+ * the cumulant's moment expression with sample means (biased by O(1/m); for
+ * comparisons).  S1 (the mean) is the same under both. */
 /* Interlaced windows (Section 3): the centre of a window weighs the signal more
  * than its edges; the same spectra computed on windows shifted by T/2 weigh it
  * the other way.  With interlaced = 1 every record (or streamer window) is

@@ -106,6 +106,7 @@ struct ps_plan_s {
     double dt = 1, f_max = 0, window_param = 0.14;
     uint32_t orders = 0;
     int window = 0, precision = 0, schedule = 0;
+    int estimator = PS_EST_KSTAT;
     bool interlaced = false;    // second frame set shifted by N/2, spectra averaged
     std::vector<int8_t> c2, c3, c4;
     double sum_g[5] = {0, 0, 0, 0, 0};
@@ -244,9 +245,14 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
     const int m = p->m, K = p->K, Nf = p->Nf;
     const int64_t nf2 = (int64_t)Nf * Nf;
     const double dt = p->dt;
-    const double scale2 = dt / ((m - 1) * p->sum_g[2]);
-    const double scale3 = dt * dt * m / ((double)(m - 1) * (m - 2) * p->sum_g[3]);
-    const double scale4 = dt * dt * dt * m * (m + 1.0) / ((double)(m - 1) * (m - 2) * (m - 3) * p->sum_g[4]);
+    // k-statistic prefactors (Section 4.1) or those of the natural estimator
+    // (Section 6: c2 = s2 / m, c3 = t3 / m, c4 = (m M4 - pairs) / m^2), with
+    // dt^(n-1) / sum g^n; scale4 goes with the form M4 - gamma (pairs).
+    const bool nat = p->estimator == PS_EST_NATURAL;
+    const double c4a = nat ? m : m * (m + 1.0);
+    const double scale2 = dt / ((nat ? m : m - 1) * p->sum_g[2]);
+    const double scale3 = dt * dt * (nat ? 1.0 / m : m / ((double)(m - 1) * (m - 2))) / p->sum_g[3];
+    const double scale4 = dt * dt * dt * c4a / ((nat ? (double)m * m : (double)(m - 1) * (m - 2) * (m - 3)) * p->sum_g[4]);
     B.stride = p->interlaced ? 2 : 1;
     const int n_int = n * B.stride;
     B.ri.assign(n_int, RecInfo{});
@@ -383,7 +389,7 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 sg.out = o && o->d_s4 ? o->d_s4 + 2 * i * nf2 : nullptr;
                 sg.err = o && o->d_s4_err ? o->d_s4_err + 2 * i * nf2 : nullptr;
                 // the BF16 x 3 matrix-core S4 kernels sum the numerator scaled by m(m+1)
-                sg.scale = p->precision == PS_PREC_BF16X3 ? scale4 / (m * (m + 1.0)) : scale4;
+                sg.scale = p->precision == PS_PREC_BF16X3 ? scale4 / c4a : scale4;
                 sg.sym = sym;
                 (single ? G.s4s : G.s4x).add(sg, sg.blocks);
                 finalize(G.f4, fin4, i, sg, (int64_t)sg.n_tiles * ((single ? TT : TX) / 256));
@@ -537,7 +543,8 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     if (cfg->schedule != PS_SCHED_BATCHED && cfg->schedule != PS_SCHED_PER_CHUNK)
         return fail(PS_E_INVALID_ARG, "unknown schedule %d", cfg->schedule);
     if (cfg->interlaced != 0 && cfg->interlaced != 1) return fail(PS_E_INVALID_ARG, "interlaced must be 0 or 1");
-    if (cfg->reserved != 0) return fail(PS_E_INVALID_ARG, "reserved must be 0");
+    if (cfg->estimator != PS_EST_KSTAT && cfg->estimator != PS_EST_NATURAL)
+        return fail(PS_E_INVALID_ARG, "unknown estimator %d", cfg->estimator);
     if (cfg->interlaced && cfg->schedule != PS_SCHED_BATCHED)
         return fail(PS_E_UNSUPPORTED, "interlaced windows need the batched schedule");
     int Nf = cfg->n_freq;
@@ -568,6 +575,7 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     p->precision = cfg->precision;
     p->schedule = cfg->schedule;
     p->interlaced = cfg->interlaced != 0;
+    p->estimator = cfg->estimator;
 
     // Channel combinations: explicit lists or every orbit.
     std::vector<int8_t> a2, a3, a4;
@@ -902,7 +910,10 @@ ps::BatchArgs batch_args(const ps_plan_s* p, const Batch& B, const SegTable& t, 
     a.win_lo = win_lo;
     a.win_hi = win_hi;
     a.accumulate = accumulate;
-    a.gamma = (p->m - 1.0) / (p->m * (p->m + 1.0));
+    const bool nat = p->estimator == PS_EST_NATURAL;
+    a.c4a = nat ? p->m : p->m * (p->m + 1);
+    a.c4b = nat ? 1 : p->m - 1;
+    a.gamma = (double)a.c4b / a.c4a;
     a.s3_fb = p->s3_fb;
     return a;
 }

@@ -159,7 +159,11 @@ struct BatchArgs {
     // processed and chunk c sits at frame (c - win_lo) m of the region.
     int per_chunk, win_lo, win_hi;
     int accumulate;         // add to the partial sums instead of overwriting
-    double gamma;           // S4: (m-1)/(m(m+1))
+    // S4 numerator v = c4a M4 - c4b (p_k p_l + |Q|^2 + |R|^2) with integer
+    // coefficients: (m(m+1), m-1) for the k-statistic, (m, 1) for the natural
+    // estimator; gamma = c4b / c4a for the kernels that form M4 - gamma (...)
+    int c4a, c4b;
+    double gamma;
     int s3_fb;              // S3 frames per LDS batch (kFrameBatchSmall or kFrameBatch); 0: chosen by m
 };
 hipError_t launch_s2(const BatchArgs& a, hipStream_t s);

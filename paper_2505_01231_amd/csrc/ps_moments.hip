@@ -326,7 +326,8 @@ __global__ __launch_bounds__(kS3Threads, 2) void k_s3(BatchArgs p) {
 // ------------------------------------------------------------------ S4, one channel
 // Plain FP32 vector arithmetic for the frame sums; FP64 for the combination
 // and the chunk sums.  Partials hold (sum v, sum v^2) with
-// v = M4 - gamma (p_k p_l + 2(X^2+Y^2+U^2+V^2)), gamma = (m-1)/(m(m+1)).
+// v = M4 - gamma (p_k p_l + 2(X^2+Y^2+U^2+V^2)), gamma = (m-1)/(m(m+1)) for the
+// k-statistic (1/m for the natural estimator).
 constexpr int kS4Threads = 256;
 
 __global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(BatchArgs p) {
@@ -579,8 +580,8 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
         row[3 * kMfmaFrames] = 0u;
         row[3 * kMfmaFrames + 1] = 0u;
     }
-    const float cm1 = (float)(v.m * (v.m + 1));         // m(m+1), exact
-    const float cm2 = (float)(v.m - 1);                 // m-1
+    const float cm1 = (float)p.c4a;                     // m(m+1) (natural: m), exact
+    const float cm2 = (float)p.c4b;                     // m-1 (natural: 1)
     const float m2c = -2.0f * cm2;
 
     Item it;
@@ -1110,8 +1111,8 @@ __global__ __launch_bounds__(kS4XMThreads, 2) void k_s4_cross_mfma(BatchArgs p) 
         row[3 * kMfmaFrames] = 0u;
         row[3 * kMfmaFrames + 1] = 0u;
     }
-    const float cm1 = (float)(v.m * (v.m + 1));         // m(m+1), exact
-    const float cm2 = (float)(v.m - 1);                 // m-1
+    const float cm1 = (float)p.c4a;                     // m(m+1) (natural: m), exact
+    const float cm2 = (float)p.c4b;                     // m-1 (natural: 1)
 
     Item it;
     while (next_item<kTileX, 4>(p, bk, it)) {

@@ -68,12 +68,15 @@ class Spectra:
 class Plan:
     """A configured estimator (ps_plan_t).  ``interlaced=True`` averages the
     spectra of the frames starting at sample 0 and of the frames starting half a
-    frame later (Section 3's interlaced windows; batched schedule only)."""
+    frame later (Section 3's interlaced windows; batched schedule only).
+    ``estimator="natural"`` selects the biased plug-in estimator of Section 6
+    instead of the k-statistics (for comparisons)."""
 
     def __init__(self, frame_len: int, n_freq: int = 0, m: int = 10, dt: float = 1.0,
                  orders=(2, 3, 4), n_channels: int = 1, window: str = "acg",
                  window_param: float = 0.14, precision: str = "fp32", schedule: str = "batched",
-                 f_max: float = 0.0, combos2=None, combos3=None, combos4=None, interlaced: bool = False):
+                 f_max: float = 0.0, combos2=None, combos3=None, combos4=None, interlaced: bool = False,
+                 estimator: str = "kstat"):
         self._lib = L.load()
         self._handle = None
         cfg = L.ps_config()
@@ -90,6 +93,7 @@ class Plan:
         cfg.precision = _PRECISION[precision]
         cfg.schedule = _SCHEDULE[schedule]
         cfg.interlaced = 1 if interlaced else 0
+        cfg.estimator = {"kstat": L.PS_EST_KSTAT, "natural": L.PS_EST_NATURAL}[estimator]
         self._keep = []
         for arity, combos in ((2, combos2), (3, combos3), (4, combos4)):
             n, arr, ptr = _flat(combos, arity)

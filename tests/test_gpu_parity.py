@@ -734,6 +734,35 @@ def test_s1_alone_constant_interlaced_and_sequential(dev):
         assert rel_err(g, ref["chunks1"].real) <= TOL
 
 
+# ---------------------------------------------------------------- natural (plug-in) estimator (Section 6)
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_natural_estimator_matches_oracle(dev, precision):
+    """estimator="natural": the plug-in cumulant estimates (biased at small m)
+    equal the oracle's natural estimator and differ from the k-statistics."""
+    say("natural estimator", precision)
+    N, Nf, m = 256, 50, 5
+    z = synth.ar2_chi2(N * m * 12 + 70, seed=121, dtype=np.float32)
+    gpu = run_gpu(z, dev, frame_len=N, n_freq=Nf, m=m, precision=precision, estimator="natural")
+    ref = O.polyspectra(z, N, Nf, m, estimator="natural")
+    compare(gpu, ref, label=f"natural-{precision}")
+    kst = O.polyspectra(z, N, Nf, m)
+    assert rel_err(gpu["s4"], kst["s4"]) > 0.05      # m = 5: the two estimators differ
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_natural_estimator_cross_channels(dev, precision):
+    """The natural estimator for every combination orbit of two channels (the
+    cross-channel S4 kernels on the vector ALUs and on the matrix cores)."""
+    say("natural estimator, 2 channels", precision)
+    N, Nf, m = 256, 32, 6
+    s = synth.ar2_chi2(N * m * 8 + 9, seed=122, r=0.9, dtype=np.float64)
+    z = np.stack([s[:-3], s[3:] ** 2 - 1.0])
+    gpu = run_gpu(z, dev, frame_len=N, n_freq=Nf, m=m, n_channels=2, precision=precision, estimator="natural")
+    ref = O.polyspectra(z, N, Nf, m, estimator="natural", combos2=gpu["plan"]["combos2"],
+                        combos3=gpu["plan"]["combos3"], combos4=gpu["plan"]["combos4"])
+    compare(gpu, ref, label=f"natural-2ch-{precision}")
+
+
 # ---------------------------------------------------------------- launch configuration (autotuner)
 def _tuning_case(dev):
     """Two channels (every S3/S4 orbit, so all four tile tables are used), a
