@@ -203,6 +203,9 @@ def main(argv=None):
     ap.add_argument("--interlaced-steps", type=int, default=2,
                     help="timed steps of the interlaced form (second frame set shifted by N/2, "
                          "spectra averaged) on the same record")
+    ap.add_argument("--sequential-steps", type=int, default=1,
+                    help="timed steps of sequential spectra (every chunk's estimate kept) over the first "
+                         "2^22 samples at N = 1024, N_f = 256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batching", action="store_true",
                     help="also time the batching form: 24 four-channel int16 records of uneven length "
@@ -338,6 +341,29 @@ def main(argv=None):
             del wsi, oi
         log(f"interlaced {interlaced['samples_per_s']:.3e} samples/s")
 
+    # Sequential spectra: each chunk's short-time estimate written out (FP64
+    # S2, S3, S4 and error-bar arrays per chunk), on a prefix of the record.
+    sequential = None
+    if args.sequential_steps > 0:
+        n_seq, n_s, nf_s = 1 << 22, 1024, 256
+        xs_ = x[:n_seq]
+        with Plan(frame_len=n_s, n_freq=nf_s, m=M, window="acg", precision=args.precision) as ps_:
+            out_ = ps_.sequential(xs_)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.sequential_steps):
+                out_ = ps_.sequential(xs_, workspace=ps_._last_workspace)
+            torch.cuda.synchronize()
+            dt_s = time.perf_counter() - t0
+            sequential = {"chunks_per_s": out_.n_chunks * args.sequential_steps / dt_s,
+                          "samples_per_s": n_seq * args.sequential_steps / dt_s,
+                          "ms_per_step": dt_s / args.sequential_steps * 1e3, "chunks": out_.n_chunks,
+                          "frame_len": n_s, "n_freq": nf_s,
+                          "output_bytes_per_step": sum(t.numel() * 8 for t in (out_.s2, out_.s2_err, out_.s3,
+                                                                                out_.s3_err, out_.s4, out_.s4_err))}
+            del out_
+        log(f"sequential {sequential['chunks_per_s']:.3e} chunks/s")
+
     batching = run_batching(torch, dev, args.precision) if args.batching else None
     streaming = run_streaming(torch, dev, args.precision) if args.streaming else None
 
@@ -378,6 +404,7 @@ def main(argv=None):
                   "speedup_vs_per_chunk_fp32": (value / plain) if plain else None},
         "s4_matrix_cores": s4_info,
         "interlaced": interlaced,
+        "sequential": sequential,
         "batching": batching,
         "streaming": streaming,
         "stage_ms_per_step": stage_ms,

@@ -198,17 +198,19 @@ ps_status ps_execute(ps_plan_t plan, const ps_record* recs, int32_t n_rec, void*
 
 /* Sequential spectra (the short-time estimates of Section 8, kept instead of
  * averaged): the spectra of chunks [chunk_lo, chunk_lo + n_chunks) of one
- * record, each chunk on its own.  outs[i] receives chunk chunk_lo + i in the
- * layouts of ps_output; its error bars are NaN (one chunk has no spread).  All
- * chunks run in the same launches as ps_execute's records (each chunk is one
- * record of m N samples; interlaced windows leave a one-chunk record as it is).
+ * record, each chunk on its own.  `out` holds, for each requested order, an
+ * array of n_chunks consecutive blocks in the layout of ps_output (chunk
+ * chunk_lo + i in block i, e.g. S3 as [n_chunks][n_combos3][N_f][N_f] complex);
+ * error bars are NaN (one chunk has no spread).  All chunks run in the same
+ * launches as ps_execute's records (each chunk is one record of m N samples;
+ * interlaced windows leave a one-chunk record as it is).
  * Errors: PS_E_INVALID_ARG if the range is not inside [0, Np) of the record or
  * n_chunks > 2^31 - 1; otherwise as ps_workspace_size / ps_execute.  n_chunks
  * == 0 enqueues nothing. */
 ps_status ps_sequential_workspace_size(ps_plan_t plan, const ps_record* rec, int64_t chunk_lo,
                                        int64_t n_chunks, size_t* bytes);
 ps_status ps_execute_sequential(ps_plan_t plan, const ps_record* rec, int64_t chunk_lo, int64_t n_chunks,
-                                void* d_ws, size_t ws_bytes, const ps_output* outs, ps_stream_t stream);
+                                void* d_ws, size_t ws_bytes, const ps_output* out, ps_stream_t stream);
 
 /* Graph form of ps_execute for repeated runs over the same buffers: the whole
  * launch sequence (one launch per stage over every record and combination) is

@@ -1131,11 +1131,21 @@ ps_status ps_sequential_workspace_size(ps_plan_t p, const ps_record* rec, int64_
 }
 
 ps_status ps_execute_sequential(ps_plan_t p, const ps_record* rec, int64_t chunk_lo, int64_t n_chunks, void* d_ws,
-                                size_t ws_bytes, const ps_output* outs, ps_stream_t stream) {
+                                size_t ws_bytes, const ps_output* out, ps_stream_t stream) {
     std::vector<ps_record> rs;
     const ps_status s = chunk_records(p, rec, chunk_lo, n_chunks, rs);
     if (s != PS_OK) return s;
-    return ps_execute(p, rs.data(), (int32_t)rs.size(), d_ws, ws_bytes, outs, stream);
+    if (n_chunks > 0 && !out) return fail(PS_E_INVALID_ARG, "out is NULL");
+    // one output block per chunk, consecutive in each array
+    const int64_t nf = p->Nf, nf2 = nf * nf;
+    const int64_t e1 = 2LL * p->C, e2 = 2 * p->n2() * nf, e3 = 2 * p->n3() * nf2, e4 = 2 * p->n4() * nf2;
+    auto at = [](double* base, int64_t i, int64_t n) { return base ? base + i * n : nullptr; };
+    std::vector<ps_output> outs((size_t)n_chunks);
+    for (int64_t i = 0; i < n_chunks; ++i)
+        outs[i] = ps_output{at(out->d_s2, i, e2), at(out->d_s2_err, i, e2), at(out->d_s3, i, e3),
+                            at(out->d_s3_err, i, e3), at(out->d_s4, i, e4), at(out->d_s4_err, i, e4),
+                            at(out->d_s1, i, e1), at(out->d_s1_err, i, e1)};
+    return ps_execute(p, rs.data(), (int32_t)rs.size(), d_ws, ws_bytes, outs.data(), stream);
 }
 
 // ------------------------------------------------------------------ graphs

@@ -237,16 +237,14 @@ class Plan:
         for key, n in (("s1", n1), ("s2", n2), ("s3", n3), ("s4", n4)):
             for suffix in ("", "_err"):
                 t[key + suffix] = torch.empty((n_chunks,) + shape[key], **f64) if n else None
-        outs = (L.ps_output * max(1, n_chunks))()
-        for i in range(n_chunks):
-            outs[i] = L.ps_output(*[None if t[k] is None else t[k][i].data_ptr()
-                                    for k in ("s2", "s2_err", "s3", "s3_err", "s4", "s4_err", "s1", "s1_err")])
+        res = Spectra(n_chunks=n_chunks, flags=0, **t)
+        out = res.c_struct()
         st = torch.cuda.current_stream(device) if stream is None else stream
         L.check(self._lib.ps_execute_sequential(self._handle, C.byref(rec), chunk_lo, n_chunks, workspace.data_ptr(),
-                                                workspace.numel(), outs, C.c_void_p(st.cuda_stream)),
+                                                workspace.numel(), C.byref(out), C.c_void_p(st.cuda_stream)),
                 "ps_execute_sequential")
         self._last_workspace = workspace
-        return Spectra(n_chunks=n_chunks, flags=0, **t)
+        return res
 
     def graph(self, xs, workspace: torch.Tensor | None = None, outputs=None) -> "Graph":
         """Capture the execution over these tensors/buffers as a HIP graph
