@@ -212,6 +212,25 @@ ps_status ps_sequential_workspace_size(ps_plan_t plan, const ps_record* rec, int
 ps_status ps_execute_sequential(ps_plan_t plan, const ps_record* rec, int64_t chunk_lo, int64_t n_chunks,
                                 void* d_ws, size_t ws_bytes, const ps_output* out, ps_stream_t stream);
 
+/* Full frequency plane (Section 9): the spectrum of one channel combination
+ * on the signed grid k, l in (-N_f, N_f), gathered from a record's
+ * positive-quadrant outputs.  For real signals a_{-k} = a_k*, so each signed
+ * point is a positive-quadrant value of a related combination, possibly
+ * conjugated or transposed (S2_ab(-k) = S2_ab(k)*; S3_abc takes values of
+ * S3_abc, S3_acb and S3_bca; S4_abcd(-k, l) = S4_bacd(k, l),
+ * S4_abcd(k, -l) = S4_abdc(k, l), S4_abcd(-k, -l) = S4_badc(k, l)); the plan
+ * must hold those combinations' orbits (it does with the default "every
+ * orbit").  order: 2, 3 or 4.  combo: host, `order` channel indices.  in: the
+ * record's ps_output as filled by ps_execute (device arrays).  d_out, d_err
+ * (device, either may be NULL): S2 [2 N_f - 1], S3 / S4 [2 N_f - 1][2 N_f - 1]
+ * complex FP64 (and sigma pairs) at index k + N_f - 1 (, l + N_f - 1).
+ * Enqueued on `stream`, after the execute that wrote `in` when on the same
+ * stream.  Errors: PS_E_INVALID_ARG for a bad order, channel or pointer, or an
+ * order the plan did not compute; PS_E_UNSUPPORTED when a needed combination
+ * is not among the plan's. */
+ps_status ps_full_plane(ps_plan_t plan, int32_t order, const int8_t* combo, const ps_output* in, double* d_out,
+                        double* d_err, ps_stream_t stream);
+
 /* Graph form of ps_execute for repeated runs over the same buffers: the whole
  * launch sequence (one launch per stage over every record and combination) is
  * captured once into a HIP graph, with its work tables built and copied

@@ -27,7 +27,7 @@ EXPORTED = (
     "ps_graph_launch", "ps_graph_destroy", "ps_streamer_create", "ps_streamer_push",
     "ps_streamer_wait", "ps_streamer_destroy", "ps_streamer_create_multi", "ps_streamer_push_multi",
     "ps_plan_get_tuning", "ps_plan_set_tuning", "ps_plan_autotune",
-    "ps_sequential_workspace_size", "ps_execute_sequential",
+    "ps_sequential_workspace_size", "ps_execute_sequential", "ps_full_plane",
 )
 PS_TUNE_MAX = 16
 
@@ -109,6 +109,7 @@ def load() -> C.CDLL:
     lib.ps_coefficients.argtypes = [vp, C.POINTER(ps_record), vp, vp]
     lib.ps_sequential_workspace_size.argtypes = [vp, C.POINTER(ps_record), i64, i64, C.POINTER(sz)]
     lib.ps_execute_sequential.argtypes = [vp, C.POINTER(ps_record), i64, i64, vp, sz, C.POINTER(ps_output), vp]
+    lib.ps_full_plane.argtypes = [vp, i32, C.POINTER(C.c_int8), C.POINTER(ps_output), vp, vp, vp]
     lib.ps_enumerate_combos.argtypes = [i32, i32, C.POINTER(C.c_int8), C.POINTER(i32)]
     lib.ps_profile_enable.argtypes = [vp, i32]
     lib.ps_profile_read.argtypes = [vp, C.POINTER(C.c_double), i32]

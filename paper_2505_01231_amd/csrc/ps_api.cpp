@@ -1100,6 +1100,40 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
 
 namespace {
 
+// The stored combination serving raw combination `x` of `order` (orbit
+// symmetries of Section 9): S2_ba = conj S2_ab; S3_bac(k, l) = S3_abc(l, k);
+// S4_badc = conj S4_abcd, S4_cdab(k, l) = S4_abcd(l, k).  Returns false if
+// no member of x's orbit is among the plan's combinations.
+bool plane_source(const ps_plan_s* p, int order, const int8_t* x, ps::PlaneSrc& out) {
+    const std::vector<int8_t>& list = order == 2 ? p->c2 : (order == 3 ? p->c3 : p->c4);
+    const int n = (int)list.size() / order;
+    struct Alt {
+        int8_t c[4];
+        int transpose, conj;
+    };
+    Alt alts[4];
+    int n_alts = 0;
+    if (order == 2) {
+        alts[n_alts++] = Alt{{x[0], x[1], 0, 0}, 0, 0};
+        alts[n_alts++] = Alt{{x[1], x[0], 0, 0}, 0, 1};
+    } else if (order == 3) {
+        alts[n_alts++] = Alt{{x[0], x[1], x[2], 0}, 0, 0};
+        alts[n_alts++] = Alt{{x[1], x[0], x[2], 0}, 1, 0};
+    } else {
+        alts[n_alts++] = Alt{{x[0], x[1], x[2], x[3]}, 0, 0};
+        alts[n_alts++] = Alt{{x[1], x[0], x[3], x[2]}, 0, 1};
+        alts[n_alts++] = Alt{{x[2], x[3], x[0], x[1]}, 1, 0};
+        alts[n_alts++] = Alt{{x[3], x[2], x[1], x[0]}, 1, 1};
+    }
+    for (int j = 0; j < n_alts; ++j)
+        for (int i = 0; i < n; ++i)
+            if (std::equal(alts[j].c, alts[j].c + order, list.begin() + (size_t)i * order)) {
+                out = ps::PlaneSrc{i, alts[j].transpose, alts[j].conj};
+                return true;
+            }
+    return false;
+}
+
 // One record of m N samples per chunk [chunk_lo, chunk_lo + n) of `rec`.
 ps_status chunk_records(ps_plan_t p, const ps_record* rec, int64_t chunk_lo, int64_t n, std::vector<ps_record>& out) {
     if (!p || !rec) return fail(PS_E_INVALID_ARG, "NULL argument");
@@ -1146,6 +1180,40 @@ ps_status ps_execute_sequential(ps_plan_t p, const ps_record* rec, int64_t chunk
                             at(out->d_s3_err, i, e3), at(out->d_s4, i, e4), at(out->d_s4_err, i, e4),
                             at(out->d_s1, i, e1), at(out->d_s1_err, i, e1)};
     return ps_execute(p, rs.data(), (int32_t)rs.size(), d_ws, ws_bytes, outs.data(), stream);
+}
+
+ps_status ps_full_plane(ps_plan_t p, int32_t order, const int8_t* combo, const ps_output* in, double* d_out,
+                        double* d_err, ps_stream_t stream) {
+    if (!p || !combo || !in) return fail(PS_E_INVALID_ARG, "NULL argument");
+    if (order < 2 || order > 4 || !p->has(order)) return fail(PS_E_INVALID_ARG, "order %d not computed", order);
+    for (int i = 0; i < order; ++i)
+        if (combo[i] < 0 || combo[i] >= p->C) return fail(PS_E_INVALID_ARG, "channel %d outside 0..%d", combo[i], p->C - 1);
+    const double* src = order == 2 ? in->d_s2 : (order == 3 ? in->d_s3 : in->d_s4);
+    const double* src_err = order == 2 ? in->d_s2_err : (order == 3 ? in->d_s3_err : in->d_s4_err);
+    if ((d_out && !src) || (d_err && !src_err)) return fail(PS_E_INVALID_ARG, "input spectrum is NULL");
+    const int8_t a = combo[0], b = combo[1];
+    std::vector<std::vector<int8_t>> raw;
+    if (order == 2) {
+        raw = {{a, b}};
+    } else if (order == 3) {
+        const int8_t c = combo[2];
+        raw = {{a, b, c}, {a, c, b}, {b, c, a}};
+    } else {
+        const int8_t c = combo[2], d = combo[3];
+        raw = {{a, b, c, d}, {b, a, c, d}, {a, b, d, c}, {b, a, d, c}};
+    }
+    ps::PlaneArgs pa{};
+    pa.order = order;
+    pa.Nf = p->Nf;
+    pa.in = src;
+    pa.in_err = src_err;
+    pa.out = d_out;
+    pa.err = d_err;
+    for (size_t i = 0; i < raw.size(); ++i)
+        if (!plane_source(p, order, raw[i].data(), pa.src[i]))
+            return fail(PS_E_UNSUPPORTED, "the plan does not hold the orbit of a combination needed for the full plane");
+    PS_HIP(ps::launch_full_plane(pa, (hipStream_t)stream));
+    return PS_OK;
 }
 
 // ------------------------------------------------------------------ graphs

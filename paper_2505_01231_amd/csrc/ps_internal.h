@@ -202,6 +202,27 @@ hipError_t launch_finalize_s1(const FinalizeArgs& a, hipStream_t s);
 
 hipError_t launch_fill_nan(double* p, int64_t n, hipStream_t s);
 
+// ---------------------------------------------------------------- full plane
+// One combination's spectrum on the signed grid (-N_f, N_f) gathered from the
+// positive-quadrant outputs (see k_full_plane for the regions).  src[i] names
+// the stored combination that serves raw combination i of the order's list
+// (S2: ab; S3: abc, acb, bca; S4: abcd, bacd, abdc, badc) and how: conjugated
+// and/or transposed.
+struct PlaneSrc {
+    int32_t idx;            // stored combination
+    int32_t transpose;      // read (q, p) instead of (p, q)
+    int32_t conj;
+};
+struct PlaneArgs {
+    int order, Nf;
+    const double* in;       // [stored combos][N_f] or [..][N_f][N_f] complex
+    const double* in_err;   // same layout (sigma_re, sigma_im), or NULL
+    PlaneSrc src[4];
+    double* out;            // [2 N_f - 1] or [2 N_f - 1][2 N_f - 1] complex, or NULL
+    double* err;
+};
+hipError_t launch_full_plane(const PlaneArgs& a, hipStream_t s);
+
 // The partial-sum slots of tile t: n consecutive slots from s0 (see Sched).
 __device__ __forceinline__ void slot_range(const Sched& sc, int64_t t, int64_t& s0, int64_t& n) {
     const int64_t T1 = sc.T1();

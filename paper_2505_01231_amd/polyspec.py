@@ -246,6 +246,25 @@ class Plan:
         self._last_workspace = workspace
         return res
 
+    def full_plane(self, spectra: Spectra, order: int, combo, stream=None):
+        """The spectrum of one channel combination on the signed grid (-N_f, N_f)
+        (ps_full_plane), gathered from a record's outputs.  Returns (values,
+        errors): [2 N_f - 1, 2] for S2, [2 N_f - 1, 2 N_f - 1, 2] for S3 / S4,
+        index k + N_f - 1."""
+        ref = getattr(spectra, f"s{order}")
+        if ref is None:
+            raise ValueError(f"order {order} was not computed")
+        e = 2 * self.n_freq - 1
+        shape = (e, 2) if order == 2 else (e, e, 2)
+        val = torch.empty(shape, dtype=torch.float64, device=ref.device)
+        err = torch.empty_like(val)
+        cb = (C.c_int8 * order)(*combo)
+        out = spectra.c_struct()
+        st = torch.cuda.current_stream(ref.device) if stream is None else stream
+        L.check(self._lib.ps_full_plane(self._handle, order, cb, C.byref(out), val.data_ptr(), err.data_ptr(),
+                                        C.c_void_p(st.cuda_stream)), "ps_full_plane")
+        return val, err
+
     def graph(self, xs, workspace: torch.Tensor | None = None, outputs=None) -> "Graph":
         """Capture the execution over these tensors/buffers as a HIP graph
         (ps_graph_create); replay with Graph.launch()."""

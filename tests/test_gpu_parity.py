@@ -763,6 +763,51 @@ def test_natural_estimator_cross_channels(dev, precision):
     compare(gpu, ref, label=f"natural-2ch-{precision}")
 
 
+# ---------------------------------------------------------------- full frequency plane (Section 9)
+def test_full_plane_matches_direct_evaluation(dev):
+    """ps_full_plane gathers one combination's S2 / S3 / S4 on the signed grid
+    (-N_f, N_f) from the positive quadrants of every orbit; the oracle evaluates
+    the same points directly (a_{-k} = a_{N-k}), with no symmetry used."""
+    import ctypes
+    from paper_2505_01231_amd import Plan
+    from paper_2505_01231_amd import _lib as L
+    say("full plane, 3 channels")
+    N, Nf, m = 256, 12, 8
+    rng = np.random.default_rng(131)
+    s = synth.ar2_chi2(N * m * 12 + 9, seed=131, r=0.8, dtype=np.float64)
+    z = np.stack([s[:-6], s[3:-3] ** 2 - 1 + 0.3 * rng.standard_normal(len(s) - 6), s[6:] * s[:-6]])
+    pts = [(k, l) for k in range(-Nf + 1, Nf) for l in range(-Nf + 1, Nf)]
+    with Plan(frame_len=N, n_freq=Nf, m=m, n_channels=3, precision="bf16x3") as p:
+        out = p.execute(torch.from_numpy(z).to(dev))
+        for order, combo in ((2, (1, 0)), (3, (0, 1, 2)), (3, (2, 0, 1)), (3, (1, 1, 0)),
+                             (4, (0, 1, 2, 0)), (4, (2, 1, 0, 1)), (4, (1, 1, 2, 2))):
+            val, err = p.full_plane(out, order, combo)
+            torch.cuda.synchronize()
+            g = torch.view_as_complex(val).cpu().numpy()
+            ge = err.cpu().numpy()
+            if order == 2:
+                ref = O.polyspectra_at(z, N, m, points2=list(range(-Nf + 1, Nf)), combo2=combo)
+                rv, re_ = ref["s2"], ref["s2_err"]
+            else:
+                ref = O.polyspectra_at(z, N, m, **{f"points{order}": pts, f"combo{order}": combo})
+                rv = ref[f"s{order}"].reshape(2 * Nf - 1, 2 * Nf - 1)
+                re_ = ref[f"s{order}_err"].reshape(2 * Nf - 1, 2 * Nf - 1, 2)
+            e, ee = rel_err(g, rv), rel_err(ge, re_)
+            say("  order", order, combo, f"{e:.2e}/{ee:.2e}")
+            assert e <= TOL and ee <= TOL, (order, combo, e, ee)
+        # the positive quadrant is the execute's own output
+        val, _ = p.full_plane(out, 3, (0, 1, 2))
+        i = p.combos3.index((0, 1, 2))
+        assert torch.equal(val[Nf - 1:, Nf - 1:], out.s3[i])
+    # a plan without the needed orbits cannot build the plane
+    with Plan(frame_len=N, n_freq=Nf, m=m, n_channels=3, combos3=[(0, 1, 2)], orders=(3,)) as p:
+        out = p.execute(torch.from_numpy(z).to(dev))
+        cb = (ctypes.c_int8 * 3)(0, 1, 2)
+        st = p._lib.ps_full_plane(p._handle, 3, cb, ctypes.byref(out.c_struct()), None, None, None)
+        assert st == L.PS_E_UNSUPPORTED
+        torch.cuda.synchronize()
+
+
 # ---------------------------------------------------------------- launch configuration (autotuner)
 def _tuning_case(dev):
     """Two channels (every S3/S4 orbit, so all four tile tables are used), a
