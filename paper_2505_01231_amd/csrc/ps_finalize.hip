@@ -70,10 +70,11 @@ __global__ __launch_bounds__(256) void k_finalize_vec(FinalizeArgs p) {
             for (int c = 0; c < 4; ++c) s[4 * set + c] += q[c * 256];
         }
     }
-    for (int c = 0; c < 8; ++c) red[g][c][kk] = s[c];
+    const int nc = two ? 8 : 4;                         // uniform over the block
+    for (int c = 0; c < nc; ++c) red[g][c][kk] = s[c];
     __syncthreads();
     if (g != 0 || k >= p.Nf) return;
-    for (int c = 0; c < 8; ++c) {
+    for (int c = 0; c < nc; ++c) {
         s[c] = 0;
         for (int gg = 0; gg < kVecGroups; ++gg) s[c] += red[gg][c][kk];
     }
