@@ -90,11 +90,12 @@ def chunk_count(n_samples: int, N: int, m: int) -> int:
 
 
 def chunk_frames(z: np.ndarray, N: int, m: int) -> np.ndarray:
-    """Contiguous frames grouped into chunks: [..., Np, m, N] float64."""
+    """Contiguous frames grouped into chunks: [..., Np, m, N] float64 (complex128
+    for a complex signal)."""
     z = np.asarray(z)
     L = z.shape[-1]
     Np = chunk_count(L, N, m)
-    x = z[..., : Np * m * N].astype(np.float64)
+    x = z[..., : Np * m * N].astype(np.complex128 if np.iscomplexobj(z) else np.float64)
     return x.reshape(z.shape[:-1] + (Np, m, N))
 
 
@@ -359,6 +360,68 @@ def polyspectra(z, N: int, Nf: int, m: int, dt: float = 1.0, window_kind: str = 
         out["chunks2"], out["chunks3"], out["chunks4"] = per2, per3, per4
         if 1 in orders:
             out["chunks1"] = per1
+    return out
+
+
+def polyspectra_complex(z, N: int, Nf: int, m: int, dt: float = 1.0, window_kind: str = "acg",
+                        window_param: float = 0.14, orders=(2, 3, 4), combos2=None, combos3=None,
+                        combos4=None, estimator: str = "kstat", return_chunks: bool = False):
+    """Spectra of a complex-valued record on the signed grid k, l in
+    (-N_f, N_f): without a_{-k} = conj(a_k) the negative frequencies carry their
+    own information, so the same definitions (Sections 3, 4 and 7) are
+    evaluated at every signed index.  Coefficients are eq. a_k at signed bins
+    (numpy's inverse FFT, index taken mod N).  Returns the keys of polyspectra
+    with grids of 2 N_f - 1 points per axis, index k + N_f - 1; 's1' (order 1)
+    is complex.
+    """
+    z = np.asarray(z)
+    if z.ndim == 1:
+        z = z[None, :]
+    C = z.shape[0]
+    combos2 = [(0, 0)] if combos2 is None else [tuple(c) for c in combos2]
+    combos3 = [(0, 0, 0)] if combos3 is None else [tuple(c) for c in combos3]
+    combos4 = [(0, 0, 0, 0)] if combos4 is None else [tuple(c) for c in combos4]
+    combos2 = combos2 if 2 in orders else []
+    combos3 = combos3 if 3 in orders else []
+    combos4 = combos4 if 4 in orders else []
+    e2, e3, e4 = ESTIMATORS[estimator]
+    g = window(window_kind, N, window_param)
+    jmax = 2 * (Nf - 1) if combos3 else Nf - 1
+    bins = np.arange(-jmax, jmax + 1)               # coefficient column c holds bin c - jmax
+    frames = chunk_frames(z.astype(np.complex128), N, m)     # [C, Np, m, N]
+    Np = frames.shape[1]
+    E = 2 * Nf - 1
+    ks = np.arange(E) - (Nf - 1)                    # signed grid
+    per1 = np.empty((Np, C), dtype=np.complex128)
+    per2 = np.empty((Np, len(combos2), E), dtype=np.complex128)
+    per3 = np.empty((Np, len(combos3), E, E), dtype=np.complex128)
+    per4 = np.empty((Np, len(combos4), E, E), dtype=np.complex128)
+    col = ks + jmax                                 # column of bin k
+    for p in range(Np):
+        full = N * dt * np.fft.ifft(frames[:, p] * g, axis=-1)   # [C, m, N]
+        A = np.swapaxes(full[..., bins % N], -1, -2)             # [C, columns, m]
+        per1[p] = A[:, jmax, :].mean(axis=-1) / _norm(g, dt, 1)
+        for i, (a, b) in enumerate(combos2):
+            per2[p, i] = e2(A[a, col], np.conj(A[b, col])) / _norm(g, dt, 2)
+        for i, (a, b, c) in enumerate(combos3):
+            x = A[a, col][:, None, :]
+            y = A[b, col][None, :, :]
+            w = np.conj(A[c][col[:, None] + ks[None, :]])         # bin k + l
+            per3[p, i] = e3(x, y, w) / _norm(g, dt, 3)
+        for i, (a, b, c, d) in enumerate(combos4):
+            x = A[a, col][:, None, :]
+            y = np.conj(A[b, col])[:, None, :]
+            u = A[c, col][None, :, :]
+            w = np.conj(A[d, col])[None, :, :]
+            per4[p, i] = e4(x, y, u, w) / _norm(g, dt, 4)
+    out = {"n_chunks": Np, "combos2": combos2, "combos3": combos3, "combos4": combos4}
+    if 1 in orders:
+        out["s1"], out["s1_err"] = average_with_error(per1)
+    out["s2"], out["s2_err"] = average_with_error(per2)
+    out["s3"], out["s3_err"] = average_with_error(per3)
+    out["s4"], out["s4_err"] = average_with_error(per4)
+    if return_chunks:
+        out["chunks1"], out["chunks2"], out["chunks3"], out["chunks4"] = per1, per2, per3, per4
     return out
 
 

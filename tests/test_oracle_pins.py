@@ -621,3 +621,52 @@ def test_s1_of_white_noise_is_its_mean():
     out = O.polyspectra(z, N, Nf, m, orders=(1,))
     s1, e = out["s1"][0].real, out["s1_err"][0][0]
     assert abs(s1 - 0.7) < 4 * e and 0 < e < 0.01
+
+
+# --------------------------------------------------------------------------
+# Complex-valued signals: spectra on the signed grid
+# --------------------------------------------------------------------------
+
+
+def test_complex_path_on_a_real_signal_is_the_full_plane():
+    """A real record given as complex: the signed-grid spectra equal the
+    point evaluator's values at negative frequencies (which uses no grid)."""
+    N, Nf, m = 32, 5, 6
+    z = synth.ar2_chi2(N * m * 12, seed=141, r=0.8, dtype=np.float64)
+    out = O.polyspectra_complex(z.astype(np.complex128), N, Nf, m, orders=(1, 2, 3, 4))
+    ks = list(range(-Nf + 1, Nf))
+    pts = [(k, l) for k in ks for l in ks]
+    ref = O.polyspectra_at(z, N, m, points2=ks, points3=pts, points4=pts)
+    for key in ("s2", "s3", "s4"):
+        got = out[key][0].ravel()
+        assert np.allclose(got, ref[key], rtol=0, atol=1e-12 * np.abs(ref[key]).max()), key
+    assert np.allclose(out["s1"][0], O.polyspectra(z, N, Nf, m, orders=(1,))["s1"][0], atol=1e-12)
+
+
+def test_complex_frequency_shift():
+    """z = x exp(+2 pi j q n / N) shifts every coefficient, a_k(z) = a_{k+q}(x),
+    so S2_z(k) = S2_x(k + q) and S4_z(k, l) = S4_x(k + q, l + q) exactly."""
+    N, Nf, m, q = 32, 5, 6, 3
+    x = synth.ar2_chi2(N * m * 10, seed=142, r=0.8, dtype=np.float64)
+    z = x * np.exp(2j * np.pi * q * np.arange(len(x)) / N)
+    out = O.polyspectra_complex(z, N, Nf, m, orders=(2, 4))
+    ks = list(range(-Nf + 1, Nf))
+    pts = [(k + q, l + q) for k in ks for l in ks]
+    ref = O.polyspectra_at(x, N, m, points2=[k + q for k in ks], points4=pts)
+    assert np.allclose(out["s2"][0], ref["s2"], rtol=0, atol=1e-12 * np.abs(ref["s2"]).max())
+    assert np.allclose(out["s4"][0].ravel(), ref["s4"], rtol=0, atol=1e-12 * np.abs(ref["s4"]).max())
+
+
+def test_complex_white_noise():
+    """Circular complex Gaussian white noise, E|z|^2 = 2: S2 = 2 dt at every
+    signed frequency (not symmetric by construction, flat by statistics);
+    S3 and S4 consistent with zero."""
+    N, Nf, m, dt = 32, 6, 8, 0.5
+    rng = np.random.default_rng(143)
+    z = rng.standard_normal(N * m * 300) + 1j * rng.standard_normal(N * m * 300)
+    out = O.polyspectra_complex(z, N, Nf, m, dt=dt, window_kind="hann")
+    s2, e2 = out["s2"][0], out["s2_err"][0]
+    assert np.all(np.abs(s2.real - 2 * dt) < 5 * e2[:, 0])
+    for key in ("s3", "s4"):
+        t = np.abs(out[key][0].real) / out[key + "_err"][0][..., 0]
+        assert np.mean(t > 3) < 0.02, (key, np.mean(t > 3))
