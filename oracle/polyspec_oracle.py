@@ -437,17 +437,19 @@ def polyspectra_interlaced(z, N: int, Nf: int, m: int, **kw):
     of the two sets' error bars (the sets overlap, their estimates are
     positively correlated, and sd(X + Y) <= sd(X) + sd(Y) makes this never an
     underestimate).  If the shifted set has no complete chunk the first set's
-    result is returned alone.  Keyword arguments are those of polyspectra.
+    result is returned alone.  Keyword arguments are those of polyspectra
+    (of polyspectra_complex for a complex record).
     Adds 'n_chunks_shifted' to the result.
     """
     z = np.asarray(z)
-    first = polyspectra(z, N, Nf, m, **kw)
+    spectra = polyspectra_complex if np.iscomplexobj(z) else polyspectra
+    first = spectra(z, N, Nf, m, **kw)
     shifted_z = z[..., N // 2:]
     if chunk_count(shifted_z.shape[-1], N, m) == 0:
         out = dict(first)
         out["n_chunks_shifted"] = 0
         return out
-    second = polyspectra(shifted_z, N, Nf, m, **kw)
+    second = spectra(shifted_z, N, Nf, m, **kw)
     out = dict(first)
     for key in ("s1", "s2", "s3", "s4", "s1_err", "s2_err", "s3_err", "s4_err"):
         if key in first:
