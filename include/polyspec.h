@@ -58,7 +58,11 @@ typedef enum ps_status {
     PS_E_INTERNAL = 5
 } ps_status;
 
-typedef enum ps_dtype { PS_F32 = 0, PS_F64 = 1, PS_I16 = 2 } ps_dtype;
+typedef enum ps_dtype {
+    PS_F32 = 0, PS_F64 = 1, PS_I16 = 2,
+    PS_C64 = 3,   /* complex: interleaved float32 (re, im); plans with complex_signal = 1 */
+    PS_C128 = 4   /* complex: interleaved float64 */
+} ps_dtype;
 typedef enum ps_estimator { PS_EST_KSTAT = 0, PS_EST_NATURAL = 1 } ps_estimator;
 
 /* Window g_i, i = 0..N-1.  HANN: symmetric sin^2(pi i/(N-1)); HANN_PERIODIC:
@@ -112,7 +116,15 @@ typedef struct ps_config {
     const int8_t* combos4; /* host [n_combos4][4]: (a, b, c, d) -> C4(a_k, b*_k, c_l, d*_l) */
     int32_t interlaced;    /* 0 or 1: interlaced windows (see below); PS_SCHED_BATCHED only */
     int32_t estimator;     /* ps_estimator */
+    int32_t complex_signal; /* 0: real records; 1: complex records (PS_C64 / PS_C128), see below */
+    int32_t reserved;      /* must be 0 */
 } ps_config;
+/* Complex-valued signals (complex_signal = 1; frame_len up to 4096): without
+ * a_{-k} = a_k* the negative frequencies carry their own information, so every
+ * spectrum is computed on the signed grid k, l in (-N_f, N_f): S2 has 2 N_f - 1
+ * points, S3 and S4 (2 N_f - 1)^2, index k + N_f - 1 (ps_plan_info.grid), and
+ * S1 is complex.  Same definitions (Sections 3, 4 and 7) and constraints on
+ * N_f; ps_full_plane does not apply (the grid is already the full plane). */
 /* Cumulant estimator per chunk.  PS_EST_KSTAT: the unbiased k-statistics of
  * Section 4.1.  PS_EST_NATURAL: the natural (plug-in) estimator of Section 6,
  * the cumulant's moment expression with sample means (biased by O(1/m); for
@@ -164,7 +176,7 @@ typedef struct ps_plan_info {
     int32_t n_coef;     /* coefficients kept per frame: 2 N_f - 1 with S3, else N_f */
     int32_t m;
     int32_t n_combos2, n_combos3, n_combos4;
-    int32_t reserved;
+    int32_t grid;       /* points per output axis: N_f, or 2 N_f - 1 for complex signals */
     double f_max;       /* (N_f - 1) / (N dt) */
     double sum_g[5];    /* sum_i g_i^n, n = 0..4, as used by the normalisation */
     const int8_t* combos2; /* host, owned by the plan */

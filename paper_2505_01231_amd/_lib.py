@@ -12,7 +12,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpolyspec.so")
 
 PS_OK, PS_E_INVALID_ARG, PS_E_UNSUPPORTED, PS_E_WORKSPACE, PS_E_HIP, PS_E_INTERNAL = range(6)
-PS_F32, PS_F64, PS_I16 = 0, 1, 2
+PS_F32, PS_F64, PS_I16, PS_C64, PS_C128 = 0, 1, 2, 3, 4
 PS_EST_KSTAT, PS_EST_NATURAL = 0, 1
 PS_WIN_HANN, PS_WIN_HANN_PERIODIC, PS_WIN_ACG = 0, 1, 2
 PS_PREC_FP32, PS_PREC_BF16X3, PS_PREC_FP16X2S = 0, 1, 2
@@ -41,6 +41,7 @@ class ps_config(C.Structure):
         ("n_combos2", C.c_int32), ("n_combos3", C.c_int32), ("n_combos4", C.c_int32),
         ("combos2", C.POINTER(C.c_int8)), ("combos3", C.POINTER(C.c_int8)),
         ("combos4", C.POINTER(C.c_int8)), ("interlaced", C.c_int32), ("estimator", C.c_int32),
+        ("complex_signal", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -59,7 +60,7 @@ class ps_plan_info(C.Structure):
     _fields_ = [
         ("frame_len", C.c_int32), ("n_freq", C.c_int32), ("n_coef", C.c_int32), ("m", C.c_int32),
         ("n_combos2", C.c_int32), ("n_combos3", C.c_int32), ("n_combos4", C.c_int32),
-        ("reserved", C.c_int32), ("f_max", C.c_double), ("sum_g", C.c_double * 5),
+        ("grid", C.c_int32), ("f_max", C.c_double), ("sum_g", C.c_double * 5),
         ("combos2", C.POINTER(C.c_int8)), ("combos3", C.POINTER(C.c_int8)),
         ("combos4", C.POINTER(C.c_int8)),
     ]

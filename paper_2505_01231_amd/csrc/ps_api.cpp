@@ -107,7 +107,12 @@ struct ps_plan_s {
     uint32_t orders = 0;
     int window = 0, precision = 0, schedule = 0;
     int estimator = PS_EST_KSTAT;
-    bool interlaced = false;    // second frame set shifted by N/2, spectra averaged
+    bool interlaced = false;
+    // Complex signals: output grid Ng = 2 N_f - 1 (signed bins), coefficient
+    // column c holds bin c - jmax, the first factors of grid index k' sit at
+    // column k' + col0; the transform runs at twice the frame length's log2.
+    bool cplx = false;
+    int Ng = 0, col0 = 0, jmax = 0, log2n_fft = 0;    // second frame set shifted by N/2, spectra averaged
     std::vector<int8_t> c2, c3, c4;
     double sum_g[5] = {0, 0, 0, 0, 0};
     int T = 0, TX = 0;
@@ -240,9 +245,14 @@ struct Batch {
 
 size_t align64(size_t x) { return (x + 63) & ~size_t(63); }
 
+// Bytes per sample of a record's dtype.
+size_t elem_size(int dtype) {
+    return dtype == PS_F32 ? 4 : dtype == PS_F64 ? 8 : dtype == PS_I16 ? 2 : dtype == PS_C64 ? 8 : 16;
+}
+
 void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_output* outs, Batch& B) {
     const bool per_chunk = p->schedule == PS_SCHED_PER_CHUNK;
-    const int m = p->m, K = p->K, Nf = p->Nf;
+    const int m = p->m, K = p->K, Nf = p->Ng;      // Nf: points per output axis
     const int64_t nf2 = (int64_t)Nf * Nf;
     const double dt = p->dt;
     // k-statistic prefactors (Section 4.1) or those of the natural estimator
@@ -261,7 +271,7 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
         const ps_record& rec = recs[ir / B.stride];
         // the shifted frame set of interlaced windows starts T/2 = N/2 samples later
         const int64_t skip = (ir % B.stride) ? p->N / 2 : 0;
-        const size_t esz = rec.dtype == PS_F32 ? 4 : (rec.dtype == PS_F64 ? 8 : 2);
+        const size_t esz = elem_size(rec.dtype);
         RecInfo& q = B.ri[ir];
         q.Np = (std::max<int64_t>(0, rec.n_samples - skip) / p->N) / m;
         q.F = q.Np * m;
@@ -413,7 +423,7 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
     B.off_part = off;
     off = align256(off + (size_t)B.part_doubles * sizeof(double));
     B.off_s1 = off;
-    if (p->has(1)) off = align256(off + (size_t)p->C * B.chunks_tot * sizeof(float));
+    if (p->has(1)) off = align256(off + (size_t)p->C * B.chunks_tot * sizeof(float2));
     B.total = std::max<size_t>(off, 256);
 }
 
@@ -442,13 +452,16 @@ struct StageTimer {
 
 ps_status check_record(const ps_plan_s* p, const ps_record* r) {
     if (!r) return fail(PS_E_INVALID_ARG, "record is NULL");
-    if (r->dtype < PS_F32 || r->dtype > PS_I16) return fail(PS_E_INVALID_ARG, "bad dtype %d", r->dtype);
+    if (r->dtype < PS_F32 || r->dtype > PS_C128) return fail(PS_E_INVALID_ARG, "bad dtype %d", r->dtype);
+    if ((r->dtype >= PS_C64) != p->cplx)
+        return fail(PS_E_INVALID_ARG, "dtype %d does not match the plan's %s signal", r->dtype,
+                    p->cplx ? "complex" : "real");
     if (r->n_samples < 0) return fail(PS_E_INVALID_ARG, "n_samples < 0");
     if (r->reserved != 0) return fail(PS_E_INVALID_ARG, "record.reserved must be 0");
     if (p->C > 1 && r->channel_stride < r->n_samples)
         return fail(PS_E_INVALID_ARG, "channel_stride (%lld) < n_samples (%lld)",
                     (long long)r->channel_stride, (long long)r->n_samples);
-    const size_t esz = r->dtype == PS_F32 ? 4 : (r->dtype == PS_F64 ? 8 : 2);
+    const size_t esz = elem_size(r->dtype);
     if (r->n_samples >= (int64_t)p->N * p->m) {
         if (!r->d_data) return fail(PS_E_INVALID_ARG, "record data is NULL");
         if (!aligned(r->d_data, esz)) return fail(PS_E_INVALID_ARG, "record data misaligned");
@@ -547,6 +560,10 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
         return fail(PS_E_INVALID_ARG, "unknown estimator %d", cfg->estimator);
     if (cfg->interlaced && cfg->schedule != PS_SCHED_BATCHED)
         return fail(PS_E_UNSUPPORTED, "interlaced windows need the batched schedule");
+    if (cfg->complex_signal != 0 && cfg->complex_signal != 1) return fail(PS_E_INVALID_ARG, "complex_signal must be 0 or 1");
+    if (cfg->reserved != 0) return fail(PS_E_INVALID_ARG, "reserved must be 0");
+    if (cfg->complex_signal && cfg->frame_len > 4096)
+        return fail(PS_E_UNSUPPORTED, "complex signals: frame_len up to 4096");
     int Nf = cfg->n_freq;
     if (Nf == 0) {
         if (!(cfg->f_max >= 0) || !std::isfinite(cfg->f_max))
@@ -564,7 +581,12 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     p->N = N;
     while ((1 << p->log2n) < N) ++p->log2n;
     p->Nf = Nf;
-    p->K = s3 ? 2 * Nf - 1 : Nf;
+    p->cplx = cfg->complex_signal != 0;
+    p->K = p->cplx ? (s3 ? 4 * Nf - 3 : 2 * Nf - 1) : (s3 ? 2 * Nf - 1 : Nf);
+    p->Ng = p->cplx ? 2 * Nf - 1 : Nf;
+    p->jmax = p->cplx ? (s3 ? 2 * (Nf - 1) : Nf - 1) : 0;
+    p->col0 = p->cplx ? p->jmax - (Nf - 1) : 0;
+    p->log2n_fft = p->log2n + (p->cplx ? 1 : 0);
     p->m = cfg->m;
     p->C = cfg->n_channels;
     p->dt = cfg->dt;
@@ -616,14 +638,18 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     std::vector<float> gf(N);
     for (int i = 0; i < N; ++i) gf[i] = (float)g[i];
     const double two_pi = 6.28318530717958647692;
+    // (complex signals: the tables of a real transform of twice the frame
+    // length, whose complex transform has the frame length; the first N2
+    // entries are then unused)
+    const int N2 = 1 << p->log2n_fft;
     std::vector<float2> tw;
-    tw.reserve(ps::fft_twiddle_count(p->log2n));
-    for (int t = 0; t < N; ++t) {
-        const double ang = two_pi * t / N;
+    tw.reserve(ps::fft_twiddle_count(p->log2n_fft));
+    for (int t = 0; t < N2; ++t) {
+        const double ang = two_pi * t / N2;
         tw.push_back(make_float2((float)std::cos(ang), (float)std::sin(ang)));
     }
     // per-pass tables of the transform's later passes, [r][k]
-    const int R2 = ps::fft_radix2(p->log2n), R3 = ps::fft_radix3(p->log2n);
+    const int R2 = ps::fft_radix2(p->log2n_fft), R3 = ps::fft_radix3(p->log2n_fft);
     const int pass_r[2] = {R2, R3}, pass_ns[2] = {16, 16 * R2};
     for (int q = 0; q < 2; ++q)
         for (int r = 0; r < pass_r[q]; ++r)
@@ -632,8 +658,8 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
                 tw.push_back(make_float2((float)std::cos(ang), (float)std::sin(ang)));
             }
 
-    p->T = (Nf + ps::kTile - 1) / ps::kTile;
-    p->TX = (Nf + ps::kTileX - 1) / ps::kTileX;
+    p->T = (p->Ng + ps::kTile - 1) / ps::kTile;
+    p->TX = (p->Ng + ps::kTileX - 1) / ps::kTileX;
     std::vector<int2> tiles[4];
     tile_order(p->T, p->tile_group, tiles[ps::kSym64], tiles[ps::kFull64]);
     tile_order(p->TX, p->tile_group, tiles[ps::kSym32], tiles[ps::kFull32]);
@@ -812,7 +838,7 @@ ps_status ps_plan_query(ps_plan_t p, ps_plan_info* info) {
     info->n_combos2 = p->n2();
     info->n_combos3 = p->n3();
     info->n_combos4 = p->n4();
-    info->reserved = 0;
+    info->grid = p->Ng;
     info->f_max = p->f_max;
     for (int n = 0; n < 5; ++n) info->sum_g[n] = p->sum_g[n];
     info->combos2 = p->c2.data();
@@ -856,7 +882,9 @@ ps_status ps_coefficients(ps_plan_t p, const ps_record* rec, float* d_coef, ps_s
     a.g_hi = F;
     a.out_g0 = 0;
     a.n_channels = p->C;
-    a.log2n = p->log2n;
+    a.log2n = p->log2n_fft;
+    a.cplx = p->cplx;
+    a.jmax = p->jmax;
     a.K = p->K;
     a.g = p->d_g;
     a.tw = p->d_tw;
@@ -905,7 +933,8 @@ ps::BatchArgs batch_args(const ps_plan_s* p, const Batch& B, const SegTable& t, 
     a.part = reinterpret_cast<double*>(ws + B.off_part);
     a.K = p->K;
     a.m = p->m;
-    a.Nf = p->Nf;
+    a.Nf = p->Ng;
+    a.col0 = p->col0;
     a.per_chunk = per_chunk;
     a.win_lo = win_lo;
     a.win_hi = win_hi;
@@ -925,8 +954,8 @@ ps::FinalizeArgs fin_args(const ps_plan_s* p, const Batch& B, const SegTable& t,
     f.n_items = t.n_items;
     f.tt = p->tables();
     f.part = reinterpret_cast<const double*>(ws + B.off_part);
-    f.Nf = p->Nf;
-    f.s1 = p->has(1) ? reinterpret_cast<const float*>(ws + B.off_s1) : nullptr;
+    f.Nf = p->Ng;
+    f.s1 = p->has(1) ? reinterpret_cast<const float2*>(ws + B.off_s1) : nullptr;
     f.s1_cs = B.chunks_tot;
     return f;
 }
@@ -992,7 +1021,7 @@ ps_status validate_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, vo
 // Every launch of one execution, given device tables at `tab`.
 ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_t n_rec, const ps_output* outs,
                       char* ws, const char* tab, hipStream_t st) {
-    const int Nf = p->Nf, m = p->m;
+    const int Nf = p->Ng, m = p->m;
     const int64_t nf2 = (int64_t)Nf * Nf;
     for (int r = 0; r < n_rec; ++r) {
         if (B.ri[r * B.stride].Np > 0) continue;
@@ -1014,7 +1043,9 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
 
     ps::FftArgs fa{};
     fa.n_channels = p->C;
-    fa.log2n = p->log2n;
+    fa.log2n = p->log2n_fft;
+    fa.cplx = p->cplx;
+    fa.jmax = p->jmax;
     fa.K = p->K;
     fa.g = p->d_g;
     fa.tw = p->d_tw;
@@ -1026,9 +1057,10 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
     ca.K = p->K;
     ca.m = m;
     ca.n_channels = p->C;
-    ca.s1 = p->has(1) ? reinterpret_cast<float*>(ws + B.off_s1) : nullptr;
+    ca.s1 = p->has(1) ? reinterpret_cast<float2*>(ws + B.off_s1) : nullptr;
     ca.s1_cs = B.chunks_tot;
     ca.s1_chunk0 = 0;
+    ca.s1_col = p->jmax;
     ps_status s = PS_OK;
 
     if (p->schedule != PS_SCHED_PER_CHUNK) {
@@ -1143,7 +1175,7 @@ ps_status chunk_records(ps_plan_t p, const ps_record* rec, int64_t chunk_lo, int
     if (chunk_lo < 0 || n < 0 || n > 0x7fffffff || chunk_lo > np - n)
         return fail(PS_E_INVALID_ARG, "chunks [%lld, %lld) outside the record's %lld", (long long)chunk_lo,
                     (long long)(chunk_lo + n), (long long)np);
-    const int64_t esz = rec->dtype == PS_F32 ? 4 : (rec->dtype == PS_F64 ? 8 : 2);
+    const int64_t esz = (int64_t)elem_size(rec->dtype);
     const int64_t span = (int64_t)p->m * p->N;
     out.assign((size_t)n, *rec);
     for (int64_t i = 0; i < n; ++i) {
@@ -1171,7 +1203,7 @@ ps_status ps_execute_sequential(ps_plan_t p, const ps_record* rec, int64_t chunk
     if (s != PS_OK) return s;
     if (n_chunks > 0 && !out) return fail(PS_E_INVALID_ARG, "out is NULL");
     // one output block per chunk, consecutive in each array
-    const int64_t nf = p->Nf, nf2 = nf * nf;
+    const int64_t nf = p->Ng, nf2 = nf * nf;
     const int64_t e1 = 2LL * p->C, e2 = 2 * p->n2() * nf, e3 = 2 * p->n3() * nf2, e4 = 2 * p->n4() * nf2;
     auto at = [](double* base, int64_t i, int64_t n) { return base ? base + i * n : nullptr; };
     std::vector<ps_output> outs((size_t)n_chunks);
@@ -1186,6 +1218,7 @@ ps_status ps_full_plane(ps_plan_t p, int32_t order, const int8_t* combo, const p
                         double* d_err, ps_stream_t stream) {
     if (!p || !combo || !in) return fail(PS_E_INVALID_ARG, "NULL argument");
     if (order < 2 || order > 4 || !p->has(order)) return fail(PS_E_INVALID_ARG, "order %d not computed", order);
+    if (p->cplx) return fail(PS_E_UNSUPPORTED, "complex signals: the output grid is already the full plane");
     for (int i = 0; i < order; ++i)
         if (combo[i] < 0 || combo[i] >= p->C) return fail(PS_E_INVALID_ARG, "channel %d outside 0..%d", combo[i], p->C - 1);
     const double* src = order == 2 ? in->d_s2 : (order == 3 ? in->d_s3 : in->d_s4);
@@ -1325,8 +1358,8 @@ ps_status ps_streamer_create_multi(ps_plan_t p, int64_t window_samples, int32_t 
                                    int32_t depth, ps_streamer_t* out) {
     if (!out) return fail(PS_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    if (!p || window_samples <= 0 || depth < 1 || depth > 16 || dtype < PS_F32 || dtype > PS_I16 ||
-        max_windows < 1 || max_windows > 64)
+    if (!p || window_samples <= 0 || depth < 1 || depth > 16 || dtype < PS_F32 || dtype > PS_C128 ||
+        (dtype >= PS_C64) != p->cplx || max_windows < 1 || max_windows > 64)
         return fail(PS_E_INVALID_ARG, "bad argument");
     auto* s = new ps_streamer_s();
     s->plan = p;
@@ -1334,7 +1367,7 @@ ps_status ps_streamer_create_multi(ps_plan_t p, int64_t window_samples, int32_t 
     s->dtype = dtype;
     s->depth = depth;
     s->max_windows = max_windows;
-    s->esz = dtype == PS_F32 ? 4 : (dtype == PS_F64 ? 8 : 2);
+    s->esz = elem_size(dtype);
     hipError_t e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
     auto alloc = [&](size_t bytes) -> void* {
         void* q = nullptr;

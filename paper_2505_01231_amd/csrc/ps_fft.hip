@@ -20,6 +20,10 @@
 // out [r][k], so that the twiddles of consecutive threads are consecutive
 // entries (a gather from the plain table touches up to one cache line per
 // lane).  The stage streams N samples in and K complex values out per frame.
+// A complex-valued signal (complex float32 / float64 samples) needs no packing:
+// its frames of M samples are windowed and transformed as they are (the same
+// passes, instantiated for twice the frame length), and column c of the output
+// holds X at bin c - jmax, taken mod M.
 #include "ps_internal.h"
 
 namespace ps {
@@ -152,6 +156,25 @@ __device__ __forceinline__ void load_first(float2 (&v)[16], const T* __restrict_
     }
 }
 
+// Complex samples (n = t + r Tn) times the real window g_n.
+template <typename T2>
+__device__ __forceinline__ void load_first_cplx(float2 (&v)[16], const T2* __restrict__ xf,
+                                                const float* __restrict__ g, int t, int Tn, bool live) {
+    if (!live) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
+        return;
+    }
+    T2 x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) x[r] = xf[t + r * Tn];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const float w = g[t + r * Tn];
+        v[r] = make_float2(w * (float)x[r].x, w * (float)x[r].y);
+    }
+}
+
 // Twiddles of a Stockham pass of radix R and span Ns (see fft_pass) for the
 // butterflies of thread t: w[b R + r] = exp(+2 pi j r k / (R Ns)), k = j mod Ns,
 // from the pass's table tbl[r Ns + k] (consecutive threads read consecutive k).
@@ -197,7 +220,7 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[16], const float2 (&w)[16],
     lds_barrier();
 }
 
-template <int LOG2N>
+template <int LOG2N, bool CPLX>
 __global__ __launch_bounds__(kFftThreads, 4) void k_window_rfft(FftArgs a) {
     constexpr int N = 1 << LOG2N;
     constexpr int LOG2M = LOG2N - 1;
@@ -223,7 +246,7 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_window_rfft(FftArgs a) {
         }
         rec = a.recs[lo];
     }
-    const int64_t off = c * rec.chan_stride + (gf - rec.frame0) * N;
+    const int64_t off = c * rec.chan_stride + (gf - rec.frame0) * (CPLX ? M : N);
     const float* __restrict__ g = a.g;
     const float2* __restrict__ tw = a.tw;
 
@@ -231,9 +254,14 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_window_rfft(FftArgs a) {
     // pass's just before its LDS reads (one pass ahead they spill registers).
     float2 v[16], w2[16], w3[16];
     if constexpr (R2 > 0) pass_twiddles<LOG2M, R2>(w2, t, 16, tw + N);
-    if (rec.dtype == 0) load_first(v, static_cast<const float*>(rec.data) + off, g, t, Tn, live);
-    else if (rec.dtype == 1) load_first(v, static_cast<const double*>(rec.data) + off, g, t, Tn, live);
-    else load_first(v, static_cast<const int16_t*>(rec.data) + off, g, t, Tn, live);
+    if constexpr (CPLX) {
+        if (rec.dtype == 3) load_first_cplx(v, static_cast<const float2*>(rec.data) + off, g, t, Tn, live);
+        else load_first_cplx(v, static_cast<const double2*>(rec.data) + off, g, t, Tn, live);
+    } else {
+        if (rec.dtype == 0) load_first(v, static_cast<const float*>(rec.data) + off, g, t, Tn, live);
+        else if (rec.dtype == 1) load_first(v, static_cast<const double*>(rec.data) + off, g, t, Tn, live);
+        else load_first(v, static_cast<const int16_t*>(rec.data) + off, g, t, Tn, live);
+    }
 
     fft_pass<LOG2M, 16, true>(v, w2, s, t, 1);
     if constexpr (R2 > 0) fft_pass<LOG2M, R2, false>(v, w2, s, t, 16);
@@ -246,6 +274,15 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_window_rfft(FftArgs a) {
     constexpr int KMAX = (M + 1 + Tn - 1) / Tn;
     const int K = a.K;
     float2* o = a.out + c * a.out_chan_stride + (gf - a.out_g0) * K;
+    if constexpr (CPLX) {
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) {
+            const int col = t + i * Tn;
+            if (col >= K) break;
+            o[col] = s[pad((col - a.jmax) & (M - 1))];
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
         const int k = t + i * Tn;
@@ -266,7 +303,12 @@ hipError_t launch_n(const FftArgs& a, hipStream_t st) {
     constexpr int M = (1 << LOG2N) / 2, F = kFftThreads / (M / 16);
     const int64_t n = a.g_hi - a.g_lo;
     dim3 grid((unsigned)((n + F - 1) / F), a.n_channels);
-    k_window_rfft<LOG2N><<<grid, kFftThreads, 0, st>>>(a);
+    if (a.cplx) {
+        if constexpr (LOG2N >= 9) k_window_rfft<LOG2N, true><<<grid, kFftThreads, 0, st>>>(a);
+        else return hipErrorInvalidValue;
+    } else {
+        k_window_rfft<LOG2N, false><<<grid, kFftThreads, 0, st>>>(a);
+    }
     return hipGetLastError();
 }
 
@@ -278,16 +320,16 @@ constexpr int kCentreRegs = 16;
 // Grid: x = chunk * kblocks + (256-wide k block), y = channel (the chunk count
 // can exceed the 65536 limit of the y and z grid dimensions).
 __global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64_t coef_cs, int K, int m,
-                                                int kblocks, float* __restrict__ s1, int64_t s1_cs,
-                                                int64_t s1_chunk0) {
+                                                int kblocks, float2* __restrict__ s1, int64_t s1_cs,
+                                                int64_t s1_chunk0, int s1_col) {
     const int64_t chunk = blockIdx.x / kblocks;
     const int k = (int)(blockIdx.x - chunk * kblocks) * 256 + threadIdx.x;
     if (k >= K) return;
     float2* p = coef + blockIdx.y * coef_cs + chunk * m * K + k;
     const float inv = 1.0f / (float)m;
     // S1: the chunk's mean of a_0 (real for a real signal)
-    auto keep_mean = [&](float mr) {
-        if (s1 && k == 0) s1[blockIdx.y * s1_cs + s1_chunk0 + chunk] = mr;
+    auto keep_mean = [&](float mr, float mi) {
+        if (s1 && k == s1_col) s1[blockIdx.y * s1_cs + s1_chunk0 + chunk] = make_float2(mr, mi);
     };
     if (m <= kCentreRegs) {
         float2 v[kCentreRegs];
@@ -301,7 +343,7 @@ __global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64
             }
         }
         const float mr = sr * inv, mi = si * inv;
-        keep_mean(mr);
+        keep_mean(mr, mi);
 #pragma unroll
         for (int f = 0; f < kCentreRegs; ++f)
             if (f < m) p[(int64_t)f * K] = make_float2(v[f].x - mr, v[f].y - mi);
@@ -314,7 +356,7 @@ __global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64
         si += v.y;
     }
     const float mr = sr * inv, mi = si * inv;
-    keep_mean(mr);
+    keep_mean(mr, mi);
     for (int f = 0; f < m; ++f) {
         const float2 v = p[(int64_t)f * K];
         p[(int64_t)f * K] = make_float2(v.x - mr, v.y - mi);
@@ -342,7 +384,8 @@ hipError_t launch_centre(const CentreArgs& a, hipStream_t s) {
     const int64_t nx = (int64_t)kblocks * a.n_chunks;
     if (nx > 0x7fffffff) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)nx, a.n_channels);
-    k_centre<<<grid, 256, 0, s>>>(a.coef, a.coef_chan_stride, a.K, a.m, kblocks, a.s1, a.s1_cs, a.s1_chunk0);
+    k_centre<<<grid, 256, 0, s>>>(a.coef, a.coef_chan_stride, a.K, a.m, kblocks, a.s1, a.s1_cs, a.s1_chunk0,
+                                  a.s1_col);
     return hipGetLastError();
 }
 

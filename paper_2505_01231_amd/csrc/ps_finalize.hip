@@ -196,50 +196,57 @@ __global__ void k_fill_nan(double* p, int64_t n) {
 }
 
 // S1: one block per (record, channel).  Thread t adds the per-chunk means of
-// a_0 of chunks t, t + 256, ... in FP64 (of each frame set); the partial sums
-// are then added in a fixed tree order.  S1 is real: Im = 0, sigma_Im = 0
-// (NaN where the mean or the error bar is undefined).
+// a_0 of chunks t, t + 256, ... in FP64 (of each frame set; real and imaginary
+// parts and their squares); the partial sums are then added in a fixed tree
+// order.  For a real signal a_0 is real, so Im and sigma_Im come out 0 (NaN
+// where the mean or the error bar is undefined).
 __global__ __launch_bounds__(256) void k_finalize_s1(FinalizeArgs p) {
-    __shared__ double red[4][256];
+    __shared__ double red[8][256];
     const int64_t x = blockIdx.x;
     if (x >= p.n_items) return;
     const Seg& sg = p.segs[find_seg(p.segs, p.n_segs, x)];
     const bool two = sg.n_chunks2 > 0;
-    const float* v = p.s1 + (int64_t)sg.ch[0] * p.s1_cs;
+    const float2* v = p.s1 + (int64_t)sg.ch[0] * p.s1_cs;
     const int tid = threadIdx.x;
     for (int set = 0; set < 2; ++set) {
         const int64_t c0 = set ? sg.part2 : sg.part, W = set ? (two ? sg.n_chunks2 : 0) : sg.n_chunks;
-        double s = 0.0, s2 = 0.0;
+        double sr = 0.0, si = 0.0, sr2 = 0.0, si2 = 0.0;
         for (int64_t c = tid; c < W; c += 256) {
-            const double d = v[c0 + c];
-            s += d;
-            s2 = fma(d, d, s2);
+            const float2 d = v[c0 + c];
+            sr += d.x;
+            si += d.y;
+            sr2 = fma((double)d.x, (double)d.x, sr2);
+            si2 = fma((double)d.y, (double)d.y, si2);
         }
-        red[2 * set][tid] = s;
-        red[2 * set + 1][tid] = s2;
+        red[4 * set][tid] = sr;
+        red[4 * set + 1][tid] = si;
+        red[4 * set + 2][tid] = sr2;
+        red[4 * set + 3][tid] = si2;
     }
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
         if (tid < h)
-            for (int q = 0; q < 4; ++q) red[q][tid] += red[q][tid + h];
+            for (int q = 0; q < 8; ++q) red[q][tid] += red[q][tid + h];
         __syncthreads();
     }
     if (tid != 0) return;
-    double mean, sigma;
-    mean_sigma(red[0][0], red[1][0], (double)sg.n_chunks, sg.scale, mean, sigma);
+    double mr, sr, mi, si;
+    mean_sigma(red[0][0], red[2][0], (double)sg.n_chunks, sg.scale, mr, sr);
+    mean_sigma(red[1][0], red[3][0], (double)sg.n_chunks, sg.scale, mi, si);
     if (two) {
-        double mean2, sigma2;
-        mean_sigma(red[2][0], red[3][0], (double)sg.n_chunks2, sg.scale, mean2, sigma2);
-        combine_sets(mean, sigma, mean2, sigma2);
+        double mr2, sr2, mi2, si2;
+        mean_sigma(red[4][0], red[6][0], (double)sg.n_chunks2, sg.scale, mr2, sr2);
+        mean_sigma(red[5][0], red[7][0], (double)sg.n_chunks2, sg.scale, mi2, si2);
+        combine_sets(mr, sr, mr2, sr2);
+        combine_sets(mi, si, mi2, si2);
     }
-    const double nan = __longlong_as_double(0x7ff8000000000000LL);
     if (sg.out) {
-        sg.out[0] = mean;
-        sg.out[1] = mean == mean ? 0.0 : nan;
+        sg.out[0] = mr;
+        sg.out[1] = mi;
     }
     if (sg.err) {
-        sg.err[0] = sigma;
-        sg.err[1] = sigma == sigma ? 0.0 : nan;
+        sg.err[0] = sr;
+        sg.err[1] = si;
     }
 }
 

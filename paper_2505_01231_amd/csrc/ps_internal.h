@@ -50,13 +50,17 @@ struct FftArgs {
     int64_t g_lo, g_hi;     // global frames to transform
     int64_t out_g0;         // global frame stored at row 0 of `out`
     int n_channels;
-    int log2n;              // log2(N), 8..13
+    int log2n;              // log2(N), 8..13 (complex signals: log2 of twice the frame length)
     int K;                  // coefficients kept per frame
+    // Complex signals: frames of M = N/2 complex samples (dtype 3: complex
+    // float32, 4: complex float64), transformed as they are; column c of the
+    // output holds bin c - jmax.  Real signals: column c holds bin c.
     const float* g;         // window [N]
     const float2* tw;       // twiddles, see fft_twiddle_count
     float2* out;            // [C][rows][K]
     int64_t out_chan_stride;
     int dtype;              // common dtype of the records (launch template)
+    int cplx, jmax;
 };
 hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s);
 
@@ -76,16 +80,17 @@ __host__ __device__ constexpr int fft_twiddle_count(int log2n) {
 }
 
 // In-place centring: a_k(f) -= mean over the m frames of its chunk.  With
-// `s1` set, the chunk's mean of Re a_0 (the first-order k-statistic) is also
-// stored at s1[channel * s1_cs + s1_chunk0 + chunk].
+// `s1` set, the chunk's mean of a_0 (column s1_col; the first-order
+// k-statistic) is also stored at s1[channel * s1_cs + s1_chunk0 + chunk].
 struct CentreArgs {
     float2* coef;           // [C][n_chunks * m][K]
     int64_t coef_chan_stride;
     int K, m;
     int64_t n_chunks;
     int n_channels;
-    float* s1;
+    float2* s1;
     int64_t s1_cs, s1_chunk0;
+    int s1_col;
 };
 hipError_t launch_centre(const CentreArgs& a, hipStream_t s);
 
@@ -154,7 +159,8 @@ struct BatchArgs {
     const float2* coef;     // coefficient region
     int64_t coef_chan_stride;
     double* part;           // partial-sum region
-    int K, m, Nf;
+    int K, m, Nf;           // Nf: points per grid axis (2 N_f - 1 for complex signals)
+    int col0;               // column of grid index 0 for the first factors (see View)
     // Per-chunk schedule: only chunks [win_lo, win_hi) of each segment are
     // processed and chunk c sits at frame (c - win_lo) m of the region.
     int per_chunk, win_lo, win_hi;
@@ -189,7 +195,7 @@ struct FinalizeArgs {
     TileTables tt;
     const double* part;
     int Nf;
-    const float* s1;        // per-chunk means of a_0, [C][s1_cs] (S1 only)
+    const float2* s1;       // per-chunk means of a_0, [C][s1_cs] (S1 only)
     int64_t s1_cs;
 };
 hipError_t launch_finalize_vec(const FinalizeArgs& a, hipStream_t s);

@@ -51,10 +51,14 @@ struct Item {
 
 // Coefficients of the item's record: chunk c, frame f, column k of channel ch
 // is at coef[ch * cs + off + (c m + f) K + k].
+// `coef` points at the coefficient of grid index 0 of the first factors:
+// column col0 of the region (0 for real signals; for complex signals grid
+// index k' is bin k' - (N_f - 1), stored at column k' + col0).  S3's third
+// factor, bin k + l, sits at column k' + l' of the region itself.
 struct View {
     const float2* coef;
     int64_t cs, off;
-    int K, m;
+    int K, m, col0;
 };
 
 __device__ __forceinline__ bool resolve_block(const BatchArgs& b, Block& bk, View& v) {
@@ -75,7 +79,8 @@ __device__ __forceinline__ bool resolve_block(const BatchArgs& b, Block& bk, Vie
     bk.v = bk.sc.run_begin(bk.j);
     bk.v1 = bk.sc.run_begin(bk.j + 1);
     bk.round = 0;
-    v.coef = b.coef;
+    v.coef = b.coef + b.col0;
+    v.col0 = b.col0;
     v.cs = b.coef_chan_stride;
     v.off = b.per_chunk ? -(int64_t)b.win_lo * b.m * b.K : s.coef;
     v.K = b.K;
@@ -218,7 +223,7 @@ __device__ __forceinline__ void s3_item(const BatchArgs& p, const View& v, const
         src = v.coef + it.ch[1] * v.cs + l0 + col - kTile;
     } else if (col < 4 * kTile - 1) {
         live = k0 + l0 + col - 2 * kTile < v.K;
-        src = v.coef + it.ch[2] * v.cs + k0 + l0 + col - 2 * kTile;
+        src = v.coef - v.col0 + it.ch[2] * v.cs + k0 + l0 + col - 2 * kTile;
     }
 
     const int per_chunk = (v.m + FB - 1) / FB;

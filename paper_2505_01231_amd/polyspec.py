@@ -17,7 +17,8 @@ from . import _lib as L
 _WINDOWS = {"hann": L.PS_WIN_HANN, "hann_periodic": L.PS_WIN_HANN_PERIODIC, "acg": L.PS_WIN_ACG}
 _PRECISION = {"fp32": L.PS_PREC_FP32, "bf16x3": L.PS_PREC_BF16X3, "fp16x2s": L.PS_PREC_FP16X2S}
 _SCHEDULE = {"batched": L.PS_SCHED_BATCHED, "per_chunk": L.PS_SCHED_PER_CHUNK}
-_DTYPES = {torch.float32: L.PS_F32, torch.float64: L.PS_F64, torch.int16: L.PS_I16}
+_DTYPES = {torch.float32: L.PS_F32, torch.float64: L.PS_F64, torch.int16: L.PS_I16,
+           torch.complex64: L.PS_C64, torch.complex128: L.PS_C128}
 
 
 def enumerate_combos(n_channels: int, order: int):
@@ -70,13 +71,15 @@ class Plan:
     spectra of the frames starting at sample 0 and of the frames starting half a
     frame later (Section 3's interlaced windows; batched schedule only).
     ``estimator="natural"`` selects the biased plug-in estimator of Section 6
-    instead of the k-statistics (for comparisons)."""
+    instead of the k-statistics (for comparisons).  ``complex_signal=True``
+    takes complex64 / complex128 records and returns every spectrum on the
+    signed grid of ``grid`` = 2 N_f - 1 points per axis (index k + N_f - 1)."""
 
     def __init__(self, frame_len: int, n_freq: int = 0, m: int = 10, dt: float = 1.0,
                  orders=(2, 3, 4), n_channels: int = 1, window: str = "acg",
                  window_param: float = 0.14, precision: str = "fp32", schedule: str = "batched",
                  f_max: float = 0.0, combos2=None, combos3=None, combos4=None, interlaced: bool = False,
-                 estimator: str = "kstat"):
+                 estimator: str = "kstat", complex_signal: bool = False):
         self._lib = L.load()
         self._handle = None
         cfg = L.ps_config()
@@ -94,6 +97,7 @@ class Plan:
         cfg.schedule = _SCHEDULE[schedule]
         cfg.interlaced = 1 if interlaced else 0
         cfg.estimator = {"kstat": L.PS_EST_KSTAT, "natural": L.PS_EST_NATURAL}[estimator]
+        cfg.complex_signal = 1 if complex_signal else 0
         self._keep = []
         for arity, combos in ((2, combos2), (3, combos3), (4, combos4)):
             n, arr, ptr = _flat(combos, arity)
@@ -107,6 +111,8 @@ class Plan:
         L.check(self._lib.ps_plan_query(h, C.byref(info)), "ps_plan_query")
         self.frame_len = info.frame_len
         self.n_freq = info.n_freq
+        self.grid = info.grid                 # points per output axis
+        self.complex_signal = bool(complex_signal)
         self.n_coef = info.n_coef
         self.m = info.m
         self.f_max = info.f_max
@@ -170,7 +176,7 @@ class Plan:
         return n.value
 
     def allocate_outputs(self, device) -> Spectra:
-        nf = self.n_freq
+        nf = self.grid
         f64 = dict(dtype=torch.float64, device=device)
         n2, n3, n4 = len(self.combos2), len(self.combos3), len(self.combos4)
         return Spectra(
@@ -228,7 +234,7 @@ class Plan:
         device = x.device
         if workspace is None or workspace.numel() < need.value:
             workspace = torch.empty(max(need.value, 256), dtype=torch.uint8, device=device)
-        nf = self.n_freq
+        nf = self.grid
         f64 = dict(dtype=torch.float64, device=device)
         n2, n3, n4 = len(self.combos2), len(self.combos3), len(self.combos4)
         n1 = self.n_channels if 1 in self.orders else 0

@@ -808,6 +808,83 @@ def test_full_plane_matches_direct_evaluation(dev):
         torch.cuda.synchronize()
 
 
+# ---------------------------------------------------------------- complex-valued signals
+def _complex_signal(n, seed, q=3, N=256, channels=1):
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in range(channels):
+        x = synth.ar2_chi2(n, seed=seed + c, r=0.9, dtype=np.float64)
+        z = x * np.exp(2j * np.pi * (q + c) * np.arange(n) / N) + 0.3 * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+        out.append(z)
+    return np.stack(out) if channels > 1 else out[0]
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_complex_signal_matches_oracle(dev, precision):
+    """A complex record (a shifted AR(2)/chi-square process plus complex noise):
+    S1..S4 on the signed grid (-N_f, N_f) equal the oracle's."""
+    say("complex signal", precision)
+    N, Nf, m = 256, 40, 8
+    z = _complex_signal(N * m * 7 + 30, seed=151, N=N).astype(np.complex64)
+    gpu = run_gpu(z, dev, frame_len=N, n_freq=Nf, m=m, precision=precision, complex_signal=True,
+                  orders=(1, 2, 3, 4))
+    ref = O.polyspectra_complex(z, N, Nf, m, orders=(1, 2, 3, 4))
+    assert gpu["s3"].shape == (1, 2 * Nf - 1, 2 * Nf - 1)
+    compare(gpu, ref, label=f"complex-{precision}")
+
+
+def test_complex_path_on_real_data_equals_full_plane(dev):
+    """Two real channels given as complex64: the complex plan's grids equal the
+    real plan's outputs gathered onto the full plane (two GPU paths)."""
+    from paper_2505_01231_amd import Plan
+    say("complex path on real data")
+    N, Nf, m = 256, 24, 8
+    s = synth.ar2_chi2(N * m * 6 + 9, seed=152, r=0.9, dtype=np.float32)
+    z = np.stack([s[:-3], s[3:] ** 2 - 1]).astype(np.float32)
+    kw = dict(frame_len=N, n_freq=Nf, m=m, n_channels=2, precision="bf16x3")
+    with Plan(complex_signal=True, **kw) as pc, Plan(**kw) as pr:
+        oc = pc.execute(torch.from_numpy(z.astype(np.complex64)).to(dev))
+        orl = pr.execute(torch.from_numpy(z).to(dev))
+        assert pc.combos3 == pr.combos3 and pc.grid == 2 * Nf - 1
+        for order in (2, 3, 4):
+            combos = getattr(pc, f"combos{order}")
+            for i, cb in enumerate(combos):
+                val, err = pr.full_plane(orl, order, cb)
+                torch.cuda.synchronize()
+                g = torch.view_as_complex(getattr(oc, f"s{order}")[i]).cpu().numpy()
+                ge = getattr(oc, f"s{order}_err")[i].cpu().numpy()
+                r = torch.view_as_complex(val).cpu().numpy()
+                assert rel_err(g, r) <= TOL, (order, cb, rel_err(g, r))
+                assert rel_err(ge, err.cpu().numpy()) <= TOL, (order, cb)
+
+
+def test_complex_channels_interlaced_and_errors(dev):
+    """Two complex128 channels, every orbit, interlaced windows, vs the oracle;
+    a real record on a complex plan and the full plane of a complex plan are
+    refused."""
+    import ctypes
+    from paper_2505_01231_amd import Plan
+    from paper_2505_01231_amd import _lib as L
+    say("complex, 2 channels, interlaced")
+    N, Nf, m = 256, 20, 6
+    z = _complex_signal(N * m * 5 + 200, seed=153, N=N, channels=2)
+    with Plan(frame_len=N, n_freq=Nf, m=m, n_channels=2, precision="bf16x3", complex_signal=True,
+              interlaced=True, orders=(1, 2, 3, 4)) as p:
+        out = p.execute(torch.from_numpy(z).to(dev))
+        torch.cuda.synchronize()
+        ref = O.polyspectra_interlaced(z, N, Nf, m, orders=(1, 2, 3, 4), combos2=p.combos2, combos3=p.combos3,
+                                       combos4=p.combos4)
+        for key in ("s1", "s2", "s3", "s4"):
+            g = torch.view_as_complex(getattr(out, key)).cpu().numpy()
+            assert rel_err(g, ref[key]) <= TOL, (key, rel_err(g, ref[key]))
+            assert rel_err(getattr(out, key + "_err").cpu().numpy(), ref[key + "_err"]) <= TOL, key
+        with pytest.raises(RuntimeError):
+            p.execute(torch.from_numpy(z.real.copy()).to(dev))
+        cb = (ctypes.c_int8 * 3)(0, 1, 0)
+        st = p._lib.ps_full_plane(p._handle, 3, cb, ctypes.byref(out.c_struct()), None, None, None)
+        assert st == L.PS_E_UNSUPPORTED
+
+
 # ---------------------------------------------------------------- launch configuration (autotuner)
 def _tuning_case(dev):
     """Two channels (every S3/S4 orbit, so all four tile tables are used), a
