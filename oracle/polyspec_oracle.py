@@ -365,14 +365,20 @@ def polyspectra(z, N: int, Nf: int, m: int, dt: float = 1.0, window_kind: str = 
 
 def polyspectra_complex(z, N: int, Nf: int, m: int, dt: float = 1.0, window_kind: str = "acg",
                         window_param: float = 0.14, orders=(2, 3, 4), combos2=None, combos3=None,
-                        combos4=None, estimator: str = "kstat", return_chunks: bool = False):
+                        combos4=None, estimator: str = "kstat", return_chunks: bool = False,
+                        s4_shift: int = 0):
     """Spectra of a complex-valued record on the signed grid k, l in
     (-N_f, N_f): without a_{-k} = conj(a_k) the negative frequencies carry their
     own information, so the same definitions (Sections 3, 4 and 7) are
     evaluated at every signed index.  Coefficients are eq. a_k at signed bins
     (numpy's inverse FFT, index taken mod N).  Returns the keys of polyspectra
     with grids of 2 N_f - 1 points per axis, index k + N_f - 1; 's1' (order 1)
-    is complex.
+    is complex.  The conjugated arguments are those of the real-signal
+    formulas (a_k, b*_k; a_k, b_l, c*_{k+l}; a_k, b*_k, c_l, d*_l).
+
+    s4_shift = q selects a plane of the three-dimensional fourth-order spectrum
+    parallel to the cut (Appendix on the full S4: shifting the channels in
+    frequency by q bins): S4[k, l] = C4(a_{k+q}, b*_{k-q}, c_{l-q}, d*_{l+q}).
     """
     z = np.asarray(z)
     if z.ndim == 1:
@@ -386,7 +392,7 @@ def polyspectra_complex(z, N: int, Nf: int, m: int, dt: float = 1.0, window_kind
     combos4 = combos4 if 4 in orders else []
     e2, e3, e4 = ESTIMATORS[estimator]
     g = window(window_kind, N, window_param)
-    jmax = 2 * (Nf - 1) if combos3 else Nf - 1
+    jmax = max(2 * (Nf - 1) if combos3 else Nf - 1, (Nf - 1 + abs(s4_shift)) if combos4 else 0)
     bins = np.arange(-jmax, jmax + 1)               # coefficient column c holds bin c - jmax
     frames = chunk_frames(z.astype(np.complex128), N, m)     # [C, Np, m, N]
     Np = frames.shape[1]
@@ -408,11 +414,12 @@ def polyspectra_complex(z, N: int, Nf: int, m: int, dt: float = 1.0, window_kind
             y = A[b, col][None, :, :]
             w = np.conj(A[c][col[:, None] + ks[None, :]])         # bin k + l
             per3[p, i] = e3(x, y, w) / _norm(g, dt, 3)
+        q = s4_shift
         for i, (a, b, c, d) in enumerate(combos4):
-            x = A[a, col][:, None, :]
-            y = np.conj(A[b, col])[:, None, :]
-            u = A[c, col][None, :, :]
-            w = np.conj(A[d, col])[None, :, :]
+            x = A[a, col + q][:, None, :]
+            y = np.conj(A[b, col - q])[:, None, :]
+            u = A[c, col - q][None, :, :]
+            w = np.conj(A[d, col + q])[None, :, :]
             per4[p, i] = e4(x, y, u, w) / _norm(g, dt, 4)
     out = {"n_chunks": Np, "combos2": combos2, "combos3": combos3, "combos4": combos4}
     if 1 in orders:
@@ -423,6 +430,32 @@ def polyspectra_complex(z, N: int, Nf: int, m: int, dt: float = 1.0, window_kind
     if return_chunks:
         out["chunks1"], out["chunks2"], out["chunks3"], out["chunks4"] = per1, per2, per3, per4
     return out
+
+
+def trispectrum_at(z, N: int, m: int, points, dt: float = 1.0, window_kind: str = "acg",
+                   window_param: float = 0.14, combo=(0, 0, 0, 0), estimator: str = "kstat"):
+    """The full fourth-order spectrum at listed frequency triples (w1, w2, w3),
+    as the general definition has it: C4(a_w1, a_w2, a_w3, a_w4) with
+    w4 = -(w1 + w2 + w3), every component unconjugated, negative bins taken
+    mod N (the Fourier components of the record at negative frequencies).
+    Normalised by dt sum g^4 like the cut.  Returns (values [n], errors [n, 2]).
+    """
+    z = np.asarray(z)
+    if z.ndim == 1:
+        z = z[None, :]
+    g = window(window_kind, N, window_param)
+    e4 = ESTIMATORS[estimator][2]
+    pts = [(int(a), int(b), int(c)) for a, b, c in points]
+    bins = sorted({w for p in pts for w in p} | {-(a + b + c) for a, b, c in pts})
+    colx = {b: i for i, b in enumerate(bins)}
+    frames = chunk_frames(z, N, m)                          # [C, Np, m, N]
+    C, Np = frames.shape[0], frames.shape[1]
+    coef = np.stack([coefficients_at(frames[ch].reshape(Np * m, N), g, dt, bins) for ch in range(C)])
+    coef = np.moveaxis(coef.reshape(C, Np, m, len(bins)), 2, -1)     # [C, Np, bins, m]
+    ca, cb, cc, cd = combo
+    per = np.stack([e4(coef[ca, :, colx[a]], coef[cb, :, colx[b]], coef[cc, :, colx[c]],
+                       coef[cd, :, colx[-(a + b + c)]]) for a, b, c in pts], axis=1) / _norm(g, dt, 4)
+    return average_with_error(per)
 
 
 def polyspectra_interlaced(z, N: int, Nf: int, m: int, **kw):

@@ -670,3 +670,20 @@ def test_complex_white_noise():
     for key in ("s3", "s4"):
         t = np.abs(out[key][0].real) / out[key + "_err"][0][..., 0]
         assert np.mean(t > 3) < 0.02, (key, np.mean(t > 3))
+
+
+def test_s4_planes_are_planes_of_the_three_dimensional_spectrum():
+    """The plane shifted by q bins equals the full fourth-order spectrum at
+    (k + q, -k + q, l - q) (Appendix on the full S4), evaluated directly with
+    unconjugated components at negative frequencies; q = 0 is the cut."""
+    N, Nf, m = 32, 5, 6
+    s = synth.ar2_chi2(N * m * 10 + 3, seed=161, r=0.8, dtype=np.float64)
+    z = np.stack([s[:-3], s[3:] ** 2 - 1.0])
+    ks = range(-Nf + 1, Nf)
+    for q, combo in ((2, (0, 0, 0, 0)), (-3, (0, 1, 1, 0)), (0, (1, 0, 0, 1))):
+        out = O.polyspectra_complex(z.astype(np.complex128), N, Nf, m, orders=(4,), combos4=[combo], s4_shift=q)
+        pts = [(k + q, -k + q, l - q) for k in ks for l in ks]
+        ref, ref_err = O.trispectrum_at(z, N, m, pts, combo=combo)
+        got = out["s4"][0].ravel()
+        assert np.allclose(got, ref, rtol=0, atol=1e-12 * np.abs(ref).max()), (q, combo)
+        assert np.allclose(out["s4_err"][0].reshape(-1, 2), ref_err, rtol=0, atol=1e-12 * ref_err.max()), (q, combo)
