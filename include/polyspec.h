@@ -117,14 +117,26 @@ typedef struct ps_config {
     int32_t interlaced;    /* 0 or 1: interlaced windows (see below); PS_SCHED_BATCHED only */
     int32_t estimator;     /* ps_estimator */
     int32_t complex_signal; /* 0: real records; 1: complex records (PS_C64 / PS_C128), see below */
-    int32_t reserved;      /* must be 0 */
+    int32_t s4_shift;      /* q: S4 on a plane parallel to the cut (complex_signal = 1), see below */
 } ps_config;
 /* Complex-valued signals (complex_signal = 1; frame_len up to 4096): without
  * a_{-k} = a_k* the negative frequencies carry their own information, so every
  * spectrum is computed on the signed grid k, l in (-N_f, N_f): S2 has 2 N_f - 1
  * points, S3 and S4 (2 N_f - 1)^2, index k + N_f - 1 (ps_plan_info.grid), and
  * S1 is complex.  Same definitions (Sections 3, 4 and 7) and constraints on
- * N_f; ps_full_plane does not apply (the grid is already the full plane). */
+ * N_f; ps_full_plane does not apply (the grid is already the full plane).
+ * The conjugated arguments are those of the real-signal formulas, so S2_ab of
+ * complex records is C2(a_k, b*_k) (the power spectrum for a = b); the
+ * unconjugated negative-frequency components of the general definition are
+ * obtained by passing conj(b) as channel b.
+ *
+ * Planes of the three-dimensional fourth-order spectrum (Appendix on the full
+ * S4): s4_shift = q != 0 computes every S4 combination on the plane parallel
+ * to the cut, S4_abcd(k, l) = C4(a_{k+q}, b*_{k-q}, c_{l-q}, d*_{l+q}), i.e. the
+ * full spectrum at (k + q, -k + q, l - q) for real data; it needs
+ * complex_signal = 1 (pass real records as complex), N_f - 1 + |q| <= N/2, and
+ * then uses every channel combination (no symmetry maps a plane onto itself
+ * for q != 0; explicit lists are taken as given). */
 /* Cumulant estimator per chunk.  PS_EST_KSTAT: the unbiased k-statistics of
  * Section 4.1.  PS_EST_NATURAL: the natural (plug-in) estimator of Section 6,
  * the cumulant's moment expression with sample means (biased by O(1/m); for

@@ -41,7 +41,7 @@ class ps_config(C.Structure):
         ("n_combos2", C.c_int32), ("n_combos3", C.c_int32), ("n_combos4", C.c_int32),
         ("combos2", C.POINTER(C.c_int8)), ("combos3", C.POINTER(C.c_int8)),
         ("combos4", C.POINTER(C.c_int8)), ("interlaced", C.c_int32), ("estimator", C.c_int32),
-        ("complex_signal", C.c_int32), ("reserved", C.c_int32),
+        ("complex_signal", C.c_int32), ("s4_shift", C.c_int32),
     ]
 
 

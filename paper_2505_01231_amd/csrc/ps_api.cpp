@@ -112,7 +112,8 @@ struct ps_plan_s {
     // column c holds bin c - jmax, the first factors of grid index k' sit at
     // column k' + col0; the transform runs at twice the frame length's log2.
     bool cplx = false;
-    int Ng = 0, col0 = 0, jmax = 0, log2n_fft = 0;    // second frame set shifted by N/2, spectra averaged
+    int Ng = 0, col0 = 0, jmax = 0, log2n_fft = 0;
+    int s4_shift = 0;       // S4 plane parallel to the cut (complex signals)    // second frame set shifted by N/2, spectra averaged
     std::vector<int8_t> c2, c3, c4;
     double sum_g[5] = {0, 0, 0, 0, 0};
     int T = 0, TX = 0;
@@ -143,14 +144,17 @@ struct ps_plan_s {
     int n3() const { return has(3) ? (int)c3.size() / 3 : 0; }
     int n4() const { return has(4) ? (int)c4.size() / 4 : 0; }
     bool s3_sym(int i) const { return c3[3 * i] == c3[3 * i + 1]; }
+    // A plane (s4_shift != 0) has neither the single-channel structure nor
+    // the transposition symmetry of the cut: the cross-channel kernels on full
+    // grids compute it.
     bool s4_single(int i) const {
         const int8_t* q = &c4[4 * i];
-        return q[0] == q[1] && q[1] == q[2] && q[2] == q[3];
+        return s4_shift == 0 && q[0] == q[1] && q[1] == q[2] && q[2] == q[3];
     }
     // S4_abcd(k,l) = S4_cdab(l,k): symmetric grid when (a,b) = (c,d).
     bool s4_sym(int i) const {
         const int8_t* q = &c4[4 * i];
-        return q[0] == q[2] && q[1] == q[3];
+        return s4_shift == 0 && q[0] == q[2] && q[1] == q[3];
     }
     ps::TileTables tables() const {
         ps::TileTables t;
@@ -561,7 +565,8 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     if (cfg->interlaced && cfg->schedule != PS_SCHED_BATCHED)
         return fail(PS_E_UNSUPPORTED, "interlaced windows need the batched schedule");
     if (cfg->complex_signal != 0 && cfg->complex_signal != 1) return fail(PS_E_INVALID_ARG, "complex_signal must be 0 or 1");
-    if (cfg->reserved != 0) return fail(PS_E_INVALID_ARG, "reserved must be 0");
+    if (cfg->s4_shift != 0 && !cfg->complex_signal)
+        return fail(PS_E_UNSUPPORTED, "S4 planes (s4_shift != 0) need complex_signal = 1");
     if (cfg->complex_signal && cfg->frame_len > 4096)
         return fail(PS_E_UNSUPPORTED, "complex signals: frame_len up to 4096");
     int Nf = cfg->n_freq;
@@ -576,15 +581,19 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
         return fail(PS_E_INVALID_ARG, "S3 needs 2 (N_f - 1) <= N/2 (N_f = %d, N = %d)", Nf, N);
     if (!s3 && Nf - 1 > N / 2)
         return fail(PS_E_INVALID_ARG, "N_f - 1 must be <= N/2 (N_f = %d, N = %d)", Nf, N);
+    if (cfg->s4_shift != 0 && Nf - 1 + std::abs(cfg->s4_shift) > N / 2)
+        return fail(PS_E_INVALID_ARG, "S4 plane needs N_f - 1 + |q| <= N/2 (q = %d)", cfg->s4_shift);
 
     auto* p = new ps_plan_s();
     p->N = N;
     while ((1 << p->log2n) < N) ++p->log2n;
     p->Nf = Nf;
     p->cplx = cfg->complex_signal != 0;
-    p->K = p->cplx ? (s3 ? 4 * Nf - 3 : 2 * Nf - 1) : (s3 ? 2 * Nf - 1 : Nf);
     p->Ng = p->cplx ? 2 * Nf - 1 : Nf;
+    p->s4_shift = cfg->s4_shift;
     p->jmax = p->cplx ? (s3 ? 2 * (Nf - 1) : Nf - 1) : 0;
+    if (p->cplx && (cfg->orders & PS_ORDER_S4)) p->jmax = std::max(p->jmax, Nf - 1 + std::abs(p->s4_shift));
+    p->K = p->cplx ? 2 * p->jmax + 1 : (s3 ? 2 * Nf - 1 : Nf);
     p->col0 = p->cplx ? p->jmax - (Nf - 1) : 0;
     p->log2n_fft = p->log2n + (p->cplx ? 1 : 0);
     p->m = cfg->m;
@@ -602,6 +611,12 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     // Channel combinations: explicit lists or every orbit.
     std::vector<int8_t> a2, a3, a4;
     all_combos(p->C, a2, a3, a4);
+    if (p->s4_shift != 0) {     // no symmetry reduces a plane's combinations
+        a4.clear();
+        for (int i = 0; i < p->C * p->C * p->C * p->C; ++i)
+            a4.insert(a4.end(), {(int8_t)(i / (p->C * p->C * p->C)), (int8_t)(i / (p->C * p->C) % p->C),
+                                 (int8_t)(i / p->C % p->C), (int8_t)(i % p->C)});
+    }
     struct { int n; const int8_t* ptr; int arity; std::vector<int8_t>* dst; std::vector<int8_t>* dflt; } lists[3] = {
         {cfg->n_combos2, cfg->combos2, 2, &p->c2, &a2},
         {cfg->n_combos3, cfg->combos3, 3, &p->c3, &a3},
@@ -935,6 +950,7 @@ ps::BatchArgs batch_args(const ps_plan_s* p, const Batch& B, const SegTable& t, 
     a.m = p->m;
     a.Nf = p->Ng;
     a.col0 = p->col0;
+    a.col3 = p->cplx ? p->jmax - 2 * (p->Nf - 1) : 0;
     a.per_chunk = per_chunk;
     a.win_lo = win_lo;
     a.win_hi = win_hi;
@@ -943,6 +959,7 @@ ps::BatchArgs batch_args(const ps_plan_s* p, const Batch& B, const SegTable& t, 
     a.c4a = nat ? p->m : p->m * (p->m + 1);
     a.c4b = nat ? 1 : p->m - 1;
     a.gamma = (double)a.c4b / a.c4a;
+    a.s4_shift = p->s4_shift;
     a.s3_fb = p->s3_fb;
     return a;
 }

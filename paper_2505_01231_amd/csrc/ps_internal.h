@@ -161,6 +161,7 @@ struct BatchArgs {
     double* part;           // partial-sum region
     int K, m, Nf;           // Nf: points per grid axis (2 N_f - 1 for complex signals)
     int col0;               // column of grid index 0 for the first factors (see View)
+    int col3;               // column of grid-sum index 0 for S3's third factor
     // Per-chunk schedule: only chunks [win_lo, win_hi) of each segment are
     // processed and chunk c sits at frame (c - win_lo) m of the region.
     int per_chunk, win_lo, win_hi;
@@ -170,6 +171,7 @@ struct BatchArgs {
     // estimator; gamma = c4b / c4a for the kernels that form M4 - gamma (...)
     int c4a, c4b;
     double gamma;
+    int s4_shift;           // S4 planes: a, d at +q columns, b, c at -q (cross-channel kernels only)
     int s3_fb;              // S3 frames per LDS batch (kFrameBatchSmall or kFrameBatch); 0: chosen by m
 };
 hipError_t launch_s2(const BatchArgs& a, hipStream_t s);

@@ -54,11 +54,12 @@ struct Item {
 // `coef` points at the coefficient of grid index 0 of the first factors:
 // column col0 of the region (0 for real signals; for complex signals grid
 // index k' is bin k' - (N_f - 1), stored at column k' + col0).  S3's third
-// factor, bin k + l, sits at column k' + l' of the region itself.
+// factor, bin k + l, sits at column k' + l' + col3 (col3 = 0 unless an S4
+// plane widened the stored bin range).
 struct View {
     const float2* coef;
     int64_t cs, off;
-    int K, m, col0;
+    int K, m, col0, col3;
 };
 
 __device__ __forceinline__ bool resolve_block(const BatchArgs& b, Block& bk, View& v) {
@@ -81,6 +82,7 @@ __device__ __forceinline__ bool resolve_block(const BatchArgs& b, Block& bk, Vie
     bk.round = 0;
     v.coef = b.coef + b.col0;
     v.col0 = b.col0;
+    v.col3 = b.col3;
     v.cs = b.coef_chan_stride;
     v.off = b.per_chunk ? -(int64_t)b.win_lo * b.m * b.K : s.coef;
     v.K = b.K;
@@ -222,8 +224,8 @@ __device__ __forceinline__ void s3_item(const BatchArgs& p, const View& v, const
         live = l0 + col - kTile < p.Nf;
         src = v.coef + it.ch[1] * v.cs + l0 + col - kTile;
     } else if (col < 4 * kTile - 1) {
-        live = k0 + l0 + col - 2 * kTile < v.K;
-        src = v.coef - v.col0 + it.ch[2] * v.cs + k0 + l0 + col - 2 * kTile;
+        live = k0 + l0 + col - 2 * kTile < 2 * p.Nf - 1;      // grid sums k' + l' <= 2 (Ng - 1)
+        src = v.coef - v.col0 + v.col3 + it.ch[2] * v.cs + k0 + l0 + col - 2 * kTile;
     }
 
     const int per_chunk = (v.m + FB - 1) / FB;
@@ -945,7 +947,8 @@ __global__ __launch_bounds__(kS4XThreads, 2) void k_s4_cross(BatchArgs p) {
     const int arr = (tid & 127) >> 5, col = tid & 31, half = tid >> 7;
     const int gcol = (arr < 2 ? k0 : l0) + col;
     const bool live = gcol < p.Nf;
-    const float2* src = v.coef + it.ch[arr] * v.cs + gcol;
+    // S4 planes: factors a and d at column + q, b and c at column - q
+    const float2* src = v.coef + it.ch[arr] * v.cs + gcol + ((arr == 0 || arr == 3) ? p.s4_shift : -p.s4_shift);
 
     double acc[4][4];
 #pragma unroll
@@ -1124,8 +1127,10 @@ __global__ __launch_bounds__(kS4XMThreads, 2) void k_s4_cross_mfma(BatchArgs p) 
     const int c0 = it.c0, c1 = it.c1;
     const int gcol = (side ? it.l0 : it.k0) + col;
     const bool live = gcol < p.Nf;
-    const float2* srcx = v.coef + it.ch[2 * side] * v.cs + gcol;        // a (k side) or c (l side)
-    const float2* srcy = v.coef + it.ch[2 * side + 1] * v.cs + gcol;    // b or d
+    // S4 planes: a (k side) and d (l side) at column + q, b and c at column - q
+    const int shx = side ? -p.s4_shift : p.s4_shift;
+    const float2* srcx = v.coef + it.ch[2 * side] * v.cs + gcol + shx;        // a (k side) or c (l side)
+    const float2* srcy = v.coef + it.ch[2 * side + 1] * v.cs + gcol - shx;    // b or d
 
     double acc[4][4];
 #pragma unroll

@@ -73,13 +73,15 @@ class Plan:
     ``estimator="natural"`` selects the biased plug-in estimator of Section 6
     instead of the k-statistics (for comparisons).  ``complex_signal=True``
     takes complex64 / complex128 records and returns every spectrum on the
-    signed grid of ``grid`` = 2 N_f - 1 points per axis (index k + N_f - 1)."""
+    signed grid of ``grid`` = 2 N_f - 1 points per axis (index k + N_f - 1).
+    ``s4_shift=q`` (complex plans) computes S4 on the plane parallel to the cut,
+    C4(a_{k+q}, b*_{k-q}, c_{l-q}, d*_{l+q})."""
 
     def __init__(self, frame_len: int, n_freq: int = 0, m: int = 10, dt: float = 1.0,
                  orders=(2, 3, 4), n_channels: int = 1, window: str = "acg",
                  window_param: float = 0.14, precision: str = "fp32", schedule: str = "batched",
                  f_max: float = 0.0, combos2=None, combos3=None, combos4=None, interlaced: bool = False,
-                 estimator: str = "kstat", complex_signal: bool = False):
+                 estimator: str = "kstat", complex_signal: bool = False, s4_shift: int = 0):
         self._lib = L.load()
         self._handle = None
         cfg = L.ps_config()
@@ -98,6 +100,7 @@ class Plan:
         cfg.interlaced = 1 if interlaced else 0
         cfg.estimator = {"kstat": L.PS_EST_KSTAT, "natural": L.PS_EST_NATURAL}[estimator]
         cfg.complex_signal = 1 if complex_signal else 0
+        cfg.s4_shift = s4_shift
         self._keep = []
         for arity, combos in ((2, combos2), (3, combos3), (4, combos4)):
             n, arr, ptr = _flat(combos, arity)

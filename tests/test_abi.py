@@ -55,7 +55,7 @@ int main(void) {
   printf("ps_tune_report %zu\n", sizeof(ps_tune_report));
   P(ps_tuning, s3_frame_batch) P(ps_tune_report, cand) P(ps_tune_report, ms)
   P(ps_config, dt) P(ps_config, window) P(ps_config, n_combos4) P(ps_config, combos2) P(ps_config, combos4)
-  P(ps_config, interlaced) P(ps_config, estimator) P(ps_config, complex_signal) P(ps_config, reserved)
+  P(ps_config, interlaced) P(ps_config, estimator) P(ps_config, complex_signal) P(ps_config, s4_shift)
   P(ps_plan_info, grid)
   P(ps_record, n_samples) P(ps_record, dtype) P(ps_output, d_s4_err) P(ps_output, d_s1) P(ps_output, d_s1_err)
   P(ps_plan_info, f_max) P(ps_plan_info, sum_g) P(ps_plan_info, combos4)
@@ -127,7 +127,8 @@ def _cfg(**kw):
     (dict(estimator=2), L.PS_E_INVALID_ARG),
     (dict(interlaced=1, schedule=L.PS_SCHED_PER_CHUNK), L.PS_E_UNSUPPORTED),
     (dict(complex_signal=2), L.PS_E_INVALID_ARG),
-    (dict(reserved=1), L.PS_E_INVALID_ARG),
+    (dict(s4_shift=2), L.PS_E_UNSUPPORTED),             # planes need complex_signal
+    (dict(complex_signal=1, s4_shift=80), L.PS_E_INVALID_ARG),
     (dict(complex_signal=1, frame_len=8192, n_freq=100), L.PS_E_UNSUPPORTED),
 ])
 def test_plan_validation_rejects_before_device_work(kw, status):

@@ -885,6 +885,34 @@ def test_complex_channels_interlaced_and_errors(dev):
         assert st == L.PS_E_UNSUPPORTED
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_s4_plane_matches_oracle(dev, precision):
+    """S4 on the plane parallel to the cut shifted by q = 3 bins, a real record
+    given as complex: C4(a_{k+q}, a*_{k-q}, a_{l-q}, a*_{l+q}) on the signed grid
+    (the cross-channel kernels, full grids) equals the oracle's."""
+    say("S4 plane", precision)
+    N, Nf, m = 256, 30, 8
+    z = synth.ar2_chi2(N * m * 6 + 40, seed=171, dtype=np.float32).astype(np.complex64)
+    gpu = run_gpu(z, dev, frame_len=N, n_freq=Nf, m=m, precision=precision, complex_signal=True, s4_shift=3,
+                  orders=(2, 4))
+    ref = O.polyspectra_complex(z, N, Nf, m, orders=(2, 4), s4_shift=3, combos4=gpu["plan"]["combos4"])
+    compare(gpu, ref, keys=("s2", "s4"), label=f"plane-{precision}")
+
+
+def test_s4_plane_wide_shift_with_s3(dev):
+    """Two complex channels, q = -N_f (a wider stored bin range, so S3's third
+    factor sits at an offset column), S2, S3 and every S4 combination."""
+    say("S4 plane, wide shift, 2 channels")
+    N, Nf, m = 256, 20, 6
+    z = _complex_signal(N * m * 5 + 11, seed=172, N=N, channels=2).astype(np.complex64)
+    gpu = run_gpu(z, dev, frame_len=N, n_freq=Nf, m=m, n_channels=2, precision="bf16x3", complex_signal=True,
+                  s4_shift=-Nf)
+    assert len(gpu["plan"]["combos4"]) == 16
+    ref = O.polyspectra_complex(z, N, Nf, m, s4_shift=-Nf, combos2=gpu["plan"]["combos2"],
+                                combos3=gpu["plan"]["combos3"], combos4=gpu["plan"]["combos4"])
+    compare(gpu, ref, label="plane-wide-2ch")
+
+
 # ---------------------------------------------------------------- launch configuration (autotuner)
 def _tuning_case(dev):
     """Two channels (every S3/S4 orbit, so all four tile tables are used), a
