@@ -113,7 +113,9 @@ struct ps_plan_s {
     // column k' + col0; the transform runs at twice the frame length's log2.
     bool cplx = false;
     int Ng = 0, col0 = 0, jmax = 0, log2n_fft = 0;
-    int s4_shift = 0;       // S4 plane parallel to the cut (complex signals)    // second frame set shifted by N/2, spectra averaged
+    int s4_shift = 0;       // S4 plane parallel to the cut (complex signals)
+    // Frame lengths N = 2 pf 2^log2n (pf = 3, 5): prime-factor transform maps
+    int pf = 0, pf_c = 0, pf_d = 0;    // second frame set shifted by N/2, spectra averaged
     std::vector<int8_t> c2, c3, c4;
     double sum_g[5] = {0, 0, 0, 0, 0};
     int T = 0, TX = 0;
@@ -540,8 +542,23 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     if (cfg->n_channels < 1 || cfg->n_channels > 4)
         return fail(PS_E_INVALID_ARG, "n_channels must be 1..4");
     const int N = cfg->frame_len;
-    if (N < 2 || (N & (N - 1)))
-        return fail(PS_E_UNSUPPORTED, "frame_len %d is not a power of two", N);
+    // powers of two 256..8192, or 2 P 2^q with P = 3, 5 and 2^q = 128..1024 (768..6144)
+    int pf = 0, log2m2 = 0;
+    if (N >= 2 && (N & (N - 1))) {
+        for (int P : {3, 5}) {
+            if (N % (2 * P)) continue;
+            const int M2 = N / (2 * P);
+            if (M2 >= 128 && M2 <= 1024 && !(M2 & (M2 - 1))) {
+                pf = P;
+                while ((1 << log2m2) < M2) ++log2m2;
+            }
+        }
+        if (!pf || N > 8192) return fail(PS_E_UNSUPPORTED, "frame_len %d is not a power of two", N);
+        // The prime-factor transform (k_window_rfft_pf) is switched off: one
+        // of its launches ended in an illegal memory access whose cause has
+        // not been found (every access checks in bounds by emulation).
+        return fail(PS_E_UNSUPPORTED, "frame_len %d: prime-factor frame lengths are disabled", N);
+    }
     if (N < 256 || N > 8192) return fail(PS_E_UNSUPPORTED, "frame_len %d outside 256..8192", N);
     if (!(cfg->dt > 0) || !std::isfinite(cfg->dt)) return fail(PS_E_INVALID_ARG, "dt must be > 0");
     const int min_m = (cfg->orders & PS_ORDER_S4)   ? 4
@@ -586,7 +603,17 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
 
     auto* p = new ps_plan_s();
     p->N = N;
-    while ((1 << p->log2n) < N) ++p->log2n;
+    if (pf) {
+        p->pf = pf;
+        p->log2n = log2m2;
+        const int M2 = 1 << log2m2, M = pf * M2;
+        for (int c = 0; c < M; c += M2)
+            if (c % pf == 1) p->pf_c = c;                   // 0 mod M2, 1 mod P
+        for (int d = 0; d < M; d += pf)
+            if (d % M2 == 1) p->pf_d = d;                   // 0 mod P, 1 mod M2
+    } else {
+        while ((1 << p->log2n) < N) ++p->log2n;
+    }
     p->Nf = Nf;
     p->cplx = cfg->complex_signal != 0;
     p->Ng = p->cplx ? 2 * Nf - 1 : Nf;
@@ -656,15 +683,18 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     // (complex signals: the tables of a real transform of twice the frame
     // length, whose complex transform has the frame length; the first N2
     // entries are then unused)
-    const int N2 = 1 << p->log2n_fft;
+    // (prime-factor lengths: the unpack table of N entries, then the pass
+    // tables of the 2^q-point subsequence transforms)
+    const int tw_log2 = p->pf ? p->log2n + 1 : p->log2n_fft;
+    const int N2 = p->pf ? N : 1 << p->log2n_fft;
     std::vector<float2> tw;
-    tw.reserve(ps::fft_twiddle_count(p->log2n_fft));
+    tw.reserve(N2 + ps::fft_twiddle_count(tw_log2));
     for (int t = 0; t < N2; ++t) {
         const double ang = two_pi * t / N2;
         tw.push_back(make_float2((float)std::cos(ang), (float)std::sin(ang)));
     }
     // per-pass tables of the transform's later passes, [r][k]
-    const int R2 = ps::fft_radix2(p->log2n_fft), R3 = ps::fft_radix3(p->log2n_fft);
+    const int R2 = ps::fft_radix2(tw_log2), R3 = ps::fft_radix3(tw_log2);
     const int pass_r[2] = {R2, R3}, pass_ns[2] = {16, 16 * R2};
     for (int q = 0; q < 2; ++q)
         for (int r = 0; r < pass_r[q]; ++r)
@@ -900,6 +930,9 @@ ps_status ps_coefficients(ps_plan_t p, const ps_record* rec, float* d_coef, ps_s
     a.log2n = p->log2n_fft;
     a.cplx = p->cplx;
     a.jmax = p->jmax;
+    a.pf = p->pf;
+    a.pf_c = p->pf_c;
+    a.pf_d = p->pf_d;
     a.K = p->K;
     a.g = p->d_g;
     a.tw = p->d_tw;
@@ -1063,6 +1096,9 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
     fa.log2n = p->log2n_fft;
     fa.cplx = p->cplx;
     fa.jmax = p->jmax;
+    fa.pf = p->pf;
+    fa.pf_c = p->pf_c;
+    fa.pf_d = p->pf_d;
     fa.K = p->K;
     fa.g = p->d_g;
     fa.tw = p->d_tw;

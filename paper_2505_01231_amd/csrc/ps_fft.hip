@@ -298,6 +298,163 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_window_rfft(FftArgs a) {
     }
 }
 
+// Frame lengths N = 2 P M2 (P = 3 or 5, M2 a power of two, 128..1024): the
+// M = P M2 packed points are transformed by the prime-factor (Good-Thomas)
+// split.  With n = (M2 n1 + P n2) mod M and k = (C k1 + D k2) mod M, where
+// C = 0 mod M2, C = 1 mod P, D = 0 mod P, D = 1 mod M2, the +j-sign transform
+// factors exactly (no twiddles between the factors):
+//   X[k] = sum_{n1 < P} w_P^{n1 k1} Y_{n1}[k2],  Y_{n1} = M2-point transform of
+//   y_{n1}[n2] = x[(M2 n1 + P n2) mod M].
+// A frame takes P groups of M2/16 threads; group n1 runs the power-of-two
+// passes on its subsequence in its own LDS region, then every thread combines
+// P values per k2 (radix P) and the frame is unpacked as above.
+template <int P>
+__device__ __forceinline__ float2 root_p(int q) {      // exp(+2 pi j q / P), q < P
+    if constexpr (P == 3) {
+        constexpr float c = -0.5f, s = 0.86602540378443865f;
+        return q == 0 ? make_float2(1.f, 0.f) : (q == 1 ? make_float2(c, s) : make_float2(c, -s));
+    } else {
+        constexpr float c1 = 0.30901699437494742f, s1 = 0.95105651629515357f;
+        constexpr float c2 = -0.80901699437494742f, s2 = 0.58778525229247313f;
+        switch (q) {
+            case 1: return make_float2(c1, s1);
+            case 2: return make_float2(c2, s2);
+            case 3: return make_float2(c2, -s2);
+            case 4: return make_float2(c1, -s1);
+            default: return make_float2(1.f, 0.f);
+        }
+    }
+}
+
+template <int LOG2M2, int P>
+constexpr int pf_frames() {
+    return (kFftThreads / (P * ((1 << LOG2M2) / 16))) > 0 ? kFftThreads / (P * ((1 << LOG2M2) / 16)) : 1;
+}
+
+template <int LOG2M2, int P>
+__global__ __launch_bounds__((pf_frames<LOG2M2, P>() * P * ((1 << LOG2M2) / 16)))
+void k_window_rfft_pf(FftArgs a) {
+    constexpr int M2 = 1 << LOG2M2, T2 = M2 / 16, TP = P * T2, F = pf_frames<LOG2M2, P>();
+    constexpr int M = P * M2, N = 2 * M, SUB = M2 + M2 / 16;
+    constexpr int R2 = fft_radix2(LOG2M2 + 1), R3 = fft_radix3(LOG2M2 + 1);
+    constexpr int JMAX = (M2 + TP - 1) / TP;                 // k2 values per thread in the combine
+    __shared__ float2 lds[F * P * SUB];
+
+    const int fl = threadIdx.x / TP, tt = threadIdx.x % TP;
+    const int n1 = tt / T2, t2 = tt % T2;
+    float2* frame = lds + fl * P * SUB;
+    float2* s = frame + n1 * SUB;
+    const int64_t gf = a.g_lo + (int64_t)blockIdx.x * F + fl;
+    const bool live = gf < a.g_hi;
+    const int c = blockIdx.y;
+    RecDesc rec = a.single;
+    if (a.recs && live) {
+        int lo = 0, hi = a.n_recs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.recs[mid].frame0 <= gf) lo = mid;
+            else hi = mid - 1;
+        }
+        rec = a.recs[lo];
+    }
+    const int64_t off = c * rec.chan_stride + (gf - rec.frame0) * N;
+    const float2* __restrict__ g2 = reinterpret_cast<const float2*>(a.g);
+    const float2* __restrict__ tw = a.tw;
+
+    float2 v[16], w2[16], w3[16];
+    if constexpr (R2 > 0) pass_twiddles<LOG2M2, R2>(w2, t2, 16, tw + N);
+    // subsequence n1: packed points (M2 n1 + P n2) mod M, n2 = t2 + 16 T2 ... (16 per thread)
+    if (!live) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
+    } else {
+        int idx[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) idx[r] = (M2 * n1 + P * (t2 + r * T2)) % M;
+        float2 x[16];
+        if (rec.dtype == 0) {
+            const float* xf = static_cast<const float*>(rec.data) + off;
+            const bool vec = (reinterpret_cast<uintptr_t>(xf) % (2 * sizeof(float))) == 0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) x[r] = sample_pair(xf, idx[r], vec);
+        } else if (rec.dtype == 1) {
+            const double* xf = static_cast<const double*>(rec.data) + off;
+            const bool vec = (reinterpret_cast<uintptr_t>(xf) % (2 * sizeof(double))) == 0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) x[r] = sample_pair(xf, idx[r], vec);
+        } else {
+            const int16_t* xf = static_cast<const int16_t*>(rec.data) + off;
+            const bool vec = (reinterpret_cast<uintptr_t>(xf) % (2 * sizeof(int16_t))) == 0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) x[r] = sample_pair(xf, idx[r], vec);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const float2 w = g2[idx[r]];
+            v[r] = make_float2(w.x * x[r].x, w.y * x[r].y);
+        }
+    }
+
+    fft_pass<LOG2M2, 16, true>(v, w2, s, t2, 1);
+    if constexpr (R2 > 0) fft_pass<LOG2M2, R2, false>(v, w2, s, t2, 16);
+    if constexpr (R3 > 0) pass_twiddles<LOG2M2, R3>(w3, t2, 16 * R2, tw + N + 16 * R2);
+    if constexpr (R3 > 0) fft_pass<LOG2M2, R3, false>(v, w3, s, t2, 16 * R2);
+
+    // radix-P combine across the P subsequences, results kept in registers
+    float2 out[JMAX][P];
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j) {
+        const int k2 = tt + j * TP;
+        if (k2 >= M2) break;
+        float2 y[P];
+#pragma unroll
+        for (int r = 0; r < P; ++r) y[r] = frame[r * SUB + pad(k2)];
+#pragma unroll
+        for (int k1 = 0; k1 < P; ++k1) {
+            float2 acc = y[0];
+#pragma unroll
+            for (int r = 1; r < P; ++r) acc = cadd(acc, cmul(y[r], root_p<P>((r * k1) % P)));
+            out[j][k1] = acc;
+        }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j) {
+        const int k2 = tt + j * TP;
+        if (k2 >= M2) break;
+#pragma unroll
+        for (int k1 = 0; k1 < P; ++k1) frame[pad((a.pf_c * k1 + a.pf_d * k2) % M)] = out[j][k1];
+    }
+    lds_barrier();
+
+    if (!live) return;
+    constexpr int KMAX = (M + 1 + TP - 1) / TP;
+    const int K = a.K;
+    float2* o = a.out + c * a.out_chan_stride + (gf - a.out_g0) * K;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        const int k = tt + i * TP;
+        if (k >= K) break;
+        const float2 xk = frame[pad(k % M)];
+        const float2 xm = frame[pad((M - k) % M)];
+        const float er = 0.5f * (xk.x + xm.x);
+        const float ei = 0.5f * (xk.y - xm.y);
+        const float orr = 0.5f * (xk.y + xm.y);
+        const float oi = -0.5f * (xk.x - xm.x);
+        const float2 w = tw[k];
+        o[k] = make_float2(er + w.x * orr - w.y * oi, ei + w.x * oi + w.y * orr);
+    }
+}
+
+template <int LOG2M2, int P>
+hipError_t launch_pf(const FftArgs& a, hipStream_t st) {
+    constexpr int T2 = (1 << LOG2M2) / 16, F = pf_frames<LOG2M2, P>();
+    const int64_t n = a.g_hi - a.g_lo;
+    dim3 grid((unsigned)((n + F - 1) / F), a.n_channels);
+    k_window_rfft_pf<LOG2M2, P><<<grid, F * P * T2, 0, st>>>(a);
+    return hipGetLastError();
+}
+
 template <int LOG2N>
 hipError_t launch_n(const FftArgs& a, hipStream_t st) {
     constexpr int M = (1 << LOG2N) / 2, F = kFftThreads / (M / 16);
@@ -367,6 +524,19 @@ __global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64
 
 hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s) {
     if (a.g_hi <= a.g_lo || a.n_channels <= 0 || a.n_recs <= 0) return hipSuccess;
+    if (a.pf) {                 // N = 2 pf 2^log2n
+        const int key = a.pf * 16 + a.log2n;
+        switch (key) {
+            case 3 * 16 + 7: return launch_pf<7, 3>(a, s);
+            case 3 * 16 + 8: return launch_pf<8, 3>(a, s);
+            case 3 * 16 + 9: return launch_pf<9, 3>(a, s);
+            case 3 * 16 + 10: return launch_pf<10, 3>(a, s);
+            case 5 * 16 + 7: return launch_pf<7, 5>(a, s);
+            case 5 * 16 + 8: return launch_pf<8, 5>(a, s);
+            case 5 * 16 + 9: return launch_pf<9, 5>(a, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (a.log2n) {
         case 8: return launch_n<8>(a, s);
         case 9: return launch_n<9>(a, s);

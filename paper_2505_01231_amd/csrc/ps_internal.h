@@ -61,6 +61,9 @@ struct FftArgs {
     int64_t out_chan_stride;
     int dtype;              // common dtype of the records (launch template)
     int cplx, jmax;
+    // Frame lengths N = 2 pf 2^log2n (pf = 3 or 5; 0: N = 2^log2n): the
+    // prime-factor transform with output map k = (pf_c k1 + pf_d k2) mod M.
+    int pf, pf_c, pf_d;
 };
 hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s);
 
