@@ -31,6 +31,8 @@ Paper anchors (section / equation of the paper):
 * Averaging and error bars: Section 4.2.  The spectrum is the mean of the
   per-chunk estimates; Var = Np/(Np-1) (mean(x^2) - mean(x)^2) separately for
   the real and imaginary parts, sigma = sqrt(Var/Np).
+* Alternative S3 estimator: c3^(opt) of the closing remark of Section 4.1
+  (its reading is stated at c3opt3).
 * Negative controls: the natural (plug-in) estimator of Section 6 (all
   m-dependent prefactors set to one) and the incomplete fourth cumulant of
   Section 4.3 (eq. C4pyHOSA).
@@ -219,11 +221,39 @@ def incomplete4(x, y, z, w):
     return _mean(xc * yc * zc * wc)
 
 
+# Alternative third-order estimator ------------------------------------------
+
+
+def c3opt3(x, y, z):
+    """Section 4.1, closing remark on estimators other than the k-statistics:
+    c3^(opt), an estimator of C3 for variables of zero mean (Fourier
+    coefficients away from frequency zero), written multilinearly.
+
+    The univariate form given there is mean(x^3) - 3 (m-1)/(m+1) (x^2 x).
+    Reading: (x^2 x) is the average of x_i^2 x_j over distinct samples
+    i != j, the unbiased estimate of <x^2><x>, whose expectation is zero for
+    zero-mean x.  The estimator is then unbiased for zero-mean data, and
+    3 (m-1)/(m+1) is exactly the coefficient of minimum variance for Gaussian
+    data among all mean(x^3) - beta (x^2 x).  For three variables each
+    product term becomes its symmetrised form:
+        c3opt = mean(xyz) - (m-1)/(m+1) [U(xy, z) + U(xz, y) + U(yz, x)],
+        U(p, r) = average of p_i r_j over i != j.
+    Unlike the k-statistic it is biased where a mean is not zero."""
+    m = x.shape[-1]
+
+    def U(p, r):
+        return (np.sum(p, axis=-1) * np.sum(r, axis=-1) - np.sum(p * r, axis=-1)) / (m * (m - 1))
+
+    return _mean(x * y * z) - (m - 1) / (m + 1) * (U(x * y, z) + U(x * z, y) + U(y * z, x))
+
+
 ESTIMATORS = {
     "kstat": (kstat2, kstat3, kstat4),
     "factorized": (kstat2, kstat3, kstat4_factorized),
     "natural": (natural2, natural3, natural4),
     "incomplete": (natural2, natural3, incomplete4),
+    # S3 by c3^(opt); S2 and S4 by the k-statistics
+    "c3opt": (kstat2, c3opt3, kstat4),
 }
 
 

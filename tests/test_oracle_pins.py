@@ -261,6 +261,119 @@ def test_unbiased_at_small_m():
 
 
 # --------------------------------------------------------------------------
+# 4b. c3^(opt), the alternative third-order estimator (closing remark of
+#     Section 4.1)
+# --------------------------------------------------------------------------
+
+
+def test_c3opt_pair_averages_by_brute_force():
+    """The closed form of the averages over distinct samples i != j against
+    explicit loops, three complex variables and one real variable."""
+    rng = np.random.default_rng(51)
+    m = 5
+    x, y, z = (rng.standard_normal(m) + 1j * rng.standard_normal(m) for _ in range(3))
+    pairs = [(i, j) for i in range(m) for j in range(m) if i != j]
+    u = sum(x[i] * y[i] * z[j] + x[i] * z[i] * y[j] + y[i] * z[i] * x[j] for i, j in pairs) / len(pairs)
+    want = sum(x[i] * y[i] * z[i] for i in range(m)) / m - (m - 1) / (m + 1) * u
+    assert abs(O.c3opt3(x, y, z) - want) < 1e-13 * abs(want)
+    r = rng.standard_normal(m)
+    u1 = sum(r[i] ** 2 * r[j] for i, j in pairs) / len(pairs)
+    want1 = sum(v ** 3 for v in r) / m - 3 * (m - 1) / (m + 1) * u1
+    assert abs(O.c3opt3(r, r, r) - want1) < 1e-13 * max(1.0, abs(want1))
+
+
+def _zero_mean(values, probs):
+    vals = np.array(values, dtype=complex)
+    w = np.array([float(q) for q in probs])
+    return [tuple(v) for v in vals - (w[:, None] * vals).sum(axis=0)]
+
+
+@pytest.mark.parametrize("values,probs", [(REAL_VALUES, REAL_PROBS), (CPLX_VALUES, CPLX_PROBS)])
+@pytest.mark.parametrize("idx,m", [((0, 1, 2), 2), ((0, 1, 2), 3), ((1, 1, 3), 4), ((2, 2, 2), 5)])
+def test_c3opt_unbiased_for_zero_mean(values, probs, idx, m):
+    """Exact expectation over every m-tuple: c3^(opt) equals C3 when every
+    variable has mean zero, already at m = 2, and misses it when the means are
+    left in (the k-statistic does not)."""
+    zero = _zero_mean(values, probs)
+    got = _expected_estimator(O.c3opt3, zero, probs, idx, m)
+    want = complex(_joint_cumulant(zero, probs, idx))
+    assert abs(got - want) <= 1e-11 * max(1.0, abs(want)), (got, want)
+    biased = _expected_estimator(O.c3opt3, values, probs, idx, m)
+    want_b = complex(_joint_cumulant(values, probs, idx))
+    assert abs(biased - want_b) > 1e-3 * max(1.0, abs(want_b))
+
+
+@pytest.mark.parametrize("m", [3, 5, 6])
+def test_c3opt_coefficient_minimises_gaussian_variance(m):
+    """Among the unbiased estimators mean(x^3) - beta (x^2 x) of a zero-mean
+    variable, beta = 3(m-1)/(m+1) has the least variance for Gaussian x.
+    Gaussian expectations are exact from the 4-node Gauss-Hermite rule (exact
+    to degree 7 in each sample; these statistics reach degree 6)."""
+    nodes, weights = np.polynomial.hermite_e.hermegauss(4)
+    weights = weights / weights.sum()
+    tup = np.array(list(itertools.product(range(4), repeat=m)))
+    x = nodes[tup]                                            # [T, m]
+    p = np.prod(weights[tup], axis=1)
+    t1 = np.mean(x ** 3, axis=1)
+    pairs = [(i, j) for i in range(m) for j in range(m) if i != j]
+    u = sum(x[:, i] ** 2 * x[:, j] for i, j in pairs) / len(pairs)
+    # Var(t1 - beta u) = a - 2 b beta + c beta^2 (t1 and u have mean zero)
+    a, b, c = np.sum(p * t1 * t1), np.sum(p * t1 * u), np.sum(p * u * u)
+    beta = b / c
+    assert abs(beta - 3 * (m - 1) / (m + 1)) < 1e-12
+    est = O.c3opt3(x, x, x)
+    assert np.max(np.abs(est - (t1 - beta * u))) < 1e-12
+    var_opt = np.sum(p * est ** 2)
+    var_k3 = np.sum(p * O.kstat3(x, x, x) ** 2)
+    # textbook normal-sample variances: Var k3 = 6m/((m-1)(m-2)), Var mean(x^3) = 15/m;
+    # the minimum a - b^2/c works out to 6(m+4)/(m(m+1))
+    assert abs(var_k3 - 6 * m / ((m - 1) * (m - 2))) < 1e-10
+    assert abs(a - 15 / m) < 1e-10
+    assert abs(var_opt - 6 * (m + 4) / (m * (m + 1))) < 1e-10
+    assert var_opt < min(var_k3, a)
+    if m >= 5:
+        # the k-statistic beats the plain third moment for Gaussian data
+        assert var_k3 < a
+
+
+@pytest.mark.parametrize("m", [2, 3, 10])
+def test_c3opt_spectrum_unbiased_for_white_chi2(m):
+    """White chi-square(1) noise minus its mean: S3 = kappa_3 = 8 at every
+    point (dt = 1), and every Fourier coefficient has mean zero, so c3^(opt)
+    is unbiased on the whole grid, down to m = 2.  S2 and S4 stay the
+    k-statistics (identical to the default estimator)."""
+    N, Nf = 16, 4
+    rng = np.random.default_rng(61 + m)
+    w = rng.standard_normal(N * 24000)
+    z = w * w - 1.0
+    out = O.polyspectra(z, N, Nf, m, window_kind="hann_periodic", orders=(2, 3), estimator="c3opt")
+    zs = _zscores(out["s3"][0], out["s3_err"][0], 8.0, imag=True)
+    assert np.max(np.abs(zs)) < 4.5, np.max(np.abs(zs))
+    if m >= 3:
+        ref = O.polyspectra(z, N, Nf, m, window_kind="hann_periodic", orders=(2, 3))
+        assert np.array_equal(out["s2"], ref["s2"])
+        assert not np.allclose(out["s3"], ref["s3"])
+
+
+def test_c3opt_biased_by_a_nonzero_mean():
+    """With the noise's mean left in, a_0 and a_1 (window leakage of the
+    periodic Hann window) have nonzero means: c3^(opt) is far off at (0, 0),
+    still unbiased where k, l, k + l avoid bins 0 and 1, and the k-statistic
+    is unbiased everywhere."""
+    N, Nf, m = 16, 4, 10
+    rng = np.random.default_rng(71)
+    w = rng.standard_normal(N * 24000)
+    z = w * w
+    out = O.polyspectra(z, N, Nf, m, window_kind="hann_periodic", orders=(3,), estimator="c3opt")
+    ref = O.polyspectra(z, N, Nf, m, window_kind="hann_periodic", orders=(3,))
+    s, e = out["s3"][0], out["s3_err"][0]
+    assert abs(s[0, 0].real - 8.0) / e[0, 0, 0] > 8
+    far = np.ix_([2, 3], [2, 3])
+    assert np.max(np.abs(_zscores(s[far], e[far], 8.0))) < 4.5
+    assert np.max(np.abs(_zscores(ref["s3"][0], ref["s3_err"][0], 8.0))) < 4.5
+
+
+# --------------------------------------------------------------------------
 # 5. Linear process: exact finite-window expectations (multilinearity)
 # --------------------------------------------------------------------------
 
