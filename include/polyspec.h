@@ -63,7 +63,7 @@ typedef enum ps_dtype {
     PS_C64 = 3,   /* complex: interleaved float32 (re, im); plans with complex_signal = 1 */
     PS_C128 = 4   /* complex: interleaved float64 */
 } ps_dtype;
-typedef enum ps_estimator { PS_EST_KSTAT = 0, PS_EST_NATURAL = 1 } ps_estimator;
+typedef enum ps_estimator { PS_EST_KSTAT = 0, PS_EST_NATURAL = 1, PS_EST_C3OPT = 2 } ps_estimator;
 
 /* Window g_i, i = 0..N-1.  HANN: symmetric sin^2(pi i/(N-1)); HANN_PERIODIC:
  * sin^2(pi i/N); ACG: the approximate confined Gaussian of Appendix B with
@@ -140,7 +140,15 @@ typedef struct ps_config {
 /* Cumulant estimator per chunk.  PS_EST_KSTAT: the unbiased k-statistics of
  * Section 4.1.  PS_EST_NATURAL: the natural (plug-in) estimator of Section 6,
  * the cumulant's moment expression with sample means (biased by O(1/m); for
- * comparisons).  S1 (the mean) is the same under both. */
+ * comparisons).  PS_EST_C3OPT: S3 by c3^(opt), the estimator of the closing
+ * remark of Section 4.1 for zero-mean data, symmetrised over the three
+ * factors: mean(xyz) - (m-1)/(m+1) [U(xy,z) + U(xz,y) + U(yz,x)], U(p, r) the
+ * average of p_i r_j over distinct frames i != j; of least variance for
+ * Gaussian-dominated data, unbiased where every factor has mean zero (away
+ * from bin 0 and the bins the window leaks a mean into) and biased elsewhere;
+ * S3 then needs m >= 2, and S2 and S4 keep the k-statistics.  It costs one
+ * more row per chunk in S3 and C * chunks * (m + 1) * K * 8 bytes of
+ * workspace.  S1 (the mean) is the same under all. */
 /* Interlaced windows (Section 3): the centre of a window weighs the signal more
  * than its edges; the same spectra computed on windows shifted by T/2 weigh it
  * the other way.  With interlaced = 1 every record (or streamer window) is

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_PKG, "libpolyspec.so")
 
 PS_OK, PS_E_INVALID_ARG, PS_E_UNSUPPORTED, PS_E_WORKSPACE, PS_E_HIP, PS_E_INTERNAL = range(6)
 PS_F32, PS_F64, PS_I16, PS_C64, PS_C128 = 0, 1, 2, 3, 4
-PS_EST_KSTAT, PS_EST_NATURAL = 0, 1
+PS_EST_KSTAT, PS_EST_NATURAL, PS_EST_C3OPT = 0, 1, 2
 PS_WIN_HANN, PS_WIN_HANN_PERIODIC, PS_WIN_ACG = 0, 1, 2
 PS_PREC_FP32, PS_PREC_BF16X3, PS_PREC_FP16X2S = 0, 1, 2
 PS_SCHED_BATCHED, PS_SCHED_PER_CHUNK = 0, 1

@@ -142,6 +142,7 @@ struct ps_plan_s {
     std::vector<Timed> timed;
 
     bool has(int order) const { return (orders >> order) & 1u; }
+    bool c3opt() const { return estimator == PS_EST_C3OPT && has(3); }
     int n2() const { return has(2) ? (int)c2.size() / 2 : 0; }
     int n3() const { return has(3) ? (int)c3.size() / 3 : 0; }
     int n4() const { return has(4) ? (int)c4.size() / 4 : 0; }
@@ -243,8 +244,9 @@ struct Batch {
     std::vector<ps::RecDesc> rd;
     int64_t F_tot = 0, chunks_tot = 0;
     int64_t coef_rows = 0;          // frames resident per channel in the coefficient region
+    int64_t coef3_rows = 0;         // c3^(opt): S3 rows per channel (m + 1 per chunk)
     std::vector<Group> groups;
-    size_t off_coef = 0, off_tab = 0, off_part = 0, off_s1 = 0, total = 0;
+    size_t off_coef = 0, off_coef3 = 0, off_tab = 0, off_part = 0, off_s1 = 0, total = 0;
     size_t tab_bytes = 0;
     int64_t part_doubles = 0;
 };
@@ -267,7 +269,10 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
     const bool nat = p->estimator == PS_EST_NATURAL;
     const double c4a = nat ? m : m * (m + 1.0);
     const double scale2 = dt / ((nat ? m : m - 1) * p->sum_g[2]);
-    const double scale3 = dt * dt * (nat ? 1.0 / m : m / ((double)(m - 1) * (m - 2))) / p->sum_g[3];
+    // c3^(opt): the S3 sum over the m + 1 rows of each chunk times (m+4)/((m+1) m)
+    const bool opt3 = p->c3opt();
+    const double c3f = opt3 ? (m + 4.0) / ((m + 1.0) * m) : nat ? 1.0 / m : m / ((double)(m - 1) * (m - 2));
+    const double scale3 = dt * dt * c3f / p->sum_g[3];
     const double scale4 = dt * dt * dt * c4a / ((nat ? (double)m * m : (double)(m - 1) * (m - 2) * (m - 3)) * p->sum_g[4]);
     B.stride = p->interlaced ? 2 : 1;
     const int n_int = n * B.stride;
@@ -293,6 +298,7 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
         d.pad = 0;
     }
     B.coef_rows = per_chunk ? m : B.F_tot;
+    B.coef3_rows = opt3 ? (per_chunk ? 1 : B.chunks_tot) * (m + 1) : 0;
 
     // groups (interlaced windows: batched schedule only)
     if (per_chunk) {
@@ -382,6 +388,7 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 sg.n_tiles = p->n_tiles[sg.tiles];
                 sg.blocks = seg_blocks(sg.n_tiles, q.Np, L3, per_chunk);
                 for (int j = 0; j < 3; ++j) sg.ch[j] = p->c3[3 * i + j];
+                if (opt3) sg.coef = q.chunk0 * (m + 1) * K;
                 sg.part = part;
                 part += ps::Sched{sg.n_tiles, q.Np, sg.blocks}.n_slots() * 4 * TT;
                 sg.out = o && o->d_s3 ? o->d_s3 + 2 * i * nf2 : nullptr;
@@ -424,6 +431,8 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
     size_t off = 0;
     B.off_coef = off;
     off = align256(off + (size_t)p->C * B.coef_rows * K * sizeof(float2));
+    B.off_coef3 = off;
+    off = align256(off + (size_t)p->C * B.coef3_rows * K * sizeof(float2));
     B.off_tab = off;
     off = align256(off + B.tab_bytes);
     B.off_part = off;
@@ -561,8 +570,9 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     }
     if (N < 256 || N > 8192) return fail(PS_E_UNSUPPORTED, "frame_len %d outside 256..8192", N);
     if (!(cfg->dt > 0) || !std::isfinite(cfg->dt)) return fail(PS_E_INVALID_ARG, "dt must be > 0");
+    // c3^(opt) (S3 only) is defined from m = 2
     const int min_m = (cfg->orders & PS_ORDER_S4)   ? 4
-                      : (cfg->orders & PS_ORDER_S3) ? 3
+                      : (cfg->orders & PS_ORDER_S3) ? (cfg->estimator == PS_EST_C3OPT ? 2 : 3)
                       : (cfg->orders & PS_ORDER_S2) ? 2
                                                     : 1;
     if (cfg->m < min_m) return fail(PS_E_INVALID_ARG, "m = %d < %d (k-statistic denominator)", cfg->m, min_m);
@@ -577,7 +587,7 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     if (cfg->schedule != PS_SCHED_BATCHED && cfg->schedule != PS_SCHED_PER_CHUNK)
         return fail(PS_E_INVALID_ARG, "unknown schedule %d", cfg->schedule);
     if (cfg->interlaced != 0 && cfg->interlaced != 1) return fail(PS_E_INVALID_ARG, "interlaced must be 0 or 1");
-    if (cfg->estimator != PS_EST_KSTAT && cfg->estimator != PS_EST_NATURAL)
+    if (cfg->estimator != PS_EST_KSTAT && cfg->estimator != PS_EST_NATURAL && cfg->estimator != PS_EST_C3OPT)
         return fail(PS_E_INVALID_ARG, "unknown estimator %d", cfg->estimator);
     if (cfg->interlaced && cfg->schedule != PS_SCHED_BATCHED)
         return fail(PS_E_UNSUPPORTED, "interlaced windows need the batched schedule");
@@ -1019,7 +1029,14 @@ ps_status launch_moments(ps_plan_t p, const Batch& B, const Group& G, char* ws, 
     }
     if (G.s3.n_items) {
         StageTimer t(p, st, 3);
-        PS_HIP(ps::launch_s3(batch_args(p, B, G.s3, ws, tab, per_chunk, win_lo, win_hi, accumulate), st));
+        ps::BatchArgs a = batch_args(p, B, G.s3, ws, tab, per_chunk, win_lo, win_hi, accumulate);
+        if (p->c3opt()) {
+            // the c3^(opt) rows: m shifted frames and one mean row per chunk
+            a.coef = reinterpret_cast<const float2*>(ws + B.off_coef3);
+            a.coef_chan_stride = B.coef3_rows * p->K;
+            a.m = p->m + 1;
+        }
+        PS_HIP(ps::launch_s3(a, st));
     }
     if (G.s4s.n_items) {
         StageTimer t(p, st, 4);
@@ -1114,6 +1131,13 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
     ca.s1_cs = B.chunks_tot;
     ca.s1_chunk0 = 0;
     ca.s1_col = p->jmax;
+    if (p->c3opt()) {
+        const double alpha = 4.0 / (m + 4.0);
+        ca.out3 = reinterpret_cast<float2*>(ws + B.off_coef3);
+        ca.out3_cs = B.coef3_rows * p->K;
+        ca.alpha = (float)alpha;
+        ca.mu = (float)std::cbrt(m * ((4.0 - 2.0 * m) / (m + 4.0) - alpha * alpha * alpha));
+    }
     ps_status s = PS_OK;
 
     if (p->schedule != PS_SCHED_PER_CHUNK) {

@@ -472,21 +472,41 @@ hipError_t launch_n(const FftArgs& a, hipStream_t st) {
 // a_k(f) -= (1/m) sum_{f' in chunk} a_k(f'), in place, one thread per (chunk, k).
 // Chunks of up to kCentreRegs frames stay in registers between the mean and
 // the subtraction, so each coefficient is read from HBM once.
+//
+// For the c3^(opt) estimator of S3 (Section 4.1) the same pass also writes the
+// rows S3 multiplies: with x_f, y_f, z_f the chunk's three factors, x' = x - mean
+// and P = sum over the three pairs of (1/m) sum_f x'_f y'_f times the third
+// factor's mean, R = the product of the three means,
+//   c3opt = ((m+4) M3' + 4 P + (4 - 2m) R) / (m + 1),  M3' = (1/m) sum x'y'z'.
+// Since sum_f x'_f = 0, the rows x'_f + alpha mean with alpha = 4/(m+4) give
+//   (1/m) sum_f (x' + alpha xm)(y' + alpha ym)(z' + alpha zm) = M3' + alpha P + alpha^3 R,
+// and one more row mu mean per chunk, mu^3 = m ((4 - 2m)/(m+4) - alpha^3), adds
+// the rest of R: the plain S3 sum over the m + 1 rows, times (m+4)/((m+1) m),
+// is c3opt.
 constexpr int kCentreRegs = 16;
 
 // Grid: x = chunk * kblocks + (256-wide k block), y = channel (the chunk count
 // can exceed the 65536 limit of the y and z grid dimensions).
 __global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64_t coef_cs, int K, int m,
                                                 int kblocks, float2* __restrict__ s1, int64_t s1_cs,
-                                                int64_t s1_chunk0, int s1_col) {
+                                                int64_t s1_chunk0, int s1_col, float2* __restrict__ out3,
+                                                int64_t out3_cs, float alpha, float mu) {
     const int64_t chunk = blockIdx.x / kblocks;
     const int k = (int)(blockIdx.x - chunk * kblocks) * 256 + threadIdx.x;
     if (k >= K) return;
     float2* p = coef + blockIdx.y * coef_cs + chunk * m * K + k;
+    // c3^(opt): the chunk's rows for S3, frames shifted by alpha mean, then mu mean
+    float2* q = out3 ? out3 + blockIdx.y * out3_cs + chunk * (m + 1) * K + k : nullptr;
     const float inv = 1.0f / (float)m;
     // S1: the chunk's mean of a_0 (real for a real signal)
     auto keep_mean = [&](float mr, float mi) {
         if (s1 && k == s1_col) s1[blockIdx.y * s1_cs + s1_chunk0 + chunk] = make_float2(mr, mi);
+        if (q) q[(int64_t)m * K] = make_float2(mu * mr, mu * mi);
+    };
+    auto put = [&](int f, float2 v, float mr, float mi) {
+        const float2 c = make_float2(v.x - mr, v.y - mi);
+        p[(int64_t)f * K] = c;
+        if (q) q[(int64_t)f * K] = make_float2(fmaf(alpha, mr, c.x), fmaf(alpha, mi, c.y));
     };
     if (m <= kCentreRegs) {
         float2 v[kCentreRegs];
@@ -503,7 +523,7 @@ __global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64
         keep_mean(mr, mi);
 #pragma unroll
         for (int f = 0; f < kCentreRegs; ++f)
-            if (f < m) p[(int64_t)f * K] = make_float2(v[f].x - mr, v[f].y - mi);
+            if (f < m) put(f, v[f], mr, mi);
         return;
     }
     float sr = 0.f, si = 0.f;
@@ -514,10 +534,7 @@ __global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64
     }
     const float mr = sr * inv, mi = si * inv;
     keep_mean(mr, mi);
-    for (int f = 0; f < m; ++f) {
-        const float2 v = p[(int64_t)f * K];
-        p[(int64_t)f * K] = make_float2(v.x - mr, v.y - mi);
-    }
+    for (int f = 0; f < m; ++f) put(f, p[(int64_t)f * K], mr, mi);
 }
 
 }  // namespace
@@ -555,7 +572,7 @@ hipError_t launch_centre(const CentreArgs& a, hipStream_t s) {
     if (nx > 0x7fffffff) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)nx, a.n_channels);
     k_centre<<<grid, 256, 0, s>>>(a.coef, a.coef_chan_stride, a.K, a.m, kblocks, a.s1, a.s1_cs, a.s1_chunk0,
-                                  a.s1_col);
+                                  a.s1_col, a.out3, a.out3_cs, a.alpha, a.mu);
     return hipGetLastError();
 }
 

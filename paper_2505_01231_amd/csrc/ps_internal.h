@@ -94,6 +94,12 @@ struct CentreArgs {
     float2* s1;
     int64_t s1_cs, s1_chunk0;
     int s1_col;
+    // c3^(opt) rows for S3 (null: none): per chunk the m frames shifted by
+    // alpha times the chunk mean, a - (1 - alpha) mean, then one row mu mean;
+    // [C][n_chunks * (m + 1)][K]
+    float2* out3;
+    int64_t out3_cs;
+    float alpha, mu;
 };
 hipError_t launch_centre(const CentreArgs& a, hipStream_t s);
 

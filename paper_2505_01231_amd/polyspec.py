@@ -71,7 +71,10 @@ class Plan:
     spectra of the frames starting at sample 0 and of the frames starting half a
     frame later (Section 3's interlaced windows; batched schedule only).
     ``estimator="natural"`` selects the biased plug-in estimator of Section 6
-    instead of the k-statistics (for comparisons).  ``complex_signal=True``
+    instead of the k-statistics (for comparisons); ``estimator="c3opt"``
+    computes S3 by c3^(opt) (Section 4.1; least variance for zero-mean,
+    Gaussian-dominated coefficients, m >= 2) and keeps the k-statistics for S2
+    and S4.  ``complex_signal=True``
     takes complex64 / complex128 records and returns every spectrum on the
     signed grid of ``grid`` = 2 N_f - 1 points per axis (index k + N_f - 1).
     ``s4_shift=q`` (complex plans) computes S4 on the plane parallel to the cut,
@@ -98,7 +101,7 @@ class Plan:
         cfg.precision = _PRECISION[precision]
         cfg.schedule = _SCHEDULE[schedule]
         cfg.interlaced = 1 if interlaced else 0
-        cfg.estimator = {"kstat": L.PS_EST_KSTAT, "natural": L.PS_EST_NATURAL}[estimator]
+        cfg.estimator = {"kstat": L.PS_EST_KSTAT, "natural": L.PS_EST_NATURAL, "c3opt": L.PS_EST_C3OPT}[estimator]
         cfg.complex_signal = 1 if complex_signal else 0
         cfg.s4_shift = s4_shift
         self._keep = []

@@ -125,7 +125,9 @@ def _cfg(**kw):
     (dict(schedule=4), L.PS_E_INVALID_ARG),
     (dict(n_freq=0, f_max=-1.0), L.PS_E_INVALID_ARG),
     (dict(interlaced=2), L.PS_E_INVALID_ARG),
-    (dict(estimator=2), L.PS_E_INVALID_ARG),
+    (dict(estimator=3), L.PS_E_INVALID_ARG),
+    (dict(estimator=L.PS_EST_C3OPT, m=3), L.PS_E_INVALID_ARG),        # c3^(opt) leaves S4 at m >= 4
+    (dict(estimator=L.PS_EST_C3OPT, m=1, orders=L.PS_ORDER_S3), L.PS_E_INVALID_ARG),
     (dict(interlaced=1, schedule=L.PS_SCHED_PER_CHUNK), L.PS_E_UNSUPPORTED),
     (dict(complex_signal=2), L.PS_E_INVALID_ARG),
     (dict(s4_shift=2), L.PS_E_UNSUPPORTED),             # planes need complex_signal

@@ -763,6 +763,66 @@ def test_natural_estimator_cross_channels(dev, precision):
     compare(gpu, ref, label=f"natural-2ch-{precision}")
 
 
+# ---------------------------------------------------------------- c3^(opt) (Section 4.1)
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_c3opt_matches_oracle(dev, precision):
+    """estimator="c3opt": S3 by c3^(opt) (the S3 kernel over m shifted frames
+    and one mean row per chunk) equals the oracle's direct formula; S2 and S4
+    are still the k-statistics."""
+    say("c3opt", precision)
+    N, Nf, m = 256, 50, 10
+    z = synth.ar2_chi2(N * m * 12 + 70, seed=181, dtype=np.float32)
+    gpu = run_gpu(z, dev, frame_len=N, n_freq=Nf, m=m, precision=precision, estimator="c3opt")
+    ref = O.polyspectra(z, N, Nf, m, estimator="c3opt")
+    compare(gpu, ref, label=f"c3opt-{precision}")
+    kst = O.polyspectra(z, N, Nf, m, orders=(3,))
+    assert rel_err(gpu["s3"], kst["s3"]) > 1e-3
+
+
+@pytest.mark.parametrize("m,schedule", [(2, "batched"), (2, "per_chunk"), (17, "batched"), (17, "per_chunk")])
+def test_c3opt_channels_small_and_large_m(dev, m, schedule):
+    """Two f64 channels with a mean offset (every S3 orbit, bias at bin 0 kept
+    as the formula gives it), m = 2 (below the k-statistic's minimum) and
+    m = 17 (the centring pass's loop form), in both schedules."""
+    say("c3opt, 2 channels", m, schedule)
+    N, Nf = 256, 24
+    s = synth.ar2_chi2(N * m * 9 + 33, seed=182, r=0.9, dtype=np.float64)
+    z = np.stack([s[:-5] + 0.4, s[5:] ** 2 - 0.5])
+    gpu = run_gpu(z, dev, frame_len=N, n_freq=Nf, m=m, n_channels=2, orders=(2, 3), estimator="c3opt",
+                  schedule=schedule, window="hann")
+    ref = O.polyspectra(z, N, Nf, m, orders=(2, 3), window_kind="hann", estimator="c3opt",
+                        combos2=gpu["plan"]["combos2"], combos3=gpu["plan"]["combos3"])
+    compare(gpu, ref, keys=("s2", "s3"), label=f"c3opt-2ch-m{m}-{schedule}")
+
+
+def test_c3opt_complex_interlaced_sequential(dev):
+    """c3^(opt) on the complex path (signed grid), with interlaced windows, and
+    per chunk (sequential spectra) against the oracle."""
+    from paper_2505_01231_amd import Plan
+    say("c3opt complex / interlaced / sequential")
+    N, Nf, m = 256, 30, 8
+    zc = _complex_signal(N * m * 6 + 20, seed=183, N=N).astype(np.complex64)
+    gpu = run_gpu(zc, dev, frame_len=N, n_freq=Nf, m=m, complex_signal=True, orders=(2, 3), estimator="c3opt")
+    ref = O.polyspectra_complex(zc, N, Nf, m, orders=(2, 3), estimator="c3opt")
+    compare(gpu, ref, keys=("s2", "s3"), label="c3opt-complex")
+    z = synth.ar2_chi2(N * m * 7 + 90, seed=184, dtype=np.float32)
+    with Plan(frame_len=N, n_freq=Nf, m=m, precision="bf16x3", interlaced=True, estimator="c3opt") as p:
+        out = p.execute(torch.from_numpy(z).to(dev))
+        torch.cuda.synchronize()
+        ref = O.polyspectra_interlaced(z, N, Nf, m, estimator="c3opt")
+        for key in ("s2", "s3", "s4"):
+            g = torch.view_as_complex(getattr(out, key)).cpu().numpy()
+            assert rel_err(g, ref[key]) <= TOL, (key, rel_err(g, ref[key]))
+            assert rel_err(getattr(out, key + "_err").cpu().numpy(), ref[key + "_err"]) <= TOL, key
+    ref = O.polyspectra(z, N, Nf, m, orders=(3,), estimator="c3opt", return_chunks=True)
+    with Plan(frame_len=N, n_freq=Nf, m=m, orders=(3,), estimator="c3opt") as p:
+        seq = p.sequential(torch.from_numpy(z).to(dev), chunk_lo=1, n_chunks=3)
+        torch.cuda.synchronize()
+        for i in range(3):
+            g = torch.view_as_complex(seq.s3[i]).cpu().numpy()
+            assert rel_err(g, ref["chunks3"][1 + i]) <= TOL, i
+
+
 # ---------------------------------------------------------------- full frequency plane (Section 9)
 def test_full_plane_matches_direct_evaluation(dev):
     """ps_full_plane gathers one combination's S2 / S3 / S4 on the signed grid
