@@ -1257,14 +1257,21 @@ hipError_t launch_s2(const BatchArgs& a, hipStream_t s) {
 }
 
 // Frame batch of the S3 kernel: 10 when m is a multiple of 10 or below it
-// (the default m = 10 fits one batch), 16 otherwise.
+// (the default m = 10 fits one batch), 11 for multiples of 11 (c3^(opt) adds
+// a mean row to chunks of 10 frames), 16 otherwise.
 bool s3_small_batch(int m) { return m <= kFrameBatchSmall || m % kFrameBatchSmall == 0; }
+constexpr int kFrameBatchRow = 11;
 
 hipError_t launch_s3(const BatchArgs& a, hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;
-    const int fb = a.s3_fb ? a.s3_fb : (s3_small_batch(a.m) ? kFrameBatchSmall : kFrameBatch);
+    const int fb = a.s3_fb ? a.s3_fb
+                   : s3_small_batch(a.m) ? kFrameBatchSmall
+                   : (a.m % kFrameBatchRow == 0) ? kFrameBatchRow
+                                                 : kFrameBatch;
     if (fb == kFrameBatchSmall)
         k_s3<kFrameBatchSmall><<<item_grid(a), kS3Threads, 0, s>>>(a);
+    else if (fb == kFrameBatchRow)
+        k_s3<kFrameBatchRow><<<item_grid(a), kS3Threads, 0, s>>>(a);
     else
         k_s3<kFrameBatch><<<item_grid(a), kS3Threads, 0, s>>>(a);
     return hipGetLastError();
