@@ -399,6 +399,17 @@ def main(argv=None):
     if cpu:
         log(f"cpu baseline {cpu['value']:.3e} samples/s")
 
+    # Achieved HBM rates of the bandwidth-bound stages from their algorithmic
+    # bytes per step: the FFT reads the samples of every full chunk and writes
+    # K = 2 N_f - 1 complex FP32 coefficients per frame; the centring reads and
+    # writes every coefficient; S2 reads the first N_f columns.
+    K_COEF = 2 * NF - 1
+    alg_bytes = {"fft": 4 * n_frames * N + 8 * K_COEF * n_frames, "mean": 16 * K_COEF * n_frames,
+                 "s2": 8 * NF * n_frames}
+    stage_rates = {f"{k}_hbm_gbps": (b / (stage_ms[k] * 1e-3) / 1e9 if stage_ms.get(k) else None)
+                   for k, b in alg_bytes.items()}
+    stage_rates.update({"algorithmic_bytes_per_step": alg_bytes, "hbm_peak_gbps": 8000.0})
+
     line = {
         "metric": "input samples/sec for S2+S3+S4 at N_f=2048; mixed vs FP32 at <=1e-5 rel err; MFMA%",
         "value": value,
@@ -437,6 +448,7 @@ def main(argv=None):
         "batching": batching,
         "streaming": streaming,
         "stage_ms_per_step": stage_ms,
+        "stage_rates": stage_rates,
     }
     print(json.dumps(line), flush=True)
     plan.close()
