@@ -823,6 +823,45 @@ def test_c3opt_complex_interlaced_sequential(dev):
             assert rel_err(g, ref["chunks3"][1 + i]) <= TOL, i
 
 
+def test_c3opt_graph_and_streamer(dev):
+    """c3^(opt) through a captured graph (three replays, each bit-identical to
+    the eager execute) and through the streamer's multi-window pushes (each
+    window's spectra equal a single execute of that window)."""
+    from paper_2505_01231_amd import Plan, Streamer
+    say("c3opt graph / streamer")
+    N, Nf, m = 512, 64, 10
+    zs = [synth.ar2_chi2(N * m * n + 77, seed=185 + n, dtype=np.float32) for n in (2, 3)]
+    xs = [torch.from_numpy(z).to(dev) for z in zs]
+    with Plan(frame_len=N, n_freq=Nf, m=m, precision="bf16x3", estimator="c3opt") as p:
+        g = p.graph(xs)
+        for rep in range(3):
+            outs = g.launch()
+            torch.cuda.synchronize()
+            eager = p.execute(xs)
+            torch.cuda.synchronize()
+            for o, e in zip(outs, eager):
+                for key in ("s2", "s3", "s4", "s2_err", "s3_err", "s4_err"):
+                    a, b = getattr(o, key).cpu().numpy(), getattr(e, key).cpu().numpy()
+                    assert np.array_equal(a, b, equal_nan=True), (rep, key)
+        g.close()
+        ref = O.polyspectra(zs[1], N, Nf, m, estimator="c3opt")
+        got = torch.view_as_complex(eager[1].s3).cpu().numpy()
+        assert rel_err(got, ref["s3"]) <= TOL
+        W = N * m * 3
+        z = synth.modulated_ar2(4 * W, seed=186, total=4 * W, r=0.9)
+        st = Streamer(p, W, dtype=torch.float32, depth=2, windows_per_push=2)
+        for w0 in (0, 2):
+            host = torch.from_numpy(z[w0 * W:(w0 + 2) * W].copy()).pin_memory()
+            outs = [p.allocate_outputs(dev) for _ in range(2)]
+            st.wait(st.push(host, outs))
+            ref = p.execute([torch.from_numpy(z[(w0 + i) * W:(w0 + i + 1) * W].copy()).to(dev) for i in range(2)])
+            torch.cuda.synchronize()
+            for i in range(2):
+                for k in ("s2", "s3", "s4", "s3_err"):
+                    assert np.array_equal(getattr(outs[i], k).cpu().numpy(), getattr(ref[i], k).cpu().numpy()), (w0, i, k)
+        st.close()
+
+
 # ---------------------------------------------------------------- full frequency plane (Section 9)
 def test_full_plane_matches_direct_evaluation(dev):
     """ps_full_plane gathers one combination's S2 / S3 / S4 on the signed grid
