@@ -361,6 +361,34 @@ def test_full_size_sampled_points(dev, precision):
         assert v <= TOL, (k, v)
 
 
+def test_full_size_c3opt_sampled_points(dev):
+    """c3^(opt) at the benchmark size (3276 chunks of 11 S3 rows, 2.5 GB of
+    workspace): sampled grid points, including the GPU's largest |S3| and the
+    bin-0 lines, equal the oracle's point-by-point evaluation."""
+    from paper_2505_01231_amd import Plan
+    say("full size 2^28 c3opt")
+    N, Nf, m = 8192, 2048, 10
+    z = synth.ar2_chi2(1 << 28, seed=3)
+    x = torch.from_numpy(z).to(dev)
+    with Plan(frame_len=N, n_freq=Nf, m=m, window="acg", orders=(2, 3), estimator="c3opt") as p:
+        out = p.execute(x)
+        torch.cuda.synchronize()
+        s3 = torch.view_as_complex(out.s3[0]).cpu().numpy()
+        e3 = out.s3_err[0].cpu().numpy()
+    del x
+    rng = np.random.default_rng(8)
+    pts = [tuple(int(v) for v in np.unravel_index(np.argmax(np.abs(s3)), s3.shape)),
+           (0, 0), (0, 700), (900, 0), (Nf - 1, Nf - 1), (63, 64)]
+    pts += [tuple(int(v) for v in rng.integers(0, Nf, 2)) for _ in range(12)]
+    ref = O.polyspectra_at(z, N, m, window_kind="acg", points3=pts, estimator="c3opt")
+    got3 = np.array([s3[k, l] for k, l in pts])
+    got3e = np.array([e3[k, l] for k, l in pts])
+    errs = {"s3": rel_err(got3, ref["s3"]), "s3_err": rel_err(got3e, ref["s3_err"])}
+    say("  sampled rel err", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= TOL, (k, v)
+
+
 def test_more_chunks_than_a_grid_dimension(dev):
     """A record with more chunks than the 65536 limit of the y/z grid
     dimensions (2^28 samples at N = 256, m = 10: 104857 chunks): its means
