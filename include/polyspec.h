@@ -343,9 +343,11 @@ ps_status ps_profile_read(ps_plan_t plan, double* stage_ms, int32_t n);
  *                   tile_group x tile_group blocks of tiles (1 = row by row);
  *                   1, 2, 4, 8 (default) or 16.  Larger blocks keep the
  *                   coefficient columns that concurrent blocks read in L2.
- *   s3_frame_batch  frames staged per LDS batch by the S3 kernel: 10 or 16, or
- *                   0 (default) to choose by m (10 when m <= 10 or m is a
- *                   multiple of 10, else 16).
+ *   s3_frame_batch  frames staged per LDS batch by the S3 kernel: 10, 11 or
+ *                   16, or 0 (default) to choose by the rows per chunk
+ *                   (m, or m + 1 with PS_EST_C3OPT): 10 when they are at most
+ *                   10 or a multiple of 10, else 11 for a multiple of 11,
+ *                   else 16.
  * ps_plan_set_tuning rewrites the plan's tile tables in device memory
  * (synchronously): no execute or graph launch of the plan may be in flight.
  * Graphs captured earlier use the new tile order from their next launch and
@@ -360,7 +362,7 @@ ps_status ps_plan_get_tuning(ps_plan_t plan, ps_tuning* t);
 ps_status ps_plan_set_tuning(ps_plan_t plan, const ps_tuning* t);
 
 /* Autotuner: times every candidate configuration (tile_group 1, 4, 8, 16;
- * with S3 requested and m > 10 also both S3 frame batches) with one warm-up
+ * with S3 requested and m > 10 also the S3 frame batches 10, 11 and 16) with one warm-up
  * and `reps` (1..100) timed ps_execute calls on the caller's records,
  * workspace and outputs (arguments as for ps_execute; the outputs end up
  * holding the last run's spectra), measured with HIP events on `stream`, and

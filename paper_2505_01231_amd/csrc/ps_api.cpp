@@ -765,7 +765,7 @@ bool valid_tuning(const ps_tuning& t) {
     const bool g = t.tile_group == 1 || t.tile_group == 2 || t.tile_group == 4 || t.tile_group == 8 ||
                    t.tile_group == 16;
     const bool f = t.s3_frame_batch == 0 || t.s3_frame_batch == ps::kFrameBatchSmall ||
-                   t.s3_frame_batch == ps::kFrameBatch;
+                   t.s3_frame_batch == ps::kFrameBatchRow || t.s3_frame_batch == ps::kFrameBatch;
     return g && f;
 }
 }  // namespace
@@ -780,8 +780,8 @@ ps_status ps_plan_get_tuning(ps_plan_t p, ps_tuning* t) {
 ps_status ps_plan_set_tuning(ps_plan_t p, const ps_tuning* t) {
     if (!p || !t) return fail(PS_E_INVALID_ARG, "NULL argument");
     if (!valid_tuning(*t))
-        return fail(PS_E_INVALID_ARG, "tuning: tile_group %d (1, 2, 4, 8 or 16), s3_frame_batch %d (0, %d or %d)",
-                    t->tile_group, t->s3_frame_batch, ps::kFrameBatchSmall, ps::kFrameBatch);
+        return fail(PS_E_INVALID_ARG, "tuning: tile_group %d (1, 2, 4, 8 or 16), s3_frame_batch %d (0, %d, %d or %d)",
+                    t->tile_group, t->s3_frame_batch, ps::kFrameBatchSmall, ps::kFrameBatchRow, ps::kFrameBatch);
     p->s3_fb = t->s3_frame_batch;
     if (t->tile_group != p->tile_group) {
         p->tile_group = t->tile_group;
@@ -803,6 +803,7 @@ ps_status ps_plan_autotune(ps_plan_t p, const ps_record* recs, int32_t n_rec, vo
     for (int g : groups) {
         if (fb_choice) {
             cand[n++] = ps_tuning{g, ps::kFrameBatchSmall};
+            cand[n++] = ps_tuning{g, ps::kFrameBatchRow};
             cand[n++] = ps_tuning{g, ps::kFrameBatch};
         } else {
             cand[n++] = ps_tuning{g, 0};

@@ -24,6 +24,7 @@ constexpr int kTileX = 32;
 // Frames staged in LDS at once by the moment kernels.
 constexpr int kFrameBatch = 16;
 constexpr int kFrameBatchSmall = 10;
+constexpr int kFrameBatchRow = 11;      // S3 only: chunks of 10 frames plus the c3^(opt) mean row
 
 // Tile tables owned by the plan.
 enum TileKind { kSym64 = 0, kFull64 = 1, kSym32 = 2, kFull32 = 3 };

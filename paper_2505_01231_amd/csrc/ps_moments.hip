@@ -1260,7 +1260,6 @@ hipError_t launch_s2(const BatchArgs& a, hipStream_t s) {
 // (the default m = 10 fits one batch), 11 for multiples of 11 (c3^(opt) adds
 // a mean row to chunks of 10 frames), 16 otherwise.
 bool s3_small_batch(int m) { return m <= kFrameBatchSmall || m % kFrameBatchSmall == 0; }
-constexpr int kFrameBatchRow = 11;
 
 hipError_t launch_s3(const BatchArgs& a, hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;

@@ -1116,7 +1116,7 @@ def test_tuning_configurations_agree(dev, precision):
             got = base[key][..., 0] + 1j * base[key][..., 1]
             assert rel_err(got, ref[key]) <= TOL, key
         for g in (1, 2, 4, 16):
-            for fb in (10, 16):
+            for fb in (10, 11, 16):
                 p.set_tuning(g, fb)
                 assert p.tuning == {"tile_group": g, "s3_frame_batch": fb}
                 out = _spectra(p.execute(x))
@@ -1140,9 +1140,9 @@ def test_autotune_keeps_the_fastest(dev):
         torch.cuda.synchronize()
         cands = rep["candidates"]
         say("  candidates", [(c["tile_group"], c["s3_frame_batch"], round(ms, 3)) for c, ms in cands])
-        assert len(cands) == 8                      # 4 tile orders x 2 S3 frame batches (m > 10)
+        assert len(cands) == 12                     # 4 tile orders x 3 S3 frame batches (m > 10)
         assert {(c["tile_group"], c["s3_frame_batch"]) for c, _ in cands} == \
-            {(g, fb) for g in (1, 4, 8, 16) for fb in (10, 16)}
+            {(g, fb) for g in (1, 4, 8, 16) for fb in (10, 11, 16)}
         assert all(ms > 0 for _, ms in cands)
         fastest = min(cands, key=lambda c: c[1])[0]
         assert rep["best"] == fastest == p.tuning
