@@ -64,7 +64,7 @@ def s3_traffic():
         return None
 
 
-def cpu_baseline(z, seconds_target=15.0):
+def cpu_baseline(z, seconds_target=15.0, estimator="kstat"):
     """The FP64 oracle on a bounded sample of the same workload (whole chunks)."""
     import numpy as np
 
@@ -72,13 +72,13 @@ def cpu_baseline(z, seconds_target=15.0):
     chunk = N * M
     n_chunks = 1
     t0 = time.perf_counter()
-    O.polyspectra(z[: chunk * n_chunks].astype(np.float64), N, NF, M, window_kind="acg")
+    O.polyspectra(z[: chunk * n_chunks].astype(np.float64), N, NF, M, window_kind="acg", estimator=estimator)
     dt1 = time.perf_counter() - t0
     extra = int(max(0, min(4, seconds_target / max(dt1, 1e-3) - 1)))
     if extra:
         n_chunks = 1 + extra
         t0 = time.perf_counter()
-        O.polyspectra(z[: chunk * n_chunks].astype(np.float64), N, NF, M, window_kind="acg")
+        O.polyspectra(z[: chunk * n_chunks].astype(np.float64), N, NF, M, window_kind="acg", estimator=estimator)
         dt1 = time.perf_counter() - t0
     return {
         "value": chunk * n_chunks / dt1,
@@ -206,6 +206,8 @@ def main(argv=None):
     ap.add_argument("--sequential-steps", type=int, default=1,
                     help="timed steps of sequential spectra (every chunk's estimate kept) over the first "
                          "2^22 samples at N = 1024, N_f = 256")
+    ap.add_argument("--estimator", default="kstat", choices=("kstat", "c3opt"),
+                    help="estimator of the main leg (c3opt: S3 by c3^(opt), one more row per chunk in S3)")
     ap.add_argument("--c3opt-steps", type=int, default=2,
                     help="timed steps with S3 by the c3^(opt) estimator (one extra mean row per chunk) "
                          "on the same record")
@@ -248,9 +250,11 @@ def main(argv=None):
     x = torch.from_numpy(z).to(dev)
     torch.cuda.synchronize()
 
-    plan = Plan(frame_len=N, n_freq=NF, m=M, window="acg", precision=args.precision)
+    plan = Plan(frame_len=N, n_freq=NF, m=M, window="acg", precision=args.precision, estimator=args.estimator)
     n_chunks, _ = plan.record_info(N_SAMPLES)
     n_frames = n_chunks * M
+    # rows the S3 kernel sums per launch (c3^(opt): m shifted frames + one mean row per chunk)
+    s3_rows = n_chunks * (M + 1) if args.estimator == "c3opt" else n_frames
     ws = torch.empty(plan.workspace_bytes([x]), dtype=torch.uint8, device=dev)
     outs = [plan.allocate_outputs(dev)]
     log(f"workspace {ws.numel() / 2**30:.2f} GiB, chunks {n_chunks}")
@@ -275,7 +279,7 @@ def main(argv=None):
     value = N_SAMPLES * args.steps / elapsed
     s3_ms, s3_n = stages["s3"]
     s3_avg_ms = s3_ms / max(1, s3_n)
-    achieved = s3_flops_per_launch(n_frames, NF) / (s3_avg_ms * 1e-3) / 1e12
+    achieved = s3_flops_per_launch(s3_rows, NF) / (s3_avg_ms * 1e-3) / 1e12
     stage_ms = {k: round(v[0] / max(1, args.steps), 4) for k, v in stages.items()}
 
     # The plain FP32 path: same kernels, one chunk per launch (the paper's structure).
@@ -395,7 +399,7 @@ def main(argv=None):
     batching = run_batching(torch, dev, args.precision) if args.batching else None
     streaming = run_streaming(torch, dev, args.precision) if args.streaming else None
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(z)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(z, estimator=args.estimator)
     if cpu:
         log(f"cpu baseline {cpu['value']:.3e} samples/s")
 
@@ -404,7 +408,9 @@ def main(argv=None):
     # K = 2 N_f - 1 complex FP32 coefficients per frame; the centring reads and
     # writes every coefficient; S2 reads the first N_f columns.
     K_COEF = 2 * NF - 1
-    alg_bytes = {"fft": 4 * n_frames * N + 8 * K_COEF * n_frames, "mean": 16 * K_COEF * n_frames,
+    # (c3^(opt): the centring also writes the S3 rows, m + 1 per chunk)
+    alg_bytes = {"fft": 4 * n_frames * N + 8 * K_COEF * n_frames,
+                 "mean": 16 * K_COEF * n_frames + (8 * K_COEF * s3_rows if args.estimator == "c3opt" else 0),
                  "s2": 8 * NF * n_frames}
     stage_rates = {f"{k}_hbm_gbps": (b / (stage_ms[k] * 1e-3) / 1e9 if stage_ms.get(k) else None)
                    for k, b in alg_bytes.items()}
@@ -423,7 +429,8 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else args.precision,
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "precision": args.precision, "n_chunks": n_chunks,
+        "config": {"workload": WORKLOAD, "precision": args.precision, "estimator": args.estimator,
+                   "n_chunks": n_chunks,
                    "samples_per_step": N_SAMPLES},
         "roofline": {
             "kernel": "k_s3 (S3 triple-product moment sums)",
@@ -432,9 +439,9 @@ def main(argv=None):
             "peak": PEAK_FP32_VALU_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VALU_TFLOPS,
-            "traffic": s3_traffic(),
+            "traffic": s3_traffic() if args.estimator == "kstat" else None,
             "avg_launch_ms": s3_avg_ms,
-            "flops_per_launch": s3_flops_per_launch(n_frames, NF),
+            "flops_per_launch": s3_flops_per_launch(s3_rows, NF),
         },
         "cpu_baseline": cpu,
         "paths": {"main": args.precision, "main_value": value, "batched_fp32": batched_fp32,
