@@ -84,6 +84,26 @@ def test_ctypes_layouts_match_header(tmp_path):
             assert getattr(getattr(L, struct), field).offset == int(val), key
 
 
+def test_constants_match_header(tmp_path):
+    """Every PS_* constant of the binding has the value the header gives it
+    (enumerators and #defines, printed by a C program compiled against the
+    header)."""
+    text = open(HEADER).read()
+    names = sorted(set(re.findall(r"\b(PS_[A-Z0-9_]+)\s*=", text)) |
+                   set(re.findall(r"#define\s+(PS_[A-Z0-9_]+)\s+\S", text)))
+    py = {n: getattr(L, n) for n in dir(L) if n.startswith("PS_") and isinstance(getattr(L, n), int)}
+    assert set(py) <= set(names), sorted(set(py) - set(names))
+    src = tmp_path / "consts.c"
+    src.write_text('#include <stdio.h>\n#include "polyspec.h"\nint main(void) {\n' +
+                   "".join(f'  printf("{n} %lld\\n", (long long)({n}));\n' for n in names) + "  return 0;\n}\n")
+    exe = tmp_path / "consts"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    got = {k: int(v) for k, v in (line.split() for line in subprocess.run(
+        [str(exe)], capture_output=True, text=True, check=True).stdout.splitlines())}
+    for n, v in py.items():
+        assert got[n] == v, (n, got[n], v)
+
+
 def _cfg(**kw):
     cfg = L.ps_config()
     cfg.struct_size = C.sizeof(L.ps_config)
