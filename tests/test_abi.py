@@ -228,3 +228,16 @@ def test_library_binds_to_torchs_hip_runtime():
             "import torch, os\n"
             "assert next(iter(hip)).startswith(os.path.dirname(torch.__file__)), hip\n") % ROOT
     subprocess.run([sys.executable, "-c", code], check=True, timeout=300)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits with status 2 and a JSON line
+    that says so, before it touches torch or a device."""
+    import json
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
