@@ -1026,18 +1026,20 @@ def test_s4_plane_matches_oracle(dev, precision):
     compare(gpu, ref, keys=("s2", "s4"), label=f"plane-{precision}")
 
 
-def test_s4_plane_wide_shift_with_s3(dev):
+@pytest.mark.parametrize("estimator", ["kstat", "c3opt"])
+def test_s4_plane_wide_shift_with_s3(dev, estimator):
     """Two complex channels, q = -N_f (a wider stored bin range, so S3's third
-    factor sits at an offset column), S2, S3 and every S4 combination."""
-    say("S4 plane, wide shift, 2 channels")
+    factor sits at an offset column), S2, S3 and every S4 combination; with
+    c3^(opt) the S3 rows carry the same offset."""
+    say("S4 plane, wide shift, 2 channels", estimator)
     N, Nf, m = 256, 20, 6
     z = _complex_signal(N * m * 5 + 11, seed=172, N=N, channels=2).astype(np.complex64)
     gpu = run_gpu(z, dev, frame_len=N, n_freq=Nf, m=m, n_channels=2, precision="bf16x3", complex_signal=True,
-                  s4_shift=-Nf)
+                  s4_shift=-Nf, estimator=estimator)
     assert len(gpu["plan"]["combos4"]) == 16
     ref = O.polyspectra_complex(z, N, Nf, m, s4_shift=-Nf, combos2=gpu["plan"]["combos2"],
-                                combos3=gpu["plan"]["combos3"], combos4=gpu["plan"]["combos4"])
-    compare(gpu, ref, label="plane-wide-2ch")
+                                combos3=gpu["plan"]["combos3"], combos4=gpu["plan"]["combos4"], estimator=estimator)
+    compare(gpu, ref, label=f"plane-wide-2ch-{estimator}")
 
 
 # ---------------------------------------------------------------- frame lengths 2 P 2^q (prime-factor transform)
