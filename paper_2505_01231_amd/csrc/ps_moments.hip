@@ -1261,18 +1261,25 @@ hipError_t launch_s2(const BatchArgs& a, hipStream_t s) {
 // a mean row to chunks of 10 frames), 16 otherwise.
 bool s3_small_batch(int m) { return m <= kFrameBatchSmall || m % kFrameBatchSmall == 0; }
 
+// Chunks of 12 to 15 rows get a batch of exactly their size: the 16-frame
+// instance costs more per row (it keeps more registers live).
 hipError_t launch_s3(const BatchArgs& a, hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;
     const int fb = a.s3_fb ? a.s3_fb
                    : s3_small_batch(a.m) ? kFrameBatchSmall
                    : (a.m % kFrameBatchRow == 0) ? kFrameBatchRow
-                                                 : kFrameBatch;
-    if (fb == kFrameBatchSmall)
-        k_s3<kFrameBatchSmall><<<item_grid(a), kS3Threads, 0, s>>>(a);
-    else if (fb == kFrameBatchRow)
-        k_s3<kFrameBatchRow><<<item_grid(a), kS3Threads, 0, s>>>(a);
-    else
-        k_s3<kFrameBatch><<<item_grid(a), kS3Threads, 0, s>>>(a);
+                   : (a.m < kFrameBatch) ? a.m
+                                         : kFrameBatch;
+    const dim3 g = item_grid(a);
+    switch (fb) {
+        case kFrameBatchSmall: k_s3<kFrameBatchSmall><<<g, kS3Threads, 0, s>>>(a); break;
+        case kFrameBatchRow: k_s3<kFrameBatchRow><<<g, kS3Threads, 0, s>>>(a); break;
+        case 12: k_s3<12><<<g, kS3Threads, 0, s>>>(a); break;
+        case 13: k_s3<13><<<g, kS3Threads, 0, s>>>(a); break;
+        case 14: k_s3<14><<<g, kS3Threads, 0, s>>>(a); break;
+        case 15: k_s3<15><<<g, kS3Threads, 0, s>>>(a); break;
+        default: k_s3<kFrameBatch><<<g, kS3Threads, 0, s>>>(a); break;
+    }
     return hipGetLastError();
 }
 

@@ -247,6 +247,26 @@ def test_cross_channel_s2_s3(dev):
     compare(gpu, ref, keys=("s2", "s3"), label="cross")
 
 
+@pytest.mark.parametrize("m", [12, 13, 15])
+def test_exact_size_s3_batches(dev, m):
+    """Chunks of 12 to 15 frames run an S3 batch of exactly their size: the
+    spectra equal the oracle's and, bit for bit, those of the 16-frame batch
+    (the frames are added in the same order)."""
+    from paper_2505_01231_amd import Plan
+    say("exact-size S3 batch", m)
+    N, Nf = 512, 100
+    z = synth.ar2_chi2(N * m * 6 + 21, seed=190 + m, dtype=np.float32)
+    x = torch.from_numpy(z).to(dev)
+    with Plan(frame_len=N, n_freq=Nf, m=m, orders=(3,), window="hann") as p:
+        a = torch.view_as_complex(p.execute(x).s3).cpu().numpy()
+        p.set_tuning(8, 16)
+        b = torch.view_as_complex(p.execute(x).s3).cpu().numpy()
+        torch.cuda.synchronize()
+    assert np.array_equal(a, b)
+    ref = O.polyspectra(z, N, Nf, m, orders=(3,), window_kind="hann")
+    assert rel_err(a[0], ref["s3"][0]) <= TOL
+
+
 # ---------------------------------------------------------------- schedule, determinism, edges
 @pytest.mark.parametrize("precision", PRECISIONS)
 def test_per_chunk_schedule_matches_batched(dev, precision):
