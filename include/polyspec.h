@@ -345,9 +345,8 @@ ps_status ps_profile_read(ps_plan_t plan, double* stage_ms, int32_t n);
  *                   coefficient columns that concurrent blocks read in L2.
  *   s3_frame_batch  frames staged per LDS batch by the S3 kernel: 10, 11 or
  *                   16, or 0 (default) to choose by the rows per chunk
- *                   (m, or m + 1 with PS_EST_C3OPT): 10 when they are at most
- *                   10 or a multiple of 10, else 11 for a multiple of 11,
- *                   else exactly their number from 12 to 15, else 16.
+ *                   (m, or m + 1 with PS_EST_C3OPT): exactly their number
+ *                   for 11 to 13 rows (one batch), else 10.
  * ps_plan_set_tuning rewrites the plan's tile tables in device memory
  * (synchronously): no execute or graph launch of the plan may be in flight.
  * Graphs captured earlier use the new tile order from their next launch and

@@ -1256,28 +1256,25 @@ hipError_t launch_s2(const BatchArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Frame batch of the S3 kernel: 10 when m is a multiple of 10 or below it
-// (the default m = 10 fits one batch), 11 for multiples of 11 (c3^(opt) adds
-// a mean row to chunks of 10 frames), 16 otherwise.
+// Frame batch of the S3 kernel, by rows per chunk r (m, or m + 1 for
+// c3^(opt)): exactly r for r = 11..13 (one batch), else 10 (the default
+// m = 10 fits one batch; longer chunks take several).  Measured at 2^28
+// samples, the 10-frame instance has the lowest cost per row; a single
+// batch of 11 to 13 beats it by 1-4 %, one of 14 to 16 loses to it by 2-8 %
+// and the 16-frame batch with a remainder by 12-20 %.
 bool s3_small_batch(int m) { return m <= kFrameBatchSmall || m % kFrameBatchSmall == 0; }
 
-// Chunks of 12 to 15 rows get a batch of exactly their size: the 16-frame
-// instance costs more per row (it keeps more registers live).
 hipError_t launch_s3(const BatchArgs& a, hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;
     const int fb = a.s3_fb ? a.s3_fb
-                   : s3_small_batch(a.m) ? kFrameBatchSmall
-                   : (a.m % kFrameBatchRow == 0) ? kFrameBatchRow
-                   : (a.m < kFrameBatch) ? a.m
-                                         : kFrameBatch;
+                   : (!s3_small_batch(a.m) && a.m <= 13) ? a.m
+                                                        : kFrameBatchSmall;
     const dim3 g = item_grid(a);
     switch (fb) {
         case kFrameBatchSmall: k_s3<kFrameBatchSmall><<<g, kS3Threads, 0, s>>>(a); break;
         case kFrameBatchRow: k_s3<kFrameBatchRow><<<g, kS3Threads, 0, s>>>(a); break;
         case 12: k_s3<12><<<g, kS3Threads, 0, s>>>(a); break;
         case 13: k_s3<13><<<g, kS3Threads, 0, s>>>(a); break;
-        case 14: k_s3<14><<<g, kS3Threads, 0, s>>>(a); break;
-        case 15: k_s3<15><<<g, kS3Threads, 0, s>>>(a); break;
         default: k_s3<kFrameBatch><<<g, kS3Threads, 0, s>>>(a); break;
     }
     return hipGetLastError();

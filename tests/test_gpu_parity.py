@@ -249,9 +249,9 @@ def test_cross_channel_s2_s3(dev):
 
 @pytest.mark.parametrize("m", [12, 13, 15])
 def test_exact_size_s3_batches(dev, m):
-    """Chunks of 12 to 15 frames run an S3 batch of exactly their size: the
-    spectra equal the oracle's and, bit for bit, those of the 16-frame batch
-    (the frames are added in the same order)."""
+    """The default S3 batch (exactly 12 or 13 frames for such chunks, else
+    several batches of 10): the spectra equal the oracle's and, bit for bit,
+    those of the 16-frame batch (the frames are added in the same order)."""
     from paper_2505_01231_amd import Plan
     say("exact-size S3 batch", m)
     N, Nf = 512, 100
