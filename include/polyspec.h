@@ -361,7 +361,8 @@ ps_status ps_plan_get_tuning(ps_plan_t plan, ps_tuning* t);
 ps_status ps_plan_set_tuning(ps_plan_t plan, const ps_tuning* t);
 
 /* Autotuner: times every candidate configuration (tile_group 1, 4, 8, 16;
- * with S3 requested and m > 10 also the S3 frame batches 10, 11 and 16) with one warm-up
+ * with S3 requested and m > 10 also the S3 frame batch: the default rule (0),
+ * 10 and 16) with one warm-up
  * and `reps` (1..100) timed ps_execute calls on the caller's records,
  * workspace and outputs (arguments as for ps_execute; the outputs end up
  * holding the last run's spectra), measured with HIP events on `stream`, and

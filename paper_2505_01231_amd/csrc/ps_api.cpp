@@ -801,9 +801,9 @@ ps_status ps_plan_autotune(ps_plan_t p, const ps_record* recs, int32_t n_rec, vo
     // The S3 frame batch matters when a chunk does not fit one small batch.
     const bool fb_choice = p->has(3) && p->m > ps::kFrameBatchSmall;
     for (int g : groups) {
-        if (fb_choice) {
+        if (fb_choice) {                        // the default rule (0), then 10 and 16
+            cand[n++] = ps_tuning{g, 0};
             cand[n++] = ps_tuning{g, ps::kFrameBatchSmall};
-            cand[n++] = ps_tuning{g, ps::kFrameBatchRow};
             cand[n++] = ps_tuning{g, ps::kFrameBatch};
         } else {
             cand[n++] = ps_tuning{g, 0};
