@@ -182,7 +182,7 @@ struct BatchArgs {
     int c4a, c4b;
     double gamma;
     int s4_shift;           // S4 planes: a, d at +q columns, b, c at -q (cross-channel kernels only)
-    int s3_fb;              // S3 frames per LDS batch (kFrameBatchSmall or kFrameBatch); 0: chosen by m
+    int s3_fb;              // S3 frames per LDS batch (10, 11 or 16); 0: chosen by the rows per chunk
 };
 hipError_t launch_s2(const BatchArgs& a, hipStream_t s);
 hipError_t launch_s3(const BatchArgs& a, hipStream_t s);
