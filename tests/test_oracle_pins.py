@@ -95,6 +95,85 @@ def test_natural_estimator_is_biased():
     assert abs(got - want) > 1e-2 * abs(want)
 
 
+def _empirical_cumulant(samples, idx):
+    """Joint cumulant of the empirical distribution of m samples (each drawn
+    with probability 1/m), by the set-partition formula: the plug-in value that
+    the natural estimator of Section 6 is by construction."""
+    m = len(samples)
+    return _joint_cumulant(samples, [Fraction(1, m)] * m, idx)
+
+
+@pytest.mark.parametrize("m", [4, 5, 9])
+def test_natural_estimators_are_empirical_cumulants(m):
+    """natural2/3/4 equal the joint cumulants of the sample's empirical
+    distribution (computed without the paper's moment expressions), and
+    incomplete4 its joint central fourth moment (computed by explicit loops)."""
+    rng = np.random.default_rng(100 + m)
+    xs = [tuple(int(v) for v in rng.integers(-4, 5, size=4)) for _ in range(m)]
+    cols = [np.array([float(s[j]) for s in xs]) for j in range(4)]
+    for est, idx in ((O.natural2, (0, 1)), (O.natural3, (0, 1, 2)), (O.natural3, (2, 2, 3)),
+                     (O.natural4, (0, 1, 2, 3)), (O.natural4, (1, 1, 3, 3)), (O.natural4, (2, 2, 2, 2))):
+        want = float(_empirical_cumulant(xs, idx))
+        got = float(est(*[cols[j] for j in idx]))
+        assert abs(got - want) <= 1e-12 * max(1.0, abs(want)), (est.__name__, idx, got, want)
+    # incomplete fourth cumulant: the mean of the product of centred values
+    means = [Fraction(sum(s[j] for s in xs), m) for j in range(4)]
+    want = sum((s[0] - means[0]) * (s[1] - means[1]) * (s[2] - means[2]) * (s[3] - means[3]) for s in xs) / m
+    got = float(O.incomplete4(*cols))
+    assert abs(got - float(want)) <= 1e-12 * max(1.0, abs(float(want)))
+
+
+@pytest.mark.parametrize("m", [5, 10, 37])
+def test_univariate_natural_matches_scipy_moments(m):
+    """Univariate plug-in cumulants from scipy's central moments m_n:
+    natural2 = m_2, natural3 = m_3, natural4 = m_4 - 3 m_2^2, incomplete4 = m_4."""
+    rng = np.random.default_rng(7 * m)
+    x = rng.standard_normal(m) ** 3 + 0.4
+    m2, m3, m4 = (scipy.stats.moment(x, n) for n in (2, 3, 4))
+    assert np.isclose(O.natural2(x, x), m2, rtol=1e-12)
+    assert np.isclose(O.natural3(x, x, x), m3, rtol=1e-11, atol=1e-13)
+    assert np.isclose(O.natural4(x, x, x, x), m4 - 3 * m2 * m2, rtol=1e-11, atol=1e-13)
+    assert np.isclose(O.incomplete4(x, x, x, x), m4, rtol=1e-12)
+
+
+@pytest.mark.parametrize("m", [4, 5, 6])
+def test_natural_and_incomplete_expectations_by_enumeration(m):
+    """Exact expectations over all m-tuples against the textbook closed forms
+    for i.i.d. samples (kappa: joint cumulants, mu: joint central moments):
+      E natural2 = (m-1)/m kappa_xy,
+      E natural3 = (m-1)(m-2)/m^2 kappa_xyz,
+      E natural4 = (m-1)/m^3 [(m^2-6m+6) kappa_xyzw - 2m (kappa_xy kappa_zw + kappa_xz kappa_yw + kappa_xw kappa_yz)],
+      E incomplete4 = (m-1)/m^3 [(m^2-3m+3) mu_xyzw + (2m-3)(mu_xy mu_zw + mu_xz mu_yw + mu_xw mu_yz)]."""
+    vals, probs = REAL_VALUES, REAL_PROBS
+
+    def kap(*idx):
+        return float(_joint_cumulant(vals, probs, idx))
+
+    def mu(*idx):
+        mean = [sum(p * v[j] for v, p in zip(vals, probs)) for j in range(4)]
+        tot = 0
+        for v, p in zip(vals, probs):
+            prod = p
+            for j in idx:
+                prod *= v[j] - mean[j]
+            tot += prod
+        return float(tot)
+
+    x, y, z, w = 0, 1, 2, 3
+    got = _expected_estimator(O.natural2, vals, probs, (x, y), m)
+    assert np.isclose(got, (m - 1) / m * kap(x, y), rtol=1e-12)
+    got = _expected_estimator(O.natural3, vals, probs, (x, y, z), m)
+    assert np.isclose(got, (m - 1) * (m - 2) / m ** 2 * kap(x, y, z), rtol=1e-12)
+    pairs_k = kap(x, y) * kap(z, w) + kap(x, z) * kap(y, w) + kap(x, w) * kap(y, z)
+    want = (m - 1) / m ** 3 * ((m * m - 6 * m + 6) * kap(x, y, z, w) - 2 * m * pairs_k)
+    got = _expected_estimator(O.natural4, vals, probs, (x, y, z, w), m)
+    assert np.isclose(got, want, rtol=1e-12), (got, want)
+    pairs_m = mu(x, y) * mu(z, w) + mu(x, z) * mu(y, w) + mu(x, w) * mu(y, z)
+    want = (m - 1) / m ** 3 * ((m * m - 3 * m + 3) * mu(x, y, z, w) + (2 * m - 3) * pairs_m)
+    got = _expected_estimator(O.incomplete4, vals, probs, (x, y, z, w), m)
+    assert np.isclose(got, want, rtol=1e-12), (got, want)
+
+
 @pytest.mark.parametrize("n", [2, 3, 4])
 def test_univariate_matches_scipy_kstat(n):
     rng = np.random.default_rng(11)
@@ -137,6 +216,27 @@ def test_acg_window_confinement(N):
     assert np.all(np.abs(edge) <= 1e-14 * g.max())
     # a wider sigma_t gives a wider window
     assert O.window("acg", N, 0.3)[N // 8] / O.window("acg", N, 0.3).max() > g[N // 8] / g.max()
+
+
+@pytest.mark.parametrize("N", [256, 4096])
+def test_acg_rms_width_is_sigma_t(N):
+    """sigma_t is the window's RMS temporal width in units of T = N (the RMS
+    time-bandwidth measure the paper cites for the choice sigma_t = 0.14,
+    Section 3): the energy-weighted spread of g about (N-1)/2,
+    sqrt(sum (i - c)^2 g_i^2 / sum g_i^2).  Where the confinement terms of
+    Appendix B are negligible (small sigma_t) it equals sigma_t N; at 0.14
+    they narrow the window slightly.  A wrong width constant in G (2 N^2 or
+    8 N^2 in place of 4 N^2) moves the ratio by a factor sqrt(2)."""
+    i = np.arange(N)
+    c = (N - 1) / 2
+
+    def rms(s):
+        g2 = O.window("acg", N, s) ** 2
+        return np.sqrt(np.sum(g2 * (i - c) ** 2) / np.sum(g2))
+
+    for s in (0.03, 0.05, 0.08):
+        assert abs(rms(s) / (N * s) - 1) < 1e-5, s
+    assert 0.97 < rms(0.14) / (N * 0.14) < 1.0
 
 
 def test_fft_and_direct_sum_agree():
@@ -783,6 +883,28 @@ def test_complex_white_noise():
     for key in ("s3", "s4"):
         t = np.abs(out[key][0].real) / out[key + "_err"][0][..., 0]
         assert np.mean(t > 3) < 0.02, (key, np.mean(t > 3))
+
+
+def test_s4_planes_by_frequency_shifted_signals():
+    """The Appendix's own construction of a plane parallel to the cut: the
+    signals x = z1 e^{+j dw t}, y = z2 e^{-j dw t}, z = z3 e^{-j dw t},
+    w = z4 e^{+j dw t} (dw = 2 pi q / T, i.e. e^{2 pi j q n / N} at sample n)
+    put through the q = 0 cut of the complex-signal estimator give the plane
+    of the original channels shifted by q bins."""
+    N, Nf, m = 32, 5, 6
+    s = synth.ar2_chi2(N * m * 9 + 5, seed=171, r=0.85, dtype=np.float64)
+    z = np.stack([s[:-5], s[5:] ** 2 - 1.0, s[2:-3] * s[:-5]])
+    n = np.arange(z.shape[1])
+    for q, (a, b, c, d) in ((2, (0, 0, 0, 0)), (-3, (0, 1, 2, 0)), (4, (2, 1, 1, 0)), (1, (1, 2, 0, 2))):
+        up = np.exp(2j * np.pi * q * n / N)
+        shifted = np.stack([z[a] * up, z[b] / up, z[c] / up, z[d] * up])
+        cut = O.polyspectra_complex(shifted, N, Nf, m, orders=(4,), combos4=[(0, 1, 2, 3)], s4_shift=0)
+        plane = O.polyspectra_complex(z.astype(np.complex128), N, Nf, m, orders=(4,), combos4=[(a, b, c, d)],
+                                      s4_shift=q)
+        scale = np.abs(plane["s4"][0]).max()
+        assert np.allclose(cut["s4"][0], plane["s4"][0], rtol=0, atol=1e-11 * scale), (q, (a, b, c, d))
+        assert np.allclose(cut["s4_err"][0], plane["s4_err"][0], rtol=0,
+                           atol=1e-11 * plane["s4_err"][0].max()), (q, (a, b, c, d))
 
 
 def test_s4_planes_are_planes_of_the_three_dimensional_spectrum():
