@@ -37,6 +37,7 @@ PEAK_HBM_GBS = 8000.0
 # 256 CUs x 64 lanes x 2 flop x 2.4 GHz.  (The vendor's 157.3 TFLOP/s assumes
 # packed FP32 instructions, which the library's device code is compiled without.)
 PEAK_FP32_VALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+VENDOR_FP32_VECTOR_TFLOPS = 157.3
 
 
 def log(*a):
@@ -64,30 +65,117 @@ def s3_traffic():
         return None
 
 
-def cpu_baseline(z, seconds_target=15.0, estimator="kstat"):
-    """The FP64 oracle on a bounded sample of the same workload (whole chunks)."""
+def _oracle_chunks(args):
+    """One worker of the multi-core CPU baseline: the oracle on chunks
+    [c0, c1) of the record, returning every chunk's normalised spectra."""
+    import numpy as np
+
+    import oracle as O
+    z, estimator = args
+    out = O.polyspectra(np.asarray(z, dtype=np.float64), N, NF, M, window_kind="acg",
+                        estimator=estimator, return_chunks=True)
+    return out["chunks2"], out["chunks3"], out["chunks4"]
+
+
+def _blas_info():
+    try:
+        from threadpoolctl import threadpool_info
+        return [f"{d.get('internal_api')} {d.get('version')} ({d.get('num_threads')} threads)"
+                for d in threadpool_info()]
+    except Exception:  # pragma: no cover
+        return []
+
+
+def cpu_baseline(z, estimator="kstat", workers=None):
+    """The FP64 oracle on bounded samples of the same workload (whole chunks
+    of the record's start):
+      * single-threaded: the oracle on the first chunks (its numpy kernels run
+        on one core), sized to ~10 s;
+      * all cores: the same oracle on one chunk per task over a process pool
+        of min(16, cpu_count) workers (chunks are independent), ~10 s;
+      * the factorized fourth-order form (Appendix H), single-threaded.
+    Returns (record for the JSON line, oracle spectra of the single-thread
+    sample for the accuracy check)."""
+    import multiprocessing as mp
+
     import numpy as np
 
     import oracle as O
     chunk = N * M
-    n_chunks = 1
+    z64 = np.asarray(z[: chunk * 64], dtype=np.float64)
     t0 = time.perf_counter()
-    O.polyspectra(z[: chunk * n_chunks].astype(np.float64), N, NF, M, window_kind="acg", estimator=estimator)
-    dt1 = time.perf_counter() - t0
-    extra = int(max(0, min(4, seconds_target / max(dt1, 1e-3) - 1)))
-    if extra:
-        n_chunks = 1 + extra
-        t0 = time.perf_counter()
-        O.polyspectra(z[: chunk * n_chunks].astype(np.float64), N, NF, M, window_kind="acg", estimator=estimator)
-        dt1 = time.perf_counter() - t0
-    return {
-        "value": chunk * n_chunks / dt1,
+    O.polyspectra(z64[:chunk], N, NF, M, window_kind="acg", estimator=estimator)
+    t1 = time.perf_counter() - t0
+    n1 = int(max(1, min(6, 10.0 / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    ref = O.polyspectra(z64[: chunk * n1], N, NF, M, window_kind="acg", estimator=estimator)
+    t1 = time.perf_counter() - t0
+    single = chunk * n1 / t1
+
+    cores = os.cpu_count() or 1
+    workers = workers or max(1, min(16, cores))
+    # whole rounds of one chunk per worker, ~10 s
+    n_par = workers * int(max(1, min(4, round(10.0 / max(t1 / n1, 1e-3)))))
+    # fresh worker interpreters (no inherited GPU state), one BLAS thread each
+    ctx = mp.get_context("spawn")
+    saved = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    os.environ.update({k: "1" for k in saved})
+    try:
+        with ctx.Pool(workers) as pool:
+            pool.map(_oracle_chunks, [(z64[:chunk], estimator)] * workers)      # start-up and imports
+            t0 = time.perf_counter()
+            parts = pool.map(_oracle_chunks, [(z64[c * chunk:(c + 1) * chunk], estimator) for c in range(n_par)])
+            tp = time.perf_counter() - t0
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    multi = chunk * n_par / tp
+
+    t0 = time.perf_counter()
+    O.polyspectra(z64[:chunk], N, NF, M, window_kind="acg", estimator="factorized")
+    tf = time.perf_counter() - t0
+    record = {
+        "value": multi,
         "unit": "samples/s",
-        "cores": 1,
+        "cores": workers,
         "kind": "oracle",
-        "sample": f"first {n_chunks} chunk(s) = {chunk * n_chunks} samples of the same record, "
-                  f"full N_f=2048 grid, numpy float64 (single-threaded elementwise), {dt1:.1f} s",
+        "sample": f"{n_par} chunks ({chunk * n_par} samples) of the record's start, one chunk per task on "
+                  f"{workers} worker processes (one thread each), full N_f=2048 grid, numpy float64, "
+                  f"{tp:.1f} s",
+        "host_cpu_count": cores,
+        "single_thread": {"value": single, "chunks": n1, "seconds": round(t1, 2)},
+        "factorized_single_thread": {"value": chunk / tf, "chunks": 1, "seconds": round(tf, 2),
+                                     "form": "Appendix H centred c4 (S2, S3 unchanged)"},
+        "numpy": np.__version__,
+        "blas": _blas_info(),
+        "extrapolated_seconds_for_2p28": N_SAMPLES / multi,
     }
+    del parts
+    return record, ref, n1
+
+
+def accuracy(torch, dev, plan, z, ref, n_chunks):
+    """Per-spectrum max relative error of the timed path against the FP64
+    oracle on the same chunks: max |S_gpu - S_oracle| / max |S_oracle| over the
+    whole grid, for S2, S3, S4 and their error bars."""
+    import numpy as np
+    x = torch.from_numpy(np.ascontiguousarray(z[: N * M * n_chunks])).to(dev)
+    out = plan.execute(x)
+    torch.cuda.synchronize()
+    err = {}
+    for k in ("s2", "s3", "s4"):
+        got = torch.view_as_complex(getattr(out, k)).cpu().numpy()[0]
+        want = ref[k][0]
+        err[k] = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+        ge, we = getattr(out, k + "_err").cpu().numpy()[0], ref[k + "_err"][0]
+        err[k + "_err"] = float(np.nanmax(np.abs(ge - we)) / np.nanmax(np.abs(we)))
+    return {"max_rel_err": err, "chunks": n_chunks, "tolerance": 1e-5,
+            "within_tolerance": all(v <= 1e-5 for v in err.values()),
+            "note": "same plan (precision, estimator) as the timed steps, run on the chunks the CPU "
+                    "baseline's single-thread oracle evaluated; normalised to each array's max |oracle|"}
 
 
 def run_batching(torch, dev, precision):
@@ -212,12 +300,12 @@ def main(argv=None):
                     help="timed steps with S3 by the c3^(opt) estimator (one extra mean row per chunk) "
                          "on the same record")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batching", action="store_true",
-                    help="also time the batching form: 24 four-channel int16 records of uneven length "
-                         "(2^16..2^22), N in {1024, 2048, 4096}, N_f = N/4, every combination orbit")
-    ap.add_argument("--streaming", action="store_true",
-                    help="also time the streaming form: 64 windows of 2^20 samples from pinned host "
-                         "memory, 8 windows per push, N = 4096, N_f = 1024, copy/compute overlap")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="skip the batching form (four-channel int16 records of uneven length "
+                         "(2^16..2^22), N in {1024, 2048, 4096}, N_f = N/4, every combination orbit)")
+    ap.add_argument("--no-streaming", action="store_true",
+                    help="skip the streaming form (64 windows of 2^20 samples from pinned host "
+                         "memory, 8 windows per push, N = 4096, N_f = 1024, copy/compute overlap)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain elementwise copy of 1 GiB (3 launches) so that profiler "
                          "byte counters can be scaled against a kernel of known traffic")
@@ -319,8 +407,8 @@ def main(argv=None):
                "useful_tflops": 10.0 * (NF * (NF + 1) / 2) * n_frames / (s4_avg_ms * 1e-3) / 1e12}
     if args.precision != "fp32":
         if args.precision == "bf16x3":
-            # per 64 x 64 tile and chunk: 4 waves x (4 K steps x 5 sums + 1) MFMA 32x32x16
-            mfma_flops = n_tiles * n_chunks * 4 * 21 * (32 * 32 * 16 * 2)
+            # per 64 x 64 tile and chunk: 4 waves x 4 K steps x 5 sums MFMA 32x32x16
+            mfma_flops = n_tiles * n_chunks * 4 * 20 * (32 * 32 * 16 * 2)
         else:
             # per 64 x 64 tile and chunk: 4 waves x 4 blocks x 5 sums MFMA 16x16x32 (one K step)
             mfma_flops = n_tiles * n_chunks * 4 * 4 * 5 * (16 * 16 * 32 * 2)
@@ -396,12 +484,16 @@ def main(argv=None):
             del out_
         log(f"sequential {sequential['chunks_per_s']:.3e} chunks/s")
 
-    batching = run_batching(torch, dev, args.precision) if args.batching else None
-    streaming = run_streaming(torch, dev, args.precision) if args.streaming else None
+    batching = None if args.no_batching else run_batching(torch, dev, args.precision)
+    streaming = None if args.no_streaming else run_streaming(torch, dev, args.precision)
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(z, estimator=args.estimator)
-    if cpu:
-        log(f"cpu baseline {cpu['value']:.3e} samples/s")
+    cpu, acc = None, None
+    if not args.no_cpu_baseline:
+        cpu, ref, n_ref = cpu_baseline(z, estimator=args.estimator)
+        log(f"cpu baseline {cpu['value']:.3e} samples/s on {cpu['cores']} workers "
+            f"(single thread {cpu['single_thread']['value']:.3e})")
+        acc = accuracy(torch, dev, plan, z, ref, n_ref)
+        log(f"accuracy vs oracle: {acc['max_rel_err']}")
 
     # Achieved HBM rates of the bandwidth-bound stages from their algorithmic
     # bytes per step: the FFT reads the samples of every full chunk and writes
@@ -439,11 +531,16 @@ def main(argv=None):
             "peak": PEAK_FP32_VALU_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VALU_TFLOPS,
+            "peak_note": "78.6 TFLOP/s = 256 CU x 64 lanes x FMA x 2.4 GHz without packed-FP32 issue "
+                         "(the library is built without packed FP32); vendor vector figure 157.3",
+            "vendor_peak": VENDOR_FP32_VECTOR_TFLOPS,
+            "frac_of_vendor_peak": achieved / VENDOR_FP32_VECTOR_TFLOPS,
             "traffic": s3_traffic() if args.estimator == "kstat" else None,
             "avg_launch_ms": s3_avg_ms,
             "flops_per_launch": s3_flops_per_launch(s3_rows, NF),
         },
         "cpu_baseline": cpu,
+        "accuracy": acc,
         "paths": {"main": args.precision, "main_value": value, "batched_fp32": batched_fp32,
                   "per_chunk_fp32": plain,
                   "speedup_vs_batched_fp32": (value / batched_fp32) if batched_fp32 else None,

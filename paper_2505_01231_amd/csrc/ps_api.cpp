@@ -411,8 +411,7 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 part += ps::Sched{sg.n_tiles, q.Np, sg.blocks}.n_slots() * sg.ncomp * (single ? TT : TX);
                 sg.out = o && o->d_s4 ? o->d_s4 + 2 * i * nf2 : nullptr;
                 sg.err = o && o->d_s4_err ? o->d_s4_err + 2 * i * nf2 : nullptr;
-                // the BF16 x 3 matrix-core S4 kernels sum the numerator scaled by m(m+1)
-                sg.scale = p->precision == PS_PREC_BF16X3 ? scale4 / c4a : scale4;
+                sg.scale = scale4;
                 sg.sym = sym;
                 (single ? G.s4s : G.s4x).add(sg, sg.blocks);
                 finalize(G.f4, fin4, i, sg, (int64_t)sg.n_tiles * ((single ? TT : TX) / 256));
@@ -1000,9 +999,7 @@ ps::BatchArgs batch_args(const ps_plan_s* p, const Batch& B, const SegTable& t, 
     a.win_hi = win_hi;
     a.accumulate = accumulate;
     const bool nat = p->estimator == PS_EST_NATURAL;
-    a.c4a = nat ? p->m : p->m * (p->m + 1);
-    a.c4b = nat ? 1 : p->m - 1;
-    a.gamma = (double)a.c4b / a.c4a;
+    a.gamma = nat ? 1.0 / p->m : (p->m - 1.0) / (p->m * (p->m + 1.0));
     a.s4_shift = p->s4_shift;
     a.s3_fb = p->s3_fb;
     return a;

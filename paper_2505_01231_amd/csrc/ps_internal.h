@@ -176,10 +176,8 @@ struct BatchArgs {
     // processed and chunk c sits at frame (c - win_lo) m of the region.
     int per_chunk, win_lo, win_hi;
     int accumulate;         // add to the partial sums instead of overwriting
-    // S4 numerator v = c4a M4 - c4b (p_k p_l + |Q|^2 + |R|^2) with integer
-    // coefficients: (m(m+1), m-1) for the k-statistic, (m, 1) for the natural
-    // estimator; gamma = c4b / c4a for the kernels that form M4 - gamma (...)
-    int c4a, c4b;
+    // S4 kernels form v = M4 - gamma (p_k p_l + |Q|^2 + |R|^2) in FP64:
+    // gamma = (m-1)/(m(m+1)) for the k-statistic, 1/m for the natural estimator
     double gamma;
     int s4_shift;           // S4 planes: a, d at +q columns, b, c at -q (cross-channel kernels only)
     int s3_fb;              // S3 frames per LDS batch (10, 11 or 16); 0: chosen by the rows per chunk

@@ -468,14 +468,14 @@ __global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(BatchArgs p) {
 // of bank conflicts at that stride).  Wave w owns the 32 x 32 quadrant
 // (k0 + 32 (w / 2), l0 + 32 (w % 2)) of the tile with five accumulators X, U,
 // V, Y, M4, so all five sums of a grid point sit in the same lane and register
-// and the k-statistic combination runs there.  The kernel accumulates the
-// k-statistic numerator with integer coefficients, exact in FP32,
-//   v = m(m+1) M4 - (m-1) (p_k p_l + 2 (X^2 + Y^2 + U^2 + V^2)),
-// (the finalize scale carries 1 / (m(m+1))): a rounded gamma = (m-1)/(m(m+1))
-// would bias every chunk alike.  The k-side P row holds m(m+1) P, and the term
-// -(m-1) p_k p_l enters the M4 contraction as one more K step (the split terms
-// of -(m-1) p_k and p_l in slots 0..5), so per grid point and chunk the
-// epilogue is v = M4' - 2 (m-1) (X^2 + Y^2 + U^2 + V^2) plus the FP64 chunk sums.
+// and the k-statistic combination runs there.  The frame sums leave the matrix
+// cores as FP32; the cancellation-prone combination (Section 4.1, eq. c4 in
+// the centred form of Appendix H) is formed from them in FP64,
+//   v = M4 - gamma (p_k p_l + 2 (X^2 + Y^2 + U^2 + V^2)),  gamma = (m-1)/(m(m+1)),
+// with the squares, the product p_k p_l and the subtraction in double (gamma
+// rounded to double biases v by at most 2^-53 of the subtracted term), then
+// added to the FP64 chunk sums.  p_k and p_l are the FP32 frame sums of P,
+// kept per column in LDS as doubles (the k side pre-multiplied by -gamma).
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float floatx2_t __attribute__((ext_vector_type(2)));
@@ -514,26 +514,14 @@ __device__ __forceinline__ void split_words(float x, uint32_t& w0, uint32_t& w1,
     }
 }
 
-// Operand words for one extra K step holding a single product a.b (split as
-// above): lanes 0..31 carry slots 0..7 = [6 terms, 0, 0], lanes 32..63 zeros.
-template <int SIDE>
-__device__ __forceinline__ bf16x8_t single_term(float x, bool live) {
-    uint32_t w0, w1, w2;
-    split_words<SIDE>(x, w0, w1, w2);
-    const u32x4_t u = {live ? w0 : 0u, live ? w1 : 0u, live ? w2 : 0u, 0u};
-    return __builtin_bit_cast(bf16x8_t, u);
-}
-
 __device__ __forceinline__ float xor1(float v) {        // value of the neighbouring lane (lane ^ 1)
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
 }
 
 // Stage one batch of this thread's frame slots (frames half + 2j) of column
-// `col` into the operand rows of its side (the P row scaled by pscale);
-// returns the sum of P over them.
+// `col` into the operand rows of its side; returns the sum of P over them.
 template <int SIDE>
-__device__ __forceinline__ float stage_rows(uint32_t (*op)[kOpDw], int col, int half, const float2 (&pre)[kMfmaFrames / 2],
-                                            float pscale) {
+__device__ __forceinline__ float stage_rows(uint32_t (*op)[kOpDw], int col, int half, const float2 (&pre)[kMfmaFrames / 2]) {
     float pa = 0.f;
 #pragma unroll
     for (int j = 0; j < kMfmaFrames / 2; ++j) {
@@ -544,7 +532,7 @@ __device__ __forceinline__ float stage_rows(uint32_t (*op)[kOpDw], int col, int 
         uint32_t a0, a1, a2, b0, b1, b2, e0, e1, e2;
         split_words<SIDE>(re, a0, a1, a2);
         split_words<SIDE>(im, b0, b1, b2);
-        split_words<SIDE>(P * pscale, e0, e1, e2);
+        split_words<SIDE>(P, e0, e1, e2);
         uint32_t* wr = &op[col][3 * f];
         uint32_t* wi = &op[kTile + col][3 * f];
         uint32_t* wp = &op[2 * kTile + col][3 * f];
@@ -560,7 +548,7 @@ template <bool ONE_BATCH>
 __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
     __shared__ __attribute__((aligned(16))) uint32_t opK[3 * kTile][kOpDw];
     __shared__ __attribute__((aligned(16))) uint32_t opL[3 * kTile][kOpDw];
-    __shared__ float psum[2][kTile];
+    __shared__ double psum[2][kTile];          // -gamma p_k (k side), p_l (l side)
 
     Block bk;
     View v;
@@ -587,9 +575,8 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
         row[3 * kMfmaFrames] = 0u;
         row[3 * kMfmaFrames + 1] = 0u;
     }
-    const float cm1 = (float)p.c4a;                     // m(m+1) (natural: m), exact
-    const float cm2 = (float)p.c4b;                     // m-1 (natural: 1)
-    const float m2c = -2.0f * cm2;
+    const double gamma = p.gamma;                       // (m-1)/(m(m+1)) (natural: 1/m)
+    const double m2g = -2.0 * gamma;
 
     Item it;
     while (next_item<kTile, 2>(p, bk, it)) {
@@ -628,10 +615,10 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
         const bool first = ONE_BATCH || fbi == 0, last = ONE_BATCH || fbi == per_chunk - 1;
         if (first) pacc = 0.f;
         lds_barrier();
-        pacc += side == 0 ? stage_rows<0>(op, col, half, pre, cm1) : stage_rows<1>(op, col, half, pre, 1.0f);
+        pacc += side == 0 ? stage_rows<0>(op, col, half, pre) : stage_rows<1>(op, col, half, pre);
         if (last) {
-            const float tot = pacc + xor1(pacc);          // p over the chunk's frames
-            if (half == 0) psum[side][col] = tot;
+            const float tot = pacc + xor1(pacc);          // p over the chunk's frames (FP32 sum)
+            if (half == 0) psum[side][col] = side == 0 ? -gamma * (double)tot : (double)tot;
         }
         lds_barrier();
         // Four K steps of 16 slots (the scheduling barrier keeps each step's
@@ -664,12 +651,6 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
             }
             __builtin_amdgcn_sched_barrier(0);
         }
-        if (last) {
-            // M4' = m(m+1) M4 - (m-1) p_k p_l: one more contraction step
-            const bf16x8_t xa = single_term<0>(-cm2 * psum[0][rowK], kh == 0);
-            const bf16x8_t xb = single_term<1>(psum[1][rowL], kh == 0);
-            d[4] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa, xb, d[4], 0, 0, 0);
-        }
         __builtin_amdgcn_s_setprio(0);
         // Next batch's loads overlap the epilogue.
         if (b + 1 < n_batches) fetch(b + 1);
@@ -677,11 +658,14 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
 
         // Register r of lane (kh, r32) is grid point
         // k = k0 + 32 (w / 2) + 8 (r / 4) + 4 kh + r % 4, l = l0 + 32 (w % 2) + r32.
+        // The k-statistic combination in FP64.
+        const double pl = psum[1][rowL];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const float X = d[0][r], U = d[1][r], V = d[2][r], Y = d[3][r];
-            const float sq = fmaf(X, X, fmaf(Y, Y, fmaf(U, U, V * V)));
-            const double val = (double)fmaf(m2c, sq, d[4][r]);
+            const double X = d[0][r], U = d[1][r], V = d[2][r], Y = d[3][r];
+            const double sq = fma(X, X, fma(Y, Y, fma(U, U, V * V)));
+            const double npk = psum[0][32 * (w >> 1) + 8 * (r >> 2) + 4 * kh + (r & 3)];
+            const double val = fma(m2g, sq, fma(npk, pl, (double)d[4][r]));
             acc[r][0] += val;
             acc[r][1] = fma(val, val, acc[r][1]);
         }
@@ -880,10 +864,10 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16(BatchArgs p) {
                 const int ll = lb * 16 + li;
                 const float pl = psum[1][0][ll] + psum[1][1][ll];
                 const float sig = s2k * sc2[1][ll];           // (s_k s_l)^2, a power of two
-                const float X = d[lb][0][e], U = d[lb][1][e], V = d[lb][2][e], Y = d[lb][3][e];
-                const float sq = fmaf(X, X, fmaf(Y, Y, fmaf(U, U, V * V)));
-                const float q = fmaf(2.0f * sig, sq, pk * pl);
-                const double val = fma(-gamma_d, (double)q, (double)(d[lb][4][e] * sig));
+                const double X = d[lb][0][e], U = d[lb][1][e], V = d[lb][2][e], Y = d[lb][3][e];
+                const double sq = fma(X, X, fma(Y, Y, fma(U, U, V * V)));
+                const double q = fma(2.0 * (double)sig, sq, (double)pk * (double)pl);
+                const double val = fma(-gamma_d, q, (double)d[lb][4][e] * (double)sig);
                 acc[lb][e][0] += val;
                 acc[lb][e][1] = fma(val, val, acc[lb][e][1]);
             }
@@ -1049,22 +1033,21 @@ __global__ __launch_bounds__(kS4XThreads, 2) void k_s4_cross(BatchArgs p) {
 // (16 (w / 2), 16 (w % 2)) with 20 accumulators of 4 registers, lane (lg, li)
 // holding grid points (4 lg + e, li).  LDS rows are 160 bytes apart, a stride
 // at which the 16-row, 16-byte-per-lane operand reads of 16x16x32 are free of
-// bank conflicts.  As in k_s4_mfma_bf16 the kernel forms the k-statistic
-// numerator with integer coefficients,
-//   v = m(m+1) sum E F - (m-1) T,  T = e f + G_ac conj(G_bd) + H_ad conj(H_bc),
-// in FP32 (the k-side E rows hold m(m+1) E, so the E.F Grams give the first
-// term; the finalize scale carries 1 / (m(m+1))), and only the chunk sums in
-// FP64.
+// bank conflicts.  As in k_s4_mfma_bf16 the Grams leave the matrix cores as
+// FP32 and everything after them is FP64: the complex frame sums are
+// assembled from the real Grams, and the k-statistic combination
+//   v = sum E F - gamma T,  T = e f + G_ac conj(G_bd) + H_ad conj(H_bc),
+// gamma = (m-1)/(m(m+1)), is formed in double before the FP64 chunk sums.
 constexpr int kOpDwX = 40;           // 32-bit words per LDS operand row (160 B; 32 used)
 constexpr int kS4XMThreads = 256;
 constexpr int kCrossSlots = 3;       // frame slots q, q + 4, q + 8 of a loader thread
 
 // Stage this thread's frame slots of column `col`: P = x conj(y) and the split
-// words of (pscale Re P, pscale Im P, Re x, Im x, Re y, Im y) into row types
-// 0..5; returns the sum of P (unscaled) over the slots.
+// words of (Re P, Im P, Re x, Im x, Re y, Im y) into row types 0..5; returns
+// the sum of P over the slots.
 template <int SIDE>
 __device__ __forceinline__ float2 stage_cross(uint32_t (*op)[kOpDwX], int col, int q, const float2 (&px)[kCrossSlots],
-                                              const float2 (&py)[kCrossSlots], float pscale) {
+                                              const float2 (&py)[kCrossSlots]) {
     float2 pa = make_float2(0.f, 0.f);
 #pragma unroll
     for (int j = 0; j < kCrossSlots; ++j) {
@@ -1074,7 +1057,7 @@ __device__ __forceinline__ float2 stage_cross(uint32_t (*op)[kOpDwX], int col, i
         const float2 P = make_float2(fmaf(x.x, y.x, x.y * y.y), fmaf(x.y, y.x, -(x.x * y.y)));
         pa.x += P.x;
         pa.y += P.y;
-        const float val[6] = {P.x * pscale, P.y * pscale, x.x, x.y, y.x, y.y};
+        const float val[6] = {P.x, P.y, x.x, x.y, y.x, y.y};
 #pragma unroll
         for (int t = 0; t < 6; ++t) {
             uint32_t w0, w1, w2;
@@ -1119,8 +1102,7 @@ __global__ __launch_bounds__(kS4XMThreads, 2) void k_s4_cross_mfma(BatchArgs p) 
         row[3 * kMfmaFrames] = 0u;
         row[3 * kMfmaFrames + 1] = 0u;
     }
-    const float cm1 = (float)p.c4a;                     // m(m+1) (natural: m), exact
-    const float cm2 = (float)p.c4b;                     // m-1 (natural: 1)
+    const double gamma = p.gamma;                       // (m-1)/(m(m+1)) (natural: 1/m)
 
     Item it;
     while (next_item<kTileX, 4>(p, bk, it)) {
@@ -1164,7 +1146,7 @@ __global__ __launch_bounds__(kS4XMThreads, 2) void k_s4_cross_mfma(BatchArgs p) 
         if (first) pacc = make_float2(0.f, 0.f);
         lds_barrier();
         {   // E = x conj(y) (k side: a b*, l side: c d*)
-            const float2 pa = side == 0 ? stage_cross<0>(op, col, q, px, py, cm1) : stage_cross<1>(op, col, q, px, py, 1.0f);
+            const float2 pa = side == 0 ? stage_cross<0>(op, col, q, px, py) : stage_cross<1>(op, col, q, px, py);
             pacc.x += pa.x;
             pacc.y += pa.y;
         }
@@ -1200,24 +1182,30 @@ __global__ __launch_bounds__(kS4XMThreads, 2) void k_s4_cross_mfma(BatchArgs p) 
         if (b + 1 < n_batches) fetch(b + 1);
         if (!last) continue;
 
+        const float2 fl32 = psum[1][rowB];
+        const double flr = fl32.x, fli = fl32.y;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const float2 ek = psum[0][16 * (w >> 1) + 4 * lg + e], fl = psum[1][rowB];
-            // complex sums from the real Grams (sum E F scaled by m(m+1))
-            const float sef_r = d[0][e] - d[1][e], sef_i = d[2][e] + d[3][e];
-            const float gac_r = d[4][e] - d[5][e], gac_i = d[6][e] + d[7][e];
-            const float hbc_r = d[8][e] + d[9][e], hbc_i = d[11][e] - d[10][e];
-            const float gbd_r = d[12][e] - d[13][e], gbd_i = d[14][e] + d[15][e];
-            const float had_r = d[16][e] + d[17][e], had_i = d[19][e] - d[18][e];
+            const float2 ek = psum[0][16 * (w >> 1) + 4 * lg + e];
+            double g[20];
+#pragma unroll
+            for (int i = 0; i < 20; ++i) g[i] = d[i][e];
+            // complex frame sums from the real Grams, in FP64
+            const double sef_r = g[0] - g[1], sef_i = g[2] + g[3];
+            const double gac_r = g[4] - g[5], gac_i = g[6] + g[7];
+            const double hbc_r = g[8] + g[9], hbc_i = g[11] - g[10];
+            const double gbd_r = g[12] - g[13], gbd_i = g[14] + g[15];
+            const double had_r = g[16] + g[17], had_i = g[19] - g[18];
             // T = e f + G_ac conj(G_bd) + H_ad conj(H_bc)
-            float tr = fmaf(ek.x, fl.x, -(ek.y * fl.y));
-            float ti = fmaf(ek.x, fl.y, ek.y * fl.x);
-            tr = fmaf(gac_r, gbd_r, fmaf(gac_i, gbd_i, tr));
-            ti = fmaf(gac_i, gbd_r, fmaf(-gac_r, gbd_i, ti));
-            tr = fmaf(had_r, hbc_r, fmaf(had_i, hbc_i, tr));
-            ti = fmaf(had_i, hbc_r, fmaf(-had_r, hbc_i, ti));
-            const double vr = (double)fmaf(-cm2, tr, sef_r);
-            const double vi = (double)fmaf(-cm2, ti, sef_i);
+            const double ekr = ek.x, eki = ek.y;
+            double tr = fma(ekr, flr, -(eki * fli));
+            double ti = fma(ekr, fli, eki * flr);
+            tr = fma(gac_r, gbd_r, fma(gac_i, gbd_i, tr));
+            ti = fma(gac_i, gbd_r, fma(-gac_r, gbd_i, ti));
+            tr = fma(had_r, hbc_r, fma(had_i, hbc_i, tr));
+            ti = fma(had_i, hbc_r, fma(-had_r, hbc_i, ti));
+            const double vr = fma(-gamma, tr, sef_r);
+            const double vi = fma(-gamma, ti, sef_i);
             acc[e][0] += vr;
             acc[e][1] += vi;
             acc[e][2] = fma(vr, vr, acc[e][2]);
