@@ -23,9 +23,21 @@
  * Conventions shared by every entry point:
  *  - Every pointer named d_* is a device (HBM) pointer on the current HIP
  *    device; every other pointer is host memory.  The caller owns all device
- *    buffers (inputs, workspace, outputs); the library allocates device memory
- *    only inside ps_plan_create (window and twiddle tables, owned by the plan,
- *    freed by ps_plan_destroy).
+ *    buffers it passes (inputs, workspace, outputs).  The library allocates
+ *    memory only in these calls, each freed by the matching destroy:
+ *      ps_plan_create        window, twiddle and tile tables (device) and, on
+ *                            the first execute, a pinned host staging area for
+ *                            the work tables (grown when an execute needs more)
+ *                            -> ps_plan_destroy;
+ *      ps_graph_create       the graph's work tables (device) -> ps_graph_destroy;
+ *      ps_streamer_create(_multi)  staging slots and workspace (device)
+ *                            -> ps_streamer_destroy;
+ *      ps_stream_begin       accumulator state, carry buffer, workspace and work
+ *                            tables (device) -> ps_stream_destroy.
+ *    ps_execute, ps_execute_sequential, ps_coefficients, ps_full_plane,
+ *    ps_spectra_zscore and the push / launch / end calls allocate no device
+ *    memory; ps_plan_autotune creates two events and destroys them before it
+ *    returns.
  *  - Calls that take a stream only enqueue work on it and return; results are
  *    valid after the caller synchronises that stream.  A plan must not be used
  *    by two streams at the same time.
@@ -204,9 +216,16 @@ typedef struct ps_plan_info {
     const int8_t* combos4;
 } ps_plan_info;
 
-/* Validate `cfg`, build the window (FP64 on the host) and the FFT tables, and
- * pick launch shapes.  Allocates the plan's small device tables on the current
- * device (synchronous).  On failure *out is NULL. */
+/* Validate `cfg`, build the window (FP64 on the host: Hann, or the confined
+ * Gaussian of Appendix B) and the FFT tables of eq. a_k (Section 3), enumerate
+ * the channel-combination orbits (Section 9) and pick launch shapes.
+ * Validation follows the estimator's definitions: m >= order (the
+ * denominators of eq. c2..c4, Section 4.1); 2 (N_f - 1) <= N/2 when S3 is
+ * requested (its third factor a_{k+l}, Section 4), else N_f - 1 <= N/2;
+ * N a power of two in 256..8192.  Allocates the plan's small device tables on
+ * the current device (synchronous).  On failure *out is NULL and the status
+ * is PS_E_INVALID_ARG (a parameter out of range), PS_E_UNSUPPORTED (allowed by
+ * the paper, not built here, e.g. N not a power of two) or PS_E_HIP. */
 ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out);
 
 /* Free the plan and its device tables (synchronous).  NULL is accepted. */
@@ -218,13 +237,24 @@ ps_status ps_plan_query(ps_plan_t plan, ps_plan_info* info);
  * interlaced windows: of the frame set that starts at sample 0). */
 ps_status ps_record_info(ps_plan_t plan, int64_t n_samples, int64_t* n_chunks, uint32_t* flags);
 
-/* Device workspace (bytes) that ps_execute needs for these records. */
+/* Device workspace (bytes) that ps_execute needs for these records: the
+ * FP32 Fourier coefficients of every frame of every complete chunk (eq. a_k,
+ * K = 2 N_f - 1 per frame with S3, else N_f; chunks as in Section 4.2), the
+ * work tables and the FP64 partial sums over chunks.  Host only; records are
+ * validated as by ps_execute (PS_E_INVALID_ARG). */
 ps_status ps_workspace_size(ps_plan_t plan, const ps_record* recs, int32_t n_rec, size_t* bytes);
 
 /* Enqueue the whole estimator for n_rec records on `stream`: windowed real FFT
- * per frame, per-chunk centring and moment sums, k-statistics, FP64 chunk
- * average and error bars.  outs[i] receives record i.  d_ws must be 256-byte
- * aligned and at least ps_workspace_size() bytes; its contents are scratch. */
+ * per frame (Section 3, eq. a_k), per-chunk centring and moment sums, the
+ * k-statistics of Section 4.1 (eq. c2..c4; multichannel arguments of
+ * Section 7), the spectra's normalisation (Sections 3 and 4), and the FP64
+ * chunk average with the error bars of Section 4.2.  recs[i] is read-only;
+ * outs[i] (caller-owned, layouts of ps_output) receives record i; a record
+ * without a complete chunk gets NaN outputs.  d_ws must be 256-byte aligned
+ * and at least ps_workspace_size() bytes; its contents are scratch.
+ * Errors (nothing enqueued): PS_E_INVALID_ARG for NULL, misaligned or
+ * inconsistent arguments, PS_E_WORKSPACE for a small workspace, PS_E_HIP when
+ * a launch fails. */
 ps_status ps_execute(ps_plan_t plan, const ps_record* recs, int32_t n_rec, void* d_ws,
                      size_t ws_bytes, const ps_output* outs, ps_stream_t stream);
 
@@ -317,6 +347,69 @@ ps_status ps_streamer_create_multi(ps_plan_t plan, int64_t window_samples, int32
                                    int32_t depth, ps_streamer_t* out);
 ps_status ps_streamer_push_multi(ps_streamer_t s, const void* h_pinned, int32_t n_windows, const ps_output* outs,
                                  ps_stream_t compute, int32_t* slot);
+
+/* Running accumulation over one long record delivered in pieces, with
+ * checkpoint and resume.  Section 4.2 estimates a spectrum and its error bar
+ * from the parts (chunks) only through the sums over chunks of each chunk's
+ * estimate x and of (Re x)^2 and (Im x)^2, and their count Np; these sums are
+ * the whole state of the estimate, so an accumulation can be stopped, saved
+ * and continued exactly.  The record's samples arrive as consecutive pushes of
+ * any length; frames and chunks are cut from the concatenated sample sequence
+ * exactly as ps_execute cuts one record (samples that do not complete a chunk
+ * wait in a carry buffer for the next push).
+ *
+ *   ps_stream_begin(plan, max_push_samples, dtype, out)
+ *       allocates (device) the FP64 state, the carry buffer of m N samples per
+ *       channel, the work tables and a workspace for pushes of up to
+ *       max_push_samples samples per channel; the state starts empty.  Needs a
+ *       plan with the batched schedule and without interlaced windows
+ *       (PS_E_UNSUPPORTED otherwise).  Freed by ps_stream_destroy.
+ *   ps_stream_push(s, d_data, n_samples, channel_stride, stream)
+ *       appends n_samples samples per channel (0 <= n_samples <=
+ *       max_push_samples; element type `dtype`; channel c at d_data + c *
+ *       channel_stride elements) and enqueues on `stream` the estimator for
+ *       every chunk the sequence now completes, adding its sums to the state.
+ *       d_data must stay valid until the stream has run the push.
+ *   ps_stream_end(s, out, stream)
+ *       enqueues the finalize of the state (mean and error bars as ps_execute
+ *       gives them, NaN without a complete chunk) into `out`; the state is
+ *       kept, so pushes may continue afterwards.
+ *   ps_stream_counts(s, n_chunks, n_samples, n_carry)
+ *       host counters: chunks accumulated, samples pushed, samples waiting.
+ *   ps_stream_export_state(s, h_buf, n_bytes)
+ *       waits for the pushes enqueued so far, then writes the state (a header
+ *       naming the plan's configuration and the dtype, the counters, the FP64
+ *       sums and the carried samples) to host memory.  With h_buf == NULL only
+ *       *n_bytes is set (the size); otherwise *n_bytes is the capacity on input
+ *       (PS_E_INVALID_ARG if too small) and the size written on output.
+ *   ps_stream_import_state(s, h_buf, n_bytes)
+ *       replaces the state of `s` by an exported one (synchronous).
+ *       PS_E_INVALID_ARG unless it was exported by a stream of the same
+ *       configuration (frame length, N_f, m, channels, orders, combinations,
+ *       window, dt, precision, estimator, signal type) and dtype.
+ * Resuming from an exported state and pushing the remaining samples gives the
+ * same outputs, bit for bit, as one uninterrupted stream.  Pushes to one
+ * stream must be enqueued from one host thread on the same `stream`. */
+typedef struct ps_accum_s* ps_accum_t;
+ps_status ps_stream_begin(ps_plan_t plan, int64_t max_push_samples, int32_t dtype, ps_accum_t* out);
+ps_status ps_stream_push(ps_accum_t s, const void* d_data, int64_t n_samples, int64_t channel_stride,
+                         ps_stream_t stream);
+ps_status ps_stream_end(ps_accum_t s, const ps_output* out, ps_stream_t stream);
+ps_status ps_stream_counts(ps_accum_t s, int64_t* n_chunks, int64_t* n_samples, int64_t* n_carry);
+ps_status ps_stream_export_state(ps_accum_t s, void* h_buf, size_t* n_bytes);
+ps_status ps_stream_import_state(ps_accum_t s, const void* h_buf, size_t n_bytes);
+ps_status ps_stream_destroy(ps_accum_t s);
+
+/* Per-point comparison of two estimates of the same spectrum, e.g. quasi-
+ * spectra computed with different m (Section 8: a spectrum that changes with m
+ * beyond its error bars points to non-stationarity): d_out[i] =
+ * |a_i - b_i| / sqrt(sa_i^2 + sb_i^2), for the real and the imaginary parts of
+ * n_points complex values (arrays [n_points][2] in the layouts of ps_output:
+ * spectra and their error-bar pairs).  0/0 gives NaN.  Enqueued on `stream`.
+ * A descriptive statistic, not a test with a known distribution when both
+ * estimates come from the same data. */
+ps_status ps_spectra_zscore(const double* d_a, const double* d_a_err, const double* d_b, const double* d_b_err,
+                            int64_t n_points, double* d_out, ps_stream_t stream);
 
 /* The first stage alone (Section 3, eq. a_k without the dt factor): for every
  * frame f < Np*m of every channel, d_coef[c][f][k] = sum_i g_i z_{fN+i}

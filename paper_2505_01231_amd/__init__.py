@@ -6,11 +6,13 @@ load it.
 """
 import importlib
 
-__all__ = ["Plan", "Spectra", "Graph", "Streamer", "enumerate_combos", "quasi_spectra", "m_dependence", "synth"]
+__all__ = ["Plan", "Spectra", "Graph", "Streamer", "Accumulator", "enumerate_combos", "quasi_spectra", "m_dependence",
+           "synth"]
 
 
 def __getattr__(name):
-    if name in ("Plan", "Spectra", "Graph", "Streamer", "enumerate_combos", "quasi_spectra", "m_dependence"):
+    if name in ("Plan", "Spectra", "Graph", "Streamer", "Accumulator", "enumerate_combos", "quasi_spectra",
+                "m_dependence"):
         return getattr(importlib.import_module(__name__ + ".polyspec"), name)
     if name == "synth":
         return importlib.import_module(__name__ + ".synth")

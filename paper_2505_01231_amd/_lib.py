@@ -28,6 +28,8 @@ EXPORTED = (
     "ps_streamer_wait", "ps_streamer_destroy", "ps_streamer_create_multi", "ps_streamer_push_multi",
     "ps_plan_get_tuning", "ps_plan_set_tuning", "ps_plan_autotune",
     "ps_sequential_workspace_size", "ps_execute_sequential", "ps_full_plane",
+    "ps_stream_begin", "ps_stream_push", "ps_stream_end", "ps_stream_counts", "ps_stream_export_state",
+    "ps_stream_import_state", "ps_stream_destroy", "ps_spectra_zscore",
 )
 PS_TUNE_MAX = 16
 
@@ -127,6 +129,19 @@ def load() -> C.CDLL:
     lib.ps_plan_set_tuning.argtypes = [vp, C.POINTER(ps_tuning)]
     lib.ps_plan_autotune.argtypes = [vp, C.POINTER(ps_record), i32, vp, sz, C.POINTER(ps_output), i32, vp,
                                      C.POINTER(ps_tune_report)]
+    lib.ps_stream_begin.argtypes = [vp, i64, i32, C.POINTER(vp)]
+    lib.ps_stream_push.argtypes = [vp, vp, i64, i64, vp]
+    lib.ps_stream_end.argtypes = [vp, C.POINTER(ps_output), vp]
+    lib.ps_stream_counts.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    lib.ps_stream_export_state.argtypes = [vp, vp, C.POINTER(sz)]
+    lib.ps_stream_import_state.argtypes = [vp, vp, sz]
+    lib.ps_stream_destroy.argtypes = [vp]
+    lib.ps_spectra_zscore.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+    for name in ("ps_stream_begin", "ps_stream_push", "ps_stream_end", "ps_stream_counts",
+                 "ps_stream_export_state", "ps_stream_import_state", "ps_stream_destroy", "ps_spectra_zscore",
+                 "ps_sequential_workspace_size", "ps_execute_sequential", "ps_full_plane",
+                 "ps_plan_get_tuning", "ps_plan_set_tuning", "ps_plan_autotune"):
+        getattr(lib, name).restype = C.c_int
     for name in ("ps_plan_create", "ps_plan_destroy", "ps_plan_query", "ps_record_info",
                  "ps_workspace_size", "ps_execute", "ps_coefficients", "ps_enumerate_combos",
                  "ps_profile_enable", "ps_profile_read", "ps_graph_create", "ps_graph_launch",

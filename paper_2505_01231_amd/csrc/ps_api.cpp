@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -229,10 +230,14 @@ struct SegTable {
 
 // One set of launches: every record (batched schedule) or one record
 // (per-chunk schedule).
+// (The list of tables is a function, not a stored array of pointers: groups
+// live in a vector, and a copied group must not point into its original.)
 struct Group {
     int rec = -1;           // record of a per-chunk group
     SegTable s2, s3, s4s, s4x, f2, f3, f4, f1;
-    SegTable* all[8] = {&s2, &s3, &s4s, &s4x, &f2, &f3, &f4, &f1};
+    SegTable acc;           // running accumulation (ps_stream_push) instead of f2..f4
+    std::array<SegTable*, 9> all() { return {&s2, &s3, &s4s, &s4x, &f2, &f3, &f4, &f1, &acc}; }
+    std::array<const SegTable*, 9> all() const { return {&s2, &s3, &s4s, &s4x, &f2, &f3, &f4, &f1, &acc}; }
 };
 
 // With interlaced windows every caller record r becomes two internal records:
@@ -258,22 +263,37 @@ size_t elem_size(int dtype) {
     return dtype == PS_F32 ? 4 : dtype == PS_F64 ? 8 : dtype == PS_I16 ? 2 : dtype == PS_C64 ? 8 : 16;
 }
 
+// Finalize scales of each order: the estimator's prefactor (k-statistics of
+// Section 4.1, or the natural estimator of Section 6: c2 = s2 / m, c3 = t3 / m,
+// c4 = (m M4 - pairs) / m^2) times dt^(n-1) / sum g^n (Sections 3 and 4);
+// s4 goes with the kernels' form M4 - gamma (pairs).
+struct Scales {
+    double s1, s2, s3, s4;
+};
+Scales spectrum_scales(const ps_plan_s* p) {
+    const int m = p->m;
+    const double dt = p->dt;
+    const bool nat = p->estimator == PS_EST_NATURAL;
+    const double c4a = nat ? m : m * (m + 1.0);
+    Scales sc;
+    sc.s1 = 1.0 / p->sum_g[1];
+    sc.s2 = dt / ((nat ? m : m - 1) * p->sum_g[2]);
+    // c3^(opt): the S3 sum over the m + 1 rows of each chunk times (m+4)/((m+1) m)
+    const double c3f = p->c3opt() ? (m + 4.0) / ((m + 1.0) * m) : nat ? 1.0 / m : m / ((double)(m - 1) * (m - 2));
+    sc.s3 = dt * dt * c3f / p->sum_g[3];
+    sc.s4 = dt * dt * dt * c4a / ((nat ? (double)m * m : (double)(m - 1) * (m - 2) * (m - 3)) * p->sum_g[4]);
+    return sc;
+}
+
+void finish_layout(const ps_plan_s* p, Batch& B);
+
 void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_output* outs, Batch& B) {
     const bool per_chunk = p->schedule == PS_SCHED_PER_CHUNK;
     const int m = p->m, K = p->K, Nf = p->Ng;      // Nf: points per output axis
     const int64_t nf2 = (int64_t)Nf * Nf;
-    const double dt = p->dt;
-    // k-statistic prefactors (Section 4.1) or those of the natural estimator
-    // (Section 6: c2 = s2 / m, c3 = t3 / m, c4 = (m M4 - pairs) / m^2), with
-    // dt^(n-1) / sum g^n; scale4 goes with the form M4 - gamma (pairs).
-    const bool nat = p->estimator == PS_EST_NATURAL;
-    const double c4a = nat ? m : m * (m + 1.0);
-    const double scale2 = dt / ((nat ? m : m - 1) * p->sum_g[2]);
-    // c3^(opt): the S3 sum over the m + 1 rows of each chunk times (m+4)/((m+1) m)
+    const Scales scl = spectrum_scales(p);
+    const double scale2 = scl.s2, scale3 = scl.s3, scale4 = scl.s4;
     const bool opt3 = p->c3opt();
-    const double c3f = opt3 ? (m + 4.0) / ((m + 1.0) * m) : nat ? 1.0 / m : m / ((double)(m - 1) * (m - 2));
-    const double scale3 = dt * dt * c3f / p->sum_g[3];
-    const double scale4 = dt * dt * dt * c4a / ((nat ? (double)m * m : (double)(m - 1) * (m - 2) * (m - 3)) * p->sum_g[4]);
     B.stride = p->interlaced ? 2 : 1;
     const int n_int = n * B.stride;
     B.ri.assign(n_int, RecInfo{});
@@ -362,7 +382,7 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                     sg.ch[0] = c;
                     sg.out = o && o->d_s1 ? o->d_s1 + 2 * c : nullptr;
                     sg.err = o && o->d_s1_err ? o->d_s1_err + 2 * c : nullptr;
-                    sg.scale = 1.0 / p->sum_g[1];
+                    sg.scale = scl.s1;
                     finalize(G.f1, fin1, c, sg, 1);
                 }
             }
@@ -419,10 +439,17 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
         }
     }
     B.part_doubles = part;
+    finish_layout(p, B);
+}
+
+// Table region and workspace offsets of a built batch (again after tables
+// were added to its groups).
+void finish_layout(const ps_plan_s* p, Batch& B) {
+    const int K = p->K;
     // table region: record descriptors, then every segment table
     size_t tab = align64(sizeof(ps::RecDesc) * std::max<size_t>(1, B.rd.size()));
     for (Group& G : B.groups)
-        for (SegTable* t : G.all) {
+        for (SegTable* t : G.all()) {
             t->dev_off = tab;
             tab = align64(tab + sizeof(ps::Seg) * t->v.size());
         }
@@ -972,7 +999,7 @@ ps_status upload_tables(ps_plan_t p, const Batch& B, char* d_tab, hipStream_t st
     char* h = p->h_stage[i];
     std::memcpy(h, B.rd.data(), sizeof(ps::RecDesc) * B.rd.size());
     for (const Group& G : B.groups)
-        for (const SegTable* t : G.all)
+        for (const SegTable* t : G.all())
             if (!t->v.empty()) std::memcpy(h + t->dev_off, t->v.data(), sizeof(ps::Seg) * t->v.size());
     PS_HIP(hipMemcpyAsync(d_tab, h, B.tab_bytes, hipMemcpyHostToDevice, st));
     PS_HIP(hipEventRecord(p->h_ev[i], st));
@@ -1083,12 +1110,21 @@ ps_status validate_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, vo
     return PS_OK;
 }
 
-// Every launch of one execution, given device tables at `tab`.
+// The running accumulation of a stream: state sums of S1 (per channel) for
+// launch_accumulate_s1; the other orders' state slots are named by the
+// group's accumulation table.
+struct AccumTarget {
+    double* s1_state;
+};
+
+// Every launch of one execution, given device tables at `tab`.  With `acc`
+// the batch's sums are added to a stream's state (its group's accumulation
+// table) instead of being finalized into outputs.
 ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_t n_rec, const ps_output* outs,
-                      char* ws, const char* tab, hipStream_t st) {
+                      char* ws, const char* tab, hipStream_t st, const AccumTarget* acc = nullptr) {
     const int Nf = p->Ng, m = p->m;
     const int64_t nf2 = (int64_t)Nf * Nf;
-    for (int r = 0; r < n_rec; ++r) {
+    for (int r = 0; r < n_rec && outs; ++r) {
         if (B.ri[r * B.stride].Np > 0) continue;
         const ps_output& o = outs[r];
         PS_HIP(ps::launch_fill_nan(o.d_s2, 2 * (int64_t)p->n2() * Nf, st));
@@ -1155,6 +1191,20 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
         }
         s = launch_moments(p, B, B.groups[0], ws, tab, 0, 0, 0, 0, st);
         if (s != PS_OK) return s;
+        if (acc) {
+            const Group& G = B.groups[0];
+            StageTimer t(p, st, 5);
+            ps::AccumArgs aa{};
+            aa.segs = reinterpret_cast<const ps::Seg*>(tab + G.acc.dev_off);
+            aa.n_segs = (int)G.acc.v.size();
+            aa.n_items = G.acc.n_items;
+            aa.part = reinterpret_cast<const double*>(ws + B.off_part);
+            PS_HIP(ps::launch_accumulate(aa, st));
+            if (p->has(1))
+                PS_HIP(ps::launch_accumulate_s1(reinterpret_cast<const float2*>(ws + B.off_s1), B.chunks_tot,
+                                                B.chunks_tot, p->C, acc->s1_state, st));
+            return PS_OK;
+        }
         return launch_finalize(p, B, B.groups[0], ws, tab, st);
     }
 
@@ -1355,7 +1405,7 @@ ps_status ps_graph_create(ps_plan_t p, const ps_record* recs, int32_t n_rec, voi
     std::vector<char> h(B.tab_bytes);
     std::memcpy(h.data(), B.rd.data(), sizeof(ps::RecDesc) * B.rd.size());
     for (const Group& G : B.groups)
-        for (const SegTable* t : G.all)
+        for (const SegTable* t : G.all())
             if (!t->v.empty()) std::memcpy(h.data() + t->dev_off, t->v.data(), sizeof(ps::Seg) * t->v.size());
     hipError_t e = hipMalloc(&g->d_tab, std::max<size_t>(B.tab_bytes, 256));
     if (e == hipSuccess) e = hipMemcpy(g->d_tab, h.data(), B.tab_bytes, hipMemcpyHostToDevice);
@@ -1526,6 +1576,462 @@ ps_status ps_streamer_push(ps_streamer_t s, const void* h_pinned, const ps_outpu
 ps_status ps_streamer_wait(ps_streamer_t s, int32_t slot) {
     if (!s || slot < 0 || slot >= s->depth) return fail(PS_E_INVALID_ARG, "bad argument");
     if (s->used[slot]) PS_HIP(hipEventSynchronize(s->done[slot]));
+    return PS_OK;
+}
+
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ running accumulation
+// (Section 4.2: the estimate depends on the chunks only through the sums over
+// chunks of x, (Re x)^2, (Im x)^2 and their count, so these sums are the state.)
+namespace {
+
+// The state slots of every spectrum (FP64): per combination the tiles of its
+// grid, [n_tiles][ncomp][points of a tile] (S2: 256-wide k blocks with 4
+// components), then 4 sums per channel for S1.
+struct StateLayout {
+    std::vector<int64_t> off2, off3, off4;
+    int64_t off1 = 0, doubles = 0;
+};
+
+int s4_kind(const ps_plan_s* p, int i) {
+    return p->s4_single(i) ? ps::kSym64 : (p->s4_sym(i) ? ps::kSym32 : ps::kFull32);
+}
+
+StateLayout state_layout(const ps_plan_s* p) {
+    StateLayout L;
+    const int64_t TT = (int64_t)ps::kTile * ps::kTile, TX = (int64_t)ps::kTileX * ps::kTileX;
+    const int64_t kblocks = (p->Ng + 255) / 256;
+    int64_t o = 0;
+    for (int i = 0; i < p->n2(); ++i) {
+        L.off2.push_back(o);
+        o += kblocks * 4 * 256;
+    }
+    for (int i = 0; i < p->n3(); ++i) {
+        L.off3.push_back(o);
+        o += (int64_t)p->n_tiles[p->s3_sym(i) ? ps::kSym64 : ps::kFull64] * 4 * TT;
+    }
+    for (int i = 0; i < p->n4(); ++i) {
+        L.off4.push_back(o);
+        const int kind = s4_kind(p, i);
+        o += kind == ps::kSym64 ? (int64_t)p->n_tiles[kind] * 2 * TT : (int64_t)p->n_tiles[kind] * 4 * TX;
+    }
+    L.off1 = o;
+    if (p->has(1)) o += 4LL * p->C;
+    L.doubles = o;
+    return L;
+}
+
+// FNV-1a over bytes (the configuration check of exported states).
+uint64_t fnv1a(const void* data, size_t n, uint64_t h = 1469598103934665603ULL) {
+    const unsigned char* b = static_cast<const unsigned char*>(data);
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ULL;
+    return h;
+}
+
+struct StateHeader {
+    char magic[8];
+    uint32_t header_bytes, version;
+    int32_t N, Nf, m, C, K, Ng;
+    uint32_t orders;
+    int32_t window, precision, estimator, complex_signal, s4_shift, dtype, tile_group;
+    int32_t n2, n3, n4;
+    double dt, window_param;
+    int64_t n_chunks, n_samples, n_carry, state_doubles, carry_bytes;
+    uint64_t combo_hash;
+};
+
+}  // namespace
+
+struct ps_accum_s {
+    ps_plan_t plan = nullptr;
+    int64_t max_push = 0, chunk_samples = 0;
+    int dtype = 0, tile_group = 0;
+    size_t esz = 0;
+    StateLayout layout;
+    double* d_state = nullptr;
+    char* d_stage = nullptr;        // [C][stage_stride] samples: carry, then the pushed samples
+    int64_t stage_stride = 0;
+    void* d_ws = nullptr;
+    size_t ws_bytes = 0;
+    void* d_tab = nullptr;          // finalize tables of ps_stream_end
+    size_t tab_bytes = 0;
+    hipEvent_t done = nullptr;      // after the last enqueued push / end
+    bool pending = false;
+    int64_t n_chunks = 0, n_samples = 0, n_carry = 0;
+};
+
+namespace {
+
+// The batch of one push: one record of `n` staged samples per channel, its
+// accumulation table pointing at the state slots.
+void build_stream_batch(const ps_accum_s* a, int64_t n, Batch& B) {
+    const ps_plan_s* p = a->plan;
+    ps_record r{};
+    r.d_data = a->d_stage;
+    r.n_samples = n;
+    r.channel_stride = a->stage_stride;
+    r.dtype = a->dtype;
+    build_batch(p, &r, 1, nullptr, B);
+    Group& G = B.groups[0];
+    const int64_t TT = (int64_t)ps::kTile * ps::kTile, TX = (int64_t)ps::kTileX * ps::kTileX;
+    auto add = [&](const SegTable& f, const std::vector<int64_t>& off, int64_t points, bool vec) {
+        for (size_t i = 0; i < f.v.size(); ++i) {
+            ps::Seg sg = f.v[i];
+            sg.n_chunks2 = 0;
+            sg.part2 = 0;
+            sg.blocks2 = 0;
+            sg.out = a->d_state + off[i];
+            sg.err = nullptr;
+            if (vec) sg.tiles = -1;
+            const int64_t P = vec ? 256 : (sg.tiles >= ps::kSym32 ? TX : TT);
+            (void)points;
+            G.acc.add(sg, (int64_t)sg.n_tiles * (P / 256));
+        }
+    };
+    add(G.f2, a->layout.off2, 256, true);
+    add(G.f3, a->layout.off3, TT, false);
+    add(G.f4, a->layout.off4, TT, false);
+    finish_layout(p, B);
+}
+
+}  // namespace
+
+extern "C" {
+
+ps_status ps_stream_destroy(ps_accum_t a) {
+    if (!a) return PS_OK;
+    if (a->done) {
+        hipEventSynchronize(a->done);
+        hipEventDestroy(a->done);
+    }
+    hipFree(a->d_state);
+    hipFree(a->d_stage);
+    hipFree(a->d_ws);
+    hipFree(a->d_tab);
+    delete a;
+    return PS_OK;
+}
+
+ps_status ps_stream_begin(ps_plan_t p, int64_t max_push_samples, int32_t dtype, ps_accum_t* out) {
+    if (!out) return fail(PS_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!p || max_push_samples < 1) return fail(PS_E_INVALID_ARG, "bad argument");
+    if (dtype < PS_F32 || dtype > PS_C128 || (dtype >= PS_C64) != p->cplx)
+        return fail(PS_E_INVALID_ARG, "dtype %d does not match the plan's %s signal", dtype,
+                    p->cplx ? "complex" : "real");
+    if (p->schedule != PS_SCHED_BATCHED) return fail(PS_E_UNSUPPORTED, "streams need the batched schedule");
+    if (p->interlaced) return fail(PS_E_UNSUPPORTED, "streams do not take interlaced windows");
+    auto* a = new ps_accum_s();
+    a->plan = p;
+    a->max_push = max_push_samples;
+    a->chunk_samples = (int64_t)p->N * p->m;
+    a->dtype = dtype;
+    a->tile_group = p->tile_group;
+    a->esz = elem_size(dtype);
+    a->layout = state_layout(p);
+    a->stage_stride = max_push_samples + a->chunk_samples;
+    // Workspace: the largest over the chunk counts a push can complete
+    // (sampled densely near both ends, log-spaced between), checked again at
+    // every push.
+    const int64_t np_max = a->stage_stride / a->chunk_samples;
+    std::vector<int64_t> counts;
+    for (int64_t c = 1; c <= std::min<int64_t>(np_max, 64); ++c) counts.push_back(c);
+    for (int64_t c = std::max<int64_t>(1, np_max - 64); c <= np_max; ++c) counts.push_back(c);
+    for (double c = 64; c < np_max; c *= 1.05) counts.push_back((int64_t)c);
+    size_t ws = 256;
+    for (int64_t c : counts) {
+        Batch B;
+        build_stream_batch(a, c * a->chunk_samples, B);
+        ws = std::max(ws, B.total);
+    }
+    a->ws_bytes = align256(ws + ws / 16 + (1 << 20));
+    a->tab_bytes = align256(sizeof(ps::Seg) * (size_t)(p->n2() + p->n3() + p->n4() + 1));
+    hipError_t e = hipMalloc((void**)&a->d_state, sizeof(double) * std::max<int64_t>(1, a->layout.doubles));
+    if (e == hipSuccess) e = hipMemset(a->d_state, 0, sizeof(double) * std::max<int64_t>(1, a->layout.doubles));
+    if (e == hipSuccess) e = hipMalloc((void**)&a->d_stage, a->esz * a->stage_stride * p->C);
+    if (e == hipSuccess) e = hipMalloc(&a->d_ws, a->ws_bytes);
+    if (e == hipSuccess) e = hipMalloc(&a->d_tab, a->tab_bytes);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&a->done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        ps_stream_destroy(a);
+        return fail(PS_E_HIP, "stream setup failed: %s", hipGetErrorString(e));
+    }
+    *out = a;
+    return PS_OK;
+}
+
+ps_status ps_stream_push(ps_accum_t a, const void* d_data, int64_t n, int64_t channel_stride, ps_stream_t stream) {
+    if (!a) return fail(PS_E_INVALID_ARG, "stream is NULL");
+    ps_plan_s* p = a->plan;
+    if (n < 0 || n > a->max_push) return fail(PS_E_INVALID_ARG, "n_samples %lld outside 0..%lld", (long long)n,
+                                              (long long)a->max_push);
+    if (n == 0) return PS_OK;
+    if (!d_data || !aligned(d_data, a->esz)) return fail(PS_E_INVALID_ARG, "data NULL or misaligned");
+    if (p->C > 1 && channel_stride < n) return fail(PS_E_INVALID_ARG, "channel_stride < n_samples");
+    if (p->tile_group != a->tile_group)
+        return fail(PS_E_INVALID_ARG, "the plan's tile order changed since ps_stream_begin");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t have = a->n_carry + n;
+    const int64_t chunks = have / a->chunk_samples;
+    const int64_t used = chunks * a->chunk_samples, tail = have - used;
+    // append the pushed samples after the carried ones
+    PS_HIP(hipMemcpy2DAsync(a->d_stage + a->n_carry * a->esz, a->esz * a->stage_stride, d_data,
+                            a->esz * (p->C > 1 ? channel_stride : n), a->esz * n, p->C, hipMemcpyDeviceToDevice,
+                            st));
+    if (chunks > 0) {
+        Batch B;
+        build_stream_batch(a, used, B);
+        if (B.total > a->ws_bytes) return fail(PS_E_INTERNAL, "stream workspace %zu < %zu", a->ws_bytes, B.total);
+        char* ws = static_cast<char*>(a->d_ws);
+        ps_status s = upload_tables(p, B, ws + B.off_tab, st);
+        if (s != PS_OK) return s;
+        ps_record r{};
+        r.d_data = a->d_stage;
+        r.n_samples = used;
+        r.channel_stride = a->stage_stride;
+        r.dtype = a->dtype;
+        AccumTarget t{a->d_state + a->layout.off1};
+        s = enqueue_all(p, B, &r, 1, nullptr, ws, ws + B.off_tab, st, &t);
+        if (s != PS_OK) return s;
+        // the samples beyond the last complete chunk move to the front
+        // (after the transform has read them; tail < m N <= used: no overlap)
+        if (tail > 0)
+            PS_HIP(hipMemcpy2DAsync(a->d_stage, a->esz * a->stage_stride, a->d_stage + used * a->esz,
+                                    a->esz * a->stage_stride, a->esz * tail, p->C, hipMemcpyDeviceToDevice, st));
+    }
+    PS_HIP(hipEventRecord(a->done, st));
+    a->pending = true;
+    a->n_chunks += chunks;
+    a->n_samples += n;
+    a->n_carry = tail;
+    return PS_OK;
+}
+
+ps_status ps_stream_end(ps_accum_t a, const ps_output* out, ps_stream_t stream) {
+    if (!a || !out) return fail(PS_E_INVALID_ARG, "NULL argument");
+    ps_plan_s* p = a->plan;
+    const double* ptrs[8] = {out->d_s2, out->d_s2_err, out->d_s3, out->d_s3_err, out->d_s4, out->d_s4_err,
+                             out->d_s1, out->d_s1_err};
+    for (const double* q : ptrs)
+        if (q && !aligned(q, 8)) return fail(PS_E_INVALID_ARG, "output pointer misaligned");
+    hipStream_t st = (hipStream_t)stream;
+    const int Nf = p->Ng;
+    const int64_t nf2 = (int64_t)Nf * Nf;
+    if (a->n_chunks == 0) {
+        PS_HIP(ps::launch_fill_nan(out->d_s2, 2 * (int64_t)p->n2() * Nf, st));
+        PS_HIP(ps::launch_fill_nan(out->d_s2_err, 2 * (int64_t)p->n2() * Nf, st));
+        PS_HIP(ps::launch_fill_nan(out->d_s3, 2 * (int64_t)p->n3() * nf2, st));
+        PS_HIP(ps::launch_fill_nan(out->d_s3_err, 2 * (int64_t)p->n3() * nf2, st));
+        PS_HIP(ps::launch_fill_nan(out->d_s4, 2 * (int64_t)p->n4() * nf2, st));
+        PS_HIP(ps::launch_fill_nan(out->d_s4_err, 2 * (int64_t)p->n4() * nf2, st));
+        if (p->has(1)) {
+            PS_HIP(ps::launch_fill_nan(out->d_s1, 2 * (int64_t)p->C, st));
+            PS_HIP(ps::launch_fill_nan(out->d_s1_err, 2 * (int64_t)p->C, st));
+        }
+        PS_HIP(hipEventRecord(a->done, st));
+        a->pending = true;
+        return PS_OK;
+    }
+    // Finalize tables over the state: each tile is one slot (a schedule of
+    // n_tiles blocks for n_tiles tiles), Np = chunks accumulated.
+    const Scales scl = spectrum_scales(p);
+    const int64_t TT = (int64_t)ps::kTile * ps::kTile, TX = (int64_t)ps::kTileX * ps::kTileX;
+    const int kblocks = (Nf + 255) / 256;
+    SegTable f2, f3, f4;
+    for (int i = 0; i < p->n2(); ++i) {
+        ps::Seg sg{};
+        sg.part = a->layout.off2[i];
+        sg.n_tiles = kblocks;
+        sg.blocks = kblocks;
+        sg.n_chunks = (int32_t)a->n_chunks;
+        sg.out = out->d_s2 ? out->d_s2 + 2 * (int64_t)i * Nf : nullptr;
+        sg.err = out->d_s2_err ? out->d_s2_err + 2 * (int64_t)i * Nf : nullptr;
+        sg.scale = scl.s2;
+        sg.ncomp = 4;
+        f2.add(sg, kblocks);
+    }
+    for (int i = 0; i < p->n3(); ++i) {
+        ps::Seg sg{};
+        sg.tiles = p->s3_sym(i) ? ps::kSym64 : ps::kFull64;
+        sg.n_tiles = p->n_tiles[sg.tiles];
+        sg.blocks = sg.n_tiles;
+        sg.part = a->layout.off3[i];
+        sg.n_chunks = (int32_t)a->n_chunks;
+        sg.out = out->d_s3 ? out->d_s3 + 2 * i * nf2 : nullptr;
+        sg.err = out->d_s3_err ? out->d_s3_err + 2 * i * nf2 : nullptr;
+        sg.scale = scl.s3;
+        sg.sym = p->s3_sym(i);
+        sg.ncomp = 4;
+        f3.add(sg, (int64_t)sg.n_tiles * (TT / 256));
+    }
+    for (int i = 0; i < p->n4(); ++i) {
+        ps::Seg sg{};
+        sg.tiles = s4_kind(p, i);
+        const bool single = sg.tiles == ps::kSym64;
+        sg.n_tiles = p->n_tiles[sg.tiles];
+        sg.blocks = sg.n_tiles;
+        sg.part = a->layout.off4[i];
+        sg.n_chunks = (int32_t)a->n_chunks;
+        sg.out = out->d_s4 ? out->d_s4 + 2 * i * nf2 : nullptr;
+        sg.err = out->d_s4_err ? out->d_s4_err + 2 * i * nf2 : nullptr;
+        sg.scale = scl.s4;
+        sg.sym = p->s4_sym(i);
+        sg.ncomp = single ? 2 : 4;
+        f4.add(sg, (int64_t)sg.n_tiles * ((single ? TT : TX) / 256));
+    }
+    // tables through the plan's pinned staging into the stream's table buffer
+    Batch B;
+    B.groups.emplace_back();
+    B.groups[0].f2 = f2;
+    B.groups[0].f3 = f3;
+    B.groups[0].f4 = f4;
+    finish_layout(p, B);
+    if (B.tab_bytes > a->tab_bytes + 64 * sizeof(ps::Seg)) return fail(PS_E_INTERNAL, "finalize tables too large");
+    if (B.tab_bytes > a->tab_bytes) {
+        // (record-descriptor padding at the front of the layout)
+        hipFree(a->d_tab);
+        a->d_tab = nullptr;
+        a->tab_bytes = align256(B.tab_bytes);
+        PS_HIP(hipMalloc(&a->d_tab, a->tab_bytes));
+    }
+    char* tab = static_cast<char*>(a->d_tab);
+    ps_status s = upload_tables(p, B, tab, st);
+    if (s != PS_OK) return s;
+    ps::FinalizeArgs fa{};
+    fa.tt = p->tables();
+    fa.part = a->d_state;
+    fa.Nf = Nf;
+    auto fin = [&](const SegTable& t, bool vec) -> hipError_t {
+        fa.segs = reinterpret_cast<const ps::Seg*>(tab + t.dev_off);
+        fa.n_segs = (int)t.v.size();
+        fa.n_items = t.n_items;
+        return vec ? ps::launch_finalize_vec(fa, st) : ps::launch_finalize_grid(fa, st);
+    };
+    if (!f2.v.empty()) PS_HIP(fin(B.groups[0].f2, true));
+    if (!f3.v.empty()) PS_HIP(fin(B.groups[0].f3, false));
+    if (!f4.v.empty()) PS_HIP(fin(B.groups[0].f4, false));
+    if (p->has(1))
+        PS_HIP(ps::launch_finalize_s1_sums(a->d_state + a->layout.off1, p->C, a->n_chunks, scl.s1, out->d_s1,
+                                           out->d_s1_err, st));
+    PS_HIP(hipEventRecord(a->done, st));
+    a->pending = true;
+    return PS_OK;
+}
+
+ps_status ps_stream_counts(ps_accum_t a, int64_t* n_chunks, int64_t* n_samples, int64_t* n_carry) {
+    if (!a) return fail(PS_E_INVALID_ARG, "stream is NULL");
+    if (n_chunks) *n_chunks = a->n_chunks;
+    if (n_samples) *n_samples = a->n_samples;
+    if (n_carry) *n_carry = a->n_carry;
+    return PS_OK;
+}
+
+namespace {
+StateHeader make_header(const ps_accum_s* a) {
+    const ps_plan_s* p = a->plan;
+    StateHeader h{};
+    std::memcpy(h.magic, "PSSTATE1", 8);
+    h.header_bytes = sizeof(StateHeader);
+    h.version = 1;
+    h.N = p->N;
+    h.Nf = p->Nf;
+    h.m = p->m;
+    h.C = p->C;
+    h.K = p->K;
+    h.Ng = p->Ng;
+    h.orders = p->orders;
+    h.window = p->window;
+    h.precision = p->precision;
+    h.estimator = p->estimator;
+    h.complex_signal = p->cplx;
+    h.s4_shift = p->s4_shift;
+    h.dtype = a->dtype;
+    h.tile_group = a->tile_group;
+    h.n2 = p->n2();
+    h.n3 = p->n3();
+    h.n4 = p->n4();
+    h.dt = p->dt;
+    h.window_param = p->window == PS_WIN_ACG ? p->window_param : 0.0;
+    h.n_chunks = a->n_chunks;
+    h.n_samples = a->n_samples;
+    h.n_carry = a->n_carry;
+    h.state_doubles = a->layout.doubles;
+    h.carry_bytes = (int64_t)(a->esz * a->n_carry * p->C);
+    uint64_t hh = fnv1a(p->c2.data(), p->c2.size());
+    hh = fnv1a(p->c3.data(), p->c3.size(), hh);
+    h.combo_hash = fnv1a(p->c4.data(), p->c4.size(), hh);
+    return h;
+}
+}  // namespace
+
+ps_status ps_stream_export_state(ps_accum_t a, void* h_buf, size_t* n_bytes) {
+    if (!a || !n_bytes) return fail(PS_E_INVALID_ARG, "NULL argument");
+    const StateHeader h = make_header(a);
+    const size_t need = sizeof(StateHeader) + sizeof(double) * (size_t)h.state_doubles + (size_t)h.carry_bytes;
+    if (!h_buf) {
+        *n_bytes = need;
+        return PS_OK;
+    }
+    if (*n_bytes < need) return fail(PS_E_INVALID_ARG, "buffer %zu < %zu bytes", *n_bytes, need);
+    if (a->pending) PS_HIP(hipEventSynchronize(a->done));
+    char* b = static_cast<char*>(h_buf);
+    std::memcpy(b, &h, sizeof h);
+    b += sizeof h;
+    if (h.state_doubles > 0)
+        PS_HIP(hipMemcpy(b, a->d_state, sizeof(double) * (size_t)h.state_doubles, hipMemcpyDeviceToHost));
+    b += sizeof(double) * (size_t)h.state_doubles;
+    if (a->n_carry > 0)
+        PS_HIP(hipMemcpy2D(b, a->esz * a->n_carry, a->d_stage, a->esz * a->stage_stride, a->esz * a->n_carry,
+                           a->plan->C, hipMemcpyDeviceToHost));
+    *n_bytes = need;
+    return PS_OK;
+}
+
+ps_status ps_stream_import_state(ps_accum_t a, const void* h_buf, size_t n_bytes) {
+    if (!a || !h_buf) return fail(PS_E_INVALID_ARG, "NULL argument");
+    if (n_bytes < sizeof(StateHeader)) return fail(PS_E_INVALID_ARG, "state too short");
+    StateHeader h;
+    std::memcpy(&h, h_buf, sizeof h);
+    if (std::memcmp(h.magic, "PSSTATE1", 8) != 0 || h.header_bytes != sizeof(StateHeader) || h.version != 1)
+        return fail(PS_E_INVALID_ARG, "not an exported stream state");
+    StateHeader mine = make_header(a);
+    // the configuration must match; the counters come from the import
+    mine.n_chunks = h.n_chunks;
+    mine.n_samples = h.n_samples;
+    mine.n_carry = h.n_carry;
+    mine.carry_bytes = h.carry_bytes;
+    if (std::memcmp(&mine, &h, sizeof h) != 0)
+        return fail(PS_E_INVALID_ARG, "the state was exported by a stream of another configuration");
+    if (h.n_carry < 0 || h.n_carry >= a->chunk_samples || h.n_chunks < 0 || h.n_samples < 0 ||
+        h.carry_bytes != (int64_t)(a->esz * h.n_carry * a->plan->C))
+        return fail(PS_E_INVALID_ARG, "inconsistent state counters");
+    const size_t need = sizeof(StateHeader) + sizeof(double) * (size_t)h.state_doubles + (size_t)h.carry_bytes;
+    if (n_bytes < need) return fail(PS_E_INVALID_ARG, "state %zu < %zu bytes", n_bytes, need);
+    if (a->pending) PS_HIP(hipEventSynchronize(a->done));
+    const char* b = static_cast<const char*>(h_buf) + sizeof h;
+    if (h.state_doubles > 0)
+        PS_HIP(hipMemcpy(a->d_state, b, sizeof(double) * (size_t)h.state_doubles, hipMemcpyHostToDevice));
+    b += sizeof(double) * (size_t)h.state_doubles;
+    if (h.n_carry > 0)
+        PS_HIP(hipMemcpy2D(a->d_stage, a->esz * a->stage_stride, b, a->esz * h.n_carry, a->esz * h.n_carry,
+                           a->plan->C, hipMemcpyHostToDevice));
+    a->n_chunks = h.n_chunks;
+    a->n_samples = h.n_samples;
+    a->n_carry = h.n_carry;
+    a->pending = false;
+    return PS_OK;
+}
+
+ps_status ps_spectra_zscore(const double* d_a, const double* d_a_err, const double* d_b, const double* d_b_err,
+                            int64_t n_points, double* d_out, ps_stream_t stream) {
+    if (n_points < 0) return fail(PS_E_INVALID_ARG, "n_points < 0");
+    if (n_points == 0) return PS_OK;
+    const double* ptrs[5] = {d_a, d_a_err, d_b, d_b_err, d_out};
+    for (const double* q : ptrs)
+        if (!q || !aligned(q, 8)) return fail(PS_E_INVALID_ARG, "pointer NULL or misaligned");
+    PS_HIP(ps::launch_zscore(d_a, d_a_err, d_b, d_b_err, 2 * n_points, d_out, (hipStream_t)stream));
     return PS_OK;
 }
 

@@ -250,7 +250,124 @@ __global__ __launch_bounds__(256) void k_finalize_s1(FinalizeArgs p) {
     }
 }
 
+// Running accumulation (ps_stream_*): one block per (segment, tile, group of
+// 256 points of the tile).  A segment names one combination and up to two
+// pieces of the batch (the chunk completed from the carry buffer, set 0, and
+// the chunks of the pushed samples, set 1); the block adds each point's slots
+// of set 0, then of set 1, in slot order, and adds the result to the state
+// slot of that tile (Seg.out), so the order of additions is fixed.
+__global__ __launch_bounds__(256) void k_accumulate(AccumArgs p) {
+    const int64_t x = blockIdx.x;
+    if (x >= p.n_items) return;
+    const Seg& sg = p.segs[find_seg(p.segs, p.n_segs, x)];
+    const int P = sg.tiles < 0 ? 256 : (sg.tiles >= kSym32 ? kTileX * kTileX : kTile * kTile);
+    const int per_tile = P / 256;
+    const int64_t local = x - sg.item0;
+    const int tile = (int)(local / per_tile);
+    const int e = (int)(local - (int64_t)tile * per_tile) * 256 + threadIdx.x;
+    const int nc = sg.ncomp;
+    double s[4] = {0, 0, 0, 0};
+    for (int set = 0; set < 2; ++set) {
+        const int64_t W = set ? sg.n_chunks2 : sg.n_chunks;
+        if (W <= 0) continue;
+        int64_t s0 = 0, ns = 0;
+        slot_range(Sched{sg.n_tiles, W, set ? sg.blocks2 : sg.blocks}, tile, s0, ns);
+        const double* base = p.part + (set ? sg.part2 : sg.part) + e;
+        for (int64_t slot = s0; slot < s0 + ns; ++slot) {
+            const double* q = base + slot * nc * P;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (c < nc) s[c] += q[c * P];
+        }
+    }
+    double* st = sg.out + (int64_t)tile * nc * P + e;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        if (c < nc) st[c * P] += s[c];
+}
+
+// S1 of a running accumulation: one block per channel adds the per-chunk means
+// of a_0 of this push's chunks (real and imaginary parts and their squares)
+// in a fixed tree order to the channel's four state sums.
+__global__ __launch_bounds__(256) void k_accumulate_s1(const float2* s1, int64_t s1_cs, int64_t n_chunks,
+                                                       double* state) {
+    __shared__ double red[4][256];
+    const int ch = blockIdx.x, tid = threadIdx.x;
+    const float2* v = s1 + (int64_t)ch * s1_cs;
+    double a[4] = {0, 0, 0, 0};
+    for (int64_t c = tid; c < n_chunks; c += 256) {
+        const float2 d = v[c];
+        a[0] += d.x;
+        a[1] += d.y;
+        a[2] = fma((double)d.x, (double)d.x, a[2]);
+        a[3] = fma((double)d.y, (double)d.y, a[3]);
+    }
+    for (int q = 0; q < 4; ++q) red[q][tid] = a[q];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h)
+            for (int q = 0; q < 4; ++q) red[q][tid] += red[q][tid + h];
+        __syncthreads();
+    }
+    if (tid < 4) state[4 * ch + tid] += red[tid][0];
+}
+
+// S1 from a running accumulation's state sums (one thread per channel).
+__global__ void k_finalize_s1_sums(const double* state, int n_channels, int64_t n_chunks, double scale,
+                                   double* out, double* err) {
+    const int ch = threadIdx.x;
+    if (ch >= n_channels) return;
+    const double* q = state + 4 * ch;
+    double mr, sr, mi, si;
+    mean_sigma(q[0], q[2], (double)n_chunks, scale, mr, sr);
+    mean_sigma(q[1], q[3], (double)n_chunks, scale, mi, si);
+    if (out) {
+        out[2 * ch] = mr;
+        out[2 * ch + 1] = mi;
+    }
+    if (err) {
+        err[2 * ch] = sr;
+        err[2 * ch + 1] = si;
+    }
+}
+
+// |a - b| / sqrt(sa^2 + sb^2) per real component.
+__global__ void k_zscore(const double* a, const double* ae, const double* b, const double* be, int64_t n,
+                         double* out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double d = fabs(a[i] - b[i]);
+    out[i] = d / sqrt(ae[i] * ae[i] + be[i] * be[i]);
+}
+
 }  // namespace
+
+hipError_t launch_accumulate(const AccumArgs& a, hipStream_t s) {
+    if (a.n_items <= 0) return hipSuccess;
+    k_accumulate<<<(unsigned)a.n_items, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate_s1(const float2* s1, int64_t s1_cs, int64_t n_chunks, int n_channels, double* state,
+                                hipStream_t s) {
+    if (n_chunks <= 0 || n_channels <= 0) return hipSuccess;
+    k_accumulate_s1<<<(unsigned)n_channels, 256, 0, s>>>(s1, s1_cs, n_chunks, state);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_s1_sums(const double* state, int n_channels, int64_t n_chunks, double scale, double* out,
+                                   double* err, hipStream_t s) {
+    if (n_channels <= 0) return hipSuccess;
+    k_finalize_s1_sums<<<1, 64, 0, s>>>(state, n_channels, n_chunks, scale, out, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_zscore(const double* a, const double* ae, const double* b, const double* be, int64_t n,
+                         double* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_zscore<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, ae, b, be, n, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_finalize_vec(const FinalizeArgs& a, hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;

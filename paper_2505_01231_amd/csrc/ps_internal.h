@@ -218,6 +218,25 @@ hipError_t launch_finalize_s1(const FinalizeArgs& a, hipStream_t s);
 
 hipError_t launch_fill_nan(double* p, int64_t n, hipStream_t s);
 
+// Running accumulation (ps_stream_*): per combination, the batch's partial
+// sums of up to two pieces (Seg.part / n_chunks / blocks and Seg.part2 /
+// n_chunks2 / blocks2) added tile by tile to the state slots at Seg.out
+// ([n_tiles][ncomp][points of a tile]; Seg.tiles < 0: the 256-point k blocks
+// of S2).  Items: n_tiles x points per tile / 256 per segment.
+struct AccumArgs {
+    const Seg* segs;
+    int n_segs;
+    int64_t n_items;
+    const double* part;
+};
+hipError_t launch_accumulate(const AccumArgs& a, hipStream_t s);
+hipError_t launch_accumulate_s1(const float2* s1, int64_t s1_cs, int64_t n_chunks, int n_channels, double* state,
+                                hipStream_t s);
+hipError_t launch_finalize_s1_sums(const double* state, int n_channels, int64_t n_chunks, double scale, double* out,
+                                   double* err, hipStream_t s);
+hipError_t launch_zscore(const double* a, const double* ae, const double* b, const double* be, int64_t n,
+                         double* out, hipStream_t s);
+
 // ---------------------------------------------------------------- full plane
 // One combination's spectrum on the signed grid (-N_f, N_f) gathered from the
 // positive-quadrant outputs (see k_full_plane for the regions).  src[i] names

@@ -468,10 +468,84 @@ def quasi_spectra(x, ms, **plan_kw) -> dict:
     return out
 
 
-def m_dependence(a: Spectra, b: Spectra, key: str = "s4") -> torch.Tensor:
+def m_dependence(a: Spectra, b: Spectra, key: str = "s4", stream=None) -> torch.Tensor:
     """Per grid point |S_a - S_b| / sqrt(sigma_a^2 + sigma_b^2) (real and
     imaginary parts separately) between two quasi-spectra of one record
-    computed with different m."""
-    d = (getattr(a, key) - getattr(b, key)).abs()
-    e = (getattr(a, key + "_err") ** 2 + getattr(b, key + "_err") ** 2).sqrt()
-    return d / e
+    computed with different m (ps_spectra_zscore)."""
+    va, ea, vb, eb = (getattr(a, key), getattr(a, key + "_err"), getattr(b, key), getattr(b, key + "_err"))
+    if va.shape != vb.shape or ea.shape != va.shape or eb.shape != vb.shape:
+        raise ValueError("the two spectra differ in shape")
+    ts = [t.contiguous() for t in (va, ea, vb, eb)]
+    out = torch.empty_like(ts[0])
+    lib = L.load()
+    st = torch.cuda.current_stream(out.device) if stream is None else stream
+    L.check(lib.ps_spectra_zscore(ts[0].data_ptr(), ts[1].data_ptr(), ts[2].data_ptr(), ts[3].data_ptr(),
+                                  ts[0].numel() // 2, out.data_ptr(), C.c_void_p(st.cuda_stream)),
+            "ps_spectra_zscore")
+    return out
+
+
+class Accumulator:
+    """Running accumulation over one long record arriving in pieces
+    (ps_stream_*): ``push`` appends samples (a device tensor [L] or [C, L]),
+    every completed chunk's sums go into the FP64 state, ``end`` writes the
+    spectra of everything pushed so far, and ``export_state`` /
+    ``import_state`` save and restore the state (bit-exact resume)."""
+
+    def __init__(self, plan: Plan, max_push_samples: int, dtype=torch.float32):
+        self._plan = plan
+        self.dtype = dtype
+        self.max_push = max_push_samples
+        h = C.c_void_p()
+        L.check(plan._lib.ps_stream_begin(plan._handle, max_push_samples, _DTYPES[dtype], C.byref(h)),
+                "ps_stream_begin")
+        self._handle = h
+        self._keep = []
+
+    def push(self, x: torch.Tensor, stream=None):
+        rec = self._plan.record(x)
+        if x.dtype != self.dtype:
+            raise ValueError("dtype differs from the accumulator's")
+        st = torch.cuda.current_stream(x.device) if stream is None else stream
+        L.check(self._plan._lib.ps_stream_push(self._handle, rec.d_data, rec.n_samples, rec.channel_stride,
+                                               C.c_void_p(st.cuda_stream)), "ps_stream_push")
+        self._keep = [x]            # the samples are read when the stream runs the push
+
+    def counts(self) -> dict:
+        n, s, c = C.c_int64(), C.c_int64(), C.c_int64()
+        L.check(self._plan._lib.ps_stream_counts(self._handle, C.byref(n), C.byref(s), C.byref(c)),
+                "ps_stream_counts")
+        return {"chunks": n.value, "samples": s.value, "carry": c.value}
+
+    def end(self, outputs: Spectra | None = None, device=None, stream=None) -> Spectra:
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        out = outputs if outputs is not None else self._plan.allocate_outputs(dev)
+        out.n_chunks = self.counts()["chunks"]
+        out.flags = (L.PS_FLAG_EMPTY if out.n_chunks == 0 else 0) | (L.PS_FLAG_NO_ERRBAR if out.n_chunks == 1 else 0)
+        o = out.c_struct()
+        st = torch.cuda.current_stream(dev) if stream is None else stream
+        L.check(self._plan._lib.ps_stream_end(self._handle, C.byref(o), C.c_void_p(st.cuda_stream)),
+                "ps_stream_end")
+        return out
+
+    def export_state(self) -> bytes:
+        n = C.c_size_t()
+        L.check(self._plan._lib.ps_stream_export_state(self._handle, None, C.byref(n)), "ps_stream_export_state")
+        buf = C.create_string_buffer(n.value)
+        L.check(self._plan._lib.ps_stream_export_state(self._handle, buf, C.byref(n)), "ps_stream_export_state")
+        return buf.raw[: n.value]
+
+    def import_state(self, state: bytes):
+        buf = C.create_string_buffer(state, len(state))
+        L.check(self._plan._lib.ps_stream_import_state(self._handle, buf, len(state)), "ps_stream_import_state")
+
+    def close(self):
+        if self._handle is not None:
+            self._plan._lib.ps_stream_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
