@@ -258,6 +258,26 @@ ps_status ps_workspace_size(ps_plan_t plan, const ps_record* recs, int32_t n_rec
 ps_status ps_execute(ps_plan_t plan, const ps_record* recs, int32_t n_rec, void* d_ws,
                      size_t ws_bytes, const ps_output* outs, ps_stream_t stream);
 
+/* Allocation-free form of ps_execute, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same estimator and outputs as ps_execute, with the
+ * workspace taken from a static device array of PS_STATIC_SCRATCH_BYTES that
+ * the library holds on every GPU it runs on until the process ends (its
+ * address is resolved for a device when the first plan is created there).
+ * The call allocates nothing: no device memory, no pinned host memory, no
+ * events (stage timing is not recorded).  Limits: ps_workspace_size() of the
+ * records must not exceed PS_STATIC_SCRATCH_BYTES, and their work tables must
+ * fit the plan's pinned staging (4 MiB; about 30,000 record-combination
+ * segments); otherwise PS_E_WORKSPACE and nothing is enqueued.
+ * PS_E_INVALID_ARG when no plan was ever created on the current device.  All
+ * calls on one GPU share its array, which keeps the last call's contents
+ * (nothing in it needs to start at zero): calls that overlap on one GPU
+ * (two streams, or two host threads) race and must be serialised by the
+ * caller. */
+#define PS_STATIC_SCRATCH_BYTES (256u * 1024u * 1024u)
+ps_status ps_execute_static(ps_plan_t plan, const ps_record* recs, int32_t n_rec, const ps_output* outs,
+                            ps_stream_t stream);
+
 /* Sequential spectra (the short-time estimates of Section 8, kept instead of
  * averaged): the spectra of chunks [chunk_lo, chunk_lo + n_chunks) of one
  * record, each chunk on its own.  `out` holds, for each requested order, an

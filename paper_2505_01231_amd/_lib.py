@@ -29,8 +29,9 @@ EXPORTED = (
     "ps_plan_get_tuning", "ps_plan_set_tuning", "ps_plan_autotune",
     "ps_sequential_workspace_size", "ps_execute_sequential", "ps_full_plane",
     "ps_stream_begin", "ps_stream_push", "ps_stream_end", "ps_stream_counts", "ps_stream_export_state",
-    "ps_stream_import_state", "ps_stream_destroy", "ps_spectra_zscore",
+    "ps_stream_import_state", "ps_stream_destroy", "ps_spectra_zscore", "ps_execute_static",
 )
+PS_STATIC_SCRATCH_BYTES = 256 * 1024 * 1024
 PS_TUNE_MAX = 16
 
 
@@ -129,6 +130,8 @@ def load() -> C.CDLL:
     lib.ps_plan_set_tuning.argtypes = [vp, C.POINTER(ps_tuning)]
     lib.ps_plan_autotune.argtypes = [vp, C.POINTER(ps_record), i32, vp, sz, C.POINTER(ps_output), i32, vp,
                                      C.POINTER(ps_tune_report)]
+    lib.ps_execute_static.argtypes = [vp, C.POINTER(ps_record), i32, C.POINTER(ps_output), vp]
+    lib.ps_execute_static.restype = C.c_int
     lib.ps_stream_begin.argtypes = [vp, i64, i32, C.POINTER(vp)]
     lib.ps_stream_push.argtypes = [vp, vp, i64, i64, vp]
     lib.ps_stream_end.argtypes = [vp, C.POINTER(ps_output), vp]

@@ -84,6 +84,8 @@ void all_combos(int C, std::vector<int8_t>& c2, std::vector<int8_t>& c3, std::ve
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+constexpr size_t kStagingBytes = 4u << 20;     // pinned work-table staging per buffer (two per plan)
+
 // Output tiles: upper triangle (kt <= lt) for symmetric spectra, all
 // otherwise, walked in G x G blocks of tiles: the consecutive tiles that one
 // XCD processes at a time then share their k and l columns (and part of the
@@ -764,6 +766,19 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
         p->n_cu = std::max(1, prop.multiProcessorCount);
+    // Pinned staging of the work tables (two, used in turn) and their events,
+    // allocated here so that executes need no allocation for batches whose
+    // tables fit (larger ones enlarge them, except on the static-scratch path).
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipHostMalloc((void**)&p->h_stage[i], kStagingBytes, hipHostMallocDefault);
+        if (e == hipSuccess) p->h_cap[i] = kStagingBytes;
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->h_ev[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = ps::static_scratch_setup();
+    if (e != hipSuccess) {
+        ps_plan_destroy(p);
+        return fail(PS_E_HIP, "plan setup failed: %s", hipGetErrorString(e));
+    }
     p->bpc_s3 = ps::s3_blocks_per_cu();
     p->bpc_s4 = p->precision == PS_PREC_FP32     ? ps::s4_blocks_per_cu()
                 : p->precision == PS_PREC_BF16X3 ? ps::s4_mfma_blocks_per_cu()
@@ -983,8 +998,13 @@ namespace {
 
 // Copy the batch's record descriptors and segment tables into the workspace
 // (one H2D copy from the plan's pinned staging buffer).
-ps_status upload_tables(ps_plan_t p, const Batch& B, char* d_tab, hipStream_t st) {
+// `grow`: the staging buffer may be enlarged (a pinned host allocation);
+// without it a batch whose tables exceed the buffer is refused.
+ps_status upload_tables(ps_plan_t p, const Batch& B, char* d_tab, hipStream_t st, bool grow = true) {
     const int i = p->h_next;
+    if (!grow && (p->h_cap[i] < B.tab_bytes || !p->h_ev[i]))
+        return fail(PS_E_WORKSPACE, "work tables of %zu bytes exceed the plan's pinned staging of %zu bytes",
+                    B.tab_bytes, p->h_cap[i]);
     p->h_next ^= 1;
     if (p->h_ev[i]) PS_HIP(hipEventSynchronize(p->h_ev[i]));
     if (p->h_cap[i] < B.tab_bytes) {
@@ -1253,6 +1273,29 @@ ps_status ps_execute(ps_plan_t p, const ps_record* recs, int32_t n_rec, void* d_
         if (s != PS_OK) return s;
     }
     return enqueue_all(p, B, recs, n_rec, outs, ws, ws + B.off_tab, st);
+}
+
+ps_status ps_execute_static(ps_plan_t p, const ps_record* recs, int32_t n_rec, const ps_output* outs,
+                            ps_stream_t stream) {
+    char* ws = static_cast<char*>(ps::static_scratch_ptr());
+    if (!ws) return fail(PS_E_INVALID_ARG, "no static scratch on the current device (create a plan on it first)");
+    ps_status s = validate_execute(p, recs, n_rec, ws, outs);
+    if (s != PS_OK || n_rec == 0) return s;
+    hipStream_t st = (hipStream_t)stream;
+    Batch B;
+    build_batch(p, recs, n_rec, outs, B);
+    if (B.total > ps::kStaticScratchBytes)
+        return fail(PS_E_WORKSPACE, "these records need %zu bytes of workspace; the static scratch holds %zu",
+                    B.total, ps::kStaticScratchBytes);
+    if (B.chunks_tot > 0) {
+        s = upload_tables(p, B, ws + B.off_tab, st, /*grow=*/false);
+        if (s != PS_OK) return s;
+    }
+    const bool prof = p->prof;
+    p->prof = false;        // stage timing would create events
+    s = enqueue_all(p, B, recs, n_rec, outs, ws, ws + B.off_tab, st);
+    p->prof = prof;
+    return s;
 }
 
 namespace {

@@ -258,6 +258,13 @@ struct PlaneArgs {
 };
 hipError_t launch_full_plane(const PlaneArgs& a, hipStream_t s);
 
+// Static scratch of ps_execute_static (ps_static.hip): kStaticScratchBytes of
+// device memory per GPU.  static_scratch_setup resolves the current device's
+// copy (at plan creation); static_scratch_ptr returns it (NULL before).
+constexpr size_t kStaticScratchBytes = size_t(256) << 20;
+hipError_t static_scratch_setup();
+void* static_scratch_ptr();
+
 // The partial-sum slots of tile t: n consecutive slots from s0 (see Sched).
 __device__ __forceinline__ void slot_range(const Sched& sc, int64_t t, int64_t& s0, int64_t& n) {
     const int64_t T1 = sc.T1();
