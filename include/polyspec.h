@@ -130,7 +130,19 @@ typedef struct ps_config {
     int32_t estimator;     /* ps_estimator */
     int32_t complex_signal; /* 0: real records; 1: complex records (PS_C64 / PS_C128), see below */
     int32_t s4_shift;      /* q: S4 on a plane parallel to the cut (complex_signal = 1), see below */
+    int32_t frame_len_set; /* further frame lengths records may carry: bit q (8..13) admits N = 2^q (see below) */
 } ps_config;
+/* Several frame lengths in one execute (frame_len_set != 0; real signals,
+ * power-of-two frame_len): a record whose ps_record.frame_len is 2^q with bit
+ * q set is cut into frames of that length; frame_len 0 means the plan's.
+ * Each frame length has its own window (same kind and sigma_t), Fourier
+ * coefficients and grid: N_f scales with the frame length when n_freq is
+ * given (n_freq * 2^q / frame_len, which must be an integer), else follows
+ * f_max as for the plan's (floor(f_max 2^q dt) + 1); the constraints on N_f
+ * hold per frame length.  Every record's spectra use its own grid (outputs
+ * sized by ps_plan_frame_info).  All records of an execute, whatever their
+ * frame length, share each stage's launch.  ps_full_plane, the streamer and
+ * the running accumulation take the plan's frame length only. */
 /* Complex-valued signals (complex_signal = 1; frame_len up to 4096): without
  * a_{-k} = a_k* the negative frequencies carry their own information, so every
  * spectrum is computed on the signed grid k, l in (-N_f, N_f): S2 has 2 N_f - 1
@@ -182,7 +194,7 @@ typedef struct ps_record {
     int64_t n_samples;      /* samples per channel (L) */
     int64_t channel_stride; /* elements from one channel's sample 0 to the next's */
     int32_t dtype;          /* ps_dtype; int16 samples are used in LSB units */
-    int32_t reserved;       /* must be 0 */
+    int32_t frame_len;      /* 0: the plan's frame_len; else a frame length of the plan's frame_len_set */
 } ps_record;
 
 /* Output of one record.  Spectra are FP64 interleaved complex (re, im); error
@@ -233,9 +245,18 @@ ps_status ps_plan_destroy(ps_plan_t plan);
 
 ps_status ps_plan_query(ps_plan_t plan, ps_plan_info* info);
 
-/* Np and PS_FLAG_* for a record of n_samples samples per channel (with
- * interlaced windows: of the frame set that starts at sample 0). */
+/* Np and PS_FLAG_* for a record of n_samples samples per channel at the
+ * plan's frame length (with interlaced windows: of the frame set that starts
+ * at sample 0). */
 ps_status ps_record_info(ps_plan_t plan, int64_t n_samples, int64_t* n_chunks, uint32_t* flags);
+
+/* The same for a record at its own frame length (rec->frame_len). */
+ps_status ps_record_chunks(ps_plan_t plan, const ps_record* rec, int64_t* n_chunks, uint32_t* flags);
+
+/* ps_plan_query for one of the plan's frame lengths (frame_len 0 or the
+ * plan's: ps_plan_query): its N_f, coefficient count, grid, f_max and window
+ * sums.  PS_E_INVALID_ARG for a frame length the plan does not hold. */
+ps_status ps_plan_frame_info(ps_plan_t plan, int32_t frame_len, ps_plan_info* info);
 
 /* Device workspace (bytes) that ps_execute needs for these records: the
  * FP32 Fourier coefficients of every frame of every complete chunk (eq. a_k,

@@ -30,6 +30,7 @@ EXPORTED = (
     "ps_sequential_workspace_size", "ps_execute_sequential", "ps_full_plane",
     "ps_stream_begin", "ps_stream_push", "ps_stream_end", "ps_stream_counts", "ps_stream_export_state",
     "ps_stream_import_state", "ps_stream_destroy", "ps_spectra_zscore", "ps_execute_static",
+    "ps_record_chunks", "ps_plan_frame_info",
 )
 PS_STATIC_SCRATCH_BYTES = 256 * 1024 * 1024
 PS_TUNE_MAX = 16
@@ -44,13 +45,13 @@ class ps_config(C.Structure):
         ("n_combos2", C.c_int32), ("n_combos3", C.c_int32), ("n_combos4", C.c_int32),
         ("combos2", C.POINTER(C.c_int8)), ("combos3", C.POINTER(C.c_int8)),
         ("combos4", C.POINTER(C.c_int8)), ("interlaced", C.c_int32), ("estimator", C.c_int32),
-        ("complex_signal", C.c_int32), ("s4_shift", C.c_int32),
+        ("complex_signal", C.c_int32), ("s4_shift", C.c_int32), ("frame_len_set", C.c_int32),
     ]
 
 
 class ps_record(C.Structure):
     _fields_ = [("d_data", C.c_void_p), ("n_samples", C.c_int64), ("channel_stride", C.c_int64),
-                ("dtype", C.c_int32), ("reserved", C.c_int32)]
+                ("dtype", C.c_int32), ("frame_len", C.c_int32)]
 
 
 class ps_output(C.Structure):
@@ -130,6 +131,10 @@ def load() -> C.CDLL:
     lib.ps_plan_set_tuning.argtypes = [vp, C.POINTER(ps_tuning)]
     lib.ps_plan_autotune.argtypes = [vp, C.POINTER(ps_record), i32, vp, sz, C.POINTER(ps_output), i32, vp,
                                      C.POINTER(ps_tune_report)]
+    lib.ps_record_chunks.argtypes = [vp, C.POINTER(ps_record), C.POINTER(i64), C.POINTER(C.c_uint32)]
+    lib.ps_record_chunks.restype = C.c_int
+    lib.ps_plan_frame_info.argtypes = [vp, i32, C.POINTER(ps_plan_info)]
+    lib.ps_plan_frame_info.restype = C.c_int
     lib.ps_execute_static.argtypes = [vp, C.POINTER(ps_record), i32, C.POINTER(ps_output), vp]
     lib.ps_execute_static.restype = C.c_int
     lib.ps_stream_begin.argtypes = [vp, i64, i32, C.POINTER(vp)]

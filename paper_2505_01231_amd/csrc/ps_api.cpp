@@ -7,6 +7,7 @@
 #include <array>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -104,6 +105,19 @@ void tile_order(int T, int G, std::vector<int2>& sym, std::vector<int2>& full) {
 
 }  // namespace
 
+// One frame length of a plan: its window and FFT tables, grid and tile
+// tables.  Class 0 is the plan's frame_len (its fields are also the plan's
+// own); further classes come from ps_config.frame_len_set.
+struct FrameClass {
+    int N = 0, log2n_fft = 0, Nf = 0, Ng = 0, K = 0, jmax = 0;
+    int T = 0, TX = 0;
+    int n_tiles[4] = {0, 0, 0, 0};
+    double sum_g[5] = {0, 0, 0, 0, 0};
+    float* d_g = nullptr;
+    float2* d_tw = nullptr;
+    int2* d_tiles[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
 struct ps_plan_s {
     int N = 0, log2n = 0, Nf = 0, K = 0, m = 0, C = 0;
     double dt = 1, f_max = 0, window_param = 0.14;
@@ -162,10 +176,15 @@ struct ps_plan_s {
         const int8_t* q = &c4[4 * i];
         return s4_shift == 0 && q[0] == q[2] && q[1] == q[3];
     }
-    ps::TileTables tables() const {
-        ps::TileTables t;
-        for (int i = 0; i < 4; ++i) t.t[i] = d_tiles[i];
-        return t;
+    // Frame lengths: fc[0] mirrors the fields above (same device tables);
+    // fc[1..] are the further frame lengths records may carry.
+    std::vector<FrameClass> fc;
+    // class of a record's frame length (0: the plan's), -1 if not declared
+    int class_of(int frame_len) const {
+        if (frame_len == 0 || frame_len == N) return 0;
+        for (size_t i = 1; i < fc.size(); ++i)
+            if (fc[i].N == frame_len) return (int)i;
+        return -1;
     }
 };
 
@@ -214,9 +233,75 @@ int32_t seg_blocks(int64_t T, int64_t Np, int64_t L, bool per_chunk) {
     return (int32_t)std::max<int64_t>(1, std::min<int64_t>(U, (U + L - 1) / L));
 }
 
+// Window (FP64, its power sums kept), FFT twiddles exp(+2 pi j t / N2)
+// rounded once to FP32 followed by the per-pass tables of a transform of
+// 2^tw_log2 points, and the tile tables of one frame length, uploaded to the
+// device (synchronous).  On failure the tables allocated so far stay in `c`
+// for the caller to free.
+hipError_t build_class_tables(const ps_plan_s* p, FrameClass& c, int tw_log2, int N2) {
+    const int N = c.N;
+    std::vector<double> g;
+    make_window(p->window, N, p->window_param, g);
+    for (int n = 0; n < 5; ++n) {
+        double sum = 0;
+        for (double v : g) sum += std::pow(v, n);
+        c.sum_g[n] = sum;
+    }
+    std::vector<float> gf(N);
+    for (int i = 0; i < N; ++i) gf[i] = (float)g[i];
+    const double two_pi = 6.28318530717958647692;
+    std::vector<float2> tw;
+    tw.reserve(N2 + ps::fft_twiddle_count(tw_log2));
+    for (int t = 0; t < N2; ++t) {
+        const double ang = two_pi * t / N2;
+        tw.push_back(make_float2((float)std::cos(ang), (float)std::sin(ang)));
+    }
+    // per-pass tables of the transform's later passes, [r][k]
+    const int R2 = ps::fft_radix2(tw_log2), R3 = ps::fft_radix3(tw_log2);
+    const int pass_r[2] = {R2, R3}, pass_ns[2] = {16, 16 * R2};
+    for (int q = 0; q < 2; ++q)
+        for (int r = 0; r < pass_r[q]; ++r)
+            for (int k = 0; k < pass_ns[q]; ++k) {
+                const double ang = two_pi * r * k / ((double)pass_r[q] * pass_ns[q]);
+                tw.push_back(make_float2((float)std::cos(ang), (float)std::sin(ang)));
+            }
+    c.T = (c.Ng + ps::kTile - 1) / ps::kTile;
+    c.TX = (c.Ng + ps::kTileX - 1) / ps::kTileX;
+    std::vector<int2> tiles[4];
+    tile_order(c.T, p->tile_group, tiles[ps::kSym64], tiles[ps::kFull64]);
+    tile_order(c.TX, p->tile_group, tiles[ps::kSym32], tiles[ps::kFull32]);
+    for (int i = 0; i < 4; ++i) c.n_tiles[i] = (int)tiles[i].size();
+    auto upload = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 16));
+        if (e != hipSuccess) return e;
+        return bytes ? hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    hipError_t e = upload((void**)&c.d_g, gf.data(), gf.size() * sizeof(float));
+    if (e == hipSuccess) e = upload((void**)&c.d_tw, tw.data(), tw.size() * sizeof(float2));
+    for (int i = 0; i < 4 && e == hipSuccess; ++i)
+        e = upload((void**)&c.d_tiles[i], tiles[i].data(), tiles[i].size() * sizeof(int2));
+    return e;
+}
+
 // ------------------------------------------------------------ batch description
 struct RecInfo {
-    int64_t Np = 0, F = 0, frame0 = 0, chunk0 = 0;
+    int64_t Np = 0, F = 0;
+    int cls = 0;            // frame length (plan class)
+    int bc = 0;             // its entry in Batch.bc
+    int64_t frame0 = 0;     // first frame within its class's coefficient block
+    int64_t chunk0c = 0;    // first chunk within its class
+    int64_t chunk0 = 0;     // first chunk of the batch, class-major (per-chunk S1 means)
+};
+
+// The records of one frame length within a batch: their coefficient block
+// [C][rows][K] (and, with c3^(opt), the block of S3 rows [C][rows3][K]).
+struct BatchClass {
+    int cls = 0;
+    int64_t F = 0, chunks = 0;      // frames and chunks per channel
+    int64_t chunk_base = 0;         // first chunk of the class in the batch
+    int64_t rows = 0, rows3 = 0;    // rows per channel of its blocks
+    size_t coef_off = 0, coef3_off = 0;     // byte offsets in the workspace
+    int rd0 = 0, n_rd = 0;          // its record descriptors in Batch.rd
 };
 
 struct SegTable {
@@ -248,12 +333,12 @@ struct Group {
 struct Batch {
     int stride = 1;                 // internal records per caller record
     std::vector<RecInfo> ri;        // per internal record
-    std::vector<ps::RecDesc> rd;
+    std::vector<ps::RecDesc> rd;    // grouped by class, frame0 ascending within a class
+    std::vector<BatchClass> bc;     // the frame lengths present, in plan class order
     int64_t F_tot = 0, chunks_tot = 0;
-    int64_t coef_rows = 0;          // frames resident per channel in the coefficient region
-    int64_t coef3_rows = 0;         // c3^(opt): S3 rows per channel (m + 1 per chunk)
     std::vector<Group> groups;
-    size_t off_coef = 0, off_coef3 = 0, off_tab = 0, off_part = 0, off_s1 = 0, total = 0;
+    size_t coef_bytes = 0;          // coefficient blocks at the workspace's start
+    size_t off_tab = 0, off_part = 0, off_s1 = 0, total = 0;
     size_t tab_bytes = 0;
     int64_t part_doubles = 0;
 };
@@ -272,18 +357,18 @@ size_t elem_size(int dtype) {
 struct Scales {
     double s1, s2, s3, s4;
 };
-Scales spectrum_scales(const ps_plan_s* p) {
+Scales spectrum_scales(const ps_plan_s* p, const double* sum_g) {
     const int m = p->m;
     const double dt = p->dt;
     const bool nat = p->estimator == PS_EST_NATURAL;
     const double c4a = nat ? m : m * (m + 1.0);
     Scales sc;
-    sc.s1 = 1.0 / p->sum_g[1];
-    sc.s2 = dt / ((nat ? m : m - 1) * p->sum_g[2]);
+    sc.s1 = 1.0 / sum_g[1];
+    sc.s2 = dt / ((nat ? m : m - 1) * sum_g[2]);
     // c3^(opt): the S3 sum over the m + 1 rows of each chunk times (m+4)/((m+1) m)
     const double c3f = p->c3opt() ? (m + 4.0) / ((m + 1.0) * m) : nat ? 1.0 / m : m / ((double)(m - 1) * (m - 2));
-    sc.s3 = dt * dt * c3f / p->sum_g[3];
-    sc.s4 = dt * dt * dt * c4a / ((nat ? (double)m * m : (double)(m - 1) * (m - 2) * (m - 3)) * p->sum_g[4]);
+    sc.s3 = dt * dt * c3f / sum_g[3];
+    sc.s4 = dt * dt * dt * c4a / ((nat ? (double)m * m : (double)(m - 1) * (m - 2) * (m - 3)) * sum_g[4]);
     return sc;
 }
 
@@ -291,36 +376,72 @@ void finish_layout(const ps_plan_s* p, Batch& B);
 
 void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_output* outs, Batch& B) {
     const bool per_chunk = p->schedule == PS_SCHED_PER_CHUNK;
-    const int m = p->m, K = p->K, Nf = p->Ng;      // Nf: points per output axis
-    const int64_t nf2 = (int64_t)Nf * Nf;
-    const Scales scl = spectrum_scales(p);
-    const double scale2 = scl.s2, scale3 = scl.s3, scale4 = scl.s4;
+    const int m = p->m;
     const bool opt3 = p->c3opt();
     B.stride = p->interlaced ? 2 : 1;
     const int n_int = n * B.stride;
     B.ri.assign(n_int, RecInfo{});
-    B.rd.assign(n_int, ps::RecDesc{});
+    // chunk counts and frame lengths
+    std::vector<int> bc_of(p->fc.size(), -1);
     for (int ir = 0; ir < n_int; ++ir) {
         const ps_record& rec = recs[ir / B.stride];
-        // the shifted frame set of interlaced windows starts T/2 = N/2 samples later
-        const int64_t skip = (ir % B.stride) ? p->N / 2 : 0;
-        const size_t esz = elem_size(rec.dtype);
         RecInfo& q = B.ri[ir];
-        q.Np = (std::max<int64_t>(0, rec.n_samples - skip) / p->N) / m;
+        q.cls = std::max(0, p->class_of(rec.frame_len));
+        const int Nr = p->fc[q.cls].N;
+        // the shifted frame set of interlaced windows starts T/2 = N/2 samples later
+        const int64_t skip = (ir % B.stride) ? Nr / 2 : 0;
+        q.Np = (std::max<int64_t>(0, rec.n_samples - skip) / Nr) / m;
         q.F = q.Np * m;
-        q.frame0 = B.F_tot;
-        q.chunk0 = B.chunks_tot;
-        B.F_tot += q.F;
-        B.chunks_tot += q.Np;
-        ps::RecDesc& d = B.rd[ir];
-        d.data = q.Np > 0 ? static_cast<const char*>(rec.d_data) + skip * esz : rec.d_data;
-        d.chan_stride = rec.channel_stride;
-        d.frame0 = q.frame0;
-        d.dtype = rec.dtype;
-        d.pad = 0;
+        bc_of[q.cls] = 0;
     }
-    B.coef_rows = per_chunk ? m : B.F_tot;
-    B.coef3_rows = opt3 ? (per_chunk ? 1 : B.chunks_tot) * (m + 1) : 0;
+    for (size_t c = 0; c < p->fc.size(); ++c)
+        if (bc_of[c] == 0) {
+            bc_of[c] = (int)B.bc.size();
+            B.bc.push_back(BatchClass{});
+            B.bc.back().cls = (int)c;
+        }
+    // frames and chunks numbered per class; descriptors grouped by class
+    int64_t chunk_base = 0;
+    for (size_t b = 0; b < B.bc.size(); ++b) {
+        BatchClass& k = B.bc[b];
+        k.rd0 = (int)B.rd.size();
+        for (int ir = 0; ir < n_int; ++ir) {
+            RecInfo& q = B.ri[ir];
+            if (q.cls != k.cls) continue;
+            const ps_record& rec = recs[ir / B.stride];
+            const int64_t skip = (ir % B.stride) ? p->fc[q.cls].N / 2 : 0;
+            q.bc = (int)b;
+            q.frame0 = k.F;
+            q.chunk0c = k.chunks;
+            k.F += q.F;
+            k.chunks += q.Np;
+            ps::RecDesc d{};
+            d.data = q.Np > 0 ? static_cast<const char*>(rec.d_data) + skip * elem_size(rec.dtype) : rec.d_data;
+            d.chan_stride = rec.channel_stride;
+            d.frame0 = q.frame0;
+            d.dtype = rec.dtype;
+            B.rd.push_back(d);
+        }
+        k.n_rd = (int)B.rd.size() - k.rd0;
+        k.chunk_base = chunk_base;
+        chunk_base += k.chunks;
+        B.F_tot += k.F;
+        B.chunks_tot += k.chunks;
+    }
+    for (RecInfo& q : B.ri) q.chunk0 = B.bc[q.bc].chunk_base + q.chunk0c;
+    // coefficient blocks (the per-chunk schedule holds one chunk per class)
+    size_t off = 0;
+    for (BatchClass& k : B.bc) {
+        k.rows = per_chunk ? m : k.F;
+        k.coef_off = off;
+        off = align256(off + (size_t)p->C * k.rows * p->fc[k.cls].K * sizeof(float2));
+    }
+    for (BatchClass& k : B.bc) {
+        k.rows3 = opt3 ? (per_chunk ? 1 : k.chunks) * (m + 1) : 0;
+        k.coef3_off = off;
+        off = align256(off + (size_t)p->C * k.rows3 * p->fc[k.cls].K * sizeof(float2));
+    }
+    B.coef_bytes = off;
 
     // groups (interlaced windows: batched schedule only)
     if (per_chunk) {
@@ -332,7 +453,6 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
     } else {
         B.groups.emplace_back();
     }
-    const int kblocks = (Nf + 255) / 256;
     const int64_t TT = (int64_t)ps::kTile * ps::kTile, TX = (int64_t)ps::kTileX * ps::kTileX;
     int64_t part = 0;
     for (Group& G : B.groups) {
@@ -342,11 +462,13 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
         for (int r = r_lo; r < r_hi; ++r) {
             const int64_t Np = B.ri[r].Np;
             if (Np == 0) continue;
+            const FrameClass& fc = p->fc[B.ri[r].cls];
+            const int kblocks = (fc.Ng + 255) / 256;
             for (int i = 0; i < p->n2(); ++i) U2.push_back((int64_t)kblocks * Np);
-            for (int i = 0; i < p->n3(); ++i) U3.push_back(p->n_tiles[p->s3_sym(i) ? ps::kSym64 : ps::kFull64] * Np);
+            for (int i = 0; i < p->n3(); ++i) U3.push_back(fc.n_tiles[p->s3_sym(i) ? ps::kSym64 : ps::kFull64] * Np);
             for (int i = 0; i < p->n4(); ++i) {
-                if (p->s4_single(i)) U4s.push_back(p->n_tiles[ps::kSym64] * Np);
-                else U4x.push_back(p->n_tiles[p->s4_sym(i) ? ps::kSym32 : ps::kFull32] * Np);
+                if (p->s4_single(i)) U4s.push_back(fc.n_tiles[ps::kSym64] * Np);
+                else U4x.push_back(fc.n_tiles[p->s4_sym(i) ? ps::kSym32 : ps::kFull32] * Np);
             }
         }
         const int64_t L2 = units_per_block(U2, 4LL * p->n_cu);
@@ -359,6 +481,12 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
         for (int r = r_lo; r < r_hi; ++r) {
             const RecInfo& q = B.ri[r];
             if (q.Np == 0) continue;
+            const FrameClass& fc = p->fc[q.cls];
+            const BatchClass& k = B.bc[q.bc];
+            const int K = fc.K, Nf = fc.Ng;     // Nf: points per output axis
+            const int64_t nf2 = (int64_t)Nf * Nf;
+            const int kblocks = (Nf + 255) / 256;
+            const Scales scl = spectrum_scales(p, fc.sum_g);
             const bool twin = r % B.stride != 0;   // shifted set: no output of its own
             const ps_output* o = outs ? &outs[r / B.stride] : nullptr;
             // a finalize segment for the first set, or the twin's sums attached to it
@@ -374,7 +502,11 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 }
             };
             ps::Seg base{};
-            base.coef = q.chunk0 * m * K;
+            // the record's chunk 0 (per-chunk schedule: the class block holds the current chunk)
+            base.coef = (int64_t)(k.coef_off / sizeof(float2)) + (per_chunk ? 0 : q.frame0 * K);
+            base.cs = k.rows * K;
+            base.K = K;
+            base.Nf = Nf;
             base.n_chunks = (int32_t)q.Np;
             if (p->has(1)) {
                 // S1 per channel: the record's per-chunk means of a_0 from index chunk0
@@ -398,7 +530,7 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 part += ps::Sched{sg.n_tiles, q.Np, sg.blocks}.n_slots() * 4 * 256;
                 sg.out = o && o->d_s2 ? o->d_s2 + 2 * (int64_t)i * Nf : nullptr;
                 sg.err = o && o->d_s2_err ? o->d_s2_err + 2 * (int64_t)i * Nf : nullptr;
-                sg.scale = scale2;
+                sg.scale = scl.s2;
                 sg.ncomp = 4;
                 G.s2.add(sg, sg.blocks);
                 finalize(G.f2, fin2, i, sg, kblocks);
@@ -407,15 +539,19 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 ps::Seg sg = base;
                 const bool sym = p->s3_sym(i);
                 sg.tiles = sym ? ps::kSym64 : ps::kFull64;
-                sg.n_tiles = p->n_tiles[sg.tiles];
+                sg.tile_tab = fc.d_tiles[sg.tiles];
+                sg.n_tiles = fc.n_tiles[sg.tiles];
                 sg.blocks = seg_blocks(sg.n_tiles, q.Np, L3, per_chunk);
                 for (int j = 0; j < 3; ++j) sg.ch[j] = p->c3[3 * i + j];
-                if (opt3) sg.coef = q.chunk0 * (m + 1) * K;
+                if (opt3) {     // the S3 rows of c3^(opt): m + 1 per chunk
+                    sg.coef = (int64_t)(k.coef3_off / sizeof(float2)) + (per_chunk ? 0 : q.chunk0c * (m + 1) * K);
+                    sg.cs = k.rows3 * K;
+                }
                 sg.part = part;
                 part += ps::Sched{sg.n_tiles, q.Np, sg.blocks}.n_slots() * 4 * TT;
                 sg.out = o && o->d_s3 ? o->d_s3 + 2 * i * nf2 : nullptr;
                 sg.err = o && o->d_s3_err ? o->d_s3_err + 2 * i * nf2 : nullptr;
-                sg.scale = scale3;
+                sg.scale = scl.s3;
                 sg.sym = sym;
                 sg.ncomp = 4;
                 G.s3.add(sg, sg.blocks);
@@ -425,7 +561,8 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 ps::Seg sg = base;
                 const bool single = p->s4_single(i), sym = p->s4_sym(i);
                 sg.tiles = single ? ps::kSym64 : (sym ? ps::kSym32 : ps::kFull32);
-                sg.n_tiles = p->n_tiles[sg.tiles];
+                sg.tile_tab = fc.d_tiles[sg.tiles];
+                sg.n_tiles = fc.n_tiles[sg.tiles];
                 sg.blocks = seg_blocks(sg.n_tiles, q.Np, single ? L4s : L4x, per_chunk);
                 for (int j = 0; j < 4; ++j) sg.ch[j] = p->c4[4 * i + j];
                 sg.ncomp = single ? 2 : 4;
@@ -433,7 +570,7 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 part += ps::Sched{sg.n_tiles, q.Np, sg.blocks}.n_slots() * sg.ncomp * (single ? TT : TX);
                 sg.out = o && o->d_s4 ? o->d_s4 + 2 * i * nf2 : nullptr;
                 sg.err = o && o->d_s4_err ? o->d_s4_err + 2 * i * nf2 : nullptr;
-                sg.scale = scale4;
+                sg.scale = scl.s4;
                 sg.sym = sym;
                 (single ? G.s4s : G.s4x).add(sg, sg.blocks);
                 finalize(G.f4, fin4, i, sg, (int64_t)sg.n_tiles * ((single ? TT : TX) / 256));
@@ -447,7 +584,6 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
 // Table region and workspace offsets of a built batch (again after tables
 // were added to its groups).
 void finish_layout(const ps_plan_s* p, Batch& B) {
-    const int K = p->K;
     // table region: record descriptors, then every segment table
     size_t tab = align64(sizeof(ps::RecDesc) * std::max<size_t>(1, B.rd.size()));
     for (Group& G : B.groups)
@@ -456,11 +592,7 @@ void finish_layout(const ps_plan_s* p, Batch& B) {
             tab = align64(tab + sizeof(ps::Seg) * t->v.size());
         }
     B.tab_bytes = tab;
-    size_t off = 0;
-    B.off_coef = off;
-    off = align256(off + (size_t)p->C * B.coef_rows * K * sizeof(float2));
-    B.off_coef3 = off;
-    off = align256(off + (size_t)p->C * B.coef3_rows * K * sizeof(float2));
+    size_t off = B.coef_bytes;
     B.off_tab = off;
     off = align256(off + B.tab_bytes);
     B.off_part = off;
@@ -500,12 +632,13 @@ ps_status check_record(const ps_plan_s* p, const ps_record* r) {
         return fail(PS_E_INVALID_ARG, "dtype %d does not match the plan's %s signal", r->dtype,
                     p->cplx ? "complex" : "real");
     if (r->n_samples < 0) return fail(PS_E_INVALID_ARG, "n_samples < 0");
-    if (r->reserved != 0) return fail(PS_E_INVALID_ARG, "record.reserved must be 0");
+    const int cls = p->class_of(r->frame_len);
+    if (cls < 0) return fail(PS_E_INVALID_ARG, "record frame_len %d is not among the plan's frame lengths", r->frame_len);
     if (p->C > 1 && r->channel_stride < r->n_samples)
         return fail(PS_E_INVALID_ARG, "channel_stride (%lld) < n_samples (%lld)",
                     (long long)r->channel_stride, (long long)r->n_samples);
     const size_t esz = elem_size(r->dtype);
-    if (r->n_samples >= (int64_t)p->N * p->m) {
+    if (r->n_samples >= (int64_t)p->fc[cls].N * p->m) {
         if (!r->d_data) return fail(PS_E_INVALID_ARG, "record data is NULL");
         if (!aligned(r->d_data, esz)) return fail(PS_E_INVALID_ARG, "record data misaligned");
     }
@@ -560,9 +693,11 @@ ps_status ps_plan_destroy(ps_plan_t p) {
         }
         if (p->h_stage[i]) hipHostFree(p->h_stage[i]);
     }
-    hipFree(p->d_g);
-    hipFree(p->d_tw);
-    for (int i = 0; i < 4; ++i) hipFree(p->d_tiles[i]);
+    for (FrameClass& c : p->fc) {
+        hipFree(c.d_g);
+        hipFree(c.d_tw);
+        for (int i = 0; i < 4; ++i) hipFree(c.d_tiles[i]);
+    }
     delete p;
     return PS_OK;
 }
@@ -571,8 +706,10 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     if (!out) return fail(PS_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (!cfg) return fail(PS_E_INVALID_ARG, "cfg is NULL");
-    if (cfg->struct_size < sizeof(ps_config))
-        return fail(PS_E_INVALID_ARG, "struct_size %u < %zu", cfg->struct_size, sizeof(ps_config));
+    // (a ps_config without the trailing frame_len_set is accepted: no further frame lengths)
+    if (cfg->struct_size < offsetof(ps_config, frame_len_set))
+        return fail(PS_E_INVALID_ARG, "struct_size %u < %zu", cfg->struct_size, offsetof(ps_config, frame_len_set));
+    const uint32_t fl_set = cfg->struct_size >= sizeof(ps_config) ? (uint32_t)cfg->frame_len_set : 0u;
     const uint32_t known = PS_ORDER_S1 | PS_ORDER_S2 | PS_ORDER_S3 | PS_ORDER_S4;
     if (cfg->orders == 0 || (cfg->orders & ~known))
         return fail(PS_E_INVALID_ARG, "orders must be a non-empty subset of {1,2,3,4}");
@@ -638,6 +775,34 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
         return fail(PS_E_INVALID_ARG, "N_f - 1 must be <= N/2 (N_f = %d, N = %d)", Nf, N);
     if (cfg->s4_shift != 0 && Nf - 1 + std::abs(cfg->s4_shift) > N / 2)
         return fail(PS_E_INVALID_ARG, "S4 plane needs N_f - 1 + |q| <= N/2 (q = %d)", cfg->s4_shift);
+
+    // Further frame lengths (frame_len_set): powers of two 256..8192, real
+    // signals; N_f scales with N when n_freq is given, else follows f_max.
+    int class_nf[14] = {0};
+    if (fl_set) {
+        if (fl_set & ~0x3F00u) return fail(PS_E_INVALID_ARG, "frame_len_set holds bits outside 8..13 (256..8192)");
+        if (cfg->complex_signal || pf)
+            return fail(PS_E_UNSUPPORTED, "further frame lengths need real signals and a power-of-two frame_len");
+        for (int q = 8; q <= 13; ++q) {
+            if (!(fl_set >> q & 1u) || (1 << q) == N) continue;
+            const int Nq = 1 << q;
+            int nfq;
+            if (cfg->n_freq > 0) {
+                if (((int64_t)Nf * Nq) % N != 0)
+                    return fail(PS_E_INVALID_ARG, "n_freq %d does not scale to frame length %d (n_freq * %d / %d)", Nf,
+                                Nq, Nq, N);
+                nfq = (int)((int64_t)Nf * Nq / N);
+            } else {
+                nfq = (int)std::floor(cfg->f_max * Nq * cfg->dt) + 1;
+            }
+            if (nfq < 1) return fail(PS_E_INVALID_ARG, "frame length %d: N_f < 1", Nq);
+            if (s3 && 2 * (nfq - 1) > Nq / 2)
+                return fail(PS_E_INVALID_ARG, "frame length %d: S3 needs 2 (N_f - 1) <= N/2 (N_f = %d)", Nq, nfq);
+            if (!s3 && nfq - 1 > Nq / 2)
+                return fail(PS_E_INVALID_ARG, "frame length %d: N_f - 1 must be <= N/2 (N_f = %d)", Nq, nfq);
+            class_nf[q] = nfq;
+        }
+    }
 
     auto* p = new ps_plan_s();
     p->N = N;
@@ -707,57 +872,43 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
             }
     }
 
-    // Window and sums (FP64); FFT twiddles exp(+2 pi j t/N) rounded once to FP32.
-    std::vector<double> g;
-    make_window(p->window, N, p->window_param, g);
-    for (int n = 0; n < 5; ++n) {
-        double s = 0;
-        for (double v : g) s += std::pow(v, n);
-        p->sum_g[n] = s;
+    // Tables of the plan's frame length (class 0): the twiddle layout depends
+    // on the transform (complex signals: the tables of a real transform of
+    // twice the frame length, whose complex transform has the frame length;
+    // prime-factor lengths: the unpack table of N entries, then the pass
+    // tables of the 2^q-point subsequence transforms).
+    FrameClass c0;
+    c0.N = N;
+    c0.log2n_fft = p->log2n_fft;
+    c0.Nf = p->Nf;
+    c0.Ng = p->Ng;
+    c0.K = p->K;
+    c0.jmax = p->jmax;
+    hipError_t e = build_class_tables(p, c0, p->pf ? p->log2n + 1 : p->log2n_fft, p->pf ? N : 1 << p->log2n_fft);
+    p->fc.push_back(c0);        // owns the device tables (also freed on failure)
+    if (e == hipSuccess) {
+        for (int n = 0; n < 5; ++n) p->sum_g[n] = c0.sum_g[n];
+        p->T = c0.T;
+        p->TX = c0.TX;
+        for (int i = 0; i < 4; ++i) p->n_tiles[i] = c0.n_tiles[i];
+        p->d_g = c0.d_g;
+        p->d_tw = c0.d_tw;
+        for (int i = 0; i < 4; ++i) p->d_tiles[i] = c0.d_tiles[i];
     }
-    std::vector<float> gf(N);
-    for (int i = 0; i < N; ++i) gf[i] = (float)g[i];
-    const double two_pi = 6.28318530717958647692;
-    // (complex signals: the tables of a real transform of twice the frame
-    // length, whose complex transform has the frame length; the first N2
-    // entries are then unused)
-    // (prime-factor lengths: the unpack table of N entries, then the pass
-    // tables of the 2^q-point subsequence transforms)
-    const int tw_log2 = p->pf ? p->log2n + 1 : p->log2n_fft;
-    const int N2 = p->pf ? N : 1 << p->log2n_fft;
-    std::vector<float2> tw;
-    tw.reserve(N2 + ps::fft_twiddle_count(tw_log2));
-    for (int t = 0; t < N2; ++t) {
-        const double ang = two_pi * t / N2;
-        tw.push_back(make_float2((float)std::cos(ang), (float)std::sin(ang)));
+    // Further frame lengths (real signals): N_f scaled with N (n_freq given)
+    // or taken from f_max, K and the constraints as for class 0.
+    for (int q = 8; q <= 13 && e == hipSuccess; ++q) {
+        const int Nq = 1 << q;
+        if (!(fl_set >> q & 1u) || Nq == N) continue;
+        FrameClass c;
+        c.N = Nq;
+        c.log2n_fft = q;
+        c.Nf = class_nf[q];
+        c.Ng = c.Nf;
+        c.K = s3 ? 2 * c.Nf - 1 : c.Nf;
+        e = build_class_tables(p, c, q, Nq);
+        p->fc.push_back(c);
     }
-    // per-pass tables of the transform's later passes, [r][k]
-    const int R2 = ps::fft_radix2(tw_log2), R3 = ps::fft_radix3(tw_log2);
-    const int pass_r[2] = {R2, R3}, pass_ns[2] = {16, 16 * R2};
-    for (int q = 0; q < 2; ++q)
-        for (int r = 0; r < pass_r[q]; ++r)
-            for (int k = 0; k < pass_ns[q]; ++k) {
-                const double ang = two_pi * r * k / ((double)pass_r[q] * pass_ns[q]);
-                tw.push_back(make_float2((float)std::cos(ang), (float)std::sin(ang)));
-            }
-
-    p->T = (p->Ng + ps::kTile - 1) / ps::kTile;
-    p->TX = (p->Ng + ps::kTileX - 1) / ps::kTileX;
-    std::vector<int2> tiles[4];
-    tile_order(p->T, p->tile_group, tiles[ps::kSym64], tiles[ps::kFull64]);
-    tile_order(p->TX, p->tile_group, tiles[ps::kSym32], tiles[ps::kFull32]);
-    for (int i = 0; i < 4; ++i) p->n_tiles[i] = (int)tiles[i].size();
-
-    auto upload = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
-        hipError_t e = hipMalloc(dst, bytes);
-        if (e != hipSuccess) return e;
-        return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
-    };
-    hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = upload((void**)&p->d_g, gf.data(), gf.size() * sizeof(float));
-    if (e == hipSuccess) e = upload((void**)&p->d_tw, tw.data(), tw.size() * sizeof(float2));
-    for (int i = 0; i < 4 && e == hipSuccess; ++i)
-        e = upload((void**)&p->d_tiles[i], tiles[i].data(), tiles[i].size() * sizeof(int2));
     if (e != hipSuccess) {
         ps_plan_destroy(p);
         return fail(PS_E_HIP, "device table setup failed: %s", hipGetErrorString(e));
@@ -791,14 +942,16 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
 // ------------------------------------------------------------ launch configuration
 namespace {
 hipError_t write_tiles(ps_plan_t p) {
-    std::vector<int2> tiles[4];
-    tile_order(p->T, p->tile_group, tiles[ps::kSym64], tiles[ps::kFull64]);
-    tile_order(p->TX, p->tile_group, tiles[ps::kSym32], tiles[ps::kFull32]);
-    for (int i = 0; i < 4; ++i) {
-        if (tiles[i].empty()) continue;
-        const hipError_t e = hipMemcpy(p->d_tiles[i], tiles[i].data(), tiles[i].size() * sizeof(int2),
-                                       hipMemcpyHostToDevice);
-        if (e != hipSuccess) return e;
+    for (const FrameClass& c : p->fc) {
+        std::vector<int2> tiles[4];
+        tile_order(c.T, p->tile_group, tiles[ps::kSym64], tiles[ps::kFull64]);
+        tile_order(c.TX, p->tile_group, tiles[ps::kSym32], tiles[ps::kFull32]);
+        for (int i = 0; i < 4; ++i) {
+            if (tiles[i].empty()) continue;
+            const hipError_t e = hipMemcpy(c.d_tiles[i], tiles[i].data(), tiles[i].size() * sizeof(int2),
+                                           hipMemcpyHostToDevice);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
@@ -952,6 +1105,32 @@ ps_status ps_record_info(ps_plan_t p, int64_t n_samples, int64_t* n_chunks, uint
     return PS_OK;
 }
 
+ps_status ps_record_chunks(ps_plan_t p, const ps_record* rec, int64_t* n_chunks, uint32_t* flags) {
+    if (!p || !rec || rec->n_samples < 0) return fail(PS_E_INVALID_ARG, "bad argument");
+    const int cls = p->class_of(rec->frame_len);
+    if (cls < 0) return fail(PS_E_INVALID_ARG, "frame_len %d is not among the plan's frame lengths", rec->frame_len);
+    const int64_t np = (rec->n_samples / p->fc[cls].N) / p->m;
+    if (n_chunks) *n_chunks = np;
+    if (flags) *flags = (np == 0 ? PS_FLAG_EMPTY : 0u) | (np == 1 ? PS_FLAG_NO_ERRBAR : 0u);
+    return PS_OK;
+}
+
+ps_status ps_plan_frame_info(ps_plan_t p, int32_t frame_len, ps_plan_info* info) {
+    if (!p || !info) return fail(PS_E_INVALID_ARG, "NULL argument");
+    const int cls = p->class_of(frame_len);
+    if (cls < 0) return fail(PS_E_INVALID_ARG, "frame_len %d is not among the plan's frame lengths", frame_len);
+    ps_status s = ps_plan_query(p, info);
+    if (s != PS_OK) return s;
+    const FrameClass& fc = p->fc[cls];
+    info->frame_len = fc.N;
+    info->n_freq = fc.Nf;
+    info->n_coef = fc.K;
+    info->grid = fc.Ng;
+    info->f_max = (fc.Nf - 1) / (fc.N * p->dt);
+    for (int n = 0; n < 5; ++n) info->sum_g[n] = fc.sum_g[n];
+    return PS_OK;
+}
+
 ps_status ps_workspace_size(ps_plan_t p, const ps_record* recs, int32_t n_rec, size_t* bytes) {
     if (!p || !bytes || n_rec < 0 || (n_rec > 0 && !recs)) return fail(PS_E_INVALID_ARG, "bad argument");
     for (int i = 0; i < n_rec; ++i) {
@@ -968,28 +1147,31 @@ ps_status ps_coefficients(ps_plan_t p, const ps_record* rec, float* d_coef, ps_s
     if (!p || !rec) return fail(PS_E_INVALID_ARG, "NULL argument");
     ps_status st = check_record(p, rec);
     if (st != PS_OK) return st;
-    const int64_t F = ((rec->n_samples / p->N) / p->m) * p->m;
+    const FrameClass& fc = p->fc[p->class_of(rec->frame_len)];
+    const int64_t F = ((rec->n_samples / fc.N) / p->m) * p->m;
     if (F == 0) return PS_OK;
     if (!d_coef || !aligned(d_coef, 8)) return fail(PS_E_INVALID_ARG, "coefficient buffer NULL or misaligned");
     ps::FftArgs a{};
-    a.recs = nullptr;
-    a.single = ps::RecDesc{rec->d_data, rec->channel_stride, 0, rec->dtype, 0};
-    a.n_recs = 1;
-    a.g_lo = 0;
-    a.g_hi = F;
-    a.out_g0 = 0;
+    a.n_cls = 1;
+    ps::FftClass& c = a.cls[0];
+    c.recs = nullptr;
+    c.single = ps::RecDesc{rec->d_data, rec->channel_stride, 0, rec->dtype, 0};
+    c.n_recs = 1;
+    c.g_lo = 0;
+    c.g_hi = F;
+    c.out_g0 = 0;
+    c.log2n = p->pf ? p->log2n : fc.log2n_fft;
+    c.jmax = fc.jmax;
+    c.K = fc.K;
+    c.g = fc.d_g;
+    c.tw = fc.d_tw;
+    c.out = reinterpret_cast<float2*>(d_coef);
+    c.out_chan_stride = F * fc.K;
     a.n_channels = p->C;
-    a.log2n = p->log2n_fft;
     a.cplx = p->cplx;
-    a.jmax = p->jmax;
     a.pf = p->pf;
     a.pf_c = p->pf_c;
     a.pf_d = p->pf_d;
-    a.K = p->K;
-    a.g = p->d_g;
-    a.tw = p->d_tw;
-    a.out = reinterpret_cast<float2*>(d_coef);
-    a.out_chan_stride = F * p->K;
     PS_HIP(ps::launch_window_rfft(a, (hipStream_t)stream));
     return PS_OK;
 }
@@ -1032,13 +1214,9 @@ ps::BatchArgs batch_args(const ps_plan_s* p, const Batch& B, const SegTable& t, 
     a.segs = reinterpret_cast<const ps::Seg*>(tab + t.dev_off);
     a.n_segs = (int)t.v.size();
     a.n_items = t.n_items;
-    a.tt = p->tables();
-    a.coef = reinterpret_cast<const float2*>(ws + B.off_coef);
-    a.coef_chan_stride = B.coef_rows * p->K;
+    a.coef = reinterpret_cast<const float2*>(ws);     // segments hold offsets from the workspace start
     a.part = reinterpret_cast<double*>(ws + B.off_part);
-    a.K = p->K;
     a.m = p->m;
-    a.Nf = p->Ng;
     a.col0 = p->col0;
     a.col3 = p->cplx ? p->jmax - 2 * (p->Nf - 1) : 0;
     a.per_chunk = per_chunk;
@@ -1057,9 +1235,7 @@ ps::FinalizeArgs fin_args(const ps_plan_s* p, const Batch& B, const SegTable& t,
     f.segs = reinterpret_cast<const ps::Seg*>(tab + t.dev_off);
     f.n_segs = (int)t.v.size();
     f.n_items = t.n_items;
-    f.tt = p->tables();
     f.part = reinterpret_cast<const double*>(ws + B.off_part);
-    f.Nf = p->Ng;
     f.s1 = p->has(1) ? reinterpret_cast<const float2*>(ws + B.off_s1) : nullptr;
     f.s1_cs = B.chunks_tot;
     return f;
@@ -1075,12 +1251,9 @@ ps_status launch_moments(ps_plan_t p, const Batch& B, const Group& G, char* ws, 
     if (G.s3.n_items) {
         StageTimer t(p, st, 3);
         ps::BatchArgs a = batch_args(p, B, G.s3, ws, tab, per_chunk, win_lo, win_hi, accumulate);
-        if (p->c3opt()) {
-            // the c3^(opt) rows: m shifted frames and one mean row per chunk
-            a.coef = reinterpret_cast<const float2*>(ws + B.off_coef3);
-            a.coef_chan_stride = B.coef3_rows * p->K;
-            a.m = p->m + 1;
-        }
+        // the c3^(opt) rows: m shifted frames and one mean row per chunk
+        // (the segments point at their blocks)
+        if (p->c3opt()) a.m = p->m + 1;
         PS_HIP(ps::launch_s3(a, st));
     }
     if (G.s4s.n_items) {
@@ -1142,10 +1315,11 @@ struct AccumTarget {
 // table) instead of being finalized into outputs.
 ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_t n_rec, const ps_output* outs,
                       char* ws, const char* tab, hipStream_t st, const AccumTarget* acc = nullptr) {
-    const int Nf = p->Ng, m = p->m;
-    const int64_t nf2 = (int64_t)Nf * Nf;
+    const int m = p->m;
     for (int r = 0; r < n_rec && outs; ++r) {
         if (B.ri[r * B.stride].Np > 0) continue;
+        const int Nf = p->fc[B.ri[r * B.stride].cls].Ng;
+        const int64_t nf2 = (int64_t)Nf * Nf;
         const ps_output& o = outs[r];
         PS_HIP(ps::launch_fill_nan(o.d_s2, 2 * (int64_t)p->n2() * Nf, st));
         PS_HIP(ps::launch_fill_nan(o.d_s2_err, 2 * (int64_t)p->n2() * Nf, st));
@@ -1159,52 +1333,79 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
         }
     }
     if (B.chunks_tot == 0) return PS_OK;
-    float2* coef = reinterpret_cast<float2*>(ws + B.off_coef);
-    const int64_t coef_cs = B.coef_rows * p->K;
 
     ps::FftArgs fa{};
     fa.n_channels = p->C;
-    fa.log2n = p->log2n_fft;
     fa.cplx = p->cplx;
-    fa.jmax = p->jmax;
     fa.pf = p->pf;
     fa.pf_c = p->pf_c;
     fa.pf_d = p->pf_d;
-    fa.K = p->K;
-    fa.g = p->d_g;
-    fa.tw = p->d_tw;
-    fa.out = coef;
-    fa.out_chan_stride = coef_cs;
     ps::CentreArgs ca{};
-    ca.coef = coef;
-    ca.coef_chan_stride = coef_cs;
-    ca.K = p->K;
     ca.m = m;
     ca.n_channels = p->C;
     ca.s1 = p->has(1) ? reinterpret_cast<float2*>(ws + B.off_s1) : nullptr;
     ca.s1_cs = B.chunks_tot;
-    ca.s1_chunk0 = 0;
     ca.s1_col = p->jmax;
     if (p->c3opt()) {
         const double alpha = 4.0 / (m + 4.0);
-        ca.out3 = reinterpret_cast<float2*>(ws + B.off_coef3);
-        ca.out3_cs = B.coef3_rows * p->K;
         ca.alpha = (float)alpha;
         ca.mu = (float)std::cbrt(m * ((4.0 - 2.0 * m) / (m + 4.0) - alpha * alpha * alpha));
     }
+    // The transform and centring arguments of one frame length's block.
+    auto fft_class = [&](const BatchClass& k) {
+        const FrameClass& fc = p->fc[k.cls];
+        ps::FftClass c{};
+        c.log2n = p->pf ? p->log2n : fc.log2n_fft;
+        c.K = fc.K;
+        c.jmax = fc.jmax;
+        c.g = fc.d_g;
+        c.tw = fc.d_tw;
+        c.out = reinterpret_cast<float2*>(ws + k.coef_off);
+        c.out_chan_stride = k.rows * fc.K;
+        return c;
+    };
+    auto centre_class = [&](const BatchClass& k) {
+        const FrameClass& fc = p->fc[k.cls];
+        ps::CentreClass c{};
+        c.coef = reinterpret_cast<float2*>(ws + k.coef_off);
+        c.coef_chan_stride = k.rows * fc.K;
+        c.K = fc.K;
+        if (p->c3opt()) {
+            c.out3 = reinterpret_cast<float2*>(ws + k.coef3_off);
+            c.out3_cs = k.rows3 * fc.K;
+        }
+        return c;
+    };
     ps_status s = PS_OK;
 
     if (p->schedule != PS_SCHED_PER_CHUNK) {
-        fa.recs = reinterpret_cast<const ps::RecDesc*>(tab);
-        fa.n_recs = (int)B.rd.size();
-        fa.g_lo = 0;
-        fa.g_hi = B.F_tot;
-        fa.out_g0 = 0;
+        // every frame length in one launch per stage
+        int64_t fft_blocks = 0, centre_blocks = 0;
+        for (const BatchClass& k : B.bc) {
+            if (k.chunks == 0) continue;
+            if (fa.n_cls == ps::kMaxClasses || ca.n_cls == ps::kMaxClasses)
+                return fail(PS_E_INTERNAL, "more than %d frame lengths in one batch", ps::kMaxClasses);
+            ps::FftClass c = fft_class(k);
+            c.recs = reinterpret_cast<const ps::RecDesc*>(tab) + k.rd0;
+            c.n_recs = k.n_rd;
+            c.g_lo = 0;
+            c.g_hi = k.F;
+            c.out_g0 = 0;
+            c.block0 = fft_blocks;
+            fft_blocks += (k.F + (8192 / p->fc[k.cls].N) - 1) / (8192 / p->fc[k.cls].N);
+            fa.cls[fa.n_cls++] = c;
+            ps::CentreClass d = centre_class(k);
+            d.n_chunks = k.chunks;
+            d.s1_chunk0 = k.chunk_base;
+            d.block0 = centre_blocks;
+            centre_blocks += (int64_t)((p->fc[k.cls].K + 255) / 256) * k.chunks;
+            ca.cls[ca.n_cls++] = d;
+        }
+        if (fa.n_cls == 1) fa.cls[0].block0 = 0;
         {
             StageTimer t(p, st, 0);
             PS_HIP(ps::launch_window_rfft(fa, st));
         }
-        ca.n_chunks = B.chunks_tot;
         {
             StageTimer t(p, st, 1);
             PS_HIP(ps::launch_centre(ca, st));
@@ -1231,19 +1432,24 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
     // Per-chunk schedule: one short-time estimate per launch set, record by record.
     for (const Group& G : B.groups) {
         const int r = G.rec;
-        fa.recs = nullptr;
-        fa.single = ps::RecDesc{recs[r].d_data, recs[r].channel_stride, 0, recs[r].dtype, 0};
-        fa.n_recs = 1;
+        const BatchClass& k = B.bc[B.ri[r].bc];
+        fa.n_cls = 1;
+        ca.n_cls = 1;
+        fa.cls[0] = fft_class(k);
+        fa.cls[0].recs = nullptr;
+        fa.cls[0].single = ps::RecDesc{recs[r].d_data, recs[r].channel_stride, 0, recs[r].dtype, 0};
+        fa.cls[0].n_recs = 1;
+        ca.cls[0] = centre_class(k);
         for (int64_t c = 0; c < B.ri[r].Np; ++c) {
-            fa.g_lo = c * m;
-            fa.g_hi = (c + 1) * m;
-            fa.out_g0 = c * m;
+            fa.cls[0].g_lo = c * m;
+            fa.cls[0].g_hi = (c + 1) * m;
+            fa.cls[0].out_g0 = c * m;
             {
                 StageTimer t(p, st, 0);
                 PS_HIP(ps::launch_window_rfft(fa, st));
             }
-            ca.n_chunks = 1;
-            ca.s1_chunk0 = B.ri[r].chunk0 + c;
+            ca.cls[0].n_chunks = 1;
+            ca.cls[0].s1_chunk0 = B.ri[r].chunk0 + c;
             {
                 StageTimer t(p, st, 1);
                 PS_HIP(ps::launch_centre(ca, st));
@@ -1339,12 +1545,13 @@ ps_status chunk_records(ps_plan_t p, const ps_record* rec, int64_t chunk_lo, int
     if (!p || !rec) return fail(PS_E_INVALID_ARG, "NULL argument");
     const ps_status s = check_record(p, rec);
     if (s != PS_OK) return s;
-    const int64_t np = (rec->n_samples / p->N) / p->m;
+    const int Nr = p->fc[p->class_of(rec->frame_len)].N;
+    const int64_t np = (rec->n_samples / Nr) / p->m;
     if (chunk_lo < 0 || n < 0 || n > 0x7fffffff || chunk_lo > np - n)
         return fail(PS_E_INVALID_ARG, "chunks [%lld, %lld) outside the record's %lld", (long long)chunk_lo,
                     (long long)(chunk_lo + n), (long long)np);
     const int64_t esz = (int64_t)elem_size(rec->dtype);
-    const int64_t span = (int64_t)p->m * p->N;
+    const int64_t span = (int64_t)p->m * Nr;
     out.assign((size_t)n, *rec);
     for (int64_t i = 0; i < n; ++i) {
         out[i].d_data = static_cast<const char*>(rec->d_data) + (chunk_lo + i) * span * esz;
@@ -1371,7 +1578,7 @@ ps_status ps_execute_sequential(ps_plan_t p, const ps_record* rec, int64_t chunk
     if (s != PS_OK) return s;
     if (n_chunks > 0 && !out) return fail(PS_E_INVALID_ARG, "out is NULL");
     // one output block per chunk, consecutive in each array
-    const int64_t nf = p->Ng, nf2 = nf * nf;
+    const int64_t nf = p->fc[p->class_of(rec->frame_len)].Ng, nf2 = nf * nf;
     const int64_t e1 = 2LL * p->C, e2 = 2 * p->n2() * nf, e3 = 2 * p->n3() * nf2, e4 = 2 * p->n4() * nf2;
     auto at = [](double* base, int64_t i, int64_t n) { return base ? base + i * n : nullptr; };
     std::vector<ps_output> outs((size_t)n_chunks);
@@ -1879,13 +2086,14 @@ ps_status ps_stream_end(ps_accum_t a, const ps_output* out, ps_stream_t stream) 
     }
     // Finalize tables over the state: each tile is one slot (a schedule of
     // n_tiles blocks for n_tiles tiles), Np = chunks accumulated.
-    const Scales scl = spectrum_scales(p);
+    const Scales scl = spectrum_scales(p, p->sum_g);
     const int64_t TT = (int64_t)ps::kTile * ps::kTile, TX = (int64_t)ps::kTileX * ps::kTileX;
     const int kblocks = (Nf + 255) / 256;
     SegTable f2, f3, f4;
     for (int i = 0; i < p->n2(); ++i) {
         ps::Seg sg{};
         sg.part = a->layout.off2[i];
+        sg.Nf = Nf;
         sg.n_tiles = kblocks;
         sg.blocks = kblocks;
         sg.n_chunks = (int32_t)a->n_chunks;
@@ -1898,6 +2106,8 @@ ps_status ps_stream_end(ps_accum_t a, const ps_output* out, ps_stream_t stream) 
     for (int i = 0; i < p->n3(); ++i) {
         ps::Seg sg{};
         sg.tiles = p->s3_sym(i) ? ps::kSym64 : ps::kFull64;
+        sg.tile_tab = p->d_tiles[sg.tiles];
+        sg.Nf = Nf;
         sg.n_tiles = p->n_tiles[sg.tiles];
         sg.blocks = sg.n_tiles;
         sg.part = a->layout.off3[i];
@@ -1912,6 +2122,8 @@ ps_status ps_stream_end(ps_accum_t a, const ps_output* out, ps_stream_t stream) 
     for (int i = 0; i < p->n4(); ++i) {
         ps::Seg sg{};
         sg.tiles = s4_kind(p, i);
+        sg.tile_tab = p->d_tiles[sg.tiles];
+        sg.Nf = Nf;
         const bool single = sg.tiles == ps::kSym64;
         sg.n_tiles = p->n_tiles[sg.tiles];
         sg.blocks = sg.n_tiles;
@@ -1943,9 +2155,7 @@ ps_status ps_stream_end(ps_accum_t a, const ps_output* out, ps_stream_t stream) 
     ps_status s = upload_tables(p, B, tab, st);
     if (s != PS_OK) return s;
     ps::FinalizeArgs fa{};
-    fa.tt = p->tables();
     fa.part = a->d_state;
-    fa.Nf = Nf;
     auto fin = [&](const SegTable& t, bool vec) -> hipError_t {
         fa.segs = reinterpret_cast<const ps::Seg*>(tab + t.dev_off);
         fa.n_segs = (int)t.v.size();

@@ -220,8 +220,10 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[16], const float2 (&w)[16],
     lds_barrier();
 }
 
+// One block's frames of one class: block `blk` of the class transforms its
+// frames g_lo + blk F + (0..F-1) of channel `c`.
 template <int LOG2N, bool CPLX>
-__global__ __launch_bounds__(kFftThreads, 4) void k_window_rfft(FftArgs a) {
+__device__ __forceinline__ void window_rfft_block(const FftClass& a, int64_t blk, int c, float2* lds) {
     constexpr int N = 1 << LOG2N;
     constexpr int LOG2M = LOG2N - 1;
     constexpr int M = N / 2, Tn = M / 16, F = kFftThreads / Tn;
@@ -229,13 +231,11 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_window_rfft(FftArgs a) {
     // radices of the passes after the first (0: none)
     constexpr int R2 = fft_radix2(LOG2N), R3 = fft_radix3(LOG2N);
     static_assert(P16 <= 3 && !(P16 == 3 && REM), "frame length up to 8192");
-    __shared__ float2 lds[kFftLds];
 
     const int fl = threadIdx.x / Tn, t = threadIdx.x % Tn;
     float2* s = lds + fl * (M + M / 16);
-    const int64_t gf = a.g_lo + (int64_t)blockIdx.x * F + fl;     // global frame
+    const int64_t gf = a.g_lo + blk * F + fl;     // frame of the class
     const bool live = gf < a.g_hi;
-    const int c = blockIdx.y;
     RecDesc rec = a.single;
     if (a.recs && live) {
         int lo = 0, hi = a.n_recs - 1;
@@ -298,6 +298,36 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_window_rfft(FftArgs a) {
     }
 }
 
+template <int LOG2N, bool CPLX>
+__global__ __launch_bounds__(kFftThreads, 4) void k_window_rfft(FftArgs a) {
+    __shared__ float2 lds[kFftLds];
+    window_rfft_block<LOG2N, CPLX>(a.cls[0], blockIdx.x, blockIdx.y, lds);
+}
+
+// Several frame lengths in one launch (real signals): a block finds its class
+// from its index and runs that frame length's transform.
+template <int LOG2N>
+__device__ __forceinline__ void rfft_class(const FftClass& k, int64_t blk, int c, float2* lds) {
+    window_rfft_block<LOG2N, false>(k, blk, c, lds);
+}
+
+__global__ __launch_bounds__(kFftThreads, 4) void k_window_rfft_multi(FftArgs a) {
+    __shared__ float2 lds[kFftLds];
+    int ci = 0;
+    for (int i = 1; i < a.n_cls; ++i)
+        if ((int64_t)blockIdx.x >= a.cls[i].block0) ci = i;
+    const FftClass& k = a.cls[ci];
+    const int64_t blk = (int64_t)blockIdx.x - k.block0;
+    switch (k.log2n) {
+        case 8: rfft_class<8>(k, blk, blockIdx.y, lds); break;
+        case 9: rfft_class<9>(k, blk, blockIdx.y, lds); break;
+        case 10: rfft_class<10>(k, blk, blockIdx.y, lds); break;
+        case 11: rfft_class<11>(k, blk, blockIdx.y, lds); break;
+        case 12: rfft_class<12>(k, blk, blockIdx.y, lds); break;
+        default: rfft_class<13>(k, blk, blockIdx.y, lds); break;
+    }
+}
+
 // Frame lengths N = 2 P M2 (P = 3 or 5, M2 a power of two, 128..1024): the
 // M = P M2 packed points are transformed by the prime-factor (Good-Thomas)
 // split.  With n = (M2 n1 + P n2) mod M and k = (C k1 + D k2) mod M, where
@@ -333,7 +363,8 @@ constexpr int pf_frames() {
 
 template <int LOG2M2, int P>
 __global__ __launch_bounds__((pf_frames<LOG2M2, P>() * P * ((1 << LOG2M2) / 16)))
-void k_window_rfft_pf(FftArgs a) {
+void k_window_rfft_pf(FftArgs args) {
+    const FftClass& a = args.cls[0];
     constexpr int M2 = 1 << LOG2M2, T2 = M2 / 16, TP = P * T2, F = pf_frames<LOG2M2, P>();
     constexpr int M = P * M2, N = 2 * M, SUB = M2 + M2 / 16;
     constexpr int R2 = fft_radix2(LOG2M2 + 1), R3 = fft_radix3(LOG2M2 + 1);
@@ -423,7 +454,7 @@ void k_window_rfft_pf(FftArgs a) {
         const int k2 = tt + j * TP;
         if (k2 >= M2) break;
 #pragma unroll
-        for (int k1 = 0; k1 < P; ++k1) frame[pad((a.pf_c * k1 + a.pf_d * k2) % M)] = out[j][k1];
+        for (int k1 = 0; k1 < P; ++k1) frame[pad((args.pf_c * k1 + args.pf_d * k2) % M)] = out[j][k1];
     }
     lds_barrier();
 
@@ -449,7 +480,7 @@ void k_window_rfft_pf(FftArgs a) {
 template <int LOG2M2, int P>
 hipError_t launch_pf(const FftArgs& a, hipStream_t st) {
     constexpr int T2 = (1 << LOG2M2) / 16, F = pf_frames<LOG2M2, P>();
-    const int64_t n = a.g_hi - a.g_lo;
+    const int64_t n = a.cls[0].g_hi - a.cls[0].g_lo;
     dim3 grid((unsigned)((n + F - 1) / F), a.n_channels);
     k_window_rfft_pf<LOG2M2, P><<<grid, F * P * T2, 0, st>>>(a);
     return hipGetLastError();
@@ -458,7 +489,7 @@ hipError_t launch_pf(const FftArgs& a, hipStream_t st) {
 template <int LOG2N>
 hipError_t launch_n(const FftArgs& a, hipStream_t st) {
     constexpr int M = (1 << LOG2N) / 2, F = kFftThreads / (M / 16);
-    const int64_t n = a.g_hi - a.g_lo;
+    const int64_t n = a.cls[0].g_hi - a.cls[0].g_lo;
     dim3 grid((unsigned)((n + F - 1) / F), a.n_channels);
     if (a.cplx) {
         if constexpr (LOG2N >= 9) k_window_rfft<LOG2N, true><<<grid, kFftThreads, 0, st>>>(a);
@@ -485,22 +516,28 @@ hipError_t launch_n(const FftArgs& a, hipStream_t st) {
 // is c3opt.
 constexpr int kCentreRegs = 16;
 
-// Grid: x = chunk * kblocks + (256-wide k block), y = channel (the chunk count
-// can exceed the 65536 limit of the y and z grid dimensions).
-__global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64_t coef_cs, int K, int m,
-                                                int kblocks, float2* __restrict__ s1, int64_t s1_cs,
-                                                int64_t s1_chunk0, int s1_col, float2* __restrict__ out3,
-                                                int64_t out3_cs, float alpha, float mu) {
-    const int64_t chunk = blockIdx.x / kblocks;
-    const int k = (int)(blockIdx.x - chunk * kblocks) * 256 + threadIdx.x;
+// Grid: x = the classes' (chunk, 256-wide k block) pairs, chunk-major within
+// each class; y = channel (the chunk count can exceed the 65536 limit of the y
+// and z grid dimensions).
+__global__ __launch_bounds__(256) void k_centre(CentreArgs a) {
+    int ci = 0;
+    for (int i = 1; i < a.n_cls; ++i)
+        if ((int64_t)blockIdx.x >= a.cls[i].block0) ci = i;
+    const CentreClass& cl = a.cls[ci];
+    const int K = cl.K, m = a.m;
+    const int kblocks = (K + 255) / 256;
+    const int64_t local = (int64_t)blockIdx.x - cl.block0;
+    const int64_t chunk = local / kblocks;
+    const int k = (int)(local - chunk * kblocks) * 256 + threadIdx.x;
     if (k >= K) return;
-    float2* p = coef + blockIdx.y * coef_cs + chunk * m * K + k;
+    float2* p = cl.coef + blockIdx.y * cl.coef_chan_stride + chunk * m * K + k;
     // c3^(opt): the chunk's rows for S3, frames shifted by alpha mean, then mu mean
-    float2* q = out3 ? out3 + blockIdx.y * out3_cs + chunk * (m + 1) * K + k : nullptr;
+    float2* q = cl.out3 ? cl.out3 + blockIdx.y * cl.out3_cs + chunk * (m + 1) * K + k : nullptr;
     const float inv = 1.0f / (float)m;
+    const float alpha = a.alpha, mu = a.mu;
     // S1: the chunk's mean of a_0 (real for a real signal)
     auto keep_mean = [&](float mr, float mi) {
-        if (s1 && k == s1_col) s1[blockIdx.y * s1_cs + s1_chunk0 + chunk] = make_float2(mr, mi);
+        if (a.s1 && k == a.s1_col) a.s1[blockIdx.y * a.s1_cs + cl.s1_chunk0 + chunk] = make_float2(mr, mi);
         if (q) q[(int64_t)m * K] = make_float2(mu * mr, mu * mi);
     };
     auto put = [&](int f, float2 v, float mr, float mi) {
@@ -540,9 +577,25 @@ __global__ __launch_bounds__(256) void k_centre(float2* __restrict__ coef, int64
 }  // namespace
 
 hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s) {
-    if (a.g_hi <= a.g_lo || a.n_channels <= 0 || a.n_recs <= 0) return hipSuccess;
+    if (a.n_cls <= 0 || a.n_channels <= 0) return hipSuccess;
+    if (a.n_cls > 1) {          // several frame lengths: one launch, a class per block range
+        if (a.cplx || a.pf || a.n_cls > kMaxClasses) return hipErrorInvalidValue;
+        int64_t blocks = 0;
+        for (int i = 0; i < a.n_cls; ++i) {
+            const FftClass& c = a.cls[i];
+            const int F = kFftThreads / ((1 << c.log2n) / 32);
+            if (c.block0 != blocks || c.g_hi < c.g_lo || c.log2n < 8 || c.log2n > 13) return hipErrorInvalidValue;
+            blocks += (c.g_hi - c.g_lo + F - 1) / F;
+        }
+        if (blocks <= 0) return hipSuccess;
+        if (blocks > 0x7fffffff) return hipErrorInvalidConfiguration;
+        k_window_rfft_multi<<<dim3((unsigned)blocks, a.n_channels), kFftThreads, 0, s>>>(a);
+        return hipGetLastError();
+    }
+    const FftClass& c0 = a.cls[0];
+    if (c0.g_hi <= c0.g_lo || c0.n_recs <= 0) return hipSuccess;
     if (a.pf) {                 // N = 2 pf 2^log2n
-        const int key = a.pf * 16 + a.log2n;
+        const int key = a.pf * 16 + c0.log2n;
         switch (key) {
             case 3 * 16 + 7: return launch_pf<7, 3>(a, s);
             case 3 * 16 + 8: return launch_pf<8, 3>(a, s);
@@ -554,7 +607,7 @@ hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s) {
             default: return hipErrorInvalidValue;
         }
     }
-    switch (a.log2n) {
+    switch (c0.log2n) {
         case 8: return launch_n<8>(a, s);
         case 9: return launch_n<9>(a, s);
         case 10: return launch_n<10>(a, s);
@@ -566,13 +619,17 @@ hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_centre(const CentreArgs& a, hipStream_t s) {
-    if (a.n_chunks <= 0) return hipSuccess;
-    const int kblocks = (a.K + 255) / 256;
-    const int64_t nx = (int64_t)kblocks * a.n_chunks;
+    if (a.n_cls <= 0 || a.n_cls > kMaxClasses) return a.n_cls <= 0 ? hipSuccess : hipErrorInvalidValue;
+    int64_t nx = 0;
+    for (int i = 0; i < a.n_cls; ++i) {
+        const CentreClass& c = a.cls[i];
+        if (c.block0 != nx || c.n_chunks < 0) return hipErrorInvalidValue;
+        nx += (int64_t)((c.K + 255) / 256) * c.n_chunks;
+    }
+    if (nx <= 0) return hipSuccess;
     if (nx > 0x7fffffff) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)nx, a.n_channels);
-    k_centre<<<grid, 256, 0, s>>>(a.coef, a.coef_chan_stride, a.K, a.m, kblocks, a.s1, a.s1_cs, a.s1_chunk0,
-                                  a.s1_col, a.out3, a.out3_cs, a.alpha, a.mu);
+    k_centre<<<grid, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_finalize_vec(FinalizeArgs p) {
     const int nc = two ? 8 : 4;                         // uniform over the block
     for (int c = 0; c < nc; ++c) red[g][c][kk] = s[c];
     __syncthreads();
-    if (g != 0 || k >= p.Nf) return;
+    if (g != 0 || k >= sg.Nf) return;
     for (int c = 0; c < nc; ++c) {
         s[c] = 0;
         for (int gg = 0; gg < kVecGroups; ++gg) s[c] += red[gg][c][kk];
@@ -114,14 +114,14 @@ __global__ __launch_bounds__(256) void k_finalize_tiles(FinalizeArgs p) {
     const int64_t local = x - sg.item0;
     const int tile = (int)(local / per_tile);
     const int sb = (int)(local - (int64_t)tile * per_tile);
-    const int2 t = p.tt.t[sg.tiles][tile];
+    const int2 t = sg.tile_tab[tile];
     const int kb = t.x * E + 16 * (sb / sub), lb = t.y * E + 16 * (sb % sub);   // sub-block origin
     const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
     const int ncomp = sg.ncomp;
     const bool two = sg.n_chunks2 > 0;
 
     const int k = kb + i, l = lb + j;
-    const bool valid = k < p.Nf && l < p.Nf && !(sg.sym && k > l);
+    const bool valid = k < sg.Nf && l < sg.Nf && !(sg.sym && k > l);
     double mr = 0.0, sr = 0.0, mi = 0.0, si = 0.0;
     // The point's offset inside the tile does not depend on the tile table,
     // and every component of every slot is loaded before any is added (one
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void k_finalize_tiles(FinalizeArgs p) {
         }
     }
     if (valid) {
-        const int64_t o = ((int64_t)k * p.Nf + l) * 2;
+        const int64_t o = ((int64_t)k * sg.Nf + l) * 2;
         if (sg.out) {
             sg.out[o] = mr;
             sg.out[o + 1] = mi;
@@ -175,8 +175,8 @@ __global__ __launch_bounds__(256) void k_finalize_tiles(FinalizeArgs p) {
     __syncthreads();
     // thread (i, j) now writes point (kb + j, lb + i) to (lb + i, kb + j)
     const int km = kb + j, lm = lb + i;
-    if (km < lm && lm < p.Nf) {
-        const int64_t o = ((int64_t)lm * p.Nf + km) * 2;
+    if (km < lm && lm < sg.Nf) {
+        const int64_t o = ((int64_t)lm * sg.Nf + km) * 2;
         if (sg.out) {
             const double2 v = sm[j][i];
             sg.out[o] = v.x;

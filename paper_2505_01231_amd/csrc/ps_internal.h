@@ -26,11 +26,8 @@ constexpr int kFrameBatch = 16;
 constexpr int kFrameBatchSmall = 10;
 constexpr int kFrameBatchRow = 11;      // S3 only: chunks of 10 frames plus the c3^(opt) mean row
 
-// Tile tables owned by the plan.
+// Tile tables owned by the plan, one per kind and grid size.
 enum TileKind { kSym64 = 0, kFull64 = 1, kSym32 = 2, kFull32 = 3 };
-struct TileTables {
-    const int2* t[4];
-};
 
 // ---------------------------------------------------------------- records (stage a1)
 // Coefficient region of the workspace: [C][F_total][K] float2, records'
@@ -44,26 +41,39 @@ struct RecDesc {
     int32_t pad;
 };
 
-struct FftArgs {
-    const RecDesc* recs;    // device table sorted by frame0, or NULL: use `single`
+// Records of several frame lengths can share one launch: the frames of each
+// frame length (a "class") are numbered on their own, and a launch carries up
+// to kMaxClasses classes, each with its own window, twiddles, coefficient
+// count and output region; a block finds its class by its index.
+constexpr int kMaxClasses = 6;
+
+struct FftClass {
+    const RecDesc* recs;    // device table sorted by frame0 (the class's frames), or NULL: use `single`
     RecDesc single;
     int n_recs;
-    int64_t g_lo, g_hi;     // global frames to transform
-    int64_t out_g0;         // global frame stored at row 0 of `out`
-    int n_channels;
+    int64_t g_lo, g_hi;     // the class's frames to transform
+    int64_t out_g0;         // frame stored at row 0 of `out`
     int log2n;              // log2(N), 8..13 (complex signals: log2 of twice the frame length)
     int K;                  // coefficients kept per frame
-    // Complex signals: frames of M = N/2 complex samples (dtype 3: complex
-    // float32, 4: complex float64), transformed as they are; column c of the
-    // output holds bin c - jmax.  Real signals: column c holds bin c.
+    int jmax;               // complex signals: column c holds bin c - jmax
     const float* g;         // window [N]
     const float2* tw;       // twiddles, see fft_twiddle_count
     float2* out;            // [C][rows][K]
     int64_t out_chan_stride;
-    int dtype;              // common dtype of the records (launch template)
-    int cplx, jmax;
+    int64_t block0;         // first block of the class in the launch
+};
+
+struct FftArgs {
+    FftClass cls[kMaxClasses];
+    int n_cls;
+    int n_channels;
+    // Complex signals: frames of M = N/2 complex samples (dtype 3: complex
+    // float32, 4: complex float64), transformed as they are; column c of the
+    // output holds bin c - jmax.  Real signals: column c holds bin c.
+    int cplx;
     // Frame lengths N = 2 pf 2^log2n (pf = 3 or 5; 0: N = 2^log2n): the
-    // prime-factor transform with output map k = (pf_c k1 + pf_d k2) mod M.
+    // prime-factor transform with output map k = (pf_c k1 + pf_d k2) mod M
+    // (one class).
     int pf, pf_c, pf_d;
 };
 hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s);
@@ -86,20 +96,28 @@ __host__ __device__ constexpr int fft_twiddle_count(int log2n) {
 // In-place centring: a_k(f) -= mean over the m frames of its chunk.  With
 // `s1` set, the chunk's mean of a_0 (column s1_col; the first-order
 // k-statistic) is also stored at s1[channel * s1_cs + s1_chunk0 + chunk].
-struct CentreArgs {
+// One class per frame length, as for the transform.
+struct CentreClass {
     float2* coef;           // [C][n_chunks * m][K]
     int64_t coef_chan_stride;
-    int K, m;
+    int K;
     int64_t n_chunks;
-    int n_channels;
-    float2* s1;
-    int64_t s1_cs, s1_chunk0;
-    int s1_col;
+    int64_t s1_chunk0;
     // c3^(opt) rows for S3 (null: none): per chunk the m frames shifted by
     // alpha times the chunk mean, a - (1 - alpha) mean, then one row mu mean;
     // [C][n_chunks * (m + 1)][K]
     float2* out3;
     int64_t out3_cs;
+    int64_t block0;         // first block of the class
+};
+struct CentreArgs {
+    CentreClass cls[kMaxClasses];
+    int n_cls;
+    int m;
+    int n_channels;
+    float2* s1;
+    int64_t s1_cs;
+    int s1_col;
     float alpha, mu;
 };
 hipError_t launch_centre(const CentreArgs& a, hipStream_t s);
@@ -143,6 +161,10 @@ struct Sched {
 struct Seg {
     int64_t item0;          // first work item (block) of the segment
     int64_t coef;           // float2 offset of the record's chunk 0 in the coefficient region
+    int64_t cs;             // float2 elements between channels of the record's coefficient block
+    const int2* tile_tab;   // the grid's tile table (tile t -> (kt, lt)); by `tiles` and the grid size
+    int32_t K;              // coefficients per frame of the record's frame length
+    int32_t Nf;             // points per grid axis of the record's spectra
     int64_t part;           // double offset of the segment's partial sums
     int32_t n_tiles;        // tiles (S3/S4) or 256-wide k blocks (S2)
     int32_t blocks;         // B of the segment's Sched (blocks of the moment stage)
@@ -165,11 +187,9 @@ struct BatchArgs {
     const Seg* segs;        // device table, sorted by item0
     int n_segs;
     int64_t n_items;
-    TileTables tt;
     const float2* coef;     // coefficient region
-    int64_t coef_chan_stride;
     double* part;           // partial-sum region
-    int K, m, Nf;           // Nf: points per grid axis (2 N_f - 1 for complex signals)
+    int m;                  // rows per chunk
     int col0;               // column of grid index 0 for the first factors (see View)
     int col3;               // column of grid-sum index 0 for S3's third factor
     // Per-chunk schedule: only chunks [win_lo, win_hi) of each segment are
@@ -199,12 +219,10 @@ int s4_cross_mfma_blocks_per_cu();
 
 // ---------------------------------------------------------------- finalize
 struct FinalizeArgs {
-    const Seg* segs;        // items: S2 k blocks, or tiles
+    const Seg* segs;        // items: S2 k blocks, or tiles (grid size and tile table per segment)
     int n_segs;
     int64_t n_items;
-    TileTables tt;
     const double* part;
-    int Nf;
     const float2* s1;       // per-chunk means of a_0, [C][s1_cs] (S1 only)
     int64_t s1_cs;
 };

@@ -59,7 +59,7 @@ struct Item {
 struct View {
     const float2* coef;
     int64_t cs, off;
-    int K, m, col0, col3;
+    int K, m, Nf, col0, col3;
 };
 
 __device__ __forceinline__ bool resolve_block(const BatchArgs& b, Block& bk, View& v) {
@@ -83,10 +83,12 @@ __device__ __forceinline__ bool resolve_block(const BatchArgs& b, Block& bk, Vie
     v.coef = b.coef + b.col0;
     v.col0 = b.col0;
     v.col3 = b.col3;
-    v.cs = b.coef_chan_stride;
-    v.off = b.per_chunk ? -(int64_t)b.win_lo * b.m * b.K : s.coef;
-    v.K = b.K;
+    v.cs = s.cs;
+    // (per-chunk schedule: the segment's block holds chunk win_lo at row 0)
+    v.off = s.coef - (b.per_chunk ? (int64_t)b.win_lo * b.m * s.K : 0);
+    v.K = s.K;
     v.m = b.m;
+    v.Nf = s.Nf;
     return true;
 }
 
@@ -117,7 +119,7 @@ __device__ __forceinline__ bool next_item(const BatchArgs& b, Block& bk, Item& i
     it.c0 = bk.cbase + (int)c0;
     it.c1 = bk.cbase + (int)c1;
     if (EDGE > 0) {
-        const int2 tt = b.tt.t[s.tiles][t];
+        const int2 tt = s.tile_tab[t];
         it.k0 = tt.x * EDGE;
         it.l0 = tt.y * EDGE;
         it.part = b.part + s.part + slot * NCOMP * EDGE * EDGE;
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(256) void k_s2(BatchArgs p) {
     Item it;
     while (next_item<0, 4>(p, bk, it)) {
         const int k = it.k0 + threadIdx.x;
-        if (k >= p.Nf) continue;
+        if (k >= v.Nf) continue;
         const float2* A = v.coef + it.ch[0] * v.cs;
         const float2* B = v.coef + it.ch[1] * v.cs;
         const bool same = it.ch[0] == it.ch[1];      // S2 of one channel: one load per frame
@@ -218,13 +220,13 @@ __device__ __forceinline__ void s3_item(const BatchArgs& p, const View& v, const
     const float2* src = nullptr;
     bool live = false;
     if (col < kTile) {
-        live = k0 + col < p.Nf;
+        live = k0 + col < v.Nf;
         src = v.coef + it.ch[0] * v.cs + k0 + col;
     } else if (col < 2 * kTile) {
-        live = l0 + col - kTile < p.Nf;
+        live = l0 + col - kTile < v.Nf;
         src = v.coef + it.ch[1] * v.cs + l0 + col - kTile;
     } else if (col < 4 * kTile - 1) {
-        live = k0 + l0 + col - 2 * kTile < 2 * p.Nf - 1;      // grid sums k' + l' <= 2 (Ng - 1)
+        live = k0 + l0 + col - 2 * kTile < 2 * v.Nf - 1;      // grid sums k' + l' <= 2 (Ng - 1)
         src = v.coef - v.col0 + v.col3 + it.ch[2] * v.cs + k0 + l0 + col - 2 * kTile;
     }
 
@@ -360,10 +362,10 @@ __global__ __launch_bounds__(kS4Threads, 2) void k_s4_single(BatchArgs p) {
     bool live = false;
     const float2* src = nullptr;
     if (col < kTile) {
-        live = k0 + col < p.Nf;
+        live = k0 + col < v.Nf;
         src = A + k0 + col;
     } else if (col < 2 * kTile) {
-        live = l0 + col - kTile < p.Nf;
+        live = l0 + col - kTile < v.Nf;
         src = A + l0 + col - kTile;
     }
     const double gamma = p.gamma;
@@ -583,7 +585,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_bf16(BatchArgs p) {
     const int c0 = it.c0, c1 = it.c1;
     const int k0 = it.k0, l0 = it.l0;
     const int gcol = (side ? l0 : k0) + col;
-    const bool live = gcol < p.Nf;
+    const bool live = gcol < v.Nf;
     const float2* src = v.coef + it.ch[0] * v.cs + gcol;
 
     double acc[16][2];
@@ -763,7 +765,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16(BatchArgs p) {
     const int c0 = it.c0, c1 = it.c1;
     const int k0 = it.k0, l0 = it.l0;
     const int gcol = (side ? l0 : k0) + col;
-    const bool live = gcol < p.Nf;
+    const bool live = gcol < v.Nf;
     const float2* src = v.coef + it.ch[0] * v.cs + gcol;
 
     double acc[4][4][2];
@@ -930,7 +932,7 @@ __global__ __launch_bounds__(kS4XThreads, 2) void k_s4_cross(BatchArgs p) {
     // Loader role: (array, column, half of the frames).
     const int arr = (tid & 127) >> 5, col = tid & 31, half = tid >> 7;
     const int gcol = (arr < 2 ? k0 : l0) + col;
-    const bool live = gcol < p.Nf;
+    const bool live = gcol < v.Nf;
     // S4 planes: factors a and d at column + q, b and c at column - q
     const float2* src = v.coef + it.ch[arr] * v.cs + gcol + ((arr == 0 || arr == 3) ? p.s4_shift : -p.s4_shift);
 
@@ -1108,7 +1110,7 @@ __global__ __launch_bounds__(kS4XMThreads, 2) void k_s4_cross_mfma(BatchArgs p) 
     while (next_item<kTileX, 4>(p, bk, it)) {
     const int c0 = it.c0, c1 = it.c1;
     const int gcol = (side ? it.l0 : it.k0) + col;
-    const bool live = gcol < p.Nf;
+    const bool live = gcol < v.Nf;
     // S4 planes: a (k side) and d (l side) at column + q, b and c at column - q
     const int shx = side ? -p.s4_shift : p.s4_shift;
     const float2* srcx = v.coef + it.ch[2 * side] * v.cs + gcol + shx;        // a (k side) or c (l side)

@@ -78,13 +78,17 @@ class Plan:
     takes complex64 / complex128 records and returns every spectrum on the
     signed grid of ``grid`` = 2 N_f - 1 points per axis (index k + N_f - 1).
     ``s4_shift=q`` (complex plans) computes S4 on the plane parallel to the cut,
-    C4(a_{k+q}, b*_{k-q}, c_{l-q}, d*_{l+q})."""
+    C4(a_{k+q}, b*_{k-q}, c_{l-q}, d*_{l+q}).  ``frame_lens`` lists further
+    frame lengths records may carry (``execute(..., frame_lens=...)``); all
+    records of an execute share each stage's launch, and every record's spectra
+    are on its own frame length's grid (``frame_info``)."""
 
     def __init__(self, frame_len: int, n_freq: int = 0, m: int = 10, dt: float = 1.0,
                  orders=(2, 3, 4), n_channels: int = 1, window: str = "acg",
                  window_param: float = 0.14, precision: str = "fp32", schedule: str = "batched",
                  f_max: float = 0.0, combos2=None, combos3=None, combos4=None, interlaced: bool = False,
-                 estimator: str = "kstat", complex_signal: bool = False, s4_shift: int = 0):
+                 estimator: str = "kstat", complex_signal: bool = False, s4_shift: int = 0,
+                 frame_lens=()):
         self._lib = L.load()
         self._handle = None
         cfg = L.ps_config()
@@ -104,6 +108,12 @@ class Plan:
         cfg.estimator = {"kstat": L.PS_EST_KSTAT, "natural": L.PS_EST_NATURAL, "c3opt": L.PS_EST_C3OPT}[estimator]
         cfg.complex_signal = 1 if complex_signal else 0
         cfg.s4_shift = s4_shift
+        fl_set = 0
+        for n in frame_lens:
+            if n <= 0 or n & (n - 1):
+                raise ValueError(f"frame length {n} is not a power of two")
+            fl_set |= 1 << (int(n).bit_length() - 1)
+        cfg.frame_len_set = fl_set
         self._keep = []
         for arity, combos in ((2, combos2), (3, combos3), (4, combos4)):
             n, arr, ptr = _flat(combos, arity)
@@ -129,6 +139,14 @@ class Plan:
         self.combos2 = [tuple(info.combos2[i * 2:(i + 1) * 2]) for i in range(info.n_combos2)]
         self.combos3 = [tuple(info.combos3[i * 3:(i + 1) * 3]) for i in range(info.n_combos3)]
         self.combos4 = [tuple(info.combos4[i * 4:(i + 1) * 4]) for i in range(info.n_combos4)]
+        self.frame_lens = tuple(sorted({self.frame_len, *[int(n) for n in frame_lens]}))
+
+    def frame_info(self, frame_len: int = 0) -> dict:
+        """Grid of one of the plan's frame lengths (ps_plan_frame_info)."""
+        info = L.ps_plan_info()
+        L.check(self._lib.ps_plan_frame_info(self._handle, frame_len, C.byref(info)), "ps_plan_frame_info")
+        return {"frame_len": info.frame_len, "n_freq": info.n_freq, "n_coef": info.n_coef, "grid": info.grid,
+                "f_max": info.f_max, "sum_g": list(info.sum_g)}
 
     # ------------------------------------------------------------------
     def close(self):
@@ -149,8 +167,9 @@ class Plan:
         self.close()
 
     # ------------------------------------------------------------------
-    def record(self, x: torch.Tensor) -> L.ps_record:
-        """ps_record for a device tensor [L] (one channel) or [C, L] (channels)."""
+    def record(self, x: torch.Tensor, frame_len: int = 0) -> L.ps_record:
+        """ps_record for a device tensor [L] (one channel) or [C, L] (channels),
+        cut into frames of `frame_len` (0: the plan's frame length)."""
         if not x.is_cuda:
             raise ValueError("input must be a device tensor")
         if x.dtype not in _DTYPES:
@@ -166,8 +185,15 @@ class Plan:
         r.n_samples = x.shape[1]
         r.channel_stride = x.stride(0) if x.shape[0] > 1 else x.shape[1]
         r.dtype = _DTYPES[x.dtype]
-        r.reserved = 0
+        r.frame_len = int(frame_len)
         return r
+
+    def record_chunks(self, rec: L.ps_record):
+        """(Np, flags) of a record at its own frame length (ps_record_chunks)."""
+        n = C.c_int64()
+        fl = C.c_uint32()
+        L.check(self._lib.ps_record_chunks(self._handle, C.byref(rec), C.byref(n), C.byref(fl)), "ps_record_chunks")
+        return n.value, fl.value
 
     def record_info(self, n_samples: int):
         n = C.c_int64()
@@ -175,14 +201,20 @@ class Plan:
         L.check(self._lib.ps_record_info(self._handle, n_samples, C.byref(n), C.byref(fl)), "ps_record_info")
         return n.value, fl.value
 
-    def workspace_bytes(self, xs) -> int:
-        recs = (L.ps_record * len(xs))(*[self.record(x) for x in xs])
+    def _records(self, xs, frame_lens=None):
+        fls = [0] * len(xs) if frame_lens is None else [int(n) for n in frame_lens]
+        if len(fls) != len(xs):
+            raise ValueError("one frame length per record")
+        return (L.ps_record * len(xs))(*[self.record(x, n) for x, n in zip(xs, fls)]), fls
+
+    def workspace_bytes(self, xs, frame_lens=None) -> int:
+        recs, _ = self._records(xs, frame_lens)
         n = C.c_size_t()
         L.check(self._lib.ps_workspace_size(self._handle, recs, len(xs), C.byref(n)), "ps_workspace_size")
         return n.value
 
-    def allocate_outputs(self, device) -> Spectra:
-        nf = self.grid
+    def allocate_outputs(self, device, frame_len: int = 0) -> Spectra:
+        nf = self.grid if frame_len in (0, self.frame_len) else self.frame_info(frame_len)["grid"]
         f64 = dict(dtype=torch.float64, device=device)
         n2, n3, n4 = len(self.combos2), len(self.combos3), len(self.combos4)
         return Spectra(
@@ -200,23 +232,25 @@ class Plan:
     def _ptr(t):
         return None if t is None else t.data_ptr()
 
-    def execute(self, xs, workspace: torch.Tensor | None = None, outputs=None, stream=None):
-        """Enqueue the estimator for one tensor or a list of tensors (records).
+    def execute(self, xs, workspace: torch.Tensor | None = None, outputs=None, stream=None, frame_lens=None):
+        """Enqueue the estimator for one tensor or a list of tensors (records),
+        record i cut into frames of frame_lens[i] (0 / None: the plan's).
         Returns a list of Spectra (or one Spectra for a single tensor)."""
         single = isinstance(xs, torch.Tensor)
         if single:
             xs = [xs]
+            frame_lens = None if frame_lens is None else [frame_lens] if isinstance(frame_lens, int) else frame_lens
         device = xs[0].device
-        recs = (L.ps_record * len(xs))(*[self.record(x) for x in xs])
+        recs, fls = self._records(xs, frame_lens)
         need = C.c_size_t()
         L.check(self._lib.ps_workspace_size(self._handle, recs, len(xs), C.byref(need)), "ps_workspace_size")
         if workspace is None or workspace.numel() < need.value:
             workspace = torch.empty(need.value, dtype=torch.uint8, device=device)
         if outputs is None:
-            outputs = [self.allocate_outputs(device) for _ in xs]
+            outputs = [self.allocate_outputs(device, n) for n in fls]
         outs = (L.ps_output * len(xs))()
         for i, o in enumerate(outputs):
-            n, fl = self.record_info(recs[i].n_samples)
+            n, fl = self.record_chunks(recs[i])
             o.n_chunks, o.flags = n, fl
             outs[i] = o.c_struct()
         st = torch.cuda.current_stream(device) if stream is None else stream
@@ -277,23 +311,24 @@ class Plan:
                                         C.c_void_p(st.cuda_stream)), "ps_full_plane")
         return val, err
 
-    def graph(self, xs, workspace: torch.Tensor | None = None, outputs=None) -> "Graph":
+    def graph(self, xs, workspace: torch.Tensor | None = None, outputs=None, frame_lens=None) -> "Graph":
         """Capture the execution over these tensors/buffers as a HIP graph
         (ps_graph_create); replay with Graph.launch()."""
         single = isinstance(xs, torch.Tensor)
         if single:
             xs = [xs]
+            frame_lens = None if frame_lens is None else [frame_lens] if isinstance(frame_lens, int) else frame_lens
         device = xs[0].device
-        recs = (L.ps_record * len(xs))(*[self.record(x) for x in xs])
+        recs, fls = self._records(xs, frame_lens)
         need = C.c_size_t()
         L.check(self._lib.ps_workspace_size(self._handle, recs, len(xs), C.byref(need)), "ps_workspace_size")
         if workspace is None or workspace.numel() < need.value:
             workspace = torch.empty(need.value, dtype=torch.uint8, device=device)
         if outputs is None:
-            outputs = [self.allocate_outputs(device) for _ in xs]
+            outputs = [self.allocate_outputs(device, n) for n in fls]
         outs = (L.ps_output * len(xs))()
         for i, o in enumerate(outputs):
-            o.n_chunks, o.flags = self.record_info(recs[i].n_samples)
+            o.n_chunks, o.flags = self.record_chunks(recs[i])
             outs[i] = o.c_struct()
         h = C.c_void_p()
         L.check(self._lib.ps_graph_create(self._handle, recs, len(xs), workspace.data_ptr(), workspace.numel(),
@@ -313,7 +348,8 @@ class Plan:
         t = L.ps_tuning(tile_group, s3_frame_batch)
         L.check(self._lib.ps_plan_set_tuning(self._handle, C.byref(t)), "ps_plan_set_tuning")
 
-    def autotune(self, xs, reps: int = 3, workspace: torch.Tensor | None = None, outputs=None, stream=None) -> dict:
+    def autotune(self, xs, reps: int = 3, workspace: torch.Tensor | None = None, outputs=None, stream=None,
+                 frame_lens=None) -> dict:
         """Time the candidate launch configurations on these records and keep the
         fastest (ps_plan_autotune).  Returns {"best": tuning, "candidates":
         [(tuning, ms per execute), ...]}; the outputs hold the last run."""
@@ -321,16 +357,16 @@ class Plan:
         if single:
             xs = [xs]
         device = xs[0].device
-        recs = (L.ps_record * len(xs))(*[self.record(x) for x in xs])
+        recs, fls = self._records(xs, frame_lens)
         need = C.c_size_t()
         L.check(self._lib.ps_workspace_size(self._handle, recs, len(xs), C.byref(need)), "ps_workspace_size")
         if workspace is None or workspace.numel() < need.value:
             workspace = torch.empty(need.value, dtype=torch.uint8, device=device)
         if outputs is None:
-            outputs = [self.allocate_outputs(device) for _ in xs]
+            outputs = [self.allocate_outputs(device, n) for n in fls]
         outs = (L.ps_output * len(xs))()
         for i, o in enumerate(outputs):
-            o.n_chunks, o.flags = self.record_info(recs[i].n_samples)
+            o.n_chunks, o.flags = self.record_chunks(recs[i])
             outs[i] = o.c_struct()
         st = torch.cuda.current_stream(device) if stream is None else stream
         rep = L.ps_tune_report()

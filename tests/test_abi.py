@@ -126,6 +126,11 @@ def _cfg(**kw):
     (dict(frame_len=128), L.PS_E_UNSUPPORTED),          # below the supported range
     (dict(frame_len=16384), L.PS_E_UNSUPPORTED),
     (dict(m=3), L.PS_E_INVALID_ARG),                    # S4 needs m >= 4
+    (dict(frame_len_set=1 << 14), L.PS_E_INVALID_ARG),   # further frame lengths only 256..8192
+    (dict(frame_len_set=1 << 7), L.PS_E_INVALID_ARG),
+    (dict(n_freq=65, frame_len=1024, frame_len_set=1 << 8), L.PS_E_INVALID_ARG),   # 65 * 256 / 1024
+    (dict(n_freq=64, frame_len=1024, frame_len_set=1 << 9, complex_signal=1), L.PS_E_UNSUPPORTED),
+    (dict(n_freq=257, frame_len=1024, frame_len_set=1 << 11), L.PS_E_INVALID_ARG),  # 514 at N = 2048: S3 bound
     (dict(m=2, orders=L.PS_ORDER_S3), L.PS_E_INVALID_ARG),
     (dict(m=1, orders=L.PS_ORDER_S2), L.PS_E_INVALID_ARG),
     (dict(n_freq=66), L.PS_E_INVALID_ARG),              # 2 (Nf - 1) > N/2 with S3
