@@ -246,3 +246,48 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     line = json.loads(r.stdout.strip().splitlines()[-1])
     assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+@pytest.mark.parametrize("n_ch", [2, 3, 4])
+@pytest.mark.parametrize("order", [3, 4])
+def test_orbit_quadrants_are_disjoint_pieces(n_ch, order):
+    """The positive quadrants of the "every orbit" combinations are disjoint
+    pieces of the multichannel polyspectrum: a value is the cumulant of a
+    multiset of (channel, frequency) pairs (frequencies summing to zero; for
+    real signals conjugation negates every frequency), and no such multiset,
+    or its conjugate, is served by two different stored combinations, except on
+    the measure-zero lines the cut itself singles out (S4 at k = l, where a
+    second pairing of opposite frequencies exists).  So the equivalences of
+    Section 9 (e.g. S3_yyx(w) = S3_xyy(M w)) relate points of different
+    stored quadrants and cannot remove an orbit from a positive-quadrant
+    computation; ps_full_plane applies them when gathering."""
+    N = 7
+    combos = []
+    n = C.c_int32(0)
+    assert lib_ok()
+    lib = L.load()
+    assert lib.ps_enumerate_combos(n_ch, order, None, C.byref(n)) == L.PS_OK
+    buf = (C.c_int8 * (n.value * order))()
+    assert lib.ps_enumerate_combos(n_ch, order, buf, C.byref(n)) == L.PS_OK
+    combos = [tuple(buf[i * order:(i + 1) * order]) for i in range(n.value)]
+    seen = {}
+    for cb in combos:
+        sym = (cb[0] == cb[1]) if order == 3 else (cb[0] == cb[2] and cb[1] == cb[3])
+        for k in range(1, N):
+            for l in range(1, N):
+                if sym and k > l:
+                    continue
+                if order == 3:
+                    pairs = [(cb[0], k), (cb[1], l), (cb[2], -k - l)]
+                else:
+                    pairs = [(cb[0], k), (cb[1], -k), (cb[2], l), (cb[3], -l)]
+                for key in (tuple(sorted(pairs)), tuple(sorted((c, -f) for c, f in pairs))):
+                    if key in seen and seen[key][0] != cb:
+                        assert order == 4 and k == l and seen[key][1] == seen[key][2] == k, (cb, k, l, seen[key])
+                    seen.setdefault(key, (cb, k, l))
+    # and every orbit member of a transposition/conjugation class is served
+    assert len(combos) == {3: {2: 6, 3: 18, 4: 40}, 4: {2: 7, 3: 27, 4: 76}}[order][n_ch]
+
+
+def lib_ok():
+    return L.load() is not None
