@@ -178,52 +178,86 @@ def accuracy(torch, dev, plan, z, ref, n_chunks):
                     "baseline's single-thread oracle evaluated; normalised to each array's max |oracle|"}
 
 
-def run_batching(torch, dev, precision):
-    """Batching form: every record of a frame length in one ps_execute (each
-    stage one launch over records x combinations), grouped so that the FP64
-    outputs of a group stay under ~16 GB."""
+def _gen_record(args):
+    from paper_2505_01231_amd import synth
+    n, seed = args
+    z, clipped = synth.mixed_channels(int(n), seed=seed)
+    return z, clipped
+
+
+def run_batching(torch, dev, precision, n_records=256, out_budget=32e9):
+    """Batching form: 256 four-channel int16 records of uneven length
+    (2^16..2^22 samples), each at a frame length drawn from {1024, 2048, 4096}
+    with N_f = N/4, every combination orbit (10 / 40 / 76).  One plan holds the
+    three frame lengths; records are taken in groups whose FP64 outputs fit
+    `out_budget` bytes, and each group is ONE ps_execute mixing all frame
+    lengths (every stage one launch over records x combinations).  The records
+    are generated on a pool of worker processes."""
+    import multiprocessing as mp
+
     import numpy as np
 
     from paper_2505_01231_amd import Plan, synth
-    lengths = synth.uneven_record_lengths(24, seed=4)
-    frame_lens = (1024, 2048, 4096)
-    total_samples, total_time, groups, launches = 0, 0.0, 0, 0
-    per_n = {}
-    for j, n in enumerate(frame_lens):
-        recs = []
-        for i in range(j, 24, 3):
-            z, clipped = synth.mixed_channels(int(lengths[i]), seed=100 + i)
-            recs.append(torch.from_numpy(z).to(dev))
-        with Plan(frame_len=n, n_freq=n // 4, m=10, window="acg", n_channels=4, precision=precision) as p:
-            nf = p.n_freq
-            out_bytes = (len(p.combos2) * nf + (len(p.combos3) + len(p.combos4)) * nf * nf) * 2 * 16
-            per_group = max(1, int(16e9 // out_bytes))
-            grp = [recs[i:i + per_group] for i in range(0, len(recs), per_group)]
-            ws = torch.empty(max(p.workspace_bytes(g) for g in grp), dtype=torch.uint8, device=dev)
-            outs = [p.allocate_outputs(dev) for _ in range(per_group)]
-            # autotuner (also the warm-up): tile order timed on the first group
-            tune = p.autotune(grp[0], reps=1, workspace=ws, outputs=outs[:len(grp[0])])
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for g in grp:
-                p.execute(g, workspace=ws, outputs=outs[:len(g)])
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            ns = sum(int(x.shape[1]) * 4 for x in recs)
-            per_n[str(n)] = {"records": len(recs), "groups": len(grp), "channel_samples": ns,
-                             "seconds": dt, "channel_samples_per_s": ns / dt,
-                             "tuning": tune["best"],
-                             "tuning_ms": {str(c["tile_group"]): round(ms, 3) for c, ms in tune["candidates"]}}
-            total_samples += ns
-            total_time += dt
-            groups += len(grp)
-            del ws, outs
-        log(f"batching N={n}: {per_n[str(n)]['channel_samples_per_s']:.3e} channel-samples/s")
-    return {"records": 24, "channels": 4, "combinations": [10, 40, 76], "executes": groups,
-            "channel_samples_per_s": total_samples / total_time, "per_frame_length": per_n,
-            "note": "each ps_execute runs every stage as one launch over its records x combinations; "
-                    "tile order per frame length chosen by ps_plan_autotune (ms per execute of the "
-                    "first group by tile_group)"}
+    lengths = synth.uneven_record_lengths(n_records, seed=4)
+    rng = np.random.default_rng(44)
+    fls = [int(v) for v in rng.choice([1024, 2048, 4096], size=n_records)]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(max(1, min(16, os.cpu_count() or 1))) as pool:
+        data = pool.map(_gen_record, [(int(L), 1000 + i) for i, L in enumerate(lengths)], chunksize=4)
+    gen_s = time.perf_counter() - t0
+    clipped = sum(c for _, c in data)
+    xs = [torch.from_numpy(z).to(dev) for z, _ in data]
+    del data
+    torch.cuda.synchronize()
+    log(f"batching: {n_records} records generated in {gen_s:.1f} s, {sum(int(x.shape[1]) for x in xs):,} samples "
+        f"per channel, {clipped} clipped")
+    with Plan(frame_len=1024, n_freq=256, m=10, window="acg", n_channels=4, precision=precision,
+              frame_lens=(2048, 4096)) as p:
+        n2, n3, n4 = len(p.combos2), len(p.combos3), len(p.combos4)
+        nf = {n: p.frame_info(n)["n_freq"] for n in (1024, 2048, 4096)}
+        out_bytes = {n: (n2 * nf[n] + (n3 + n4) * nf[n] ** 2) * 2 * 16 for n in nf}
+        groups, cur, cur_b = [], [], 0
+        for i in range(n_records):
+            if cur and cur_b + out_bytes[fls[i]] > out_budget:
+                groups.append(cur)
+                cur, cur_b = [], 0
+            cur.append(i)
+            cur_b += out_bytes[fls[i]]
+        groups.append(cur)
+        ws_bytes = max(p.workspace_bytes([xs[i] for i in g], frame_lens=[fls[i] for i in g]) for g in groups)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+        # output sets per frame length for the most records of that length in a group, reused by every group
+        need = {n: max(sum(1 for i in g if fls[i] == n) for g in groups) for n in nf}
+        outs_by_n = {n: [p.allocate_outputs(dev, n) for _ in range(need[n])] for n in nf}
+
+        def outs_of(g):
+            used = {n: 0 for n in nf}
+            res = []
+            for i in g:
+                res.append(outs_by_n[fls[i]][used[fls[i]]])
+                used[fls[i]] += 1
+            return res
+
+        g0 = groups[0]
+        tune = p.autotune([xs[i] for i in g0], reps=1, workspace=ws, outputs=outs_of(g0),
+                          frame_lens=[fls[i] for i in g0])       # also the warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for g in groups:
+            p.execute([xs[i] for i in g], workspace=ws, outputs=outs_of(g), frame_lens=[fls[i] for i in g])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    ns = sum(int(x.shape[1]) * 4 for x in xs)
+    per_n = {str(n): {"records": fls.count(n), "n_freq": nf[n]} for n in nf}
+    log(f"batching: {ns / dt:.3e} channel-samples/s over {len(groups)} executes")
+    del ws, outs_by_n, xs
+    return {"records": n_records, "channels": 4, "combinations": [n2, n3, n4], "executes": len(groups),
+            "frame_lengths_per_execute": "1024, 2048 and 4096 mixed", "channel_samples": ns, "seconds": dt,
+            "channel_samples_per_s": ns / dt, "per_frame_length": per_n, "workspace_bytes": ws_bytes,
+            "tuning": tune["best"], "generation_s": gen_s,
+            "note": "each ps_execute runs every stage as one launch over its records (all three frame lengths) x "
+                    "combinations; records grouped so that each execute's FP64 outputs stay under "
+                    f"{out_budget / 1e9:.0f} GB; tile order chosen by ps_plan_autotune on the first group"}
 
 
 def run_streaming(torch, dev, precision, n_windows=64, pool=16, per_push=8, depth=3):

@@ -984,10 +984,14 @@ def test_section9_equivalences_on_full_planes(dev):
                 pairs.append(((y, y, x), (k, l), (x, y, y), (-k - l, k)))
             pairs.append(((y, x, y, y), (k, l), (x, y, y, y), (-k, l)))
             pairs.append(((x, y, y, x), (k, l), (x, y, x, y), (k, -l)))
+    # Away from zero frequencies both sides are gathered from the same stored
+    # value; where a frequency is zero two stored quadrants hold the same
+    # cumulant, computed separately, so they agree to the parity tolerance.
     scale = {c: np.abs(v).max() for c, v in planes.items()}
     for cb, (k, l), cb2, (k2, l2) in pairs:
         a, b = planes[cb][at(k), at(l)], planes[cb2][at(k2), at(l2)]
-        assert abs(a - b) <= 1e-12 * scale[cb], (cb, k, l, cb2, k2, l2, a, b)
+        tol = TOL if 0 in ((k, l, k + l) if len(cb) == 3 else (k, l)) else 1e-12
+        assert abs(a - b) <= tol * scale[cb], (cb, k, l, cb2, k2, l2, a, b)
     # the mapped S3 points against the oracle's direct evaluation
     pts = [(k2, l2) for cb, _, cb2, (k2, l2) in pairs if len(cb2) == 3]
     ref = O.polyspectra_at(z, N, m, window_kind="acg", points3=pts, combo3=(x, y, y))
