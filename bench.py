@@ -1,12 +1,14 @@
 """Throughput of the polyspectrum estimator on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|bf16x3|fp16x2s]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp16x2s|bf16x3|fp32]
 
 Workload: one channel, 2^28 float32 samples of an AR(2) process (poles
 0.95 e^{+-0.3 pi j}) driven by centred chi-square(1) noise, frame length
 N = 8192, acG window (sigma_t = 0.14), N_f = 2048 frequencies, m = 10
 frames per chunk (3276 chunks); S2, S3 and S4 with FP64 chunk averages and
-error bars.  One step = one ps_execute over the whole resident record.
+error bars.  One step = one ps_execute over the whole resident record, by
+default in the scaled FP16 x 2 precision (matrix-core S4 on operands the
+centring pass splits).
 
 Prints ONE JSON line (rank 0).  `value` is input samples per second.
 """
@@ -33,11 +35,12 @@ WORKLOAD = "ar2-chi2 1ch 2^28 f32, N=8192, N_f=2048, m=10, acG 0.14, S2+S3+S4"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_s3_ar2_2p28_n8192_nf2048_traffic.json")
 
 PEAK_HBM_GBS = 8000.0
-# FP32 FMA on the vector ALUs without packed-FP32 instructions:
-# 256 CUs x 64 lanes x 2 flop x 2.4 GHz.  (The vendor's 157.3 TFLOP/s assumes
-# packed FP32 instructions, which the library's device code is compiled without.)
-PEAK_FP32_VALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
-VENDOR_FP32_VECTOR_TFLOPS = 157.3
+# FP32 FMA on the vector ALUs: the vendor's 157.3 TFLOP/s (256 CUs x 128
+# lanes x 2 flop x 2.4 GHz).  It does not need packed-FP32 instructions (which
+# the library's device code is compiled without): a wave64 v_fma_f32 issues
+# every 2.2-2.5 SIMD cycles with four or more waves per SIMD (measured on this
+# chip; one wave alone issues every ~6 cycles).
+PEAK_FP32_VALU_TFLOPS = 157.3
 
 
 def log(*a):
@@ -251,7 +254,8 @@ def run_batching(torch, dev, precision, n_records=256, out_budget=32e9):
     per_n = {str(n): {"records": fls.count(n), "n_freq": nf[n]} for n in nf}
     log(f"batching: {ns / dt:.3e} channel-samples/s over {len(groups)} executes")
     del ws, outs_by_n, xs
-    return {"records": n_records, "channels": 4, "combinations": [n2, n3, n4], "executes": len(groups),
+    return {"records": n_records, "channels": 4, "precision": precision, "combinations": [n2, n3, n4],
+            "executes": len(groups),
             "frame_lengths_per_execute": "1024, 2048 and 4096 mixed", "channel_samples": ns, "seconds": dt,
             "channel_samples_per_s": ns / dt, "per_frame_length": per_n, "workspace_bytes": ws_bytes,
             "tuning": tune["best"], "generation_s": gen_s,
@@ -318,7 +322,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="bf16x3")
+    ap.add_argument("--precision", default="fp16x2s", choices=("fp32", "bf16x3", "fp16x2s"))
     ap.add_argument("--fp32-steps", type=int, default=3,
                     help="timed steps of the batched all-FP32 path (for mixed-vs-FP32)")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the per-chunk FP32 path")
@@ -444,8 +448,9 @@ def main(argv=None):
             # per 64 x 64 tile and chunk: 4 waves x 4 K steps x 5 sums MFMA 32x32x16
             mfma_flops = n_tiles * n_chunks * 4 * 20 * (32 * 32 * 16 * 2)
         else:
-            # per 64 x 64 tile and chunk: 4 waves x 4 blocks x 5 sums MFMA 16x16x32 (one K step)
-            mfma_flops = n_tiles * n_chunks * 4 * 4 * 5 * (16 * 16 * 32 * 2)
+            # operands split by the centring pass (m <= 10): per 64 x 64 tile
+            # and chunk 4 waves x 2 K steps x 5 sums MFMA 32x32x16 (f16)
+            mfma_flops = n_tiles * n_chunks * 4 * 10 * (32 * 32 * 16 * 2)
         s4_info.update({"mfma_executed_tflops": mfma_flops / (s4_avg_ms * 1e-3) / 1e12,
                         "mfma_peak_tflops": 2500.0,
                         "mfma_frac_of_peak": mfma_flops / (s4_avg_ms * 1e-3) / 2.5e15})
@@ -518,7 +523,9 @@ def main(argv=None):
             del out_
         log(f"sequential {sequential['chunks_per_s']:.3e} chunks/s")
 
-    batching = None if args.no_batching else run_batching(torch, dev, args.precision)
+    # (the four-channel records are mostly cross-channel S4, which has a
+    # matrix-core kernel in BF16 x 3 only)
+    batching = None if args.no_batching else run_batching(torch, dev, "fp32" if args.precision == "fp32" else "bf16x3")
     streaming = None if args.no_streaming else run_streaming(torch, dev, args.precision)
 
     cpu, acc = None, None
@@ -565,10 +572,8 @@ def main(argv=None):
             "peak": PEAK_FP32_VALU_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VALU_TFLOPS,
-            "peak_note": "78.6 TFLOP/s = 256 CU x 64 lanes x FMA x 2.4 GHz without packed-FP32 issue "
-                         "(the library is built without packed FP32); vendor vector figure 157.3",
-            "vendor_peak": VENDOR_FP32_VECTOR_TFLOPS,
-            "frac_of_vendor_peak": achieved / VENDOR_FP32_VECTOR_TFLOPS,
+            "peak_note": "vendor FP32 vector figure; reachable without packed FP32 (a wave64 v_fma_f32 "
+                         "issues every 2.2-2.5 SIMD cycles at >= 4 waves per SIMD, measured)",
             "traffic": s3_traffic() if args.estimator == "kstat" else None,
             "avg_launch_ms": s3_avg_ms,
             "flops_per_launch": s3_flops_per_launch(s3_rows, NF),

@@ -141,6 +141,10 @@ struct ps_plan_s {
     float2* d_tw = nullptr;
     int2* d_tiles[4] = {nullptr, nullptr, nullptr, nullptr};
     int n_cu = 256, bpc_s3 = 2, bpc_s4 = 2, bpc_s4x = 2;
+    // Single-channel S4 on the matrix cores with operands scaled and split
+    // once per column and chunk by the centring pass (scaled FP16 x 2, real
+    // signals, the cut, m <= ps::kOpFrames).
+    bool s4_pre = false;
     // Launch configuration (ps_plan_set_tuning / ps_plan_autotune).
     int tile_group = 8;     // tile order: tile_group x tile_group blocks
     int s3_fb = 0;          // S3 frame batch; 0: chosen by m
@@ -301,6 +305,11 @@ struct BatchClass {
     int64_t chunk_base = 0;         // first chunk of the class in the batch
     int64_t rows = 0, rows3 = 0;    // rows per channel of its blocks
     size_t coef_off = 0, coef3_off = 0;     // byte offsets in the workspace
+    // pre-split S4 operands: chunk slots per channel, byte offsets of the
+    // operand records [C][op_chunks][3][kOpPieces][N_f'][4] and the P sums and
+    // scales [C][op_chunks][2][N_f'] (N_f' = N_f rounded up to the tile edge)
+    int64_t op_chunks = 0;
+    size_t op4_off = 0, p4_off = 0;
     int rd0 = 0, n_rd = 0;          // its record descriptors in Batch.rd
 };
 
@@ -330,7 +339,16 @@ struct Group {
 // With interlaced windows every caller record r becomes two internal records:
 // 2r, its frames from sample 0, and 2r + 1, its frames from sample N/2 (stride
 // 2); the finalize of 2r combines both.
+// Columns of the S4 operand records: N_f rounded up to the tile edge.
+inline int op_cols(int nf) { return (nf + ps::kTile - 1) / ps::kTile * ps::kTile; }
+
 struct Batch {
+    // single-channel S4 combinations of the plan (those the pre-split operands serve)
+    static int n_s4_single(const ps_plan_s* p) {
+        int n = 0;
+        for (int i = 0; i < p->n4(); ++i) n += p->s4_single(i) ? 1 : 0;
+        return n;
+    }
     int stride = 1;                 // internal records per caller record
     std::vector<RecInfo> ri;        // per internal record
     std::vector<ps::RecDesc> rd;    // grouped by class, frame0 ascending within a class
@@ -440,6 +458,15 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
         k.rows3 = opt3 ? (per_chunk ? 1 : k.chunks) * (m + 1) : 0;
         k.coef3_off = off;
         off = align256(off + (size_t)p->C * k.rows3 * p->fc[k.cls].K * sizeof(float2));
+    }
+    const bool op4 = p->s4_pre && B.n_s4_single(p) > 0;
+    for (BatchClass& k : B.bc) {
+        const int64_t ng = op_cols(p->fc[k.cls].Ng);
+        k.op_chunks = op4 ? (per_chunk ? 1 : k.chunks) : 0;
+        k.op4_off = off;
+        off = align256(off + (size_t)p->C * k.op_chunks * 3 * ng * ps::kOpWords * sizeof(uint32_t));
+        k.p4_off = off;
+        off = align256(off + (size_t)p->C * k.op_chunks * 2 * ng * sizeof(float));
     }
     B.coef_bytes = off;
 
@@ -566,6 +593,14 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                 sg.blocks = seg_blocks(sg.n_tiles, q.Np, single ? L4s : L4x, per_chunk);
                 for (int j = 0; j < 4; ++j) sg.ch[j] = p->c4[4 * i + j];
                 sg.ncomp = single ? 2 : 4;
+                if (single && k.op_chunks > 0) {
+                    const int64_t ngp = op_cols(Nf);
+                    const int64_t rec = 3 * ngp * ps::kOpWords;       // uint32 per chunk
+                    sg.op4 = (int64_t)(k.op4_off / sizeof(uint32_t)) + (per_chunk ? 0 : q.chunk0c * rec);
+                    sg.op4_cs = k.op_chunks * rec;
+                    sg.p4 = (int64_t)(k.p4_off / sizeof(float)) + (per_chunk ? 0 : q.chunk0c * 2 * ngp);
+                    sg.p4_cs = k.op_chunks * 2 * ngp;
+                }
                 sg.part = part;
                 part += ps::Sched{sg.n_tiles, q.Np, sg.blocks}.n_slots() * sg.ncomp * (single ? TT : TX);
                 sg.out = o && o->d_s4 ? o->d_s4 + 2 * i * nf2 : nullptr;
@@ -931,8 +966,10 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
         return fail(PS_E_HIP, "plan setup failed: %s", hipGetErrorString(e));
     }
     p->bpc_s3 = ps::s3_blocks_per_cu();
+    p->s4_pre = p->precision == PS_PREC_FP16X2S && !p->cplx && p->s4_shift == 0 && p->m <= ps::kOpFrames;
     p->bpc_s4 = p->precision == PS_PREC_FP32     ? ps::s4_blocks_per_cu()
                 : p->precision == PS_PREC_BF16X3 ? ps::s4_mfma_blocks_per_cu()
+                : p->s4_pre                      ? ps::s4_mfma_pre_blocks_per_cu()
                                                  : ps::s4_mfma_f16_blocks_per_cu();
     p->bpc_s4x = p->precision == PS_PREC_BF16X3 ? ps::s4_cross_mfma_blocks_per_cu() : ps::s4_cross_blocks_per_cu();
     *out = p;
@@ -1258,7 +1295,11 @@ ps_status launch_moments(ps_plan_t p, const Batch& B, const Group& G, char* ws, 
     }
     if (G.s4s.n_items) {
         StageTimer t(p, st, 4);
-        const ps::BatchArgs a = batch_args(p, B, G.s4s, ws, tab, per_chunk, win_lo, win_hi, accumulate);
+        ps::BatchArgs a = batch_args(p, B, G.s4s, ws, tab, per_chunk, win_lo, win_hi, accumulate);
+        if (p->s4_pre) {                // operands split by the centring pass
+            a.op4 = reinterpret_cast<const uint32_t*>(ws);
+            a.p4 = reinterpret_cast<const float*>(ws);
+        }
         if (p->precision == PS_PREC_FP32) {
             PS_HIP(ps::launch_s4_single(a, st));
         } else if (p->precision == PS_PREC_BF16X3) {
@@ -1373,6 +1414,14 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
         if (p->c3opt()) {
             c.out3 = reinterpret_cast<float2*>(ws + k.coef3_off);
             c.out3_cs = k.rows3 * fc.K;
+        }
+        if (k.op_chunks > 0) {
+            const int ngp = op_cols(fc.Ng);
+            c.op4 = reinterpret_cast<uint32_t*>(ws + k.op4_off);
+            c.op4_cs = k.op_chunks * 3 * (int64_t)ngp * ps::kOpWords;
+            c.p4 = reinterpret_cast<float*>(ws + k.p4_off);
+            c.p4_cs = k.op_chunks * 2 * (int64_t)ngp;
+            c.op4_cols = ngp;
         }
         return c;
     };

@@ -516,6 +516,61 @@ hipError_t launch_n(const FftArgs& a, hipStream_t st) {
 // is c3opt.
 constexpr int kCentreRegs = 16;
 
+// float16 word pair (lo, hi), each rounded to nearest even.
+typedef _Float16 f16x2_v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t f16_pair(float lo, float hi) {
+    const f16x2_v v = {(_Float16)lo, (_Float16)hi};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// The operand records of the matrix-core S4 kernel for one column of one
+// chunk (see kOpWords): piece i of value v (Re, Im, P) of column k at the
+// 16-byte unit (3 v + i) op4_cols + k of the chunk's block, and p = sum_f P,
+// s^2 at p4[chunk][0][k], p4[chunk][1][k].  v holds the chunk's m <= kOpFrames
+// uncentred values; a column without coefficients (k >= K, padding up to
+// op4_cols) gets zero records, p = 0 and s = 1.
+__device__ __forceinline__ void write_op_records(const CentreClass& cl, int64_t chunk, int k, int m,
+                                                 const float2 (&v)[kCentreRegs], float mr, float mi, bool live) {
+    const int64_t ngp = cl.op4_cols;
+    uint4* rec = reinterpret_cast<uint4*>(cl.op4 + blockIdx.y * cl.op4_cs + chunk * (3 * kOpWords) * ngp) + k;
+    float re[kOpFrames], im[kOpFrames], amax = 0.f;
+#pragma unroll
+    for (int f = 0; f < kOpFrames; ++f) {
+        const bool on = live && f < m;
+        re[f] = on ? v[f].x - mr : 0.f;                     // the centred values written to coef
+        im[f] = on ? v[f].y - mi : 0.f;
+        amax = fmaxf(amax, fmaxf(fabsf(re[f]), fabsf(im[f])));
+    }
+    const float s = pow2_above(amax);
+    const float inv_s = 1.0f / s, inv_s2 = inv_s * inv_s;    // exact: powers of two
+    float psum = 0.f;
+#pragma unroll
+    for (int val = 0; val < 3; ++val) {
+        uint32_t w[kOpWords];
+#pragma unroll
+        for (int f = 0; f < kOpFrames; f += 2) {
+            float x[2], l[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const float P = fmaf(re[f + u], re[f + u], im[f + u] * im[f + u]);
+                if (val == 2) psum += P;
+                x[u] = val == 0 ? re[f + u] * inv_s : val == 1 ? im[f + u] * inv_s : P * inv_s2;
+                l[u] = x[u] - (float)(_Float16)x[u];
+            }
+            w[f >> 1] = f16_pair(x[0], x[1]);
+            w[5 + (f >> 1)] = f16_pair(l[0], l[1]);
+        }
+        w[10] = w[11] = 0u;
+        uint4* dst = rec + val * kOpPieces * ngp;
+        dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
+        dst[ngp] = make_uint4(w[4], w[5], w[6], w[7]);
+        dst[2 * ngp] = make_uint4(w[8], w[9], w[10], w[11]);
+    }
+    float* pp = cl.p4 + blockIdx.y * cl.p4_cs + chunk * 2 * ngp + k;
+    pp[0] = psum;
+    pp[ngp] = s * s;
+}
+
 // Grid: x = the classes' (chunk, 256-wide k block) pairs, chunk-major within
 // each class; y = channel (the chunk count can exceed the 65536 limit of the y
 // and z grid dimensions).
@@ -529,7 +584,15 @@ __global__ __launch_bounds__(256) void k_centre(CentreArgs a) {
     const int64_t local = (int64_t)blockIdx.x - cl.block0;
     const int64_t chunk = local / kblocks;
     const int k = (int)(local - chunk * kblocks) * 256 + threadIdx.x;
-    if (k >= K) return;
+    if (k >= K) {
+        if (cl.op4 && k < cl.op4_cols) {            // padding columns of the S4 operand records
+            float2 z[kCentreRegs];
+#pragma unroll
+            for (int f = 0; f < kCentreRegs; ++f) z[f] = make_float2(0.f, 0.f);
+            write_op_records(cl, chunk, k, m, z, 0.f, 0.f, false);
+        }
+        return;
+    }
     float2* p = cl.coef + blockIdx.y * cl.coef_chan_stride + chunk * m * K + k;
     // c3^(opt): the chunk's rows for S3, frames shifted by alpha mean, then mu mean
     float2* q = cl.out3 ? cl.out3 + blockIdx.y * cl.out3_cs + chunk * (m + 1) * K + k : nullptr;
@@ -561,6 +624,7 @@ __global__ __launch_bounds__(256) void k_centre(CentreArgs a) {
 #pragma unroll
         for (int f = 0; f < kCentreRegs; ++f)
             if (f < m) put(f, v[f], mr, mi);
+        if (cl.op4 && k < cl.op4_cols) write_op_records(cl, chunk, k, m, v, mr, mi, true);
         return;
     }
     float sr = 0.f, si = 0.f;

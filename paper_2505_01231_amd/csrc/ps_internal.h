@@ -93,6 +93,28 @@ __host__ __device__ constexpr int fft_twiddle_count(int log2n) {
     return (1 << log2n) + fft_radix2(log2n) * 16 + fft_radix3(log2n) * 16 * fft_radix2(log2n);
 }
 
+// Operand records of the matrix-core S4 kernel (scaled FP16 x 2): for each
+// chunk and column, a power of two s > max_f (|Re a'|, |Im a'|) over the
+// chunk's frames, and each of the values Re a' / s, Im a' / s, P / s^2
+// (P = |a'|^2) of frames 0..9 split into two float16 terms x = h + l
+// (h = fp16(x), l = fp16(x - h), both rounded to nearest).  A value's record
+// is kOpWords 32-bit words: 0..4 the h terms (two frames per word, the earlier
+// frame in the low half), 5..9 the l terms, 10..11 zero; frames >= m are zero.
+// It is stored as kOpPieces 16-byte pieces (words 4i..4i+3), piece-major over
+// the columns, and the column count is padded to a multiple of the 64-wide
+// tile with zero records (op4_cols).
+constexpr int kOpFrames = 10;
+constexpr int kOpPieces = 3;
+constexpr int kOpWords = 4 * kOpPieces;
+
+// The smallest power of two strictly above a >= 0 (1 for a == 0).
+__device__ __forceinline__ float pow2_above(float a) {
+    if (!(a > 0.f)) return 1.0f;
+    int e;
+    (void)frexpf(a, &e);            // a = f 2^e, f in [0.5, 1)
+    return ldexpf(1.0f, e);
+}
+
 // In-place centring: a_k(f) -= mean over the m frames of its chunk.  With
 // `s1` set, the chunk's mean of a_0 (column s1_col; the first-order
 // k-statistic) is also stored at s1[channel * s1_cs + s1_chunk0 + chunk].
@@ -108,6 +130,16 @@ struct CentreClass {
     // [C][n_chunks * (m + 1)][K]
     float2* out3;
     int64_t out3_cs;
+    // Matrix-core S4 operands (null: none; chunks of m <= kOpFrames frames):
+    // per chunk and column k < op4_cols of every channel, the split terms of
+    // Re a' / s, Im a' / s and P / s^2 (see kOpWords), p = sum_f P and s^2;
+    // op4_cols is N_f rounded up to a multiple of 64 (columns from K on: zero
+    // records, p = 0, s = 1).
+    uint32_t* op4;          // [C][n_chunks][3][kOpPieces][op4_cols][4]
+    int64_t op4_cs;         // uint32 elements between channels
+    float* p4;              // [C][n_chunks][2][op4_cols]: p, then s^2
+    int64_t p4_cs;
+    int op4_cols;
     int64_t block0;         // first block of the class
 };
 struct CentreArgs {
@@ -162,6 +194,8 @@ struct Seg {
     int64_t item0;          // first work item (block) of the segment
     int64_t coef;           // float2 offset of the record's chunk 0 in the coefficient region
     int64_t cs;             // float2 elements between channels of the record's coefficient block
+    int64_t op4, op4_cs;    // S4 operand records of the record's chunk 0 (uint32 offset), channel stride
+    int64_t p4, p4_cs;      // and its column sums of P and scales s^2 (float offset), channel stride
     const int2* tile_tab;   // the grid's tile table (tile t -> (kt, lt)); by `tiles` and the grid size
     int32_t K;              // coefficients per frame of the record's frame length
     int32_t Nf;             // points per grid axis of the record's spectra
@@ -188,6 +222,8 @@ struct BatchArgs {
     int n_segs;
     int64_t n_items;
     const float2* coef;     // coefficient region
+    const uint32_t* op4;    // S4 operand records (pre-split; null: the S4 kernel splits)
+    const float* p4;
     double* part;           // partial-sum region
     int m;                  // rows per chunk
     int col0;               // column of grid index 0 for the first factors (see View)
@@ -213,6 +249,7 @@ hipError_t launch_s4_cross_mfma(const BatchArgs& a, hipStream_t s);
 int s3_blocks_per_cu();
 int s4_blocks_per_cu();
 int s4_mfma_blocks_per_cu();
+int s4_mfma_pre_blocks_per_cu();
 int s4_mfma_f16_blocks_per_cu();
 int s4_cross_blocks_per_cu();
 int s4_cross_mfma_blocks_per_cu();

@@ -725,14 +725,6 @@ __device__ __forceinline__ void put_pair_f16(unsigned short* row, int f, float x
     }
 }
 
-__device__ __forceinline__ float pow2_above(float a) {
-    // smallest power of two strictly above a (a >= 0); 1 for a == 0
-    if (!(a > 0.f)) return 1.0f;
-    int e;
-    (void)frexpf(a, &e);            // a = f 2^e, f in [0.5, 1)
-    return ldexpf(1.0f, e);
-}
-
 __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16(BatchArgs p) {
     __shared__ __attribute__((aligned(16))) unsigned short opK[3 * kTile][kF16Stride];
     __shared__ __attribute__((aligned(16))) unsigned short opL[3 * kTile][kF16Stride];
@@ -888,6 +880,191 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16(BatchArgs p) {
                 if (p.accumulate) val += o[comp * kTile * kTile + idx];
                 o[comp * kTile * kTile + idx] = val;
             }
+        }
+    }
+    }
+}
+
+// ------------------------------------------------------------------ S4, one channel, matrix cores, scaled FP16 x 2, pre-split operands
+// The sums of k_s4_mfma_f16 from the operand records the centring pass writes
+// (see kOpWords): per chunk and column a power of two s, the values scaled by
+// s (P by s^2) and split in two float16 terms x = h + l.  The K dimension of
+// one chunk holds three blocks of ten frame slots, the products h.h, h.l,
+// l.h: the k-side row [h h l] and the l-side row [h l h] of term blocks (30 of
+// 32 slots; 30, 31 zero), so one contraction over the row gives the frame sum
+// h_k h_l + h_k l_l + l_k h_l of each Gram sum.  v_mfma_f32_32x32x16_f16 on
+// 64 x 64 tiles, four waves of 32 x 32; building a row is a copy of term
+// blocks from the record into LDS.  The records of chunk c + 1 travel from
+// memory into an LDS staging area by asynchronous copies while chunk c is
+// contracted and combined (no registers held across).
+//
+// With the scale sigma = s_k^2 s_l^2 (exact) of the point, M4 and
+// X^2 + Y^2 + U^2 + V^2 of the scaled values are both sigma times the
+// unscaled ones, so the chunk's term is
+//   v = sigma (M4' - 2 gamma (X'^2 + Y'^2 + U'^2 + V'^2)) - gamma p_k p_l,
+// formed in FP64 (p = sum_f P unscaled, FP32 from the centring pass).
+constexpr int kF16PreDw = 20;          // 32-bit words per LDS operand row (80 B; 16 used)
+
+// Asynchronous copy of 16 (or 4) bytes per lane from global memory into LDS:
+// lane i writes lds + i * bytes (lds uniform over the wave); completion is
+// counted like a global load, and the LDS fence of lds_barrier waits for it.
+__device__ __forceinline__ void copy_to_lds16(const void* g, void* lds) {
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
+                                     (void __attribute__((address_space(3)))*)lds, 16, 0, 0);
+}
+__device__ __forceinline__ void copy_to_lds4(const void* g, void* lds) {
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
+                                     (void __attribute__((address_space(3)))*)lds, 4, 0, 0);
+}
+
+__global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p) {
+    __shared__ __attribute__((aligned(16))) uint32_t opK[3 * kTile][kF16PreDw];
+    __shared__ __attribute__((aligned(16))) uint32_t opL[3 * kTile][kF16PreDw];
+    __shared__ double psum[2][kTile];          // -gamma p_k (k side), p_l (l side)
+    __shared__ double sc2[2][kTile];           // s_k^2, s_l^2
+    // The next chunk's records as copied: [side][value][piece][column] and
+    // [side][p, s^2][column].
+    __shared__ __attribute__((aligned(16))) uint4 stg[2][3][kOpPieces][kTile];
+    __shared__ __attribute__((aligned(16))) float stgp[2][2][kTile];
+
+    Block bk;
+    View v;
+    if (!resolve_block(p, bk, v)) return;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int r32 = lane & 31, kh = lane >> 5;
+    const int rowK = 32 * (w >> 1) + r32, rowL = 32 * (w & 1) + r32;
+    const int wv = __builtin_amdgcn_readfirstlane(w);
+
+    // Row builders, uniform per wave: thread t < 192 (waves 0-2) builds
+    // k-side row t (value t / 64, column t % 64), thread t >= 64 (waves 1-3)
+    // builds l-side row t - 64; wave 0 stages p, s^2 of the k side, wave 3
+    // those of the l side.
+    const bool ldK = wv < 3, ldL = wv >= 1;
+    const int rK = tid, rL = tid - kTile;
+    const int valK = rK / kTile, colK = rK % kTile, valL = rL / kTile, colL = rL % kTile;
+    const double gamma = p.gamma;
+    const double m2g = -2.0 * gamma;
+    // Records: 3 kOpWords ngp words per chunk; value v, piece i of column k
+    // is the 16-byte unit (3 v + i) ngp + k of the chunk's block.
+    const int64_t ngp = (int64_t)(v.Nf + kTile - 1) / kTile * kTile;
+    const int64_t cunits = 3 * kOpPieces * ngp;                    // 16-byte units per chunk
+    const int64_t cbase = p.per_chunk ? -(int64_t)p.win_lo : 0;   // per-chunk schedule: chunk win_lo at 0
+
+    Item it;
+    while (next_item<kTile, 2>(p, bk, it)) {
+    const Seg& sg = *bk.s;
+    const int c0 = it.c0, c1 = it.c1;
+    const int k0 = it.k0, l0 = it.l0;
+    const uint4* base = reinterpret_cast<const uint4*>(p.op4 + it.ch[0] * sg.op4_cs + sg.op4);
+    const float* pbase = p.p4 + it.ch[0] * sg.p4_cs + sg.p4;
+    // Copy of chunk c into the staging buffers: 18 record copies (side,
+    // value, piece) and 4 p / s^2 copies of 64 columns, dealt over the waves.
+    auto copy_chunk = [&](int c) {
+        const uint4* rc = base + (cbase + c) * cunits + lane;
+        for (int q = wv; q < 2 * 3 * kOpPieces; q += 4) {
+            const int side = q / (3 * kOpPieces), vp = q % (3 * kOpPieces);
+            copy_to_lds16(rc + (int64_t)vp * ngp + (side ? l0 : k0), &stg[side][0][0][0] + vp * kTile);
+        }
+        const float* pc = pbase + (cbase + c) * 2 * ngp + lane;
+        const int side = wv >> 1, comp = wv & 1;
+        copy_to_lds4(pc + comp * ngp + (side ? l0 : k0), &stgp[side][comp][0]);
+    };
+
+    double acc[16][2];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r][0] = acc[r][1] = 0.0;
+
+    // (the previous piece's last chunk may still be read from the rows)
+    lds_barrier();
+    copy_chunk(c0);
+    floatx16_t d[5];
+#pragma unroll 1
+    for (int c = c0; c < c1; ++c) {
+        lds_barrier();                                 // the copy of chunk c has landed
+        // Record words [0, 5) h, [5, 10) l of frames 0..9: rec[0] = h0..h3,
+        // rec[1] = h4 l0 l1 l2, rec[2] = l3 l4 0 0.  A row is written as four
+        // 16-byte groups (at the 20-word row stride the 16 lanes of each LDS
+        // cycle cover all banks once); word 15 holds the zero slots 30, 31.
+        if (ldK) {                                             // [h h l]
+            const uint4 r0 = stg[0][valK][0][colK], r1 = stg[0][valK][1][colK], r2 = stg[0][valK][2][colK];
+            uint4* row = reinterpret_cast<uint4*>(opK[rK]);
+            row[0] = r0;
+            row[1] = make_uint4(r1.x, r0.x, r0.y, r0.z);
+            row[2] = make_uint4(r0.w, r1.x, r1.y, r1.z);
+            row[3] = make_uint4(r1.w, r2.x, r2.y, 0u);
+        }
+        if (ldL) {                                             // [h l h]
+            const uint4 r0 = stg[1][valL][0][colL], r1 = stg[1][valL][1][colL], r2 = stg[1][valL][2][colL];
+            uint4* row = reinterpret_cast<uint4*>(opL[rL]);
+            row[0] = r0;
+            row[1] = r1;
+            row[2] = make_uint4(r2.x, r2.y, r0.x, r0.y);
+            row[3] = make_uint4(r0.z, r0.w, r1.x, 0u);
+        }
+        if (wv == 0) {
+            psum[0][lane] = -gamma * (double)stgp[0][0][lane];
+            sc2[0][lane] = (double)stgp[0][1][lane];
+        } else if (wv == 3) {
+            psum[1][lane] = (double)stgp[1][0][lane];
+            sc2[1][lane] = (double)stgp[1][1][lane];
+        }
+        lds_barrier();                                 // rows ready, staging free
+        if (c + 1 < c1) copy_chunk(c + 1);
+        // Two K steps of 16 slots (the scheduling barrier keeps each step's
+        // operand reads next to its contractions: fewer live registers).
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const int wo = 8 * ks + 4 * kh;                    // first word of this lane's 8 slots
+            const halfx8_t aR = __builtin_bit_cast(halfx8_t, *reinterpret_cast<const u32x4_t*>(&opK[rowK][wo]));
+            const halfx8_t aI = __builtin_bit_cast(halfx8_t, *reinterpret_cast<const u32x4_t*>(&opK[kTile + rowK][wo]));
+            const halfx8_t aP = __builtin_bit_cast(halfx8_t, *reinterpret_cast<const u32x4_t*>(&opK[2 * kTile + rowK][wo]));
+            const halfx8_t bR = __builtin_bit_cast(halfx8_t, *reinterpret_cast<const u32x4_t*>(&opL[rowL][wo]));
+            const halfx8_t bI = __builtin_bit_cast(halfx8_t, *reinterpret_cast<const u32x4_t*>(&opL[kTile + rowL][wo]));
+            const halfx8_t bP = __builtin_bit_cast(halfx8_t, *reinterpret_cast<const u32x4_t*>(&opL[2 * kTile + rowL][wo]));
+            if (ks == 0) {
+                const floatx16_t z = {};
+                d[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aR, bR, z, 0, 0, 0);   // X
+                d[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aR, bI, z, 0, 0, 0);   // U
+                d[2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aI, bR, z, 0, 0, 0);   // V
+                d[3] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aI, bI, z, 0, 0, 0);   // Y
+                d[4] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aP, bP, z, 0, 0, 0);   // M4
+            } else {
+                d[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aR, bR, d[0], 0, 0, 0);
+                d[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aR, bI, d[1], 0, 0, 0);
+                d[2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aI, bR, d[2], 0, 0, 0);
+                d[3] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aI, bI, d[3], 0, 0, 0);
+                d[4] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aP, bP, d[4], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+
+        // Register r of lane (kh, r32) is grid point
+        // k = k0 + 32 (w / 2) + 8 (r / 4) + 4 kh + r % 4, l = l0 + 32 (w % 2) + r32.
+        // The k-statistic combination in FP64.
+        const double pl = psum[1][rowL], sl2 = sc2[1][rowL];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int kr = 32 * (w >> 1) + 8 * (r >> 2) + 4 * kh + (r & 3);
+            const double X = d[0][r], U = d[1][r], V = d[2][r], Y = d[3][r];
+            const double sq = fma(X, X, fma(Y, Y, fma(U, U, V * V)));
+            const double sig = sc2[0][kr] * sl2;
+            const double val = fma(sig, fma(m2g, sq, (double)d[4][r]), psum[0][kr] * pl);
+            acc[r][0] += val;
+            acc[r][1] = fma(val, val, acc[r][1]);
+        }
+    }
+
+    double* o = it.part;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int idx = (32 * (w >> 1) + 8 * (r >> 2) + 4 * kh + (r & 3)) * kTile + 32 * (w & 1) + r32;
+#pragma unroll
+        for (int comp = 0; comp < 2; ++comp) {
+            double val = acc[r][comp];
+            if (p.accumulate) val += o[comp * kTile * kTile + idx];
+            o[comp * kTile * kTile + idx] = val;
         }
     }
     }
@@ -1314,12 +1491,21 @@ int s3_blocks_per_cu() {
 int s4_blocks_per_cu() { return blocks_per_cu(reinterpret_cast<const void*>(&k_s4_single), kS4Threads); }
 hipError_t launch_s4_mfma_f16(const BatchArgs& a, hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;
+    if (a.op4) {
+        if (a.m > kOpFrames) return hipErrorInvalidValue;
+        k_s4_mfma_f16_pre<<<item_grid(a), kS4MThreads, 0, s>>>(a);
+        return hipGetLastError();
+    }
     k_s4_mfma_f16<<<item_grid(a), kS4MThreads, 0, s>>>(a);
     return hipGetLastError();
 }
 
 int s4_mfma_f16_blocks_per_cu() {
     return blocks_per_cu(reinterpret_cast<const void*>(&k_s4_mfma_f16), kS4MThreads);
+}
+
+int s4_mfma_pre_blocks_per_cu() {
+    return blocks_per_cu(reinterpret_cast<const void*>(&k_s4_mfma_f16_pre), kS4MThreads);
 }
 
 int s4_mfma_blocks_per_cu() {
