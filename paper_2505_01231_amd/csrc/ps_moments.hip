@@ -907,7 +907,8 @@ constexpr int kF16PreDw = 20;          // 32-bit words per LDS operand row (80 B
 
 // Asynchronous copy of 16 (or 4) bytes per lane from global memory into LDS:
 // lane i writes lds + i * bytes (lds uniform over the wave); completion is
-// counted like a global load, and the LDS fence of lds_barrier waits for it.
+// counted like a global load.  LDS reads of other arrays need not wait for
+// it (the compiler tells the targets apart by their arrays).
 __device__ __forceinline__ void copy_to_lds16(const void* g, void* lds) {
     __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
                                      (void __attribute__((address_space(3)))*)lds, 16, 0, 0);
@@ -915,6 +916,16 @@ __device__ __forceinline__ void copy_to_lds16(const void* g, void* lds) {
 __device__ __forceinline__ void copy_to_lds4(const void* g, void* lds) {
     __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
                                      (void __attribute__((address_space(3)))*)lds, 4, 0, 0);
+}
+
+// Workgroup barrier after which the copies every wave has issued into LDS
+// have landed: each wave first waits for its own copies (vmcnt, which the
+// compiler does not always add for a copy issued in the previous trip of a
+// loop) and LDS accesses (lgkmcnt).  s_waitcnt fields on this target:
+// vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
+__device__ __forceinline__ void copies_barrier() {
+    __builtin_amdgcn_s_waitcnt(0x0070);        // vmcnt(0) lgkmcnt(0)
+    lds_barrier();
 }
 
 __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p) {
@@ -982,7 +993,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
     floatx16_t d[5];
 #pragma unroll 1
     for (int c = c0; c < c1; ++c) {
-        lds_barrier();                                 // the copy of chunk c has landed
+        copies_barrier();                              // the copy of chunk c has landed
         // Record words [0, 5) h, [5, 10) l of frames 0..9: rec[0] = h0..h3,
         // rec[1] = h4 l0 l1 l2, rec[2] = l3 l4 0 0.  A row is written as four
         // 16-byte groups (at the 20-word row stride the 16 lanes of each LDS
