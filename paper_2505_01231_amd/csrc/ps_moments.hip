@@ -923,9 +923,62 @@ __device__ __forceinline__ void copy_to_lds4(const void* g, void* lds) {
 // compiler does not always add for a copy issued in the previous trip of a
 // loop) and LDS accesses (lgkmcnt).  s_waitcnt fields on this target:
 // vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
+// Workgroup barrier for kernels with several copies in flight: the wave's
+// LDS accesses are complete (lgkmcnt) but its copies may still be running;
+// the empty asm statements keep the compiler from moving memory accesses
+// across (and from adding a wait for the copies, as the LDS fence of
+// lds_barrier can).  lds_sync: the caller has already waited as needed.
+__device__ __forceinline__ void lds_sync() {
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
+}
+__device__ __forceinline__ void lds_sync_rows() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);        // lgkmcnt(0); vmcnt, expcnt at their maximum
+    lds_sync();
+}
 __device__ __forceinline__ void copies_barrier() {
     __builtin_amdgcn_s_waitcnt(0x0070);        // vmcnt(0) lgkmcnt(0)
     lds_barrier();
+}
+
+// Reads of a staging buffer filled by asynchronous copies whose completion
+// the caller has established (its own wait on the copy count, then a
+// workgroup barrier).  Written as LDS reads in inline assembly, with their
+// wait in the same statement, because the compiler's own wait for copies in
+// flight cannot tell the two staging buffers apart and would wait for the
+// copies into the other buffer too.  read_staged_record: the three 16-byte
+// pieces of a record at a stride of kTile records (the third piece's first
+// 8 bytes); read_staged_pair: two floats at a stride of kTile floats.
+__device__ __forceinline__ void read_staged_record(const uint4* p, uint4& r0, uint4& r1, uint2& r2) {
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    static_assert(kTile * sizeof(uint4) == 1024, "piece stride in the offsets below");
+    const unsigned a = (unsigned)(size_t)(const __attribute__((address_space(3))) uint4*)p;
+    u32x4 x, y;
+    u32x2 z;
+    __asm__ volatile(
+        "ds_read_b128 %0, %3\n\t"
+        "ds_read_b128 %1, %3 offset:1024\n\t"
+        "ds_read_b64 %2, %3 offset:2048\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(x), "=&v"(y), "=&v"(z)
+        : "v"(a)
+        : "memory");
+    r0 = make_uint4(x.x, x.y, x.z, x.w);
+    r1 = make_uint4(y.x, y.y, y.z, y.w);
+    r2 = make_uint2(z.x, z.y);
+}
+__device__ __forceinline__ void read_staged_pair(const float* p, float& u, float& v) {
+    static_assert(kTile * sizeof(float) == 256, "stride in the offset below");
+    const unsigned a = (unsigned)(size_t)(const __attribute__((address_space(3))) float*)p;
+    __asm__ volatile(
+        "ds_read_b32 %0, %2\n\t"
+        "ds_read_b32 %1, %2 offset:256\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(u), "=&v"(v)
+        : "v"(a)
+        : "memory");
 }
 
 __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p) {
@@ -933,10 +986,14 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
     __shared__ __attribute__((aligned(16))) uint32_t opL[3 * kTile][kF16PreDw];
     __shared__ double psum[2][kTile];          // -gamma p_k (k side), p_l (l side)
     __shared__ double sc2[2][kTile];           // s_k^2, s_l^2
-    // The next chunk's records as copied: [side][value][piece][column] and
-    // [side][p, s^2][column].
-    __shared__ __attribute__((aligned(16))) uint4 stg[2][3][kOpPieces][kTile];
-    __shared__ __attribute__((aligned(16))) float stgp[2][2][kTile];
+    // Two chunks' records as copied, [side][value][piece][column] and
+    // [side][p, s^2][column]: even chunks of a piece in the A buffers, odd
+    // ones in the B buffers (distinct arrays, so that reading one never waits
+    // for the copies into the other).
+    __shared__ __attribute__((aligned(16))) uint4 stgA[2][3][kOpPieces][kTile];
+    __shared__ __attribute__((aligned(16))) uint4 stgB[2][3][kOpPieces][kTile];
+    __shared__ __attribute__((aligned(16))) float stgpA[2][2][kTile];
+    __shared__ __attribute__((aligned(16))) float stgpB[2][2][kTile];
 
     Block bk;
     View v;
@@ -970,36 +1027,60 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
     const int k0 = it.k0, l0 = it.l0;
     const uint4* base = reinterpret_cast<const uint4*>(p.op4 + it.ch[0] * sg.op4_cs + sg.op4);
     const float* pbase = p.p4 + it.ch[0] * sg.p4_cs + sg.p4;
-    // Copy of chunk c into the staging buffers: 18 record copies (side,
-    // value, piece) and 4 p / s^2 copies of 64 columns, dealt over the waves.
-    auto copy_chunk = [&](int c) {
-        const uint4* rc = base + (cbase + c) * cunits + lane;
-        for (int q = wv; q < 2 * 3 * kOpPieces; q += 4) {
+    // Copy of chunk c into staging buffers: 18 record copies (side, value,
+    // piece) and 4 p / s^2 copies of 64 columns, dealt over the waves.  Every
+    // wave issues the same straight-line six copies (waves 2, 3 repeat one
+    // record copy of theirs: same bytes to the same place), so that the
+    // number of copies in flight behind a chunk is a constant.
+    using Stg = uint4[2][3][kOpPieces][kTile];
+    using StgP = float[2][2][kTile];
+    constexpr int kCopiesPerChunk = 6;
+    // (addresses: a wave-uniform part plus the lane's 32-bit byte offset)
+    const uint32_t lane16 = 16u * lane, lane4 = 4u * lane;
+    auto copy_chunk = [&](Stg& stg, StgP& stgp, int c) {
+        const uint4* rc = base + (cbase + c) * cunits;
+#pragma unroll
+        for (int j = 0; j < kCopiesPerChunk - 1; ++j) {
+            int q = wv + 4 * j;
+            q = q < 2 * 3 * kOpPieces ? q : q - 4;
             const int side = q / (3 * kOpPieces), vp = q % (3 * kOpPieces);
-            copy_to_lds16(rc + (int64_t)vp * ngp + (side ? l0 : k0), &stg[side][0][0][0] + vp * kTile);
+            const char* g = reinterpret_cast<const char*>(rc + (int64_t)vp * ngp + (side ? l0 : k0));
+            copy_to_lds16(g + lane16, &stg[side][0][0][0] + vp * kTile);
         }
-        const float* pc = pbase + (cbase + c) * 2 * ngp + lane;
         const int side = wv >> 1, comp = wv & 1;
-        copy_to_lds4(pc + comp * ngp + (side ? l0 : k0), &stgp[side][comp][0]);
+        const char* g = reinterpret_cast<const char*>(pbase + (cbase + c) * 2 * ngp + comp * ngp + (side ? l0 : k0));
+        copy_to_lds4(g + lane4, &stgp[side][comp][0]);
+    };
+    // Barrier after which chunk c's copies have landed: each wave waits until
+    // at most the next chunk's copies are outstanding (copies complete in
+    // order).  Copies are issued unconditionally, the ones past the piece's
+    // last chunk repeating that chunk into a free buffer, so that the count
+    // is the same on every path.
+    // s_waitcnt: vmcnt in bits 3:0, lgkmcnt(0), expcnt field left at 7.
+    static_assert(kCopiesPerChunk == 6, "the vmcnt below counts six copies per chunk");
+    auto landed_barrier = [&]() {
+        __builtin_amdgcn_s_waitcnt(0x0076);                            // vmcnt(6)
+        lds_sync();
     };
 
     double acc[16][2];
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r][0] = acc[r][1] = 0.0;
 
-    // (the previous piece's last chunk may still be read from the rows)
-    lds_barrier();
-    copy_chunk(c0);
     floatx16_t d[5];
-#pragma unroll 1
-    for (int c = c0; c < c1; ++c) {
-        copies_barrier();                              // the copy of chunk c has landed
+    // Chunk c of the piece from the staging buffers stg, stgp: its rows, then
+    // (the buffers free again) the copy of chunk c + 2 into them, the
+    // contractions and the combination.
+    auto step = [&](Stg& stg, StgP& stgp, int c) {
+        landed_barrier();                              // the copy of chunk c has landed
         // Record words [0, 5) h, [5, 10) l of frames 0..9: rec[0] = h0..h3,
         // rec[1] = h4 l0 l1 l2, rec[2] = l3 l4 0 0.  A row is written as four
         // 16-byte groups (at the 20-word row stride the 16 lanes of each LDS
         // cycle cover all banks once); word 15 holds the zero slots 30, 31.
         if (ldK) {                                             // [h h l]
-            const uint4 r0 = stg[0][valK][0][colK], r1 = stg[0][valK][1][colK], r2 = stg[0][valK][2][colK];
+            uint4 r0, r1;
+            uint2 r2;
+            read_staged_record(&stg[0][valK][0][colK], r0, r1, r2);
             uint4* row = reinterpret_cast<uint4*>(opK[rK]);
             row[0] = r0;
             row[1] = make_uint4(r1.x, r0.x, r0.y, r0.z);
@@ -1007,22 +1088,24 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
             row[3] = make_uint4(r1.w, r2.x, r2.y, 0u);
         }
         if (ldL) {                                             // [h l h]
-            const uint4 r0 = stg[1][valL][0][colL], r1 = stg[1][valL][1][colL], r2 = stg[1][valL][2][colL];
+            uint4 r0, r1;
+            uint2 r2;
+            read_staged_record(&stg[1][valL][0][colL], r0, r1, r2);
             uint4* row = reinterpret_cast<uint4*>(opL[rL]);
             row[0] = r0;
             row[1] = r1;
             row[2] = make_uint4(r2.x, r2.y, r0.x, r0.y);
             row[3] = make_uint4(r0.z, r0.w, r1.x, 0u);
         }
-        if (wv == 0) {
-            psum[0][lane] = -gamma * (double)stgp[0][0][lane];
-            sc2[0][lane] = (double)stgp[0][1][lane];
-        } else if (wv == 3) {
-            psum[1][lane] = (double)stgp[1][0][lane];
-            sc2[1][lane] = (double)stgp[1][1][lane];
+        if (wv == 0 || wv == 3) {                              // wave 0: k side, wave 3: l side
+            const int side = wv == 3;
+            float pv, s2;
+            read_staged_pair(&stgp[side][0][lane], pv, s2);
+            psum[side][lane] = (side ? 1.0 : -gamma) * (double)pv;
+            sc2[side][lane] = (double)s2;
         }
-        lds_barrier();                                 // rows ready, staging free
-        if (c + 1 < c1) copy_chunk(c + 1);
+        lds_sync_rows();                               // rows ready, staging free
+        copy_chunk(stg, stgp, min(c + 2, c1 - 1));
         // Two K steps of 16 slots (the scheduling barrier keeps each step's
         // operand reads next to its contractions: fewer live registers).
 #pragma unroll
@@ -1065,6 +1148,19 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
             acc[r][0] += val;
             acc[r][1] = fma(val, val, acc[r][1]);
         }
+    };
+
+    // (every wave is done with the previous piece's rows and staging, and has
+    // no memory access of its own in flight: the counts waited for below are
+    // then the copies' alone)
+    copies_barrier();
+    copy_chunk(stgA, stgpA, c0);
+    copy_chunk(stgB, stgpB, min(c0 + 1, c1 - 1));
+    int c = c0;
+#pragma unroll 1
+    for (; c < c1; c += 2) {
+        step(stgA, stgpA, c);
+        if (c + 1 < c1) step(stgB, stgpB, c + 1);
     }
 
     double* o = it.part;
