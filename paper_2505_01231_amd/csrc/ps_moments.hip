@@ -1136,13 +1136,16 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
 
         // Register r of lane (kh, r32) is grid point
         // k = k0 + 32 (w / 2) + 8 (r / 4) + 4 kh + r % 4, l = l0 + 32 (w % 2) + r32.
-        // The k-statistic combination in FP64.
+        // The k-statistic combination in FP64.  The sum of the four squares
+        // (no cancellation: positive terms, like M4 itself a sum of
+        // positive FP32 terms) is formed in FP32; the cancellation between
+        // M4, the squares and p_k p_l happens in FP64.
         const double pl = psum[1][rowL], sl2 = sc2[1][rowL];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int kr = 32 * (w >> 1) + 8 * (r >> 2) + 4 * kh + (r & 3);
-            const double X = d[0][r], U = d[1][r], V = d[2][r], Y = d[3][r];
-            const double sq = fma(X, X, fma(Y, Y, fma(U, U, V * V)));
+            const float X = d[0][r], U = d[1][r], V = d[2][r], Y = d[3][r];
+            const double sq = fmaf(X, X, fmaf(Y, Y, fmaf(U, U, V * V)));
             const double sig = sc2[0][kr] * sl2;
             const double val = fma(sig, fma(m2g, sq, (double)d[4][r]), psum[0][kr] * pl);
             acc[r][0] += val;
