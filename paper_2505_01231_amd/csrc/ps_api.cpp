@@ -306,8 +306,9 @@ struct BatchClass {
     int64_t rows = 0, rows3 = 0;    // rows per channel of its blocks
     size_t coef_off = 0, coef3_off = 0;     // byte offsets in the workspace
     // pre-split S4 operands: chunk slots per channel, byte offsets of the
-    // operand records [C][op_chunks][3][kOpPieces][N_f'][4] and the P sums and
-    // scales [C][op_chunks][2][N_f'] (N_f' = N_f rounded up to the tile edge)
+    // operand records [C][op_chunks][3][kOpPieces][N_f'][4] and the FP64
+    // (P sum, scale s^2) pairs [C][op_chunks][N_f'][2] (N_f' = N_f rounded up
+    // to the tile edge)
     int64_t op_chunks = 0;
     size_t op4_off = 0, p4_off = 0;
     int rd0 = 0, n_rd = 0;          // its record descriptors in Batch.rd
@@ -466,7 +467,7 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
         k.op4_off = off;
         off = align256(off + (size_t)p->C * k.op_chunks * 3 * ng * ps::kOpWords * sizeof(uint32_t));
         k.p4_off = off;
-        off = align256(off + (size_t)p->C * k.op_chunks * 2 * ng * sizeof(float));
+        off = align256(off + (size_t)p->C * k.op_chunks * 2 * ng * sizeof(double));
     }
     B.coef_bytes = off;
 
@@ -598,7 +599,7 @@ void build_batch(const ps_plan_s* p, const ps_record* recs, int n, const ps_outp
                     const int64_t rec = 3 * ngp * ps::kOpWords;       // uint32 per chunk
                     sg.op4 = (int64_t)(k.op4_off / sizeof(uint32_t)) + (per_chunk ? 0 : q.chunk0c * rec);
                     sg.op4_cs = k.op_chunks * rec;
-                    sg.p4 = (int64_t)(k.p4_off / sizeof(float)) + (per_chunk ? 0 : q.chunk0c * 2 * ngp);
+                    sg.p4 = (int64_t)(k.p4_off / sizeof(double)) + (per_chunk ? 0 : q.chunk0c * 2 * ngp);
                     sg.p4_cs = k.op_chunks * 2 * ngp;
                 }
                 sg.part = part;
@@ -1298,7 +1299,7 @@ ps_status launch_moments(ps_plan_t p, const Batch& B, const Group& G, char* ws, 
         ps::BatchArgs a = batch_args(p, B, G.s4s, ws, tab, per_chunk, win_lo, win_hi, accumulate);
         if (p->s4_pre) {                // operands split by the centring pass
             a.op4 = reinterpret_cast<const uint32_t*>(ws);
-            a.p4 = reinterpret_cast<const float*>(ws);
+            a.p4 = reinterpret_cast<const double*>(ws);
         }
         if (p->precision == PS_PREC_FP32) {
             PS_HIP(ps::launch_s4_single(a, st));
@@ -1419,7 +1420,7 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
             const int ngp = op_cols(fc.Ng);
             c.op4 = reinterpret_cast<uint32_t*>(ws + k.op4_off);
             c.op4_cs = k.op_chunks * 3 * (int64_t)ngp * ps::kOpWords;
-            c.p4 = reinterpret_cast<float*>(ws + k.p4_off);
+            c.p4 = reinterpret_cast<double*>(ws + k.p4_off);
             c.p4_cs = k.op_chunks * 2 * (int64_t)ngp;
             c.op4_cols = ngp;
         }

@@ -525,8 +525,8 @@ __device__ __forceinline__ uint32_t f16_pair(float lo, float hi) {
 
 // The operand records of the matrix-core S4 kernel for one column of one
 // chunk (see kOpWords): piece i of value v (Re, Im, P) of column k at the
-// 16-byte unit (3 v + i) op4_cols + k of the chunk's block, and p = sum_f P,
-// s^2 at p4[chunk][0][k], p4[chunk][1][k].  v holds the chunk's m <= kOpFrames
+// 16-byte unit (3 v + i) op4_cols + k of the chunk's block, and the pair
+// (p = sum_f P, s^2) at p4[chunk][k].  v holds the chunk's m <= kOpFrames
 // uncentred values; a column without coefficients (k >= K, padding up to
 // op4_cols) gets zero records, p = 0 and s = 1.
 __device__ __forceinline__ void write_op_records(const CentreClass& cl, int64_t chunk, int k, int m,
@@ -546,7 +546,7 @@ __device__ __forceinline__ void write_op_records(const CentreClass& cl, int64_t 
     float psum = 0.f;
 #pragma unroll
     for (int val = 0; val < 3; ++val) {
-        uint32_t w[kOpWords];
+        uint32_t w[10];
 #pragma unroll
         for (int f = 0; f < kOpFrames; f += 2) {
             float x[2], l[2];
@@ -560,15 +560,13 @@ __device__ __forceinline__ void write_op_records(const CentreClass& cl, int64_t 
             w[f >> 1] = f16_pair(x[0], x[1]);
             w[5 + (f >> 1)] = f16_pair(l[0], l[1]);
         }
-        w[10] = w[11] = 0u;
         uint4* dst = rec + val * kOpPieces * ngp;
-        dst[0] = make_uint4(w[0], w[1], w[2], w[3]);
-        dst[ngp] = make_uint4(w[4], w[5], w[6], w[7]);
-        dst[2 * ngp] = make_uint4(w[8], w[9], w[10], w[11]);
+        dst[0] = make_uint4(w[0], w[1], w[2], w[3]);                // H: h words 0..3
+        dst[ngp] = make_uint4(w[5], w[6], w[7], w[8]);              // L: l words 0..3
+        dst[2 * ngp] = make_uint4(w[4], w[9], 0u, 0u);              // T: h word 4, l word 4
     }
-    float* pp = cl.p4 + blockIdx.y * cl.p4_cs + chunk * 2 * ngp + k;
-    pp[0] = psum;
-    pp[ngp] = s * s;
+    double2* pp = reinterpret_cast<double2*>(cl.p4 + blockIdx.y * cl.p4_cs + chunk * 2 * ngp) + k;
+    *pp = make_double2((double)psum, (double)(s * s));
 }
 
 // Grid: x = the classes' (chunk, 256-wide k block) pairs, chunk-major within

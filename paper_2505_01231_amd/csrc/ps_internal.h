@@ -97,12 +97,12 @@ __host__ __device__ constexpr int fft_twiddle_count(int log2n) {
 // chunk and column, a power of two s > max_f (|Re a'|, |Im a'|) over the
 // chunk's frames, and each of the values Re a' / s, Im a' / s, P / s^2
 // (P = |a'|^2) of frames 0..9 split into two float16 terms x = h + l
-// (h = fp16(x), l = fp16(x - h), both rounded to nearest).  A value's record
-// is kOpWords 32-bit words: 0..4 the h terms (two frames per word, the earlier
-// frame in the low half), 5..9 the l terms, 10..11 zero; frames >= m are zero.
-// It is stored as kOpPieces 16-byte pieces (words 4i..4i+3), piece-major over
-// the columns, and the column count is padded to a multiple of the 64-wide
-// tile with zero records (op4_cols).
+// (h = fp16(x), l = fp16(x - h), both rounded to nearest).  Two frames make a
+// 32-bit word (the earlier frame in the low half): h words 0..4, l words
+// 0..4.  A value's record is kOpPieces 16-byte pieces, H = h words 0..3,
+// L = l words 0..3, T = (h word 4, l word 4, 0, 0), frames >= m zero, stored
+// piece-major over the columns; the column count is padded to a multiple of
+// the 64-wide tile with zero records (op4_cols).
 constexpr int kOpFrames = 10;
 constexpr int kOpPieces = 3;
 constexpr int kOpWords = 4 * kOpPieces;
@@ -137,8 +137,8 @@ struct CentreClass {
     // records, p = 0, s = 1).
     uint32_t* op4;          // [C][n_chunks][3][kOpPieces][op4_cols][4]
     int64_t op4_cs;         // uint32 elements between channels
-    float* p4;              // [C][n_chunks][2][op4_cols]: p, then s^2
-    int64_t p4_cs;
+    double* p4;             // [C][n_chunks][op4_cols][2]: (p, s^2) per column
+    int64_t p4_cs;          // double elements between channels
     int op4_cols;
     int64_t block0;         // first block of the class
 };
@@ -195,7 +195,7 @@ struct Seg {
     int64_t coef;           // float2 offset of the record's chunk 0 in the coefficient region
     int64_t cs;             // float2 elements between channels of the record's coefficient block
     int64_t op4, op4_cs;    // S4 operand records of the record's chunk 0 (uint32 offset), channel stride
-    int64_t p4, p4_cs;      // and its column sums of P and scales s^2 (float offset), channel stride
+    int64_t p4, p4_cs;      // and its (column sum of P, scale s^2) pairs (double offset), channel stride
     const int2* tile_tab;   // the grid's tile table (tile t -> (kt, lt)); by `tiles` and the grid size
     int32_t K;              // coefficients per frame of the record's frame length
     int32_t Nf;             // points per grid axis of the record's spectra
@@ -223,7 +223,7 @@ struct BatchArgs {
     int64_t n_items;
     const float2* coef;     // coefficient region
     const uint32_t* op4;    // S4 operand records (pre-split; null: the S4 kernel splits)
-    const float* p4;
+    const double* p4;
     double* part;           // partial-sum region
     int m;                  // rows per chunk
     int col0;               // column of grid index 0 for the first factors (see View)

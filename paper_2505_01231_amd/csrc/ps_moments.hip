@@ -888,112 +888,126 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16(BatchArgs p) {
 // ------------------------------------------------------------------ S4, one channel, matrix cores, scaled FP16 x 2, pre-split operands
 // The sums of k_s4_mfma_f16 from the operand records the centring pass writes
 // (see kOpWords): per chunk and column a power of two s, the values scaled by
-// s (P by s^2) and split in two float16 terms x = h + l.  The K dimension of
-// one chunk holds three blocks of ten frame slots, the products h.h, h.l,
-// l.h: the k-side row [h h l] and the l-side row [h l h] of term blocks (30 of
-// 32 slots; 30, 31 zero), so one contraction over the row gives the frame sum
-// h_k h_l + h_k l_l + l_k h_l of each Gram sum.  v_mfma_f32_32x32x16_f16 on
-// 64 x 64 tiles, four waves of 32 x 32; building a row is a copy of term
-// blocks from the record into LDS.  The records of chunk c + 1 travel from
-// memory into an LDS staging area by asynchronous copies while chunk c is
-// contracted and combined (no registers held across).
+// s (P by s^2) and split in two float16 terms x = h + l, stored as the pieces
+// H = h words 0..3, L = l words 0..3, T = (h word 4, l word 4, 0, 0) (a word
+// holds two frames).  Each frame sum h_k h_l + h_k l_l + l_k h_l is one
+// contraction of two K steps of v_mfma_f32_32x32x16_f16; the lanes of the
+// lower and upper K half (kh) of step ks pair the k-side and l-side words
+//   ks 0:  kh 0: H_k . H_l      kh 1: H_k . L_l
+//   ks 1:  kh 0: L_k . H_l      kh 1: (h4 l4 h4 0)_k . (h4 h4 l4 0)_l
+// so every operand is a staged piece read as it is (the lane picks the piece
+// by its kh), or for kh 1 of step 1 a piece with one or two words taken from
+// another lane half's position (a select per word).  64 x 64 tiles, four
+// waves of 32 x 32.
+//
+// The records and the (p, s^2) pairs of a chunk travel from memory into one
+// of kS4Stages LDS staging buffers by asynchronous copies issued
+// kS4Stages - 1 chunks ahead; one workgroup barrier per chunk both publishes
+// the chunk's copies and frees the buffer the previous chunk was read from.
+// Staging reads are LDS reads in inline assembly with their wait in the same
+// statement (see read_lds_b128x): the compiler's own wait for copies in
+// flight cannot tell the buffers apart and would drain all of them.
 //
 // With the scale sigma = s_k^2 s_l^2 (exact) of the point, M4 and
 // X^2 + Y^2 + U^2 + V^2 of the scaled values are both sigma times the
 // unscaled ones, so the chunk's term is
 //   v = sigma (M4' - 2 gamma (X'^2 + Y'^2 + U'^2 + V'^2)) - gamma p_k p_l,
-// formed in FP64 (p = sum_f P unscaled, FP32 from the centring pass).
-constexpr int kF16PreDw = 20;          // 32-bit words per LDS operand row (80 B; 16 used)
+// formed in FP64 (p = sum_f P unscaled, FP32 from the centring pass, stored
+// as FP64 with s^2); the sum of the four squares, positive terms, in FP32.
 
-// Asynchronous copy of 16 (or 4) bytes per lane from global memory into LDS:
-// lane i writes lds + i * bytes (lds uniform over the wave); completion is
-// counted like a global load.  LDS reads of other arrays need not wait for
-// it (the compiler tells the targets apart by their arrays).
+// Asynchronous copy of 16 bytes per lane from global memory into LDS: lane i
+// writes lds + 16 i (lds uniform over the wave); completion is counted like a
+// global load, in issue order.
 __device__ __forceinline__ void copy_to_lds16(const void* g, void* lds) {
     __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
                                      (void __attribute__((address_space(3)))*)lds, 16, 0, 0);
 }
-__device__ __forceinline__ void copy_to_lds4(const void* g, void* lds) {
-    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
-                                     (void __attribute__((address_space(3)))*)lds, 4, 0, 0);
-}
 
-// Workgroup barrier after which the copies every wave has issued into LDS
-// have landed: each wave first waits for its own copies (vmcnt, which the
-// compiler does not always add for a copy issued in the previous trip of a
-// loop) and LDS accesses (lgkmcnt).  s_waitcnt fields on this target:
-// vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
-// Workgroup barrier for kernels with several copies in flight: the wave's
-// LDS accesses are complete (lgkmcnt) but its copies may still be running;
-// the empty asm statements keep the compiler from moving memory accesses
-// across (and from adding a wait for the copies, as the LDS fence of
-// lds_barrier can).  lds_sync: the caller has already waited as needed.
+// Workgroup barrier with copies still in flight: the caller has waited for
+// what it needs; the empty asm statements keep the compiler from moving
+// memory accesses across (and from adding a wait for the copies, as the LDS
+// fence of lds_barrier can).
 __device__ __forceinline__ void lds_sync() {
     __asm__ volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     __asm__ volatile("" ::: "memory");
 }
-__device__ __forceinline__ void lds_sync_rows() {
-    __builtin_amdgcn_s_waitcnt(0xC07F);        // lgkmcnt(0); vmcnt, expcnt at their maximum
-    lds_sync();
-}
+// Workgroup barrier after which every memory access the waves issued,
+// copies included, is complete.  s_waitcnt fields on this target: vmcnt bits
+// 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8.
 __device__ __forceinline__ void copies_barrier() {
     __builtin_amdgcn_s_waitcnt(0x0070);        // vmcnt(0) lgkmcnt(0)
     lds_barrier();
 }
 
-// Reads of a staging buffer filled by asynchronous copies whose completion
-// the caller has established (its own wait on the copy count, then a
-// workgroup barrier).  Written as LDS reads in inline assembly, with their
-// wait in the same statement, because the compiler's own wait for copies in
-// flight cannot tell the two staging buffers apart and would wait for the
-// copies into the other buffer too.  read_staged_record: the three 16-byte
-// pieces of a record at a stride of kTile records (the third piece's first
-// 8 bytes); read_staged_pair: two floats at a stride of kTile floats.
-__device__ __forceinline__ void read_staged_record(const uint4* p, uint4& r0, uint4& r1, uint2& r2) {
-    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
-    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-    static_assert(kTile * sizeof(uint4) == 1024, "piece stride in the offsets below");
-    const unsigned a = (unsigned)(size_t)(const __attribute__((address_space(3))) uint4*)p;
-    u32x4 x, y;
-    u32x2 z;
+typedef unsigned u32x4_v __attribute__((ext_vector_type(4)));
+// N 16-byte LDS reads from the lane's addresses a[i] (byte offsets in LDS,
+// 16-byte aligned) into x[i], complete when the statement ends.
+template <int N>
+__device__ __forceinline__ void read_lds_b128x(const unsigned (&a)[N], u32x4_v (&x)[N]);
+template <>
+__device__ __forceinline__ void read_lds_b128x<4>(const unsigned (&a)[4], u32x4_v (&x)[4]) {
     __asm__ volatile(
-        "ds_read_b128 %0, %3\n\t"
-        "ds_read_b128 %1, %3 offset:1024\n\t"
-        "ds_read_b64 %2, %3 offset:2048\n\t"
+        "ds_read_b128 %0, %4\n\t"
+        "ds_read_b128 %1, %5\n\t"
+        "ds_read_b128 %2, %6\n\t"
+        "ds_read_b128 %3, %7\n\t"
         "s_waitcnt lgkmcnt(0)"
-        : "=&v"(x), "=&v"(y), "=&v"(z)
-        : "v"(a)
+        : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3])
+        : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3])
         : "memory");
-    r0 = make_uint4(x.x, x.y, x.z, x.w);
-    r1 = make_uint4(y.x, y.y, y.z, y.w);
-    r2 = make_uint2(z.x, z.y);
 }
-__device__ __forceinline__ void read_staged_pair(const float* p, float& u, float& v) {
-    static_assert(kTile * sizeof(float) == 256, "stride in the offset below");
-    const unsigned a = (unsigned)(size_t)(const __attribute__((address_space(3))) float*)p;
+template <>
+__device__ __forceinline__ void read_lds_b128x<5>(const unsigned (&a)[5], u32x4_v (&x)[5]) {
     __asm__ volatile(
-        "ds_read_b32 %0, %2\n\t"
-        "ds_read_b32 %1, %2 offset:256\n\t"
+        "ds_read_b128 %0, %5\n\t"
+        "ds_read_b128 %1, %6\n\t"
+        "ds_read_b128 %2, %7\n\t"
+        "ds_read_b128 %3, %8\n\t"
+        "ds_read_b128 %4, %9\n\t"
         "s_waitcnt lgkmcnt(0)"
-        : "=&v"(u), "=&v"(v)
-        : "v"(a)
+        : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3]), "=&v"(x[4])
+        : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4])
+        : "memory");
+}
+template <>
+__device__ __forceinline__ void read_lds_b128x<12>(const unsigned (&a)[12], u32x4_v (&x)[12]) {
+    __asm__ volatile(
+        "ds_read_b128 %0, %12\n\t"
+        "ds_read_b128 %1, %13\n\t"
+        "ds_read_b128 %2, %14\n\t"
+        "ds_read_b128 %3, %15\n\t"
+        "ds_read_b128 %4, %16\n\t"
+        "ds_read_b128 %5, %17\n\t"
+        "ds_read_b128 %6, %18\n\t"
+        "ds_read_b128 %7, %19\n\t"
+        "ds_read_b128 %8, %20\n\t"
+        "ds_read_b128 %9, %21\n\t"
+        "ds_read_b128 %10, %22\n\t"
+        "ds_read_b128 %11, %23\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3]), "=&v"(x[4]), "=&v"(x[5]),
+          "=&v"(x[6]), "=&v"(x[7]), "=&v"(x[8]), "=&v"(x[9]), "=&v"(x[10]), "=&v"(x[11])
+        : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]),
+          "v"(a[6]), "v"(a[7]), "v"(a[8]), "v"(a[9]), "v"(a[10]), "v"(a[11])
         : "memory");
 }
 
+__device__ __forceinline__ unsigned lds_addr(const void* p) {
+    return (unsigned)(size_t)(const __attribute__((address_space(3))) char*)p;
+}
+
+constexpr int kS4Stages = 3;            // staging buffers: copies kS4Stages - 1 chunks ahead
+constexpr int kS4CopiesPerWave = 5;     // copies per wave and chunk (see copy_chunk)
+
+// One chunk's staged operands of a 64 x 64 tile.
+struct S4Stage {
+    uint4 rec[2][3][kOpPieces][kTile];  // [side k, l][value Re, Im, P][piece H, L, T][column]
+    double2 pw[2][kTile];               // [side][column]: (p, s^2)
+};
+
 __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p) {
-    __shared__ __attribute__((aligned(16))) uint32_t opK[3 * kTile][kF16PreDw];
-    __shared__ __attribute__((aligned(16))) uint32_t opL[3 * kTile][kF16PreDw];
-    __shared__ double psum[2][kTile];          // -gamma p_k (k side), p_l (l side)
-    __shared__ double sc2[2][kTile];           // s_k^2, s_l^2
-    // Two chunks' records as copied, [side][value][piece][column] and
-    // [side][p, s^2][column]: even chunks of a piece in the A buffers, odd
-    // ones in the B buffers (distinct arrays, so that reading one never waits
-    // for the copies into the other).
-    __shared__ __attribute__((aligned(16))) uint4 stgA[2][3][kOpPieces][kTile];
-    __shared__ __attribute__((aligned(16))) uint4 stgB[2][3][kOpPieces][kTile];
-    __shared__ __attribute__((aligned(16))) float stgpA[2][2][kTile];
-    __shared__ __attribute__((aligned(16))) float stgpB[2][2][kTile];
+    __shared__ __attribute__((aligned(16))) S4Stage stage[kS4Stages];
 
     Block bk;
     View v;
@@ -1004,166 +1018,170 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
     const int r32 = lane & 31, kh = lane >> 5;
     const int rowK = 32 * (w >> 1) + r32, rowL = 32 * (w & 1) + r32;
     const int wv = __builtin_amdgcn_readfirstlane(w);
-
-    // Row builders, uniform per wave: thread t < 192 (waves 0-2) builds
-    // k-side row t (value t / 64, column t % 64), thread t >= 64 (waves 1-3)
-    // builds l-side row t - 64; wave 0 stages p, s^2 of the k side, wave 3
-    // those of the l side.
-    const bool ldK = wv < 3, ldL = wv >= 1;
-    const int rK = tid, rL = tid - kTile;
-    const int valK = rK / kTile, colK = rK % kTile, valL = rL / kTile, colL = rL % kTile;
     const double gamma = p.gamma;
     const double m2g = -2.0 * gamma;
     // Records: 3 kOpWords ngp words per chunk; value v, piece i of column k
-    // is the 16-byte unit (3 v + i) ngp + k of the chunk's block.
+    // is the 16-byte unit (3 v + i) ngp + k of the chunk's block; the (p, s^2)
+    // pairs: ngp per chunk.
     const int64_t ngp = (int64_t)(v.Nf + kTile - 1) / kTile * kTile;
     const int64_t cunits = 3 * kOpPieces * ngp;                    // 16-byte units per chunk
     const int64_t cbase = p.per_chunk ? -(int64_t)p.win_lo : 0;   // per-chunk schedule: chunk win_lo at 0
+    const uint32_t lane16 = 16u * lane;
+
+    // Lane addresses of its operands and pair values in stage 0 (a stage is
+    // sizeof(S4Stage) further): step 0 reads piece H of its k-side column
+    // and piece H (kh 0) or L (kh 1) of its l-side column, step 1 piece L or
+    // T of the k side and H or T of the l side, each for Re, Im, P.
+    const unsigned aK0 = lds_addr(&stage[0].rec[0][0][0][rowK]);
+    const unsigned aK1 = lds_addr(&stage[0].rec[0][0][1 + kh][rowK]);
+    const unsigned aL0 = lds_addr(&stage[0].rec[1][0][kh][rowL]);
+    const unsigned aL1 = lds_addr(&stage[0].rec[1][0][2 * kh][rowL]);
+    constexpr unsigned kValBytes = kOpPieces * kTile * sizeof(uint4);
+    const unsigned aPk = lds_addr(&stage[0].pw[0][32 * (w >> 1) + 4 * kh]);
+    const unsigned aPl = lds_addr(&stage[0].pw[1][rowL]);
+    static_assert(sizeof(S4Stage) % 16 == 0, "stage alignment");
 
     Item it;
     while (next_item<kTile, 2>(p, bk, it)) {
     const Seg& sg = *bk.s;
-    const int c0 = it.c0, c1 = it.c1;
+    const int c0 = it.c0, c1 = it.c1;          // c1 > c0: pieces are never empty
     const int k0 = it.k0, l0 = it.l0;
     const uint4* base = reinterpret_cast<const uint4*>(p.op4 + it.ch[0] * sg.op4_cs + sg.op4);
-    const float* pbase = p.p4 + it.ch[0] * sg.p4_cs + sg.p4;
-    // Copy of chunk c into staging buffers: 18 record copies (side, value,
-    // piece) and 4 p / s^2 copies of 64 columns, dealt over the waves.  Every
-    // wave issues the same straight-line six copies (waves 2, 3 repeat one
-    // record copy of theirs: same bytes to the same place), so that the
-    // number of copies in flight behind a chunk is a constant.
-    using Stg = uint4[2][3][kOpPieces][kTile];
-    using StgP = float[2][2][kTile];
-    constexpr int kCopiesPerChunk = 6;
-    // (addresses: a wave-uniform part plus the lane's 32-bit byte offset)
-    const uint32_t lane16 = 16u * lane, lane4 = 4u * lane;
-    auto copy_chunk = [&](Stg& stg, StgP& stgp, int c) {
+    const double2* pbase = reinterpret_cast<const double2*>(p.p4 + it.ch[0] * sg.p4_cs + sg.p4);
+
+    // Copy of chunk c into stage b: 18 record copies (side, value, piece) and
+    // the two sides' (p, s^2) pairs, 64 columns of 16 bytes each; wave wv
+    // issues records wv, wv + 4, wv + 8, wv + 12, then record 16 + wv (waves
+    // 0, 1) or side wv - 2's pairs (waves 2, 3): kS4CopiesPerWave each.
+    // Copies past the piece's last chunk repeat it (into a buffer no step
+    // reads), so that every path issues the same copies.
+    auto copy_chunk = [&](int b, int c) {
+        c = min(c, c1 - 1);
+        S4Stage& st = stage[b];
         const uint4* rc = base + (cbase + c) * cunits;
 #pragma unroll
-        for (int j = 0; j < kCopiesPerChunk - 1; ++j) {
-            int q = wv + 4 * j;
-            q = q < 2 * 3 * kOpPieces ? q : q - 4;
+        for (int j = 0; j < 4; ++j) {
+            const int q = wv + 4 * j;
             const int side = q / (3 * kOpPieces), vp = q % (3 * kOpPieces);
             const char* g = reinterpret_cast<const char*>(rc + (int64_t)vp * ngp + (side ? l0 : k0));
-            copy_to_lds16(g + lane16, &stg[side][0][0][0] + vp * kTile);
+            copy_to_lds16(g + lane16, &st.rec[side][0][0][0] + vp * kTile);
         }
-        const int side = wv >> 1, comp = wv & 1;
-        const char* g = reinterpret_cast<const char*>(pbase + (cbase + c) * 2 * ngp + comp * ngp + (side ? l0 : k0));
-        copy_to_lds4(g + lane4, &stgp[side][comp][0]);
-    };
-    // Barrier after which chunk c's copies have landed: each wave waits until
-    // at most the next chunk's copies are outstanding (copies complete in
-    // order).  Copies are issued unconditionally, the ones past the piece's
-    // last chunk repeating that chunk into a free buffer, so that the count
-    // is the same on every path.
-    // s_waitcnt: vmcnt in bits 3:0, lgkmcnt(0), expcnt field left at 7.
-    static_assert(kCopiesPerChunk == 6, "the vmcnt below counts six copies per chunk");
-    auto landed_barrier = [&]() {
-        __builtin_amdgcn_s_waitcnt(0x0076);                            // vmcnt(6)
-        lds_sync();
+        if (wv < 2) {
+            const int vp = 7 + wv;                             // records 16, 17: l side, value 2, pieces 1, 2
+            const char* g = reinterpret_cast<const char*>(rc + (int64_t)vp * ngp + l0);
+            copy_to_lds16(g + lane16, &st.rec[1][0][0][0] + vp * kTile);
+        } else {
+            const int side = wv - 2;
+            const char* g = reinterpret_cast<const char*>(pbase + (cbase + c) * ngp + (side ? l0 : k0));
+            copy_to_lds16(g + lane16, &st.pw[side][0]);
+        }
     };
 
     double acc[16][2];
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r][0] = acc[r][1] = 0.0;
 
-    floatx16_t d[5];
-    // Chunk c of the piece from the staging buffers stg, stgp: its rows, then
-    // (the buffers free again) the copy of chunk c + 2 into them, the
-    // contractions and the combination.
-    auto step = [&](Stg& stg, StgP& stgp, int c) {
-        landed_barrier();                              // the copy of chunk c has landed
-        // Record words [0, 5) h, [5, 10) l of frames 0..9: rec[0] = h0..h3,
-        // rec[1] = h4 l0 l1 l2, rec[2] = l3 l4 0 0.  A row is written as four
-        // 16-byte groups (at the 20-word row stride the 16 lanes of each LDS
-        // cycle cover all banks once); word 15 holds the zero slots 30, 31.
-        if (ldK) {                                             // [h h l]
-            uint4 r0, r1;
-            uint2 r2;
-            read_staged_record(&stg[0][valK][0][colK], r0, r1, r2);
-            uint4* row = reinterpret_cast<uint4*>(opK[rK]);
-            row[0] = r0;
-            row[1] = make_uint4(r1.x, r0.x, r0.y, r0.z);
-            row[2] = make_uint4(r0.w, r1.x, r1.y, r1.z);
-            row[3] = make_uint4(r1.w, r2.x, r2.y, 0u);
-        }
-        if (ldL) {                                             // [h l h]
-            uint4 r0, r1;
-            uint2 r2;
-            read_staged_record(&stg[1][valL][0][colL], r0, r1, r2);
-            uint4* row = reinterpret_cast<uint4*>(opL[rL]);
-            row[0] = r0;
-            row[1] = r1;
-            row[2] = make_uint4(r2.x, r2.y, r0.x, r0.y);
-            row[3] = make_uint4(r0.z, r0.w, r1.x, 0u);
-        }
-        if (wv == 0 || wv == 3) {                              // wave 0: k side, wave 3: l side
-            const int side = wv == 3;
-            float pv, s2;
-            read_staged_pair(&stgp[side][0][lane], pv, s2);
-            psum[side][lane] = (side ? 1.0 : -gamma) * (double)pv;
-            sc2[side][lane] = (double)s2;
-        }
-        lds_sync_rows();                               // rows ready, staging free
-        copy_chunk(stg, stgp, min(c + 2, c1 - 1));
-        // Two K steps of 16 slots (the scheduling barrier keeps each step's
-        // operand reads next to its contractions: fewer live registers).
+    // (every wave is done with the previous piece's stages and has no memory
+    // access of its own in flight: the counts waited for below are the
+    // copies' alone)
+    copies_barrier();
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            const int wo = 8 * ks + 4 * kh;                    // first word of this lane's 8 slots
-            const halfx8_t aR = __builtin_bit_cast(halfx8_t, *reinterpret_cast<const u32x4_t*>(&opK[rowK][wo]));
-            const halfx8_t aI = __builtin_bit_cast(halfx8_t, *reinterpret_cast<const u32x4_t*>(&opK[kTile + rowK][wo]));
-            const halfx8_t aP = __builtin_bit_cast(halfx8_t, *reinterpret_cast<const u32x4_t*>(&opK[2 * kTile + rowK][wo]));
-            const halfx8_t bR = __builtin_bit_cast(halfx8_t, *reinterpret_cast<const u32x4_t*>(&opL[rowL][wo]));
-            const halfx8_t bI = __builtin_bit_cast(halfx8_t, *reinterpret_cast<const u32x4_t*>(&opL[kTile + rowL][wo]));
-            const halfx8_t bP = __builtin_bit_cast(halfx8_t, *reinterpret_cast<const u32x4_t*>(&opL[2 * kTile + rowL][wo]));
-            if (ks == 0) {
-                const floatx16_t z = {};
-                d[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aR, bR, z, 0, 0, 0);   // X
-                d[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aR, bI, z, 0, 0, 0);   // U
-                d[2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aI, bR, z, 0, 0, 0);   // V
-                d[3] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aI, bI, z, 0, 0, 0);   // Y
-                d[4] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aP, bP, z, 0, 0, 0);   // M4
-            } else {
-                d[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aR, bR, d[0], 0, 0, 0);
-                d[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aR, bI, d[1], 0, 0, 0);
-                d[2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aI, bR, d[2], 0, 0, 0);
-                d[3] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aI, bI, d[3], 0, 0, 0);
-                d[4] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aP, bP, d[4], 0, 0, 0);
+    for (int j = 0; j < kS4Stages - 1; ++j) copy_chunk(j, c0 + j);
+
+    int b = 0;                                           // stage of chunk c
+#pragma unroll 1
+    for (int c = c0; c < c1; ++c) {
+        // Chunk c's copies have landed once at most the next kS4Stages - 2
+        // chunks' copies are in flight (each wave waits for its own, the
+        // barrier for the others'); the barrier also frees the stage chunk
+        // c - 1 was read from, which takes chunk c + kS4Stages - 1.
+        static_assert(kS4Stages == 3 && kS4CopiesPerWave == 5, "the vmcnt below counts 5 copies in flight");
+        __builtin_amdgcn_s_waitcnt(0x0075);                            // vmcnt(5) lgkmcnt(0)
+        lds_sync();
+        copy_chunk(b == 0 ? kS4Stages - 1 : b - 1, c + kS4Stages - 1);
+
+        const unsigned so = (unsigned)b * (unsigned)sizeof(S4Stage);            // stage b's offset
+        unsigned ad[12];
+        u32x4_v op[12];
+#pragma unroll
+        for (int val = 0; val < 3; ++val) {
+            ad[val] = aK0 + so + val * kValBytes;
+            ad[3 + val] = aL0 + so + val * kValBytes;
+            ad[6 + val] = aK1 + so + val * kValBytes;
+            ad[9 + val] = aL1 + so + val * kValBytes;
+        }
+        read_lds_b128x<12>(ad, op);
+        floatx16_t d[5];
+        {
+            const floatx16_t z = {};
+            const halfx8_t aR = __builtin_bit_cast(halfx8_t, op[0]), aI = __builtin_bit_cast(halfx8_t, op[1]),
+                           aP = __builtin_bit_cast(halfx8_t, op[2]);
+            const halfx8_t bR = __builtin_bit_cast(halfx8_t, op[3]), bI = __builtin_bit_cast(halfx8_t, op[4]),
+                           bP = __builtin_bit_cast(halfx8_t, op[5]);
+            d[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aR, bR, z, 0, 0, 0);     // X
+            d[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aR, bI, z, 0, 0, 0);     // U
+            d[2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aI, bR, z, 0, 0, 0);     // V
+            d[3] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aI, bI, z, 0, 0, 0);     // Y
+            d[4] = __builtin_amdgcn_mfma_f32_32x32x16_f16(aP, bP, z, 0, 0, 0);     // M4
+        }
+        {
+            // step 1, kh 1: k side (h4 l4 h4 0) from T = (h4 l4 0 0), l side
+            // (h4 h4 l4 0); kh 0 takes the pieces as read
+            halfx8_t a1[3], b1[3];
+#pragma unroll
+            for (int val = 0; val < 3; ++val) {
+                const u32x4_v q = op[6 + val], t = op[9 + val];
+                const u32x4_v qa = {q.x, q.y, kh ? q.x : q.z, q.w};
+                const u32x4_v tb = {t.x, kh ? t.x : t.y, kh ? t.y : t.z, t.w};
+                a1[val] = __builtin_bit_cast(halfx8_t, qa);
+                b1[val] = __builtin_bit_cast(halfx8_t, tb);
             }
-            __builtin_amdgcn_sched_barrier(0);
+            d[0] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1[0], b1[0], d[0], 0, 0, 0);
+            d[1] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1[0], b1[1], d[1], 0, 0, 0);
+            d[2] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1[1], b1[0], d[2], 0, 0, 0);
+            d[3] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1[1], b1[1], d[3], 0, 0, 0);
+            d[4] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a1[2], b1[2], d[4], 0, 0, 0);
         }
 
         // Register r of lane (kh, r32) is grid point
         // k = k0 + 32 (w / 2) + 8 (r / 4) + 4 kh + r % 4, l = l0 + 32 (w % 2) + r32.
-        // The k-statistic combination in FP64.  The sum of the four squares
-        // (no cancellation: positive terms, like M4 itself a sum of
-        // positive FP32 terms) is formed in FP32; the cancellation between
-        // M4, the squares and p_k p_l happens in FP64.
-        const double pl = psum[1][rowL], sl2 = sc2[1][rowL];
+        // The k-statistic combination in FP64, the (p, s^2) pairs of the
+        // k side read four columns (k .. k + 3 of one r / 4) at a time.
+        double pl = 0.0, sl2 = 0.0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int kr = 32 * (w >> 1) + 8 * (r >> 2) + 4 * kh + (r & 3);
-            const float X = d[0][r], U = d[1][r], V = d[2][r], Y = d[3][r];
-            const double sq = fmaf(X, X, fmaf(Y, Y, fmaf(U, U, V * V)));
-            const double sig = sc2[0][kr] * sl2;
-            const double val = fma(sig, fma(m2g, sq, (double)d[4][r]), psum[0][kr] * pl);
-            acc[r][0] += val;
-            acc[r][1] = fma(val, val, acc[r][1]);
+        for (int j = 0; j < 4; ++j) {
+            u32x4_v pk[5];
+            if (j == 0) {
+                unsigned pa[5];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) pa[i] = aPk + so + (8 * j + i) * 16;
+                pa[4] = aPl + so;
+                read_lds_b128x<5>(pa, pk);
+                const double2 l2 = __builtin_bit_cast(double2, pk[4]);
+                pl = -gamma * l2.x;
+                sl2 = l2.y;
+            } else {
+                unsigned pa[4];
+                u32x4_v pq[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) pa[i] = aPk + so + (8 * j + i) * 16;
+                read_lds_b128x<4>(pa, pq);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) pk[i] = pq[i];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 4 * j + i;
+                const double2 kp = __builtin_bit_cast(double2, pk[i]);    // (p_k, s_k^2)
+                const float X = d[0][r], U = d[1][r], V = d[2][r], Y = d[3][r];
+                const double sq = fmaf(X, X, fmaf(Y, Y, fmaf(U, U, V * V)));
+                const double sig = kp.y * sl2;
+                const double val = fma(sig, fma(m2g, sq, (double)d[4][r]), kp.x * pl);
+                acc[r][0] += val;
+                acc[r][1] = fma(val, val, acc[r][1]);
+            }
         }
-    };
-
-    // (every wave is done with the previous piece's rows and staging, and has
-    // no memory access of its own in flight: the counts waited for below are
-    // then the copies' alone)
-    copies_barrier();
-    copy_chunk(stgA, stgpA, c0);
-    copy_chunk(stgB, stgpB, min(c0 + 1, c1 - 1));
-    int c = c0;
-#pragma unroll 1
-    for (; c < c1; c += 2) {
-        step(stgA, stgpA, c);
-        if (c + 1 < c1) step(stgB, stgpB, c + 1);
+        b = b == kS4Stages - 1 ? 0 : b + 1;
     }
 
     double* o = it.part;
