@@ -26,6 +26,8 @@
 // by the hardware; the ids are remapped so that each XCD sees a contiguous
 // range of blocks: the tiles of one round on one XCD then walk the same chunks
 // at the same time and share their coefficients in that XCD's L2.
+#include <type_traits>
+
 #include "ps_internal.h"
 
 namespace ps {
@@ -905,7 +907,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16(BatchArgs p) {
 // kS4Stages - 1 chunks ahead; one workgroup barrier per chunk both publishes
 // the chunk's copies and frees the buffer the previous chunk was read from.
 // Staging reads are LDS reads in inline assembly with their wait in the same
-// statement (see read_lds_b128x): the compiler's own wait for copies in
+// statement (see read_lds_ops): the compiler's own wait for copies in
 // flight cannot tell the buffers apart and would drain all of them.
 //
 // With the scale sigma = s_k^2 s_l^2 (exact) of the point, M4 and
@@ -941,56 +943,66 @@ __device__ __forceinline__ void copies_barrier() {
 }
 
 typedef unsigned u32x4_v __attribute__((ext_vector_type(4)));
-// N 16-byte LDS reads from the lane's addresses a[i] (byte offsets in LDS,
-// 16-byte aligned) into x[i], complete when the statement ends.
-template <int N>
-__device__ __forceinline__ void read_lds_b128x(const unsigned (&a)[N], u32x4_v (&x)[N]);
-template <>
-__device__ __forceinline__ void read_lds_b128x<4>(const unsigned (&a)[4], u32x4_v (&x)[4]) {
+// 16-byte LDS reads at base + OFF (base: byte address in LDS, 16-byte
+// aligned; OFF an immediate), complete when the statement ends.  The twelve
+// operand reads of one chunk: four bases, three value offsets each.
+template <unsigned O0, unsigned O1, unsigned O2>
+__device__ __forceinline__ void read_lds_ops(unsigned aK0, unsigned aL0, unsigned aK1, unsigned aL1,
+                                             u32x4_v (&x)[12]) {
     __asm__ volatile(
-        "ds_read_b128 %0, %4\n\t"
-        "ds_read_b128 %1, %5\n\t"
-        "ds_read_b128 %2, %6\n\t"
-        "ds_read_b128 %3, %7\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3])
-        : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3])
-        : "memory");
-}
-template <>
-__device__ __forceinline__ void read_lds_b128x<5>(const unsigned (&a)[5], u32x4_v (&x)[5]) {
-    __asm__ volatile(
-        "ds_read_b128 %0, %5\n\t"
-        "ds_read_b128 %1, %6\n\t"
-        "ds_read_b128 %2, %7\n\t"
-        "ds_read_b128 %3, %8\n\t"
-        "ds_read_b128 %4, %9\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3]), "=&v"(x[4])
-        : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4])
-        : "memory");
-}
-template <>
-__device__ __forceinline__ void read_lds_b128x<12>(const unsigned (&a)[12], u32x4_v (&x)[12]) {
-    __asm__ volatile(
-        "ds_read_b128 %0, %12\n\t"
-        "ds_read_b128 %1, %13\n\t"
-        "ds_read_b128 %2, %14\n\t"
-        "ds_read_b128 %3, %15\n\t"
-        "ds_read_b128 %4, %16\n\t"
-        "ds_read_b128 %5, %17\n\t"
-        "ds_read_b128 %6, %18\n\t"
-        "ds_read_b128 %7, %19\n\t"
-        "ds_read_b128 %8, %20\n\t"
-        "ds_read_b128 %9, %21\n\t"
-        "ds_read_b128 %10, %22\n\t"
-        "ds_read_b128 %11, %23\n\t"
+        "ds_read_b128 %0, %12 offset:%16\n\t"
+        "ds_read_b128 %1, %12 offset:%17\n\t"
+        "ds_read_b128 %2, %12 offset:%18\n\t"
+        "ds_read_b128 %3, %13 offset:%16\n\t"
+        "ds_read_b128 %4, %13 offset:%17\n\t"
+        "ds_read_b128 %5, %13 offset:%18\n\t"
+        "ds_read_b128 %6, %14 offset:%16\n\t"
+        "ds_read_b128 %7, %14 offset:%17\n\t"
+        "ds_read_b128 %8, %14 offset:%18\n\t"
+        "ds_read_b128 %9, %15 offset:%16\n\t"
+        "ds_read_b128 %10, %15 offset:%17\n\t"
+        "ds_read_b128 %11, %15 offset:%18\n\t"
         "s_waitcnt lgkmcnt(0)"
         : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3]), "=&v"(x[4]), "=&v"(x[5]),
           "=&v"(x[6]), "=&v"(x[7]), "=&v"(x[8]), "=&v"(x[9]), "=&v"(x[10]), "=&v"(x[11])
-        : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(a[5]),
-          "v"(a[6]), "v"(a[7]), "v"(a[8]), "v"(a[9]), "v"(a[10]), "v"(a[11])
+        : "v"(aK0), "v"(aL0), "v"(aK1), "v"(aL1), "i"(O0), "i"(O1), "i"(O2)
         : "memory");
+}
+// Four consecutive 16-byte values at base + OFF (and, with the second form,
+// one more at base2 + OFF2).
+template <unsigned OFF>
+__device__ __forceinline__ void read_lds_x4(unsigned base, u32x4_v (&x)[4]) {
+    __asm__ volatile(
+        "ds_read_b128 %0, %4 offset:%5\n\t"
+        "ds_read_b128 %1, %4 offset:%6\n\t"
+        "ds_read_b128 %2, %4 offset:%7\n\t"
+        "ds_read_b128 %3, %4 offset:%8\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3])
+        : "v"(base), "i"(OFF), "i"(OFF + 16), "i"(OFF + 32), "i"(OFF + 48)
+        : "memory");
+}
+template <unsigned OFF, unsigned OFF2>
+__device__ __forceinline__ void read_lds_x4_1(unsigned base, unsigned base2, u32x4_v (&x)[4], u32x4_v& y) {
+    __asm__ volatile(
+        "ds_read_b128 %0, %5 offset:%7\n\t"
+        "ds_read_b128 %1, %5 offset:%8\n\t"
+        "ds_read_b128 %2, %5 offset:%9\n\t"
+        "ds_read_b128 %3, %5 offset:%10\n\t"
+        "ds_read_b128 %4, %6 offset:%11\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3]), "=&v"(y)
+        : "v"(base), "v"(base2), "i"(OFF), "i"(OFF + 16), "i"(OFF + 32), "i"(OFF + 48), "i"(OFF2)
+        : "memory");
+}
+
+// The wave's copy of a value the compiler cannot prove uniform (it is):
+// uniform addresses let a copy take a scalar base and the lane's offset.
+__device__ __forceinline__ const char* wave_uniform(const void* p) {
+    const uint64_t u = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return reinterpret_cast<const char*>(((uint64_t)hi << 32) | lo);
 }
 
 __device__ __forceinline__ unsigned lds_addr(const void* p) {
@@ -1028,8 +1040,8 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
     const int64_t cbase = p.per_chunk ? -(int64_t)p.win_lo : 0;   // per-chunk schedule: chunk win_lo at 0
     const uint32_t lane16 = 16u * lane;
 
-    // Lane addresses of its operands and pair values in stage 0 (a stage is
-    // sizeof(S4Stage) further): step 0 reads piece H of its k-side column
+    // Lane addresses of its operands and pair values in stage 0 (stage b is
+    // b sizeof(S4Stage) further, an immediate offset): step 0 reads piece H of its k-side column
     // and piece H (kh 0) or L (kh 1) of its l-side column, step 1 piece L or
     // T of the k side and H or T of the l side, each for Re, Im, P.
     const unsigned aK0 = lds_addr(&stage[0].rec[0][0][0][rowK]);
@@ -1045,9 +1057,9 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
     while (next_item<kTile, 2>(p, bk, it)) {
     const Seg& sg = *bk.s;
     const int c0 = it.c0, c1 = it.c1;          // c1 > c0: pieces are never empty
-    const int k0 = it.k0, l0 = it.l0;
-    const uint4* base = reinterpret_cast<const uint4*>(p.op4 + it.ch[0] * sg.op4_cs + sg.op4);
-    const double2* pbase = reinterpret_cast<const double2*>(p.p4 + it.ch[0] * sg.p4_cs + sg.p4);
+    const int k0 = __builtin_amdgcn_readfirstlane(it.k0), l0 = __builtin_amdgcn_readfirstlane(it.l0);
+    const char* base = wave_uniform(p.op4 + it.ch[0] * sg.op4_cs + sg.op4);
+    const char* pbase = wave_uniform(p.p4 + it.ch[0] * sg.p4_cs + sg.p4);
 
     // Copy of chunk c into stage b: 18 record copies (side, value, piece) and
     // the two sides' (p, s^2) pairs, 64 columns of 16 bytes each; wave wv
@@ -1058,21 +1070,21 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
     auto copy_chunk = [&](int b, int c) {
         c = min(c, c1 - 1);
         S4Stage& st = stage[b];
-        const uint4* rc = base + (cbase + c) * cunits;
+        const char* rc = base + (cbase + c) * cunits * (int64_t)sizeof(uint4);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int q = wv + 4 * j;
             const int side = q / (3 * kOpPieces), vp = q % (3 * kOpPieces);
-            const char* g = reinterpret_cast<const char*>(rc + (int64_t)vp * ngp + (side ? l0 : k0));
+            const char* g = rc + ((int64_t)vp * ngp + (side ? l0 : k0)) * (int64_t)sizeof(uint4);
             copy_to_lds16(g + lane16, &st.rec[side][0][0][0] + vp * kTile);
         }
         if (wv < 2) {
             const int vp = 7 + wv;                             // records 16, 17: l side, value 2, pieces 1, 2
-            const char* g = reinterpret_cast<const char*>(rc + (int64_t)vp * ngp + l0);
+            const char* g = rc + ((int64_t)vp * ngp + l0) * (int64_t)sizeof(uint4);
             copy_to_lds16(g + lane16, &st.rec[1][0][0][0] + vp * kTile);
         } else {
             const int side = wv - 2;
-            const char* g = reinterpret_cast<const char*>(pbase + (cbase + c) * ngp + (side ? l0 : k0));
+            const char* g = pbase + ((cbase + c) * ngp + (side ? l0 : k0)) * (int64_t)sizeof(double2);
             copy_to_lds16(g + lane16, &st.pw[side][0]);
         }
     };
@@ -1081,16 +1093,11 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r][0] = acc[r][1] = 0.0;
 
-    // (every wave is done with the previous piece's stages and has no memory
-    // access of its own in flight: the counts waited for below are the
-    // copies' alone)
-    copies_barrier();
-#pragma unroll
-    for (int j = 0; j < kS4Stages - 1; ++j) copy_chunk(j, c0 + j);
-
-    int b = 0;                                           // stage of chunk c
-#pragma unroll 1
-    for (int c = c0; c < c1; ++c) {
+    // Chunk c from stage B (a compile-time index, so that every LDS read
+    // offset is an immediate).
+    auto step = [&](auto B, int c) {
+        constexpr int b = decltype(B)::value;
+        constexpr unsigned so = b * sizeof(S4Stage);
         // Chunk c's copies have landed once at most the next kS4Stages - 2
         // chunks' copies are in flight (each wave waits for its own, the
         // barrier for the others'); the barrier also frees the stage chunk
@@ -1100,17 +1107,8 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
         lds_sync();
         copy_chunk(b == 0 ? kS4Stages - 1 : b - 1, c + kS4Stages - 1);
 
-        const unsigned so = (unsigned)b * (unsigned)sizeof(S4Stage);            // stage b's offset
-        unsigned ad[12];
         u32x4_v op[12];
-#pragma unroll
-        for (int val = 0; val < 3; ++val) {
-            ad[val] = aK0 + so + val * kValBytes;
-            ad[3 + val] = aL0 + so + val * kValBytes;
-            ad[6 + val] = aK1 + so + val * kValBytes;
-            ad[9 + val] = aL1 + so + val * kValBytes;
-        }
-        read_lds_b128x<12>(ad, op);
+        read_lds_ops<so, so + kValBytes, so + 2 * kValBytes>(aK0, aL0, aK1, aL1, op);
         floatx16_t d[5];
         {
             const floatx16_t z = {};
@@ -1148,27 +1146,7 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
         // The k-statistic combination in FP64, the (p, s^2) pairs of the
         // k side read four columns (k .. k + 3 of one r / 4) at a time.
         double pl = 0.0, sl2 = 0.0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            u32x4_v pk[5];
-            if (j == 0) {
-                unsigned pa[5];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) pa[i] = aPk + so + (8 * j + i) * 16;
-                pa[4] = aPl + so;
-                read_lds_b128x<5>(pa, pk);
-                const double2 l2 = __builtin_bit_cast(double2, pk[4]);
-                pl = -gamma * l2.x;
-                sl2 = l2.y;
-            } else {
-                unsigned pa[4];
-                u32x4_v pq[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) pa[i] = aPk + so + (8 * j + i) * 16;
-                read_lds_b128x<4>(pa, pq);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) pk[i] = pq[i];
-            }
+        auto combine = [&](int j, const u32x4_v (&pk)[4]) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = 4 * j + i;
@@ -1180,8 +1158,47 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
                 acc[r][0] += val;
                 acc[r][1] = fma(val, val, acc[r][1]);
             }
+        };
+        {
+            u32x4_v pk[4], lp;
+            read_lds_x4_1<so, so>(aPk, aPl, pk, lp);
+            const double2 l2 = __builtin_bit_cast(double2, lp);
+            pl = -gamma * l2.x;
+            sl2 = l2.y;
+            combine(0, pk);
         }
-        b = b == kS4Stages - 1 ? 0 : b + 1;
+        {
+            u32x4_v pk[4];
+            read_lds_x4<so + 8 * 16>(aPk, pk);
+            combine(1, pk);
+        }
+        {
+            u32x4_v pk[4];
+            read_lds_x4<so + 16 * 16>(aPk, pk);
+            combine(2, pk);
+        }
+        {
+            u32x4_v pk[4];
+            read_lds_x4<so + 24 * 16>(aPk, pk);
+            combine(3, pk);
+        }
+    };
+
+    // (every wave is done with the previous piece's stages and has no memory
+    // access of its own in flight: the counts waited for below are the
+    // copies' alone)
+    copies_barrier();
+#pragma unroll
+    for (int j = 0; j < kS4Stages - 1; ++j) copy_chunk(j, c0 + j);
+    static_assert(kS4Stages == 3, "the loop below cycles through three stages");
+#pragma unroll 1
+    for (int c = c0;;) {
+        step(std::integral_constant<int, 0>{}, c);
+        if (++c >= c1) break;
+        step(std::integral_constant<int, 1>{}, c);
+        if (++c >= c1) break;
+        step(std::integral_constant<int, 2>{}, c);
+        if (++c >= c1) break;
     }
 
     double* o = it.part;
