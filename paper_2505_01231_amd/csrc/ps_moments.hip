@@ -968,31 +968,42 @@ __device__ __forceinline__ void read_lds_ops(unsigned aK0, unsigned aL0, unsigne
         : "v"(aK0), "v"(aL0), "v"(aK1), "v"(aL1), "i"(O0), "i"(O1), "i"(O2)
         : "memory");
 }
-// Four consecutive 16-byte values at base + OFF (and, with the second form,
-// one more at base2 + OFF2).
+// Two runs of four consecutive 16-byte values, at base + OFF and base + OFF
+// + 128, and (second form) one more at base2 + OFF2.
 template <unsigned OFF>
-__device__ __forceinline__ void read_lds_x4(unsigned base, u32x4_v (&x)[4]) {
+__device__ __forceinline__ void read_lds_x8(unsigned base, u32x4_v (&x)[8]) {
     __asm__ volatile(
-        "ds_read_b128 %0, %4 offset:%5\n\t"
-        "ds_read_b128 %1, %4 offset:%6\n\t"
-        "ds_read_b128 %2, %4 offset:%7\n\t"
-        "ds_read_b128 %3, %4 offset:%8\n\t"
+        "ds_read_b128 %0, %8 offset:%9\n\t"
+        "ds_read_b128 %1, %8 offset:%10\n\t"
+        "ds_read_b128 %2, %8 offset:%11\n\t"
+        "ds_read_b128 %3, %8 offset:%12\n\t"
+        "ds_read_b128 %4, %8 offset:%13\n\t"
+        "ds_read_b128 %5, %8 offset:%14\n\t"
+        "ds_read_b128 %6, %8 offset:%15\n\t"
+        "ds_read_b128 %7, %8 offset:%16\n\t"
         "s_waitcnt lgkmcnt(0)"
-        : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3])
-        : "v"(base), "i"(OFF), "i"(OFF + 16), "i"(OFF + 32), "i"(OFF + 48)
+        : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3]), "=&v"(x[4]), "=&v"(x[5]), "=&v"(x[6]), "=&v"(x[7])
+        : "v"(base), "i"(OFF), "i"(OFF + 16), "i"(OFF + 32), "i"(OFF + 48),
+          "i"(OFF + 128), "i"(OFF + 144), "i"(OFF + 160), "i"(OFF + 176)
         : "memory");
 }
 template <unsigned OFF, unsigned OFF2>
-__device__ __forceinline__ void read_lds_x4_1(unsigned base, unsigned base2, u32x4_v (&x)[4], u32x4_v& y) {
+__device__ __forceinline__ void read_lds_x8_1(unsigned base, unsigned base2, u32x4_v (&x)[8], u32x4_v& y) {
     __asm__ volatile(
-        "ds_read_b128 %0, %5 offset:%7\n\t"
-        "ds_read_b128 %1, %5 offset:%8\n\t"
-        "ds_read_b128 %2, %5 offset:%9\n\t"
-        "ds_read_b128 %3, %5 offset:%10\n\t"
-        "ds_read_b128 %4, %6 offset:%11\n\t"
+        "ds_read_b128 %0, %9 offset:%11\n\t"
+        "ds_read_b128 %1, %9 offset:%12\n\t"
+        "ds_read_b128 %2, %9 offset:%13\n\t"
+        "ds_read_b128 %3, %9 offset:%14\n\t"
+        "ds_read_b128 %4, %9 offset:%15\n\t"
+        "ds_read_b128 %5, %9 offset:%16\n\t"
+        "ds_read_b128 %6, %9 offset:%17\n\t"
+        "ds_read_b128 %7, %9 offset:%18\n\t"
+        "ds_read_b128 %8, %10 offset:%19\n\t"
         "s_waitcnt lgkmcnt(0)"
-        : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3]), "=&v"(y)
-        : "v"(base), "v"(base2), "i"(OFF), "i"(OFF + 16), "i"(OFF + 32), "i"(OFF + 48), "i"(OFF2)
+        : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3]), "=&v"(x[4]), "=&v"(x[5]), "=&v"(x[6]), "=&v"(x[7]),
+          "=&v"(y)
+        : "v"(base), "v"(base2), "i"(OFF), "i"(OFF + 16), "i"(OFF + 32), "i"(OFF + 48),
+          "i"(OFF + 128), "i"(OFF + 144), "i"(OFF + 160), "i"(OFF + 176), "i"(OFF2)
         : "memory");
 }
 
@@ -1144,9 +1155,9 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
         // Register r of lane (kh, r32) is grid point
         // k = k0 + 32 (w / 2) + 8 (r / 4) + 4 kh + r % 4, l = l0 + 32 (w % 2) + r32.
         // The k-statistic combination in FP64, the (p, s^2) pairs of the
-        // k side read four columns (k .. k + 3 of one r / 4) at a time.
+        // k side read for two runs of four columns (r / 4 = j, j + 1) at a time.
         double pl = 0.0, sl2 = 0.0;
-        auto combine = [&](int j, const u32x4_v (&pk)[4]) {
+        auto combine = [&](int j, const u32x4_v* pk) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = 4 * j + i;
@@ -1160,27 +1171,19 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
             }
         };
         {
-            u32x4_v pk[4], lp;
-            read_lds_x4_1<so, so>(aPk, aPl, pk, lp);
+            u32x4_v pk[8], lp;
+            read_lds_x8_1<so, so>(aPk, aPl, pk, lp);
             const double2 l2 = __builtin_bit_cast(double2, lp);
             pl = -gamma * l2.x;
             sl2 = l2.y;
             combine(0, pk);
+            combine(1, pk + 4);
         }
         {
-            u32x4_v pk[4];
-            read_lds_x4<so + 8 * 16>(aPk, pk);
-            combine(1, pk);
-        }
-        {
-            u32x4_v pk[4];
-            read_lds_x4<so + 16 * 16>(aPk, pk);
+            u32x4_v pk[8];
+            read_lds_x8<so + 16 * 16>(aPk, pk);
             combine(2, pk);
-        }
-        {
-            u32x4_v pk[4];
-            read_lds_x4<so + 24 * 16>(aPk, pk);
-            combine(3, pk);
+            combine(3, pk + 4);
         }
     };
 
