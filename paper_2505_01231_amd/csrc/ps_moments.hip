@@ -1052,9 +1052,10 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
     const uint32_t lane16 = 16u * lane;
 
     // Lane addresses of its operands and pair values in stage 0 (stage b is
-    // b sizeof(S4Stage) further, an immediate offset): step 0 reads piece H of its k-side column
-    // and piece H (kh 0) or L (kh 1) of its l-side column, step 1 piece L or
-    // T of the k side and H or T of the l side, each for Re, Im, P.
+    // b sizeof(S4Stage) further, an immediate offset of the reads): step 0
+    // reads piece H of its k-side column and piece H (kh 0) or L (kh 1) of
+    // its l-side column, step 1 piece L or T of the k side and H or T of the
+    // l side, each for Re, Im, P.
     const unsigned aK0 = lds_addr(&stage[0].rec[0][0][0][rowK]);
     const unsigned aK1 = lds_addr(&stage[0].rec[0][0][1 + kh][rowK]);
     const unsigned aL0 = lds_addr(&stage[0].rec[1][0][kh][rowL]);
@@ -1063,6 +1064,9 @@ __global__ __launch_bounds__(kS4MThreads, 2) void k_s4_mfma_f16_pre(BatchArgs p)
     const unsigned aPk = lds_addr(&stage[0].pw[0][32 * (w >> 1) + 4 * kh]);
     const unsigned aPl = lds_addr(&stage[0].pw[1][rowL]);
     static_assert(sizeof(S4Stage) % 16 == 0, "stage alignment");
+    static_assert((kS4Stages - 1) * sizeof(S4Stage) + 2 * kValBytes < 65536 &&
+                  (kS4Stages - 1) * sizeof(S4Stage) + 24 * 16 + 176 < 65536,
+                  "LDS read offsets are 16-bit immediates");
 
     Item it;
     while (next_item<kTile, 2>(p, bk, it)) {
