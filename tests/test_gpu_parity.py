@@ -227,6 +227,25 @@ def test_large_m_uses_several_frame_batches(dev, precision):
     compare(gpu, ref, label="m37")
 
 
+@pytest.mark.parametrize("m", [4, 10])
+@pytest.mark.parametrize("n_chunks", [1, 2, 3, 4, 5, 7])
+def test_fp16_records_every_piece_length(dev, m, n_chunks):
+    """Scaled FP16x2 S4 from the centring pass's records for records of 1-7
+    chunks: pieces of every length relative to the kernel's three staging
+    buffers (copies two chunks ahead, the ones past a piece's end repeated),
+    and chunks with fewer frames than the records hold."""
+    say("fp16 records", m, n_chunks)
+    z = synth.ar2_chi2(256 * m * n_chunks + 17, seed=40 + n_chunks, dtype=np.float32)
+    gpu, ref = both(z, dev, 256, 100, m, window="acg", precision="fp16x2s", orders=(2, 4))
+    assert gpu["n_chunks"] == n_chunks
+    if n_chunks == 1:       # one chunk: the spectra are defined, the error bars are not
+        for k in ("s2", "s4"):
+            assert rel_err(gpu[k], ref[k]) <= TOL, k
+            assert np.isnan(gpu[k + "_err"]).all()
+    else:
+        compare(gpu, ref, keys=("s2", "s4"), label=f"fp16-records-m{m}-c{n_chunks}")
+
+
 def test_fp16_split_needs_one_batch_per_chunk(dev):
     from paper_2505_01231_amd import Plan
     from paper_2505_01231_amd._lib import PS_E_UNSUPPORTED, PolyspecError
