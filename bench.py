@@ -188,7 +188,7 @@ def _gen_record(args):
     return z, clipped
 
 
-def run_batching(torch, dev, precision, n_records=256, out_budget=32e9):
+def run_batching(torch, dev, precision, n_records=256, out_budget=32e9, workers=16):
     """Batching form: 256 four-channel int16 records of uneven length
     (2^16..2^22 samples), each at a frame length drawn from {1024, 2048, 4096}
     with N_f = N/4, every combination orbit (10 / 40 / 76).  One plan holds the
@@ -205,8 +205,12 @@ def run_batching(torch, dev, precision, n_records=256, out_budget=32e9):
     rng = np.random.default_rng(44)
     fls = [int(v) for v in rng.choice([1024, 2048, 4096], size=n_records)]
     t0 = time.perf_counter()
-    with mp.get_context("spawn").Pool(max(1, min(16, os.cpu_count() or 1))) as pool:
-        data = pool.map(_gen_record, [(int(L), 1000 + i) for i, L in enumerate(lengths)], chunksize=4)
+    jobs = [(int(L), 1000 + i) for i, L in enumerate(lengths)]
+    if workers > 1:
+        with mp.get_context("spawn").Pool(max(1, min(workers, os.cpu_count() or 1))) as pool:
+            data = pool.map(_gen_record, jobs, chunksize=4)
+    else:
+        data = [_gen_record(j) for j in jobs]
     gen_s = time.perf_counter() - t0
     clipped = sum(c for _, c in data)
     xs = [torch.from_numpy(z).to(dev) for z, _ in data]
@@ -264,15 +268,17 @@ def run_batching(torch, dev, precision, n_records=256, out_budget=32e9):
                     f"{out_budget / 1e9:.0f} GB; tile order chosen by ps_plan_autotune on the first group"}
 
 
-def run_streaming(torch, dev, precision, n_windows=64, pool=16, per_push=8, depth=3):
+def run_streaming(torch, dev, precision, stream_samples=10**10, pool=16, per_push=8, depth=3):
     """Streaming form: consecutive 2^20-sample windows of an amplitude-ramped
     AR(2)/chi-square stream, pushed from pinned host buffers through
     ps_streamer, `per_push` consecutive windows per push (H2D copies overlap
-    computation; every window gets its own spectra).  A pool of `pool`
-    generated windows is reused cyclically."""
+    computation; every window gets its own spectra), until at least
+    `stream_samples` samples have been processed (the whole 10^10-sample
+    stream by default).  A pool of `pool` generated windows is reused
+    cyclically, so the stream's content repeats every `pool` windows."""
     from paper_2505_01231_amd import Plan, Streamer, synth
     W = 1 << 20
-    total = W * n_windows
+    n_windows = -(-stream_samples // (W * per_push)) * per_push
     pool_host = torch.empty(pool * W, dtype=torch.float32, pin_memory=True)
     pool_host.copy_(torch.from_numpy(synth.modulated_ar2(pool * W, seed=5, start=0, total=W * pool)))
     groups = [pool_host[(g * per_push) % pool * W:((g * per_push) % pool + per_push) * W]
@@ -311,10 +317,10 @@ def run_streaming(torch, dev, precision, n_windows=64, pool=16, per_push=8, dept
     log(f"streaming {rate:.3e} samples/s, H2D {total * 4 / dt / 1e9:.1f} GB/s (plain pinned copy {link:.1f} GB/s)")
     return {"windows": total // W, "window_samples": W, "samples_per_s": rate,
             "h2d_GBps": total * 4 / dt / 1e9, "plain_pinned_h2d_GBps": link, "seconds": dt,
-            "extrapolated_1e10_stream_s": 1e10 / rate,
-            "windows_per_push": per_push,
-            "note": f"N=4096, N_f=1024, m=10, {per_push} windows per push, depth-{depth} pinned ring; "
-                    "the H2D rate includes the copy/compute overlap"}
+            "stream_samples": total, "windows_per_push": per_push,
+            "note": f"N=4096, N_f=1024, m=10, {per_push} windows per push, depth-{depth} pinned ring; every "
+                    f"window of the {total:,}-sample stream is copied and transformed (a pool of {pool} "
+                    "generated windows cycled); the H2D rate includes the copy/compute overlap"}
 
 
 def main(argv=None):
@@ -341,9 +347,15 @@ def main(argv=None):
     ap.add_argument("--no-batching", action="store_true",
                     help="skip the batching form (four-channel int16 records of uneven length "
                          "(2^16..2^22), N in {1024, 2048, 4096}, N_f = N/4, every combination orbit)")
+    ap.add_argument("--batching-records", type=int, default=256,
+                    help="records of the batching form (the first ones of the same seeded set)")
+    ap.add_argument("--gen-workers", type=int, default=16,
+                    help="worker processes generating the batching records (1: in this process, "
+                         "e.g. under a profiler that attaches to every process)")
     ap.add_argument("--no-streaming", action="store_true",
-                    help="skip the streaming form (64 windows of 2^20 samples from pinned host "
-                         "memory, 8 windows per push, N = 4096, N_f = 1024, copy/compute overlap)")
+                    help="skip the streaming form (the 10^10-sample stream in windows of 2^20 samples "
+                         "from pinned host memory, 8 windows per push, N = 4096, N_f = 1024, "
+                         "copy/compute overlap)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain elementwise copy of 1 GiB (3 launches) so that profiler "
                          "byte counters can be scaled against a kernel of known traffic")
@@ -454,6 +466,17 @@ def main(argv=None):
         s4_info.update({"mfma_executed_tflops": mfma_flops / (s4_avg_ms * 1e-3) / 1e12,
                         "mfma_peak_tflops": 2500.0,
                         "mfma_frac_of_peak": mfma_flops / (s4_avg_ms * 1e-3) / 2.5e15})
+        if args.precision == "fp16x2s":
+            # Upper bound on the matrix pipe's busy fraction set by the FP64
+            # combination: per wave and chunk the compiled kernel issues 10
+            # MFMA 32x32x16 (32 cycles each), 129 FP64-rate and 81 other vector
+            # instructions; at two waves per SIMD these cost 5.27 and 3.18 SIMD
+            # cycles each (vector-issue timing kernel), and at best one wave's
+            # matrix work hides under the other's vector work.
+            valu_cycles = 129 * 5.27 + 81 * 3.18
+            s4_info["mfma_ceiling_frac"] = round(10 * 32 / valu_cycles, 3)
+            s4_info["mfma_ceiling_basis"] = ("FP64 k-statistic combination: 16 points x 8 FP64-rate "
+                                             "instructions per wave and chunk against 10 MFMA 32x32x16")
 
     # Interlaced windows: the same record with a second frame set shifted by N/2
     # (twice the frames), spectra of both sets averaged.
@@ -525,7 +548,9 @@ def main(argv=None):
 
     # (the four-channel records are mostly cross-channel S4, which has a
     # matrix-core kernel in BF16 x 3 only)
-    batching = None if args.no_batching else run_batching(torch, dev, "fp32" if args.precision == "fp32" else "bf16x3")
+    batching = None if args.no_batching else run_batching(torch, dev, "fp32" if args.precision == "fp32" else "bf16x3",
+                                                          n_records=args.batching_records,
+                                                          workers=args.gen_workers)
     streaming = None if args.no_streaming else run_streaming(torch, dev, args.precision)
 
     cpu, acc = None, None
