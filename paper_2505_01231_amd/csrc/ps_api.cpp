@@ -2047,7 +2047,9 @@ ps_status ps_stream_begin(ps_plan_t p, int64_t max_push_samples, int32_t dtype, 
         ws = std::max(ws, B.total);
     }
     a->ws_bytes = align256(ws + ws / 16 + (1 << 20));
-    a->tab_bytes = align256(sizeof(ps::Seg) * (size_t)(p->n2() + p->n3() + p->n4() + 1));
+    // finalize tables of ps_stream_end: one segment per spectrum and combination,
+    // plus the padding finish_layout may put in front of them
+    a->tab_bytes = align256(sizeof(ps::Seg) * (size_t)(p->n2() + p->n3() + p->n4() + 1 + 64));
     hipError_t e = hipMalloc((void**)&a->d_state, sizeof(double) * std::max<int64_t>(1, a->layout.doubles));
     if (e == hipSuccess) e = hipMemset(a->d_state, 0, sizeof(double) * std::max<int64_t>(1, a->layout.doubles));
     if (e == hipSuccess) e = hipMalloc((void**)&a->d_stage, a->esz * a->stage_stride * p->C);
@@ -2193,14 +2195,8 @@ ps_status ps_stream_end(ps_accum_t a, const ps_output* out, ps_stream_t stream) 
     B.groups[0].f3 = f3;
     B.groups[0].f4 = f4;
     finish_layout(p, B);
-    if (B.tab_bytes > a->tab_bytes + 64 * sizeof(ps::Seg)) return fail(PS_E_INTERNAL, "finalize tables too large");
-    if (B.tab_bytes > a->tab_bytes) {
-        // (record-descriptor padding at the front of the layout)
-        hipFree(a->d_tab);
-        a->d_tab = nullptr;
-        a->tab_bytes = align256(B.tab_bytes);
-        PS_HIP(hipMalloc(&a->d_tab, a->tab_bytes));
-    }
+    if (B.tab_bytes > a->tab_bytes)
+        return fail(PS_E_INTERNAL, "finalize tables of %zu bytes exceed the stream's %zu", B.tab_bytes, a->tab_bytes);
     char* tab = static_cast<char*>(a->d_tab);
     ps_status s = upload_tables(p, B, tab, st);
     if (s != PS_OK) return s;

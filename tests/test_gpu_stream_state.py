@@ -91,6 +91,32 @@ def test_stream_pieces_match_oracle_and_execute(dev, precision):
     assert _rel(_complex(got["s1"]), ref["s1"]) <= TOL
 
 
+def test_stream_four_channels_every_orbit(dev):
+    """Four int16 channels with every combination orbit (10 + 40 + 76
+    spectra, the largest finalize tables an accumulator builds), pushed in
+    pieces, with an intermediate end: the accumulated spectra equal ps_execute
+    on the whole record up to the order of FP64 additions."""
+    from paper_2505_01231_amd import Accumulator, Plan
+    N, Nf, m = 256, 40, 4
+    z, _ = synth.mixed_channels(N * m * 9 + 77, seed=19)
+    x = torch.from_numpy(z).to(dev)
+    say("stream four channels")
+    with Plan(frame_len=N, n_freq=Nf, m=m, n_channels=4, orders=(1, 2, 3, 4), precision="bf16x3") as p:
+        assert (len(p.combos2), len(p.combos3), len(p.combos4)) == (10, 40, 76)
+        acc = Accumulator(p, max_push_samples=N * m * 4, dtype=torch.int16)
+        for i, (a, b) in enumerate(_pieces(z.shape[1], 11, 500, N * m * 4)):
+            acc.push(x[:, a:b])
+            if i == 1:
+                acc.end()
+        got = _host(acc.end())
+        whole = _host(p.execute(x))
+        torch.cuda.synchronize()
+        assert acc.counts() == {"chunks": 9, "samples": z.shape[1], "carry": 77}
+        acc.close()
+    for k in whole:
+        assert _rel(got[k], whole[k]) <= 1e-12, k
+
+
 def test_stream_resume_is_bit_exact(dev):
     """Export after some pushes, tear everything down, import into a new
     accumulator of a new plan and push the rest: the outputs equal the
