@@ -64,7 +64,7 @@ typedef void* ps_stream_t; /* a hipStream_t; NULL is the null stream */
 typedef enum ps_status {
     PS_OK = 0,
     PS_E_INVALID_ARG = 1, /* a parameter is out of range, a pointer is NULL or misaligned */
-    PS_E_UNSUPPORTED = 2, /* valid per the paper but not implemented here (e.g. N not a power of two) */
+    PS_E_UNSUPPORTED = 2, /* valid per the paper but not implemented here (e.g. complex records at N not a power of two) */
     PS_E_WORKSPACE = 3,   /* workspace smaller than ps_workspace_size() */
     PS_E_HIP = 4,         /* a HIP runtime call failed */
     PS_E_INTERNAL = 5
@@ -111,7 +111,7 @@ typedef struct ps_config {
     uint32_t struct_size; /* sizeof(ps_config) */
     uint32_t orders;      /* PS_ORDER_* bitmask, non-zero */
     int32_t n_channels;   /* 1..4 (Section 7) */
-    int32_t frame_len;    /* N: power of two, 256..8192 */
+    int32_t frame_len;    /* N: 256..8192; a power of two takes the FFT, any other length the direct transform */
     int32_t n_freq;       /* N_f; 0 => floor(f_max * N * dt) + 1 */
     int32_t m;            /* frames per chunk: >= 1 (S1), >= 2 (S2), >= 3 (S3), >= 4 (S4) */
     double f_max;         /* used only when n_freq == 0 */
@@ -234,10 +234,15 @@ typedef struct ps_plan_info {
  * Validation follows the estimator's definitions: m >= order (the
  * denominators of eq. c2..c4, Section 4.1); 2 (N_f - 1) <= N/2 when S3 is
  * requested (its third factor a_{k+l}, Section 4), else N_f - 1 <= N/2;
- * N a power of two in 256..8192.  Allocates the plan's small device tables on
- * the current device (synchronous).  On failure *out is NULL and the status
- * is PS_E_INVALID_ARG (a parameter out of range), PS_E_UNSUPPORTED (allowed by
- * the paper, not built here, e.g. N not a power of two) or PS_E_HIP. */
+ * N in 256..8192.  The paper takes N a power of two, or at least a product of
+ * small primes, for the FFT (Section 3); a power of two here runs the FFT,
+ * any other length the direct transform of eq. a_k (FP64 accumulation,
+ * ~N / log2 N times the FFT's arithmetic; real records, one frame length per
+ * plan).  Allocates the plan's small device tables on the current device
+ * (synchronous).  On failure *out is NULL and the status is PS_E_INVALID_ARG
+ * (a parameter out of range), PS_E_UNSUPPORTED (allowed by the paper, not
+ * built here, e.g. complex records at a frame length that is not a power of
+ * two) or PS_E_HIP. */
 ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out);
 
 /* Free the plan and its device tables (synchronous).  NULL is accepted. */

@@ -115,6 +115,7 @@ struct FrameClass {
     double sum_g[5] = {0, 0, 0, 0, 0};
     float* d_g = nullptr;
     float2* d_tw = nullptr;
+    double2* d_tw64 = nullptr;      // exp(+2 pi j t / N), t < N (direct transform)
     int2* d_tiles[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
@@ -131,8 +132,8 @@ struct ps_plan_s {
     bool cplx = false;
     int Ng = 0, col0 = 0, jmax = 0, log2n_fft = 0;
     int s4_shift = 0;       // S4 plane parallel to the cut (complex signals)
-    // Frame lengths N = 2 pf 2^log2n (pf = 3, 5): prime-factor transform maps
-    int pf = 0, pf_c = 0, pf_d = 0;    // second frame set shifted by N/2, spectra averaged
+    // N not a power of two: the direct transform (k_window_dft) instead of the FFT
+    bool dft = false;
     std::vector<int8_t> c2, c3, c4;
     double sum_g[5] = {0, 0, 0, 0, 0};
     int T = 0, TX = 0;
@@ -282,6 +283,15 @@ hipError_t build_class_tables(const ps_plan_s* p, FrameClass& c, int tw_log2, in
     };
     hipError_t e = upload((void**)&c.d_g, gf.data(), gf.size() * sizeof(float));
     if (e == hipSuccess) e = upload((void**)&c.d_tw, tw.data(), tw.size() * sizeof(float2));
+    if (e == hipSuccess && p->dft) {
+        // exp(+2 pi j t / N) for the direct transform: long double angle, one rounding
+        std::vector<double2> t64(N);
+        for (int t = 0; t < N; ++t) {
+            const long double ang = 2.0L * 3.14159265358979323846264338327950288L * t / N;
+            t64[t] = make_double2((double)std::cos(ang), (double)std::sin(ang));
+        }
+        e = upload((void**)&c.d_tw64, t64.data(), t64.size() * sizeof(double2));
+    }
     for (int i = 0; i < 4 && e == hipSuccess; ++i)
         e = upload((void**)&c.d_tiles[i], tiles[i].data(), tiles[i].size() * sizeof(int2));
     return e;
@@ -732,6 +742,7 @@ ps_status ps_plan_destroy(ps_plan_t p) {
     for (FrameClass& c : p->fc) {
         hipFree(c.d_g);
         hipFree(c.d_tw);
+        hipFree(c.d_tw64);
         for (int i = 0; i < 4; ++i) hipFree(c.d_tiles[i]);
     }
     delete p;
@@ -752,24 +763,11 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     if (cfg->n_channels < 1 || cfg->n_channels > 4)
         return fail(PS_E_INVALID_ARG, "n_channels must be 1..4");
     const int N = cfg->frame_len;
-    // powers of two 256..8192, or 2 P 2^q with P = 3, 5 and 2^q = 128..1024 (768..6144)
-    int pf = 0, log2m2 = 0;
-    if (N >= 2 && (N & (N - 1))) {
-        for (int P : {3, 5}) {
-            if (N % (2 * P)) continue;
-            const int M2 = N / (2 * P);
-            if (M2 >= 128 && M2 <= 1024 && !(M2 & (M2 - 1))) {
-                pf = P;
-                while ((1 << log2m2) < M2) ++log2m2;
-            }
-        }
-        if (!pf || N > 8192) return fail(PS_E_UNSUPPORTED, "frame_len %d is not a power of two", N);
-        // The prime-factor transform (k_window_rfft_pf) is switched off: one
-        // of its launches ended in an illegal memory access whose cause has
-        // not been found (every access checks in bounds by emulation).
-        return fail(PS_E_UNSUPPORTED, "frame_len %d: prime-factor frame lengths are disabled", N);
-    }
+    // 256..8192: powers of two by the FFT, any other length by the direct transform
     if (N < 256 || N > 8192) return fail(PS_E_UNSUPPORTED, "frame_len %d outside 256..8192", N);
+    const bool dft = (N & (N - 1)) != 0;
+    if (dft && cfg->complex_signal)
+        return fail(PS_E_UNSUPPORTED, "complex signals need a power-of-two frame_len (N = %d)", N);
     if (!(cfg->dt > 0) || !std::isfinite(cfg->dt)) return fail(PS_E_INVALID_ARG, "dt must be > 0");
     // c3^(opt) (S3 only) is defined from m = 2
     const int min_m = (cfg->orders & PS_ORDER_S4)   ? 4
@@ -817,7 +815,7 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     int class_nf[14] = {0};
     if (fl_set) {
         if (fl_set & ~0x3F00u) return fail(PS_E_INVALID_ARG, "frame_len_set holds bits outside 8..13 (256..8192)");
-        if (cfg->complex_signal || pf)
+        if (cfg->complex_signal || dft)
             return fail(PS_E_UNSUPPORTED, "further frame lengths need real signals and a power-of-two frame_len");
         for (int q = 8; q <= 13; ++q) {
             if (!(fl_set >> q & 1u) || (1 << q) == N) continue;
@@ -842,17 +840,9 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
 
     auto* p = new ps_plan_s();
     p->N = N;
-    if (pf) {
-        p->pf = pf;
-        p->log2n = log2m2;
-        const int M2 = 1 << log2m2, M = pf * M2;
-        for (int c = 0; c < M; c += M2)
-            if (c % pf == 1) p->pf_c = c;                   // 0 mod M2, 1 mod P
-        for (int d = 0; d < M; d += pf)
-            if (d % M2 == 1) p->pf_d = d;                   // 0 mod P, 1 mod M2
-    } else {
+    p->dft = dft;
+    if (!dft)
         while ((1 << p->log2n) < N) ++p->log2n;
-    }
     p->Nf = Nf;
     p->cplx = cfg->complex_signal != 0;
     p->Ng = p->cplx ? 2 * Nf - 1 : Nf;
@@ -920,7 +910,7 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     c0.Ng = p->Ng;
     c0.K = p->K;
     c0.jmax = p->jmax;
-    hipError_t e = build_class_tables(p, c0, p->pf ? p->log2n + 1 : p->log2n_fft, p->pf ? N : 1 << p->log2n_fft);
+    hipError_t e = build_class_tables(p, c0, p->dft ? 8 : p->log2n_fft, p->dft ? N : 1 << p->log2n_fft);
     p->fc.push_back(c0);        // owns the device tables (also freed on failure)
     if (e == hipSuccess) {
         for (int n = 0; n < 5; ++n) p->sum_g[n] = c0.sum_g[n];
@@ -1198,18 +1188,17 @@ ps_status ps_coefficients(ps_plan_t p, const ps_record* rec, float* d_coef, ps_s
     c.g_lo = 0;
     c.g_hi = F;
     c.out_g0 = 0;
-    c.log2n = p->pf ? p->log2n : fc.log2n_fft;
+    c.log2n = fc.log2n_fft;
     c.jmax = fc.jmax;
     c.K = fc.K;
     c.g = fc.d_g;
     c.tw = fc.d_tw;
+    c.dft_n = p->dft ? fc.N : 0;
+    c.tw64 = fc.d_tw64;
     c.out = reinterpret_cast<float2*>(d_coef);
     c.out_chan_stride = F * fc.K;
     a.n_channels = p->C;
     a.cplx = p->cplx;
-    a.pf = p->pf;
-    a.pf_c = p->pf_c;
-    a.pf_d = p->pf_d;
     PS_HIP(ps::launch_window_rfft(a, (hipStream_t)stream));
     return PS_OK;
 }
@@ -1379,9 +1368,6 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
     ps::FftArgs fa{};
     fa.n_channels = p->C;
     fa.cplx = p->cplx;
-    fa.pf = p->pf;
-    fa.pf_c = p->pf_c;
-    fa.pf_d = p->pf_d;
     ps::CentreArgs ca{};
     ca.m = m;
     ca.n_channels = p->C;
@@ -1397,11 +1383,13 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
     auto fft_class = [&](const BatchClass& k) {
         const FrameClass& fc = p->fc[k.cls];
         ps::FftClass c{};
-        c.log2n = p->pf ? p->log2n : fc.log2n_fft;
+        c.log2n = fc.log2n_fft;
         c.K = fc.K;
         c.jmax = fc.jmax;
         c.g = fc.d_g;
         c.tw = fc.d_tw;
+        c.dft_n = p->dft ? fc.N : 0;
+        c.tw64 = fc.d_tw64;
         c.out = reinterpret_cast<float2*>(ws + k.coef_off);
         c.out_chan_stride = k.rows * fc.K;
         return c;

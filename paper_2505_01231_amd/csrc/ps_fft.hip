@@ -328,56 +328,43 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_window_rfft_multi(FftArgs a)
     }
 }
 
-// Frame lengths N = 2 P M2 (P = 3 or 5, M2 a power of two, 128..1024): the
-// M = P M2 packed points are transformed by the prime-factor (Good-Thomas)
-// split.  With n = (M2 n1 + P n2) mod M and k = (C k1 + D k2) mod M, where
-// C = 0 mod M2, C = 1 mod P, D = 0 mod P, D = 1 mod M2, the +j-sign transform
-// factors exactly (no twiddles between the factors):
-//   X[k] = sum_{n1 < P} w_P^{n1 k1} Y_{n1}[k2],  Y_{n1} = M2-point transform of
-//   y_{n1}[n2] = x[(M2 n1 + P n2) mod M].
-// A frame takes P groups of M2/16 threads; group n1 runs the power-of-two
-// passes on its subsequence in its own LDS region, then every thread combines
-// P values per k2 (radix P) and the frame is unpacked as above.
-template <int P>
-__device__ __forceinline__ float2 root_p(int q) {      // exp(+2 pi j q / P), q < P
-    if constexpr (P == 3) {
-        constexpr float c = -0.5f, s = 0.86602540378443865f;
-        return q == 0 ? make_float2(1.f, 0.f) : (q == 1 ? make_float2(c, s) : make_float2(c, -s));
-    } else {
-        constexpr float c1 = 0.30901699437494742f, s1 = 0.95105651629515357f;
-        constexpr float c2 = -0.80901699437494742f, s2 = 0.58778525229247313f;
-        switch (q) {
-            case 1: return make_float2(c1, s1);
-            case 2: return make_float2(c2, s2);
-            case 3: return make_float2(c2, -s2);
-            case 4: return make_float2(c1, -s1);
-            default: return make_float2(1.f, 0.f);
-        }
-    }
+// Frame lengths that are not a power of two: the windowed transform by its
+// definition (Section 3, eq. a_k),
+//   a_k = sum_{i<N} g_i z_i exp(+2 pi j i k / N),  k < K,
+// as the product of the windowed frames [frames x N] with the exponentials
+// [N x K], accumulated in FP64; exp(+2 pi j t / N) for t = i k mod N comes from
+// an FP64 table of N entries (tw64).  N^2/2 complex products per frame where
+// the FFT takes ~N log2 N: a slow path for the lengths the FFT does not take.
+// A 256-thread block computes kDftFrames frames x kDftBins bins of one
+// channel: thread (tf, tb) = (tid / 16, tid % 16) accumulates the frames
+// f0 + tf + 16 u (u < 2) at the bins k0 + tb + 16 v (v < 4).  The samples pass
+// in steps of kDftStep: each thread stages 4 windowed samples of one frame
+// (FP64) and 8 exponentials of the step, then every thread adds the step's
+// products.  Grid: x = frame blocks, y = channels, z = bin blocks.
+constexpr int kDftFrames = 32, kDftBins = 64, kDftStep = 32;
+
+__device__ __forceinline__ double dft_sample(const RecDesc& rec, int64_t idx) {
+    if (rec.dtype == 0) return (double)static_cast<const float*>(rec.data)[idx];
+    if (rec.dtype == 1) return static_cast<const double*>(rec.data)[idx];
+    return (double)static_cast<const int16_t*>(rec.data)[idx];
 }
 
-template <int LOG2M2, int P>
-constexpr int pf_frames() {
-    return (kFftThreads / (P * ((1 << LOG2M2) / 16))) > 0 ? kFftThreads / (P * ((1 << LOG2M2) / 16)) : 1;
-}
-
-template <int LOG2M2, int P>
-__global__ __launch_bounds__((pf_frames<LOG2M2, P>() * P * ((1 << LOG2M2) / 16)))
-void k_window_rfft_pf(FftArgs args) {
+__global__ __launch_bounds__(256) void k_window_dft(FftArgs args) {
     const FftClass& a = args.cls[0];
-    constexpr int M2 = 1 << LOG2M2, T2 = M2 / 16, TP = P * T2, F = pf_frames<LOG2M2, P>();
-    constexpr int M = P * M2, N = 2 * M, SUB = M2 + M2 / 16;
-    constexpr int R2 = fft_radix2(LOG2M2 + 1), R3 = fft_radix3(LOG2M2 + 1);
-    constexpr int JMAX = (M2 + TP - 1) / TP;                 // k2 values per thread in the combine
-    __shared__ float2 lds[F * P * SUB];
+    __shared__ double sw[kDftFrames][kDftStep + 1];     // windowed samples of the step
+    __shared__ double2 st[kDftStep][kDftBins];          // exponentials of the step
 
-    const int fl = threadIdx.x / TP, tt = threadIdx.x % TP;
-    const int n1 = tt / T2, t2 = tt % T2;
-    float2* frame = lds + fl * P * SUB;
-    float2* s = frame + n1 * SUB;
-    const int64_t gf = a.g_lo + (int64_t)blockIdx.x * F + fl;
-    const bool live = gf < a.g_hi;
+    const int N = a.dft_n, K = a.K;
+    const int tid = threadIdx.x;
+    const int tf = tid >> 4, tb = tid & 15;
+    const int64_t f0 = a.g_lo + (int64_t)blockIdx.x * kDftFrames;
+    const int k0 = (int)blockIdx.z * kDftBins;
     const int c = blockIdx.y;
+
+    // staging role: frame lf of the block, samples ls .. ls + 3 of each step
+    const int lf = tid >> 3, ls = 4 * (tid & 7);
+    const int64_t gf = f0 + lf;
+    const bool live = gf < a.g_hi;
     RecDesc rec = a.single;
     if (a.recs && live) {
         int lo = 0, hi = a.n_recs - 1;
@@ -389,100 +376,62 @@ void k_window_rfft_pf(FftArgs args) {
         rec = a.recs[lo];
     }
     const int64_t off = c * rec.chan_stride + (gf - rec.frame0) * N;
-    const float2* __restrict__ g2 = reinterpret_cast<const float2*>(a.g);
-    const float2* __restrict__ tw = a.tw;
 
-    float2 v[16], w2[16], w3[16];
-    if constexpr (R2 > 0) pass_twiddles<LOG2M2, R2>(w2, t2, 16, tw + N);
-    // subsequence n1: packed points (M2 n1 + P n2) mod M, n2 = t2 + 16 T2 ... (16 per thread)
-    if (!live) {
+    double acc[2][4][2];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = make_float2(0.f, 0.f);
-    } else {
-        int idx[16];
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) idx[r] = (M2 * n1 + P * (t2 + r * T2)) % M;
-        float2 x[16];
-        if (rec.dtype == 0) {
-            const float* xf = static_cast<const float*>(rec.data) + off;
-            const bool vec = (reinterpret_cast<uintptr_t>(xf) % (2 * sizeof(float))) == 0;
+        for (int v = 0; v < 4; ++v) acc[u][v][0] = acc[u][v][1] = 0.0;
+
+    for (int i0 = 0; i0 < N; i0 += kDftStep) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) x[r] = sample_pair(xf, idx[r], vec);
-        } else if (rec.dtype == 1) {
-            const double* xf = static_cast<const double*>(rec.data) + off;
-            const bool vec = (reinterpret_cast<uintptr_t>(xf) % (2 * sizeof(double))) == 0;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) x[r] = sample_pair(xf, idx[r], vec);
-        } else {
-            const int16_t* xf = static_cast<const int16_t*>(rec.data) + off;
-            const bool vec = (reinterpret_cast<uintptr_t>(xf) % (2 * sizeof(int16_t))) == 0;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) x[r] = sample_pair(xf, idx[r], vec);
+        for (int q = 0; q < 4; ++q) {
+            const int i = i0 + ls + q;
+            sw[lf][ls + q] = (live && i < N) ? (double)a.g[i] * dft_sample(rec, off + i) : 0.0;
         }
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const float2 w = g2[idx[r]];
-            v[r] = make_float2(w.x * x[r].x, w.y * x[r].y);
+        for (int q = 0; q < 8; ++q) {
+            const int e = tid + 256 * q;                     // < kDftStep * kDftBins
+            const int s = e / kDftBins, b = e % kDftBins;
+            const int i = i0 + s, k = k0 + b;
+            st[s][b] = (i < N && k < K) ? a.tw64[(int)(((int64_t)i * k) % N)] : make_double2(0.0, 0.0);
         }
-    }
-
-    fft_pass<LOG2M2, 16, true>(v, w2, s, t2, 1);
-    if constexpr (R2 > 0) fft_pass<LOG2M2, R2, false>(v, w2, s, t2, 16);
-    if constexpr (R3 > 0) pass_twiddles<LOG2M2, R3>(w3, t2, 16 * R2, tw + N + 16 * R2);
-    if constexpr (R3 > 0) fft_pass<LOG2M2, R3, false>(v, w3, s, t2, 16 * R2);
-
-    // radix-P combine across the P subsequences, results kept in registers
-    float2 out[JMAX][P];
+        lds_barrier();
+#pragma unroll 4
+        for (int s = 0; s < kDftStep; ++s) {
+            const double w0 = sw[tf][s], w1 = sw[tf + 16][s];
 #pragma unroll
-    for (int j = 0; j < JMAX; ++j) {
-        const int k2 = tt + j * TP;
-        if (k2 >= M2) break;
-        float2 y[P];
-#pragma unroll
-        for (int r = 0; r < P; ++r) y[r] = frame[r * SUB + pad(k2)];
-#pragma unroll
-        for (int k1 = 0; k1 < P; ++k1) {
-            float2 acc = y[0];
-#pragma unroll
-            for (int r = 1; r < P; ++r) acc = cadd(acc, cmul(y[r], root_p<P>((r * k1) % P)));
-            out[j][k1] = acc;
+            for (int v = 0; v < 4; ++v) {
+                const double2 t = st[s][tb + 16 * v];
+                acc[0][v][0] = fma(w0, t.x, acc[0][v][0]);
+                acc[0][v][1] = fma(w0, t.y, acc[0][v][1]);
+                acc[1][v][0] = fma(w1, t.x, acc[1][v][0]);
+                acc[1][v][1] = fma(w1, t.y, acc[1][v][1]);
+            }
         }
+        lds_barrier();
     }
-    lds_barrier();
-#pragma unroll
-    for (int j = 0; j < JMAX; ++j) {
-        const int k2 = tt + j * TP;
-        if (k2 >= M2) break;
-#pragma unroll
-        for (int k1 = 0; k1 < P; ++k1) frame[pad((args.pf_c * k1 + args.pf_d * k2) % M)] = out[j][k1];
-    }
-    lds_barrier();
 
-    if (!live) return;
-    constexpr int KMAX = (M + 1 + TP - 1) / TP;
-    const int K = a.K;
-    float2* o = a.out + c * a.out_chan_stride + (gf - a.out_g0) * K;
 #pragma unroll
-    for (int i = 0; i < KMAX; ++i) {
-        const int k = tt + i * TP;
-        if (k >= K) break;
-        const float2 xk = frame[pad(k % M)];
-        const float2 xm = frame[pad((M - k) % M)];
-        const float er = 0.5f * (xk.x + xm.x);
-        const float ei = 0.5f * (xk.y - xm.y);
-        const float orr = 0.5f * (xk.y + xm.y);
-        const float oi = -0.5f * (xk.x - xm.x);
-        const float2 w = tw[k];
-        o[k] = make_float2(er + w.x * orr - w.y * oi, ei + w.x * oi + w.y * orr);
+    for (int u = 0; u < 2; ++u) {
+        const int64_t g = f0 + tf + 16 * u;
+        if (g >= a.g_hi) continue;
+        float2* o = a.out + c * a.out_chan_stride + (g - a.out_g0) * K;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int k = k0 + tb + 16 * v;
+            if (k < K) o[k] = make_float2((float)acc[u][v][0], (float)acc[u][v][1]);
+        }
     }
 }
 
-template <int LOG2M2, int P>
-hipError_t launch_pf(const FftArgs& a, hipStream_t st) {
-    constexpr int T2 = (1 << LOG2M2) / 16, F = pf_frames<LOG2M2, P>();
-    const int64_t n = a.cls[0].g_hi - a.cls[0].g_lo;
-    dim3 grid((unsigned)((n + F - 1) / F), a.n_channels);
-    k_window_rfft_pf<LOG2M2, P><<<grid, F * P * T2, 0, st>>>(a);
+hipError_t launch_dft(const FftArgs& a, hipStream_t st) {
+    const FftClass& c = a.cls[0];
+    const int64_t n = c.g_hi - c.g_lo;
+    if (c.dft_n < 2 || !c.tw64 || c.K < 1) return hipErrorInvalidValue;
+    const int64_t bx = (n + kDftFrames - 1) / kDftFrames, bz = (c.K + kDftBins - 1) / kDftBins;
+    if (bx > 0x7fffffff) return hipErrorInvalidConfiguration;
+    k_window_dft<<<dim3((unsigned)bx, a.n_channels, (unsigned)bz), 256, 0, st>>>(a);
     return hipGetLastError();
 }
 
@@ -641,7 +590,9 @@ __global__ __launch_bounds__(256) void k_centre(CentreArgs a) {
 hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s) {
     if (a.n_cls <= 0 || a.n_channels <= 0) return hipSuccess;
     if (a.n_cls > 1) {          // several frame lengths: one launch, a class per block range
-        if (a.cplx || a.pf || a.n_cls > kMaxClasses) return hipErrorInvalidValue;
+        if (a.cplx || a.n_cls > kMaxClasses) return hipErrorInvalidValue;
+        for (int i = 0; i < a.n_cls; ++i)
+            if (a.cls[i].dft_n) return hipErrorInvalidValue;
         int64_t blocks = 0;
         for (int i = 0; i < a.n_cls; ++i) {
             const FftClass& c = a.cls[i];
@@ -656,18 +607,9 @@ hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s) {
     }
     const FftClass& c0 = a.cls[0];
     if (c0.g_hi <= c0.g_lo || c0.n_recs <= 0) return hipSuccess;
-    if (a.pf) {                 // N = 2 pf 2^log2n
-        const int key = a.pf * 16 + c0.log2n;
-        switch (key) {
-            case 3 * 16 + 7: return launch_pf<7, 3>(a, s);
-            case 3 * 16 + 8: return launch_pf<8, 3>(a, s);
-            case 3 * 16 + 9: return launch_pf<9, 3>(a, s);
-            case 3 * 16 + 10: return launch_pf<10, 3>(a, s);
-            case 5 * 16 + 7: return launch_pf<7, 5>(a, s);
-            case 5 * 16 + 8: return launch_pf<8, 5>(a, s);
-            case 5 * 16 + 9: return launch_pf<9, 5>(a, s);
-            default: return hipErrorInvalidValue;
-        }
+    if (c0.dft_n) {            // N not a power of two: the direct transform
+        if (a.cplx) return hipErrorInvalidValue;
+        return launch_dft(a, s);
     }
     switch (c0.log2n) {
         case 8: return launch_n<8>(a, s);

@@ -61,6 +61,10 @@ struct FftClass {
     float2* out;            // [C][rows][K]
     int64_t out_chan_stride;
     int64_t block0;         // first block of the class in the launch
+    // Frame length N when it is not a power of two (0: the FFT): the direct
+    // transform with exp(+2 pi j t / N), t < N, from tw64 (FP64).
+    int dft_n;
+    const double2* tw64;
 };
 
 struct FftArgs {
@@ -71,10 +75,6 @@ struct FftArgs {
     // float32, 4: complex float64), transformed as they are; column c of the
     // output holds bin c - jmax.  Real signals: column c holds bin c.
     int cplx;
-    // Frame lengths N = 2 pf 2^log2n (pf = 3 or 5; 0: N = 2^log2n): the
-    // prime-factor transform with output map k = (pf_c k1 + pf_d k2) mod M
-    // (one class).
-    int pf, pf_c, pf_d;
 };
 hipError_t launch_window_rfft(const FftArgs& a, hipStream_t s);
 

@@ -41,6 +41,7 @@ struct int2 {
     int x, y;
 };
 inline float2 make_float2(float a, float b) { return float2{a, b}; }
+inline double2 make_double2(double a, double b) { return double2{a, b}; }
 inline int2 make_int2(int a, int b) { return int2{a, b}; }
 
 typedef int hipError_t;

@@ -121,8 +121,9 @@ def _cfg(**kw):
 
 
 @pytest.mark.parametrize("kw,status", [
-    (dict(frame_len=300), L.PS_E_UNSUPPORTED),          # not a power of two
-    (dict(frame_len=1536, n_freq=100), L.PS_E_UNSUPPORTED),   # prime-factor lengths switched off
+    (dict(frame_len=300, complex_signal=1), L.PS_E_UNSUPPORTED),    # complex: power-of-two frame lengths only
+    (dict(frame_len=1536, n_freq=100, frame_len_set=1 << 9), L.PS_E_UNSUPPORTED),  # further lengths: power of two
+    (dict(frame_len=255), L.PS_E_UNSUPPORTED),          # below the supported range
     (dict(frame_len=128), L.PS_E_UNSUPPORTED),          # below the supported range
     (dict(frame_len=16384), L.PS_E_UNSUPPORTED),
     (dict(m=3), L.PS_E_INVALID_ARG),                    # S4 needs m >= 4

@@ -1127,22 +1127,16 @@ def test_s4_plane_wide_shift_with_s3(dev, estimator):
     compare(gpu, ref, label=f"plane-wide-2ch-{estimator}")
 
 
-# ---------------------------------------------------------------- frame lengths 2 P 2^q (prime-factor transform)
-_PF_OFF = pytest.mark.skip(reason="prime-factor frame lengths are switched off: a launch at N = 1536 (int16) "
-                                   "ended in an illegal memory access whose cause is not shown (the kernel's own "
-                                   "source runs in bounds and correct under ASan/UBSan in the CPU emulation of "
-                                   "tests/test_fft_cpu_emulation.py); the path stays off")
-
-
-@_PF_OFF
-@pytest.mark.parametrize("N,dtype", [(768, np.float32), (1280, np.float64), (1536, np.int16), (2560, np.float32),
-                                     (3072, np.float32), (5120, np.float32), (6144, np.float64)])
-def test_prime_factor_frame_lengths_coefficients(dev, N, dtype):
-    """Frame lengths N = 2 * 3 * 2^q and 2 * 5 * 2^q: the windowed transform
-    (prime-factor split into 2^q-point transforms and a radix-3/5 combine)
-    equals the oracle's FFT of the frames, for all K = 2 N_f - 1 coefficients."""
+# ---------------------------------------------------------------- frame lengths that are not a power of two
+@pytest.mark.parametrize("N,dtype", [(768, np.float32), (1280, np.float64), (1536, np.int16), (1000, np.float32),
+                                     (2560, np.float32), (3072, np.int16), (5120, np.float32), (6144, np.float64),
+                                     (999, np.int16)])
+def test_direct_transform_frame_lengths_coefficients(dev, N, dtype):
+    """Frame lengths that are not a power of two take the direct transform
+    (k_window_dft, FP64 accumulation): it equals the oracle's FFT of the
+    frames for all K = N // 2 + 1 coefficients."""
     from paper_2505_01231_amd import Plan
-    say("prime-factor coefficients", N, dtype.__name__)
+    say("direct transform coefficients", N, dtype.__name__)
     m = 4
     Nf = N // 4 + 1
     if dtype == np.int16:
@@ -1154,7 +1148,7 @@ def test_prime_factor_frame_lengths_coefficients(dev, N, dtype):
         torch.cuda.synchronize()
         a = a.cpu().numpy()[0]
         K = p.n_coef
-    assert K == 2 * Nf - 1 == N // 2 + 1
+    assert K == 2 * Nf - 1 <= N // 2 + 1
     g = O.window("acg", N)
     ref = O.coefficients(O.chunk_frames(z, N, m).reshape(-1, N), g, 1.0, K)
     e = rel_err(a, ref)
@@ -1162,16 +1156,26 @@ def test_prime_factor_frame_lengths_coefficients(dev, N, dtype):
     assert a.shape == ref.shape and e < 2e-6
 
 
-@_PF_OFF
 @pytest.mark.parametrize("precision", PRECISIONS)
-def test_prime_factor_frame_length_spectra(dev, precision):
+def test_direct_transform_frame_length_spectra(dev, precision):
     """S1..S4 at N = 1536 (2 * 3 * 256) vs the oracle."""
-    say("prime-factor spectra", precision)
+    say("direct transform spectra", precision)
     N, Nf, m = 1536, 120, 8
     z = synth.ar2_chi2(N * m * 6 + 5, seed=181, dtype=np.float32)
     gpu = run_gpu(z, dev, frame_len=N, n_freq=Nf, m=m, precision=precision, orders=(1, 2, 3, 4))
     ref = O.polyspectra(z, N, Nf, m, orders=(1, 2, 3, 4))
-    compare(gpu, ref, label=f"pf-1536-{precision}")
+    compare(gpu, ref, label=f"dft-1536-{precision}")
+
+
+def test_direct_transform_odd_length_channels_interlaced(dev):
+    """An odd frame length (N = 1001) with two int16 channels, every orbit and
+    interlaced windows (the second frame set N // 2 samples in) vs the oracle."""
+    say("direct transform odd length, two channels, interlaced")
+    N, Nf, m = 1001, 150, 5
+    z, clipped = synth.mixed_channels(N * m * 5 + N // 2 + 9, seed=23, n_channels=2)
+    assert clipped == 0 and z.dtype == np.int16
+    gpu, ref = both_interlaced(z, dev, N, Nf, m, n_channels=2, precision="bf16x3")
+    compare(gpu, ref, label="dft-1001-2ch-interlaced")
 
 
 # ---------------------------------------------------------------- launch configuration (autotuner)
