@@ -901,8 +901,8 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     // Tables of the plan's frame length (class 0): the twiddle layout depends
     // on the transform (complex signals: the tables of a real transform of
     // twice the frame length, whose complex transform has the frame length;
-    // prime-factor lengths: the unpack table of N entries, then the pass
-    // tables of the 2^q-point subsequence transforms).
+    // a frame length that is not a power of two: the FP64 exponentials of the
+    // direct transform, beside small unused FFT tables).
     FrameClass c0;
     c0.N = N;
     c0.log2n_fft = p->log2n_fft;
