@@ -279,8 +279,8 @@ ps_status ps_workspace_size(ps_plan_t plan, const ps_record* recs, int32_t n_rec
  * without a complete chunk gets NaN outputs.  d_ws must be 256-byte aligned
  * and at least ps_workspace_size() bytes; its contents are scratch.
  * Errors (nothing enqueued): PS_E_INVALID_ARG for NULL, misaligned or
- * inconsistent arguments, PS_E_WORKSPACE for a small workspace, PS_E_HIP when
- * a launch fails. */
+ * inconsistent arguments, PS_E_UNSUPPORTED for a record of more than 2^31 - 1
+ * chunks, PS_E_WORKSPACE for a small workspace, PS_E_HIP when a launch fails. */
 ps_status ps_execute(ps_plan_t plan, const ps_record* recs, int32_t n_rec, void* d_ws,
                      size_t ws_bytes, const ps_output* outs, ps_stream_t stream);
 
@@ -416,6 +416,8 @@ ps_status ps_streamer_push_multi(ps_streamer_t s, const void* h_pinned, int32_t 
  *       channel_stride elements) and enqueues on `stream` the estimator for
  *       every chunk the sequence now completes, adding its sums to the state.
  *       d_data must stay valid until the stream has run the push.
+ *       PS_E_UNSUPPORTED (nothing enqueued) once the state would hold more
+ *       than 2^31 - 1 chunks.
  *   ps_stream_end(s, out, stream)
  *       enqueues the finalize of the state (mean and error bars as ps_execute
  *       gives them, NaN without a complete chunk) into `out`; the state is

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstddef>
@@ -683,6 +684,9 @@ ps_status check_record(const ps_plan_s* p, const ps_record* r) {
     if (p->C > 1 && r->channel_stride < r->n_samples)
         return fail(PS_E_INVALID_ARG, "channel_stride (%lld) < n_samples (%lld)",
                     (long long)r->channel_stride, (long long)r->n_samples);
+    if ((r->n_samples / p->fc[cls].N) / p->m > INT32_MAX)
+        return fail(PS_E_UNSUPPORTED, "record of %lld samples: at most 2^31 - 1 chunks per record",
+                    (long long)r->n_samples);
     const size_t esz = elem_size(r->dtype);
     if (r->n_samples >= (int64_t)p->fc[cls].N * p->m) {
         if (!r->d_data) return fail(PS_E_INVALID_ARG, "record data is NULL");
@@ -2066,6 +2070,9 @@ ps_status ps_stream_push(ps_accum_t a, const void* d_data, int64_t n, int64_t ch
     const int64_t have = a->n_carry + n;
     const int64_t chunks = have / a->chunk_samples;
     const int64_t used = chunks * a->chunk_samples, tail = have - used;
+    if (a->n_chunks + chunks > INT32_MAX)
+        return fail(PS_E_UNSUPPORTED, "a stream holds at most 2^31 - 1 chunks (%lld accumulated)",
+                    (long long)a->n_chunks);
     // append the pushed samples after the carried ones
     PS_HIP(hipMemcpy2DAsync(a->d_stage + a->n_carry * a->esz, a->esz * a->stage_stride, d_data,
                             a->esz * (p->C > 1 ? channel_stride : n), a->esz * n, p->C, hipMemcpyDeviceToDevice,

@@ -356,6 +356,14 @@ def test_errors_are_reported_not_faulted(dev):
         rec[0].dtype = 9
         assert L.load().ps_execute(p._handle, rec, 1, small.data_ptr(), small.numel(), outs, None) \
             == L.PS_E_INVALID_ARG
+        # a record of more chunks than the per-record counters hold is refused
+        # before anything reads it
+        rec = (L.ps_record * 1)(p.record(x))
+        rec[0].n_samples = (1 << 31) * 256 * 4
+        assert L.load().ps_execute(p._handle, rec, 1, small.data_ptr(), small.numel(), outs, None) \
+            == L.PS_E_UNSUPPORTED
+        nbytes = C.c_size_t(0)
+        assert L.load().ps_workspace_size(p._handle, rec, 1, C.byref(nbytes)) == L.PS_E_UNSUPPORTED
         with pytest.raises(PolyspecError):
             L.check(L.PS_E_INVALID_ARG, "x")
 
