@@ -1186,6 +1186,53 @@ def test_direct_transform_odd_length_channels_interlaced(dev):
     compare(gpu, ref, label="dft-1001-2ch-interlaced")
 
 
+def test_direct_transform_through_every_entry_point(dev):
+    """An odd frame length (N = 1000, the direct transform) through the other
+    entry points: graph replays equal the eager run; a running accumulation
+    pushed in pieces equals one execute; sequential spectra equal the oracle's
+    per-chunk estimates; c3^(opt) and the natural estimator equal the oracle."""
+    from paper_2505_01231_amd import Accumulator, Plan
+    say("direct transform, every entry point")
+    N, Nf, m = 1000, 120, 6
+    z = synth.ar2_chi2(N * m * 7 + 321, seed=141, dtype=np.float32)
+    x = torch.from_numpy(z).to(dev)
+    with Plan(frame_len=N, n_freq=Nf, m=m, window="acg", precision="fp16x2s", orders=(1, 2, 3, 4)) as p:
+        eager = p.execute(x)
+        g = p.graph([x])
+        for rep in range(3):
+            outs = g.launch()
+            torch.cuda.synchronize()
+            for key in ("s2", "s3", "s4", "s2_err", "s3_err", "s4_err"):
+                a, b = getattr(outs[0], key).cpu().numpy(), getattr(eager, key).cpu().numpy()
+                assert np.array_equal(a, b, equal_nan=True), (rep, key)
+        g.close()
+        acc = Accumulator(p, max_push_samples=N * m * 2)
+        cuts = [0, N * m * 2, N * m * 2 + 777, N * m * 3 + 782]
+        cuts += list(range(cuts[-1] + N * m * 2, len(z), N * m * 2)) + [len(z)]
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            acc.push(x[a:b])
+        got = acc.end()
+        torch.cuda.synchronize()
+        acc.close()
+        for key in ("s2", "s3", "s4", "s2_err", "s3_err", "s4_err"):
+            e = rel_err(getattr(got, key).cpu().numpy(), getattr(eager, key).cpu().numpy())
+            assert e <= 1e-12, key
+        seq = p.sequential(x, chunk_lo=1, n_chunks=3)
+        torch.cuda.synchronize()
+        ref = O.polyspectra(z, N, Nf, m, orders=(1, 2, 3, 4), return_chunks=True)
+        for i in range(3):
+            for o in (2, 3, 4):
+                gs = torch.view_as_complex(getattr(seq, f"s{o}")[i]).cpu().numpy()
+                assert rel_err(gs, ref[f"chunks{o}"][1 + i]) <= TOL, (i, o)
+        ev = {k: torch.view_as_complex(getattr(eager, k)).cpu().numpy() for k in ("s2", "s3", "s4")}
+    for k in ("s2", "s3", "s4"):
+        assert rel_err(ev[k], ref[k]) <= TOL, k
+    for est in ("c3opt", "natural"):
+        gpu = run_gpu(z, dev, frame_len=N, n_freq=Nf, m=m, window="acg", precision="bf16x3", estimator=est)
+        refe = O.polyspectra(z, N, Nf, m, estimator=est)
+        compare(gpu, refe, label=f"dft-1000-{est}")
+
+
 # ---------------------------------------------------------------- launch configuration (autotuner)
 def _tuning_case(dev):
     """Two channels (every S3/S4 orbit, so all four tile tables are used), a
