@@ -343,6 +343,9 @@ def main(argv=None):
     ap.add_argument("--c3opt-steps", type=int, default=2,
                     help="timed steps with S3 by the c3^(opt) estimator (one extra mean row per chunk) "
                          "on the same record")
+    ap.add_argument("--direct-steps", type=int, default=2,
+                    help="timed steps of a frame length that is not a power of two (N = 1536, the direct "
+                         "transform) on the first 2^24 samples, S2+S3+S4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batching", action="store_true",
                     help="skip the batching form (four-channel int16 records of uneven length "
@@ -523,6 +526,33 @@ def main(argv=None):
             del wso, oo
         log(f"c3opt {c3opt['samples_per_s']:.3e} samples/s")
 
+    # A frame length that is not a power of two (the direct transform of the
+    # frames in FP64 instead of the FFT), the whole estimator on a prefix.
+    direct = None
+    if args.direct_steps > 0:
+        n_d, N_d = 1 << 24, 1536
+        xd = x[:n_d]
+        with Plan(frame_len=N_d, n_freq=N_d // 4 + 1, m=M, window="acg", precision=args.precision) as pd:
+            wsd = torch.empty(pd.workspace_bytes([xd]), dtype=torch.uint8, device=dev)
+            od = [pd.allocate_outputs(dev)]
+            pd.execute([xd], workspace=wsd, outputs=od)
+            torch.cuda.synchronize()
+            pd.profile(True)
+            pd.profile_read()
+            t0 = time.perf_counter()
+            for _ in range(args.direct_steps):
+                pd.execute([xd], workspace=wsd, outputs=od)
+            torch.cuda.synchronize()
+            dt_d = time.perf_counter() - t0
+            st_d = pd.profile_read()
+            pd.profile(False)
+            direct = {"frame_len": N_d, "n_freq": N_d // 4 + 1, "samples": n_d,
+                      "samples_per_s": n_d * args.direct_steps / dt_d,
+                      "ms_per_step": dt_d / args.direct_steps * 1e3, "steps": args.direct_steps,
+                      "stage_ms_per_step": {k: round(v[0] / args.direct_steps, 4) for k, v in st_d.items()}}
+            del wsd, od
+        log(f"direct transform (N = 1536) {direct['samples_per_s']:.3e} samples/s")
+
     # Sequential spectra: each chunk's short-time estimate written out (FP64
     # S2, S3, S4 and error-bar arrays per chunk), on a prefix of the record.
     sequential = None
@@ -612,6 +642,7 @@ def main(argv=None):
         "s4_matrix_cores": s4_info,
         "interlaced": interlaced,
         "c3opt": c3opt,
+        "direct_transform": direct,
         "sequential": sequential,
         "batching": batching,
         "streaming": streaming,
