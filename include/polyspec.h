@@ -236,9 +236,9 @@ typedef struct ps_plan_info {
  * requested (its third factor a_{k+l}, Section 4), else N_f - 1 <= N/2;
  * N in 256..8192.  The paper takes N a power of two, or at least a product of
  * small primes, for the FFT (Section 3); a power of two here runs the FFT,
- * any other length the direct transform of eq. a_k (FP64 accumulation,
- * ~N / log2 N times the FFT's arithmetic; real records, one frame length per
- * plan).  Allocates the plan's small device tables on the current device
+ * any other length the direct transform of eq. a_k (FP64 accumulation, in
+ * two stages N = N1 N2 when N has a divisor 8 <= N1 <= sqrt(N), else in one;
+ * slower than the FFT; real records, one frame length per plan).  Allocates the plan's small device tables on the current device
  * (synchronous).  On failure *out is NULL and the status is PS_E_INVALID_ARG
  * (a parameter out of range), PS_E_UNSUPPORTED (allowed by the paper, not
  * built here, e.g. complex records at a frame length that is not a power of

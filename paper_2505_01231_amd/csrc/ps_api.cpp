@@ -133,8 +133,11 @@ struct ps_plan_s {
     bool cplx = false;
     int Ng = 0, col0 = 0, jmax = 0, log2n_fft = 0;
     int s4_shift = 0;       // S4 plane parallel to the cut (complex signals)
-    // N not a power of two: the direct transform (k_window_dft) instead of the FFT
+    // N not a power of two: the direct transform (k_window_dft) instead of the
+    // FFT, in two stages N = dft_n1 (N / dft_n1) when N has a divisor of at least
+    // 8 below its square root (k_window_dft2), else in one
     bool dft = false;
+    int dft_n1 = 0;
     std::vector<int8_t> c2, c3, c4;
     double sum_g[5] = {0, 0, 0, 0, 0};
     int T = 0, TX = 0;
@@ -847,6 +850,11 @@ ps_status ps_plan_create(const ps_config* cfg, ps_plan_t* out) {
     p->dft = dft;
     if (!dft)
         while ((1 << p->log2n) < N) ++p->log2n;
+    if (dft) {
+        for (int d = 1; d * d <= N; ++d)
+            if (N % d == 0) p->dft_n1 = d;
+        if (p->dft_n1 < 8) p->dft_n1 = 0;
+    }
     p->Nf = Nf;
     p->cplx = cfg->complex_signal != 0;
     p->Ng = p->cplx ? 2 * Nf - 1 : Nf;
@@ -1199,6 +1207,7 @@ ps_status ps_coefficients(ps_plan_t p, const ps_record* rec, float* d_coef, ps_s
     c.tw = fc.d_tw;
     c.dft_n = p->dft ? fc.N : 0;
     c.tw64 = fc.d_tw64;
+    c.dft_n1 = p->dft_n1;
     c.out = reinterpret_cast<float2*>(d_coef);
     c.out_chan_stride = F * fc.K;
     a.n_channels = p->C;
@@ -1394,6 +1403,7 @@ ps_status enqueue_all(ps_plan_t p, const Batch& B, const ps_record* recs, int32_
         c.tw = fc.d_tw;
         c.dft_n = p->dft ? fc.N : 0;
         c.tw64 = fc.d_tw64;
+        c.dft_n1 = p->dft_n1;
         c.out = reinterpret_cast<float2*>(ws + k.coef_off);
         c.out_chan_stride = k.rows * fc.K;
         return c;

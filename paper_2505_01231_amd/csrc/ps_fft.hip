@@ -425,10 +425,102 @@ __global__ __launch_bounds__(256) void k_window_dft(FftArgs args) {
     }
 }
 
+// The same transform in two stages when N = N1 N2 factors well (N1 <= N2,
+// both from dft_n1): with n = N2 n1 + n2 and k = k1 + N1 k2 (Cooley-Tukey),
+//   Y[k1][n2] = exp(+2 pi j n2 k1 / N) sum_{n1 < N1} w[N2 n1 + n2] exp(+2 pi j n1 k1 / N1),
+//   a_{k1 + N1 k2} = sum_{n2 < N2} Y[k1][n2] exp(+2 pi j n2 k2 / N2),
+// N (N1 + N2) products instead of N K.  One block per frame and channel: the
+// windowed frame (FP32), the two stages' exponentials and Y (FP32, rows
+// padded by one) sit in LDS, every sum is accumulated in FP64, every
+// exponential comes from the FP64 table of exp(+2 pi j t / N)
+// (exp(+2 pi j t / N1) = entry t N2, exp(+2 pi j t / N2) = entry t N1).
+// LDS (dynamic): the N samples (FP32), the exponentials of the two stages
+// exp(+2 pi j t / N1), t < N1, and exp(+2 pi j t / N2), t < N2 (FP64), then Y.
+__host__ __device__ constexpr size_t dft2_sx_bytes(int N) { return ((size_t)N * 4 + 15) / 16 * 16; }
+__host__ __device__ constexpr size_t dft2_lds_bytes(int N, int N1) {
+    return dft2_sx_bytes(N) + (size_t)(N1 + N / N1) * 16 + (size_t)N1 * (N / N1 + 1) * 8;
+}
+
+__global__ __launch_bounds__(256) void k_window_dft2(FftArgs args) {
+    const FftClass& a = args.cls[0];
+    HIP_DYNAMIC_SHARED(double2, dyn)
+    const int N = a.dft_n, N1 = a.dft_n1, N2 = N / N1, K = a.K;
+    float* sx = reinterpret_cast<float*>(dyn);                        // windowed samples of the frame
+    double2* sw1 = dyn + dft2_sx_bytes(N) / 16;                       // exp(+2 pi j t / N1)
+    double2* sw2 = sw1 + N1;                                          // exp(+2 pi j t / N2)
+    float2* sy = reinterpret_cast<float2*>(sw2 + N2);                 // Y, N1 rows of N2 + 1
+
+    const int tid = threadIdx.x;
+    const int64_t gf = a.g_lo + (int64_t)blockIdx.x;
+    const int c = blockIdx.y;
+    if (gf >= a.g_hi) return;                            // (block-uniform)
+    RecDesc rec = a.single;
+    if (a.recs) {
+        int lo = 0, hi = a.n_recs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.recs[mid].frame0 <= gf) lo = mid;
+            else hi = mid - 1;
+        }
+        rec = a.recs[lo];
+    }
+    const int64_t off = c * rec.chan_stride + (gf - rec.frame0) * N;
+    for (int i = tid; i < N; i += 256) sx[i] = (float)((double)a.g[i] * dft_sample(rec, off + i));
+    for (int t = tid; t < N1; t += 256) sw1[t] = a.tw64[t * N2];
+    for (int t = tid; t < N2; t += 256) sw2[t] = a.tw64[t * N1];
+    lds_barrier();
+
+    // stage 1: (k1, n2) = (e / N2, e % N2), e < N
+    for (int e = tid; e < N; e += 256) {
+        const int k1 = e / N2, n2 = e - k1 * N2;
+        double yr = 0.0, yi = 0.0;
+        int t = 0;                                       // n1 k1 mod N1
+        for (int n1 = 0; n1 < N1; ++n1) {
+            const double x = sx[N2 * n1 + n2];
+            const double2 w = sw1[t];
+            yr = fma(x, w.x, yr);
+            yi = fma(x, w.y, yi);
+            t += k1;
+            if (t >= N1) t -= N1;
+        }
+        const double2 w = a.tw64[n2 * k1];               // n2 k1 < N
+        sy[k1 * (N2 + 1) + n2] = make_float2((float)(yr * w.x - yi * w.y), (float)(yr * w.y + yi * w.x));
+    }
+    lds_barrier();
+
+    // stage 2: coefficient k = k1 + N1 k2 < K
+    float2* o = a.out + c * a.out_chan_stride + (gf - a.out_g0) * K;
+    for (int k = tid; k < K; k += 256) {
+        const int k2 = k / N1, k1 = k - k2 * N1;
+        const float2* y = sy + k1 * (N2 + 1);
+        const int step = k2 % N2;
+        double xr = 0.0, xi = 0.0;
+        int t = 0;                                       // n2 k2 mod N2
+        for (int n2 = 0; n2 < N2; ++n2) {
+            const float2 v = y[n2];
+            const double2 w = sw2[t];
+            xr = fma((double)v.x, w.x, fma(-(double)v.y, w.y, xr));
+            xi = fma((double)v.x, w.y, fma((double)v.y, w.x, xi));
+            t += step;
+            if (t >= N2) t -= N2;
+        }
+        o[k] = make_float2((float)xr, (float)xi);
+    }
+}
+
 hipError_t launch_dft(const FftArgs& a, hipStream_t st) {
     const FftClass& c = a.cls[0];
     const int64_t n = c.g_hi - c.g_lo;
     if (c.dft_n < 2 || !c.tw64 || c.K < 1) return hipErrorInvalidValue;
+    if (c.dft_n1 > 0) {                 // two stages, N = N1 N2
+        const int n2 = c.dft_n / c.dft_n1;
+        if (n2 * c.dft_n1 != c.dft_n || c.dft_n1 > n2) return hipErrorInvalidValue;
+        const size_t lds = dft2_lds_bytes(c.dft_n, c.dft_n1);
+        if (lds > 160 * 1024) return hipErrorInvalidValue;
+        if (n > 0x7fffffff) return hipErrorInvalidConfiguration;
+        k_window_dft2<<<dim3((unsigned)n, a.n_channels), 256, lds, st>>>(a);
+        return hipGetLastError();
+    }
     const int64_t bx = (n + kDftFrames - 1) / kDftFrames, bz = (c.K + kDftBins - 1) / kDftBins;
     if (bx > 0x7fffffff) return hipErrorInvalidConfiguration;
     k_window_dft<<<dim3((unsigned)bx, a.n_channels, (unsigned)bz), 256, 0, st>>>(a);

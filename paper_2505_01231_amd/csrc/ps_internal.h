@@ -65,6 +65,9 @@ struct FftClass {
     // transform with exp(+2 pi j t / N), t < N, from tw64 (FP64).
     int dft_n;
     const double2* tw64;
+    // N = dft_n1 * (N / dft_n1) with dft_n1 <= N / dft_n1: the two-stage form
+    // of the direct transform (0: one stage)
+    int dft_n1;
 };
 
 struct FftArgs {

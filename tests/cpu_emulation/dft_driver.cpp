@@ -1,13 +1,14 @@
 // Host driver of the emulated direct transform kernel (test infrastructure
 // only).
 //
-//   dft_driver N FRAMES K DTYPE MISALIGN OUT.f32
+//   dft_driver N FRAMES K DTYPE MISALIGN N1 OUT.f32
 //
-// Runs k_window_dft (frame length N, not a power of two) on FRAMES frames of
-// one channel with the launch shape and the argument fields the library uses
-// (the FP64 table exp(+2 pi j t / N) of N entries, K coefficients per frame),
-// every buffer allocated to its exact size, and writes the FRAMES x K complex
-// outputs.  DTYPE 0 float32, 1 float64, 2 int16; MISALIGN 1 starts the
+// Runs k_window_dft (N1 = 0) or its two-stage form k_window_dft2 (N = N1 N2)
+// for frame length N (not a power of two) on FRAMES frames of one channel with
+// the launch shape and the argument fields the library uses (the FP64 table
+// exp(+2 pi j t / N) of N entries, K coefficients per frame), every buffer,
+// the dynamic LDS included, allocated to its exact size, and writes the
+// FRAMES x K complex outputs.  DTYPE 0 float32, 1 float64, 2 int16; MISALIGN 1 starts the
 // samples one element past an aligned address.  Samples and window are
 // deterministic; OUT.f32.in receives the samples (float64) and the window
 // (float32) for the reference.
@@ -21,6 +22,7 @@
 
 thread_local emu_idx threadIdx, blockIdx;
 std::barrier<>* emu_block_barrier = nullptr;
+char* emu_dyn_smem = nullptr;
 
 template <typename KernelFn>
 static void emu_launch(KernelFn fn, dim3 grid, int threads) {
@@ -43,10 +45,11 @@ static void emu_launch(KernelFn fn, dim3 grid, int threads) {
 }
 
 int main(int argc, char** argv) {
-    if (argc != 7) return 2;
+    if (argc != 8) return 2;
     const int N = atoi(argv[1]);
     const int64_t frames = atoll(argv[2]);
-    const int K = atoi(argv[3]), dtype = atoi(argv[4]), mis = atoi(argv[5]);
+    const int K = atoi(argv[3]), dtype = atoi(argv[4]), mis = atoi(argv[5]), N1 = atoi(argv[6]);
+    const char* out_path = argv[7];
     if (N < 2 || K < 1 || K > N / 2 + 1 || frames < 1) return 2;
     const size_t esz = dtype == 0 ? 4 : dtype == 1 ? 8 : 2;
     char* raw = (char*)malloc(esz * (size_t)(frames * N + mis));
@@ -81,14 +84,23 @@ int main(int argc, char** argv) {
     c.tw = nullptr;
     c.dft_n = N;
     c.tw64 = d_tw64;
+    c.dft_n1 = N1;
     c.out = out;
     c.out_chan_stride = frames * K;
     a.n_channels = 1;
-    // the library's launch shape (launch_dft)
-    const dim3 grid((unsigned)((frames + ps::kDftFrames - 1) / ps::kDftFrames), 1,
-                    (unsigned)((K + ps::kDftBins - 1) / ps::kDftBins));
-    emu_launch([a] { ps::k_window_dft(a); }, grid, 256);
-    FILE* f = fopen(argv[6], "wb");
+    // the library's launch shapes (launch_dft)
+    if (N1 > 0) {
+        if (N % N1 != 0 || N1 > N / N1) return 2;
+        const size_t lds = ps::dft2_lds_bytes(N, N1);
+        emu_dyn_smem = (char*)malloc(lds);
+        emu_launch([a] { ps::k_window_dft2(a); }, dim3((unsigned)frames, 1), 256);
+        free(emu_dyn_smem);
+    } else {
+        const dim3 grid((unsigned)((frames + ps::kDftFrames - 1) / ps::kDftFrames), 1,
+                        (unsigned)((K + ps::kDftBins - 1) / ps::kDftBins));
+        emu_launch([a] { ps::k_window_dft(a); }, grid, 256);
+    }
+    FILE* f = fopen(out_path, "wb");
     if (!f) return 4;
     fwrite(out, sizeof(float2), (size_t)(frames * K), f);
     fclose(f);
@@ -96,7 +108,7 @@ int main(int argc, char** argv) {
     for (int64_t i = 0; i < frames * N; ++i)
         samp[i] = dtype == 0 ? ((const float*)data)[i] : dtype == 1 ? ((const double*)data)[i]
                                                                    : ((const int16_t*)data)[i];
-    std::string p2 = std::string(argv[6]) + ".in";
+    std::string p2 = std::string(out_path) + ".in";
     f = fopen(p2.c_str(), "wb");
     fwrite(samp.data(), sizeof(double), samp.size(), f);
     fwrite(d_g, sizeof(float), N, f);

@@ -17,6 +17,9 @@
 #define __forceinline__ inline
 #define __launch_bounds__(...)
 #define __shared__ static
+// dynamic LDS of the emulated launch: a buffer of exactly the launch's size
+extern char* emu_dyn_smem;
+#define HIP_DYNAMIC_SHARED(type, var) type* var = reinterpret_cast<type*>(emu_dyn_smem);
 #define __restrict__ __restrict
 
 struct dim3 {

@@ -1,5 +1,5 @@
-"""The direct transform kernel (frame lengths that are not a power of two,
-k_window_dft) compiled from its own source for the CPU and run under
+"""The direct transform kernels (frame lengths that are not a power of two,
+k_window_dft and its two-stage form k_window_dft2) compiled from its own source for the CPU and run under
 AddressSanitizer and UndefinedBehaviorSanitizer, with the launch shape and the
 argument fields the library uses (test infrastructure; no GPU).
 
@@ -23,10 +23,25 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(ROOT, "paper_2505_01231_amd", "csrc")
 EMU = os.path.join(HERE, "cpu_emulation")
 
-# (N, frames, dtype, misaligned): frame counts and coefficient counts that
-# leave partial frame and bin blocks, every input type, an odd frame length
-INSTANCES = [(768, 12, 0, 0), (1000, 5, 0, 1), (1280, 33, 1, 0), (1536, 12, 2, 0), (1536, 12, 2, 1),
-             (999, 3, 1, 1)]
+# (N, frames, dtype, misaligned, N1): frame counts and coefficient counts that
+# leave partial frame and bin blocks, every input type, odd frame lengths; N1
+# the library's factor for the two-stage form (0: one stage, as for a prime N)
+INSTANCES = [(768, 12, 0, 0, 0), (1000, 5, 0, 1, 0), (1280, 33, 1, 0, 0), (1536, 12, 2, 0, 0), (1536, 12, 2, 1, 0),
+             (999, 3, 1, 1, 0), (1536, 12, 2, 0, 32), (1536, 3, 2, 1, 32), (1000, 5, 0, 1, 25), (999, 3, 1, 0, 27),
+             (8190, 2, 0, 0, 90), (6144, 2, 1, 0, 64), (1021, 2, 0, 0, 0)]
+
+
+def library_factor(N):
+    """The two-stage factor the library picks: the largest divisor of N not
+    above its square root, if at least 8 (else 0, one stage)."""
+    d = max(d for d in range(1, int(N ** 0.5) + 1) if N % d == 0)
+    return d if d >= 8 else 0
+
+
+def test_instances_use_the_library_factor():
+    for N, _, _, _, n1 in INSTANCES:
+        if n1:
+            assert library_factor(N) == n1, N
 
 
 @pytest.fixture(scope="module")
@@ -55,13 +70,13 @@ def _reference(samples, g, N, K):
     return full[:, :K]
 
 
-@pytest.mark.parametrize("N,frames,dtype,mis", INSTANCES)
-def test_direct_transform_kernel_in_bounds_and_correct(driver, tmp_path, N, frames, dtype, mis):
+@pytest.mark.parametrize("N,frames,dtype,mis,n1", INSTANCES)
+def test_direct_transform_kernel_in_bounds_and_correct(driver, tmp_path, N, frames, dtype, mis, n1):
     K = N // 2 + 1                      # the largest coefficient count (N_f = N/4 + 1 with S3)
     out = tmp_path / "out.f32"
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
-    r = subprocess.run([str(driver), str(N), str(frames), str(K), str(dtype), str(mis), str(out)],
+    r = subprocess.run([str(driver), str(N), str(frames), str(K), str(dtype), str(mis), str(n1), str(out)],
                        capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0, (r.returncode, r.stderr[-6000:])
     got = np.fromfile(out, dtype=np.float32).reshape(frames, K, 2)
