@@ -594,15 +594,26 @@ def main(argv=None):
     # Achieved HBM rates of the bandwidth-bound stages from their algorithmic
     # bytes per step: the FFT reads the samples of every full chunk and writes
     # K = 2 N_f - 1 complex FP32 coefficients per frame; the centring reads and
-    # writes every coefficient; S2 reads the first N_f columns.
+    # writes every coefficient and, for the scaled FP16 x 2 S4, writes each
+    # chunk's operand records (3 values x 3 16-byte pieces and one 16-byte
+    # (p, s^2) pair per column, N_f padded to 64 columns); S2 reads the first
+    # N_f columns.
     K_COEF = 2 * NF - 1
+    rec_cols = (NF + 63) // 64 * 64
     # (c3^(opt): the centring also writes the S3 rows, m + 1 per chunk)
     alg_bytes = {"fft": 4 * n_frames * N + 8 * K_COEF * n_frames,
-                 "mean": 16 * K_COEF * n_frames + (8 * K_COEF * s3_rows if args.estimator == "c3opt" else 0),
+                 "mean": 16 * K_COEF * n_frames + (8 * K_COEF * s3_rows if args.estimator == "c3opt" else 0)
+                 + (160 * rec_cols * n_chunks if args.precision == "fp16x2s" else 0),
                  "s2": 8 * NF * n_frames}
     stage_rates = {f"{k}_hbm_gbps": (b / (stage_ms[k] * 1e-3) / 1e9 if stage_ms.get(k) else None)
                    for k, b in alg_bytes.items()}
     stage_rates.update({"algorithmic_bytes_per_step": alg_bytes, "hbm_peak_gbps": 8000.0})
+    # S3 is bound by the vector ALUs; its HBM rate from the stored counters
+    # (L2-miss bytes per launch) and from its algorithmic bytes (the
+    # coefficient region read once)
+    s3_tr = s3_traffic() if args.estimator == "kstat" else None
+    stage_rates["s3_hbm_gbps_counters"] = s3_tr / (s3_avg_ms * 1e-3) / 1e9 if s3_tr else None
+    stage_rates["s3_hbm_gbps_algorithmic"] = 8 * K_COEF * n_frames / (s3_avg_ms * 1e-3) / 1e9
 
     line = {
         "metric": "input samples/sec for S2+S3+S4 at N_f=2048; mixed vs FP32 at <=1e-5 rel err; MFMA%",
