@@ -343,6 +343,8 @@ def main(argv=None):
     ap.add_argument("--c3opt-steps", type=int, default=2,
                     help="timed steps with S3 by the c3^(opt) estimator (one extra mean row per chunk) "
                          "on the same record")
+    ap.add_argument("--graph-steps", type=int, default=5,
+                    help="timed replays of the main step captured as one HIP graph")
     ap.add_argument("--direct-steps", type=int, default=2,
                     help="timed steps of a frame length that is not a power of two (N = 1536, the direct "
                          "transform) on the first 2^24 samples, S2+S3+S4")
@@ -422,6 +424,23 @@ def main(argv=None):
     s3_avg_ms = s3_ms / max(1, s3_n)
     achieved = s3_flops_per_launch(s3_rows, NF) / (s3_avg_ms * 1e-3) / 1e12
     stage_ms = {k: round(v[0] / max(1, args.steps), 4) for k, v in stages.items()}
+
+    # The same step replayed from one captured HIP graph (ps_graph_create /
+    # ps_graph_launch) on the same workspace and outputs.
+    graph = None
+    if args.graph_steps > 0:
+        g = plan.graph([x], workspace=ws, outputs=outs)
+        g.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.graph_steps):
+            g.launch()
+        torch.cuda.synchronize()
+        dt_g = time.perf_counter() - t0
+        g.close()
+        graph = {"samples_per_s": N_SAMPLES * args.graph_steps / dt_g, "ms_per_step": dt_g / args.graph_steps * 1e3,
+                 "steps": args.graph_steps}
+        log(f"graph replay {graph['samples_per_s']:.3e} samples/s")
 
     # The plain FP32 path: same kernels, one chunk per launch (the paper's structure).
     plain = None
@@ -650,6 +669,7 @@ def main(argv=None):
                   "per_chunk_fp32": plain,
                   "speedup_vs_batched_fp32": (value / batched_fp32) if batched_fp32 else None,
                   "speedup_vs_per_chunk_fp32": (value / plain) if plain else None},
+        "graph": graph,
         "s4_matrix_cores": s4_info,
         "interlaced": interlaced,
         "c3opt": c3opt,
