@@ -239,9 +239,12 @@ def test_acg_rms_width_is_sigma_t(N):
     assert 0.97 < rms(0.14) / (N * 0.14) < 1.0
 
 
-def test_fft_and_direct_sum_agree():
+@pytest.mark.parametrize("N", [64, 96, 75, 77, 101])
+def test_fft_and_direct_sum_agree(N):
+    """eq. a_k by numpy's FFT equals the sum written out, at powers of two and
+    at the frame lengths that are not (composite, odd, prime)."""
     rng = np.random.default_rng(5)
-    N, K = 64, 64
+    K = N
     fr = rng.standard_normal((3, N))
     g = O.window("acg", N)
     a = O.coefficients(fr, g, 0.25, K, "fft")
