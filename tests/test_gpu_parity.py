@@ -1138,11 +1138,12 @@ def test_s4_plane_wide_shift_with_s3(dev, estimator):
 # ---------------------------------------------------------------- frame lengths that are not a power of two
 @pytest.mark.parametrize("N,dtype", [(768, np.float32), (1280, np.float64), (1536, np.int16), (1000, np.float32),
                                      (2560, np.float32), (3072, np.int16), (5120, np.float32), (6144, np.float64),
-                                     (999, np.int16), (1021, np.float32), (2042, np.int16)])
+                                     (999, np.int16), (1021, np.float32), (2042, np.int16), (8190, np.float32)])
 def test_direct_transform_frame_lengths_coefficients(dev, N, dtype):
     """Frame lengths that are not a power of two take the direct transform
     (FP64 accumulation; in two stages for N = N1 N2 with 8 <= N1 <= sqrt(N),
-    in one for the prime 1021 and for 2042 = 2 * 1021): it equals the oracle's
+    8190 = 90 * 91 the largest LDS use, in one for the prime 1021 and for
+    2042 = 2 * 1021): it equals the oracle's
     FFT of the frames for all K = N // 2 + 1 coefficients."""
     from paper_2505_01231_amd import Plan
     say("direct transform coefficients", N, dtype.__name__)
