@@ -268,7 +268,7 @@ def run_batching(torch, dev, precision, n_records=256, out_budget=32e9, workers=
                     f"{out_budget / 1e9:.0f} GB; tile order chosen by ps_plan_autotune on the first group"}
 
 
-def run_streaming(torch, dev, precision, stream_samples=10**10, pool=16, per_push=8, depth=3):
+def run_streaming(torch, dev, precision, stream_samples=10**10, pool=16, per_push=16, depth=3):
     """Streaming form: consecutive 2^20-sample windows of an amplitude-ramped
     AR(2)/chi-square stream, pushed from pinned host buffers through
     ps_streamer, `per_push` consecutive windows per push (H2D copies overlap
@@ -359,7 +359,7 @@ def main(argv=None):
                          "e.g. under a profiler that attaches to every process)")
     ap.add_argument("--no-streaming", action="store_true",
                     help="skip the streaming form (the 10^10-sample stream in windows of 2^20 samples "
-                         "from pinned host memory, 8 windows per push, N = 4096, N_f = 1024, "
+                         "from pinned host memory, 16 windows per push, N = 4096, N_f = 1024, "
                          "copy/compute overlap)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain elementwise copy of 1 GiB (3 launches) so that profiler "
