@@ -334,7 +334,9 @@ __global__ __launch_bounds__(kFftThreads, 4) void k_window_rfft_multi(FftArgs a)
 // as the product of the windowed frames [frames x N] with the exponentials
 // [N x K], accumulated in FP64; exp(+2 pi j t / N) for t = i k mod N comes from
 // an FP64 table of N entries (tw64).  N^2/2 complex products per frame where
-// the FFT takes ~N log2 N: a slow path for the lengths the FFT does not take.
+// the FFT takes ~N log2 N: the path of the lengths that neither the FFT nor
+// the two-stage form below takes (primes, and lengths without a divisor
+// between 8 and sqrt(N)).
 // A 256-thread block computes kDftFrames frames x kDftBins bins of one
 // channel: thread (tf, tb) = (tid / 16, tid % 16) accumulates the frames
 // f0 + tf + 16 u (u < 2) at the bins k0 + tb + 16 v (v < 4).  The samples pass
