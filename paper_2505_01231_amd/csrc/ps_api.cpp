@@ -1,6 +1,9 @@
 // Host runtime behind the C ABI of include/polyspec.h: validation, the FP64
 // window and FFT tables, the channel-combination lists, workspace layout, the
 // choice of launch shapes, and the order of kernel launches per record.
+// Release calls on teardown and clean-up paths, written (void)hip...(),
+// discard their status on purpose: the objects are gone either way, and the
+// error that led there, if any, is the one reported.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -661,7 +664,10 @@ struct StageTimer {
     int stage;
     hipEvent_t a = nullptr;
     StageTimer(ps_plan_s* p_, hipStream_t st_, int stage_) : p(p_), st(st_), stage(stage_) {
-        if (p->prof && hipEventCreate(&a) == hipSuccess) hipEventRecord(a, st);
+        if (p->prof && hipEventCreate(&a) == hipSuccess && hipEventRecord(a, st) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            a = nullptr;
+        }
     }
     ~StageTimer() {
         if (!a) return;
@@ -669,8 +675,8 @@ struct StageTimer {
         if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, st) == hipSuccess) {
             p->timed.push_back({stage, a, b});
         } else {
-            hipEventDestroy(a);
-            if (b) hipEventDestroy(b);
+            (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
         }
     }
 };
@@ -736,21 +742,21 @@ ps_status ps_enumerate_combos(int32_t n_channels, int32_t order, int8_t* out, in
 ps_status ps_plan_destroy(ps_plan_t p) {
     if (!p) return PS_OK;
     for (auto& t : p->timed) {
-        hipEventDestroy(t.a);
-        hipEventDestroy(t.b);
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
     }
     for (int i = 0; i < 2; ++i) {
         if (p->h_ev[i]) {
-            hipEventSynchronize(p->h_ev[i]);
-            hipEventDestroy(p->h_ev[i]);
+            (void)hipEventSynchronize(p->h_ev[i]);
+            (void)hipEventDestroy(p->h_ev[i]);
         }
-        if (p->h_stage[i]) hipHostFree(p->h_stage[i]);
+        if (p->h_stage[i]) (void)hipHostFree(p->h_stage[i]);
     }
     for (FrameClass& c : p->fc) {
-        hipFree(c.d_g);
-        hipFree(c.d_tw);
-        hipFree(c.d_tw64);
-        for (int i = 0; i < 4; ++i) hipFree(c.d_tiles[i]);
+        (void)hipFree(c.d_g);
+        (void)hipFree(c.d_tw);
+        (void)hipFree(c.d_tw64);
+        for (int i = 0; i < 4; ++i) (void)hipFree(c.d_tiles[i]);
     }
     delete p;
     return PS_OK;
@@ -1047,7 +1053,7 @@ ps_status ps_plan_autotune(ps_plan_t p, const ps_record* recs, int32_t n_rec, vo
     hipEvent_t e0 = nullptr, e1 = nullptr;
     PS_HIP(hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return fail(PS_E_HIP, "autotune: hipEventCreate failed");
     }
     double ms[PS_TUNE_MAX];
@@ -1068,8 +1074,8 @@ ps_status ps_plan_autotune(ps_plan_t p, const ps_record* recs, int32_t n_rec, vo
         ms[i] = el / reps;
         if (ms[i] < ms[best]) best = i;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc != PS_OK) {
         // keep the configuration the plan had (the error detail stays the first failure's)
         if (orig.tile_group != p->tile_group) {
@@ -1111,8 +1117,8 @@ ps_status ps_profile_read(ps_plan_t p, double* stage_ms, int32_t n) {
         }
         ms[t.stage] += e;
         cnt[t.stage] += 1;
-        hipEventDestroy(t.a);
-        hipEventDestroy(t.b);
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
     }
     p->timed.clear();
     for (int i = 0; i < n && i < 12; ++i) stage_ms[i] = i < 6 ? ms[i] : cnt[i - 6];
@@ -1230,7 +1236,7 @@ ps_status upload_tables(ps_plan_t p, const Batch& B, char* d_tab, hipStream_t st
     p->h_next ^= 1;
     if (p->h_ev[i]) PS_HIP(hipEventSynchronize(p->h_ev[i]));
     if (p->h_cap[i] < B.tab_bytes) {
-        if (p->h_stage[i]) hipHostFree(p->h_stage[i]);
+        if (p->h_stage[i]) (void)hipHostFree(p->h_stage[i]);
         p->h_stage[i] = nullptr;
         p->h_cap[i] = 0;
         const size_t cap = std::max<size_t>(B.tab_bytes, 1 << 20);
@@ -1685,9 +1691,9 @@ struct ps_graph_s {
 
 ps_status ps_graph_destroy(ps_graph_t g) {
     if (!g) return PS_OK;
-    if (g->exec) hipGraphExecDestroy(g->exec);
-    if (g->graph) hipGraphDestroy(g->graph);
-    if (g->d_tab) hipFree(g->d_tab);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->d_tab) (void)hipFree(g->d_tab);
     delete g;
     return PS_OK;
 }
@@ -1714,7 +1720,7 @@ ps_status ps_graph_create(ps_plan_t p, const ps_record* recs, int32_t n_rec, voi
     hipStream_t cs = nullptr;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e != hipSuccess) {
-        if (cs) hipStreamDestroy(cs);
+        if (cs) (void)hipStreamDestroy(cs);
         ps_graph_destroy(g);
         return fail(PS_E_HIP, "graph setup failed: %s", hipGetErrorString(e));
     }
@@ -1731,7 +1737,7 @@ ps_status ps_graph_create(ps_plan_t p, const ps_record* recs, int32_t n_rec, voi
         s = fail(PS_E_HIP, "stream capture failed: %s", hipGetErrorString(e));
     }
     p->prof = prof;
-    hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs);
     if (s == PS_OK) {
         e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
         if (e != hipSuccess) s = fail(PS_E_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
@@ -1769,14 +1775,14 @@ struct ps_streamer_s {
 ps_status ps_streamer_destroy(ps_streamer_t s) {
     if (!s) return PS_OK;
     for (hipEvent_t e : s->done)
-        if (e) hipEventSynchronize(e);
-    if (s->copy) hipStreamSynchronize(s->copy);
+        if (e) (void)hipEventSynchronize(e);
+    if (s->copy) (void)hipStreamSynchronize(s->copy);
     for (hipEvent_t e : s->copied)
-        if (e) hipEventDestroy(e);
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : s->done)
-        if (e) hipEventDestroy(e);
-    for (void* a : s->allocs) hipFree(a);
-    if (s->copy) hipStreamDestroy(s->copy);
+        if (e) (void)hipEventDestroy(e);
+    for (void* a : s->allocs) (void)hipFree(a);
+    if (s->copy) (void)hipStreamDestroy(s->copy);
     delete s;
     return PS_OK;
 }
@@ -2005,13 +2011,13 @@ extern "C" {
 ps_status ps_stream_destroy(ps_accum_t a) {
     if (!a) return PS_OK;
     if (a->done) {
-        hipEventSynchronize(a->done);
-        hipEventDestroy(a->done);
+        (void)hipEventSynchronize(a->done);
+        (void)hipEventDestroy(a->done);
     }
-    hipFree(a->d_state);
-    hipFree(a->d_stage);
-    hipFree(a->d_ws);
-    hipFree(a->d_tab);
+    (void)hipFree(a->d_state);
+    (void)hipFree(a->d_stage);
+    (void)hipFree(a->d_ws);
+    (void)hipFree(a->d_tab);
     delete a;
     return PS_OK;
 }
