@@ -148,13 +148,15 @@ __global__ __launch_bounds__(256) void k_s2(BatchArgs p) {
     if (!resolve_block(p, bk, v)) return;
     Item it;
     while (next_item<0, 4>(p, bk, it)) {
+        // Lanes past the grid write zero sums: every lane's slots are read
+        // when a running accumulation adds them to its state.
         const int k = it.k0 + threadIdx.x;
-        if (k >= v.Nf) continue;
+        const int c_end = k < v.Nf ? it.c1 : it.c0;
         const float2* A = v.coef + it.ch[0] * v.cs;
         const float2* B = v.coef + it.ch[1] * v.cs;
         const bool same = it.ch[0] == it.ch[1];      // S2 of one channel: one load per frame
         double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        for (int c = it.c0; c < it.c1; ++c) {
+        for (int c = it.c0; c < c_end; ++c) {
             const int64_t base = v.off + (int64_t)c * v.m * v.K + k;
             float re = 0.f, im = 0.f;
             if (v.m <= kS2Regs && same) {

@@ -137,6 +137,7 @@ def test_stream_resume_is_bit_exact(dev):
                 acc.end()                       # an intermediate look
         full = _host(acc.end())
         torch.cuda.synchronize()
+        full_state = acc.export_state()
         acc.close()
     split = len(cuts) // 2
     with Plan(**kw) as p:
@@ -152,10 +153,12 @@ def test_stream_resume_is_bit_exact(dev):
             acc2.push(x[a:b])
         res = _host(acc2.end())
         torch.cuda.synchronize()
-        # exporting again gives the same bytes as exporting the uninterrupted run's state would
+        res_state = acc2.export_state()
         acc2.close()
     for k in full:
         assert np.array_equal(full[k], res[k], equal_nan=True), k
+    # the resumed accumulator ends in the uninterrupted one's state, byte for byte
+    assert bytes(res_state) == bytes(full_state)
 
 
 def test_stream_import_rejects_other_configurations(dev):
