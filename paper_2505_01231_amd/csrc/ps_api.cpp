@@ -1945,10 +1945,14 @@ struct StateHeader {
     uint32_t orders;
     int32_t window, precision, estimator, complex_signal, s4_shift, dtype, tile_group;
     int32_t n2, n3, n4;
+    int32_t reserved;   // zero; keeps the doubles aligned without padding bytes
     double dt, window_param;
     int64_t n_chunks, n_samples, n_carry, state_doubles, carry_bytes;
     uint64_t combo_hash;
 };
+// The header is compared byte for byte on import: it must hold no padding.
+static_assert(sizeof(StateHeader) == 8 + 2 * 4 + 6 * 4 + 4 + 7 * 4 + 4 * 4 + 2 * 8 + 5 * 8 + 8,
+              "state header without padding");
 
 }  // namespace
 
@@ -2241,7 +2245,8 @@ ps_status ps_stream_counts(ps_accum_t a, int64_t* n_chunks, int64_t* n_samples, 
 namespace {
 StateHeader make_header(const ps_accum_s* a) {
     const ps_plan_s* p = a->plan;
-    StateHeader h{};
+    StateHeader h;
+    std::memset(&h, 0, sizeof h);
     std::memcpy(h.magic, "PSSTATE1", 8);
     h.header_bytes = sizeof(StateHeader);
     h.version = 1;
