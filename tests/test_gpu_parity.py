@@ -310,6 +310,25 @@ def test_deterministic(dev, precision):
         assert np.array_equal(a[k], b[k], equal_nan=True), k
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_identical_chunks_have_zero_error_bars(dev, precision):
+    """A record made of one chunk repeated six times: every chunk's estimate is
+    the same, so the averages equal that one chunk's estimate and the error
+    bars (Section 4.2) vanish up to the FP64 rounding of the sums."""
+    N, Nf, m = 512, 80, 10
+    one = synth.ar2_chi2(N * m, seed=23, dtype=np.float32)
+    say("identical chunks", precision)
+    kw = dict(frame_len=N, n_freq=Nf, m=m, window="acg", precision=precision, orders=(1, 2, 3, 4))
+    rep = run_gpu(np.tile(one, 6), dev, **kw)
+    single = run_gpu(one, dev, **kw)
+    assert rep["n_chunks"] == 6 and single["n_chunks"] == 1
+    for k in ("s2", "s3", "s4"):
+        scale = np.max(np.abs(single[k]))
+        assert np.max(np.abs(rep[k] - single[k])) <= 1e-12 * scale, k
+        assert np.all(np.isfinite(rep[k + "_err"])), k
+        assert np.max(rep[k + "_err"]) <= 1e-7 * scale, k
+
+
 def test_edge_records(dev):
     """Several records in one call: no complete chunk (NaN), one chunk (NaN error
     bars), and a normal record."""
