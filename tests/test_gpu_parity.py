@@ -329,6 +329,28 @@ def test_identical_chunks_have_zero_error_bars(dev, precision):
         assert np.max(rep[k + "_err"]) <= 1e-7 * scale, k
 
 
+@pytest.mark.parametrize("precision,q,orders", [("fp32", 8, (2, 3, 4)), ("bf16x3", 8, (2, 3, 4)),
+                                                ("fp16x2s", 8, (2, 3, 4)), ("fp16x2s", -24, (2, 3, 4)),
+                                                ("fp16x2s", 40, (2, 4))])
+def test_power_of_two_scaling_is_exact(dev, precision, q, orders):
+    """z -> 2^q z scales S_n by 2^(nq) (a cumulant of order n is homogeneous
+    of degree n): with a power of two every product, split and scale in the
+    path is exact, so the outputs scale bit for bit.  q = 40 puts the
+    coefficients near 10^16, beyond the FP32 fourth powers' range, which the
+    scaled FP16 x 2 S4 reaches through its per-column scales."""
+    N, Nf, m = 512, 64, 10
+    z = synth.ar2_chi2(N * m * 5, seed=24, dtype=np.float32)
+    say("power-of-two scaling", precision, q, orders)
+    kw = dict(frame_len=N, n_freq=Nf, m=m, window="acg", precision=precision, orders=orders)
+    base = run_gpu(z, dev, **kw)
+    scaled = run_gpu(np.ldexp(z, q).astype(np.float32), dev, **kw)
+    for n in orders:
+        k = f"s{n}"
+        for key in (k, k + "_err"):
+            assert np.all(np.isfinite(scaled[key])), key
+            assert np.array_equal(scaled[key], base[key] * 2.0 ** (n * q)), key    # exact: a power of two
+
+
 def test_edge_records(dev):
     """Several records in one call: no complete chunk (NaN), one chunk (NaN error
     bars), and a normal record."""
