@@ -351,6 +351,42 @@ def test_power_of_two_scaling_is_exact(dev, precision, q, orders):
             assert np.array_equal(scaled[key], base[key] * 2.0 ** (n * q)), key    # exact: a power of two
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_time_reversal_conjugates(dev, precision):
+    """Appendix C: for a symmetric window, reversing a record of whole chunks
+    conjugates S3 and leaves S2 and S4 (and every error bar) unchanged: each
+    reversed frame's coefficients are e^(-2 pi j k/N) conj(a_k), whose phase
+    factors cancel in a_k a_l a*_(k+l), and the chunks are the same set."""
+    N, Nf, m = 512, 100, 10
+    z = synth.ar2_chi2(N * m * 8, seed=25, dtype=np.float32)
+    say("time reversal", precision)
+    for window in ("hann", "acg"):
+        kw = dict(frame_len=N, n_freq=Nf, m=m, window=window, precision=precision)
+        fwd = run_gpu(z, dev, **kw)
+        rev = run_gpu(z[::-1].copy(), dev, **kw)
+        for k in ("s2", "s3", "s4"):
+            want = np.conj(fwd[k]) if k == "s3" else fwd[k]
+            assert rel_err(rev[k], want) <= TOL, (window, k, rel_err(rev[k], want))
+            assert rel_err(rev[k + "_err"], fwd[k + "_err"]) <= TOL, (window, k)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_duplicated_channel_reduces_to_single(dev, precision):
+    """Two copies of one signal as two channels: every combination's S2, S3,
+    S4 and error bars equal the single-channel spectra (the cross-channel
+    kernels against the single-channel ones)."""
+    N, Nf, m = 256, 48, 8
+    z = synth.ar2_chi2(N * m * 9, seed=26, dtype=np.float32)
+    say("duplicated channel", precision)
+    one = run_gpu(z, dev, frame_len=N, n_freq=Nf, m=m, precision=precision)
+    two = run_gpu(np.stack([z, z]), dev, frame_len=N, n_freq=Nf, m=m, n_channels=2, precision=precision)
+    for k in ("s2", "s3", "s4"):
+        assert two[k].shape[0] > 1
+        for i in range(two[k].shape[0]):
+            assert rel_err(two[k][i], one[k][0]) <= TOL, (k, i, rel_err(two[k][i], one[k][0]))
+            assert rel_err(two[k + "_err"][i], one[k + "_err"][0]) <= TOL, (k, i)
+
+
 def test_edge_records(dev):
     """Several records in one call: no complete chunk (NaN), one chunk (NaN error
     bars), and a normal record."""
