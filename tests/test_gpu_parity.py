@@ -387,6 +387,20 @@ def test_duplicated_channel_reduces_to_single(dev, precision):
             assert rel_err(two[k + "_err"][i], one[k + "_err"][0]) <= TOL, (k, i)
 
 
+def test_sampling_interval_scaling_is_exact(dev):
+    """dt -> dt / 4 scales S_n by 4^-(n-1) (the prefactor dt^(n-1) of the
+    normalisation): a power of two, so bit for bit, error bars included."""
+    N, Nf, m = 512, 64, 10
+    z = synth.ar2_chi2(N * m * 4, seed=27, dtype=np.float32)
+    say("dt scaling")
+    kw = dict(frame_len=N, n_freq=Nf, m=m, window="acg", precision="fp16x2s")
+    base = run_gpu(z, dev, dt=1.0, **kw)
+    fine = run_gpu(z, dev, dt=0.25, **kw)
+    for n in (2, 3, 4):
+        for key in (f"s{n}", f"s{n}_err"):
+            assert np.array_equal(fine[key], base[key] * 0.25 ** (n - 1)), key
+
+
 def test_edge_records(dev):
     """Several records in one call: no complete chunk (NaN), one chunk (NaN error
     bars), and a normal record."""
