@@ -401,6 +401,36 @@ def test_sampling_interval_scaling_is_exact(dev):
             assert np.array_equal(fine[key], base[key] * 0.25 ** (n - 1)), key
 
 
+def test_record_beyond_2p31_samples(dev):
+    """A record longer than 2^31 samples (int16, 4.3 GB, 1.68 million chunks):
+    one 1280-sample chunk repeated, a period that does not divide 2^31, so a
+    sample offset wrapped at 32 bits would read a shifted chunk.  Every chunk
+    is then the same: the averages equal that chunk's estimate and the error
+    bars vanish up to the FP64 rounding of 1.68 million equal terms."""
+    from paper_2505_01231_amd import Plan
+    N, Nf, m = 256, 8, 5
+    reps = (1 << 31) // (N * m) + 3
+    z, _ = synth.mixed_channels(N * m, seed=28)
+    pattern = torch.from_numpy(np.ascontiguousarray(z[0])).to(dev)
+    say("record beyond 2^31 samples", reps * N * m)
+    with Plan(frame_len=N, n_freq=Nf, m=m, precision="bf16x3") as p:
+        one = p.execute(pattern)
+        torch.cuda.synchronize()
+        ref = {k: getattr(one, k).cpu().numpy() for k in ("s2", "s3", "s4")}
+        x = pattern.repeat(reps)
+        assert x.numel() > (1 << 31)
+        out = p.execute(x)
+        torch.cuda.synchronize()
+        assert out.n_chunks == reps
+        got = {k: getattr(out, k).cpu().numpy() for k in ("s2", "s3", "s4")}
+        err = {k: getattr(out, k + "_err").cpu().numpy() for k in ("s2", "s3", "s4")}
+        del x
+    for k in ("s2", "s3", "s4"):
+        scale = np.max(np.abs(ref[k]))
+        assert np.max(np.abs(got[k] - ref[k])) <= 1e-9 * scale, k
+        assert np.max(err[k]) <= 1e-6 * scale, k
+
+
 def test_edge_records(dev):
     """Several records in one call: no complete chunk (NaN), one chunk (NaN error
     bars), and a normal record."""
